@@ -1,0 +1,807 @@
+/*
+ * shape_oracle.c -- plain, slow, FP64 CPU reference for the importance-sampling
+ * (IS) estimator of Gaussian molecular shape overlap (Tuzharov, Bochenkova,
+ * Maximov, "Importance-Sampling Estimation of Gaussian Molecular Shape Overlap:
+ * Exact Union Volumes and Confidence-Bounded Virtual Screening").
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this file; only the test-suite, the smoke check and the CPU-baseline
+ * leg of the benchmark do.  It shares no code, header, table or helper with the
+ * HIP path.
+ *
+ * Every function computes its quantity straight from the definition in the
+ * paper (section / equation named at each function), in double precision, with
+ * no blocking, fusion or reordering beyond the definition.  Inputs arrive as
+ * float32 (the canonical input representation) and are promoted to double.
+ *
+ * Readings of points the paper leaves open (stated where used):
+ *   R1 Gaussian widths: unit-height atom Gaussians (Eq. occ) with
+ *      alpha = kappa / (lambda R^2), kappa = pi (3/(4 pi))^(2/3).
+ *   R2 Random numbers: one Philox4x32-10 block per sample point, counter
+ *      (k mod 2^32, k div 2^32, mol_id, 0), key (seed mod 2^32, seed div 2^32).
+ *      Words 1..3 give uniforms u = ((x >> 8) + 0.5) / 2^24 turned into standard
+ *      normals by the inverse normal CDF; word 0 picks the mixture component
+ *      through integer thresholds floor(2^32 * cumsum(v)/Z).
+ *   R3 Symmetrised estimate = plain average of the A-sided and B-sided
+ *      estimates (section "Importance-sampling estimator").
+ *   R4 Sample variances use the n-1 denominator, two-pass.
+ *   R5 Tanimoto standard error: the paper's delta-method expression (section
+ *      "Confidence-bounded screening"); a full delta-method value that also
+ *      propagates the self-overlap errors is reported beside it.
+ *   R6 Adaptive screening: rounds of 256 samples per side (512 per pair); after
+ *      each round stop when SE(T) <= tau or the pair total reaches the cap.
+ *   R7 Pose: unnormalised quaternion q (rotation R(q/|q|)) and translation t
+ *      acting on every centre of B about B's own origin.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define OR_PI 3.14159265358979323846
+
+/* ------------------------------------------------------------------------- */
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as    */
+/* easy as 1, 2, 3", SC'11): ten rounds of two 32x32->64 multiplies with the  */
+/* Weyl-sequence key schedule.                                               */
+/* ------------------------------------------------------------------------- */
+void or_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2],
+                      uint32_t out[4]) {
+  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+  const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+  uint32_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
+  uint32_t k0 = key_in[0], k1 = key_in[1];
+  for (int round = 0; round < 10; ++round) {
+    if (round > 0) {
+      k0 += W0;
+      k1 += W1;
+    }
+    uint64_t p0 = (uint64_t)M0 * (uint64_t)c0;
+    uint64_t p1 = (uint64_t)M1 * (uint64_t)c2;
+    uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    uint32_t n0 = hi1 ^ c1 ^ k0;
+    uint32_t n1 = lo1;
+    uint32_t n2 = hi0 ^ c3 ^ k1;
+    uint32_t n3 = lo0;
+    c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+  }
+  out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Inverse of the standard normal CDF, Phi(z) = erfc(-z/sqrt 2)/2, solved by  */
+/* bracketed Newton iteration on the C library's erfc.  The lower half is     */
+/* solved directly; the upper half by symmetry from 1-u (exact for the        */
+/* uniforms used here).                                                       */
+/* ------------------------------------------------------------------------- */
+static double or_phi_cdf(double z) { return 0.5 * erfc(-z / sqrt(2.0)); }
+
+double or_norm_inv(double u) {
+  if (!(u > 0.0 && u < 1.0)) return NAN;
+  if (u > 0.5) return -or_norm_inv(1.0 - u);
+  if (u == 0.5) return 0.0;
+  /* solve Phi(z) = u for z < 0 */
+  double lo = -40.0, hi = 0.0;
+  double z = -sqrt(-2.0 * log(u)); /* |z| over-estimate: Phi(z) < u here */
+  if (z < lo) z = lo;
+  for (int it = 0; it < 200; ++it) {
+    double f = or_phi_cdf(z) - u;
+    if (f > 0) hi = z; else lo = z;
+    double dens = exp(-0.5 * z * z) / sqrt(2.0 * OR_PI);
+    double zn = z - f / dens;
+    if (!(zn > lo && zn < hi)) zn = 0.5 * (lo + hi); /* fall back to bisection */
+    if (fabs(zn - z) <= 1e-16 * fabs(z) || hi - lo <= 1e-16 * fabs(z)) {
+      z = zn;
+      break;
+    }
+    z = zn;
+  }
+  return z;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Atom widths (Eq. occ): alpha = kappa/(lambda R^2), kappa = pi(3/4pi)^(2/3). */
+/* ------------------------------------------------------------------------- */
+void or_alpha_from_radius(const float* radius, int64_t n, double lambda,
+                          float* alpha_out) {
+  const double kappa = OR_PI * pow(3.0 / (4.0 * OR_PI), 2.0 / 3.0);
+  for (int64_t i = 0; i < n; ++i) {
+    double R = (double)radius[i];
+    alpha_out[i] = (float)(kappa / (lambda * R * R));
+  }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Molecule: centres and widths promoted to double, mixture weights           */
+/* v_i = (pi/alpha_i)^(3/2), Z = sum v_i (section "Importance-sampling         */
+/* estimator"), and the component-selection thresholds of reading R2.          */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+  int n;
+  double* c;       /* [n][3] */
+  double* alpha;   /* [n] */
+  double* v;       /* [n] */
+  uint32_t* thr;   /* [n-1] */
+  double Z;
+} or_mol;
+
+static int or_mol_init(or_mol* M, int n, const float* xyz, const float* alpha) {
+  M->n = n;
+  M->c = (double*)malloc(sizeof(double) * 3 * (size_t)n);
+  M->alpha = (double*)malloc(sizeof(double) * (size_t)n);
+  M->v = (double*)malloc(sizeof(double) * (size_t)n);
+  M->thr = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)(n > 1 ? n - 1 : 1));
+  if (!M->c || !M->alpha || !M->v || !M->thr) return -1;
+  double Z = 0.0;
+  for (int i = 0; i < n; ++i) {
+    for (int d = 0; d < 3; ++d) M->c[3 * i + d] = (double)xyz[3 * i + d];
+    M->alpha[i] = (double)alpha[i];
+    double t = OR_PI / M->alpha[i];
+    M->v[i] = t * sqrt(t);
+    Z += M->v[i];
+  }
+  M->Z = Z;
+  double cum = 0.0;
+  for (int i = 0; i + 1 < n; ++i) {
+    cum += M->v[i];
+    double f = floor(4294967296.0 * (cum / Z));
+    if (f > 4294967295.0) f = 4294967295.0;
+    M->thr[i] = (uint32_t)f;
+  }
+  return 0;
+}
+
+static void or_mol_free(or_mol* M) {
+  free(M->c); free(M->alpha); free(M->v); free(M->thr);
+}
+
+/* exported: weights, Z and thresholds of one molecule (for host-prep checks) */
+int or_mol_prep(int n, const float* xyz, const float* alpha, double* v_out,
+                double* Z_out, uint32_t* thr_out) {
+  or_mol M;
+  if (or_mol_init(&M, n, xyz, alpha)) return -1;
+  for (int i = 0; i < n; ++i) v_out[i] = M.v[i];
+  for (int i = 0; i + 1 < n; ++i) thr_out[i] = M.thr[i];
+  *Z_out = M.Z;
+  or_mol_free(&M);
+  return 0;
+}
+
+/* Sample k of molecule M (reading R2): exact draw from q_M = m_M / Z_M: pick
+ * component j with probability v_j/Z, then r ~ N(c_j, I/(2 alpha_j)). */
+static int or_sample(const or_mol* M, uint32_t mol_id, uint64_t k, uint64_t seed,
+                     double r[3]) {
+  uint32_t ctr[4] = {(uint32_t)k, (uint32_t)(k >> 32), mol_id, 0u};
+  uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  uint32_t x[4];
+  or_philox4x32_10(ctr, key, x);
+  int j = 0;
+  for (int i = 0; i + 1 < M->n; ++i)
+    if (x[0] >= M->thr[i]) j++;
+  double sd = 1.0 / sqrt(2.0 * M->alpha[j]);
+  for (int d = 0; d < 3; ++d) {
+    double u = ((double)(x[d + 1] >> 8) + 0.5) / 16777216.0;
+    r[d] = M->c[3 * j + d] + or_norm_inv(u) * sd;
+  }
+  return j;
+}
+
+/* exported: sample points of one molecule for counters k0..k0+n-1 */
+int or_sample_points(int n_atoms, const float* xyz, const float* alpha,
+                     uint32_t mol_id, uint64_t seed, uint64_t k0, int64_t n,
+                     double* r_out, int32_t* comp_out) {
+  or_mol M;
+  if (or_mol_init(&M, n_atoms, xyz, alpha)) return -1;
+  for (int64_t k = 0; k < n; ++k) {
+    int j = or_sample(&M, mol_id, k0 + (uint64_t)k, seed, r_out + 3 * k);
+    if (comp_out) comp_out[k] = j;
+  }
+  or_mol_free(&M);
+  return 0;
+}
+
+/* Densities at r (Eqs. occ, union and the first-order sum):
+ * o_i = exp(-alpha_i |r-c_i|^2), m = sum o_i, u = 1 - prod (1 - o_i). */
+static void or_density(const or_mol* M, const double r[3], double* m, double* u) {
+  double sm = 0.0, prod = 1.0;
+  for (int i = 0; i < M->n; ++i) {
+    double dx = r[0] - M->c[3 * i], dy = r[1] - M->c[3 * i + 1],
+           dz = r[2] - M->c[3 * i + 2];
+    double o = exp(-M->alpha[i] * (dx * dx + dy * dy + dz * dz));
+    sm += o;
+    prod *= (1.0 - o);
+  }
+  *m = sm;
+  *u = 1.0 - prod;
+}
+
+/* exported: m and u of a molecule at given points */
+int or_densities(int n_atoms, const float* xyz, const float* alpha, int64_t n_pts,
+                 const double* r, double* m_out, double* u_out) {
+  or_mol M;
+  if (or_mol_init(&M, n_atoms, xyz, alpha)) return -1;
+  for (int64_t k = 0; k < n_pts; ++k) or_density(&M, r + 3 * k, m_out + k, u_out + k);
+  or_mol_free(&M);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* One side of the estimator: samples from P, integrands for the pair (P, Q). */
+/* Eq. union-is (bounded weight) and Eq. expectation / Eq. var (FO channel).   */
+/* ------------------------------------------------------------------------- */
+enum { F_PQ = 0, F_PP = 1, F_V = 2, F_FOPQ = 3, F_FOPP = 4, NF = 5 };
+
+/* per-sample integrands for counters [k0, k1) into f[NF][k1-k0] */
+static void or_side_integrands(const or_mol* P, const or_mol* Q, uint32_t id_p,
+                               uint64_t seed, int64_t k0, int64_t k1, double* f) {
+  int64_t n = k1 - k0;
+  for (int64_t k = k0; k < k1; ++k) {
+    double r[3], mP, uP, mQ, uQ;
+    or_sample(P, id_p, (uint64_t)k, seed, r);
+    or_density(P, r, &mP, &uP);
+    or_density(Q, r, &mQ, &uQ);
+    double w = (mP > 0.0) ? uP / mP : 0.0;
+    int64_t i = k - k0;
+    f[F_PQ * n + i] = w * uQ;
+    f[F_PP * n + i] = w * uP;
+    f[F_V * n + i] = w;
+    f[F_FOPQ * n + i] = mQ;
+    f[F_FOPP * n + i] = mP;
+  }
+}
+
+typedef struct {
+  double mean[NF];
+  double var[NF];   /* sample variance, n-1 */
+  double cov12;     /* sample covariance of f_PQ and f_PP, n-1 */
+  int64_t n;
+} or_side_stats;
+
+static void or_stats(const double* f, int64_t n, or_side_stats* s) {
+  s->n = n;
+  for (int a = 0; a < NF; ++a) {
+    double sum = 0.0;
+    for (int64_t i = 0; i < n; ++i) sum += f[a * n + i];
+    s->mean[a] = sum / (double)n;
+    double ss = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+      double d = f[a * n + i] - s->mean[a];
+      ss += d * d;
+    }
+    s->var[a] = (n > 1) ? ss / (double)(n - 1) : 0.0;
+  }
+  double cs = 0.0;
+  for (int64_t i = 0; i < n; ++i)
+    cs += (f[F_PQ * n + i] - s->mean[F_PQ]) * (f[F_PP * n + i] - s->mean[F_PP]);
+  s->cov12 = (n > 1) ? cs / (double)(n - 1) : 0.0;
+}
+
+/* Result of one pair (all FP64). */
+typedef struct {
+  double O_ab, O_aa, O_bb, V_a, V_b, T;
+  double se_O_ab, se_O_aa, se_O_bb, se_V_a, se_V_b, se_T, se_T_full;
+  double O_ab_from_a, O_ab_from_b, Ofo_ab_is, Ofo_aa_is, Ofo_bb_is;
+  int64_t n_a, n_b;
+} or_result;
+
+/* Pair combination: symmetrised overlap (R3), Tanimoto and its delta-method
+ * standard errors (section "Confidence-bounded screening"; R5). */
+static void or_combine(double Za, double Zb, const or_side_stats* A,
+                       const or_side_stats* B, or_result* out) {
+  double na = (double)A->n, nb = (double)B->n;
+  double Xa = Za * A->mean[F_PQ], Xb = Zb * B->mean[F_PQ];
+  double se_Xa = Za * sqrt(A->var[F_PQ] / na), se_Xb = Zb * sqrt(B->var[F_PQ] / nb);
+  out->O_ab_from_a = Xa;
+  out->O_ab_from_b = Xb;
+  out->O_ab = 0.5 * (Xa + Xb);
+  out->se_O_ab = 0.5 * sqrt(se_Xa * se_Xa + se_Xb * se_Xb);
+  out->O_aa = Za * A->mean[F_PP];
+  out->O_bb = Zb * B->mean[F_PP];
+  out->se_O_aa = Za * sqrt(A->var[F_PP] / na);
+  out->se_O_bb = Zb * sqrt(B->var[F_PP] / nb);
+  out->V_a = Za * A->mean[F_V];
+  out->V_b = Zb * B->mean[F_V];
+  out->se_V_a = Za * sqrt(A->var[F_V] / na);
+  out->se_V_b = Zb * sqrt(B->var[F_V] / nb);
+  out->Ofo_ab_is = 0.5 * (Za * A->mean[F_FOPQ] + Zb * B->mean[F_FOPQ]);
+  out->Ofo_aa_is = Za * A->mean[F_FOPP];
+  out->Ofo_bb_is = Zb * B->mean[F_FOPP];
+  double S = out->O_aa + out->O_bb;
+  double D = S - out->O_ab;
+  out->T = out->O_ab / D;
+  out->se_T = fabs(S / (D * D)) * out->se_O_ab;
+  double g_ab = S / (D * D), g_s = -out->O_ab / (D * D);
+  double var_ab = out->se_O_ab * out->se_O_ab;
+  double var_s = out->se_O_aa * out->se_O_aa + out->se_O_bb * out->se_O_bb;
+  double cov = 0.5 * Za * Za * A->cov12 / na + 0.5 * Zb * Zb * B->cov12 / nb;
+  double vt = g_ab * g_ab * var_ab + g_s * g_s * var_s + 2.0 * g_ab * g_s * cov;
+  out->se_T_full = sqrt(vt > 0 ? vt : 0.0);
+  out->n_a = A->n;
+  out->n_b = B->n;
+}
+
+static int or_pair_estimate(const or_mol* A, const or_mol* B, uint32_t id_a,
+                            uint32_t id_b, int64_t n_a, int64_t n_b, uint64_t seed,
+                            or_result* out) {
+  double* fa = (double*)malloc(sizeof(double) * NF * (size_t)n_a);
+  double* fb = (double*)malloc(sizeof(double) * NF * (size_t)n_b);
+  if (!fa || !fb) { free(fa); free(fb); return -1; }
+  or_side_integrands(A, B, id_a, seed, 0, n_a, fa);
+  or_side_integrands(B, A, id_b, seed, 0, n_b, fb);
+  or_side_stats sa, sb;
+  or_stats(fa, n_a, &sa);
+  or_stats(fb, n_b, &sb);
+  or_combine(A->Z, B->Z, &sa, &sb, out);
+  free(fa); free(fb);
+  return 0;
+}
+
+/* exported: single pair estimate */
+int or_estimate(int na_atoms, const float* xyz_a, const float* alpha_a, uint32_t id_a,
+                int nb_atoms, const float* xyz_b, const float* alpha_b, uint32_t id_b,
+                int64_t n_a, int64_t n_b, uint64_t seed, double* out20) {
+  if (na_atoms < 1 || nb_atoms < 1 || n_a < 2 || n_b < 2) return -2;
+  or_mol A, B;
+  if (or_mol_init(&A, na_atoms, xyz_a, alpha_a)) return -1;
+  if (or_mol_init(&B, nb_atoms, xyz_b, alpha_b)) { or_mol_free(&A); return -1; }
+  or_result r;
+  int rc = or_pair_estimate(&A, &B, id_a, id_b, n_a, n_b, seed, &r);
+  memcpy(out20, &r, sizeof(double) * 18);
+  out20[18] = (double)r.n_a;
+  out20[19] = (double)r.n_b;
+  or_mol_free(&A); or_mol_free(&B);
+  return rc;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Screening: one query against listed library molecules (CSR layout).       */
+/* mode 0: fixed n per side.  mode 1: adaptive rounds (R6).                    */
+/* Outputs per pair (double): T, se_T, O_ab, O_aa, O_bb, n_used (pair total). */
+/* ------------------------------------------------------------------------- */
+int or_screen(int nq, const float* xyz_q, const float* alpha_q, uint32_t id_q,
+              const int32_t* lib_off, const float* lib_xyz, const float* lib_alpha,
+              const uint32_t* lib_id, const int32_t* pairs, int32_t n_pairs,
+              int mode, int64_t n_fixed, int64_t round_per_pair, int64_t cap_per_pair,
+              double tau, uint64_t seed, int n_threads, double* out6) {
+  or_mol Q;
+  if (or_mol_init(&Q, nq, xyz_q, alpha_q)) return -1;
+  int err = 0;
+#ifdef _OPENMP
+  if (n_threads > 0) omp_set_num_threads(n_threads);
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : err)
+#endif
+  for (int32_t p = 0; p < n_pairs; ++p) {
+    int32_t m = pairs ? pairs[p] : p;
+    int32_t a0 = lib_off[m], a1 = lib_off[m + 1];
+    uint32_t idm = lib_id ? lib_id[m] : (uint32_t)m;
+    or_mol B;
+    if (or_mol_init(&B, a1 - a0, lib_xyz + 3 * (size_t)a0, lib_alpha + a0)) { err |= 1; continue; }
+    or_result r;
+    if (mode == 0) {
+      if (or_pair_estimate(&Q, &B, id_q, idm, n_fixed, n_fixed, seed, &r)) err |= 1;
+    } else {
+      int64_t side_round = round_per_pair / 2;
+      int64_t max_side = cap_per_pair / 2;
+      double* fa = (double*)malloc(sizeof(double) * NF * (size_t)max_side);
+      double* fb = (double*)malloc(sizeof(double) * NF * (size_t)max_side);
+      double* ta = (double*)malloc(sizeof(double) * NF * (size_t)max_side);
+      double* tb = (double*)malloc(sizeof(double) * NF * (size_t)max_side);
+      if (!fa || !fb || !ta || !tb) { err |= 1; free(fa); free(fb); free(ta); free(tb); or_mol_free(&B); continue; }
+      int64_t n = 0;
+      for (;;) {
+        /* round: samples [n, n + side_round) on each side */
+        double* ra = (double*)malloc(sizeof(double) * NF * (size_t)side_round);
+        double* rb = (double*)malloc(sizeof(double) * NF * (size_t)side_round);
+        or_side_integrands(&Q, &B, id_q, seed, n, n + side_round, ra);
+        or_side_integrands(&B, &Q, idm, seed, n, n + side_round, rb);
+        int64_t nn = n + side_round;
+        /* re-pack [NF][nn] */
+        for (int a = 0; a < NF; ++a) {
+          for (int64_t i = 0; i < n; ++i) { ta[a * nn + i] = fa[a * n + i]; tb[a * nn + i] = fb[a * n + i]; }
+          for (int64_t i = 0; i < side_round; ++i) {
+            ta[a * nn + n + i] = ra[a * side_round + i];
+            tb[a * nn + n + i] = rb[a * side_round + i];
+          }
+        }
+        free(ra); free(rb);
+        memcpy(fa, ta, sizeof(double) * NF * (size_t)nn);
+        memcpy(fb, tb, sizeof(double) * NF * (size_t)nn);
+        n = nn;
+        or_side_stats sa, sb;
+        or_stats(fa, n, &sa);
+        or_stats(fb, n, &sb);
+        or_combine(Q.Z, B.Z, &sa, &sb, &r);
+        if (r.se_T <= tau || 2 * n >= cap_per_pair) break;
+      }
+      free(fa); free(fb); free(ta); free(tb);
+    }
+    out6[6 * (size_t)p + 0] = r.T;
+    out6[6 * (size_t)p + 1] = r.se_T;
+    out6[6 * (size_t)p + 2] = r.O_ab;
+    out6[6 * (size_t)p + 3] = r.O_aa;
+    out6[6 * (size_t)p + 4] = r.O_bb;
+    out6[6 * (size_t)p + 5] = (double)(r.n_a + r.n_b);
+    or_mol_free(&B);
+  }
+  or_mol_free(&Q);
+  return err ? -1 : 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Closed forms.                                                              */
+/* ------------------------------------------------------------------------- */
+
+/* Integral of a product of unit-height Gaussians exp(-a_i |r-c_i|^2) over R^3
+ * (Gaussian product theorem, the building block of Eq. fo):
+ * (pi/A)^(3/2) exp(-sum_{i<j} a_i a_j |c_i-c_j|^2 / A), A = sum a_i. */
+static double or_gauss_product_integral(int k, const double* c, const double* a) {
+  double A = 0.0;
+  for (int i = 0; i < k; ++i) A += a[i];
+  double e = 0.0;
+  for (int i = 0; i < k; ++i)
+    for (int j = i + 1; j < k; ++j) {
+      double dx = c[3 * i] - c[3 * j], dy = c[3 * i + 1] - c[3 * j + 1],
+             dz = c[3 * i + 2] - c[3 * j + 2];
+      e += a[i] * a[j] * (dx * dx + dy * dy + dz * dz);
+    }
+  double t = OR_PI / A;
+  return t * sqrt(t) * exp(-e / A);
+}
+
+/* Eq. fo: first-order overlap int m_A m_B. */
+double or_fo_overlap(int na, const float* xyz_a, const float* alpha_a, int nb,
+                     const float* xyz_b, const float* alpha_b) {
+  double s = 0.0;
+  for (int i = 0; i < na; ++i)
+    for (int j = 0; j < nb; ++j) {
+      double c[6], a[2];
+      for (int d = 0; d < 3; ++d) { c[d] = xyz_a[3 * i + d]; c[3 + d] = xyz_b[3 * j + d]; }
+      a[0] = alpha_a[i]; a[1] = alpha_b[j];
+      s += or_gauss_product_integral(2, c, a);
+    }
+  return s;
+}
+
+/* int m_A m_B^2 = Z_A E_qA[m_B^2]: the second moment behind Eq. var. */
+double or_fo_second_moment(int na, const float* xyz_a, const float* alpha_a, int nb,
+                           const float* xyz_b, const float* alpha_b) {
+  double s = 0.0;
+  for (int i = 0; i < na; ++i)
+    for (int j = 0; j < nb; ++j)
+      for (int l = 0; l < nb; ++l) {
+        double c[9], a[3];
+        for (int d = 0; d < 3; ++d) {
+          c[d] = xyz_a[3 * i + d]; c[3 + d] = xyz_b[3 * j + d]; c[6 + d] = xyz_b[3 * l + d];
+        }
+        a[0] = alpha_a[i]; a[1] = alpha_b[j]; a[2] = alpha_b[l];
+        s += or_gauss_product_integral(3, c, a);
+      }
+  return s;
+}
+
+/* Eq. incexc summed in full: int u_A u_B, int u_A^2 (pass B = A) and int u_A
+ * (pass nb = 0) for small molecules: every non-empty subset S of A and T of B
+ * contributes (-1)^(|S|+|T|) int prod_S o prod_T o. */
+double or_incexc(int na, const float* xyz_a, const float* alpha_a, int nb,
+                 const float* xyz_b, const float* alpha_b) {
+  if (na > 16 || nb > 16) return NAN;
+  double c[3 * 32], a[32];
+  double total = 0.0;
+  uint32_t nsa = 1u << na, nsb = 1u << nb;
+  for (uint32_t S = 1; S < nsa; ++S) {
+    uint32_t Tlo = (nb == 0) ? 0 : 1;
+    uint32_t Thi = (nb == 0) ? 1 : nsb;
+    for (uint32_t T = Tlo; T < Thi; ++T) {
+      int k = 0, sz = 0;
+      for (int i = 0; i < na; ++i)
+        if (S >> i & 1u) {
+          for (int d = 0; d < 3; ++d) c[3 * k + d] = xyz_a[3 * i + d];
+          a[k++] = alpha_a[i];
+          sz++;
+        }
+      for (int j = 0; j < nb; ++j)
+        if (T >> j & 1u) {
+          for (int d = 0; d < 3; ++d) c[3 * k + d] = xyz_b[3 * j + d];
+          a[k++] = alpha_b[j];
+          sz++;
+        }
+      /* u_A u_B: sign (-1)^(|S|+|T|); u_A alone: (-1)^(|S|+1) */
+      int sgn_exp = (nb == 0) ? sz + 1 : sz;
+      double term = or_gauss_product_integral(k, c, a);
+      total += (sgn_exp & 1) ? -term : term;
+    }
+  }
+  return total;
+}
+
+/* Pointwise union by the expanded series (Eq. incexc) at one point. */
+double or_union_series_at(int n, const float* xyz, const float* alpha, const double r[3]) {
+  if (n > 20) return NAN;
+  double o[20];
+  for (int i = 0; i < n; ++i) {
+    double dx = r[0] - xyz[3 * i], dy = r[1] - xyz[3 * i + 1], dz = r[2] - xyz[3 * i + 2];
+    o[i] = exp(-(double)alpha[i] * (dx * dx + dy * dy + dz * dz));
+  }
+  double s = 0.0;
+  for (uint32_t S = 1; S < (1u << n); ++S) {
+    double p = 1.0;
+    int sz = 0;
+    for (int i = 0; i < n; ++i)
+      if (S >> i & 1u) { p *= o[i]; sz++; }
+    s += (sz & 1) ? p : -p;
+  }
+  return s;
+}
+
+/* Dense-grid quadrature (section "Exact union overlap by bounded reweighting"
+ * names it as ground truth): trapezoid rule with spacing h over the box of
+ * both molecules' atom extents padded by pad on every side, Neumaier-summed.
+ * out8 = int u_A u_B, int u_A^2, int u_B^2, int u_A, int u_B, int m_A m_B,
+ *        int m_A^2, int m_B^2. */
+int or_grid_integrals(int na, const float* xyz_a, const float* alpha_a, int nb,
+                      const float* xyz_b, const float* alpha_b, double h, double pad,
+                      int n_threads, double* out8) {
+  or_mol A, B;
+  if (or_mol_init(&A, na, xyz_a, alpha_a)) return -1;
+  if (or_mol_init(&B, nb, xyz_b, alpha_b)) { or_mol_free(&A); return -1; }
+  double lo[3], hi[3];
+  for (int d = 0; d < 3; ++d) { lo[d] = 1e300; hi[d] = -1e300; }
+  for (int i = 0; i < na; ++i)
+    for (int d = 0; d < 3; ++d) { lo[d] = fmin(lo[d], A.c[3 * i + d]); hi[d] = fmax(hi[d], A.c[3 * i + d]); }
+  for (int i = 0; i < nb; ++i)
+    for (int d = 0; d < 3; ++d) { lo[d] = fmin(lo[d], B.c[3 * i + d]); hi[d] = fmax(hi[d], B.c[3 * i + d]); }
+  int ng[3];
+  for (int d = 0; d < 3; ++d) {
+    lo[d] -= pad; hi[d] += pad;
+    ng[d] = (int)ceil((hi[d] - lo[d]) / h) + 1;
+  }
+  double acc[8] = {0}, comp[8] = {0};
+#ifdef _OPENMP
+  if (n_threads > 0) omp_set_num_threads(n_threads);
+#endif
+  int nx = ng[0];
+  double* part = (double*)calloc((size_t)nx * 16, sizeof(double));
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+  for (int ix = 0; ix < nx; ++ix) {
+    double s[8] = {0}, cc[8] = {0};
+    double wx = (ix == 0 || ix == ng[0] - 1) ? 0.5 : 1.0;
+    for (int iy = 0; iy < ng[1]; ++iy) {
+      double wy = (iy == 0 || iy == ng[1] - 1) ? 0.5 : 1.0;
+      for (int iz = 0; iz < ng[2]; ++iz) {
+        double wz = (iz == 0 || iz == ng[2] - 1) ? 0.5 : 1.0;
+        double r[3] = {lo[0] + ix * h, lo[1] + iy * h, lo[2] + iz * h};
+        double mA, uA, mB, uB;
+        or_density(&A, r, &mA, &uA);
+        or_density(&B, r, &mB, &uB);
+        double w = wx * wy * wz;
+        double v[8] = {uA * uB, uA * uA, uB * uB, uA, uB, mA * mB, mA * mA, mB * mB};
+        for (int q = 0; q < 8; ++q) {
+          /* Neumaier compensated summation */
+          double x = w * v[q];
+          double t = s[q] + x;
+          if (fabs(s[q]) >= fabs(x)) cc[q] += (s[q] - t) + x; else cc[q] += (x - t) + s[q];
+          s[q] = t;
+        }
+      }
+    }
+    for (int q = 0; q < 8; ++q) { part[16 * ix + q] = s[q]; part[16 * ix + 8 + q] = cc[q]; }
+  }
+  for (int ix = 0; ix < nx; ++ix)
+    for (int q = 0; q < 8; ++q) {
+      double x = part[16 * ix + q] + part[16 * ix + 8 + q];
+      double t = acc[q] + x;
+      if (fabs(acc[q]) >= fabs(x)) comp[q] += (acc[q] - t) + x; else comp[q] += (x - t) + acc[q];
+      acc[q] = t;
+    }
+  free(part);
+  double h3 = h * h * h;
+  for (int q = 0; q < 8; ++q) out8[q] = (acc[q] + comp[q]) * h3;
+  or_mol_free(&A); or_mol_free(&B);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Alignment (section "Differentiable alignment and the hybrid pipeline").    */
+/* ------------------------------------------------------------------------- */
+
+/* Rotation matrix of the unit quaternion (w, x, y, z), row-major. */
+static void or_quat_matrix(const double q[4], double R[9]) {
+  double w = q[0], x = q[1], y = q[2], z = q[3];
+  R[0] = 1 - 2 * (y * y + z * z); R[1] = 2 * (x * y - w * z);     R[2] = 2 * (x * z + w * y);
+  R[3] = 2 * (x * y + w * z);     R[4] = 1 - 2 * (x * x + z * z); R[5] = 2 * (y * z - w * x);
+  R[6] = 2 * (x * z - w * y);     R[7] = 2 * (y * z + w * x);     R[8] = 1 - 2 * (x * x + y * y);
+}
+
+/* dR/dq_hat_i for the matrix above (i = w, x, y, z), each row-major 3x3. */
+static void or_quat_matrix_grad(const double q[4], double dR[4][9]) {
+  double w = q[0], x = q[1], y = q[2], z = q[3];
+  /* d/dw */
+  double Dw[9] = {0, -2 * z, 2 * y, 2 * z, 0, -2 * x, -2 * y, 2 * x, 0};
+  /* d/dx */
+  double Dx[9] = {0, 2 * y, 2 * z, 2 * y, -4 * x, -2 * w, 2 * z, 2 * w, -4 * x};
+  /* d/dy */
+  double Dy[9] = {-4 * y, 2 * x, 2 * w, 2 * x, 0, 2 * z, -2 * w, 2 * z, -4 * y};
+  /* d/dz */
+  double Dz[9] = {-4 * z, -2 * w, 2 * x, 2 * w, -4 * z, 2 * y, 2 * x, 2 * y, 0};
+  memcpy(dR[0], Dw, sizeof Dw); memcpy(dR[1], Dx, sizeof Dx);
+  memcpy(dR[2], Dy, sizeof Dy); memcpy(dR[3], Dz, sizeof Dz);
+}
+
+/* Self terms of the aligned Tanimoto: O_PP = Z_P * mean(u_P^2/m_P) over the
+ * first n samples of P (pose invariant). */
+static double or_self_overlap(const or_mol* P, uint32_t id, int64_t n, uint64_t seed) {
+  double s = 0.0;
+  for (int64_t k = 0; k < n; ++k) {
+    double r[3], m, u;
+    or_sample(P, id, (uint64_t)k, seed, r);
+    or_density(P, r, &m, &u);
+    s += (m > 0 ? u / m : 0.0) * u;
+  }
+  return P->Z * s / (double)n;
+}
+
+/* Value and gradient of T(xi) = O(xi)/(O_aa + O_bb - O(xi)) with
+ * O(xi) = Z_A/n sum_k w_A(r_k) u_B(r_k; xi), r_k the first n samples of A held
+ * fixed (Eq. grad, common random numbers).  Gradient with respect to the seven
+ * pose parameters (qw, qx, qy, qz, tx, ty, tz), q unnormalised (R7); the
+ * derivative of u_B with respect to o_j is prod_{l != j} (1 - o_l), formed
+ * directly. */
+static void or_align_eval(const or_mol* A, const or_mol* B, uint32_t id_a,
+                          const double* ra, const double* wa, int64_t n,
+                          double O_aa, double O_bb, const double pose[7],
+                          double* T_out, double* O_out, double grad[7]) {
+  double qn = sqrt(pose[0] * pose[0] + pose[1] * pose[1] + pose[2] * pose[2] + pose[3] * pose[3]);
+  double qh[4] = {pose[0] / qn, pose[1] / qn, pose[2] / qn, pose[3] / qn};
+  double R[9], dR[4][9];
+  or_quat_matrix(qh, R);
+  or_quat_matrix_grad(qh, dR);
+  int nb = B->n;
+  double* cp = (double*)malloc(sizeof(double) * 3 * (size_t)nb);
+  double* o = (double*)malloc(sizeof(double) * (size_t)nb);
+  for (int j = 0; j < nb; ++j)
+    for (int a = 0; a < 3; ++a)
+      cp[3 * j + a] = R[3 * a] * B->c[3 * j] + R[3 * a + 1] * B->c[3 * j + 1] +
+                      R[3 * a + 2] * B->c[3 * j + 2] + pose[4 + a];
+  double sumO = 0.0;
+  double gc[4] = {0}, gt[3] = {0};  /* d O / d q_hat, d O / d t (before Z/n) */
+  (void)id_a;
+  for (int64_t k = 0; k < n; ++k) {
+    const double* r = ra + 3 * k;
+    double prod = 1.0;
+    for (int j = 0; j < nb; ++j) {
+      double dx = r[0] - cp[3 * j], dy = r[1] - cp[3 * j + 1], dz = r[2] - cp[3 * j + 2];
+      o[j] = exp(-B->alpha[j] * (dx * dx + dy * dy + dz * dz));
+      prod *= (1.0 - o[j]);
+    }
+    double uB = 1.0 - prod;
+    sumO += wa[k] * uB;
+    for (int j = 0; j < nb; ++j) {
+      double others = 1.0;
+      for (int l = 0; l < nb; ++l)
+        if (l != j) others *= (1.0 - o[l]);
+      /* d u_B / d c'_j = others * 2 alpha_j o_j (r - c'_j) */
+      double coef = wa[k] * others * 2.0 * B->alpha[j] * o[j];
+      double g[3] = {coef * (r[0] - cp[3 * j]), coef * (r[1] - cp[3 * j + 1]),
+                     coef * (r[2] - cp[3 * j + 2])};
+      for (int a = 0; a < 3; ++a) gt[a] += g[a];
+      for (int i = 0; i < 4; ++i) {
+        /* d c'_j / d q_hat_i = dR_i c_j */
+        for (int a = 0; a < 3; ++a) {
+          double dc = dR[i][3 * a] * B->c[3 * j] + dR[i][3 * a + 1] * B->c[3 * j + 1] +
+                      dR[i][3 * a + 2] * B->c[3 * j + 2];
+          gc[i] += g[a] * dc;
+        }
+      }
+    }
+  }
+  double scale = A->Z / (double)n;
+  double O = scale * sumO;
+  double S = O_aa + O_bb;
+  double D = S - O;
+  double T = O / D;
+  double dT_dO = S / (D * D);
+  /* chain q_hat = q/|q|: d q_hat_i / d q_k = (delta_ik - qh_i qh_k)/|q| */
+  for (int kk = 0; kk < 4; ++kk) {
+    double s = 0.0;
+    for (int i = 0; i < 4; ++i) s += gc[i] * (((i == kk) ? 1.0 : 0.0) - qh[i] * qh[kk]) / qn;
+    grad[kk] = dT_dO * scale * s;
+  }
+  for (int a = 0; a < 3; ++a) grad[4 + a] = dT_dO * scale * gt[a];
+  *T_out = T;
+  if (O_out) *O_out = O;
+  free(cp); free(o);
+}
+
+typedef struct {
+  double* ra;
+  double* wa;
+  double O_aa, O_bb;
+} or_align_fixed;
+
+static int or_align_setup(const or_mol* A, const or_mol* B, uint32_t id_a, uint32_t id_b,
+                          int64_t n, uint64_t seed, or_align_fixed* F) {
+  F->ra = (double*)malloc(sizeof(double) * 3 * (size_t)n);
+  F->wa = (double*)malloc(sizeof(double) * (size_t)n);
+  if (!F->ra || !F->wa) return -1;
+  for (int64_t k = 0; k < n; ++k) {
+    double m, u;
+    or_sample(A, id_a, (uint64_t)k, seed, F->ra + 3 * k);
+    or_density(A, F->ra + 3 * k, &m, &u);
+    F->wa[k] = m > 0 ? u / m : 0.0;
+  }
+  F->O_aa = or_self_overlap(A, id_a, n, seed);
+  F->O_bb = or_self_overlap(B, id_b, n, seed);
+  return 0;
+}
+
+/* exported: T and dT/dpose for poses [n_poses][7] of one pair; also returns the
+ * self-overlaps used (2 doubles). */
+int or_align_grad(int na, const float* xyz_a, const float* alpha_a, uint32_t id_a,
+                  int nb, const float* xyz_b, const float* alpha_b, uint32_t id_b,
+                  int64_t n_samples, uint64_t seed, int32_t n_poses, const double* poses,
+                  double* T_out, double* grad_out, double* self_out) {
+  or_mol A, B;
+  if (or_mol_init(&A, na, xyz_a, alpha_a)) return -1;
+  if (or_mol_init(&B, nb, xyz_b, alpha_b)) { or_mol_free(&A); return -1; }
+  or_align_fixed F;
+  if (or_align_setup(&A, &B, id_a, id_b, n_samples, seed, &F)) return -1;
+  for (int32_t p = 0; p < n_poses; ++p)
+    or_align_eval(&A, &B, id_a, F.ra, F.wa, n_samples, F.O_aa, F.O_bb, poses + 7 * p,
+                  T_out + p, NULL, grad_out + 7 * p);
+  if (self_out) { self_out[0] = F.O_aa; self_out[1] = F.O_bb; }
+  free(F.ra); free(F.wa);
+  or_mol_free(&A); or_mol_free(&B);
+  return 0;
+}
+
+/* Adam (Kingma and Ba) on -T over the seven pose parameters, renormalising q
+ * after each step; returns the final pose and T evaluated at it for each start.
+ * betas (0.9, 0.999), eps 1e-8. */
+int or_align_adam(int na, const float* xyz_a, const float* alpha_a, uint32_t id_a,
+                  int nb, const float* xyz_b, const float* alpha_b, uint32_t id_b,
+                  int64_t n_samples, uint64_t seed, int32_t n_starts, const double* pose0,
+                  int32_t n_steps, double lr, double* pose_out, double* T_out) {
+  or_mol A, B;
+  if (or_mol_init(&A, na, xyz_a, alpha_a)) return -1;
+  if (or_mol_init(&B, nb, xyz_b, alpha_b)) { or_mol_free(&A); return -1; }
+  or_align_fixed F;
+  if (or_align_setup(&A, &B, id_a, id_b, n_samples, seed, &F)) return -1;
+  const double b1 = 0.9, b2 = 0.999, eps = 1e-8;
+  for (int32_t s = 0; s < n_starts; ++s) {
+    double x[7], m[7] = {0}, v[7] = {0}, g[7], T;
+    memcpy(x, pose0 + 7 * s, sizeof x);
+    for (int32_t it = 1; it <= n_steps; ++it) {
+      or_align_eval(&A, &B, id_a, F.ra, F.wa, n_samples, F.O_aa, F.O_bb, x, &T, NULL, g);
+      for (int i = 0; i < 7; ++i) {
+        double gi = -g[i]; /* minimise -T */
+        m[i] = b1 * m[i] + (1 - b1) * gi;
+        v[i] = b2 * v[i] + (1 - b2) * gi * gi;
+        double mh = m[i] / (1 - pow(b1, it));
+        double vh = v[i] / (1 - pow(b2, it));
+        x[i] -= lr * mh / (sqrt(vh) + eps);
+      }
+      double qn = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2] + x[3] * x[3]);
+      for (int i = 0; i < 4; ++i) x[i] /= qn;
+    }
+    or_align_eval(&A, &B, id_a, F.ra, F.wa, n_samples, F.O_aa, F.O_bb, x, &T, NULL, g);
+    memcpy(pose_out + 7 * s, x, sizeof x);
+    T_out[s] = T;
+  }
+  free(F.ra); free(F.wa);
+  or_mol_free(&A); or_mol_free(&B);
+  return 0;
+}
+
+int or_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
