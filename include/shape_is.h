@@ -1,0 +1,198 @@
+/*
+ * shape_is.h -- C ABI of the MI355X importance-sampling (IS) engine for
+ * Gaussian molecular shape overlap (Tuzharov, Bochenkova, Maximov,
+ * "Importance-Sampling Estimation of Gaussian Molecular Shape Overlap: Exact
+ * Union Volumes and Confidence-Bounded Virtual Screening").
+ *
+ * Model (section "Gaussian shape and its union volume", Eqs. occ/union):
+ * atom i of a molecule has centre c_i and width alpha_i and the unit-height
+ * occupancy o_i(r) = exp(-alpha_i |r - c_i|^2); the molecule's union occupancy
+ * is u(r) = 1 - prod_i (1 - o_i(r)), its first-order density m(r) = sum_i o_i.
+ * The union overlap of A and B is O_AB = int u_A u_B (Eq. union-overlap), the
+ * shape Tanimoto T = O_AB / (O_AA + O_BB - O_AB).
+ *
+ * Estimator (sections "Importance-sampling estimator", "Exact union overlap
+ * by bounded reweighting", Eqs. expectation/var/union-is): sample points are
+ * drawn exactly from A's own normalised mixture q_A = m_A / Z_A,
+ * Z_A = sum_i (pi/alpha_i)^(3/2), and O_AB ~ Z_A/n sum_k w_A(r_k) u_B(r_k) with
+ * the bounded weight w_A = u_A/m_A.  The estimate is symmetrised by averaging
+ * the A-sided and B-sided estimates.  Each value carries its analytic
+ * standard error Z * std / sqrt(n).
+ *
+ * Random numbers: sample k of a molecule with stream id `id` is one
+ * Philox4x32-10 block with counter (k mod 2^32, k div 2^32, id, 0) and key
+ * (seed mod 2^32, seed div 2^32).  Word 0 selects the mixture component through
+ * the integer thresholds floor(2^32 * (v_0+..+v_i)/Z); words 1..3 give the
+ * uniforms ((x >> 8) + 0.5) / 2^24 mapped to standard normals.  Results are
+ * therefore reproducible sample by sample and independent of launch shape.
+ *
+ * Conventions for every call below:
+ *  - Array arguments are DEVICE pointers on the context's device unless a
+ *    parameter says "host".  The caller owns them; the library never frees or
+ *    retains them after the work queued on `stream` completes.
+ *  - `stream` is a hipStream_t (NULL = the null stream).  Calls are
+ *    asynchronous on that stream unless they return values in host memory,
+ *    in which case they synchronise the stream before returning.
+ *  - The context owns only internal scratch (grown on demand with hipMalloc,
+ *    which happens at most on the first calls with a given problem size).
+ *  - Return value: SHAPE_OK or a negative SHAPE_E_* code; a message is kept
+ *    in the context (shape_last_error).  No exception or abort crosses the
+ *    ABI.  A context is not thread-safe: one host thread per context.
+ */
+#ifndef SHAPE_IS_H
+#define SHAPE_IS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SHAPE_OK 0
+#define SHAPE_E_INVAL (-1)       /* NULL or ill-formed argument */
+#define SHAPE_E_RANGE (-2)       /* size/count outside its documented range */
+#define SHAPE_E_NOMEM (-3)       /* device allocation failed */
+#define SHAPE_E_HIP (-4)         /* HIP runtime error, or no usable device */
+#define SHAPE_E_UNSUPPORTED (-5) /* device is not gfx950 */
+#define SHAPE_E_DATA (-6)        /* invalid molecule data found on device */
+
+/* Largest number of atoms in one molecule. */
+#define SHAPE_MAX_ATOMS 256
+
+typedef struct shape_ctx shape_ctx;
+
+/* Create a context on HIP device `device` (the device must be gfx950).
+ * *out receives the context, or NULL on failure. */
+int shape_create(shape_ctx** out, int device);
+
+/* Free the context and its scratch.  NULL is accepted. */
+void shape_destroy(shape_ctx* ctx);
+
+/* Message of the last failed call on ctx (ctx NULL: last failed
+ * shape_create).  Never NULL; valid until the next call on ctx. */
+const char* shape_last_error(const shape_ctx* ctx);
+
+/* Library version string (host memory, static). */
+const char* shape_version(void);
+
+/* Atom widths of Eq. occ: alpha_i = kappa / (lambda R_i^2) with
+ * kappa = pi (3 / (4 pi))^(2/3).  lambda = 1 makes a single occupancy integrate
+ * to the hard-sphere volume; a Gaussian height p in the Grant-Pickup form
+ * alpha = pi (3p / (4 pi R^3))^(2/3) corresponds to lambda = p^(-2/3).
+ * radius, alpha: device float [n] (Angstrom, Angstrom^-2).  n >= 0.
+ * Errors: SHAPE_E_INVAL (NULL pointers with n > 0, lambda <= 0). */
+int shape_alpha_from_radius(shape_ctx* ctx, const float* radius, int64_t n,
+                            double lambda, float* alpha, void* stream);
+
+/* A set of molecules in CSR layout (all device pointers except the ints).
+ *  n_mols       number of molecules (>= 1)
+ *  max_atoms    host-known upper bound on atoms per molecule, 1..SHAPE_MAX_ATOMS
+ *               (sizes on-chip staging; a molecule above it is invalid data)
+ *  n_atoms      host-known total number of atoms (= atom_offset[n_mols]);
+ *               every offset must lie in [0, n_atoms]
+ *  atom_offset  int32 [n_mols + 1], non-decreasing, atom_offset[0] = 0
+ *  xyz          float32 [n_atoms][3] atom centres (Angstrom)
+ *  alpha        float32 [n_atoms] atom widths alpha_i > 0 (Angstrom^-2)
+ *  mol_id       uint32 [n_mols] random-stream id of each molecule, or NULL
+ *               (id = index in the set).  Equal ids give common random numbers.
+ * A molecule with no atoms, more than max_atoms atoms, offsets outside
+ * [0, n_atoms], a non-finite coordinate or a width that is not finite and
+ * positive is invalid data. */
+typedef struct {
+  int32_t n_mols;
+  int32_t max_atoms;
+  int64_t n_atoms;
+  const int32_t* atom_offset;
+  const float* xyz;
+  const float* alpha;
+  const uint32_t* mol_id;
+} shape_mols;
+
+/* Result of one symmetrised pair estimate (host struct, FP64).
+ *  O_ab, se_O_ab        union overlap int u_A u_B and its SE
+ *  O_aa, O_bb           union self-overlaps int u^2 (from each side's samples)
+ *  V_a, V_b             union volumes int u
+ *  T, se_T              shape Tanimoto and the delta-method SE of section
+ *                       "Confidence-bounded screening" (O_ab error only)
+ *  se_T_full            delta-method SE that also propagates the errors of
+ *                       O_aa, O_bb and their covariance with O_ab
+ *  O_ab_from_a/_from_b  the one-sided estimates that are averaged into O_ab
+ *  Ofo_ab_is, Ofo_aa_is, Ofo_bb_is  first-order overlaps estimated from the
+ *                       same samples (f = m_B, Eq. var), a built-in check
+ *                       against the closed form of Eq. fo
+ *  n_a, n_b             samples drawn from A and from B */
+typedef struct {
+  double O_ab, O_aa, O_bb, V_a, V_b, T;
+  double se_O_ab, se_O_aa, se_O_bb, se_V_a, se_V_b, se_T, se_T_full;
+  double O_ab_from_a, O_ab_from_b, Ofo_ab_is, Ofo_aa_is, Ofo_bb_is;
+  int64_t n_a, n_b;
+} shape_result;
+
+/* One pair, fixed sample counts (Eqs. expectation, var, union-is).
+ * A, B: molecule sets with n_mols == 1 each.  n_a, n_b: samples from A and
+ * from B, 2..2^31.  out: HOST struct; the call synchronises `stream`.
+ * Errors: SHAPE_E_INVAL, SHAPE_E_RANGE, SHAPE_E_DATA, SHAPE_E_NOMEM,
+ * SHAPE_E_HIP. */
+int shape_estimate(shape_ctx* ctx, const shape_mols* A, const shape_mols* B,
+                   int64_t n_a, int64_t n_b, uint64_t seed, void* stream,
+                   shape_result* out);
+
+#define SHAPE_SCREEN_FIXED 0
+#define SHAPE_SCREEN_ADAPTIVE 1
+
+/* Screening parameters (host struct).
+ *  mode            SHAPE_SCREEN_FIXED or SHAPE_SCREEN_ADAPTIVE
+ *  n_per_side      FIXED: samples per molecule side, a multiple of 64 in
+ *                  [64, 2^20]
+ *  round_per_pair  ADAPTIVE: samples per pair per round (half per side),
+ *                  a multiple of 128 in [128, 8192]
+ *  cap_per_pair    ADAPTIVE: sample cap per pair, a multiple of
+ *                  round_per_pair, at most 2^21
+ *  tau             ADAPTIVE: stop once SE(T) <= tau (tau > 0)
+ *  seed            Philox key
+ * Adaptive screening (section "Confidence-bounded screening"): each pair
+ * draws rounds of samples until the delta-method SE(T) is at most tau or the
+ * cap is reached; the decision is taken in FP64 after every round. */
+typedef struct {
+  int32_t mode;
+  int32_t n_per_side;
+  int32_t round_per_pair;
+  int32_t cap_per_pair;
+  double tau;
+  uint64_t seed;
+} shape_screen_params;
+
+/* Per-pair outputs (device pointers; T and se_T required when n_pairs > 0,
+ * others may be NULL).  n_used is the total number of samples of the pair
+ * (both sides). */
+typedef struct {
+  float* T;
+  float* se_T;
+  float* O_ab;
+  float* O_aa;
+  float* O_bb;
+  int32_t* n_used;
+} shape_screen_out;
+
+/* Screen one query molecule against library molecules.
+ * query: n_mols == 1.  lib: the library.  pairs: device int32 [n_pairs]
+ * library indices to score, or NULL to score lib molecule p for p < n_pairs
+ * (then n_pairs <= lib->n_mols).  Outputs are indexed by pair.
+ * Asynchronous.  Invalid molecules produce NaN outputs and are reported by
+ * shape_check_data.  Errors: SHAPE_E_INVAL, SHAPE_E_RANGE, SHAPE_E_NOMEM,
+ * SHAPE_E_HIP. */
+int shape_screen(shape_ctx* ctx, const shape_mols* query, const shape_mols* lib,
+                 const int32_t* pairs, int32_t n_pairs,
+                 const shape_screen_params* params, void* stream,
+                 const shape_screen_out* out);
+
+/* Synchronise `stream` and report whether any molecule seen by the calls
+ * queued since the previous check was invalid (SHAPE_E_DATA) or not
+ * (SHAPE_OK); clears the flag. */
+int shape_check_data(shape_ctx* ctx, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SHAPE_IS_H */

@@ -1,0 +1,347 @@
+// C-ABI layer of the IS shape-overlap engine: argument validation, context
+// scratch, launches.  No exception crosses the ABI.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+
+#include "shape_is.h"
+#include "shape_kernels.hpp"
+
+#define SHAPE_VERSION_STR "shape_is 0.1.0 (gfx950)"
+
+namespace {
+
+struct Buffer {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+};
+
+enum Slot {
+  S_Q_ATOM, S_Q_SAMP, S_Q_Z, S_Q_ID, S_Q_BAD,
+  S_L_ATOM, S_L_SAMP, S_L_Z, S_L_ID, S_L_BAD,
+  S_PARTIALS, S_RESULT, S_QS, S_QF2,
+  S_COUNT
+};
+
+}  // namespace
+
+struct shape_ctx {
+  int device = -1;
+  int n_cu = 0;
+  std::string err;
+  Buffer buf[S_COUNT];
+  int* flag = nullptr;  // invalid-data flag (device int)
+};
+
+namespace {
+
+thread_local std::string g_create_err;
+
+int fail(shape_ctx* c, int code, const char* fmt, ...) {
+  char msg[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(msg, sizeof msg, fmt, ap);
+  va_end(ap);
+  if (c) c->err = msg; else g_create_err = msg;
+  return code;
+}
+
+int hip_fail(shape_ctx* c, hipError_t e, const char* what) {
+  return fail(c, SHAPE_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(ctx, expr, what)                     \
+  do {                                               \
+    hipError_t _e = (expr);                          \
+    if (_e != hipSuccess) return hip_fail(ctx, _e, what); \
+  } while (0)
+
+// Grow-only scratch.  Freed buffers are released after a device sync so a
+// buffer still in use by queued work is never returned to the allocator.
+int ensure(shape_ctx* c, Slot s, size_t bytes, void** out) {
+  Buffer& b = c->buf[s];
+  if (b.bytes < bytes) {
+    if (b.ptr) {
+      hipError_t e = hipDeviceSynchronize();
+      if (e != hipSuccess) return hip_fail(c, e, "hipDeviceSynchronize");
+      (void)hipFree(b.ptr);
+      b.ptr = nullptr;
+      b.bytes = 0;
+    }
+    size_t want = bytes + bytes / 4 + 256;
+    hipError_t e = hipMalloc(&b.ptr, want);
+    if (e != hipSuccess) {
+      b.ptr = nullptr;
+      return fail(c, SHAPE_E_NOMEM, "hipMalloc(%zu) failed: %s", want, hipGetErrorString(e));
+    }
+    b.bytes = want;
+  }
+  *out = b.ptr;
+  return SHAPE_OK;
+}
+
+int set_device(shape_ctx* c) {
+  HIP_TRY(c, hipSetDevice(c->device), "hipSetDevice");
+  return SHAPE_OK;
+}
+
+int check_mols(shape_ctx* c, const shape_mols* m, const char* name, bool single) {
+  if (!m) return fail(c, SHAPE_E_INVAL, "%s is NULL", name);
+  if (m->n_mols < 1) return fail(c, SHAPE_E_RANGE, "%s->n_mols = %d < 1", name, m->n_mols);
+  if (single && m->n_mols != 1)
+    return fail(c, SHAPE_E_RANGE, "%s must hold exactly one molecule (n_mols = %d)", name,
+                m->n_mols);
+  if (m->max_atoms < 1 || m->max_atoms > SHAPE_MAX_ATOMS)
+    return fail(c, SHAPE_E_RANGE, "%s->max_atoms = %d outside [1, %d]", name, m->max_atoms,
+                SHAPE_MAX_ATOMS);
+  if (m->n_atoms < 1 || m->n_atoms > (int64_t)0x7FFFFFFF)
+    return fail(c, SHAPE_E_RANGE, "%s->n_atoms = %lld outside [1, 2^31)", name,
+                (long long)m->n_atoms);
+  if (!m->atom_offset || !m->xyz || !m->alpha)
+    return fail(c, SHAPE_E_INVAL, "%s has a NULL array", name);
+  return SHAPE_OK;
+}
+
+// Prepare a molecule set into the query (q = true) or library slots.
+int prepare(shape_ctx* c, const shape_mols* m, bool q, hipStream_t st, shape::Prepared* P) {
+  const int base = q ? S_Q_ATOM : S_L_ATOM;
+  void* p[5];
+  int rc;
+  const size_t na = (size_t)m->n_atoms, nm = (size_t)m->n_mols;
+  if ((rc = ensure(c, (Slot)(base + 0), na * sizeof(shape::Atom), &p[0]))) return rc;
+  if ((rc = ensure(c, (Slot)(base + 1), na * sizeof(shape::AtomSampling), &p[1]))) return rc;
+  if ((rc = ensure(c, (Slot)(base + 2), nm * sizeof(double), &p[2]))) return rc;
+  if ((rc = ensure(c, (Slot)(base + 3), nm * sizeof(uint32_t), &p[3]))) return rc;
+  if ((rc = ensure(c, (Slot)(base + 4), nm * sizeof(int), &p[4]))) return rc;
+  P->atom = (shape::Atom*)p[0];
+  P->samp = (shape::AtomSampling*)p[1];
+  P->Z = (double*)p[2];
+  P->id = (uint32_t*)p[3];
+  P->bad = (int*)p[4];
+  shape::MolsDev in{m->n_mols, m->max_atoms, m->n_atoms, m->atom_offset, m->xyz, m->alpha,
+                    m->mol_id};
+  HIP_TRY(c, shape::launch_prepare(in, *P, c->flag, st), "prepare kernel");
+  return SHAPE_OK;
+}
+
+uint2 key_of(uint64_t seed) { return make_uint2((uint32_t)seed, (uint32_t)(seed >> 32)); }
+
+}  // namespace
+
+extern "C" {
+
+const char* shape_version(void) { return SHAPE_VERSION_STR; }
+
+int shape_create(shape_ctx** out, int device) {
+  if (!out) return fail(nullptr, SHAPE_E_INVAL, "out is NULL");
+  *out = nullptr;
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess || n == 0)
+    return fail(nullptr, SHAPE_E_HIP, "no HIP device available (%s)",
+                e != hipSuccess ? hipGetErrorString(e) : "count 0");
+  if (device < 0 || device >= n)
+    return fail(nullptr, SHAPE_E_RANGE, "device %d outside [0, %d)", device, n);
+  hipDeviceProp_t prop;
+  e = hipGetDeviceProperties(&prop, device);
+  if (e != hipSuccess) return fail(nullptr, SHAPE_E_HIP, "hipGetDeviceProperties: %s",
+                                   hipGetErrorString(e));
+  if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(nullptr, SHAPE_E_UNSUPPORTED, "device %d is %s, not gfx950", device,
+                prop.gcnArchName);
+  shape_ctx* c = new (std::nothrow) shape_ctx();
+  if (!c) return fail(nullptr, SHAPE_E_NOMEM, "context allocation failed");
+  c->device = device;
+  c->n_cu = prop.multiProcessorCount;
+  e = hipSetDevice(device);
+  if (e == hipSuccess) e = hipMalloc(&c->flag, sizeof(int));
+  if (e == hipSuccess) e = hipMemset(c->flag, 0, sizeof(int));
+  if (e != hipSuccess) {
+    delete c;
+    return fail(nullptr, SHAPE_E_HIP, "context set-up: %s", hipGetErrorString(e));
+  }
+  *out = c;
+  return SHAPE_OK;
+}
+
+void shape_destroy(shape_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  for (auto& b : c->buf)
+    if (b.ptr) (void)hipFree(b.ptr);
+  if (c->flag) (void)hipFree(c->flag);
+  delete c;
+}
+
+const char* shape_last_error(const shape_ctx* c) {
+  return c ? c->err.c_str() : g_create_err.c_str();
+}
+
+int shape_alpha_from_radius(shape_ctx* c, const float* radius, int64_t n, double lambda,
+                            float* alpha, void* stream) {
+  if (!c) return SHAPE_E_INVAL;
+  try {
+    if (n < 0) return fail(c, SHAPE_E_RANGE, "n = %lld < 0", (long long)n);
+    if (n > 0 && (!radius || !alpha)) return fail(c, SHAPE_E_INVAL, "NULL array");
+    if (!(lambda > 0.0) || !isfinite(lambda))
+      return fail(c, SHAPE_E_INVAL, "lambda must be finite and > 0");
+    int rc = set_device(c);
+    if (rc) return rc;
+    const double kappa = M_PI * pow(3.0 / (4.0 * M_PI), 2.0 / 3.0);
+    HIP_TRY(c, shape::launch_alpha_from_radius(radius, n, kappa, lambda, alpha,
+                                               (hipStream_t)stream),
+            "alpha kernel");
+    return SHAPE_OK;
+  } catch (...) {
+    return fail(c, SHAPE_E_HIP, "internal error");
+  }
+}
+
+int shape_estimate(shape_ctx* c, const shape_mols* A, const shape_mols* B, int64_t n_a,
+                   int64_t n_b, uint64_t seed, void* stream, shape_result* out) {
+  if (!c) return SHAPE_E_INVAL;
+  try {
+    int rc;
+    if ((rc = check_mols(c, A, "A", true))) return rc;
+    if ((rc = check_mols(c, B, "B", true))) return rc;
+    if (!out) return fail(c, SHAPE_E_INVAL, "out is NULL");
+    if (n_a < 2 || n_b < 2 || n_a > (int64_t)1 << 31 || n_b > (int64_t)1 << 31)
+      return fail(c, SHAPE_E_RANGE, "sample counts must lie in [2, 2^31]");
+    if ((rc = set_device(c))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    shape::Prepared PA, PB;
+    if ((rc = prepare(c, A, true, st, &PA))) return rc;
+    if ((rc = prepare(c, B, false, st, &PB))) return rc;
+    const int nblk = shape::est_blocks(n_a > n_b ? n_a : n_b);
+    void *partials, *res;
+    if ((rc = ensure(c, S_PARTIALS, (size_t)2 * nblk * shape::kEstSums * sizeof(double),
+                     &partials)))
+      return rc;
+    if ((rc = ensure(c, S_RESULT, sizeof(shape_result), &res))) return rc;
+    // invalid inputs are reported before the sampling kernels read them
+    int bad[2] = {0, 0};
+    HIP_TRY(c, hipMemcpyAsync(&bad[0], PA.bad, sizeof(int), hipMemcpyDeviceToHost, st), "copy");
+    HIP_TRY(c, hipMemcpyAsync(&bad[1], PB.bad, sizeof(int), hipMemcpyDeviceToHost, st), "copy");
+    HIP_TRY(c, hipStreamSynchronize(st), "hipStreamSynchronize");
+    if (bad[0] || bad[1]) {
+      HIP_TRY(c, shape::launch_fill_int(c->flag, 1, 0, st), "flag reset");
+      return fail(c, SHAPE_E_DATA, "invalid molecule data in %s", bad[0] ? "A" : "B");
+    }
+    HIP_TRY(c, shape::launch_estimate(PA, PB, A->atom_offset, B->atom_offset, n_a, n_b,
+                                      key_of(seed), (double*)partials, nblk,
+                                      (shape_result*)res, st),
+            "estimate kernels");
+    HIP_TRY(c, hipMemcpyAsync(out, res, sizeof(shape_result), hipMemcpyDeviceToHost, st),
+            "result copy");
+    HIP_TRY(c, hipStreamSynchronize(st), "hipStreamSynchronize");
+    return SHAPE_OK;
+  } catch (...) {
+    return fail(c, SHAPE_E_HIP, "internal error");
+  }
+}
+
+int shape_screen(shape_ctx* c, const shape_mols* query, const shape_mols* lib,
+                 const int32_t* pairs, int32_t n_pairs, const shape_screen_params* prm,
+                 void* stream, const shape_screen_out* out) {
+  if (!c) return SHAPE_E_INVAL;
+  try {
+    int rc;
+    if ((rc = check_mols(c, query, "query", true))) return rc;
+    if ((rc = check_mols(c, lib, "lib", false))) return rc;
+    if (!prm || !out) return fail(c, SHAPE_E_INVAL, "params or out is NULL");
+    if (n_pairs < 0) return fail(c, SHAPE_E_RANGE, "n_pairs < 0");
+    if (n_pairs > 0 && (!out->T || !out->se_T))
+      return fail(c, SHAPE_E_INVAL, "out->T and out->se_T are required");
+    if (!pairs && n_pairs > lib->n_mols)
+      return fail(c, SHAPE_E_RANGE, "n_pairs = %d exceeds lib->n_mols = %d", n_pairs,
+                  lib->n_mols);
+    int64_t n_fixed = 0, cap = 0;
+    int round_side = 0;
+    if (prm->mode == SHAPE_SCREEN_FIXED) {
+      if (prm->n_per_side < 64 || prm->n_per_side > (1 << 20) || prm->n_per_side % 64)
+        return fail(c, SHAPE_E_RANGE, "n_per_side must be a multiple of 64 in [64, 2^20]");
+      n_fixed = prm->n_per_side;
+      round_side = (int)(n_fixed % 256 == 0 ? 256 : 64);
+    } else if (prm->mode == SHAPE_SCREEN_ADAPTIVE) {
+      if (prm->round_per_pair < 128 || prm->round_per_pair > 8192 || prm->round_per_pair % 128)
+        return fail(c, SHAPE_E_RANGE, "round_per_pair must be a multiple of 128 in [128, 8192]");
+      if (prm->cap_per_pair < prm->round_per_pair || prm->cap_per_pair > (1 << 21) ||
+          prm->cap_per_pair % prm->round_per_pair)
+        return fail(c, SHAPE_E_RANGE,
+                    "cap_per_pair must be a multiple of round_per_pair, at most 2^21");
+      if (!(prm->tau > 0.0) || !isfinite(prm->tau))
+        return fail(c, SHAPE_E_RANGE, "tau must be finite and > 0");
+      round_side = prm->round_per_pair / 2;
+      cap = prm->cap_per_pair;
+    } else {
+      return fail(c, SHAPE_E_INVAL, "unknown mode %d", prm->mode);
+    }
+    if (n_pairs == 0) return SHAPE_OK;
+    if ((rc = set_device(c))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    shape::Prepared PQ, PL;
+    if ((rc = prepare(c, query, true, st, &PQ))) return rc;
+    if ((rc = prepare(c, lib, false, st, &PL))) return rc;
+    const int64_t n_cache = prm->mode == SHAPE_SCREEN_FIXED ? n_fixed : cap / 2;
+    void *qs, *qf2;
+    if ((rc = ensure(c, S_QS, (size_t)n_cache * sizeof(float4), &qs))) return rc;
+    if ((rc = ensure(c, S_QF2, (size_t)n_cache * sizeof(float), &qf2))) return rc;
+    const uint2 key = key_of(prm->seed);
+    HIP_TRY(c, shape::launch_query_cache(PQ, query->atom_offset, n_cache, key, (float4*)qs,
+                                         (float*)qf2, st),
+            "query cache kernel");
+    shape::ScreenArgs a;
+    a.Q = PQ;
+    a.offQ = query->atom_offset;
+    a.max_q = query->max_atoms;
+    a.L = PL;
+    a.offL = lib->atom_offset;
+    a.n_lib = lib->n_mols;
+    a.max_b = lib->max_atoms;
+    a.qs = (const float4*)qs;
+    a.qf2 = (const float*)qf2;
+    a.pairs = pairs;
+    a.n_pairs = n_pairs;
+    a.mode = prm->mode;
+    a.n_fixed = n_fixed;
+    a.round_side = round_side;
+    a.cap_pair = cap;
+    a.tau = prm->tau;
+    a.key = key;
+    a.T = out->T;
+    a.se_T = out->se_T;
+    a.O_ab = out->O_ab;
+    a.O_aa = out->O_aa;
+    a.O_bb = out->O_bb;
+    a.n_used = out->n_used;
+    HIP_TRY(c, shape::launch_screen(a, st), "screen kernel");
+    return SHAPE_OK;
+  } catch (...) {
+    return fail(c, SHAPE_E_HIP, "internal error");
+  }
+}
+
+int shape_check_data(shape_ctx* c, void* stream) {
+  if (!c) return SHAPE_E_INVAL;
+  int rc = set_device(c);
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  int flag = 0;
+  HIP_TRY(c, hipMemcpyAsync(&flag, c->flag, sizeof(int), hipMemcpyDeviceToHost, st), "copy");
+  HIP_TRY(c, hipStreamSynchronize(st), "hipStreamSynchronize");
+  if (flag) {
+    HIP_TRY(c, shape::launch_fill_int(c->flag, 1, 0, st), "flag reset");
+    HIP_TRY(c, hipStreamSynchronize(st), "hipStreamSynchronize");
+    return fail(c, SHAPE_E_DATA, "invalid molecule data seen since the last check");
+  }
+  return SHAPE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,143 @@
+// Device primitives of the IS shape-overlap engine (gfx950, wave64).
+//
+// Everything here runs in FP32 on the vector ALU except Philox (32-bit
+// integer multiplies) and the per-molecule preparation (FP64).  Notation
+// follows the paper: o_i = exp(-alpha_i |r - c_i|^2), m = sum o_i,
+// u = 1 - prod (1 - o_i), w = u / m, Z = sum (pi/alpha_i)^(3/2).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace shape {
+
+constexpr int kWave = 64;
+
+// Prepared atom record used by every hot loop: centre and the exponent scale
+// for exp2, a2 = alpha * log2(e), so that o = exp2(-a2 |r - c|^2).
+struct __align__(16) Atom {
+  float x, y, z, a2;
+};
+
+// Sampling record of an atom: standard deviation 1/sqrt(2 alpha) of its
+// mixture component and the component-selection threshold (word 0 of the
+// Philox block selects component j = #{i < N-1 : word0 >= thr_i}).
+struct __align__(8) AtomSampling {
+  float sd;
+  uint32_t thr;
+};
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds; each round multiplies
+// words 0 and 2 by the two round constants and mixes high halves with the
+// other words and the key; the key advances by the Weyl constants.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint2 k) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t hi0 = __umulhi(0xD2511F53u, c.x);
+    const uint32_t lo0 = 0xD2511F53u * c.x;
+    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z);
+    const uint32_t lo1 = 0xCD9E8D57u * c.z;
+    c = make_uint4(hi1 ^ c.y ^ k.x, lo1, hi0 ^ c.w ^ k.y, lo0);
+    k.x += 0x9E3779B9u;
+    k.y += 0xBB67AE85u;
+  }
+  return c;
+}
+
+// Standard normal from the top 24 bits of a Philox word: u = (b + 1/2) 2^-24,
+// z = Phi^-1(u) = sqrt(2) erfinv(2u - 1).  2u - 1 = (2b + 1 - 2^24) 2^-24 is
+// formed exactly in FP32, so the tails are resolved to the last bit.
+__device__ __forceinline__ float normal_from_bits(uint32_t word) {
+  const int b = (int)(word >> 8);
+  const float v = (float)(2 * b + 1 - (1 << 24)) * 0x1p-24f;
+  return 1.41421356237309505f * erfinvf(v);
+}
+
+// Sample point k of a molecule (exact draw from its normalised mixture):
+// component by integer thresholds, then r = c_j + z * sd_j per axis.
+// atoms/samp point at the molecule's own records (LDS or global).
+__device__ __forceinline__ void sample_point(const Atom* atoms, const AtomSampling* samp,
+                                             int n, uint32_t mol_id, uint64_t k, uint2 key,
+                                             float& rx, float& ry, float& rz) {
+  const uint4 x = philox4x32_10(make_uint4((uint32_t)k, (uint32_t)(k >> 32), mol_id, 0u), key);
+  int j = 0;
+  for (int i = 0; i < n - 1; ++i) j += (x.x >= samp[i].thr) ? 1 : 0;
+  const Atom c = atoms[j];
+  const float sd = samp[j].sd;
+  rx = fmaf(normal_from_bits(x.y), sd, c.x);
+  ry = fmaf(normal_from_bits(x.z), sd, c.y);
+  rz = fmaf(normal_from_bits(x.w), sd, c.z);
+}
+
+__device__ __forceinline__ float occupancy(const Atom& a, float rx, float ry, float rz) {
+  const float dx = rx - a.x, dy = ry - a.y, dz = rz - a.z;
+  const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+  return __builtin_amdgcn_exp2f(-a.a2 * d2);
+}
+
+// Union complement q = prod (1 - o_i) of a molecule at S points (the caller
+// initialises q to 1); u = 1 - q.  One fused multiply-add per atom and point.
+template <int S>
+__device__ __forceinline__ void eval_union(const Atom* __restrict__ atoms, int n,
+                                           const float (&rx)[S], const float (&ry)[S],
+                                           const float (&rz)[S], float (&q)[S]) {
+#pragma unroll 2
+  for (int i = 0; i < n; ++i) {
+    const Atom a = atoms[i];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const float o = occupancy(a, rx[s], ry[s], rz[s]);
+      q[s] = fmaf(-q[s], o, q[s]);
+    }
+  }
+}
+
+// First-order density m = sum o_i and union complement q at S points.
+template <int S>
+__device__ __forceinline__ void eval_density(const Atom* __restrict__ atoms, int n,
+                                             const float (&rx)[S], const float (&ry)[S],
+                                             const float (&rz)[S], float (&m)[S],
+                                             float (&q)[S]) {
+#pragma unroll 2
+  for (int i = 0; i < n; ++i) {
+    const Atom a = atoms[i];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const float o = occupancy(a, rx[s], ry[s], rz[s]);
+      m[s] += o;
+      q[s] = fmaf(-q[s], o, q[s]);
+    }
+  }
+}
+
+// Bounded weight w = u/m in [0, 1] (m > 0 for every sampled point; guard 0).
+__device__ __forceinline__ float bounded_weight(float u, float m) {
+  return m > 0.0f ? fminf(u / m, 1.0f) : 0.0f;
+}
+
+// ---------------------------------------------------------------------------
+// Wave-level reductions (fixed butterfly order: deterministic).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+__device__ __forceinline__ float wave_sumf(float v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+// Orders LDS writes of this wave before its later LDS reads (wave-private
+// staging needs no workgroup barrier).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+}  // namespace shape

@@ -1,0 +1,496 @@
+// HIP kernels of the IS shape-overlap engine: molecule preparation, the
+// single-pair estimator and fixed / adaptive screening.
+//
+// Data layout in HBM (prepared by k_prepare, one record per atom, CSR order):
+//   Atom          16 B  (x, y, z, alpha*log2 e)       hot-loop operand
+//   AtomSampling   8 B  (1/sqrt(2 alpha), threshold)  only for sampling
+//   Z             FP64 per molecule, stream id per molecule, invalid flag.
+#include "shape_kernels.hpp"
+
+#include <math.h>
+
+namespace shape {
+
+// ---------------------------------------------------------------------------
+// Eq. occ widths: alpha = kappa / (lambda R^2).
+// ---------------------------------------------------------------------------
+__global__ void k_alpha_from_radius(const float* __restrict__ R, int64_t n, double kappa,
+                                    double lambda, float* __restrict__ alpha) {
+#pragma clang fp contract(off)
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double r = (double)R[i];
+  alpha[i] = (float)(kappa / (lambda * r * r));
+}
+
+// ---------------------------------------------------------------------------
+// Molecule preparation, one thread per molecule, FP64: mixture weights
+// v_i = (pi/alpha_i)^(3/2) (= t sqrt t, t = pi/alpha_i), Z = sum v_i in atom
+// order, thresholds floor(2^32 cumsum(v)/Z) for the first N-1 atoms.
+// ---------------------------------------------------------------------------
+__global__ void k_prepare(MolsDev in, Prepared out, int* __restrict__ flag) {
+  // FP64 without contraction: Z and the thresholds are the values the plain
+  // expressions define, bit for bit.
+#pragma clang fp contract(off)
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= in.n_mols) return;
+  const int a0 = in.off[m], a1 = in.off[m + 1];
+  const int n = a1 - a0;
+  bool bad = !(a0 >= 0 && (int64_t)a1 <= in.n_atoms && n >= 1 && n <= in.max_atoms);
+  double Z = 0.0;
+  if (!bad) {
+    for (int i = a0; i < a1; ++i) {
+      const double al = (double)in.alpha[i];
+      const float x = in.xyz[3 * i], y = in.xyz[3 * i + 1], z = in.xyz[3 * i + 2];
+      if (!(al > 0.0) || !isfinite(al) || !isfinite(x) || !isfinite(y) || !isfinite(z)) {
+        bad = true;
+        break;
+      }
+      const double t = M_PI / al;
+      Z += t * sqrt(t);
+    }
+  }
+  out.id[m] = in.id ? in.id[m] : (uint32_t)m;
+  out.bad[m] = bad ? 1 : 0;
+  if (bad) {
+    out.Z[m] = __builtin_nan("");
+    atomicOr(flag, 1);
+    return;
+  }
+  out.Z[m] = Z;
+  const double log2e = 1.4426950408889634074;
+  double cum = 0.0;
+  for (int i = a0; i < a1; ++i) {
+    const double al = (double)in.alpha[i];
+    const double t = M_PI / al;
+    cum += t * sqrt(t);
+    Atom a;
+    a.x = in.xyz[3 * i];
+    a.y = in.xyz[3 * i + 1];
+    a.z = in.xyz[3 * i + 2];
+    a.a2 = (float)(al * log2e);
+    out.atom[i] = a;
+    AtomSampling s;
+    s.sd = (float)(1.0 / sqrt(2.0 * al));
+    if (i + 1 < a1) {
+      double f = floor(4294967296.0 * (cum / Z));
+      if (f > 4294967295.0) f = 4294967295.0;
+      s.thr = (uint32_t)f;
+    } else {
+      s.thr = 0xFFFFFFFFu;
+    }
+    out.samp[i] = s;
+  }
+}
+
+__global__ void k_fill_int(int* __restrict__ p, int n, int v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// Block reduction of K doubles (wave butterflies, then waves in order).
+// ---------------------------------------------------------------------------
+template <int K>
+__device__ void block_sum(double (&v)[K], double* lds /* [4][K] */) {
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+#pragma unroll
+  for (int j = 0; j < K; ++j) v[j] = wave_sum(v[j]);
+  if (lane == 0)
+#pragma unroll
+    for (int j = 0; j < K; ++j) lds[wave * K + j] = v[j];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int nw = blockDim.x / kWave;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      double s = 0.0;
+      for (int w = 0; w < nw; ++w) s += lds[w * K + j];
+      v[j] = s;
+    }
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Single pair: per-block partial sums of the eleven per-sample quantities of
+// one side (samples from P, partner Q):
+//   f1 = w_P u_Q, f2 = w_P u_P, f3 = w_P, f4 = m_Q, f5 = m_P
+// sums: f1, f1^2, f2, f2^2, f3, f3^2, f4, f4^2, f5, f5^2, f1 f2.
+// blockIdx.y = side (0: P = A, 1: P = B).
+// ---------------------------------------------------------------------------
+constexpr int kEstSPT = 8;
+
+__global__ __launch_bounds__(256) void k_est_partials(Prepared A, Prepared B, int64_t n_a,
+                                                      int64_t n_b, uint2 key,
+                                                      double* __restrict__ partials,
+                                                      int nblk, const int* __restrict__ offA,
+                                                      const int* __restrict__ offB) {
+  __shared__ Atom sP[SHAPE_MAX_ATOMS];
+  __shared__ Atom sQ[SHAPE_MAX_ATOMS];
+  __shared__ AtomSampling sS[SHAPE_MAX_ATOMS];
+  __shared__ double red[4 * kEstSums];
+  const int side = blockIdx.y;
+  const Prepared& P = side ? B : A;
+  const Prepared& Q = side ? A : B;
+  const int* offP = side ? offB : offA;
+  const int* offQ = side ? offA : offB;
+  const int64_t n = side ? n_b : n_a;
+  const int p0 = offP[0], np = offP[1] - offP[0];
+  const int q0 = offQ[0], nq = offQ[1] - offQ[0];
+  const uint32_t idp = P.id[0];
+  for (int i = threadIdx.x; i < np; i += blockDim.x) {
+    sP[i] = P.atom[p0 + i];
+    sS[i] = P.samp[p0 + i];
+  }
+  for (int i = threadIdx.x; i < nq; i += blockDim.x) sQ[i] = Q.atom[q0 + i];
+  __syncthreads();
+  float acc[kEstSums];
+#pragma unroll
+  for (int j = 0; j < kEstSums; ++j) acc[j] = 0.0f;
+  const int64_t base = (int64_t)blockIdx.x * blockDim.x * kEstSPT;
+  for (int s = 0; s < kEstSPT; ++s) {
+    const int64_t k = base + (int64_t)s * blockDim.x + threadIdx.x;
+    if (k >= n) break;
+    float rx[1], ry[1], rz[1];
+    sample_point(sP, sS, np, idp, (uint64_t)k, key, rx[0], ry[0], rz[0]);
+    float mp[1] = {0.0f}, qp[1] = {1.0f}, mq[1] = {0.0f}, qq[1] = {1.0f};
+    eval_density<1>(sP, np, rx, ry, rz, mp, qp);
+    eval_density<1>(sQ, nq, rx, ry, rz, mq, qq);
+    const float uP = 1.0f - qp[0], uQ = 1.0f - qq[0];
+    const float w = bounded_weight(uP, mp[0]);
+    const float f1 = w * uQ, f2 = w * uP, f3 = w, f4 = mq[0], f5 = mp[0];
+    acc[0] += f1; acc[1] += f1 * f1;
+    acc[2] += f2; acc[3] += f2 * f2;
+    acc[4] += f3; acc[5] += f3 * f3;
+    acc[6] += f4; acc[7] += f4 * f4;
+    acc[8] += f5; acc[9] += f5 * f5;
+    acc[10] += f1 * f2;
+  }
+  double v[kEstSums];
+#pragma unroll
+  for (int j = 0; j < kEstSums; ++j) v[j] = (double)acc[j];
+  block_sum<kEstSums>(v, red);
+  if (threadIdx.x == 0) {
+    double* dst = partials + ((size_t)side * nblk + blockIdx.x) * kEstSums;
+#pragma unroll
+    for (int j = 0; j < kEstSums; ++j) dst[j] = v[j];
+  }
+}
+
+// Mean, sample variance (n-1) and covariance from running sums.
+struct Moments {
+  double n, s, ss;
+  __device__ double mean() const { return s / n; }
+  __device__ double var() const {
+    const double v = (ss - s * s / n) / (n - 1.0);
+    return v > 0.0 ? v : 0.0;
+  }
+};
+
+__global__ __launch_bounds__(256) void k_est_finalize(const double* __restrict__ partials,
+                                                      int nblk, Prepared A, Prepared B,
+                                                      int64_t n_a, int64_t n_b,
+                                                      shape_result* __restrict__ out) {
+  __shared__ double red[4 * 2 * kEstSums];
+  double v[2 * kEstSums];
+#pragma unroll
+  for (int j = 0; j < 2 * kEstSums; ++j) v[j] = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
+#pragma unroll
+    for (int side = 0; side < 2; ++side)
+#pragma unroll
+      for (int j = 0; j < kEstSums; ++j)
+        v[side * kEstSums + j] += partials[((size_t)side * nblk + b) * kEstSums + j];
+  }
+  block_sum<2 * kEstSums>(v, red);
+  if (threadIdx.x != 0) return;
+  const double Za = A.Z[0], Zb = B.Z[0];
+  const double na = (double)n_a, nb = (double)n_b;
+  const double* a = v;
+  const double* b = v + kEstSums;
+  auto mom = [](double n, const double* s, int j) { return Moments{n, s[2 * j], s[2 * j + 1]}; };
+  const Moments a1 = mom(na, a, 0), a2 = mom(na, a, 1), a3 = mom(na, a, 2), a4 = mom(na, a, 3),
+                a5 = mom(na, a, 4);
+  const Moments b1 = mom(nb, b, 0), b2 = mom(nb, b, 1), b3 = mom(nb, b, 2), b4 = mom(nb, b, 3),
+                b5 = mom(nb, b, 4);
+  const double cov_a = (a[10] - a[0] * a[2] / na) / (na - 1.0);
+  const double cov_b = (b[10] - b[0] * b[2] / nb) / (nb - 1.0);
+  shape_result r;
+  r.O_ab_from_a = Za * a1.mean();
+  r.O_ab_from_b = Zb * b1.mean();
+  const double se_xa = Za * sqrt(a1.var() / na), se_xb = Zb * sqrt(b1.var() / nb);
+  r.O_ab = 0.5 * (r.O_ab_from_a + r.O_ab_from_b);
+  r.se_O_ab = 0.5 * sqrt(se_xa * se_xa + se_xb * se_xb);
+  r.O_aa = Za * a2.mean();
+  r.O_bb = Zb * b2.mean();
+  r.se_O_aa = Za * sqrt(a2.var() / na);
+  r.se_O_bb = Zb * sqrt(b2.var() / nb);
+  r.V_a = Za * a3.mean();
+  r.V_b = Zb * b3.mean();
+  r.se_V_a = Za * sqrt(a3.var() / na);
+  r.se_V_b = Zb * sqrt(b3.var() / nb);
+  r.Ofo_ab_is = 0.5 * (Za * a4.mean() + Zb * b4.mean());
+  r.Ofo_aa_is = Za * a5.mean();
+  r.Ofo_bb_is = Zb * b5.mean();
+  const double S = r.O_aa + r.O_bb, D = S - r.O_ab;
+  r.T = r.O_ab / D;
+  r.se_T = fabs(S / (D * D)) * r.se_O_ab;
+  const double g_ab = S / (D * D), g_s = -r.O_ab / (D * D);
+  const double var_s = r.se_O_aa * r.se_O_aa + r.se_O_bb * r.se_O_bb;
+  const double cov = 0.5 * Za * Za * cov_a / na + 0.5 * Zb * Zb * cov_b / nb;
+  const double vt = g_ab * g_ab * r.se_O_ab * r.se_O_ab + g_s * g_s * var_s + 2.0 * g_ab * g_s * cov;
+  r.se_T_full = sqrt(vt > 0.0 ? vt : 0.0);
+  r.n_a = n_a;
+  r.n_b = n_b;
+  *out = r;
+}
+
+// ---------------------------------------------------------------------------
+// Query-side sample cache for screening: the query's own samples, weights and
+// self integrand are the same for every library partner (random numbers are
+// keyed by molecule), so they are computed once per call.
+//   qs[k] = (r_k, w_A(r_k)),  qf2[k] = w_A u_A at r_k.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_query_cache(Prepared Qp, const int* __restrict__ offQ,
+                                                     int64_t n, uint2 key,
+                                                     float4* __restrict__ qs,
+                                                     float* __restrict__ qf2) {
+  __shared__ Atom sQ[SHAPE_MAX_ATOMS];
+  __shared__ AtomSampling sS[SHAPE_MAX_ATOMS];
+  // an invalid query is never staged (its atom count is not trusted); the
+  // screening kernel then reports every pair as NaN without reading the cache
+  if (Qp.bad[0] != 0) return;
+  const int q0 = offQ[0], nq = offQ[1] - offQ[0];
+  for (int i = threadIdx.x; i < nq; i += blockDim.x) {
+    sQ[i] = Qp.atom[q0 + i];
+    sS[i] = Qp.samp[q0 + i];
+  }
+  __syncthreads();
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  float rx[1], ry[1], rz[1];
+  sample_point(sQ, sS, nq, Qp.id[0], (uint64_t)k, key, rx[0], ry[0], rz[0]);
+  float m[1] = {0.0f}, q[1] = {1.0f};
+  eval_density<1>(sQ, nq, rx, ry, rz, m, q);
+  const float u = 1.0f - q[0];
+  const float w = bounded_weight(u, m[0]);
+  qs[k] = make_float4(rx[0], ry[0], rz[0], w);
+  qf2[k] = w * u;
+}
+
+// ---------------------------------------------------------------------------
+// Screening kernel: one single-wave workgroup per (query, library) pair, so
+// the pair index comes from blockIdx and is uniform by construction (no
+// cross-lane broadcast); the hardware dispatcher balances pairs of uneven
+// size.  Per round, `round_side` samples on each side:
+//   side A (query samples, from the cache): f1 = w_A u_B, f2 = w_A u_A
+//   side B (library samples, drawn here):   f1 = w_B u_A, f2 = w_B u_B
+// FP32 in-lane sums per round, FP64 lane accumulators across rounds, wave
+// butterflies for the pair totals (every lane ends with the same value).
+// Adaptive mode takes the stopping decision on SE(T) in FP64 after every
+// round; the decision is read from the first lane so the branch is scalar.
+// ---------------------------------------------------------------------------
+constexpr int kSA = 4;  // side-A points per lane evaluated together
+constexpr int kSB = 2;  // side-B points per lane evaluated together
+
+__device__ __forceinline__ double se_tanimoto(double n, double Za, double Zb, double a1,
+                                              double a11, double a2, double b1, double b11,
+                                              double b2, double* T_out, double* Oab_out,
+                                              double* Oaa_out, double* Obb_out) {
+  const double xa = Za * a1 / n, xb = Zb * b1 / n;
+  double va = (a11 - a1 * a1 / n) / (n - 1.0);
+  double vb = (b11 - b1 * b1 / n) / (n - 1.0);
+  va = va > 0.0 ? va : 0.0;
+  vb = vb > 0.0 ? vb : 0.0;
+  const double se_a = Za * sqrt(va / n), se_b = Zb * sqrt(vb / n);
+  const double O_ab = 0.5 * (xa + xb);
+  const double se_O = 0.5 * sqrt(se_a * se_a + se_b * se_b);
+  const double O_aa = Za * a2 / n, O_bb = Zb * b2 / n;
+  const double S = O_aa + O_bb, D = S - O_ab;
+  if (T_out) *T_out = O_ab / D;
+  if (Oab_out) *Oab_out = O_ab;
+  if (Oaa_out) *Oaa_out = O_aa;
+  if (Obb_out) *Obb_out = O_bb;
+  return fabs(S / (D * D)) * se_O;
+}
+
+__global__ __launch_bounds__(64) void k_screen(ScreenArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  Atom* sQ = reinterpret_cast<Atom*>(smem);
+  Atom* sB = sQ + a.max_q;
+  AtomSampling* sBS = reinterpret_cast<AtomSampling*>(sB + a.max_b);
+  const int lane = threadIdx.x;
+  const int p = blockIdx.x;
+  if (p >= a.n_pairs) return;
+  const int m = a.pairs ? a.pairs[p] : p;
+  const bool bad = a.Q.bad[0] != 0 || m < 0 || m >= a.n_lib || a.L.bad[m] != 0;
+  if (bad) {
+    if (lane == 0) {
+      const float nanv = __builtin_nanf("");
+      a.T[p] = nanv;
+      a.se_T[p] = nanv;
+      if (a.O_ab) a.O_ab[p] = nanv;
+      if (a.O_aa) a.O_aa[p] = nanv;
+      if (a.O_bb) a.O_bb[p] = nanv;
+      if (a.n_used) a.n_used[p] = 0;
+    }
+    return;
+  }
+  const int q0 = a.offQ[0], nq = a.offQ[1] - a.offQ[0];
+  const int b0 = a.offL[m], nb = a.offL[m + 1] - b0;
+  for (int i = lane; i < nq; i += kWave) sQ[i] = a.Q.atom[q0 + i];
+  for (int i = lane; i < nb; i += kWave) {
+    sB[i] = a.L.atom[b0 + i];
+    sBS[i] = a.L.samp[b0 + i];
+  }
+  __syncthreads();
+  const double Za = a.Q.Z[0];
+  const uint32_t idb = a.L.id[m];
+  const double Zb = a.L.Z[m];
+  const int rs = a.round_side;
+  const int per_lane = rs / kWave;
+  double acc[10];
+#pragma unroll
+  for (int j = 0; j < 10; ++j) acc[j] = 0.0;
+  int64_t n_side = 0;
+  for (;;) {
+    float fa[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+    float fb[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+    // side A: query samples from the cache, partner = library molecule
+    for (int t = 0; t < per_lane; t += kSA) {
+      float rx[kSA], ry[kSA], rz[kSA], w[kSA], f2[kSA], q[kSA], valid[kSA];
+#pragma unroll
+      for (int s = 0; s < kSA; ++s) {
+        const bool ok = (t + s) < per_lane;
+        const int64_t k = n_side + (int64_t)lane + (int64_t)kWave * (ok ? t + s : t);
+        const float4 c = a.qs[k];
+        rx[s] = c.x; ry[s] = c.y; rz[s] = c.z; w[s] = c.w;
+        f2[s] = a.qf2[k];
+        q[s] = 1.0f;
+        valid[s] = ok ? 1.0f : 0.0f;
+      }
+      eval_union<kSA>(sB, nb, rx, ry, rz, q);
+#pragma unroll
+      for (int s = 0; s < kSA; ++s) {
+        const float f1 = w[s] * (1.0f - q[s]) * valid[s];
+        const float g2 = f2[s] * valid[s];
+        fa[0] += f1; fa[1] += f1 * f1;
+        fa[2] += g2; fa[3] += g2 * g2;
+        fa[4] += f1 * g2;
+      }
+    }
+    // side B: library samples drawn here, partner = query
+    for (int t = 0; t < per_lane; t += kSB) {
+      float rx[kSB], ry[kSB], rz[kSB], mb[kSB], qb[kSB], qa[kSB], valid[kSB];
+#pragma unroll
+      for (int s = 0; s < kSB; ++s) {
+        const bool ok = (t + s) < per_lane;
+        const int64_t k = n_side + (int64_t)lane + (int64_t)kWave * (ok ? t + s : t);
+        sample_point(sB, sBS, nb, idb, (uint64_t)k, a.key, rx[s], ry[s], rz[s]);
+        mb[s] = 0.0f; qb[s] = 1.0f; qa[s] = 1.0f;
+        valid[s] = ok ? 1.0f : 0.0f;
+      }
+      eval_density<kSB>(sB, nb, rx, ry, rz, mb, qb);
+      eval_union<kSB>(sQ, nq, rx, ry, rz, qa);
+#pragma unroll
+      for (int s = 0; s < kSB; ++s) {
+        const float ub = 1.0f - qb[s];
+        const float w = bounded_weight(ub, mb[s]) * valid[s];
+        const float f1 = w * (1.0f - qa[s]);
+        const float f2 = w * ub;
+        fb[0] += f1; fb[1] += f1 * f1;
+        fb[2] += f2; fb[3] += f2 * f2;
+        fb[4] += f1 * f2;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+      acc[j] += (double)fa[j];
+      acc[5 + j] += (double)fb[j];
+    }
+    n_side += rs;
+    int stop;
+    if (a.mode == SHAPE_SCREEN_ADAPTIVE) {
+      const double sa1 = wave_sum(acc[0]), sa11 = wave_sum(acc[1]), sa2 = wave_sum(acc[2]);
+      const double sb1 = wave_sum(acc[5]), sb11 = wave_sum(acc[6]), sb2 = wave_sum(acc[7]);
+      const double se = se_tanimoto((double)n_side, Za, Zb, sa1, sa11, sa2, sb1, sb11, sb2,
+                                    nullptr, nullptr, nullptr, nullptr);
+      stop = (se <= a.tau || 2 * n_side >= a.cap_pair) ? 1 : 0;
+    } else {
+      stop = n_side >= a.n_fixed ? 1 : 0;
+    }
+    if (__builtin_amdgcn_readfirstlane(stop)) break;
+  }
+  double tot[10];
+#pragma unroll
+  for (int j = 0; j < 10; ++j) tot[j] = wave_sum(acc[j]);
+  if (lane == 0) {
+    double T, O_ab, O_aa, O_bb;
+    const double se = se_tanimoto((double)n_side, Za, Zb, tot[0], tot[1], tot[2], tot[5],
+                                  tot[6], tot[7], &T, &O_ab, &O_aa, &O_bb);
+    a.T[p] = (float)T;
+    a.se_T[p] = (float)se;
+    if (a.O_ab) a.O_ab[p] = (float)O_ab;
+    if (a.O_aa) a.O_aa[p] = (float)O_aa;
+    if (a.O_bb) a.O_bb[p] = (float)O_bb;
+    if (a.n_used) a.n_used[p] = (int)(2 * n_side);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers.
+// ---------------------------------------------------------------------------
+hipError_t launch_alpha_from_radius(const float* R, int64_t n, double kappa, double lambda,
+                                    float* alpha, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const int64_t blocks = (n + 255) / 256;
+  hipLaunchKernelGGL(k_alpha_from_radius, dim3((unsigned)blocks), dim3(256), 0, st, R, n, kappa,
+                     lambda, alpha);
+  return hipGetLastError();
+}
+
+hipError_t launch_prepare(const MolsDev& in, const Prepared& out, int* flag, hipStream_t st) {
+  const int blocks = (in.n_mols + 255) / 256;
+  hipLaunchKernelGGL(k_prepare, dim3(blocks), dim3(256), 0, st, in, out, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_int(int* p, int n, int v, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill_int, dim3((n + 255) / 256), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+int est_blocks(int64_t n) { return (int)((n + 256 * kEstSPT - 1) / (256 * kEstSPT)); }
+
+hipError_t launch_estimate(const Prepared& A, const Prepared& B, const int* offA,
+                           const int* offB, int64_t n_a, int64_t n_b, uint2 key,
+                           double* partials, int nblk, shape_result* out_dev, hipStream_t st) {
+  hipLaunchKernelGGL(k_est_partials, dim3(nblk, 2), dim3(256), 0, st, A, B, n_a, n_b, key,
+                     partials, nblk, offA, offB);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_est_finalize, dim3(1), dim3(256), 0, st, partials, nblk, A, B, n_a, n_b,
+                     out_dev);
+  return hipGetLastError();
+}
+
+hipError_t launch_query_cache(const Prepared& Q, const int* offQ, int64_t n, uint2 key,
+                              float4* qs, float* qf2, hipStream_t st) {
+  const int64_t blocks = (n + 255) / 256;
+  hipLaunchKernelGGL(k_query_cache, dim3((unsigned)blocks), dim3(256), 0, st, Q, offQ, n, key,
+                     qs, qf2);
+  return hipGetLastError();
+}
+
+size_t screen_lds_bytes(int max_q, int max_b) {
+  return (size_t)max_q * sizeof(Atom) + (size_t)max_b * (sizeof(Atom) + sizeof(AtomSampling));
+}
+
+hipError_t launch_screen(const ScreenArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(k_screen, dim3((unsigned)a.n_pairs), dim3(kWave),
+                     screen_lds_bytes(a.max_q, a.max_b), st, a);
+  return hipGetLastError();
+}
+
+}  // namespace shape

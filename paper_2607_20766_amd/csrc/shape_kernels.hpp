@@ -1,0 +1,74 @@
+// Kernel-side structures and host launchers shared by the kernels and the
+// C-ABI layer of the IS shape-overlap engine.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "shape_device.hpp"
+#include "shape_is.h"
+
+namespace shape {
+
+constexpr int kEstSums = 11;
+
+// Molecule set as handed over through the C ABI.
+struct MolsDev {
+  int n_mols;
+  int max_atoms;
+  int64_t n_atoms;
+  const int* off;
+  const float* xyz;
+  const float* alpha;
+  const uint32_t* id;
+};
+
+// Prepared per-atom / per-molecule records (context scratch).
+struct Prepared {
+  Atom* atom;
+  AtomSampling* samp;
+  double* Z;
+  uint32_t* id;
+  int* bad;
+};
+
+struct ScreenArgs {
+  Prepared Q;
+  const int* offQ;
+  int max_q;
+  Prepared L;
+  const int* offL;
+  int n_lib;
+  int max_b;
+  const float4* qs;
+  const float* qf2;
+  const int* pairs;
+  int n_pairs;
+  int mode;
+  int64_t n_fixed;     // fixed mode: samples per side
+  int round_side;      // samples per side per round (multiple of 64)
+  int64_t cap_pair;    // adaptive cap, samples per pair
+  double tau;
+  uint2 key;
+  float* T;
+  float* se_T;
+  float* O_ab;
+  float* O_aa;
+  float* O_bb;
+  int* n_used;
+};
+
+hipError_t launch_alpha_from_radius(const float* R, int64_t n, double kappa, double lambda,
+                                    float* alpha, hipStream_t st);
+hipError_t launch_prepare(const MolsDev& in, const Prepared& out, int* flag, hipStream_t st);
+hipError_t launch_fill_int(int* p, int n, int v, hipStream_t st);
+int est_blocks(int64_t n);
+hipError_t launch_estimate(const Prepared& A, const Prepared& B, const int* offA,
+                           const int* offB, int64_t n_a, int64_t n_b, uint2 key,
+                           double* partials, int nblk, shape_result* out_dev, hipStream_t st);
+hipError_t launch_query_cache(const Prepared& Q, const int* offQ, int64_t n, uint2 key,
+                              float4* qs, float* qf2, hipStream_t st);
+size_t screen_lds_bytes(int max_q, int max_b);
+hipError_t launch_screen(const ScreenArgs& a, hipStream_t st);
+
+}  // namespace shape

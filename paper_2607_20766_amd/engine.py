@@ -1,0 +1,223 @@
+"""Thin Python binding of the C ABI in include/shape_is.h.
+
+Argument marshalling only: torch provides device memory and the HIP stream,
+every step of the computation runs in the HIP library.  The library must be
+built (``python -m paper_2607_20766_amd.build``); there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libshape_is.so")
+
+SHAPE_OK = 0
+SHAPE_SCREEN_FIXED = 0
+SHAPE_SCREEN_ADAPTIVE = 1
+SHAPE_MAX_ATOMS = 256
+
+# Eq. occ width convention of the synthetic workloads: a Gaussian height
+# p = 2.7 in the Grant-Pickup width corresponds to lambda = p^(-2/3).
+LAMBDA_P27 = 2.7 ** (-2.0 / 3.0)
+
+ERRORS = {-1: "SHAPE_E_INVAL", -2: "SHAPE_E_RANGE", -3: "SHAPE_E_NOMEM",
+          -4: "SHAPE_E_HIP", -5: "SHAPE_E_UNSUPPORTED", -6: "SHAPE_E_DATA"}
+
+
+class ShapeError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class ShapeMols(ctypes.Structure):
+    _fields_ = [("n_mols", ctypes.c_int32), ("max_atoms", ctypes.c_int32),
+                ("n_atoms", ctypes.c_int64), ("atom_offset", ctypes.c_void_p),
+                ("xyz", ctypes.c_void_p), ("alpha", ctypes.c_void_p),
+                ("mol_id", ctypes.c_void_p)]
+
+
+RESULT_FIELDS = ("O_ab", "O_aa", "O_bb", "V_a", "V_b", "T",
+                 "se_O_ab", "se_O_aa", "se_O_bb", "se_V_a", "se_V_b", "se_T",
+                 "se_T_full", "O_ab_from_a", "O_ab_from_b", "Ofo_ab_is",
+                 "Ofo_aa_is", "Ofo_bb_is")
+
+
+class ShapeResult(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_double) for f in RESULT_FIELDS] + [
+        ("n_a", ctypes.c_int64), ("n_b", ctypes.c_int64)]
+
+
+class ShapeScreenParams(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("n_per_side", ctypes.c_int32),
+                ("round_per_pair", ctypes.c_int32), ("cap_per_pair", ctypes.c_int32),
+                ("tau", ctypes.c_double), ("seed", ctypes.c_uint64)]
+
+
+class ShapeScreenOut(ctypes.Structure):
+    _fields_ = [("T", ctypes.c_void_p), ("se_T", ctypes.c_void_p),
+                ("O_ab", ctypes.c_void_p), ("O_aa", ctypes.c_void_p),
+                ("O_bb", ctypes.c_void_p), ("n_used", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def load_library():
+    """Load libshape_is.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2607_20766_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, u64, d = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
+                                ctypes.c_uint64, ctypes.c_double)
+        L.shape_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int]
+        L.shape_destroy.argtypes = [vp]
+        L.shape_destroy.restype = None
+        L.shape_last_error.argtypes = [vp]
+        L.shape_last_error.restype = ctypes.c_char_p
+        L.shape_version.restype = ctypes.c_char_p
+        L.shape_alpha_from_radius.argtypes = [vp, vp, i64, d, vp, vp]
+        L.shape_estimate.argtypes = [vp, ctypes.POINTER(ShapeMols), ctypes.POINTER(ShapeMols),
+                                     i64, i64, u64, vp, ctypes.POINTER(ShapeResult)]
+        L.shape_screen.argtypes = [vp, ctypes.POINTER(ShapeMols), ctypes.POINTER(ShapeMols),
+                                   vp, i32, ctypes.POINTER(ShapeScreenParams), vp,
+                                   ctypes.POINTER(ShapeScreenOut)]
+        L.shape_check_data.argtypes = [vp, vp]
+        _lib = L
+    return _lib
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+@dataclasses.dataclass
+class Molecules:
+    """A molecule set resident on the device (CSR layout, see shape_mols)."""
+
+    offsets: torch.Tensor  # int32 [n_mols + 1]
+    xyz: torch.Tensor      # float32 [n_atoms, 3]
+    alpha: torch.Tensor    # float32 [n_atoms]
+    mol_id: torch.Tensor | None  # int32 [n_mols] (bit pattern of uint32 ids) or None
+    max_atoms: int
+
+    @property
+    def n_mols(self) -> int:
+        return int(self.offsets.shape[0] - 1)
+
+    @property
+    def n_atoms(self) -> int:
+        return int(self.xyz.shape[0])
+
+    def c_struct(self) -> ShapeMols:
+        return ShapeMols(self.n_mols, self.max_atoms, self.n_atoms,
+                         self.offsets.data_ptr(), self.xyz.data_ptr(),
+                         self.alpha.data_ptr(),
+                         None if self.mol_id is None else self.mol_id.data_ptr())
+
+
+class Engine:
+    """One library context on one HIP device."""
+
+    def __init__(self, device: int = 0):
+        L = load_library()
+        self.device = device
+        self._ctx = ctypes.c_void_p()
+        rc = L.shape_create(ctypes.byref(self._ctx), device)
+        if rc != SHAPE_OK:
+            raise ShapeError(rc, L.shape_last_error(None).decode())
+        self.torch_device = torch.device("cuda", device)
+
+    def close(self):
+        if self._ctx:
+            load_library().shape_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc != SHAPE_OK:
+            raise ShapeError(rc, load_library().shape_last_error(self._ctx).decode())
+
+    # -- molecule upload -------------------------------------------------------
+    def alpha_from_radius(self, radius: torch.Tensor, lam: float = LAMBDA_P27,
+                          stream=None) -> torch.Tensor:
+        radius = radius.contiguous()
+        alpha = torch.empty_like(radius)
+        self._check(load_library().shape_alpha_from_radius(
+            self._ctx, _ptr(radius), radius.numel(), float(lam), _ptr(alpha), _stream(stream)))
+        return alpha
+
+    def molecules(self, molset, lam: float = LAMBDA_P27, mol_id=None) -> Molecules:
+        """Upload a host MolSet (geometry + radii); widths come from
+        shape_alpha_from_radius on the device."""
+        dev = self.torch_device
+        off = torch.from_numpy(np.ascontiguousarray(molset.offsets, np.int32)).to(dev)
+        xyz = torch.from_numpy(np.ascontiguousarray(molset.xyz, np.float32)).to(dev)
+        rad = torch.from_numpy(np.ascontiguousarray(molset.radius, np.float32)).to(dev)
+        alpha = self.alpha_from_radius(rad, lam)
+        ids = None
+        if mol_id is not None:
+            ids = torch.from_numpy(
+                np.ascontiguousarray(np.asarray(mol_id, np.uint32).view(np.int32))).to(dev)
+        max_atoms = int(np.max(np.diff(molset.offsets))) if molset.n_mols else 1
+        return Molecules(off, xyz, alpha, ids, max_atoms)
+
+    # -- estimator ---------------------------------------------------------------
+    def shape_estimate(self, A: Molecules, B: Molecules, n_a: int, n_b: int,
+                       seed: int = 0, stream=None) -> dict:
+        res = ShapeResult()
+        a, b = A.c_struct(), B.c_struct()
+        self._check(load_library().shape_estimate(self._ctx, ctypes.byref(a), ctypes.byref(b),
+                                                  int(n_a), int(n_b), int(seed),
+                                                  _stream(stream), ctypes.byref(res)))
+        out = {f: getattr(res, f) for f in RESULT_FIELDS}
+        out["n_a"], out["n_b"] = res.n_a, res.n_b
+        return out
+
+    def shape_screen(self, query: Molecules, lib: Molecules, *, mode: int = SHAPE_SCREEN_FIXED,
+                     n_per_side: int = 4096, round_per_pair: int = 512,
+                     cap_per_pair: int = 65536, tau: float = 0.005, seed: int = 0,
+                     pairs: torch.Tensor | None = None, n_pairs: int | None = None,
+                     out: dict | None = None, stream=None) -> dict:
+        """Screen the query against library molecules; returns device tensors
+        T, se_T, O_ab, O_aa, O_bb (float32) and n_used (int32) per pair."""
+        if pairs is not None:
+            pairs = pairs.to(torch.int32).contiguous()
+            n = int(pairs.numel())
+        else:
+            n = lib.n_mols if n_pairs is None else int(n_pairs)
+        if out is None:
+            dev = self.torch_device
+            out = {k: torch.empty(n, dtype=torch.float32, device=dev)
+                   for k in ("T", "se_T", "O_ab", "O_aa", "O_bb")}
+            out["n_used"] = torch.empty(n, dtype=torch.int32, device=dev)
+        prm = ShapeScreenParams(mode, n_per_side, round_per_pair, cap_per_pair, tau, seed)
+        o = ShapeScreenOut(*(out[k].data_ptr() if out.get(k) is not None else None
+                             for k in ("T", "se_T", "O_ab", "O_aa", "O_bb", "n_used")))
+        q, l_ = query.c_struct(), lib.c_struct()
+        self._check(load_library().shape_screen(self._ctx, ctypes.byref(q), ctypes.byref(l_),
+                                                _ptr(pairs), n, ctypes.byref(prm),
+                                                _stream(stream), ctypes.byref(o)))
+        return out
+
+    def shape_check_data(self, stream=None):
+        self._check(load_library().shape_check_data(self._ctx, _stream(stream)))

@@ -1,0 +1,158 @@
+"""GPU parity of screening (shape_screen) against the FP64 oracle on identical
+samples: fixed budgets and confidence-bounded adaptive rounds, small
+libraries in full and the 100,000-molecule library on sampled pairs."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2607_20766_amd import molgen
+from paper_2607_20766_amd.engine import (Engine, LAMBDA_P27, SHAPE_SCREEN_ADAPTIVE,
+                                         SHAPE_SCREEN_FIXED, ShapeError)
+from tests.gpu_common import oracle_mol, rel_err, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+QUERY_ID = 0xFFFFFF00
+
+
+@pytest.fixture(scope="module")
+def eng():
+    require_gpu()
+    return Engine(0)
+
+
+@pytest.fixture(scope="module")
+def small_lib():
+    q = molgen.molecule(1, 0, 30)
+    L = molgen.library(11, 61, 10, 50, workers=1)  # ragged: not a multiple of 4 waves
+    return q, L
+
+
+def _oracle_screen(q, L, **kw):
+    la = O.alpha_from_radius(L.radius, LAMBDA_P27)
+    return O.screen(oracle_mol(O, q), QUERY_ID, L.offsets, L.xyz, la, **kw)
+
+
+def _to_np(out):
+    return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+def _compare(g, r, idx=None, tol=1e-5, se_tol=1e-4):
+    if idx is None:
+        idx = np.arange(r.shape[0])
+    assert np.all(rel_err(g["T"][idx], r[:, 0]) <= tol), np.max(rel_err(g["T"][idx], r[:, 0]))
+    assert np.all(rel_err(g["O_ab"][idx], r[:, 2], floor=1e-3) <= tol)
+    assert np.all(rel_err(g["O_aa"][idx], r[:, 3]) <= tol)
+    assert np.all(rel_err(g["O_bb"][idx], r[:, 4]) <= tol)
+    assert np.all(rel_err(g["se_T"][idx], r[:, 1], floor=1e-9) <= se_tol)
+
+
+@pytest.mark.parametrize("n_side", [4096, 320])
+def test_fixed_small_library(eng, small_lib, n_side):
+    q, L = small_lib
+    print(f"case: fixed screen, 61 molecules, n_side={n_side}", flush=True)
+    Q = eng.molecules(q, mol_id=[QUERY_ID])
+    lib = eng.molecules(L)
+    g = _to_np(eng.shape_screen(Q, lib, mode=SHAPE_SCREEN_FIXED, n_per_side=n_side, seed=7))
+    torch.cuda.synchronize()
+    r = _oracle_screen(q, L, mode=0, n_fixed=n_side, seed=7)
+    _compare(g, r)
+    assert np.all(g["n_used"] == 2 * n_side)
+
+
+def test_fixed_pair_subset_and_self(eng, small_lib):
+    q, L = small_lib
+    # put the query itself into the library with the query's stream id
+    Lq = molgen.MolSet.concat([L, q])
+    ids = np.arange(Lq.n_mols, dtype=np.uint32)
+    ids[-1] = QUERY_ID
+    Q = eng.molecules(q, mol_id=[QUERY_ID])
+    lib = eng.molecules(Lq, mol_id=ids)
+    pairs = torch.tensor([Lq.n_mols - 1, 5, 5, 0, 60], dtype=torch.int32, device="cuda")
+    g = _to_np(eng.shape_screen(Q, lib, n_per_side=1024, seed=2, pairs=pairs))
+    assert g["T"][0] == 1.0
+    assert g["T"][1] == g["T"][2]
+    la = O.alpha_from_radius(Lq.radius, LAMBDA_P27)
+    r = O.screen(oracle_mol(O, q), QUERY_ID, Lq.offsets, Lq.xyz, la, lib_id=ids,
+                 pairs=pairs.cpu().numpy(), mode=0, n_fixed=1024, seed=2)
+    _compare(g, r)
+
+
+def test_adaptive_small_library(eng, small_lib):
+    q, L = small_lib
+    tau, cap = 0.005, 65536
+    print("case: adaptive screen, 61 molecules, tau=0.005", flush=True)
+    Q = eng.molecules(q, mol_id=[QUERY_ID])
+    lib = eng.molecules(L)
+    g = _to_np(eng.shape_screen(Q, lib, mode=SHAPE_SCREEN_ADAPTIVE, round_per_pair=512,
+                                cap_per_pair=cap, tau=tau, seed=1))
+    r = _oracle_screen(q, L, mode=1, round_per_pair=512, cap_per_pair=cap, tau=tau, seed=1)
+    n_g = g["n_used"]
+    n_r = r[:, 5].astype(np.int64)
+    # both sides decide in FP64; a decision may differ only where SE(T) sits
+    # within FP32 rounding of tau, then compare at the GPU's sample count
+    same = n_g == n_r
+    assert same.mean() >= 0.95
+    _compare(g, r[same], idx=np.nonzero(same)[0])
+    for p in np.nonzero(~same)[0]:
+        a0, a1 = L.offsets[p], L.offsets[p + 1]
+        ref = O.estimate(oracle_mol(O, q),
+                         (L.xyz[a0:a1], O.alpha_from_radius(L.radius[a0:a1], LAMBDA_P27)),
+                         n_g[p] // 2, n_g[p] // 2, seed=1, id_a=QUERY_ID, id_b=p)
+        assert abs(ref["se_T"] - tau) <= 1e-4 * tau or n_g[p] == cap
+        assert rel_err(g["T"][p], ref["T"]) <= 1e-5
+    assert np.all((g["se_T"] <= tau * (1 + 1e-6)) | (n_g == cap))
+    assert np.all(n_g % 512 == 0)
+
+
+def test_adaptive_tiny_and_huge_tau(eng, small_lib):
+    q, L = small_lib
+    Q = eng.molecules(q, mol_id=[QUERY_ID])
+    lib = eng.molecules(L)
+    g = _to_np(eng.shape_screen(Q, lib, mode=SHAPE_SCREEN_ADAPTIVE, round_per_pair=512,
+                                cap_per_pair=2048, tau=1e-9, seed=1))
+    assert np.all(g["n_used"] == 2048)
+    g = _to_np(eng.shape_screen(Q, lib, mode=SHAPE_SCREEN_ADAPTIVE, round_per_pair=512,
+                                cap_per_pair=2048, tau=1e9, seed=1))
+    assert np.all(g["n_used"] == 512)
+    f = _to_np(eng.shape_screen(Q, lib, mode=SHAPE_SCREEN_FIXED, n_per_side=256, seed=1))
+    assert np.array_equal(g["T"], f["T"])  # one adaptive round == fixed 256 per side
+
+
+def test_full_library_sampled_pairs(eng):
+    """configs[1] workload: 30-atom query vs 100,000 molecules (10-50 atoms),
+    4096 samples per side; 96 pairs spread over the library checked against
+    the oracle one by one."""
+    q = molgen.molecule(1, 0, 30)
+    L = molgen.library(1, 100000, 10, 50)
+    print("case: full 100k library fixed 4096", flush=True)
+    Q = eng.molecules(q, mol_id=[QUERY_ID])
+    lib = eng.molecules(L)
+    g = _to_np(eng.shape_screen(Q, lib, n_per_side=4096, seed=0))
+    assert np.all(np.isfinite(g["T"]))
+    idx = np.unique(np.concatenate([np.arange(8), np.arange(99992, 100000),
+                                    np.random.default_rng(0).integers(0, 100000, 80)]))
+    r = _oracle_screen(q, L, pairs=idx.astype(np.int32), mode=0, n_fixed=4096, seed=0)
+    _compare({k: v[idx] for k, v in g.items()}, r)
+    # repeatable bit for bit
+    g2 = _to_np(eng.shape_screen(Q, lib, n_per_side=4096, seed=0))
+    for k in g:
+        assert np.array_equal(g[k], g2[k])
+
+
+def test_invalid_molecules_flagged(eng, small_lib):
+    q, L = small_lib
+    Q = eng.molecules(q, mol_id=[QUERY_ID])
+    lib = eng.molecules(L)
+    lib.alpha[int(L.offsets[4])] = -1.0
+    g = _to_np(eng.shape_screen(Q, lib, n_per_side=256, seed=0))
+    assert np.isnan(g["T"][4]) and np.all(np.isfinite(np.delete(g["T"], 4)))
+    with pytest.raises(ShapeError) as e:
+        eng.shape_check_data()
+    assert e.value.code == -6
+    eng.shape_check_data()  # flag cleared
+    with pytest.raises(ShapeError):
+        eng.shape_screen(Q, lib, n_per_side=100)
+    out = eng.shape_screen(Q, lib, n_per_side=256, n_pairs=0)
+    assert out["T"].numel() == 0
