@@ -191,6 +191,16 @@ int shape_screen(shape_ctx* ctx, const shape_mols* query, const shape_mols* lib,
  * (SHAPE_OK); clears the flag. */
 int shape_check_data(shape_ctx* ctx, void* stream);
 
+/* Kernel timing (measurement support, not part of the method).  While
+ * enabled, every call records a pair of HIP events on its stream around its
+ * dominant kernel (the screening kernel of shape_screen, the sample kernel of
+ * shape_estimate).  shape_timing_read synchronises those events and returns
+ * the summed kernel time in milliseconds and the number of launches since the
+ * last reset (host pointers; either may be NULL); reset != 0 clears them.
+ * Errors: SHAPE_E_INVAL, SHAPE_E_HIP. */
+int shape_timing_enable(shape_ctx* ctx, int enable);
+int shape_timing_read(shape_ctx* ctx, double* total_ms, int64_t* launches, int reset);
+
 #ifdef __cplusplus
 }
 #endif

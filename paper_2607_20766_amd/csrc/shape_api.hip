@@ -8,6 +8,8 @@
 #include <string.h>
 
 #include <string>
+#include <utility>
+#include <vector>
 
 #include "shape_is.h"
 #include "shape_kernels.hpp"
@@ -22,8 +24,8 @@ struct Buffer {
 };
 
 enum Slot {
-  S_Q_ATOM, S_Q_SAMP, S_Q_Z, S_Q_ID, S_Q_BAD,
-  S_L_ATOM, S_L_SAMP, S_L_Z, S_L_ID, S_L_BAD,
+  S_Q_ATOM, S_Q_SAMP, S_Q_Z, S_Q_ID, S_Q_BAD, S_Q_CENTRE,
+  S_L_ATOM, S_L_SAMP, S_L_Z, S_L_ID, S_L_BAD, S_L_CENTRE,
   S_PARTIALS, S_RESULT, S_QS, S_QF2,
   S_COUNT
 };
@@ -36,6 +38,8 @@ struct shape_ctx {
   std::string err;
   Buffer buf[S_COUNT];
   int* flag = nullptr;  // invalid-data flag (device int)
+  bool timing = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
 };
 
 namespace {
@@ -111,7 +115,7 @@ int check_mols(shape_ctx* c, const shape_mols* m, const char* name, bool single)
 // Prepare a molecule set into the query (q = true) or library slots.
 int prepare(shape_ctx* c, const shape_mols* m, bool q, hipStream_t st, shape::Prepared* P) {
   const int base = q ? S_Q_ATOM : S_L_ATOM;
-  void* p[5];
+  void* p[6];
   int rc;
   const size_t na = (size_t)m->n_atoms, nm = (size_t)m->n_mols;
   if ((rc = ensure(c, (Slot)(base + 0), na * sizeof(shape::Atom), &p[0]))) return rc;
@@ -119,11 +123,13 @@ int prepare(shape_ctx* c, const shape_mols* m, bool q, hipStream_t st, shape::Pr
   if ((rc = ensure(c, (Slot)(base + 2), nm * sizeof(double), &p[2]))) return rc;
   if ((rc = ensure(c, (Slot)(base + 3), nm * sizeof(uint32_t), &p[3]))) return rc;
   if ((rc = ensure(c, (Slot)(base + 4), nm * sizeof(int), &p[4]))) return rc;
+  if ((rc = ensure(c, (Slot)(base + 5), nm * sizeof(float4), &p[5]))) return rc;
   P->atom = (shape::Atom*)p[0];
   P->samp = (shape::AtomSampling*)p[1];
   P->Z = (double*)p[2];
   P->id = (uint32_t*)p[3];
   P->bad = (int*)p[4];
+  P->centre = (float4*)p[5];
   shape::MolsDev in{m->n_mols, m->max_atoms, m->n_atoms, m->atom_offset, m->xyz, m->alpha,
                     m->mol_id};
   HIP_TRY(c, shape::launch_prepare(in, *P, c->flag, st), "prepare kernel");
@@ -131,6 +137,25 @@ int prepare(shape_ctx* c, const shape_mols* m, bool q, hipStream_t st, shape::Pr
 }
 
 uint2 key_of(uint64_t seed) { return make_uint2((uint32_t)seed, (uint32_t)(seed >> 32)); }
+
+// Brackets the dominant kernel of a call with HIP events when timing is on.
+struct KernelTimer {
+  shape_ctx* c;
+  hipStream_t st;
+  hipEvent_t a = nullptr, b = nullptr;
+  KernelTimer(shape_ctx* c_, hipStream_t st_) : c(c_), st(st_) {
+    if (!c->timing) return;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess ||
+        hipEventRecord(a, st) != hipSuccess) {
+      a = b = nullptr;
+    }
+  }
+  void stop() {
+    if (!a) return;
+    if (hipEventRecord(b, st) == hipSuccess) c->events.emplace_back(a, b);
+    a = b = nullptr;
+  }
+};
 
 }  // namespace
 
@@ -176,6 +201,10 @@ void shape_destroy(shape_ctx* c) {
   (void)hipDeviceSynchronize();
   for (auto& b : c->buf)
     if (b.ptr) (void)hipFree(b.ptr);
+  for (auto& e : c->events) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
   if (c->flag) (void)hipFree(c->flag);
   delete c;
 }
@@ -234,10 +263,12 @@ int shape_estimate(shape_ctx* c, const shape_mols* A, const shape_mols* B, int64
       HIP_TRY(c, shape::launch_fill_int(c->flag, 1, 0, st), "flag reset");
       return fail(c, SHAPE_E_DATA, "invalid molecule data in %s", bad[0] ? "A" : "B");
     }
+    KernelTimer timer(c, st);
     HIP_TRY(c, shape::launch_estimate(PA, PB, A->atom_offset, B->atom_offset, n_a, n_b,
                                       key_of(seed), (double*)partials, nblk,
                                       (shape_result*)res, st),
             "estimate kernels");
+    timer.stop();
     HIP_TRY(c, hipMemcpyAsync(out, res, sizeof(shape_result), hipMemcpyDeviceToHost, st),
             "result copy");
     HIP_TRY(c, hipStreamSynchronize(st), "hipStreamSynchronize");
@@ -321,11 +352,42 @@ int shape_screen(shape_ctx* c, const shape_mols* query, const shape_mols* lib,
     a.O_aa = out->O_aa;
     a.O_bb = out->O_bb;
     a.n_used = out->n_used;
+    KernelTimer timer(c, st);
     HIP_TRY(c, shape::launch_screen(a, st), "screen kernel");
+    timer.stop();
     return SHAPE_OK;
   } catch (...) {
     return fail(c, SHAPE_E_HIP, "internal error");
   }
+}
+
+int shape_timing_enable(shape_ctx* c, int enable) {
+  if (!c) return SHAPE_E_INVAL;
+  c->timing = enable != 0;
+  return SHAPE_OK;
+}
+
+int shape_timing_read(shape_ctx* c, double* total_ms, int64_t* launches, int reset) {
+  if (!c) return SHAPE_E_INVAL;
+  int rc = set_device(c);
+  if (rc) return rc;
+  double sum = 0.0;
+  for (auto& e : c->events) {
+    HIP_TRY(c, hipEventSynchronize(e.second), "hipEventSynchronize");
+    float ms = 0.0f;
+    HIP_TRY(c, hipEventElapsedTime(&ms, e.first, e.second), "hipEventElapsedTime");
+    sum += ms;
+  }
+  if (total_ms) *total_ms = sum;
+  if (launches) *launches = (int64_t)c->events.size();
+  if (reset) {
+    for (auto& e : c->events) {
+      (void)hipEventDestroy(e.first);
+      (void)hipEventDestroy(e.second);
+    }
+    c->events.clear();
+  }
+  return SHAPE_OK;
 }
 
 int shape_check_data(shape_ctx* c, void* stream) {

@@ -112,6 +112,83 @@ __device__ __forceinline__ void eval_density(const Atom* __restrict__ atoms, int
   }
 }
 
+// ---------------------------------------------------------------------------
+// Expanded-quadratic atom records.  In a frame centred at `ref`, with
+// c' = c - ref and r' = r - ref, the exponent of o = exp2(-e) is
+//   e = a2 |r' - c'|^2 = a2 |r'|^2 + (-2 a2 c') . r' + a2 |c'|^2,
+// four fused multiply-adds per atom once |r'|^2 is known for the point.
+// Records are formed in FP64 and rounded once; frames keep |r'| at the size
+// of a molecule so the cancellation in e stays at FP32 rounding level.
+// ---------------------------------------------------------------------------
+struct __align__(16) AtomRec {
+  float bx, by, bz, c;  // -2 a2 c', a2 |c'|^2
+};
+
+__device__ __forceinline__ void make_rec(const Atom& a, float rx, float ry, float rz,
+                                         AtomRec& rec, float& a2) {
+  const double x = (double)a.x - (double)rx, y = (double)a.y - (double)ry,
+               z = (double)a.z - (double)rz;
+  const double k = (double)a.a2;
+  rec.bx = (float)(-2.0 * k * x);
+  rec.by = (float)(-2.0 * k * y);
+  rec.bz = (float)(-2.0 * k * z);
+  rec.c = (float)(k * (x * x + y * y + z * z));
+  a2 = a.a2;
+}
+
+__device__ __forceinline__ float occupancy_x(const AtomRec& b, float a2, float rx, float ry,
+                                             float rz, float r2) {
+  float e = fmaf(a2, r2, b.c);
+  e = fmaf(b.bx, rx, e);
+  e = fmaf(b.by, ry, e);
+  e = fmaf(b.bz, rz, e);
+  return __builtin_amdgcn_exp2f(-e);
+}
+
+// Union complement q = prod(1 - o_i) at S points (expanded form).
+template <int S>
+__device__ __forceinline__ void eval_union_x(const AtomRec* __restrict__ rec,
+                                             const float* __restrict__ a2, int n,
+                                             const float (&rx)[S], const float (&ry)[S],
+                                             const float (&rz)[S], const float (&r2)[S],
+                                             float (&q)[S]) {
+#pragma unroll 2
+  for (int i = 0; i < n; ++i) {
+    const AtomRec b = rec[i];
+    const float a = a2[i];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const float o = occupancy_x(b, a, rx[s], ry[s], rz[s], r2[s]);
+      q[s] = fmaf(-q[s], o, q[s]);
+    }
+  }
+}
+
+// First-order density m and union complement q at S points (expanded form).
+template <int S>
+__device__ __forceinline__ void eval_density_x(const AtomRec* __restrict__ rec,
+                                               const float* __restrict__ a2, int n,
+                                               const float (&rx)[S], const float (&ry)[S],
+                                               const float (&rz)[S], const float (&r2)[S],
+                                               float (&m)[S], float (&q)[S]) {
+#pragma unroll 2
+  for (int i = 0; i < n; ++i) {
+    const AtomRec b = rec[i];
+    const float a = a2[i];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const float o = occupancy_x(b, a, rx[s], ry[s], rz[s], r2[s]);
+      m[s] += o;
+      q[s] = fmaf(-q[s], o, q[s]);
+    }
+  }
+}
+
+// |r|^2 of a point.
+__device__ __forceinline__ float norm2(float x, float y, float z) {
+  return fmaf(x, x, fmaf(y, y, z * z));
+}
+
 // Bounded weight w = u/m in [0, 1] (m > 0 for every sampled point; guard 0).
 __device__ __forceinline__ float bounded_weight(float u, float m) {
   return m > 0.0f ? fminf(u / m, 1.0f) : 0.0f;

@@ -54,10 +54,18 @@ __global__ void k_prepare(MolsDev in, Prepared out, int* __restrict__ flag) {
   out.bad[m] = bad ? 1 : 0;
   if (bad) {
     out.Z[m] = __builtin_nan("");
+    out.centre[m] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     atomicOr(flag, 1);
     return;
   }
   out.Z[m] = Z;
+  double cx = 0.0, cy = 0.0, cz = 0.0;
+  for (int i = a0; i < a1; ++i) {
+    cx += (double)in.xyz[3 * i];
+    cy += (double)in.xyz[3 * i + 1];
+    cz += (double)in.xyz[3 * i + 2];
+  }
+  out.centre[m] = make_float4((float)(cx / n), (float)(cy / n), (float)(cz / n), 0.0f);
   const double log2e = 1.4426950408889634074;
   double cum = 0.0;
   for (int i = a0; i < a1; ++i) {
@@ -249,30 +257,43 @@ __global__ __launch_bounds__(256) void k_est_finalize(const double* __restrict__
 // ---------------------------------------------------------------------------
 // Query-side sample cache for screening: the query's own samples, weights and
 // self integrand are the same for every library partner (random numbers are
-// keyed by molecule), so they are computed once per call.
-//   qs[k] = (r_k, w_A(r_k)),  qf2[k] = w_A u_A at r_k.
+// keyed by molecule), so they are computed once per call.  Points are kept in
+// the query's frame (origin at its centre):
+//   qs[k] = (r'_k, w_A(r_k)),  qf2[k] = w_A u_A at r_k.
+// The densities use the expanded form with the same records the screening
+// kernel builds, so a library copy of the query reproduces them bit for bit.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_query_cache(Prepared Qp, const int* __restrict__ offQ,
                                                      int64_t n, uint2 key,
                                                      float4* __restrict__ qs,
                                                      float* __restrict__ qf2) {
-  __shared__ Atom sQ[SHAPE_MAX_ATOMS];
+  __shared__ Atom sF[SHAPE_MAX_ATOMS];          // frame coordinates for sampling
   __shared__ AtomSampling sS[SHAPE_MAX_ATOMS];
+  __shared__ AtomRec sR[SHAPE_MAX_ATOMS];
+  __shared__ float sA[SHAPE_MAX_ATOMS];
   // an invalid query is never staged (its atom count is not trusted); the
   // screening kernel then reports every pair as NaN without reading the cache
   if (Qp.bad[0] != 0) return;
   const int q0 = offQ[0], nq = offQ[1] - offQ[0];
+  const float4 cq = Qp.centre[0];
   for (int i = threadIdx.x; i < nq; i += blockDim.x) {
-    sQ[i] = Qp.atom[q0 + i];
+    const Atom a = Qp.atom[q0 + i];
+    Atom f = a;
+    f.x = a.x - cq.x;
+    f.y = a.y - cq.y;
+    f.z = a.z - cq.z;
+    sF[i] = f;
     sS[i] = Qp.samp[q0 + i];
+    make_rec(a, cq.x, cq.y, cq.z, sR[i], sA[i]);
   }
   __syncthreads();
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
-  float rx[1], ry[1], rz[1];
-  sample_point(sQ, sS, nq, Qp.id[0], (uint64_t)k, key, rx[0], ry[0], rz[0]);
+  float rx[1], ry[1], rz[1], r2[1];
+  sample_point(sF, sS, nq, Qp.id[0], (uint64_t)k, key, rx[0], ry[0], rz[0]);
+  r2[0] = norm2(rx[0], ry[0], rz[0]);
   float m[1] = {0.0f}, q[1] = {1.0f};
-  eval_density<1>(sQ, nq, rx, ry, rz, m, q);
+  eval_density_x<1>(sR, sA, nq, rx, ry, rz, r2, m, q);
   const float u = 1.0f - q[0];
   const float w = bounded_weight(u, m[0]);
   qs[k] = make_float4(rx[0], ry[0], rz[0], w);
@@ -316,10 +337,21 @@ __device__ __forceinline__ double se_tanimoto(double n, double Za, double Zb, do
 }
 
 __global__ __launch_bounds__(64) void k_screen(ScreenArgs a) {
+  // LDS (per pair, n = atoms):
+  //   sBF   [max_b] Atom          library atoms in the library frame (sampling)
+  //   sBS   [max_b] AtomSampling  their sampling records
+  //   sBB   [max_b] AtomRec + a2  library atoms, library frame (own density)
+  //   sBA   [max_b] AtomRec + a2  library atoms, query frame (side A partner)
+  //   sAB   [max_q] AtomRec + a2  query atoms, library frame (side B partner)
   extern __shared__ __align__(16) unsigned char smem[];
-  Atom* sQ = reinterpret_cast<Atom*>(smem);
-  Atom* sB = sQ + a.max_q;
-  AtomSampling* sBS = reinterpret_cast<AtomSampling*>(sB + a.max_b);
+  Atom* sBF = reinterpret_cast<Atom*>(smem);
+  AtomRec* sBB = reinterpret_cast<AtomRec*>(sBF + a.max_b);
+  AtomRec* sBA = sBB + a.max_b;
+  AtomRec* sAB = sBA + a.max_b;
+  float* aBB = reinterpret_cast<float*>(sAB + a.max_q);
+  float* aBA = aBB + a.max_b;
+  float* aAB = aBA + a.max_b;
+  AtomSampling* sBS = reinterpret_cast<AtomSampling*>(aAB + a.max_q);
   const int lane = threadIdx.x;
   const int p = blockIdx.x;
   if (p >= a.n_pairs) return;
@@ -339,10 +371,19 @@ __global__ __launch_bounds__(64) void k_screen(ScreenArgs a) {
   }
   const int q0 = a.offQ[0], nq = a.offQ[1] - a.offQ[0];
   const int b0 = a.offL[m], nb = a.offL[m + 1] - b0;
-  for (int i = lane; i < nq; i += kWave) sQ[i] = a.Q.atom[q0 + i];
+  const float4 cA = a.Q.centre[0];
+  const float4 cB = a.L.centre[m];
+  for (int i = lane; i < nq; i += kWave) make_rec(a.Q.atom[q0 + i], cB.x, cB.y, cB.z, sAB[i], aAB[i]);
   for (int i = lane; i < nb; i += kWave) {
-    sB[i] = a.L.atom[b0 + i];
+    const Atom at = a.L.atom[b0 + i];
+    Atom f = at;
+    f.x = at.x - cB.x;
+    f.y = at.y - cB.y;
+    f.z = at.z - cB.z;
+    sBF[i] = f;
     sBS[i] = a.L.samp[b0 + i];
+    make_rec(at, cB.x, cB.y, cB.z, sBB[i], aBB[i]);
+    make_rec(at, cA.x, cA.y, cA.z, sBA[i], aBA[i]);
   }
   __syncthreads();
   const double Za = a.Q.Z[0];
@@ -357,20 +398,21 @@ __global__ __launch_bounds__(64) void k_screen(ScreenArgs a) {
   for (;;) {
     float fa[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
     float fb[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
-    // side A: query samples from the cache, partner = library molecule
+    // side A: query samples from the cache (query frame), partner = library
     for (int t = 0; t < per_lane; t += kSA) {
-      float rx[kSA], ry[kSA], rz[kSA], w[kSA], f2[kSA], q[kSA], valid[kSA];
+      float rx[kSA], ry[kSA], rz[kSA], r2[kSA], w[kSA], f2[kSA], q[kSA], valid[kSA];
 #pragma unroll
       for (int s = 0; s < kSA; ++s) {
         const bool ok = (t + s) < per_lane;
         const int64_t k = n_side + (int64_t)lane + (int64_t)kWave * (ok ? t + s : t);
         const float4 c = a.qs[k];
         rx[s] = c.x; ry[s] = c.y; rz[s] = c.z; w[s] = c.w;
+        r2[s] = norm2(c.x, c.y, c.z);
         f2[s] = a.qf2[k];
         q[s] = 1.0f;
         valid[s] = ok ? 1.0f : 0.0f;
       }
-      eval_union<kSA>(sB, nb, rx, ry, rz, q);
+      eval_union_x<kSA>(sBA, aBA, nb, rx, ry, rz, r2, q);
 #pragma unroll
       for (int s = 0; s < kSA; ++s) {
         const float f1 = w[s] * (1.0f - q[s]) * valid[s];
@@ -380,19 +422,20 @@ __global__ __launch_bounds__(64) void k_screen(ScreenArgs a) {
         fa[4] += f1 * g2;
       }
     }
-    // side B: library samples drawn here, partner = query
+    // side B: library samples drawn here (library frame), partner = query
     for (int t = 0; t < per_lane; t += kSB) {
-      float rx[kSB], ry[kSB], rz[kSB], mb[kSB], qb[kSB], qa[kSB], valid[kSB];
+      float rx[kSB], ry[kSB], rz[kSB], r2[kSB], mb[kSB], qb[kSB], qa[kSB], valid[kSB];
 #pragma unroll
       for (int s = 0; s < kSB; ++s) {
         const bool ok = (t + s) < per_lane;
         const int64_t k = n_side + (int64_t)lane + (int64_t)kWave * (ok ? t + s : t);
-        sample_point(sB, sBS, nb, idb, (uint64_t)k, a.key, rx[s], ry[s], rz[s]);
+        sample_point(sBF, sBS, nb, idb, (uint64_t)k, a.key, rx[s], ry[s], rz[s]);
+        r2[s] = norm2(rx[s], ry[s], rz[s]);
         mb[s] = 0.0f; qb[s] = 1.0f; qa[s] = 1.0f;
         valid[s] = ok ? 1.0f : 0.0f;
       }
-      eval_density<kSB>(sB, nb, rx, ry, rz, mb, qb);
-      eval_union<kSB>(sQ, nq, rx, ry, rz, qa);
+      eval_density_x<kSB>(sBB, aBB, nb, rx, ry, rz, r2, mb, qb);
+      eval_union_x<kSB>(sAB, aAB, nq, rx, ry, rz, r2, qa);
 #pragma unroll
       for (int s = 0; s < kSB; ++s) {
         const float ub = 1.0f - qb[s];
@@ -484,7 +527,9 @@ hipError_t launch_query_cache(const Prepared& Q, const int* offQ, int64_t n, uin
 }
 
 size_t screen_lds_bytes(int max_q, int max_b) {
-  return (size_t)max_q * sizeof(Atom) + (size_t)max_b * (sizeof(Atom) + sizeof(AtomSampling));
+  return (size_t)max_b * (sizeof(Atom) + 2 * (sizeof(AtomRec) + sizeof(float)) +
+                          sizeof(AtomSampling)) +
+         (size_t)max_q * (sizeof(AtomRec) + sizeof(float));
 }
 
 hipError_t launch_screen(const ScreenArgs& a, hipStream_t st) {

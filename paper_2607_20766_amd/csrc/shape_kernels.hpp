@@ -30,6 +30,7 @@ struct Prepared {
   double* Z;
   uint32_t* id;
   int* bad;
+  float4* centre;  // mean atom position (frame origin of the expanded form)
 };
 
 struct ScreenArgs {

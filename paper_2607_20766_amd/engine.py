@@ -91,6 +91,8 @@ def load_library():
                                    vp, i32, ctypes.POINTER(ShapeScreenParams), vp,
                                    ctypes.POINTER(ShapeScreenOut)]
         L.shape_check_data.argtypes = [vp, vp]
+        L.shape_timing_enable.argtypes = [vp, ctypes.c_int]
+        L.shape_timing_read.argtypes = [vp, ctypes.POINTER(d), ctypes.POINTER(i64), ctypes.c_int]
         _lib = L
     return _lib
 
@@ -218,6 +220,17 @@ class Engine:
                                                 _ptr(pairs), n, ctypes.byref(prm),
                                                 _stream(stream), ctypes.byref(o)))
         return out
+
+    def shape_timing_enable(self, enable: bool = True):
+        self._check(load_library().shape_timing_enable(self._ctx, int(enable)))
+
+    def shape_timing_read(self, reset: bool = True):
+        """(summed dominant-kernel milliseconds, launches) since the last reset."""
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        self._check(load_library().shape_timing_read(self._ctx, ctypes.byref(ms),
+                                                     ctypes.byref(n), int(reset)))
+        return ms.value, n.value
 
     def shape_check_data(self, stream=None):
         self._check(load_library().shape_check_data(self._ctx, _stream(stream)))
