@@ -191,6 +191,57 @@ int shape_screen(shape_ctx* ctx, const shape_mols* query, const shape_mols* lib,
  * (SHAPE_OK); clears the flag. */
 int shape_check_data(shape_ctx* ctx, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Differentiable rigid alignment (section "Differentiable alignment and the
+ * hybrid pipeline", Eqs. pose and grad).  B is moved rigidly,
+ * c_j -> R(q/|q|) c_j + t, with the pose as seven floats
+ * (qw, qx, qy, qz, tx, ty, tz): an unnormalised quaternion (rotation about
+ * the origin of B's coordinates) and a translation.  A's first n_samples
+ * sample points and weights are held fixed (common random numbers), so
+ *   O(pose) = Z_A/n sum_k w_A(r_k) u_B(r_k; pose),
+ *   T(pose) = O / (O_aa + O_bb - O)
+ * is a smooth function of the pose with the pathwise gradient of Eq. grad.
+ * ------------------------------------------------------------------------ */
+
+/* Pose-invariant self-overlaps O_MM = Z_M/n sum_k w_M u_M over each
+ * molecule's own first n_samples samples.  O_self: device float [n_mols].
+ * n_samples in [2, 2^20].  Asynchronous; invalid molecules give NaN. */
+int shape_self_overlap(shape_ctx* ctx, const shape_mols* M, int32_t n_samples,
+                       uint64_t seed, void* stream, float* O_self);
+
+/* Aligned Tanimoto and its gradient for n_starts poses of every pair.
+ * A, B: molecule sets paired by index (equal n_mols = number of pairs).
+ * pose: device float [pairs][n_starts][7].  O_aa, O_bb: device float [pairs]
+ * (from shape_self_overlap with the same n_samples and seed).  n_samples in
+ * [64, 4096], n_starts >= 1.  T: device float [pairs][n_starts];
+ * dT_dpose: device float [pairs][n_starts][7], or NULL for values only.
+ * Asynchronous.  Errors: SHAPE_E_INVAL, SHAPE_E_RANGE (including on-chip
+ * staging larger than the device allows), SHAPE_E_NOMEM, SHAPE_E_HIP. */
+int shape_align_grad(shape_ctx* ctx, const shape_mols* A, const shape_mols* B,
+                     int32_t n_starts, const float* pose, const float* O_aa,
+                     const float* O_bb, int32_t n_samples, uint64_t seed,
+                     void* stream, float* T, float* dT_dpose);
+
+/* One Adam step (Kingma and Ba) that increases T on n_poses poses:
+ * g = -dT/dpose; m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
+ * pose -= lr (m/(1-b1^t)) / (sqrt(v/(1-b2^t)) + eps), then the quaternion is
+ * renormalised.  step: device int32 holding the number of steps already
+ * taken (t - 1), advanced by one.  pose, m, v: device float [n_poses][7]
+ * (m, v zero before the first step).  Asynchronous. */
+int shape_adam_pose(shape_ctx* ctx, float* pose, const float* dT_dpose, float* m, float* v,
+                    int64_t n_poses, int32_t* step, float lr, float beta1, float beta2,
+                    float eps, void* stream);
+
+/* Multi-start alignment driver: self-overlaps, then n_steps of
+ * (shape_align_grad, shape_adam_pose) from the given starts, then T at the
+ * final poses and the best start of each pair (largest final T).
+ * pose: device float [pairs][n_starts][7], updated in place.  T_final:
+ * device float [pairs][n_starts].  best: device int32 [pairs] or NULL.
+ * Adam uses beta1 = 0.9, beta2 = 0.999, eps = 1e-8.  Asynchronous. */
+int shape_align(shape_ctx* ctx, const shape_mols* A, const shape_mols* B, int32_t n_starts,
+                float* pose, int32_t n_samples, int32_t n_steps, float lr, uint64_t seed,
+                void* stream, float* T_final, int32_t* best);
+
 /* Kernel timing (measurement support, not part of the method).  While
  * enabled, every call records a pair of HIP events on its stream around its
  * dominant kernel (the screening kernel of shape_screen, the sample kernel of

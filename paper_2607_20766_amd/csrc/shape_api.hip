@@ -27,6 +27,7 @@ enum Slot {
   S_Q_ATOM, S_Q_SAMP, S_Q_Z, S_Q_ID, S_Q_BAD, S_Q_CENTRE,
   S_L_ATOM, S_L_SAMP, S_L_Z, S_L_ID, S_L_BAD, S_L_CENTRE,
   S_PARTIALS, S_RESULT, S_QS, S_QF2,
+  S_SELF_A, S_SELF_B, S_ADAM_M, S_ADAM_V, S_ADAM_STEP, S_GRAD,
   S_COUNT
 };
 
@@ -35,6 +36,7 @@ enum Slot {
 struct shape_ctx {
   int device = -1;
   int n_cu = 0;
+  size_t lds_per_block = 0;
   std::string err;
   Buffer buf[S_COUNT];
   int* flag = nullptr;  // invalid-data flag (device int)
@@ -184,6 +186,7 @@ int shape_create(shape_ctx** out, int device) {
   if (!c) return fail(nullptr, SHAPE_E_NOMEM, "context allocation failed");
   c->device = device;
   c->n_cu = prop.multiProcessorCount;
+  c->lds_per_block = prop.sharedMemPerBlock;
   e = hipSetDevice(device);
   if (e == hipSuccess) e = hipMalloc(&c->flag, sizeof(int));
   if (e == hipSuccess) e = hipMemset(c->flag, 0, sizeof(int));
@@ -355,6 +358,169 @@ int shape_screen(shape_ctx* c, const shape_mols* query, const shape_mols* lib,
     KernelTimer timer(c, st);
     HIP_TRY(c, shape::launch_screen(a, st), "screen kernel");
     timer.stop();
+    return SHAPE_OK;
+  } catch (...) {
+    return fail(c, SHAPE_E_HIP, "internal error");
+  }
+}
+
+int shape_self_overlap(shape_ctx* c, const shape_mols* M, int32_t n_samples, uint64_t seed,
+                       void* stream, float* O_self) {
+  if (!c) return SHAPE_E_INVAL;
+  try {
+    int rc;
+    if ((rc = check_mols(c, M, "M", false))) return rc;
+    if (!O_self) return fail(c, SHAPE_E_INVAL, "O_self is NULL");
+    if (n_samples < 2 || n_samples > (1 << 20))
+      return fail(c, SHAPE_E_RANGE, "n_samples must lie in [2, 2^20]");
+    if ((rc = set_device(c))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    shape::Prepared P;
+    if ((rc = prepare(c, M, false, st, &P))) return rc;
+    HIP_TRY(c, shape::launch_self_overlap(P, M->atom_offset, M->n_mols, n_samples, key_of(seed),
+                                          O_self, st),
+            "self-overlap kernel");
+    return SHAPE_OK;
+  } catch (...) {
+    return fail(c, SHAPE_E_HIP, "internal error");
+  }
+}
+
+namespace {
+
+int align_check(shape_ctx* c, const shape_mols* A, const shape_mols* B, int32_t n_starts,
+                int32_t n_samples) {
+  int rc;
+  if ((rc = check_mols(c, A, "A", false))) return rc;
+  if ((rc = check_mols(c, B, "B", false))) return rc;
+  if (A->n_mols != B->n_mols)
+    return fail(c, SHAPE_E_RANGE, "A and B must hold the same number of molecules");
+  if (n_starts < 1) return fail(c, SHAPE_E_RANGE, "n_starts < 1");
+  if (n_samples < 64 || n_samples > 4096)
+    return fail(c, SHAPE_E_RANGE, "n_samples must lie in [64, 4096]");
+  const size_t lds = shape::align_lds_bytes(n_samples, A->max_atoms, B->max_atoms);
+  if (lds > c->lds_per_block)
+    return fail(c, SHAPE_E_RANGE, "alignment staging needs %zu B of LDS, device allows %zu",
+                lds, c->lds_per_block);
+  return SHAPE_OK;
+}
+
+int align_launch(shape_ctx* c, const shape_mols* A, const shape_mols* B,
+                 const shape::Prepared& PA, const shape::Prepared& PB, int32_t n_starts,
+                 const float* pose, const float* O_aa, const float* O_bb, int32_t n_samples,
+                 uint64_t seed, hipStream_t st, float* T, float* grad) {
+  shape::AlignArgs a;
+  a.A = PA;
+  a.offA = A->atom_offset;
+  a.max_a = A->max_atoms;
+  a.B = PB;
+  a.offB = B->atom_offset;
+  a.max_b = B->max_atoms;
+  a.n_starts = n_starts;
+  a.n_samples = n_samples;
+  a.key = key_of(seed);
+  a.pose = pose;
+  a.O_aa = O_aa;
+  a.O_bb = O_bb;
+  a.T = T;
+  a.grad = grad;
+  HIP_TRY(c, shape::launch_align(a, A->n_mols, st), "alignment kernel");
+  return SHAPE_OK;
+}
+
+}  // namespace
+
+int shape_align_grad(shape_ctx* c, const shape_mols* A, const shape_mols* B, int32_t n_starts,
+                     const float* pose, const float* O_aa, const float* O_bb, int32_t n_samples,
+                     uint64_t seed, void* stream, float* T, float* dT_dpose) {
+  if (!c) return SHAPE_E_INVAL;
+  try {
+    int rc;
+    if ((rc = align_check(c, A, B, n_starts, n_samples))) return rc;
+    if (!pose || !O_aa || !O_bb || !T) return fail(c, SHAPE_E_INVAL, "NULL array");
+    if ((rc = set_device(c))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    shape::Prepared PA, PB;
+    if ((rc = prepare(c, A, true, st, &PA))) return rc;
+    if ((rc = prepare(c, B, false, st, &PB))) return rc;
+    KernelTimer timer(c, st);
+    rc = align_launch(c, A, B, PA, PB, n_starts, pose, O_aa, O_bb, n_samples, seed, st, T,
+                      dT_dpose);
+    timer.stop();
+    return rc;
+  } catch (...) {
+    return fail(c, SHAPE_E_HIP, "internal error");
+  }
+}
+
+int shape_adam_pose(shape_ctx* c, float* pose, const float* dT_dpose, float* m, float* v,
+                    int64_t n_poses, int32_t* step, float lr, float beta1, float beta2, float eps,
+                    void* stream) {
+  if (!c) return SHAPE_E_INVAL;
+  if (n_poses < 0) return fail(c, SHAPE_E_RANGE, "n_poses < 0");
+  if (n_poses == 0) return SHAPE_OK;
+  if (!pose || !dT_dpose || !m || !v || !step) return fail(c, SHAPE_E_INVAL, "NULL array");
+  if (!(lr > 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) ||
+      !(eps > 0.f))
+    return fail(c, SHAPE_E_RANGE, "Adam hyper-parameters out of range");
+  int rc = set_device(c);
+  if (rc) return rc;
+  HIP_TRY(c, shape::launch_adam_pose(pose, dT_dpose, m, v, n_poses, step, lr, beta1, beta2, eps,
+                                     (hipStream_t)stream),
+          "Adam kernel");
+  return SHAPE_OK;
+}
+
+int shape_align(shape_ctx* c, const shape_mols* A, const shape_mols* B, int32_t n_starts,
+                float* pose, int32_t n_samples, int32_t n_steps, float lr, uint64_t seed,
+                void* stream, float* T_final, int32_t* best) {
+  if (!c) return SHAPE_E_INVAL;
+  try {
+    int rc;
+    if ((rc = align_check(c, A, B, n_starts, n_samples))) return rc;
+    if (!pose || !T_final) return fail(c, SHAPE_E_INVAL, "NULL array");
+    if (n_steps < 0) return fail(c, SHAPE_E_RANGE, "n_steps < 0");
+    if (!(lr > 0.f)) return fail(c, SHAPE_E_RANGE, "lr must be > 0");
+    if ((rc = set_device(c))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const int pairs = A->n_mols;
+    const int64_t n_poses = (int64_t)pairs * n_starts;
+    shape::Prepared PA, PB;
+    void *saa, *sbb, *mm, *vv, *stp, *grad;
+    if ((rc = ensure(c, S_SELF_A, (size_t)pairs * sizeof(float), &saa))) return rc;
+    if ((rc = ensure(c, S_SELF_B, (size_t)pairs * sizeof(float), &sbb))) return rc;
+    if ((rc = ensure(c, S_ADAM_M, (size_t)n_poses * 7 * sizeof(float), &mm))) return rc;
+    if ((rc = ensure(c, S_ADAM_V, (size_t)n_poses * 7 * sizeof(float), &vv))) return rc;
+    if ((rc = ensure(c, S_ADAM_STEP, sizeof(int), &stp))) return rc;
+    if ((rc = ensure(c, S_GRAD, (size_t)n_poses * 7 * sizeof(float), &grad))) return rc;
+    // self-overlaps use the library slots; prepare both sets afterwards
+    if ((rc = prepare(c, A, false, st, &PB))) return rc;
+    HIP_TRY(c, shape::launch_self_overlap(PB, A->atom_offset, pairs, n_samples, key_of(seed),
+                                          (float*)saa, st),
+            "self-overlap kernel");
+    if ((rc = prepare(c, B, false, st, &PB))) return rc;
+    HIP_TRY(c, shape::launch_self_overlap(PB, B->atom_offset, pairs, n_samples, key_of(seed),
+                                          (float*)sbb, st),
+            "self-overlap kernel");
+    if ((rc = prepare(c, A, true, st, &PA))) return rc;
+    HIP_TRY(c, shape::launch_fill_int((int*)mm, (int)(n_poses * 7), 0, st), "state reset");
+    HIP_TRY(c, shape::launch_fill_int((int*)vv, (int)(n_poses * 7), 0, st), "state reset");
+    HIP_TRY(c, shape::launch_fill_int((int*)stp, 1, 0, st), "state reset");
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    KernelTimer timer(c, st);
+    for (int it = 0; it < n_steps; ++it) {
+      if ((rc = align_launch(c, A, B, PA, PB, n_starts, pose, (const float*)saa,
+                             (const float*)sbb, n_samples, seed, st, T_final, (float*)grad)))
+        return rc;
+      HIP_TRY(c, shape::launch_adam_pose(pose, (const float*)grad, (float*)mm, (float*)vv,
+                                         n_poses, (int*)stp, lr, b1, b2, eps, st),
+              "Adam kernel");
+    }
+    if ((rc = align_launch(c, A, B, PA, PB, n_starts, pose, (const float*)saa,
+                           (const float*)sbb, n_samples, seed, st, T_final, nullptr)))
+      return rc;
+    timer.stop();
+    if (best) HIP_TRY(c, shape::launch_best_start(T_final, pairs, n_starts, best, st), "best");
     return SHAPE_OK;
   } catch (...) {
     return fail(c, SHAPE_E_HIP, "internal error");

@@ -184,6 +184,30 @@ __device__ __forceinline__ void eval_density_x(const AtomRec* __restrict__ rec,
   }
 }
 
+// First-order density m and union u itself at S points (expanded form), u
+// by the cancellation-free recurrence u <- u + o - u o.  Slightly dearer than
+// tracking q = 1 - u, but u keeps its relative precision where every o_i is
+// small, so w = u/m stays accurate in a molecule's tails (where a moved
+// partner can sit during alignment).
+template <int S>
+__device__ __forceinline__ void eval_density_u_x(const AtomRec* __restrict__ rec,
+                                                 const float* __restrict__ a2, int n,
+                                                 const float (&rx)[S], const float (&ry)[S],
+                                                 const float (&rz)[S], const float (&r2)[S],
+                                                 float (&m)[S], float (&u)[S]) {
+#pragma unroll 2
+  for (int i = 0; i < n; ++i) {
+    const AtomRec b = rec[i];
+    const float a = a2[i];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const float o = occupancy_x(b, a, rx[s], ry[s], rz[s], r2[s]);
+      m[s] += o;
+      u[s] = fmaf(-u[s], o, u[s] + o);
+    }
+  }
+}
+
 // |r|^2 of a point.
 __device__ __forceinline__ float norm2(float x, float y, float z) {
   return fmaf(x, x, fmaf(y, y, z * z));

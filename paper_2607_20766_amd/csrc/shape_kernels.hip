@@ -343,15 +343,17 @@ __global__ __launch_bounds__(64) void k_screen(ScreenArgs a) {
   //   sBB   [max_b] AtomRec + a2  library atoms, library frame (own density)
   //   sBA   [max_b] AtomRec + a2  library atoms, query frame (side A partner)
   //   sAB   [max_q] AtomRec + a2  query atoms, library frame (side B partner)
+  // 16-byte records first, then the 8-byte, then the 4-byte arrays, so every
+  // array is aligned to its element size whatever the atom counts.
   extern __shared__ __align__(16) unsigned char smem[];
   Atom* sBF = reinterpret_cast<Atom*>(smem);
   AtomRec* sBB = reinterpret_cast<AtomRec*>(sBF + a.max_b);
   AtomRec* sBA = sBB + a.max_b;
   AtomRec* sAB = sBA + a.max_b;
-  float* aBB = reinterpret_cast<float*>(sAB + a.max_q);
+  AtomSampling* sBS = reinterpret_cast<AtomSampling*>(sAB + a.max_q);
+  float* aBB = reinterpret_cast<float*>(sBS + a.max_b);
   float* aBA = aBB + a.max_b;
   float* aAB = aBA + a.max_b;
-  AtomSampling* sBS = reinterpret_cast<AtomSampling*>(aAB + a.max_q);
   const int lane = threadIdx.x;
   const int p = blockIdx.x;
   if (p >= a.n_pairs) return;

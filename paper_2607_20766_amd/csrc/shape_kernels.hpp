@@ -59,6 +59,33 @@ struct ScreenArgs {
   int* n_used;
 };
 
+// Alignment: pairs (A[p], B[p]), n_starts poses each.
+struct AlignArgs {
+  Prepared A;
+  const int* offA;
+  int max_a;
+  Prepared B;
+  const int* offB;
+  int max_b;
+  int n_starts;
+  int n_samples;
+  uint2 key;
+  const float* pose;  // [pairs][starts][7] (qw, qx, qy, qz, tx, ty, tz)
+  const float* O_aa;  // [pairs]
+  const float* O_bb;  // [pairs]
+  float* T;           // [pairs][starts]
+  float* grad;        // [pairs][starts][7] or nullptr
+};
+
+size_t align_lds_bytes(int n_samples, int max_a, int max_b);
+hipError_t launch_align(const AlignArgs& a, int n_pairs, hipStream_t st);
+hipError_t launch_self_overlap(const Prepared& M, const int* off, int n_mols, int n_samples,
+                               uint2 key, float* out, hipStream_t st);
+hipError_t launch_adam_pose(float* pose, const float* dT, float* m, float* v, int64_t n_poses,
+                            int* step, float lr, float b1, float b2, float eps, hipStream_t st);
+hipError_t launch_best_start(const float* T, int n_pairs, int n_starts, int* best,
+                             hipStream_t st);
+
 hipError_t launch_alpha_from_radius(const float* R, int64_t n, double kappa, double lambda,
                                     float* alpha, hipStream_t st);
 hipError_t launch_prepare(const MolsDev& in, const Prepared& out, int* flag, hipStream_t st);

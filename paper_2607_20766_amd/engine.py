@@ -91,6 +91,13 @@ def load_library():
                                    vp, i32, ctypes.POINTER(ShapeScreenParams), vp,
                                    ctypes.POINTER(ShapeScreenOut)]
         L.shape_check_data.argtypes = [vp, vp]
+        L.shape_self_overlap.argtypes = [vp, ctypes.POINTER(ShapeMols), i32, u64, vp, vp]
+        L.shape_align_grad.argtypes = [vp, ctypes.POINTER(ShapeMols), ctypes.POINTER(ShapeMols),
+                                       i32, vp, vp, vp, i32, u64, vp, vp, vp]
+        L.shape_adam_pose.argtypes = [vp, vp, vp, vp, vp, i64, vp, ctypes.c_float,
+                                      ctypes.c_float, ctypes.c_float, ctypes.c_float, vp]
+        L.shape_align.argtypes = [vp, ctypes.POINTER(ShapeMols), ctypes.POINTER(ShapeMols), i32,
+                                  vp, i32, i32, ctypes.c_float, u64, vp, vp, vp]
         L.shape_timing_enable.argtypes = [vp, ctypes.c_int]
         L.shape_timing_read.argtypes = [vp, ctypes.POINTER(d), ctypes.POINTER(i64), ctypes.c_int]
         _lib = L
@@ -221,6 +228,51 @@ class Engine:
                                                 _stream(stream), ctypes.byref(o)))
         return out
 
+    # -- alignment -------------------------------------------------------------
+    def shape_self_overlap(self, M: Molecules, n_samples: int = 2048, seed: int = 0,
+                           stream=None) -> torch.Tensor:
+        out = torch.empty(M.n_mols, dtype=torch.float32, device=self.torch_device)
+        m = M.c_struct()
+        self._check(load_library().shape_self_overlap(self._ctx, ctypes.byref(m), int(n_samples),
+                                                      int(seed), _stream(stream), _ptr(out)))
+        return out
+
+    def shape_align_grad(self, A: Molecules, B: Molecules, pose: torch.Tensor,
+                         O_aa: torch.Tensor, O_bb: torch.Tensor, n_samples: int = 2048,
+                         seed: int = 0, need_grad: bool = True, stream=None):
+        """T [pairs, starts] and dT/dpose [pairs, starts, 7] (None if not needed)."""
+        pose = pose.contiguous()
+        pairs, starts = pose.shape[0], pose.shape[1]
+        T = torch.empty(pairs, starts, dtype=torch.float32, device=self.torch_device)
+        g = (torch.empty(pairs, starts, 7, dtype=torch.float32, device=self.torch_device)
+             if need_grad else None)
+        a, b = A.c_struct(), B.c_struct()
+        self._check(load_library().shape_align_grad(
+            self._ctx, ctypes.byref(a), ctypes.byref(b), starts, _ptr(pose),
+            _ptr(O_aa.contiguous()), _ptr(O_bb.contiguous()), int(n_samples), int(seed),
+            _stream(stream), _ptr(T), _ptr(g)))
+        return T, g
+
+    def shape_adam_pose(self, pose, dT, m, v, step, lr=0.05, beta1=0.9, beta2=0.999, eps=1e-8,
+                        stream=None):
+        self._check(load_library().shape_adam_pose(
+            self._ctx, _ptr(pose), _ptr(dT), _ptr(m), _ptr(v), pose.numel() // 7, _ptr(step),
+            float(lr), float(beta1), float(beta2), float(eps), _stream(stream)))
+
+    def shape_align(self, A: Molecules, B: Molecules, pose: torch.Tensor, n_samples: int = 2048,
+                    n_steps: int = 60, lr: float = 0.05, seed: int = 0, stream=None):
+        """Multi-start Adam alignment in place on `pose` [pairs, starts, 7];
+        returns (T at the final poses [pairs, starts], best start [pairs])."""
+        assert pose.is_contiguous() and pose.dtype == torch.float32
+        pairs, starts = pose.shape[0], pose.shape[1]
+        T = torch.empty(pairs, starts, dtype=torch.float32, device=self.torch_device)
+        best = torch.empty(pairs, dtype=torch.int32, device=self.torch_device)
+        a, b = A.c_struct(), B.c_struct()
+        self._check(load_library().shape_align(
+            self._ctx, ctypes.byref(a), ctypes.byref(b), starts, _ptr(pose), int(n_samples),
+            int(n_steps), float(lr), int(seed), _stream(stream), _ptr(T), _ptr(best)))
+        return T, best
+
     def shape_timing_enable(self, enable: bool = True):
         self._check(load_library().shape_timing_enable(self._ctx, int(enable)))
 
@@ -234,3 +286,23 @@ class Engine:
 
     def shape_check_data(self, stream=None):
         self._check(load_library().shape_check_data(self._ctx, _stream(stream)))
+
+
+class ShapeAlignFn(torch.autograd.Function):
+    """T(pose) with the library's pathwise gradient (common random numbers).
+
+    forward(pose [pairs, starts, 7]) runs shape_align_grad once and keeps
+    dT/dpose; backward multiplies it by the incoming gradient.
+    """
+
+    @staticmethod
+    def forward(ctx, pose, engine, A, B, O_aa, O_bb, n_samples=2048, seed=0):
+        T, g = engine.shape_align_grad(A, B, pose.detach(), O_aa, O_bb, n_samples, seed,
+                                       need_grad=True)
+        ctx.save_for_backward(g)
+        return T
+
+    @staticmethod
+    def backward(ctx, grad_T):
+        (g,) = ctx.saved_tensors
+        return grad_T.unsqueeze(-1) * g, None, None, None, None, None, None, None

@@ -156,3 +156,16 @@ def test_invalid_molecules_flagged(eng, small_lib):
         eng.shape_screen(Q, lib, n_per_side=100)
     out = eng.shape_screen(Q, lib, n_per_side=256, n_pairs=0)
     assert out["T"].numel() == 0
+
+
+def test_odd_atom_counts(eng):
+    """Odd query and library sizes (LDS arrays of 8-byte records after odd
+    counts of 4-byte ones must stay aligned)."""
+    q = molgen.molecule(1, 5, 31)
+    L = molgen.library(12, 9, 11, 17, workers=1)
+    assert int(L.sizes().max()) % 2 == 1 or q.n_atoms % 2 == 1
+    Q = eng.molecules(q, mol_id=[QUERY_ID])
+    lib = eng.molecules(L)
+    g = _to_np(eng.shape_screen(Q, lib, n_per_side=512, seed=4))
+    r = _oracle_screen(q, L, mode=0, n_fixed=512, seed=4)
+    _compare(g, r)
