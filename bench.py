@@ -131,6 +131,107 @@ def bench_align(eng, n_pairs, n_starts=16, n_steps=60, n_samples=2048, lr=0.05):
     }
 
 
+def bench_triage(eng, n_lib, n_queries=256, n_train_lib=3907, epochs=10):
+    """Learned triage: a BF16 MLP trained on ~10^6 IS-labelled pairs (256
+    queries x 3907 molecules) ranks an n_lib-molecule library against a
+    held-out 30-atom query; the top 5 % are refined by adaptive IS with
+    budgets seeded from the predicted SE scale.  Compared with plain adaptive
+    IS over the whole library (same tau, rounds, cap)."""
+    import scipy.stats
+    import torch
+
+    from paper_2607_20766_amd import molgen
+    from paper_2607_20766_amd.engine import SHAPE_SCREEN_ADAPTIVE
+    from paper_2607_20766_amd.surrogate import Triage
+
+    log("triage: training set labels")
+    Lt = molgen.library(40, n_train_lib, 10, 50)
+    Qs = molgen.library(41, n_queries, 10, 50)
+    lib_t = eng.molecules(Lt)
+    f_lib_t = eng.shape_features(lib_t)
+    f_q = eng.shape_features(eng.molecules(Qs))
+    tr = Triage(eng, seed=0)
+    t0 = time.perf_counter()
+    qi, mi, Y, FO = [], [], [], []
+    for i in range(Qs.n_mols):
+        q = eng.molecules(Qs.mol(i), mol_id=[0xFFFF0000 + i])
+        T, s_, _ = tr.labels(q, lib_t)
+        FO.append(eng.shape_fo_overlap(q, lib_t).cpu().numpy())
+        qi.append(np.full(Lt.n_mols, i))
+        mi.append(np.arange(Lt.n_mols))
+        Y.append(np.stack([T, s_], 1))
+    qi, mi, Y, FO = (np.concatenate(x) for x in (qi, mi, Y, FO))
+    t_labels = time.perf_counter() - t0
+    tr.fit_standardisation(f_q, f_lib_t, qi, mi, fo=FO)
+    t0 = time.perf_counter()
+    hist = tr.train(f_q, f_lib_t, qi, mi, Y, fo=FO, epochs=epochs, batch=4096, lr=1e-3)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+
+    log(f"triage: {n_lib}-molecule library")
+    qt = molgen.molecule(5, 0, 30)
+    L = molgen.library(5, n_lib, 10, 50)
+    Q = eng.molecules(qt, mol_id=[QUERY_ID])
+    lib = eng.molecules(L)
+
+    def run_triage():
+        f_qt = eng.shape_features(Q)
+        f_l = eng.shape_features(lib)
+        return tr.screen(Q, lib, f_qt, f_l, frac=0.05)
+
+    def run_plain():
+        return eng.shape_screen(Q, lib, mode=SHAPE_SCREEN_ADAPTIVE, round_per_pair=ROUND,
+                                cap_per_pair=CAP, tau=TAU, seed=0)
+
+    def wall(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        t = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            r = fn()
+            torch.cuda.synchronize()
+            t.append(time.perf_counter() - t0)
+        return float(np.median(t)), r
+
+    t_plain, plain = wall(run_plain)
+    t_tri, (top, out, raw) = wall(run_triage)
+    T_plain = plain["T"].cpu().numpy()
+    n_plain = int(plain["n_used"].cpu().numpy().astype(np.int64).sum())
+    n_tri = int(out["n_used"].cpu().numpy().astype(np.int64).sum())
+    k1 = n_lib // 100
+    true_top = set(np.argsort(-T_plain, kind="stable")[:k1].tolist())
+    top = top.cpu().numpy()
+    T_ref = out["T"].cpu().numpy()
+    got = set(top[np.argsort(-T_ref, kind="stable")[:k1]].tolist())
+    T_hat, _ = tr.to_labels(raw.cpu().numpy())
+    fo_t = eng.shape_fo_overlap(Q, lib).cpu().numpy()
+    fq = eng.shape_features(Q).cpu().numpy()[0]
+    fl = eng.shape_features(lib).cpu().numpy()
+    T_fo = fo_t / (fq[23] + fl[:, 23] - fo_t)
+    fo_top = set(np.argsort(-T_fo, kind="stable")[: n_lib // 20].tolist())
+    return {
+        "workload": f"MLP 96-256-256-256-2 (BF16 MFMA, FP32 accumulation) trained on "
+                    f"{qi.size} IS-labelled pairs ({n_queries} queries x {n_train_lib}), "
+                    f"{epochs} epochs; held-out 30-atom query vs {n_lib} molecules; top 5 % "
+                    f"refined by adaptive IS (tau {TAU}) with seeded budgets",
+        "pairs_per_s_surrogate_is": n_lib / t_tri,
+        "pairs_per_s_plain_adaptive_is": n_lib / t_plain,
+        "speedup": t_plain / t_tri,
+        "ms_surrogate_is": t_tri * 1e3,
+        "ms_plain_adaptive_is": t_plain * 1e3,
+        "is_samples_surrogate_is": n_tri,
+        "is_samples_plain": n_plain,
+        "recall_top1pct": len(true_top & got) / k1,
+        "mae_T_surrogate_vs_is": float(np.abs(T_hat - T_plain).mean()),
+        "spearman_surrogate_vs_is": float(scipy.stats.spearmanr(T_hat, T_plain)[0]),
+        "recall_top1pct_within_fo_tanimoto_top5pct": len(true_top & fo_top) / k1,
+        "train_s": t_train,
+        "label_s": t_labels,
+        "final_train_loss": hist[-1],
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -143,6 +244,8 @@ def main():
                     help="skip the converged-ranking comparison (untimed)")
     ap.add_argument("--no-align", action="store_true", help="skip the alignment workload")
     ap.add_argument("--align-pairs", type=int, default=10000)
+    ap.add_argument("--no-triage", action="store_true", help="skip the learned-triage workload")
+    ap.add_argument("--triage-library", type=int, default=1000000)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the engine has no multi-GPU path in this "
@@ -286,6 +389,9 @@ def main():
 
     if not args.no_align:
         res["align"] = bench_align(eng, args.align_pairs)
+
+    if not args.no_triage:
+        res["triage"] = bench_triage(eng, args.triage_library)
 
     if not args.no_cpu_baseline:
         log("CPU oracle baseline")

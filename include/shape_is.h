@@ -150,6 +150,11 @@ int shape_estimate(shape_ctx* ctx, const shape_mols* A, const shape_mols* B,
  *                  round_per_pair, at most 2^21
  *  tau             ADAPTIVE: stop once SE(T) <= tau (tau > 0)
  *  seed            Philox key
+ *  n_start         ADAPTIVE, optional: device int32 [n_pairs] sample budgets
+ *                  per pair; the stop test is first taken once a pair has
+ *                  drawn n_start[p] samples (rounded up to whole rounds,
+ *                  capped), e.g. budgets predicted by a surrogate; NULL =
+ *                  test after every round
  * Adaptive screening (section "Confidence-bounded screening"): each pair
  * draws rounds of samples until the delta-method SE(T) is at most tau or the
  * cap is reached; the decision is taken in FP64 after every round. */
@@ -160,6 +165,7 @@ typedef struct {
   int32_t cap_per_pair;
   double tau;
   uint64_t seed;
+  const int32_t* n_start;
 } shape_screen_params;
 
 /* Per-pair outputs (device pointers; T and se_T required when n_pairs > 0,
@@ -241,6 +247,77 @@ int shape_adam_pose(shape_ctx* ctx, float* pose, const float* dT_dpose, float* m
 int shape_align(shape_ctx* ctx, const shape_mols* A, const shape_mols* B, int32_t n_starts,
                 float* pose, int32_t n_samples, int32_t n_steps, float lr, uint64_t seed,
                 void* stream, float* T_final, int32_t* best);
+
+/* ------------------------------------------------------------------------
+ * Learned triage (an addition to the paper's method: a surrogate that ranks a
+ * library cheaply so that confidence-bounded IS refines only the head of the
+ * ranking; IS stays the judge of every reported value).
+ * ------------------------------------------------------------------------ */
+
+/* Per-molecule features, 24 floats each (out: device float [n_mols][24]):
+ * [0..15] histogram of atom distances from the mixture mean (0.5 A bins over
+ * [0, 8), last bin open); [16..18] square roots of the descending
+ * eigenvalues of the mixture covariance sum pi_i (c_i c_i^T + I/(2 alpha_i))
+ * - mu mu^T; [19..22] atoms per width class (alpha < 0.767, < 0.893, < 0.995,
+ * otherwise); [23] the first-order self-overlap (Eq. fo with B = A).
+ * Invalid molecules give NaN rows.  Asynchronous. */
+int shape_features(shape_ctx* ctx, const shape_mols* M, void* stream, float* out);
+
+/* First-order cross-overlap (Eq. fo) of the query with library molecules at
+ * their given poses: out[p] = O^FO(query, lib[m]), m = pairs[p] (pairs NULL:
+ * m = p).  O(N_q N_m) per pair.  out: device float [n_pairs].  Asynchronous;
+ * invalid molecules give NaN. */
+int shape_fo_overlap(shape_ctx* ctx, const shape_mols* query, const shape_mols* lib,
+                     const int32_t* pairs, int32_t n_pairs, void* stream, float* out);
+
+/* Standardised pair features (out: device float [n][96]): for pair p with
+ * query row q = qidx[p] (qidx NULL: q = 0) and library row m = idx[p] (idx
+ * NULL: m = p), raw = [f_q, f_m, |f_q - f_m|, f_q * f_m] and
+ * out[p][j] = (raw_j - mean[j]) * inv_std[j].  If fo_cross (device float
+ * [n], from shape_fo_overlap) is given, raw[71] (|.| of the self-overlaps)
+ * becomes the pair's first-order Tanimoto O_qm/(O_qq + O_mm - O_qm) and
+ * raw[95] (their product) becomes O_qm.  f_q: device float [*][24]; f_lib:
+ * device float [*][24]; mean, inv_std: device float [96]. */
+int shape_pair_features(shape_ctx* ctx, const float* f_q, const float* f_lib,
+                        const int32_t* qidx, const int32_t* idx, int32_t n,
+                        const float* fo_cross, const float* mean, const float* inv_std,
+                        void* stream, float* out);
+
+#define SHAPE_GEMM_BF16 1u  /* round A and B to bfloat16 (else FP32 operands) */
+#define SHAPE_GEMM_RELU 2u  /* epilogue ReLU after the bias */
+
+/* Dense layer on the matrix cores, FP32 accumulation:
+ *   C[m][n] = epi( sum_k A(m,k) B(k,n) ),  A(m,k) = A[m*sam + k*sak],
+ *   B(k,n) = B[k*sbk + n*sbn],  C[m][n] at C[m*scm + n],
+ * epi: + bias[n] (bias may be NULL), then ReLU if SHAPE_GEMM_RELU, then, if
+ * gate is not NULL, zero where gate[m*sgm + n] <= 0 (backward through ReLU).
+ * All device float arrays; M, N, K >= 1.  Asynchronous. */
+int shape_gemm(shape_ctx* ctx, int32_t M, int32_t N, int32_t K, const float* A, int64_t sam,
+               int64_t sak, const float* B, int64_t sbk, int64_t sbn, float* C, int64_t scm,
+               const float* bias, const float* gate, int64_t sgm, uint32_t flags, void* stream);
+
+/* Column sums out[n] = sum_m A[m*lda + n] (device float).  Asynchronous. */
+int shape_colsum(shape_ctx* ctx, int32_t M, int32_t N, const float* A, int64_t lda,
+                 float* out, void* stream);
+
+/* Weighted mean squared error of predictions y against targets t (device
+ * float [B][N]) with per-output weights w (device float [N]):
+ * loss = sum_j w_j mean_b (y - t)^2 (device float [1]), grad = dloss/dy
+ * (device float [B][N]).  Deterministic.  Asynchronous. */
+int shape_mse(shape_ctx* ctx, int32_t B, int32_t N, const float* y, const float* t,
+              const float* w, void* stream, float* grad, float* loss);
+
+/* Adam (Kingma and Ba) descent step on a flat FP32 vector p with gradient g
+ * and moments m, v (all device float [n]); step: device int32 holding the
+ * steps already taken, advanced by one.  Asynchronous. */
+int shape_adam(shape_ctx* ctx, float* p, const float* g, float* m, float* v, int64_t n,
+               int32_t* step, float lr, float beta1, float beta2, float eps, void* stream);
+
+/* Indices of the k largest scores (device float [n]; NaN ranks lowest; ties
+ * go to the lower index), written in increasing index order to idx (device
+ * int32 [k]).  1 <= k <= n.  Asynchronous. */
+int shape_topk(shape_ctx* ctx, const float* score, int32_t n, int32_t k, void* stream,
+               int32_t* idx);
 
 /* Kernel timing (measurement support, not part of the method).  While
  * enabled, every call records a pair of HIP events on its stream around its

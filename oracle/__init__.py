@@ -55,7 +55,7 @@ def lib():
         L.or_estimate.argtypes = [_i, _f32p, _f32p, _u32, _i, _f32p, _f32p, _u32,
                                   _i64, _i64, _u64, _f64p]
         L.or_screen.argtypes = [_i, _f32p, _f32p, _u32, _i32p, _f32p, _f32p, _vp, _vp,
-                                ctypes.c_int32, _i, _i64, _i64, _i64, _d, _u64, _i, _f64p]
+                                ctypes.c_int32, _i, _i64, _i64, _i64, _d, _u64, _i, _vp, _f64p]
         L.or_fo_overlap.argtypes = [_i, _f32p, _f32p, _i, _f32p, _f32p]
         L.or_fo_overlap.restype = _d
         L.or_fo_second_moment.argtypes = [_i, _f32p, _f32p, _i, _f32p, _f32p]
@@ -70,6 +70,14 @@ def lib():
         L.or_align_adam.argtypes = [_i, _f32p, _f32p, _u32, _i, _f32p, _f32p, _u32,
                                     _i64, _u64, ctypes.c_int32, _f64p, ctypes.c_int32, _d,
                                     _f64p, _f64p]
+        L.or_features.argtypes = [ctypes.c_int32, _i32p, _f32p, _f32p, _f64p]
+        L.or_mlp_nparams.argtypes = [_i, _i32p]
+        L.or_mlp_nparams.restype = _i64
+        L.or_mlp_forward.argtypes = [_i, _i32p, _f64p, ctypes.c_int32, _f64p, _f64p]
+        L.or_mlp_loss_grad.argtypes = [_i, _i32p, _f64p, ctypes.c_int32, _f64p, _f64p, _f64p,
+                                       _f64p, _f64p]
+        L.or_adam.argtypes = [_i64, _f64p, _f64p, _f64p, _f64p, ctypes.c_int32, _d, _d, _d, _d]
+        L.or_adam.restype = None
         L.or_num_threads.restype = _i
         _lib = L
     return _lib
@@ -145,7 +153,7 @@ def estimate(A, B, n_a, n_b, seed=0, id_a=0, id_b=1) -> dict:
 
 def screen(query, id_q, lib_off, lib_xyz, lib_alpha, lib_id=None, pairs=None,
            mode=0, n_fixed=4096, round_per_pair=512, cap_per_pair=65536,
-           tau=0.005, seed=0, n_threads=0):
+           tau=0.005, seed=0, n_threads=0, n_start=None):
     """Returns [n_pairs, 6] = T, se_T, O_ab, O_aa, O_bb, n_used (pair total)."""
     xq, aq = _mol(*query)
     off = np.ascontiguousarray(lib_off, np.int32)
@@ -154,12 +162,13 @@ def screen(query, id_q, lib_off, lib_xyz, lib_alpha, lib_id=None, pairs=None,
     ids = None if lib_id is None else np.ascontiguousarray(lib_id, np.uint32)
     pr = None if pairs is None else np.ascontiguousarray(pairs, np.int32)
     n_pairs = off.size - 1 if pr is None else pr.size
+    ns = None if n_start is None else np.ascontiguousarray(n_start, np.int32)
     out = np.zeros((n_pairs, 6))
     rc = lib().or_screen(aq.size, xq, aq, id_q, off, lx, la,
                          None if ids is None else ids.ctypes.data,
                          None if pr is None else pr.ctypes.data, n_pairs, mode,
                          n_fixed, round_per_pair, cap_per_pair, tau, seed,
-                         n_threads, out)
+                         n_threads, None if ns is None else ns.ctypes.data, out)
     if rc:
         raise RuntimeError("oracle screen failed")
     return out
@@ -235,3 +244,50 @@ def align_adam(A, B, pose0, n_steps=60, lr=0.05, n_samples=2048, seed=0, id_a=0,
 
 def num_threads() -> int:
     return lib().or_num_threads()
+
+
+# ----------------------------------------------------------------------------
+# Surrogate (learned triage): features, MLP and Adam in FP64.
+# ----------------------------------------------------------------------------
+FEATURES = 24
+
+
+def features(offsets, xyz, alpha) -> np.ndarray:
+    """[n_mols, 24] per-molecule features (see shape_oracle.c)."""
+    off = np.ascontiguousarray(offsets, np.int32)
+    x = np.ascontiguousarray(xyz, np.float32).reshape(-1, 3)
+    a = np.ascontiguousarray(alpha, np.float32)
+    out = np.zeros((off.size - 1, FEATURES))
+    if lib().or_features(off.size - 1, off, x, a, out):
+        raise RuntimeError("oracle features failed")
+    return out
+
+
+def mlp_nparams(width) -> int:
+    w = np.ascontiguousarray(width, np.int32)
+    return int(lib().or_mlp_nparams(w.size - 1, w))
+
+
+def mlp_forward(width, params, x) -> np.ndarray:
+    w = np.ascontiguousarray(width, np.int32)
+    x = np.ascontiguousarray(x, np.float64)
+    y = np.zeros((x.shape[0], int(w[-1])))
+    lib().or_mlp_forward(w.size - 1, w, np.ascontiguousarray(params, np.float64), x.shape[0],
+                         x, y)
+    return y
+
+
+def mlp_loss_grad(width, params, x, target, loss_weights):
+    w = np.ascontiguousarray(width, np.int32)
+    x = np.ascontiguousarray(x, np.float64)
+    g = np.zeros(mlp_nparams(width))
+    loss = np.zeros(1)
+    lib().or_mlp_loss_grad(w.size - 1, w, np.ascontiguousarray(params, np.float64), x.shape[0],
+                           x, np.ascontiguousarray(target, np.float64),
+                           np.ascontiguousarray(loss_weights, np.float64), loss, g)
+    return float(loss[0]), g
+
+
+def adam(p, g, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
+    """In place on p, m, v (float64 arrays)."""
+    lib().or_adam(p.size, p, np.ascontiguousarray(g, np.float64), m, v, int(t), lr, b1, b2, eps)

@@ -366,7 +366,8 @@ int or_screen(int nq, const float* xyz_q, const float* alpha_q, uint32_t id_q,
               const int32_t* lib_off, const float* lib_xyz, const float* lib_alpha,
               const uint32_t* lib_id, const int32_t* pairs, int32_t n_pairs,
               int mode, int64_t n_fixed, int64_t round_per_pair, int64_t cap_per_pair,
-              double tau, uint64_t seed, int n_threads, double* out6) {
+              double tau, uint64_t seed, int n_threads, const int32_t* n_start,
+              double* out6) {
   or_mol Q;
   if (or_mol_init(&Q, nq, xyz_q, alpha_q)) return -1;
   int err = 0;
@@ -415,6 +416,8 @@ int or_screen(int nq, const float* xyz_q, const float* alpha_q, uint32_t id_q,
         or_stats(fa, n, &sa);
         or_stats(fb, n, &sb);
         or_combine(Q.Z, B.Z, &sa, &sb, &r);
+        /* a seeded budget defers the first stop test until it is spent */
+        if (n_start && 2 * n < (int64_t)n_start[p] && 2 * n < cap_per_pair) continue;
         if (r.se_T <= tau || 2 * n >= cap_per_pair) break;
       }
       free(fa); free(fb); free(ta); free(tb);
@@ -804,4 +807,210 @@ int or_num_threads(void) {
 #else
   return 1;
 #endif
+}
+
+/* ------------------------------------------------------------------------- */
+/* Surrogate features (no counterpart in the paper: the learned triage model  */
+/* that seeds confidence-bounded screening).  Per molecule, 24 numbers:       */
+/*   [0..15]  histogram of |c_i - mu| in 0.5 A bins over [0, 8), last bin     */
+/*            open, mu = sum pi_i c_i the mixture mean (pi_i = v_i / Z)       */
+/*   [16..18] square roots of the eigenvalues (descending) of the mixture    */
+/*            covariance sum pi_i (c_i c_i^T + I/(2 alpha_i)) - mu mu^T       */
+/*   [19..22] counts of atoms in four width classes, alpha < 0.767,          */
+/*            [0.767, 0.893), [0.893, 0.995), >= 0.995 A^-2                   */
+/*   [23]     first-order self-overlap (Eq. fo with B = A)                    */
+/* Eigenvalues by Jacobi rotations (plain, converged to machine precision).   */
+/* ------------------------------------------------------------------------- */
+static void or_sym3_eig(double a[3][3], double ev[3]) {
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = fabs(a[0][1]) + fabs(a[0][2]) + fabs(a[1][2]);
+    if (off < 1e-300) break;
+    for (int p = 0; p < 2; ++p)
+      for (int q = p + 1; q < 3; ++q) {
+        if (a[p][q] == 0.0) continue;
+        double theta = (a[q][q] - a[p][p]) / (2.0 * a[p][q]);
+        double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+        double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+        for (int k = 0; k < 3; ++k) {  /* columns p, q */
+          double akp = a[k][p], akq = a[k][q];
+          a[k][p] = c * akp - s * akq;
+          a[k][q] = s * akp + c * akq;
+        }
+        for (int k = 0; k < 3; ++k) {  /* rows p, q */
+          double apk = a[p][k], aqk = a[q][k];
+          a[p][k] = c * apk - s * aqk;
+          a[q][k] = s * apk + c * aqk;
+        }
+      }
+  }
+  ev[0] = a[0][0]; ev[1] = a[1][1]; ev[2] = a[2][2];
+  /* descending */
+  for (int i = 0; i < 3; ++i)
+    for (int j = i + 1; j < 3; ++j)
+      if (ev[j] > ev[i]) { double t = ev[i]; ev[i] = ev[j]; ev[j] = t; }
+}
+
+int or_features(int32_t n_mols, const int32_t* off, const float* xyz, const float* alpha,
+                double* out24) {
+  for (int32_t m = 0; m < n_mols; ++m) {
+    int a0 = off[m], n = off[m + 1] - off[m];
+    double* f = out24 + 24 * (size_t)m;
+    for (int k = 0; k < 24; ++k) f[k] = 0.0;
+    or_mol M;
+    if (or_mol_init(&M, n, xyz + 3 * (size_t)a0, alpha + a0)) return -1;
+    double mu[3] = {0, 0, 0};
+    for (int i = 0; i < n; ++i)
+      for (int d = 0; d < 3; ++d) mu[d] += (M.v[i] / M.Z) * M.c[3 * i + d];
+    for (int i = 0; i < n; ++i) {
+      double dx = M.c[3 * i] - mu[0], dy = M.c[3 * i + 1] - mu[1], dz = M.c[3 * i + 2] - mu[2];
+      double r = sqrt(dx * dx + dy * dy + dz * dz);
+      int b = (int)floor(r / 0.5);
+      if (b > 15) b = 15;
+      f[b] += 1.0;
+    }
+    double cov[3][3] = {{0}};
+    for (int i = 0; i < n; ++i) {
+      double pi = M.v[i] / M.Z;
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+          cov[a][b] += pi * (M.c[3 * i + a] * M.c[3 * i + b] + (a == b ? 0.5 / M.alpha[i] : 0.0));
+    }
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) cov[a][b] -= mu[a] * mu[b];
+    double ev[3];
+    or_sym3_eig(cov, ev);
+    for (int k = 0; k < 3; ++k) f[16 + k] = sqrt(ev[k] > 0 ? ev[k] : 0.0);
+    for (int i = 0; i < n; ++i) {
+      double al = M.alpha[i];
+      int cls = al < 0.767 ? 0 : (al < 0.893 ? 1 : (al < 0.995 ? 2 : 3));
+      f[19 + cls] += 1.0;
+    }
+    f[23] = or_fo_overlap(n, xyz + 3 * (size_t)a0, alpha + a0, n, xyz + 3 * (size_t)a0, alpha + a0);
+    or_mol_free(&M);
+  }
+  return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Surrogate MLP in FP64: L dense layers, ReLU between them, linear output.   */
+/* Layer l maps width[l] -> width[l+1]: h_{l+1} = act(h_l W_l + b_l), W_l     */
+/* row-major [width[l]][width[l+1]].  Parameters are packed W_0, b_0, W_1,    */
+/* b_1, ...  Loss: sum over outputs j of lw_j * mean_b (y_bj - t_bj)^2.       */
+/* or_mlp_loss_grad returns the loss and d loss / d params (same packing).    */
+/* ------------------------------------------------------------------------- */
+int64_t or_mlp_nparams(int L, const int32_t* width) {
+  int64_t n = 0;
+  for (int l = 0; l < L; ++l) n += (int64_t)width[l] * width[l + 1] + width[l + 1];
+  return n;
+}
+
+int or_mlp_forward(int L, const int32_t* width, const double* params, int32_t batch,
+                   const double* x, double* y) {
+  int maxw = 0;
+  for (int l = 0; l <= L; ++l) if (width[l] > maxw) maxw = width[l];
+  double* h = (double*)malloc(sizeof(double) * (size_t)batch * maxw);
+  double* g = (double*)malloc(sizeof(double) * (size_t)batch * maxw);
+  if (!h || !g) { free(h); free(g); return -1; }
+  memcpy(h, x, sizeof(double) * (size_t)batch * width[0]);
+  const double* p = params;
+  for (int l = 0; l < L; ++l) {
+    int ni = width[l], no = width[l + 1];
+    const double* W = p;
+    const double* b = p + (size_t)ni * no;
+    for (int32_t s = 0; s < batch; ++s)
+      for (int j = 0; j < no; ++j) {
+        double acc = b[j];
+        for (int i = 0; i < ni; ++i) acc += h[(size_t)s * ni + i] * W[(size_t)i * no + j];
+        g[(size_t)s * no + j] = (l + 1 < L && acc < 0.0) ? 0.0 : acc;
+      }
+    double* t = h; h = g; g = t;
+    p += (size_t)ni * no + no;
+  }
+  memcpy(y, h, sizeof(double) * (size_t)batch * width[L]);
+  free(h); free(g);
+  return 0;
+}
+
+int or_mlp_loss_grad(int L, const int32_t* width, const double* params, int32_t batch,
+                     const double* x, const double* target, const double* lw,
+                     double* loss_out, double* grad) {
+  /* keep every layer's output */
+  int64_t offs[17];
+  if (L > 16) return -2;
+  int64_t tot = 0;
+  for (int l = 0; l <= L; ++l) { offs[l] = tot; tot += (int64_t)batch * width[l]; }
+  double* H = (double*)malloc(sizeof(double) * (size_t)tot);
+  if (!H) return -1;
+  memcpy(H, x, sizeof(double) * (size_t)batch * width[0]);
+  const double* p = params;
+  for (int l = 0; l < L; ++l) {
+    int ni = width[l], no = width[l + 1];
+    const double* W = p;
+    const double* b = p + (size_t)ni * no;
+    for (int32_t s = 0; s < batch; ++s)
+      for (int j = 0; j < no; ++j) {
+        double acc = b[j];
+        for (int i = 0; i < ni; ++i) acc += H[offs[l] + (size_t)s * ni + i] * W[(size_t)i * no + j];
+        H[offs[l + 1] + (size_t)s * no + j] = (l + 1 < L && acc < 0.0) ? 0.0 : acc;
+      }
+    p += (size_t)ni * no + no;
+  }
+  int nout = width[L];
+  double loss = 0.0;
+  int maxw = 0;
+  for (int l = 0; l <= L; ++l) if (width[l] > maxw) maxw = width[l];
+  double* d = (double*)malloc(sizeof(double) * (size_t)batch * maxw);
+  double* dn = (double*)malloc(sizeof(double) * (size_t)batch * maxw);
+  if (!d || !dn) { free(H); free(d); free(dn); return -1; }
+  for (int32_t s = 0; s < batch; ++s)
+    for (int j = 0; j < nout; ++j) {
+      double e = H[offs[L] + (size_t)s * nout + j] - target[(size_t)s * nout + j];
+      loss += lw[j] * e * e / batch;
+      d[(size_t)s * nout + j] = 2.0 * lw[j] * e / batch;
+    }
+  *loss_out = loss;
+  /* walk layers backwards; parameter offsets */
+  int64_t poff[17];
+  int64_t acc = 0;
+  for (int l = 0; l < L; ++l) { poff[l] = acc; acc += (int64_t)width[l] * width[l + 1] + width[l + 1]; }
+  for (int l = L - 1; l >= 0; --l) {
+    int ni = width[l], no = width[l + 1];
+    const double* W = params + poff[l];
+    double* gW = grad + poff[l];
+    double* gb = gW + (size_t)ni * no;
+    for (int i = 0; i < ni; ++i)
+      for (int j = 0; j < no; ++j) {
+        double s2 = 0.0;
+        for (int32_t s = 0; s < batch; ++s) s2 += H[offs[l] + (size_t)s * ni + i] * d[(size_t)s * no + j];
+        gW[(size_t)i * no + j] = s2;
+      }
+    for (int j = 0; j < no; ++j) {
+      double s2 = 0.0;
+      for (int32_t s = 0; s < batch; ++s) s2 += d[(size_t)s * no + j];
+      gb[j] = s2;
+    }
+    if (l > 0) {
+      for (int32_t s = 0; s < batch; ++s)
+        for (int i = 0; i < ni; ++i) {
+          double s2 = 0.0;
+          for (int j = 0; j < no; ++j) s2 += d[(size_t)s * no + j] * W[(size_t)i * no + j];
+          /* ReLU of layer l's output: derivative 1 where the output is > 0 */
+          dn[(size_t)s * ni + i] = H[offs[l] + (size_t)s * ni + i] > 0.0 ? s2 : 0.0;
+        }
+      double* t = d; d = dn; dn = t;
+    }
+  }
+  free(H); free(d); free(dn);
+  return 0;
+}
+
+/* Adam (Kingma and Ba) on a flat parameter vector, step t >= 1, descending. */
+void or_adam(int64_t n, double* p, const double* g, double* m, double* v, int32_t t, double lr,
+             double b1, double b2, double eps) {
+  for (int64_t i = 0; i < n; ++i) {
+    m[i] = b1 * m[i] + (1 - b1) * g[i];
+    v[i] = b2 * v[i] + (1 - b2) * g[i] * g[i];
+    double mh = m[i] / (1 - pow(b1, t)), vh = v[i] / (1 - pow(b2, t));
+    p[i] -= lr * mh / (sqrt(vh) + eps);
+  }
 }

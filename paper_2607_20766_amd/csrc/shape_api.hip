@@ -28,6 +28,7 @@ enum Slot {
   S_L_ATOM, S_L_SAMP, S_L_Z, S_L_ID, S_L_BAD, S_L_CENTRE,
   S_PARTIALS, S_RESULT, S_QS, S_QF2,
   S_SELF_A, S_SELF_B, S_ADAM_M, S_ADAM_V, S_ADAM_STEP, S_GRAD,
+  S_MSE, S_TOPK_SEL, S_TOPK_HIST, S_TOPK_GT, S_TOPK_EQ,
   S_COUNT
 };
 
@@ -349,6 +350,7 @@ int shape_screen(shape_ctx* c, const shape_mols* query, const shape_mols* lib,
     a.cap_pair = cap;
     a.tau = prm->tau;
     a.key = key;
+    a.n_start = prm->mode == SHAPE_SCREEN_ADAPTIVE ? prm->n_start : nullptr;
     a.T = out->T;
     a.se_T = out->se_T;
     a.O_ab = out->O_ab;
@@ -525,6 +527,143 @@ int shape_align(shape_ctx* c, const shape_mols* A, const shape_mols* B, int32_t 
   } catch (...) {
     return fail(c, SHAPE_E_HIP, "internal error");
   }
+}
+
+int shape_features(shape_ctx* c, const shape_mols* M, void* stream, float* out) {
+  if (!c) return SHAPE_E_INVAL;
+  try {
+    int rc;
+    if ((rc = check_mols(c, M, "M", false))) return rc;
+    if (!out) return fail(c, SHAPE_E_INVAL, "out is NULL");
+    if ((rc = set_device(c))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    shape::Prepared P;
+    if ((rc = prepare(c, M, false, st, &P))) return rc;
+    KernelTimer timer(c, st);
+    HIP_TRY(c, shape::launch_features(P, M->atom_offset, M->alpha, M->n_mols, out, st),
+            "features kernel");
+    timer.stop();
+    return SHAPE_OK;
+  } catch (...) {
+    return fail(c, SHAPE_E_HIP, "internal error");
+  }
+}
+
+int shape_fo_overlap(shape_ctx* c, const shape_mols* query, const shape_mols* lib,
+                     const int32_t* pairs, int32_t n_pairs, void* stream, float* out) {
+  if (!c) return SHAPE_E_INVAL;
+  try {
+    int rc;
+    if ((rc = check_mols(c, query, "query", true))) return rc;
+    if ((rc = check_mols(c, lib, "lib", false))) return rc;
+    if (n_pairs < 0) return fail(c, SHAPE_E_RANGE, "n_pairs < 0");
+    if (!pairs && n_pairs > lib->n_mols)
+      return fail(c, SHAPE_E_RANGE, "n_pairs exceeds lib->n_mols");
+    if (n_pairs == 0) return SHAPE_OK;
+    if (!out) return fail(c, SHAPE_E_INVAL, "out is NULL");
+    if ((rc = set_device(c))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    shape::Prepared PQ, PL;
+    if ((rc = prepare(c, query, true, st, &PQ))) return rc;
+    if ((rc = prepare(c, lib, false, st, &PL))) return rc;
+    HIP_TRY(c, shape::launch_fo_cross(PQ, query->atom_offset, query->alpha, PL, lib->atom_offset,
+                                      lib->alpha, pairs, n_pairs, lib->n_mols, out, st),
+            "first-order overlap kernel");
+    return SHAPE_OK;
+  } catch (...) {
+    return fail(c, SHAPE_E_HIP, "internal error");
+  }
+}
+
+int shape_pair_features(shape_ctx* c, const float* f_q, const float* f_lib, const int32_t* qidx,
+                        const int32_t* idx, int32_t n, const float* fo_cross, const float* mean,
+                        const float* inv_std, void* stream, float* out) {
+  if (!c) return SHAPE_E_INVAL;
+  if (n < 0) return fail(c, SHAPE_E_RANGE, "n < 0");
+  if (n == 0) return SHAPE_OK;
+  if (!f_q || !f_lib || !mean || !inv_std || !out) return fail(c, SHAPE_E_INVAL, "NULL array");
+  int rc = set_device(c);
+  if (rc) return rc;
+  HIP_TRY(c, shape::launch_pair_features(f_q, f_lib, qidx, idx, n, fo_cross, mean, inv_std,
+                                         out, (hipStream_t)stream),
+          "pair features kernel");
+  return SHAPE_OK;
+}
+
+int shape_gemm(shape_ctx* c, int32_t M, int32_t N, int32_t K, const float* A, int64_t sam,
+               int64_t sak, const float* B, int64_t sbk, int64_t sbn, float* C, int64_t scm,
+               const float* bias, const float* gate, int64_t sgm, uint32_t flags, void* stream) {
+  if (!c) return SHAPE_E_INVAL;
+  if (M < 1 || N < 1 || K < 1) return fail(c, SHAPE_E_RANGE, "M, N, K must be >= 1");
+  if (!A || !B || !C) return fail(c, SHAPE_E_INVAL, "NULL array");
+  if (flags & ~(SHAPE_GEMM_BF16 | SHAPE_GEMM_RELU)) return fail(c, SHAPE_E_INVAL, "bad flags");
+  int rc = set_device(c);
+  if (rc) return rc;
+  shape::GemmArgs g{M, N, K, A, sam, sak, B, sbk, sbn, C, scm, bias, gate, sgm, (int)flags};
+  HIP_TRY(c, shape::launch_gemm(g, (hipStream_t)stream), "gemm kernel");
+  return SHAPE_OK;
+}
+
+int shape_colsum(shape_ctx* c, int32_t M, int32_t N, const float* A, int64_t lda, float* out,
+                 void* stream) {
+  if (!c) return SHAPE_E_INVAL;
+  if (M < 1 || N < 1) return fail(c, SHAPE_E_RANGE, "M, N must be >= 1");
+  if (!A || !out) return fail(c, SHAPE_E_INVAL, "NULL array");
+  int rc = set_device(c);
+  if (rc) return rc;
+  HIP_TRY(c, shape::launch_colsum(A, M, N, lda, out, (hipStream_t)stream), "colsum kernel");
+  return SHAPE_OK;
+}
+
+int shape_mse(shape_ctx* c, int32_t B, int32_t N, const float* y, const float* t, const float* w,
+              void* stream, float* grad, float* loss) {
+  if (!c) return SHAPE_E_INVAL;
+  if (B < 1 || N < 1) return fail(c, SHAPE_E_RANGE, "B, N must be >= 1");
+  if (!y || !t || !w || !grad || !loss) return fail(c, SHAPE_E_INVAL, "NULL array");
+  int rc = set_device(c);
+  if (rc) return rc;
+  void* part;
+  if ((rc = ensure(c, S_MSE, (size_t)shape::mse_blocks(B, N) * sizeof(double), &part))) return rc;
+  HIP_TRY(c, shape::launch_mse(y, t, w, B, N, grad, (double*)part, loss, (hipStream_t)stream),
+          "mse kernels");
+  return SHAPE_OK;
+}
+
+int shape_adam(shape_ctx* c, float* p, const float* g, float* m, float* v, int64_t n,
+               int32_t* step, float lr, float beta1, float beta2, float eps, void* stream) {
+  if (!c) return SHAPE_E_INVAL;
+  if (n < 0) return fail(c, SHAPE_E_RANGE, "n < 0");
+  if (n == 0) return SHAPE_OK;
+  if (!p || !g || !m || !v || !step) return fail(c, SHAPE_E_INVAL, "NULL array");
+  if (!(lr > 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) ||
+      !(eps > 0.f))
+    return fail(c, SHAPE_E_RANGE, "Adam hyper-parameters out of range");
+  int rc = set_device(c);
+  if (rc) return rc;
+  HIP_TRY(c, shape::launch_adam(p, g, m, v, n, step, lr, beta1, beta2, eps, (hipStream_t)stream),
+          "Adam kernel");
+  return SHAPE_OK;
+}
+
+int shape_topk(shape_ctx* c, const float* score, int32_t n, int32_t k, void* stream,
+               int32_t* idx) {
+  if (!c) return SHAPE_E_INVAL;
+  if (n < 1 || k < 1 || k > n) return fail(c, SHAPE_E_RANGE, "need 1 <= k <= n");
+  if (!score || !idx) return fail(c, SHAPE_E_INVAL, "NULL array");
+  int rc = set_device(c);
+  if (rc) return rc;
+  void *sel, *hist, *gt, *eq;
+  const int nb = shape::topk_blocks(n);
+  if ((rc = ensure(c, S_TOPK_SEL, 4 * sizeof(uint32_t), &sel))) return rc;
+  if ((rc = ensure(c, S_TOPK_HIST, 256 * sizeof(uint32_t), &hist))) return rc;
+  if ((rc = ensure(c, S_TOPK_GT, (size_t)nb * sizeof(int), &gt))) return rc;
+  if ((rc = ensure(c, S_TOPK_EQ, (size_t)nb * sizeof(int), &eq))) return rc;
+  KernelTimer timer(c, (hipStream_t)stream);
+  HIP_TRY(c, shape::launch_topk(score, n, k, (uint32_t*)sel, (uint32_t*)hist, (int*)gt, (int*)eq,
+                                idx, (hipStream_t)stream),
+          "top-k kernels");
+  timer.stop();
+  return SHAPE_OK;
 }
 
 int shape_timing_enable(shape_ctx* c, int enable) {

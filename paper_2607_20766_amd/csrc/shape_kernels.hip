@@ -397,6 +397,7 @@ __global__ __launch_bounds__(64) void k_screen(ScreenArgs a) {
 #pragma unroll
   for (int j = 0; j < 10; ++j) acc[j] = 0.0;
   int64_t n_side = 0;
+  const int64_t first_check = a.n_start ? (int64_t)a.n_start[p] : 0;
   for (;;) {
     float fa[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
     float fb[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
@@ -456,7 +457,9 @@ __global__ __launch_bounds__(64) void k_screen(ScreenArgs a) {
     }
     n_side += rs;
     int stop;
-    if (a.mode == SHAPE_SCREEN_ADAPTIVE) {
+    if (a.mode == SHAPE_SCREEN_ADAPTIVE && 2 * n_side < first_check && 2 * n_side < a.cap_pair) {
+      stop = 0;  // below the pair's seeded budget: no test yet
+    } else if (a.mode == SHAPE_SCREEN_ADAPTIVE) {
       const double sa1 = wave_sum(acc[0]), sa11 = wave_sum(acc[1]), sa2 = wave_sum(acc[2]);
       const double sb1 = wave_sum(acc[5]), sb11 = wave_sum(acc[6]), sb2 = wave_sum(acc[7]);
       const double se = se_tanimoto((double)n_side, Za, Zb, sa1, sa11, sa2, sb1, sb11, sb2,

@@ -51,6 +51,7 @@ struct ScreenArgs {
   int64_t cap_pair;    // adaptive cap, samples per pair
   double tau;
   uint2 key;
+  const int* n_start;  // optional per-pair budgets (adaptive)
   float* T;
   float* se_T;
   float* O_ab;
@@ -76,6 +77,40 @@ struct AlignArgs {
   float* T;           // [pairs][starts]
   float* grad;        // [pairs][starts][7] or nullptr
 };
+
+// Dense layer C = epilogue(A B) with strided operands (see shape_gemm).
+struct GemmArgs {
+  int M, N, K;
+  const float* A;
+  int64_t sam, sak;
+  const float* B;
+  int64_t sbk, sbn;
+  float* C;
+  int64_t scm;
+  const float* bias;
+  const float* gate;
+  int64_t sgm;
+  int flags;
+};
+
+hipError_t launch_features(const Prepared& M, const int* off, const float* alpha, int n_mols,
+                           float* out, hipStream_t st);
+hipError_t launch_pair_features(const float* fq, const float* flib, const int* qidx,
+                                const int* idx, int n, const float* fo_cross, const float* mean,
+                                const float* inv_std, float* out, hipStream_t st);
+hipError_t launch_fo_cross(const Prepared& Q, const int* offQ, const float* alphaQ,
+                           const Prepared& L, const int* offL, const float* alphaL,
+                           const int* pairs, int n_pairs, int n_lib, float* out, hipStream_t st);
+hipError_t launch_gemm(const GemmArgs& g, hipStream_t st);
+hipError_t launch_colsum(const float* A, int M, int N, int64_t lda, float* out, hipStream_t st);
+int mse_blocks(int B, int N);
+hipError_t launch_mse(const float* y, const float* t, const float* w, int B, int N, float* grad,
+                      double* partial, float* loss, hipStream_t st);
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, int* step,
+                       float lr, float b1, float b2, float eps, hipStream_t st);
+int topk_blocks(int n);
+hipError_t launch_topk(const float* s, int n, int k, uint32_t* sel, uint32_t* hist, int* cnt_gt,
+                       int* cnt_eq, int* out, hipStream_t st);
 
 size_t align_lds_bytes(int n_samples, int max_a, int max_b);
 hipError_t launch_align(const AlignArgs& a, int n_pairs, hipStream_t st);

@@ -1,0 +1,584 @@
+// Learned triage for confidence-bounded screening: per-molecule features, the
+// dense layers of a small MLP on the matrix cores (BF16 or FP32 operands,
+// FP32 accumulation), its loss, Adam, and top-k selection.
+#include "shape_kernels.hpp"
+
+#include <math.h>
+
+namespace shape {
+
+// ---------------------------------------------------------------------------
+// Features, one wave per molecule (24 floats):
+//   [0..15]  counts of |c_i - mu| in 0.5 A bins over [0, 8), last bin open
+//   [16..18] sqrt of the descending eigenvalues of the mixture covariance
+//            sum pi_i (c_i c_i^T + I/(2 alpha_i)) - mu mu^T, pi_i = v_i / Z
+//   [19..22] atoms in the width classes alpha < 0.767, [0.767, 0.893),
+//            [0.893, 0.995), >= 0.995
+//   [23]     first-order self-overlap sum_ij (pi/(a_i+a_j))^(3/2)
+//            exp(-a_i a_j/(a_i+a_j) |c_i-c_j|^2)
+// Moments in FP64; the O(N^2) overlap sum in FP32 per lane, FP64 across lanes.
+// ---------------------------------------------------------------------------
+__device__ void sym3_eigen_desc(double a[3][3], double ev[3]) {
+  // cyclic Jacobi rotations
+  for (int sweep = 0; sweep < 50; ++sweep) {
+    const double off = fabs(a[0][1]) + fabs(a[0][2]) + fabs(a[1][2]);
+    if (off < 1e-300) break;
+    for (int p = 0; p < 2; ++p)
+      for (int q = p + 1; q < 3; ++q) {
+        if (a[p][q] == 0.0) continue;
+        const double theta = (a[q][q] - a[p][p]) / (2.0 * a[p][q]);
+        const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+        const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+        for (int k = 0; k < 3; ++k) {
+          const double akp = a[k][p], akq = a[k][q];
+          a[k][p] = c * akp - s * akq;
+          a[k][q] = s * akp + c * akq;
+        }
+        for (int k = 0; k < 3; ++k) {
+          const double apk = a[p][k], aqk = a[q][k];
+          a[p][k] = c * apk - s * aqk;
+          a[q][k] = s * apk + c * aqk;
+        }
+      }
+  }
+  ev[0] = a[0][0];
+  ev[1] = a[1][1];
+  ev[2] = a[2][2];
+  for (int i = 0; i < 3; ++i)
+    for (int j = i + 1; j < 3; ++j)
+      if (ev[j] > ev[i]) {
+        const double t = ev[i];
+        ev[i] = ev[j];
+        ev[j] = t;
+      }
+}
+
+__global__ __launch_bounds__(64) void k_features(Prepared M, const int* __restrict__ off,
+                                                 const float* __restrict__ alpha, int n_mols,
+                                                 float* __restrict__ out) {
+  __shared__ float4 sC[SHAPE_MAX_ATOMS];  // x, y, z, alpha
+  const int mol = blockIdx.x;
+  const int lane = threadIdx.x;
+  if (mol >= n_mols) return;
+  float* f = out + (size_t)mol * 24;
+  if (M.bad[mol] != 0) {
+    for (int k = lane; k < 24; k += kWave) f[k] = __builtin_nanf("");
+    return;
+  }
+  const int a0 = off[mol], n = off[mol + 1] - a0;
+  for (int i = lane; i < n; i += kWave) {
+    const Atom at = M.atom[a0 + i];
+    sC[i] = make_float4(at.x, at.y, at.z, alpha[a0 + i]);
+  }
+  __syncthreads();
+  const double Z = M.Z[mol];
+  double mx = 0.0, my = 0.0, mz = 0.0;
+  double sxx = 0.0, syy = 0.0, szz = 0.0, sxy = 0.0, sxz = 0.0, syz = 0.0;
+  for (int i = lane; i < n; i += kWave) {
+    const float4 c = sC[i];
+    const double al = (double)c.w, t = M_PI / al;
+    const double pi = t * sqrt(t) / Z;
+    const double x = c.x, y = c.y, z = c.z, h = 0.5 / al;
+    mx += pi * x; my += pi * y; mz += pi * z;
+    sxx += pi * (x * x + h); syy += pi * (y * y + h); szz += pi * (z * z + h);
+    sxy += pi * x * y; sxz += pi * x * z; syz += pi * y * z;
+  }
+  mx = wave_sum(mx); my = wave_sum(my); mz = wave_sum(mz);
+  sxx = wave_sum(sxx); syy = wave_sum(syy); szz = wave_sum(szz);
+  sxy = wave_sum(sxy); sxz = wave_sum(sxz); syz = wave_sum(syz);
+  // radial histogram and width classes by wave ballots (exact integer counts)
+  int hist_mine = 0, cls_mine = 0;  // lane b < 16 keeps bin b, lane c < 4 class c
+  for (int base = 0; base < n; base += kWave) {
+    const int i = base + lane;
+    int bin = -1, cls = -1;
+    if (i < n) {
+      const float4 c = sC[i];
+      const double dx = c.x - mx, dy = c.y - my, dz = c.z - mz;
+      const double r = sqrt(dx * dx + dy * dy + dz * dz);
+      bin = (int)floor(r / 0.5);
+      bin = bin > 15 ? 15 : bin;
+      cls = c.w < 0.767f ? 0 : (c.w < 0.893f ? 1 : (c.w < 0.995f ? 2 : 3));
+    }
+    for (int b = 0; b < 16; ++b) {
+      const int cnt = __popcll(__ballot(bin == b));
+      if (lane == b) hist_mine += cnt;
+    }
+    for (int b = 0; b < 4; ++b) {
+      const int cnt = __popcll(__ballot(cls == b));
+      if (lane == b) cls_mine += cnt;
+    }
+  }
+  // first-order self-overlap: lane i owns rows i, i+64, ...
+  float fo = 0.0f;
+  for (int i = lane; i < n; i += kWave) {
+    const float4 ci = sC[i];
+    for (int j = 0; j < n; ++j) {
+      const float4 cj = sC[j];
+      const float as = ci.w + cj.w;
+      const float dx = ci.x - cj.x, dy = ci.y - cj.y, dz = ci.z - cj.z;
+      const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+      const float t = 3.14159265358979f / as;
+      fo = fmaf(t * sqrtf(t), expf(-(ci.w * cj.w / as) * d2), fo);
+    }
+  }
+  const double fo_sum = wave_sum((double)fo);
+  if (lane < 16) f[lane] = (float)hist_mine;
+  if (lane < 4) f[19 + lane] = (float)cls_mine;
+  if (lane == 0) {
+    double cov[3][3] = {{sxx - mx * mx, sxy - mx * my, sxz - mx * mz},
+                        {sxy - mx * my, syy - my * my, syz - my * mz},
+                        {sxz - mx * mz, syz - my * mz, szz - mz * mz}};
+    double ev[3];
+    sym3_eigen_desc(cov, ev);
+    for (int k = 0; k < 3; ++k) f[16 + k] = (float)sqrt(ev[k] > 0.0 ? ev[k] : 0.0);
+    f[23] = (float)fo_sum;
+  }
+}
+
+// First-order cross-overlap of (query, library molecule) pairs at their
+// current poses, Eq. fo: sum_ij (pi/(a_i+a_j))^(3/2)
+// exp(-a_i a_j/(a_i+a_j) |c_i - c_j|^2); one wave per pair, lanes over the
+// query atoms, FP32 per lane, FP64 across lanes.
+__global__ __launch_bounds__(64) void k_fo_cross(Prepared Q, const int* __restrict__ offQ,
+                                                 const float* __restrict__ alphaQ, Prepared L,
+                                                 const int* __restrict__ offL,
+                                                 const float* __restrict__ alphaL,
+                                                 const int* __restrict__ pairs, int n_pairs,
+                                                 int n_lib, float* __restrict__ out) {
+  __shared__ float4 sB[SHAPE_MAX_ATOMS];
+  const int p = blockIdx.x, lane = threadIdx.x;
+  if (p >= n_pairs) return;
+  const int m = pairs ? pairs[p] : p;
+  if (Q.bad[0] != 0 || m < 0 || m >= n_lib || L.bad[m] != 0) {
+    if (lane == 0) out[p] = __builtin_nanf("");
+    return;
+  }
+  const int q0 = offQ[0], nq = offQ[1] - q0;
+  const int b0 = offL[m], nb = offL[m + 1] - b0;
+  for (int j = lane; j < nb; j += kWave) {
+    const Atom at = L.atom[b0 + j];
+    sB[j] = make_float4(at.x, at.y, at.z, alphaL[b0 + j]);
+  }
+  __syncthreads();
+  float acc = 0.0f;
+  for (int i = lane; i < nq; i += kWave) {
+    const Atom ai = Q.atom[q0 + i];
+    const float al = alphaQ[q0 + i];
+    for (int j = 0; j < nb; ++j) {
+      const float4 cj = sB[j];
+      const float as = al + cj.w;
+      const float dx = ai.x - cj.x, dy = ai.y - cj.y, dz = ai.z - cj.z;
+      const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+      const float t = 3.14159265358979f / as;
+      acc = fmaf(t * sqrtf(t), expf(-(al * cj.w / as) * d2), acc);
+    }
+  }
+  const double s = wave_sum((double)acc);
+  if (lane == 0) out[p] = (float)s;
+}
+
+// Pair features standardised, x_j = (raw_j - mean_j) * inv_std_j, with
+// raw = [f_q, f_m, |f_q - f_m|, f_q * f_m]; when the pair's first-order
+// cross-overlap O_qm is given, the two slots that would combine the two
+// self-overlaps (|.| and product of feature 23) carry the pair's first-order
+// Tanimoto O_qm / (O_qq + O_mm - O_qm) and O_qm itself.  One thread per
+// output element.
+__global__ void k_pair_features(const float* __restrict__ fq, const float* __restrict__ flib,
+                                const int* __restrict__ qidx, const int* __restrict__ idx, int n,
+                                const float* __restrict__ fo_cross,
+                                const float* __restrict__ mean,
+                                const float* __restrict__ inv_std, float* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)n * 96) return;
+  const int p = (int)(t / 96), j = (int)(t % 96);
+  const int m = idx ? idx[p] : p;
+  const int q = qidx ? qidx[p] : 0;
+  const int k = j % 24;
+  const float a = fq[(size_t)q * 24 + k], b = flib[(size_t)m * 24 + k];
+  float raw;
+  switch (j / 24) {
+    case 0: raw = a; break;
+    case 1: raw = b; break;
+    case 2: raw = fabsf(a - b); break;
+    default: raw = a * b; break;
+  }
+  if (fo_cross && k == 23 && j >= 48) {
+    const float o = fo_cross[p];
+    raw = (j < 72) ? o / (a + b - o) : o;
+  }
+  out[t] = (raw - mean[j]) * inv_std[j];
+}
+
+// ---------------------------------------------------------------------------
+// Dense layer on the matrix cores:
+//   C[m][n] = epilogue( sum_k A[m][k] B[k][n] )
+// A(m, k) = A[m sam + k sak], B(k, n) = B[k sbk + n sbn] (any transposition),
+// epilogue: + bias[n], then ReLU, or multiplication by 1[gate[m][n] > 0]
+// (ReLU backward).  Workgroup tile 64 x 64 (4 waves x 32 x 32, each 2 x 2
+// MFMA 16 x 16 tiles).  BF16: v_mfma_f32_16x16x16bf16_1k, operands rounded to
+// nearest even; FP32: v_mfma_f32_16x16x4f32.  Lane l supplies row (or column)
+// l mod 16 and k-group l / 16; result element (4 (l/16) + r, l mod 16) sits in
+// accumulator r of lane l.
+// ---------------------------------------------------------------------------
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ short to_bf16(float x) {
+  uint32_t u = __float_as_uint(x);
+  if ((u & 0x7F800000u) == 0x7F800000u) return (short)(u >> 16);  // inf / nan
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (short)(u >> 16);
+}
+
+template <bool BF16>
+__global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const int m0 = blockIdx.y * 64 + (wave >> 1) * 32;
+  const int n0 = blockIdx.x * 64 + (wave & 1) * 32;
+  const int li = lane & 15, lk = lane >> 4;
+  v4f acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+  const int kstep = BF16 ? 16 : 4;
+  for (int k0 = 0; k0 < g.K; k0 += kstep) {
+    if (BF16) {
+      v4s a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int m = m0 + 16 * i + li;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int k = k0 + 4 * lk + e;
+          const float v = (m < g.M && k < g.K) ? g.A[(int64_t)m * g.sam + (int64_t)k * g.sak] : 0.f;
+          a[i][e] = to_bf16(v);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int n = n0 + 16 * j + li;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int k = k0 + 4 * lk + e;
+          const float v = (n < g.N && k < g.K) ? g.B[(int64_t)k * g.sbk + (int64_t)n * g.sbn] : 0.f;
+          b[j][e] = to_bf16(v);
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+    } else {
+      float a[2], b[2];
+      const int k = k0 + lk;
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int m = m0 + 16 * i + li;
+        a[i] = (m < g.M && k < g.K) ? g.A[(int64_t)m * g.sam + (int64_t)k * g.sak] : 0.f;
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int n = n0 + 16 * j + li;
+        b[j] = (n < g.N && k < g.K) ? g.B[(int64_t)k * g.sbk + (int64_t)n * g.sbn] : 0.f;
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + 16 * i + 4 * lk + r;
+        const int n = n0 + 16 * j + li;
+        if (m < g.M && n < g.N) {
+          float v = acc[i][j][r];
+          if (g.bias) v += g.bias[n];
+          if (g.flags & SHAPE_GEMM_RELU) v = v > 0.f ? v : 0.f;
+          if (g.gate && !(g.gate[(int64_t)m * g.sgm + n] > 0.f)) v = 0.f;
+          g.C[(int64_t)m * g.scm + n] = v;
+        }
+      }
+}
+
+// Column sums of A[M][N] (row stride lda), one thread per column, in row
+// order (deterministic).
+__global__ void k_colsum(const float* __restrict__ A, int M, int N, int64_t lda,
+                         float* __restrict__ out) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  double s = 0.0;
+  for (int m = 0; m < M; ++m) s += A[(int64_t)m * lda + n];
+  out[n] = (float)s;
+}
+
+// Weighted mean squared error over a batch: loss = sum_j w_j mean_b (y - t)^2,
+// grad = 2 w_j (y - t) / B.  Loss partials per block, then one block sums them
+// in order.
+__global__ __launch_bounds__(256) void k_mse(const float* __restrict__ y,
+                                             const float* __restrict__ t,
+                                             const float* __restrict__ w, int B, int N,
+                                             float* __restrict__ grad,
+                                             double* __restrict__ partial) {
+  __shared__ double red[4];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double l = 0.0;
+  if (i < (int64_t)B * N) {
+    const int j = (int)(i % N);
+    const float e = y[i] - t[i];
+    grad[i] = 2.f * w[j] * e / (float)B;
+    l = (double)w[j] * (double)e * (double)e / (double)B;
+  }
+  l = wave_sum(l);
+  if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = l;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ void k_sum_partials(const double* __restrict__ partial, int n, float* __restrict__ out) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  double s = 0.0;
+  for (int i = 0; i < n; ++i) s += partial[i];
+  *out = (float)s;
+}
+
+// Adam on a flat FP32 vector; the step counter is read from device memory
+// and advanced by k_step_bump after the update.
+__global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, int64_t n, const int* __restrict__ step, float lr,
+                       float b1, float b2, float eps) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int t = *step + 1;
+  const float c1 = 1.f - powf(b1, (float)t), c2 = 1.f - powf(b2, (float)t);
+  const float gi = g[i];
+  const float mi = fmaf(b1, m[i], (1.f - b1) * gi);
+  const float vi = fmaf(b2, v[i], (1.f - b2) * gi * gi);
+  m[i] = mi;
+  v[i] = vi;
+  p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+__global__ void k_step_bump(int* step) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *step += 1;
+}
+
+// ---------------------------------------------------------------------------
+// Top-k (largest scores, ties to the lower index) by radix selection on the
+// order-preserving 32-bit image of the scores (NaN ranks lowest), then an
+// index-ordered compaction.  State in device memory:
+//   sel[0] = key prefix found so far, sel[1] = still needed from the prefix,
+//   sel[2] = number strictly above the final key.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t order_key(float x) {
+  if (x != x) return 0u;
+  const uint32_t u = __float_as_uint(x);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+__global__ __launch_bounds__(256) void k_radix_hist(const float* __restrict__ s, int n,
+                                                    const uint32_t* __restrict__ sel, int shift,
+                                                    uint32_t* __restrict__ hist) {
+  __shared__ uint32_t h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const uint32_t prefix = sel[0];
+  const uint32_t pmask = shift >= 24 ? 0u : (0xFFFFFFFFu << (shift + 8));
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t k = order_key(s[i]);
+    if ((k & pmask) == (prefix & pmask)) atomicAdd(&h[(k >> shift) & 0xFFu], 1u);
+  }
+  __syncthreads();
+  if (h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
+}
+
+// One thread: walk the 256 bins from the top, fix this digit of the k-th
+// largest key, clear the histogram for the next pass.
+__global__ void k_radix_pick(uint32_t* __restrict__ hist, uint32_t* __restrict__ sel, int shift) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  uint32_t need = sel[1];
+  uint32_t above = 0;
+  int b = 255;
+  for (; b > 0; --b) {
+    if (above + hist[b] >= need) break;
+    above += hist[b];
+  }
+  sel[0] |= (uint32_t)b << shift;
+  sel[1] = need - above;
+  sel[2] += above;
+  for (int i = 0; i < 256; ++i) hist[i] = 0;
+}
+
+// Per-block counts of selected elements (key > K, or key == K).
+__global__ __launch_bounds__(256) void k_select_count(const float* __restrict__ s, int n,
+                                                      const uint32_t* __restrict__ sel,
+                                                      int* __restrict__ cnt_gt,
+                                                      int* __restrict__ cnt_eq) {
+  __shared__ int red[2][4];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t K = sel[0];
+  int gt = 0, eq = 0;
+  if (i < n) {
+    const uint32_t k = order_key(s[i]);
+    gt = k > K;
+    eq = k == K;
+  }
+  const int g = __popcll(__ballot(gt)), e = __popcll(__ballot(eq));
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+    red[0][threadIdx.x / kWave] = g;
+    red[1][threadIdx.x / kWave] = e;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    cnt_gt[blockIdx.x] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+    cnt_eq[blockIdx.x] = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+  }
+}
+
+// One thread: exclusive scans of the block counts; equal keys are admitted
+// in index order up to the number still needed.
+__global__ void k_select_scan(int* __restrict__ cnt_gt, int* __restrict__ cnt_eq, int nblk,
+                              const uint32_t* __restrict__ sel) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  int need_eq = (int)sel[1];
+  int pos = 0;
+  for (int b = 0; b < nblk; ++b) {
+    const int g = cnt_gt[b], e = cnt_eq[b];
+    const int take = e < need_eq ? e : need_eq;
+    need_eq -= take;
+    cnt_gt[b] = pos;   // output offset of the block
+    cnt_eq[b] = take;  // equal keys the block may emit
+    pos += g + take;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_select_write(const float* __restrict__ s, int n,
+                                                      const uint32_t* __restrict__ sel,
+                                                      const int* __restrict__ offs,
+                                                      const int* __restrict__ take_eq,
+                                                      int* __restrict__ out) {
+  __shared__ int wgt[4], weq[4];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t K = sel[0];
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  int gt = 0, eq = 0;
+  if (i < n) {
+    const uint32_t k = order_key(s[i]);
+    gt = k > K;
+    eq = k == K;
+  }
+  const uint64_t bg = __ballot(gt), be = __ballot(eq);
+  const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+  if (lane == 0) {
+    wgt[wave] = __popcll(bg);
+    weq[wave] = __popcll(be);
+  }
+  __syncthreads();
+  int og = 0, oe = 0;
+  for (int w = 0; w < wave; ++w) {
+    og += wgt[w];
+    oe += weq[w];
+  }
+  const int eq_rank = oe + __popcll(be & below);
+  const int gt_rank = og + __popcll(bg & below);
+  // the block's output: gt and admitted eq elements interleaved in index order
+  const int admitted_before = eq_rank < take_eq[blockIdx.x] ? eq_rank : take_eq[blockIdx.x];
+  if (gt || (eq && eq_rank < take_eq[blockIdx.x])) out[offs[blockIdx.x] + gt_rank + admitted_before] = (int)i;
+}
+
+// ---------------------------------------------------------------------------
+// Launchers.
+// ---------------------------------------------------------------------------
+hipError_t launch_features(const Prepared& M, const int* off, const float* alpha, int n_mols,
+                           float* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_features, dim3((unsigned)n_mols), dim3(kWave), 0, st, M, off, alpha,
+                     n_mols, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_pair_features(const float* fq, const float* flib, const int* qidx,
+                                const int* idx, int n, const float* fo_cross, const float* mean,
+                                const float* inv_std, float* out, hipStream_t st) {
+  const int64_t tot = (int64_t)n * 96;
+  hipLaunchKernelGGL(k_pair_features, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, fq,
+                     flib, qidx, idx, n, fo_cross, mean, inv_std, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_fo_cross(const Prepared& Q, const int* offQ, const float* alphaQ,
+                           const Prepared& L, const int* offL, const float* alphaL,
+                           const int* pairs, int n_pairs, int n_lib, float* out,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(k_fo_cross, dim3((unsigned)n_pairs), dim3(kWave), 0, st, Q, offQ, alphaQ,
+                     L, offL, alphaL, pairs, n_pairs, n_lib, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm(const GemmArgs& g, hipStream_t st) {
+  const dim3 grid((unsigned)((g.N + 63) / 64), (unsigned)((g.M + 63) / 64));
+  if (g.flags & SHAPE_GEMM_BF16)
+    hipLaunchKernelGGL(k_gemm<true>, grid, dim3(256), 0, st, g);
+  else
+    hipLaunchKernelGGL(k_gemm<false>, grid, dim3(256), 0, st, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_colsum(const float* A, int M, int N, int64_t lda, float* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_colsum, dim3((N + 255) / 256), dim3(256), 0, st, A, M, N, lda, out);
+  return hipGetLastError();
+}
+
+int mse_blocks(int B, int N) { return (int)(((int64_t)B * N + 255) / 256); }
+
+hipError_t launch_mse(const float* y, const float* t, const float* w, int B, int N, float* grad,
+                      double* partial, float* loss, hipStream_t st) {
+  const int nb = mse_blocks(B, N);
+  hipLaunchKernelGGL(k_mse, dim3(nb), dim3(256), 0, st, y, t, w, B, N, grad, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1), 0, st, partial, nb, loss);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, int* step,
+                       float lr, float b1, float b2, float eps, hipStream_t st) {
+  hipLaunchKernelGGL(k_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, g, m, v, n,
+                     step, lr, b1, b2, eps);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_step_bump, dim3(1), dim3(1), 0, st, step);
+  return hipGetLastError();
+}
+
+int topk_blocks(int n) { return (n + 255) / 256; }
+
+hipError_t launch_topk(const float* s, int n, int k, uint32_t* sel, uint32_t* hist, int* cnt_gt,
+                       int* cnt_eq, int* out, hipStream_t st) {
+  // sel = {prefix 0, need k, above 0}; histogram cleared
+  hipError_t e;
+  if ((e = launch_fill_int(reinterpret_cast<int*>(hist), 256, 0, st)) != hipSuccess) return e;
+  if ((e = launch_fill_int(reinterpret_cast<int*>(sel), 1, 0, st)) != hipSuccess) return e;
+  if ((e = launch_fill_int(reinterpret_cast<int*>(sel + 1), 1, k, st)) != hipSuccess) return e;
+  if ((e = launch_fill_int(reinterpret_cast<int*>(sel + 2), 1, 0, st)) != hipSuccess) return e;
+  const int blocks = n < 256 * 1024 ? topk_blocks(n) : 1024;
+  for (int shift = 24; shift >= 0; shift -= 8) {
+    hipLaunchKernelGGL(k_radix_hist, dim3(blocks), dim3(256), 0, st, s, n, sel, shift, hist);
+    hipLaunchKernelGGL(k_radix_pick, dim3(1), dim3(1), 0, st, hist, sel, shift);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  const int nb = topk_blocks(n);
+  hipLaunchKernelGGL(k_select_count, dim3(nb), dim3(256), 0, st, s, n, sel, cnt_gt, cnt_eq);
+  hipLaunchKernelGGL(k_select_scan, dim3(1), dim3(1), 0, st, cnt_gt, cnt_eq, nb, sel);
+  hipLaunchKernelGGL(k_select_write, dim3(nb), dim3(256), 0, st, s, n, sel, cnt_gt, cnt_eq, out);
+  return hipGetLastError();
+}
+
+}  // namespace shape

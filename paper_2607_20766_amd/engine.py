@@ -56,7 +56,8 @@ class ShapeResult(ctypes.Structure):
 class ShapeScreenParams(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("n_per_side", ctypes.c_int32),
                 ("round_per_pair", ctypes.c_int32), ("cap_per_pair", ctypes.c_int32),
-                ("tau", ctypes.c_double), ("seed", ctypes.c_uint64)]
+                ("tau", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("n_start", ctypes.c_void_p)]
 
 
 class ShapeScreenOut(ctypes.Structure):
@@ -98,6 +99,17 @@ def load_library():
                                       ctypes.c_float, ctypes.c_float, ctypes.c_float, vp]
         L.shape_align.argtypes = [vp, ctypes.POINTER(ShapeMols), ctypes.POINTER(ShapeMols), i32,
                                   vp, i32, i32, ctypes.c_float, u64, vp, vp, vp]
+        L.shape_features.argtypes = [vp, ctypes.POINTER(ShapeMols), vp, vp]
+        L.shape_pair_features.argtypes = [vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp]
+        L.shape_fo_overlap.argtypes = [vp, ctypes.POINTER(ShapeMols), ctypes.POINTER(ShapeMols),
+                                       vp, i32, vp, vp]
+        L.shape_gemm.argtypes = [vp, i32, i32, i32, vp, i64, i64, vp, i64, i64, vp, i64, vp, vp,
+                                 i64, ctypes.c_uint32, vp]
+        L.shape_colsum.argtypes = [vp, i32, i32, vp, i64, vp, vp]
+        L.shape_mse.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp, vp]
+        L.shape_adam.argtypes = [vp, vp, vp, vp, vp, i64, vp, ctypes.c_float, ctypes.c_float,
+                                 ctypes.c_float, ctypes.c_float, vp]
+        L.shape_topk.argtypes = [vp, vp, i32, i32, vp, vp]
         L.shape_timing_enable.argtypes = [vp, ctypes.c_int]
         L.shape_timing_read.argtypes = [vp, ctypes.POINTER(d), ctypes.POINTER(i64), ctypes.c_int]
         _lib = L
@@ -206,7 +218,8 @@ class Engine:
                      n_per_side: int = 4096, round_per_pair: int = 512,
                      cap_per_pair: int = 65536, tau: float = 0.005, seed: int = 0,
                      pairs: torch.Tensor | None = None, n_pairs: int | None = None,
-                     out: dict | None = None, stream=None) -> dict:
+                     n_start: torch.Tensor | None = None, out: dict | None = None,
+                     stream=None) -> dict:
         """Screen the query against library molecules; returns device tensors
         T, se_T, O_ab, O_aa, O_bb (float32) and n_used (int32) per pair."""
         if pairs is not None:
@@ -219,7 +232,10 @@ class Engine:
             out = {k: torch.empty(n, dtype=torch.float32, device=dev)
                    for k in ("T", "se_T", "O_ab", "O_aa", "O_bb")}
             out["n_used"] = torch.empty(n, dtype=torch.int32, device=dev)
-        prm = ShapeScreenParams(mode, n_per_side, round_per_pair, cap_per_pair, tau, seed)
+        if n_start is not None:
+            n_start = n_start.to(torch.int32).contiguous()
+        prm = ShapeScreenParams(mode, n_per_side, round_per_pair, cap_per_pair, tau, seed,
+                                None if n_start is None else n_start.data_ptr())
         o = ShapeScreenOut(*(out[k].data_ptr() if out.get(k) is not None else None
                              for k in ("T", "se_T", "O_ab", "O_aa", "O_bb", "n_used")))
         q, l_ = query.c_struct(), lib.c_struct()
@@ -272,6 +288,73 @@ class Engine:
             self._ctx, ctypes.byref(a), ctypes.byref(b), starts, _ptr(pose), int(n_samples),
             int(n_steps), float(lr), int(seed), _stream(stream), _ptr(T), _ptr(best)))
         return T, best
+
+    # -- learned triage ----------------------------------------------------------
+    def shape_features(self, M: Molecules, stream=None) -> torch.Tensor:
+        out = torch.empty(M.n_mols, 24, dtype=torch.float32, device=self.torch_device)
+        m = M.c_struct()
+        self._check(load_library().shape_features(self._ctx, ctypes.byref(m), _stream(stream),
+                                                  _ptr(out)))
+        return out
+
+    def shape_fo_overlap(self, query: Molecules, lib: Molecules, pairs=None, n_pairs=None,
+                         out=None, stream=None) -> torch.Tensor:
+        if pairs is not None:
+            pairs = pairs.to(torch.int32).contiguous()
+            n = pairs.numel()
+        else:
+            n = lib.n_mols if n_pairs is None else int(n_pairs)
+        if out is None:
+            out = torch.empty(n, dtype=torch.float32, device=self.torch_device)
+        q, l_ = query.c_struct(), lib.c_struct()
+        self._check(load_library().shape_fo_overlap(self._ctx, ctypes.byref(q), ctypes.byref(l_),
+                                                    _ptr(pairs), n, _stream(stream), _ptr(out)))
+        return out
+
+    def shape_pair_features(self, f_q, f_lib, mean, inv_std, idx=None, qidx=None, n=None,
+                            fo_cross=None, out=None, stream=None) -> torch.Tensor:
+        if idx is not None:
+            idx = idx.to(torch.int32).contiguous()
+            n = idx.numel()
+        elif n is None:
+            n = f_lib.shape[0]
+        if qidx is not None:
+            qidx = qidx.to(torch.int32).contiguous()
+        if out is None:
+            out = torch.empty(n, 96, dtype=torch.float32, device=self.torch_device)
+        self._check(load_library().shape_pair_features(
+            self._ctx, _ptr(f_q.contiguous()), _ptr(f_lib.contiguous()), _ptr(qidx), _ptr(idx),
+            int(n), _ptr(fo_cross), _ptr(mean), _ptr(inv_std), _stream(stream), _ptr(out)))
+        return out
+
+    def shape_gemm(self, M, N, K, A, sam, sak, B, sbk, sbn, C, scm, bias=None, gate=None, sgm=0,
+                   bf16=True, relu=False, stream=None):
+        flags = (1 if bf16 else 0) | (2 if relu else 0)
+        self._check(load_library().shape_gemm(
+            self._ctx, int(M), int(N), int(K), _ptr(A), int(sam), int(sak), _ptr(B), int(sbk),
+            int(sbn), _ptr(C), int(scm), _ptr(bias), _ptr(gate), int(sgm), flags,
+            _stream(stream)))
+
+    def shape_colsum(self, A, M, N, lda, out, stream=None):
+        self._check(load_library().shape_colsum(self._ctx, int(M), int(N), _ptr(A), int(lda),
+                                                _ptr(out), _stream(stream)))
+
+    def shape_mse(self, y, t, w, grad, loss, stream=None):
+        B, N = y.shape
+        self._check(load_library().shape_mse(self._ctx, int(B), int(N), _ptr(y), _ptr(t),
+                                             _ptr(w), _stream(stream), _ptr(grad), _ptr(loss)))
+
+    def shape_adam(self, p, g, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        self._check(load_library().shape_adam(self._ctx, _ptr(p), _ptr(g), _ptr(m), _ptr(v),
+                                               p.numel(), _ptr(step), float(lr), float(beta1),
+                                               float(beta2), float(eps), _stream(stream)))
+
+    def shape_topk(self, score, k, out=None, stream=None) -> torch.Tensor:
+        if out is None:
+            out = torch.empty(int(k), dtype=torch.int32, device=self.torch_device)
+        self._check(load_library().shape_topk(self._ctx, _ptr(score.contiguous()),
+                                              score.numel(), int(k), _stream(stream), _ptr(out)))
+        return out
 
     def shape_timing_enable(self, enable: bool = True):
         self._check(load_library().shape_timing_enable(self._ctx, int(enable)))

@@ -1,0 +1,288 @@
+"""Learned triage for confidence-bounded screening.
+
+A small MLP (96 -> 256 -> 256 -> 256 -> 2, ReLU, BF16 operands with FP32
+accumulation on the matrix cores) predicts, from cheap pair features, the
+shape Tanimoto of a (query, library) pair and the per-sample scale of its
+standard error, log(SE(T) sqrt(n)).  Trained on labels produced by the IS
+screening kernel itself, it ranks a library so that confidence-bounded IS
+refines only the head of the ranking, with per-pair sample budgets seeded
+from the predicted scale (n = (sigma / tau)^2).  IS is both the fallback and
+the judge: every reported Tanimoto comes from IS.
+
+Every arithmetic step runs in the HIP library (features, pair features,
+dense layers, loss, Adam, top-k, IS); this module orders the calls.  Small
+host-side steps are bookkeeping on at most a few MB (feature statistics from
+a subsample, label transforms, budget rounding).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import torch
+
+from .engine import SHAPE_SCREEN_ADAPTIVE, Engine, Molecules
+
+WIDTH = (96, 256, 256, 256, 2)
+
+
+def n_params(width=WIDTH) -> int:
+    return sum(width[i] * width[i + 1] + width[i + 1] for i in range(len(width) - 1))
+
+
+def init_params(seed: int, width=WIDTH) -> np.ndarray:
+    """He-uniform weights, zero biases, packed W_0, b_0, W_1, b_1, ... with
+    W_l row-major [in][out] (random numbers drawn on the host and passed in)."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([int(seed), 0x31C])))
+    parts = []
+    for i in range(len(width) - 1):
+        bound = math.sqrt(6.0 / width[i])
+        parts.append(rng.uniform(-bound, bound, size=width[i] * width[i + 1]))
+        parts.append(np.zeros(width[i + 1]))
+    return np.concatenate(parts).astype(np.float32)
+
+
+class MLP:
+    """Dense ReLU network whose forward, backward, loss and Adam run in the
+    library's kernels (shape_gemm, shape_colsum, shape_mse, shape_adam)."""
+
+    def __init__(self, eng: Engine, params: np.ndarray, width=WIDTH, bf16: bool = True):
+        self.eng = eng
+        self.width = tuple(width)
+        self.bf16 = bf16
+        dev = eng.torch_device
+        self.params = torch.from_numpy(np.ascontiguousarray(params, np.float32)).to(dev)
+        assert self.params.numel() == n_params(width)
+        self.grad = torch.zeros_like(self.params)
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.step = torch.zeros(1, dtype=torch.int32, device=dev)
+        self._acts = {}
+
+    def _views(self, flat):
+        out, off = [], 0
+        for i in range(len(self.width) - 1):
+            n_in, n_out = self.width[i], self.width[i + 1]
+            W = flat[off:off + n_in * n_out]
+            off += n_in * n_out
+            b = flat[off:off + n_out]
+            off += n_out
+            out.append((W, b))
+        return out
+
+    def _buffers(self, B):
+        if B not in self._acts:
+            dev = self.eng.torch_device
+            self._acts[B] = {
+                "h": [torch.empty(B, w, dtype=torch.float32, device=dev) for w in self.width[1:]],
+                "d": [torch.empty(B, w, dtype=torch.float32, device=dev) for w in self.width[1:]],
+                "loss": torch.empty(1, dtype=torch.float32, device=dev),
+            }
+        return self._acts[B]
+
+    def forward(self, x: torch.Tensor) -> torch.Tensor:
+        """x: [B, width[0]] float32 on the device -> [B, width[-1]]."""
+        B = x.shape[0]
+        buf = self._buffers(B)
+        h = x
+        L = len(self.width) - 1
+        for l, (W, b) in enumerate(self._views(self.params)):
+            n_in, n_out = self.width[l], self.width[l + 1]
+            out = buf["h"][l]
+            self.eng.shape_gemm(B, n_out, n_in, h, n_in, 1, W, n_out, 1, out, n_out, bias=b,
+                                bf16=self.bf16, relu=(l + 1 < L))
+            h = out
+        return h
+
+    def backward(self, x: torch.Tensor, dout: torch.Tensor):
+        """Gradient of the loss w.r.t. the parameters into self.grad, given
+        d loss / d output (the activations of the last forward are reused)."""
+        B = x.shape[0]
+        buf = self._buffers(B)
+        L = len(self.width) - 1
+        Ws = self._views(self.params)
+        Gs = self._views(self.grad)
+        dz = dout
+        for l in range(L - 1, -1, -1):
+            n_in, n_out = self.width[l], self.width[l + 1]
+            h_in = x if l == 0 else buf["h"][l - 1]
+            gW, gb = Gs[l]
+            # dW[i][o] = sum_b h_in[b][i] dz[b][o]
+            self.eng.shape_gemm(n_in, n_out, B, h_in, 1, n_in, dz, n_out, 1, gW, n_out,
+                                bf16=self.bf16)
+            self.eng.shape_colsum(dz, B, n_out, n_out, gb)
+            if l > 0:
+                # dh[b][i] = sum_o dz[b][o] W[i][o], through the ReLU of layer l-1
+                W, _ = Ws[l]
+                dnext = buf["d"][l - 1]
+                self.eng.shape_gemm(B, n_in, n_out, dz, n_out, 1, W, 1, n_out, dnext, n_in,
+                                    gate=buf["h"][l - 1], sgm=n_in, bf16=self.bf16)
+                dz = dnext
+
+    def loss_grad(self, x, target, loss_weights):
+        """Forward, weighted MSE and backward; returns the loss tensor [1]."""
+        y = self.forward(x)
+        buf = self._buffers(x.shape[0])
+        dout = buf["d"][-1]
+        self.eng.shape_mse(y, target, loss_weights, dout, buf["loss"])
+        self.backward(x, dout)
+        return buf["loss"]
+
+    def adam_step(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+        self.eng.shape_adam(self.params, self.grad, self.m, self.v, self.step, lr, beta1, beta2,
+                            eps)
+
+    def predict(self, x: torch.Tensor, chunk: int = 65536) -> torch.Tensor:
+        out = torch.empty(x.shape[0], self.width[-1], dtype=torch.float32,
+                          device=self.eng.torch_device)
+        for s in range(0, x.shape[0], chunk):
+            e = min(s + chunk, x.shape[0])
+            out[s:e].copy_(self.forward(x[s:e]))
+        return out
+
+
+class Triage:
+    """Surrogate-seeded confidence-bounded screening.
+
+    Training data are (query, library molecule) pairs given by index arrays
+    into per-molecule feature tables; minibatches are assembled on the device
+    by shape_pair_features.  Labels (host arrays) come from adaptive IS.
+    """
+
+    def __init__(self, eng: Engine, seed: int = 0, bf16: bool = True, tau: float = 0.005,
+                 round_per_pair: int = 512, cap_per_pair: int = 65536, use_fo: bool = True):
+        self.eng = eng
+        # use the pair's analytic first-order overlap (Eq. fo) in two feature slots
+        self.use_fo = use_fo
+        self.mlp = MLP(eng, init_params(seed), bf16=bf16)
+        dev = eng.torch_device
+        self.mean = torch.zeros(96, dtype=torch.float32, device=dev)
+        self.inv_std = torch.ones(96, dtype=torch.float32, device=dev)
+        self.y_mean = np.zeros(2)
+        self.y_std = np.ones(2)
+        self.tau = tau
+        self.round_per_pair = round_per_pair
+        self.cap_per_pair = cap_per_pair
+
+    # -- labels and features -----------------------------------------------------
+    def labels(self, query: Molecules, lib: Molecules, seed: int = 0):
+        """IS labels of one query against the library: T and
+        log(SE(T) sqrt(n_used)) (the per-sample scale) from adaptive screening."""
+        out = self.eng.shape_screen(query, lib, mode=SHAPE_SCREEN_ADAPTIVE,
+                                    round_per_pair=self.round_per_pair,
+                                    cap_per_pair=self.cap_per_pair, tau=self.tau, seed=seed)
+        T = out["T"].cpu().numpy().astype(np.float64)
+        se = out["se_T"].cpu().numpy().astype(np.float64)
+        n = out["n_used"].cpu().numpy().astype(np.float64)
+        return T, np.log(se * np.sqrt(n)), n
+
+    def fo_overlap(self, query: Molecules, lib: Molecules):
+        """First-order cross-overlaps of the query with every library molecule
+        (device) when the model uses them, else None."""
+        return self.eng.shape_fo_overlap(query, lib) if self.use_fo else None
+
+    def fit_standardisation(self, f_q, f_lib, qidx: np.ndarray, midx: np.ndarray,
+                            fo: np.ndarray | None = None, n_sample: int = 65536, seed: int = 0):
+        """Mean and standard deviation of the 96 raw pair features over a
+        random subsample of the training pairs."""
+        dev = self.eng.torch_device
+        rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([int(seed), 0x57D])))
+        sel = rng.choice(qidx.size, size=min(n_sample, qidx.size), replace=False)
+        zero = torch.zeros(96, dtype=torch.float32, device=dev)
+        one = torch.ones(96, dtype=torch.float32, device=dev)
+        fo_sel = None
+        if self.use_fo:
+            fo_sel = torch.from_numpy(np.ascontiguousarray(fo[sel], np.float32)).to(dev)
+        raw = self.eng.shape_pair_features(
+            f_q, f_lib, zero, one, idx=torch.from_numpy(midx[sel].astype(np.int32)).to(dev),
+            qidx=torch.from_numpy(qidx[sel].astype(np.int32)).to(dev),
+            fo_cross=fo_sel).cpu().numpy()
+        mu = raw.astype(np.float64).mean(0)
+        sd = raw.astype(np.float64).std(0)
+        sd[sd < 1e-6] = 1.0
+        self.mean.copy_(torch.from_numpy(mu.astype(np.float32)))
+        self.inv_std.copy_(torch.from_numpy((1.0 / sd).astype(np.float32)))
+
+    # -- training --------------------------------------------------------------------
+    def train(self, f_q, f_lib, qidx: np.ndarray, midx: np.ndarray, Y: np.ndarray,
+              fo: np.ndarray | None = None, epochs: int = 8, batch: int = 4096,
+              lr: float = 1e-3, seed: int = 0, log=None):
+        """Minibatch Adam on the weighted MSE of standardised labels Y [n, 2]."""
+        dev = self.eng.torch_device
+        self.y_mean = Y.mean(0)
+        self.y_std = Y.std(0)
+        Ys = ((Y - self.y_mean) / self.y_std).astype(np.float32)
+        lw = torch.ones(2, dtype=torch.float32, device=dev)
+        n = qidx.size
+        nb = n // batch
+        rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([int(seed), 0x7EA])))
+        xb = torch.empty(batch, 96, dtype=torch.float32, device=dev)
+        losses = torch.empty(max(nb, 1), dtype=torch.float32, device=dev)
+        history = []
+        for ep in range(epochs):
+            perm = rng.permutation(n)[: nb * batch]
+            q_ep = torch.from_numpy(qidx[perm].astype(np.int32)).to(dev)
+            m_ep = torch.from_numpy(midx[perm].astype(np.int32)).to(dev)
+            y_ep = torch.from_numpy(np.ascontiguousarray(Ys[perm])).to(dev)
+            fo_ep = (torch.from_numpy(np.ascontiguousarray(fo[perm], np.float32)).to(dev)
+                     if self.use_fo else None)
+            for b in range(nb):
+                s, e = b * batch, (b + 1) * batch
+                self.eng.shape_pair_features(f_q, f_lib, self.mean, self.inv_std,
+                                             idx=m_ep[s:e], qidx=q_ep[s:e], out=xb,
+                                             fo_cross=None if fo_ep is None else fo_ep[s:e])
+                loss = self.mlp.loss_grad(xb, y_ep[s:e], lw)
+                self.mlp.adam_step(lr)
+                losses[b:b + 1].copy_(loss)
+            history.append(float(losses.cpu().numpy().mean()))
+            if log:
+                log(f"epoch {ep}: loss {history[-1]:.4f}")
+        return history
+
+    def predict_raw(self, f_q, f_lib, fo=None, chunk: int = 65536):
+        """Standardised network outputs [n, 2] on the device for the query
+        against every library row (fo: first-order cross-overlaps, device)."""
+        dev = self.eng.torch_device
+        n = f_lib.shape[0]
+        out = torch.empty(n, 2, dtype=torch.float32, device=dev)
+        xb = torch.empty(min(chunk, n), 96, dtype=torch.float32, device=dev)
+        for s in range(0, n, chunk):
+            e = min(s + chunk, n)
+            x = xb[: e - s]
+            self.eng.shape_pair_features(f_q, f_lib[s:e], self.mean, self.inv_std, out=x,
+                                         n=e - s, fo_cross=None if fo is None else fo[s:e])
+            out[s:e].copy_(self.mlp.forward(x))
+        return out
+
+    def to_labels(self, raw: np.ndarray):
+        """(predicted T, predicted log SE scale) from standardised outputs."""
+        y = raw.astype(np.float64) * self.y_std + self.y_mean
+        return y[:, 0], y[:, 1]
+
+    # -- screening ---------------------------------------------------------------
+    def seed_budget(self, log_scale: np.ndarray) -> np.ndarray:
+        """n = (sigma / tau)^2 samples per pair, in whole rounds within
+        [round, cap]."""
+        n = np.exp(2.0 * log_scale) / self.tau ** 2
+        n = np.ceil(n / self.round_per_pair) * self.round_per_pair
+        return np.clip(n, self.round_per_pair, self.cap_per_pair).astype(np.int32)
+
+    def screen(self, query: Molecules, lib: Molecules, f_q, f_lib, frac: float = 0.05,
+               seed: int = 0):
+        """Rank the library by predicted T, refine the top `frac` by adaptive
+        IS with budgets seeded from the predicted SE scale.  Returns
+        (refined library indices [k] (device, increasing), IS outputs, raw
+        network outputs [n, 2])."""
+        n = lib.n_mols
+        k = max(1, int(round(frac * n)))
+        raw = self.predict_raw(f_q, f_lib, self.fo_overlap(query, lib))
+        score = torch.empty(n, dtype=torch.float32, device=raw.device)
+        score.copy_(raw[:, 0])
+        top = self.eng.shape_topk(score, k)
+        sel_raw = torch.index_select(raw, 0, top.long()).cpu().numpy()
+        budget = torch.from_numpy(self.seed_budget(self.to_labels(sel_raw)[1])).to(raw.device)
+        out = self.eng.shape_screen(query, lib, mode=SHAPE_SCREEN_ADAPTIVE, pairs=top,
+                                    round_per_pair=self.round_per_pair,
+                                    cap_per_pair=self.cap_per_pair, tau=self.tau, seed=seed,
+                                    n_start=budget)
+        return top, out, raw

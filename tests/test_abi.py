@@ -42,7 +42,7 @@ def test_struct_layouts_match_header():
     # shape_mols: 2 int32 + int64 + 4 pointers
     assert ctypes.sizeof(engine.ShapeMols) == 8 + 8 + 4 * 8
     assert ctypes.sizeof(engine.ShapeResult) == 18 * 8 + 2 * 8
-    assert ctypes.sizeof(engine.ShapeScreenParams) == 4 * 4 + 8 + 8
+    assert ctypes.sizeof(engine.ShapeScreenParams) == 4 * 4 + 8 + 8 + 8
     assert ctypes.sizeof(engine.ShapeScreenOut) == 6 * 8
 
 

@@ -169,3 +169,21 @@ def test_odd_atom_counts(eng):
     g = _to_np(eng.shape_screen(Q, lib, n_per_side=512, seed=4))
     r = _oracle_screen(q, L, mode=0, n_fixed=512, seed=4)
     _compare(g, r)
+
+
+def test_adaptive_seeded_budgets(eng, small_lib):
+    """Per-pair budgets defer the first stop test; GPU and oracle agree."""
+    q, L = small_lib
+    rng = np.random.default_rng(8)
+    n_start = (rng.integers(1, 40, L.n_mols) * 512).astype(np.int32)
+    Q = eng.molecules(q, mol_id=[QUERY_ID])
+    lib = eng.molecules(L)
+    g = _to_np(eng.shape_screen(Q, lib, mode=SHAPE_SCREEN_ADAPTIVE, round_per_pair=512,
+                                cap_per_pair=16384, tau=0.005, seed=3,
+                                n_start=torch.from_numpy(n_start).cuda()))
+    r = _oracle_screen(q, L, mode=1, round_per_pair=512, cap_per_pair=16384, tau=0.005,
+                       seed=3, n_start=n_start)
+    assert np.all(g["n_used"] >= np.minimum(n_start, 16384))
+    same = g["n_used"] == r[:, 5]
+    assert same.mean() >= 0.95
+    _compare(g, r[same], idx=np.nonzero(same)[0])
