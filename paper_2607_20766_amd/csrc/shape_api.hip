@@ -28,7 +28,7 @@ enum Slot {
   S_L_ATOM, S_L_SAMP, S_L_Z, S_L_ID, S_L_BAD, S_L_CENTRE,
   S_PARTIALS, S_RESULT, S_QS, S_QF2,
   S_SELF_A, S_SELF_B, S_ADAM_M, S_ADAM_V, S_ADAM_STEP, S_GRAD,
-  S_MSE, S_TOPK_SEL, S_TOPK_HIST, S_TOPK_GT, S_TOPK_EQ,
+  S_MSE, S_TOPK_SEL, S_TOPK_HIST, S_TOPK_GT, S_TOPK_EQ, S_COLSUM,
   S_COUNT
 };
 
@@ -611,7 +611,11 @@ int shape_colsum(shape_ctx* c, int32_t M, int32_t N, const float* A, int64_t lda
   if (!A || !out) return fail(c, SHAPE_E_INVAL, "NULL array");
   int rc = set_device(c);
   if (rc) return rc;
-  HIP_TRY(c, shape::launch_colsum(A, M, N, lda, out, (hipStream_t)stream), "colsum kernel");
+  void* part;
+  if ((rc = ensure(c, S_COLSUM, (size_t)shape::colsum_chunks(M) * N * sizeof(float), &part)))
+    return rc;
+  HIP_TRY(c, shape::launch_colsum(A, M, N, lda, (float*)part, out, (hipStream_t)stream),
+          "colsum kernels");
   return SHAPE_OK;
 }
 

@@ -24,70 +24,92 @@ __global__ void k_alpha_from_radius(const float* __restrict__ R, int64_t n, doub
 }
 
 // ---------------------------------------------------------------------------
-// Molecule preparation, one thread per molecule, FP64: mixture weights
-// v_i = (pi/alpha_i)^(3/2) (= t sqrt t, t = pi/alpha_i), Z = sum v_i in atom
-// order, thresholds floor(2^32 cumsum(v)/Z) for the first N-1 atoms.
+// Molecule preparation, one wave per molecule (four per workgroup), FP64:
+// mixture weights v_i = (pi/alpha_i)^(3/2) (= t sqrt t, t = pi/alpha_i) per
+// lane, then Z = sum v_i and the running sums for the thresholds
+// floor(2^32 cumsum(v)/Z) in atom order by one lane, so both are the plain
+// sequential sums bit for bit; records are written by all lanes.
 // ---------------------------------------------------------------------------
-__global__ void k_prepare(MolsDev in, Prepared out, int* __restrict__ flag) {
+constexpr int kPrepWaves = 4;
+
+__global__ __launch_bounds__(256) void k_prepare(MolsDev in, Prepared out, int* __restrict__ flag) {
   // FP64 without contraction: Z and the thresholds are the values the plain
   // expressions define, bit for bit.
 #pragma clang fp contract(off)
-  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  __shared__ double sv[kPrepWaves][SHAPE_MAX_ATOMS];
+  __shared__ double sZ[kPrepWaves];
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  const int m = blockIdx.x * kPrepWaves + w;
   if (m >= in.n_mols) return;
   const int a0 = in.off[m], a1 = in.off[m + 1];
   const int n = a1 - a0;
-  bool bad = !(a0 >= 0 && (int64_t)a1 <= in.n_atoms && n >= 1 && n <= in.max_atoms);
-  double Z = 0.0;
-  if (!bad) {
-    for (int i = a0; i < a1; ++i) {
-      const double al = (double)in.alpha[i];
-      const float x = in.xyz[3 * i], y = in.xyz[3 * i + 1], z = in.xyz[3 * i + 2];
-      if (!(al > 0.0) || !isfinite(al) || !isfinite(x) || !isfinite(y) || !isfinite(z)) {
-        bad = true;
-        break;
-      }
+  const bool range_bad = !(a0 >= 0 && (int64_t)a1 <= in.n_atoms && n >= 1 && n <= in.max_atoms);
+  bool bad = range_bad;
+  double* v = sv[w];
+  double cx = 0.0, cy = 0.0, cz = 0.0;
+  if (!range_bad) {
+    for (int i = lane; i < n; i += kWave) {
+      const double al = (double)in.alpha[a0 + i];
+      const float x = in.xyz[3 * (a0 + i)], y = in.xyz[3 * (a0 + i) + 1],
+                  z = in.xyz[3 * (a0 + i) + 2];
+      if (!(al > 0.0) || !isfinite(al) || !isfinite(x) || !isfinite(y) || !isfinite(z)) bad = true;
       const double t = M_PI / al;
-      Z += t * sqrt(t);
+      v[i] = t * sqrt(t);
+      cx += (double)x;
+      cy += (double)y;
+      cz += (double)z;
     }
   }
-  out.id[m] = in.id ? in.id[m] : (uint32_t)m;
-  out.bad[m] = bad ? 1 : 0;
+  bad = __ballot(bad) != 0;
+  if (lane == 0) {
+    out.id[m] = in.id ? in.id[m] : (uint32_t)m;
+    out.bad[m] = bad ? 1 : 0;
+  }
   if (bad) {
-    out.Z[m] = __builtin_nan("");
-    out.centre[m] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    atomicOr(flag, 1);
+    if (lane == 0) {
+      out.Z[m] = __builtin_nan("");
+      out.centre[m] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      atomicOr(flag, 1);
+    }
     return;
   }
-  out.Z[m] = Z;
-  double cx = 0.0, cy = 0.0, cz = 0.0;
-  for (int i = a0; i < a1; ++i) {
-    cx += (double)in.xyz[3 * i];
-    cy += (double)in.xyz[3 * i + 1];
-    cz += (double)in.xyz[3 * i + 2];
-  }
-  out.centre[m] = make_float4((float)(cx / n), (float)(cy / n), (float)(cz / n), 0.0f);
-  const double log2e = 1.4426950408889634074;
-  double cum = 0.0;
-  for (int i = a0; i < a1; ++i) {
-    const double al = (double)in.alpha[i];
-    const double t = M_PI / al;
-    cum += t * sqrt(t);
-    Atom a;
-    a.x = in.xyz[3 * i];
-    a.y = in.xyz[3 * i + 1];
-    a.z = in.xyz[3 * i + 2];
-    a.a2 = (float)(al * log2e);
-    out.atom[i] = a;
-    AtomSampling s;
-    s.sd = (float)(1.0 / sqrt(2.0 * al));
-    if (i + 1 < a1) {
-      double f = floor(4294967296.0 * (cum / Z));
-      if (f > 4294967295.0) f = 4294967295.0;
-      s.thr = (uint32_t)f;
-    } else {
-      s.thr = 0xFFFFFFFFu;
+  cx = wave_sum(cx);
+  cy = wave_sum(cy);
+  cz = wave_sum(cz);
+  wave_lds_sync();
+  if (lane == 0) {
+    double Z = 0.0;
+    for (int i = 0; i < n; ++i) Z += v[i];
+    double cum = 0.0;
+    for (int i = 0; i < n; ++i) {
+      cum += v[i];
+      v[i] = cum;  // running sums replace the weights
     }
-    out.samp[i] = s;
+    sZ[w] = Z;
+    out.Z[m] = Z;
+    out.centre[m] = make_float4((float)(cx / n), (float)(cy / n), (float)(cz / n), 0.0f);
+  }
+  wave_lds_sync();
+  const double Z = sZ[w];
+  const double log2e = 1.4426950408889634074;
+  for (int i = lane; i < n; i += kWave) {
+    const double al = (double)in.alpha[a0 + i];
+    Atom a;
+    a.x = in.xyz[3 * (a0 + i)];
+    a.y = in.xyz[3 * (a0 + i) + 1];
+    a.z = in.xyz[3 * (a0 + i) + 2];
+    a.a2 = (float)(al * log2e);
+    out.atom[a0 + i] = a;
+    AtomSampling smp;
+    smp.sd = (float)(1.0 / sqrt(2.0 * al));
+    if (i + 1 < n) {
+      double f = floor(4294967296.0 * (v[i] / Z));
+      if (f > 4294967295.0) f = 4294967295.0;
+      smp.thr = (uint32_t)f;
+    } else {
+      smp.thr = 0xFFFFFFFFu;
+    }
+    out.samp[a0 + i] = smp;
   }
 }
 
@@ -499,7 +521,7 @@ hipError_t launch_alpha_from_radius(const float* R, int64_t n, double kappa, dou
 }
 
 hipError_t launch_prepare(const MolsDev& in, const Prepared& out, int* flag, hipStream_t st) {
-  const int blocks = (in.n_mols + 255) / 256;
+  const int blocks = (in.n_mols + kPrepWaves - 1) / kPrepWaves;
   hipLaunchKernelGGL(k_prepare, dim3(blocks), dim3(256), 0, st, in, out, flag);
   return hipGetLastError();
 }

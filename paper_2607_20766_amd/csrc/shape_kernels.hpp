@@ -102,7 +102,9 @@ hipError_t launch_fo_cross(const Prepared& Q, const int* offQ, const float* alph
                            const Prepared& L, const int* offL, const float* alphaL,
                            const int* pairs, int n_pairs, int n_lib, float* out, hipStream_t st);
 hipError_t launch_gemm(const GemmArgs& g, hipStream_t st);
-hipError_t launch_colsum(const float* A, int M, int N, int64_t lda, float* out, hipStream_t st);
+int colsum_chunks(int M);
+hipError_t launch_colsum(const float* A, int M, int N, int64_t lda, float* part, float* out,
+                         hipStream_t st);
 int mse_blocks(int B, int N);
 hipError_t launch_mse(const float* y, const float* t, const float* w, int B, int N, float* grad,
                       double* partial, float* loss, hipStream_t st);

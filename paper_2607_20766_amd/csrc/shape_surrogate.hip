@@ -16,34 +16,33 @@ namespace shape {
 //            [0.893, 0.995), >= 0.995
 //   [23]     first-order self-overlap sum_ij (pi/(a_i+a_j))^(3/2)
 //            exp(-a_i a_j/(a_i+a_j) |c_i-c_j|^2)
-// Moments in FP64; the O(N^2) overlap sum in FP32 per lane, FP64 across lanes.
+// Moments in two passes (mean, then centred second moments); the overlap sum
+// over the i < j triangle is spread over all 64 lanes.
 // ---------------------------------------------------------------------------
-__device__ void sym3_eigen_desc(double a[3][3], double ev[3]) {
-  // cyclic Jacobi rotations
-  for (int sweep = 0; sweep < 50; ++sweep) {
-    const double off = fabs(a[0][1]) + fabs(a[0][2]) + fabs(a[1][2]);
-    if (off < 1e-300) break;
-    for (int p = 0; p < 2; ++p)
-      for (int q = p + 1; q < 3; ++q) {
-        if (a[p][q] == 0.0) continue;
-        const double theta = (a[q][q] - a[p][p]) / (2.0 * a[p][q]);
-        const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-        const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
-        for (int k = 0; k < 3; ++k) {
-          const double akp = a[k][p], akq = a[k][q];
-          a[k][p] = c * akp - s * akq;
-          a[k][q] = s * akp + c * akq;
-        }
-        for (int k = 0; k < 3; ++k) {
-          const double apk = a[p][k], aqk = a[q][k];
-          a[p][k] = c * apk - s * aqk;
-          a[q][k] = s * apk + c * aqk;
-        }
-      }
+
+// Eigenvalues of a symmetric 3 x 3 matrix, descending, by the trigonometric
+// closed form (Smith, CACM 1961).
+__device__ void sym3_eigen_desc(double a00, double a11, double a22, double a01, double a02,
+                                double a12, double ev[3]) {
+  const double p1 = a01 * a01 + a02 * a02 + a12 * a12;
+  const double q = (a00 + a11 + a22) / 3.0;
+  if (p1 <= 1e-300 * (q * q + 1e-300)) {
+    ev[0] = a00; ev[1] = a11; ev[2] = a22;
+  } else {
+    const double b00 = a00 - q, b11 = a11 - q, b22 = a22 - q;
+    const double p2 = b00 * b00 + b11 * b11 + b22 * b22 + 2.0 * p1;
+    const double p = sqrt(p2 / 6.0);
+    const double ip = 1.0 / p;
+    const double c00 = b00 * ip, c11 = b11 * ip, c22 = b22 * ip;
+    const double c01 = a01 * ip, c02 = a02 * ip, c12 = a12 * ip;
+    double r = 0.5 * (c00 * (c11 * c22 - c12 * c12) - c01 * (c01 * c22 - c12 * c02) +
+                      c02 * (c01 * c12 - c11 * c02));
+    r = r < -1.0 ? -1.0 : (r > 1.0 ? 1.0 : r);
+    const double phi = acos(r) / 3.0;
+    ev[0] = q + 2.0 * p * cos(phi);
+    ev[2] = q + 2.0 * p * cos(phi + 2.0943951023931954923);
+    ev[1] = 3.0 * q - ev[0] - ev[2];
   }
-  ev[0] = a[0][0];
-  ev[1] = a[1][1];
-  ev[2] = a[2][2];
   for (int i = 0; i < 3; ++i)
     for (int j = i + 1; j < 3; ++j)
       if (ev[j] > ev[i]) {
@@ -51,6 +50,14 @@ __device__ void sym3_eigen_desc(double a[3][3], double ev[3]) {
         ev[i] = ev[j];
         ev[j] = t;
       }
+}
+
+// (pi / (a + b))^(3/2) exp(-a b / (a + b) d2), with hardware reciprocal,
+// square root and exp2 (a feature, not an estimate: ~1e-6 relative).
+__device__ __forceinline__ float fo_term(float a, float b, float d2) {
+  const float ir = __builtin_amdgcn_rcpf(a + b);
+  const float t = 3.14159265358979f * ir;
+  return t * __builtin_amdgcn_sqrtf(t) * __builtin_amdgcn_exp2f(-1.44269504088896f * a * b * ir * d2);
 }
 
 __global__ __launch_bounds__(64) void k_features(Prepared M, const int* __restrict__ off,
@@ -71,31 +78,32 @@ __global__ __launch_bounds__(64) void k_features(Prepared M, const int* __restri
     sC[i] = make_float4(at.x, at.y, at.z, alpha[a0 + i]);
   }
   __syncthreads();
-  const double Z = M.Z[mol];
-  double mx = 0.0, my = 0.0, mz = 0.0;
-  double sxx = 0.0, syy = 0.0, szz = 0.0, sxy = 0.0, sxz = 0.0, syz = 0.0;
+  const float iZ = (float)(1.0 / M.Z[mol]);
+  // pass 1: mixture mean
+  float mx = 0.f, my = 0.f, mz = 0.f;
   for (int i = lane; i < n; i += kWave) {
     const float4 c = sC[i];
-    const double al = (double)c.w, t = M_PI / al;
-    const double pi = t * sqrt(t) / Z;
-    const double x = c.x, y = c.y, z = c.z, h = 0.5 / al;
-    mx += pi * x; my += pi * y; mz += pi * z;
-    sxx += pi * (x * x + h); syy += pi * (y * y + h); szz += pi * (z * z + h);
-    sxy += pi * x * y; sxz += pi * x * z; syz += pi * y * z;
+    const float t = 3.14159265358979f / c.w;
+    const float pi = t * sqrtf(t) * iZ;
+    mx = fmaf(pi, c.x, mx); my = fmaf(pi, c.y, my); mz = fmaf(pi, c.z, mz);
   }
-  mx = wave_sum(mx); my = wave_sum(my); mz = wave_sum(mz);
-  sxx = wave_sum(sxx); syy = wave_sum(syy); szz = wave_sum(szz);
-  sxy = wave_sum(sxy); sxz = wave_sum(sxz); syz = wave_sum(syz);
-  // radial histogram and width classes by wave ballots (exact integer counts)
+  mx = wave_sumf(mx); my = wave_sumf(my); mz = wave_sumf(mz);
+  // pass 2: centred second moments, radial histogram, width classes
+  float sxx = 0.f, syy = 0.f, szz = 0.f, sxy = 0.f, sxz = 0.f, syz = 0.f;
   int hist_mine = 0, cls_mine = 0;  // lane b < 16 keeps bin b, lane c < 4 class c
   for (int base = 0; base < n; base += kWave) {
     const int i = base + lane;
     int bin = -1, cls = -1;
     if (i < n) {
       const float4 c = sC[i];
-      const double dx = c.x - mx, dy = c.y - my, dz = c.z - mz;
-      const double r = sqrt(dx * dx + dy * dy + dz * dz);
-      bin = (int)floor(r / 0.5);
+      const float t = 3.14159265358979f / c.w;
+      const float pi = t * sqrtf(t) * iZ;
+      const float x = c.x - mx, y = c.y - my, z = c.z - mz, h = 0.5f / c.w;
+      sxx = fmaf(pi, fmaf(x, x, h), sxx); syy = fmaf(pi, fmaf(y, y, h), syy);
+      szz = fmaf(pi, fmaf(z, z, h), szz);
+      sxy = fmaf(pi * x, y, sxy); sxz = fmaf(pi * x, z, sxz); syz = fmaf(pi * y, z, syz);
+      const float r = sqrtf(fmaf(x, x, fmaf(y, y, z * z)));
+      bin = (int)floorf(r * 2.0f);
       bin = bin > 15 ? 15 : bin;
       cls = c.w < 0.767f ? 0 : (c.w < 0.893f ? 1 : (c.w < 0.995f ? 2 : 3));
     }
@@ -108,28 +116,29 @@ __global__ __launch_bounds__(64) void k_features(Prepared M, const int* __restri
       if (lane == b) cls_mine += cnt;
     }
   }
-  // first-order self-overlap: lane i owns rows i, i+64, ...
-  float fo = 0.0f;
-  for (int i = lane; i < n; i += kWave) {
-    const float4 ci = sC[i];
-    for (int j = 0; j < n; ++j) {
-      const float4 cj = sC[j];
-      const float as = ci.w + cj.w;
-      const float dx = ci.x - cj.x, dy = ci.y - cj.y, dz = ci.z - cj.z;
-      const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-      const float t = 3.14159265358979f / as;
-      fo = fmaf(t * sqrtf(t), expf(-(ci.w * cj.w / as) * d2), fo);
-    }
+  sxx = wave_sumf(sxx); syy = wave_sumf(syy); szz = wave_sumf(szz);
+  sxy = wave_sumf(sxy); sxz = wave_sumf(sxz); syz = wave_sumf(syz);
+  // first-order self-overlap: diagonal + 2 x the i < j triangle, flattened
+  float fo = 0.f;
+  for (int i = lane; i < n; i += kWave) fo += fo_term(sC[i].w, sC[i].w, 0.f);
+  const int P = n * (n - 1) / 2;
+  for (int p = lane; p < P; p += kWave) {
+    // row i of the strict upper triangle holding flat index p
+    int i = n - 2 - (int)floorf(sqrtf((float)(-8 * p + 4 * n * (n - 1) - 7)) * 0.5f - 0.5f);
+    i = i < 0 ? 0 : (i > n - 2 ? n - 2 : i);
+    while (i > 0 && i * n - i * (i + 1) / 2 > p) --i;
+    while (i < n - 2 && (i + 1) * n - (i + 1) * (i + 2) / 2 <= p) ++i;
+    const int j = p - (i * n - i * (i + 1) / 2) + i + 1;
+    const float4 ci = sC[i], cj = sC[j];
+    const float dx = ci.x - cj.x, dy = ci.y - cj.y, dz = ci.z - cj.z;
+    fo = fmaf(2.0f, fo_term(ci.w, cj.w, fmaf(dx, dx, fmaf(dy, dy, dz * dz))), fo);
   }
   const double fo_sum = wave_sum((double)fo);
   if (lane < 16) f[lane] = (float)hist_mine;
   if (lane < 4) f[19 + lane] = (float)cls_mine;
   if (lane == 0) {
-    double cov[3][3] = {{sxx - mx * mx, sxy - mx * my, sxz - mx * mz},
-                        {sxy - mx * my, syy - my * my, syz - my * mz},
-                        {sxz - mx * mz, syz - my * mz, szz - mz * mz}};
     double ev[3];
-    sym3_eigen_desc(cov, ev);
+    sym3_eigen_desc(sxx, syy, szz, sxy, sxz, syz, ev);
     for (int k = 0; k < 3; ++k) f[16 + k] = (float)sqrt(ev[k] > 0.0 ? ev[k] : 0.0);
     f[23] = (float)fo_sum;
   }
@@ -166,11 +175,8 @@ __global__ __launch_bounds__(64) void k_fo_cross(Prepared Q, const int* __restri
     const float al = alphaQ[q0 + i];
     for (int j = 0; j < nb; ++j) {
       const float4 cj = sB[j];
-      const float as = al + cj.w;
       const float dx = ai.x - cj.x, dy = ai.y - cj.y, dz = ai.z - cj.z;
-      const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-      const float t = 3.14159265358979f / as;
-      acc = fmaf(t * sqrtf(t), expf(-(al * cj.w / as) * d2), acc);
+      acc += fo_term(al, cj.w, fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
     }
   }
   const double s = wave_sum((double)acc);
@@ -308,14 +314,116 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
       }
 }
 
-// Column sums of A[M][N] (row stride lda), one thread per column, in row
-// order (deterministic).
-__global__ void k_colsum(const float* __restrict__ A, int M, int N, int64_t lda,
-                         float* __restrict__ out) {
+// BF16 dense layer with LDS tiling: workgroup tile 128 x 128, k-slab 32.
+// Both operands are staged as bfloat16 with k contiguous (A_s[m][k],
+// B_s[n][k]), loaded from global memory along whichever dimension is
+// contiguous there, so every wave reads whole cache lines.  Each of the four
+// waves computes a 64 x 64 sub-tile as 4 x 4 MFMA 16x16x16 tiles.
+constexpr int kTM = 128, kTN = 128, kTK = 32, kLdk = kTK + 8;
+
+__global__ __launch_bounds__(256) void k_gemm_bf16_tiled(GemmArgs g) {
+  __shared__ short As[kTM * kLdk];
+  __shared__ short Bs[kTN * kLdk];
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+  const int bm = blockIdx.y * kTM, bn = blockIdx.x * kTN;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  const int li = lane & 15, lk = lane >> 4;
+  v4f acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+  const bool a_kfast = g.sak == 1;
+  const bool b_nfast = g.sbn == 1;
+  for (int k0 = 0; k0 < g.K; k0 += kTK) {
+    // stage A: 128 x 32 elements, 16 per thread
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      int m, k;
+      if (a_kfast) {
+        k = tid & 31;
+        m = (tid >> 5) + 8 * r;
+      } else {
+        m = tid & 127;
+        k = (tid >> 7) + 2 * r;
+      }
+      const int gm = bm + m, gk = k0 + k;
+      const float v = (gm < g.M && gk < g.K) ? g.A[(int64_t)gm * g.sam + (int64_t)gk * g.sak] : 0.f;
+      As[m * kLdk + k] = to_bf16(v);
+    }
+    // stage B: 32 x 128 elements, stored transposed as Bs[n][k]
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      int n, k;
+      if (b_nfast) {
+        n = tid & 127;
+        k = (tid >> 7) + 2 * r;
+      } else {
+        k = tid & 31;
+        n = (tid >> 5) + 8 * r;
+      }
+      const int gn = bn + n, gk = k0 + k;
+      const float v = (gn < g.N && gk < g.K) ? g.B[(int64_t)gk * g.sbk + (int64_t)gn * g.sbn] : 0.f;
+      Bs[n * kLdk + k] = to_bf16(v);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < kTK; kk += 16) {
+      v4s a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        a[i] = *reinterpret_cast<const v4s*>(&As[(wm + 16 * i + li) * kLdk + kk + 4 * lk]);
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        b[j] = *reinterpret_cast<const v4s*>(&Bs[(wn + 16 * j + li) * kLdk + kk + 4 * lk]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = bm + wm + 16 * i + 4 * lk + r;
+        const int n = bn + wn + 16 * j + li;
+        if (m < g.M && n < g.N) {
+          float v = acc[i][j][r];
+          if (g.bias) v += g.bias[n];
+          if (g.flags & SHAPE_GEMM_RELU) v = v > 0.f ? v : 0.f;
+          if (g.gate && !(g.gate[(int64_t)m * g.sgm + n] > 0.f)) v = 0.f;
+          g.C[(int64_t)m * g.scm + n] = v;
+        }
+      }
+}
+
+// Column sums of A[M][N] (row stride lda), deterministic: stage 1 sums
+// chunks of kColRows rows per column (threads along columns, coalesced), stage
+// 2 adds the chunk partials in order.
+constexpr int kColRows = 256;
+
+__global__ void k_colsum_partial(const float* __restrict__ A, int M, int N, int64_t lda,
+                                 float* __restrict__ part) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  const int chunk = blockIdx.y;
+  if (n >= N) return;
+  const int m0 = chunk * kColRows, m1 = min(M, m0 + kColRows);
+  float s = 0.f;
+  for (int m = m0; m < m1; ++m) s += A[(int64_t)m * lda + n];
+  part[(size_t)chunk * N + n] = s;
+}
+
+__global__ void k_colsum_final(const float* __restrict__ part, int chunks, int N,
+                               float* __restrict__ out) {
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= N) return;
   double s = 0.0;
-  for (int m = 0; m < M; ++m) s += A[(int64_t)m * lda + n];
+  for (int c = 0; c < chunks; ++c) s += part[(size_t)c * N + n];
   out[n] = (float)s;
 }
 
@@ -523,16 +631,33 @@ hipError_t launch_fo_cross(const Prepared& Q, const int* offQ, const float* alph
 }
 
 hipError_t launch_gemm(const GemmArgs& g, hipStream_t st) {
-  const dim3 grid((unsigned)((g.N + 63) / 64), (unsigned)((g.M + 63) / 64));
-  if (g.flags & SHAPE_GEMM_BF16)
-    hipLaunchKernelGGL(k_gemm<true>, grid, dim3(256), 0, st, g);
-  else
+  if (g.flags & SHAPE_GEMM_BF16) {
+    // narrow outputs keep the 64 x 64 kernel (a 128-wide tile would idle)
+    if (g.N >= 64) {
+      const dim3 grid((unsigned)((g.N + kTN - 1) / kTN), (unsigned)((g.M + kTM - 1) / kTM));
+      hipLaunchKernelGGL(k_gemm_bf16_tiled, grid, dim3(256), 0, st, g);
+    } else {
+      const dim3 grid((unsigned)((g.N + 63) / 64), (unsigned)((g.M + 63) / 64));
+      hipLaunchKernelGGL(k_gemm<true>, grid, dim3(256), 0, st, g);
+    }
+  } else {
+    const dim3 grid((unsigned)((g.N + 63) / 64), (unsigned)((g.M + 63) / 64));
     hipLaunchKernelGGL(k_gemm<false>, grid, dim3(256), 0, st, g);
+  }
   return hipGetLastError();
 }
 
-hipError_t launch_colsum(const float* A, int M, int N, int64_t lda, float* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_colsum, dim3((N + 255) / 256), dim3(256), 0, st, A, M, N, lda, out);
+int colsum_chunks(int M) { return (M + kColRows - 1) / kColRows; }
+
+hipError_t launch_colsum(const float* A, int M, int N, int64_t lda, float* part, float* out,
+                         hipStream_t st) {
+  const int chunks = colsum_chunks(M);
+  hipLaunchKernelGGL(k_colsum_partial, dim3((N + 255) / 256, chunks), dim3(256), 0, st, A, M, N,
+                     lda, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_colsum_final, dim3((N + 255) / 256), dim3(256), 0, st, part, chunks, N,
+                     out);
   return hipGetLastError();
 }
 
