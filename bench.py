@@ -44,6 +44,9 @@ VALU_PER_EVAL = 9
 EXP_SLOTS = 3
 OPS_PER_EVAL = VALU_PER_EVAL + EXP_SLOTS
 PEAK_LANE_OPS = 157.3e12 / 2
+# Measured HBM traffic of the adaptive screening kernel per launch (counters,
+# scaled by a plain copy); valid for the kernel version it was taken on.
+TRAFFIC_BYTES = 138.8e6 + 19.2e6
 
 
 def log(msg):
@@ -245,6 +248,9 @@ def main():
     ap.add_argument("--no-align", action="store_true", help="skip the alignment workload")
     ap.add_argument("--align-pairs", type=int, default=10000)
     ap.add_argument("--no-triage", action="store_true", help="skip the learned-triage workload")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy 1 GiB device to device three times (a plain copy of known "
+                         "size for scaling the FETCH_SIZE / WRITE_SIZE counters) and exit")
     ap.add_argument("--triage-library", type=int, default=1000000)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -253,6 +259,15 @@ def main():
         sys.exit(2)
 
     import torch
+
+    if args.copy_calibration:
+        a = torch.zeros(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_launch": a.numel() * 4}))
+        return
 
     from paper_2607_20766_amd import molgen
     from paper_2607_20766_amd.engine import (SHAPE_SCREEN_ADAPTIVE, SHAPE_SCREEN_FIXED,
@@ -352,7 +367,10 @@ def main():
             "peak": peak,
             "unit": "TOP/s",
             "frac": achieved / peak,
-            "traffic": None,
+            # HBM bytes per launch from rocprofv3 FETCH_SIZE (x2.0) and
+            # WRITE_SIZE (x1.0) scaled by a 1 GiB copy of known size: 138.8 MB
+            # read + 19.2 MB written (see the traffic summary in profiles/)
+            "traffic": TRAFFIC_BYTES,
             "kernel_ms": kern_ms,
             "atom_evals_per_launch": ev_other + ev_own,
             "ops_per_atom_eval": OPS_PER_EVAL,
