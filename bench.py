@@ -45,8 +45,9 @@ EXP_SLOTS = 3
 OPS_PER_EVAL = VALU_PER_EVAL + EXP_SLOTS
 PEAK_LANE_OPS = 157.3e12 / 2
 # Measured HBM traffic of the adaptive screening kernel per launch (counters,
-# scaled by a plain copy); valid for the kernel version it was taken on.
-TRAFFIC_BYTES = 138.8e6 + 19.2e6
+# scaled by a plain copy); valid for the kernel version it was taken on, None
+# until the current version has been measured.
+TRAFFIC_BYTES = None
 
 
 def log(msg):

@@ -9,6 +9,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "shape_normal_poly.hpp"
+
 namespace shape {
 
 constexpr int kWave = 64;
@@ -30,29 +32,66 @@ struct __align__(8) AtomSampling {
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon et al., SC'11): ten rounds; each round multiplies
 // words 0 and 2 by the two round constants and mixes high halves with the
-// other words and the key; the key advances by the Weyl constants.
+// other words and the key; the key advances by the Weyl constants.  The
+// products are written as 32x32->64-bit multiplies so that each is one
+// v_mad_u64_u32 rather than a v_mul_hi_u32/v_mul_lo_u32 pair.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint2 k) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
-    const uint32_t hi0 = __umulhi(0xD2511F53u, c.x);
-    const uint32_t lo0 = 0xD2511F53u * c.x;
-    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z);
-    const uint32_t lo1 = 0xCD9E8D57u * c.z;
-    c = make_uint4(hi1 ^ c.y ^ k.x, lo1, hi0 ^ c.w ^ k.y, lo0);
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+    c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k.x, (uint32_t)p1,
+                   (uint32_t)(p0 >> 32) ^ c.w ^ k.y, (uint32_t)p0);
     k.x += 0x9E3779B9u;
     k.y += 0xBB67AE85u;
   }
   return c;
 }
 
-// Standard normal from the top 24 bits of a Philox word: u = (b + 1/2) 2^-24,
-// z = Phi^-1(u) = sqrt(2) erfinv(2u - 1).  2u - 1 = (2b + 1 - 2^24) 2^-24 is
-// formed exactly in FP32, so the tails are resolved to the last bit.
+// Standard normal from the top 24 bits b of a Philox word: u = (b + 1/2) 2^-24,
+// z = Phi^-1(u) = sqrt(2) erfinv(x), x = 2u - 1 = b 2^-23 + (2^-24 - 1), which
+// one FP32 fma forms exactly, so the tails are resolved to the last bit.
+// erfinv after Giles (2011): z = x P(L), L = -log2(1 - x^2), with one
+// polynomial in L for L < kSplit and one in sqrt(L) above it (coefficients
+// from gen_normal_poly.py; relative error below 3e-7 over every 24-bit u).
+// The tail branch runs only when some lane of the wave needs it.
 __device__ __forceinline__ float normal_from_bits(uint32_t word) {
-  const int b = (int)(word >> 8);
-  const float v = (float)(2 * b + 1 - (1 << 24)) * 0x1p-24f;
-  return 1.41421356237309505f * erfinvf(v);
+  using namespace normal_poly;
+  const float x = fmaf((float)(word >> 8), 0x1p-23f, 0x1p-24f - 1.0f);
+  const float ax = fabsf(x);
+  const float y = (1.0f - ax) * (1.0f + ax);  // 1 - x^2 >= 2^-24 (1 + 2^-24)
+  const float L = -__builtin_amdgcn_logf(y);
+  float p;
+  if (L < kSplit) {
+    const float t = fmaf(L, kCenScale, kCenOff);
+    p = kCen[8];
+#pragma unroll
+    for (int i = 7; i >= 0; --i) p = fmaf(p, t, kCen[i]);
+  } else {
+    const float t = fmaf(__builtin_amdgcn_sqrtf(L), kTailScale, kTailOff);
+    p = kTail[8];
+#pragma unroll
+    for (int i = 7; i >= 0; --i) p = fmaf(p, t, kTail[i]);
+  }
+  return x * p;
+}
+
+// Component of a molecule's mixture selected by a Philox word:
+// j = #{i < n-1 : word >= thr_i}.  The thresholds are non-decreasing, so the
+// count is found by binary lifting in ceil(log2(n)) steps (the step count is
+// the same for every lane); every index read is below n-1.
+__device__ __forceinline__ int select_component(const AtomSampling* samp, int n, uint32_t word) {
+  const int last = n - 1;
+  int j = 0;
+  if (last > 0) {
+    for (int step = 1 << (31 - __builtin_clz((unsigned)last)); step > 0; step >>= 1) {
+      const int c = j + step;
+      const int idx = (c < last ? c : last) - 1;
+      if (c <= last && word >= samp[idx].thr) j = c;
+    }
+  }
+  return j;
 }
 
 // Sample point k of a molecule (exact draw from its normalised mixture):
@@ -62,8 +101,7 @@ __device__ __forceinline__ void sample_point(const Atom* atoms, const AtomSampli
                                              int n, uint32_t mol_id, uint64_t k, uint2 key,
                                              float& rx, float& ry, float& rz) {
   const uint4 x = philox4x32_10(make_uint4((uint32_t)k, (uint32_t)(k >> 32), mol_id, 0u), key);
-  int j = 0;
-  for (int i = 0; i < n - 1; ++i) j += (x.x >= samp[i].thr) ? 1 : 0;
+  const int j = select_component(samp, n, x.x);
   const Atom c = atoms[j];
   const float sd = samp[j].sd;
   rx = fmaf(normal_from_bits(x.y), sd, c.x);
@@ -214,8 +252,9 @@ __device__ __forceinline__ float norm2(float x, float y, float z) {
 }
 
 // Bounded weight w = u/m in [0, 1] (m > 0 for every sampled point; guard 0).
+// u times the hardware reciprocal of m: within 2 ulp of the quotient.
 __device__ __forceinline__ float bounded_weight(float u, float m) {
-  return m > 0.0f ? fminf(u / m, 1.0f) : 0.0f;
+  return m > 0.0f ? fminf(u * __builtin_amdgcn_rcpf(m), 1.0f) : 0.0f;
 }
 
 // ---------------------------------------------------------------------------
@@ -225,6 +264,25 @@ __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
   return v;
+}
+
+// Wave sum by DPP: an inclusive scan inside each row of 16 lanes (shifts 1,
+// 2, 4, 8), then lane 15 of rows 0 and 2 is added into rows 1 and 3 and lane
+// 31 into rows 2 and 3, leaving the total in lane 63, which is returned to
+// every lane.  Fixed order: deterministic.
+template <int Ctrl, int RowMask>
+__device__ __forceinline__ float dpp_step(float v) {
+  const int s = __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), Ctrl, RowMask, 0xf, true);
+  return v + __builtin_bit_cast(float, s);
+}
+__device__ __forceinline__ float wave_sum_dpp(float v) {
+  v = dpp_step<0x111, 0xf>(v);  // row_shr:1
+  v = dpp_step<0x112, 0xf>(v);  // row_shr:2
+  v = dpp_step<0x114, 0xf>(v);  // row_shr:4
+  v = dpp_step<0x118, 0xf>(v);  // row_shr:8
+  v = dpp_step<0x142, 0xa>(v);  // row_bcast:15 into rows 1, 3
+  v = dpp_step<0x143, 0xc>(v);  // row_bcast:31 into rows 2, 3
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
 }
 
 __device__ __forceinline__ float wave_sumf(float v) {

@@ -415,21 +415,23 @@ __global__ __launch_bounds__(64) void k_screen(ScreenArgs a) {
   const double Zb = a.L.Z[m];
   const int rs = a.round_side;
   const int per_lane = rs / kWave;
-  double acc[10];
-#pragma unroll
-  for (int j = 0; j < 10; ++j) acc[j] = 0.0;
+  // Running sums over both sides, identical in every lane: per round each
+  // lane's FP32 partials are summed across the wave (DPP) and added in FP64.
+  // S[0..2] = sum f1, sum f1^2, sum f2 on side A; S[3..5] the same on side B.
+  double S[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   int64_t n_side = 0;
   const int64_t first_check = a.n_start ? (int64_t)a.n_start[p] : 0;
+  const double tau2x4 = 4.0 * a.tau * a.tau;
   for (;;) {
-    float fa[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
-    float fb[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+    float fa[3] = {0.f, 0.f, 0.f};
+    float fb[3] = {0.f, 0.f, 0.f};
     // side A: query samples from the cache (query frame), partner = library
     for (int t = 0; t < per_lane; t += kSA) {
       float rx[kSA], ry[kSA], rz[kSA], r2[kSA], w[kSA], f2[kSA], q[kSA], valid[kSA];
 #pragma unroll
       for (int s = 0; s < kSA; ++s) {
         const bool ok = (t + s) < per_lane;
-        const int64_t k = n_side + (int64_t)lane + (int64_t)kWave * (ok ? t + s : t);
+        const int k = (int)n_side + lane + kWave * (ok ? t + s : t);
         const float4 c = a.qs[k];
         rx[s] = c.x; ry[s] = c.y; rz[s] = c.z; w[s] = c.w;
         r2[s] = norm2(c.x, c.y, c.z);
@@ -441,10 +443,8 @@ __global__ __launch_bounds__(64) void k_screen(ScreenArgs a) {
 #pragma unroll
       for (int s = 0; s < kSA; ++s) {
         const float f1 = w[s] * (1.0f - q[s]) * valid[s];
-        const float g2 = f2[s] * valid[s];
-        fa[0] += f1; fa[1] += f1 * f1;
-        fa[2] += g2; fa[3] += g2 * g2;
-        fa[4] += f1 * g2;
+        fa[0] += f1; fa[1] = fmaf(f1, f1, fa[1]);
+        fa[2] = fmaf(f2[s], valid[s], fa[2]);
       }
     }
     // side B: library samples drawn here (library frame), partner = query
@@ -466,39 +466,47 @@ __global__ __launch_bounds__(64) void k_screen(ScreenArgs a) {
         const float ub = 1.0f - qb[s];
         const float w = bounded_weight(ub, mb[s]) * valid[s];
         const float f1 = w * (1.0f - qa[s]);
-        const float f2 = w * ub;
-        fb[0] += f1; fb[1] += f1 * f1;
-        fb[2] += f2; fb[3] += f2 * f2;
-        fb[4] += f1 * f2;
+        fb[0] += f1; fb[1] = fmaf(f1, f1, fb[1]);
+        fb[2] = fmaf(w, ub, fb[2]);
       }
     }
 #pragma unroll
-    for (int j = 0; j < 5; ++j) {
-      acc[j] += (double)fa[j];
-      acc[5 + j] += (double)fb[j];
+    for (int j = 0; j < 3; ++j) {
+      S[j] += (double)wave_sum_dpp(fa[j]);
+      S[3 + j] += (double)wave_sum_dpp(fb[j]);
     }
     n_side += rs;
     int stop;
-    if (a.mode == SHAPE_SCREEN_ADAPTIVE && 2 * n_side < first_check && 2 * n_side < a.cap_pair) {
-      stop = 0;  // below the pair's seeded budget: no test yet
-    } else if (a.mode == SHAPE_SCREEN_ADAPTIVE) {
-      const double sa1 = wave_sum(acc[0]), sa11 = wave_sum(acc[1]), sa2 = wave_sum(acc[2]);
-      const double sb1 = wave_sum(acc[5]), sb11 = wave_sum(acc[6]), sb2 = wave_sum(acc[7]);
-      const double se = se_tanimoto((double)n_side, Za, Zb, sa1, sa11, sa2, sb1, sb11, sb2,
-                                    nullptr, nullptr, nullptr, nullptr);
-      stop = (se <= a.tau || 2 * n_side >= a.cap_pair) ? 1 : 0;
+    if (a.mode == SHAPE_SCREEN_ADAPTIVE) {
+      if (2 * n_side >= a.cap_pair) {
+        stop = 1;
+      } else if (2 * n_side < first_check) {
+        stop = 0;  // below the pair's seeded budget: no test yet
+      } else {
+        // SE(T) <= tau without divisions or roots: with n samples per side,
+        // S' = Za a2 + Zb b2, D' = S' - (Za a1 + Zb b1)/2 and
+        // V = n a11 - a1^2 (clamped at 0), the delta-method SE satisfies
+        //   SE(T)^2 = S'^2 (Za^2 Va + Zb^2 Vb) / (4 (n-1) D'^4),
+        // so the test is S'^2 (Za^2 Va + Zb^2 Vb) <= 4 tau^2 (n-1) D'^4 with
+        // D' != 0 (NaN sums never stop).
+        const double n = (double)n_side;
+        const double Sp = Za * S[2] + Zb * S[5];
+        const double Dp = Sp - 0.5 * (Za * S[0] + Zb * S[3]);
+        const double Va = fmax(n * S[1] - S[0] * S[0], 0.0);
+        const double Vb = fmax(n * S[4] - S[3] * S[3], 0.0);
+        const double lhs = Sp * Sp * (Za * Za * Va + Zb * Zb * Vb);
+        const double D2 = Dp * Dp;
+        stop = (Dp != 0.0 && lhs <= tau2x4 * (n - 1.0) * D2 * D2) ? 1 : 0;
+      }
     } else {
       stop = n_side >= a.n_fixed ? 1 : 0;
     }
     if (__builtin_amdgcn_readfirstlane(stop)) break;
   }
-  double tot[10];
-#pragma unroll
-  for (int j = 0; j < 10; ++j) tot[j] = wave_sum(acc[j]);
   if (lane == 0) {
     double T, O_ab, O_aa, O_bb;
-    const double se = se_tanimoto((double)n_side, Za, Zb, tot[0], tot[1], tot[2], tot[5],
-                                  tot[6], tot[7], &T, &O_ab, &O_aa, &O_bb);
+    const double se = se_tanimoto((double)n_side, Za, Zb, S[0], S[1], S[2], S[3], S[4], S[5],
+                                  &T, &O_ab, &O_aa, &O_bb);
     a.T[p] = (float)T;
     a.se_T[p] = (float)se;
     if (a.O_ab) a.O_ab[p] = (float)O_ab;
