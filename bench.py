@@ -317,8 +317,26 @@ def main():
         eng.shape_timing_enable(False)
         return start.elapsed_time(stop) / steps, kern_ms / max(launches, 1)
 
-    log("timing adaptive screen")
-    ms_step, kern_ms = timed(adaptive, args.steps, args.warmup)
+    # work granularity of the screening kernel, autotuned on this workload
+    # (every variant gives bit-identical results; untimed set-up)
+    log("tuning the screening kernel")
+    best, tune_ms = eng.shape_screen_tune(Q, lib, mode=SHAPE_SCREEN_ADAPTIVE,
+                                          round_per_pair=ROUND, cap_per_pair=CAP, tau=TAU,
+                                          seed=0)
+    log(f"tile variant {best}: " + ", ".join(f"{t:.2f}" for t in tune_ms) + " ms")
+
+    log("timing adaptive screen (direct launches; kernel events)")
+    ms_eager, kern_ms = timed(adaptive, args.steps, args.warmup)
+    eng.shape_check_data()
+    # the step's launches (preparation, query cache, screen) as one HIP graph
+    graph = eng.capture(adaptive)
+
+    def replay():
+        graph.replay()
+
+    log("timing adaptive screen (graph replays)")
+    ms_step, _ = timed(replay, args.steps, args.warmup)
+    graph.close()
     eng.shape_check_data()
     n_used = out["n_used"].cpu().numpy().astype(np.int64)
     se_T = out["se_T"].cpu().numpy()
@@ -356,6 +374,8 @@ def main():
             "library": n, "query_atoms": na, "tau": TAU, "round_per_pair": ROUND,
             "cap_per_pair": CAP,
         },
+        "ms_per_step_direct_launches": ms_eager,
+        "tuning": {"variant": best, "ms_per_variant": tune_ms},
         "atom_evals_per_s": (ev_other + ev_own) / (ms_step * 1e-3),
         "plain_equivalent_atom_evals_per_s": ev_plain / (ms_step * 1e-3),
         "samples_per_step": int(n_used.sum()),
@@ -369,8 +389,8 @@ def main():
             "unit": "TOP/s",
             "frac": achieved / peak,
             # HBM bytes per launch from rocprofv3 FETCH_SIZE (x2.0) and
-            # WRITE_SIZE (x1.0) scaled by a 1 GiB copy of known size: 138.8 MB
-            # read + 19.2 MB written (see the traffic summary in profiles/)
+            # WRITE_SIZE (x1.0) scaled by a 1 GiB copy of known size (the
+            # traffic summary in profiles/)
             "traffic": TRAFFIC_BYTES,
             "kernel_ms": kern_ms,
             "atom_evals_per_launch": ev_other + ev_own,

@@ -197,6 +197,53 @@ int shape_screen(shape_ctx* ctx, const shape_mols* query, const shape_mols* lib,
  * (SHAPE_OK); clears the flag. */
 int shape_check_data(shape_ctx* ctx, void* stream);
 
+/* Work-granularity autotuning of the screening kernel (adaptive batching,
+ * section "Confidence-bounded screening": the rounds and the stopping rule
+ * are fixed by the method; only how many points a lane evaluates per atom
+ * record is tuned).  Every variant draws the same samples, assigns them to
+ * the same lanes and sums them in the same order, so results are
+ * bit-identical whichever variant runs.
+ *
+ * shape_screen_tune runs the screen described by its arguments (as for
+ * shape_screen; outputs go to context scratch) once per variant after one
+ * untimed warm-up launch, times each with HIP events on `stream`, keeps the
+ * fastest as the context's variant for later shape_screen calls, and writes
+ * its index to *best (host pointer, may be NULL) and the measured kernel
+ * times to ms[SHAPE_SCREEN_VARIANTS] (host, may be NULL).  Synchronises
+ * `stream`.  Errors: as shape_screen; SHAPE_E_UNSUPPORTED during capture.
+ * shape_screen_set_variant selects a variant by index (-1 = default);
+ * shape_screen_get_variant returns the current one (-1 if ctx is NULL). */
+#define SHAPE_SCREEN_VARIANTS 8
+int shape_screen_tune(shape_ctx* ctx, const shape_mols* query, const shape_mols* lib,
+                      const int32_t* pairs, int32_t n_pairs,
+                      const shape_screen_params* params, void* stream, float* ms,
+                      int32_t* best);
+int shape_screen_set_variant(shape_ctx* ctx, int32_t variant);
+int32_t shape_screen_get_variant(const shape_ctx* ctx);
+
+/* HIP graphs of a sequence of asynchronous calls (launch overhead only;
+ * results are those of the same calls made directly).
+ * shape_graph_begin starts capturing `stream` (which must not be the null
+ * stream); every asynchronous call of this library on that stream is then
+ * recorded instead of run, until shape_graph_end, which ends the capture and
+ * returns an executable graph in *out (owned by the caller; release with
+ * shape_graph_destroy).  shape_graph_launch replays it on `stream`.
+ * Replays read and write the same device addresses as the captured calls,
+ * so those buffers must stay allocated while the graph is used; input data
+ * may change between replays.  During capture the library allocates
+ * nothing: run the same calls once, uncaptured, beforehand so its scratch is
+ * large enough (else SHAPE_E_UNSUPPORTED), and calls that synchronise
+ * (shape_estimate, shape_check_data, shape_screen_tune, shape_timing_read)
+ * return SHAPE_E_UNSUPPORTED.  Kernel timing is suspended while capturing.
+ * A failed call inside the capture leaves it open; shape_graph_end then
+ * discards it and returns the error.  Errors: SHAPE_E_INVAL, SHAPE_E_HIP,
+ * SHAPE_E_UNSUPPORTED. */
+typedef struct shape_graph shape_graph;
+int shape_graph_begin(shape_ctx* ctx, void* stream);
+int shape_graph_end(shape_ctx* ctx, void* stream, shape_graph** out);
+int shape_graph_launch(shape_ctx* ctx, shape_graph* graph, void* stream);
+void shape_graph_destroy(shape_graph* graph);
+
 /* ------------------------------------------------------------------------
  * Differentiable rigid alignment (section "Differentiable alignment and the
  * hybrid pipeline", Eqs. pose and grad).  B is moved rigidly,

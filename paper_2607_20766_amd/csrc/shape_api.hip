@@ -28,7 +28,7 @@ enum Slot {
   S_L_ATOM, S_L_SAMP, S_L_Z, S_L_ID, S_L_BAD, S_L_CENTRE,
   S_PARTIALS, S_RESULT, S_QS, S_QF2,
   S_SELF_A, S_SELF_B, S_ADAM_M, S_ADAM_V, S_ADAM_STEP, S_GRAD,
-  S_MSE, S_TOPK_SEL, S_TOPK_HIST, S_TOPK_GT, S_TOPK_EQ, S_COLSUM,
+  S_MSE, S_TOPK_SEL, S_TOPK_HIST, S_TOPK_GT, S_TOPK_EQ, S_COLSUM, S_TUNE,
   S_COUNT
 };
 
@@ -43,6 +43,15 @@ struct shape_ctx {
   int* flag = nullptr;  // invalid-data flag (device int)
   bool timing = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+  int screen_variant = -1;        // -1: default tile shape
+  bool capturing = false;         // a graph capture is open on capture_stream
+  bool capture_failed = false;    // a call failed while capturing
+  hipStream_t capture_stream = nullptr;
+};
+
+struct shape_graph {
+  hipGraphExec_t exec = nullptr;
+  int device = -1;
 };
 
 namespace {
@@ -55,7 +64,12 @@ int fail(shape_ctx* c, int code, const char* fmt, ...) {
   va_start(ap, fmt);
   vsnprintf(msg, sizeof msg, fmt, ap);
   va_end(ap);
-  if (c) c->err = msg; else g_create_err = msg;
+  if (c) {
+    c->err = msg;
+    if (c->capturing) c->capture_failed = true;
+  } else {
+    g_create_err = msg;
+  }
   return code;
 }
 
@@ -74,6 +88,10 @@ int hip_fail(shape_ctx* c, hipError_t e, const char* what) {
 int ensure(shape_ctx* c, Slot s, size_t bytes, void** out) {
   Buffer& b = c->buf[s];
   if (b.bytes < bytes) {
+    if (c->capturing)
+      return fail(c, SHAPE_E_UNSUPPORTED,
+                  "scratch would grow during graph capture: make the same calls once "
+                  "before capturing");
     if (b.ptr) {
       hipError_t e = hipDeviceSynchronize();
       if (e != hipSuccess) return hip_fail(c, e, "hipDeviceSynchronize");
@@ -139,6 +157,12 @@ int prepare(shape_ctx* c, const shape_mols* m, bool q, hipStream_t st, shape::Pr
   return SHAPE_OK;
 }
 
+// Calls that synchronise cannot be recorded into a graph.
+int refuse_in_capture(shape_ctx* c, const char* what) {
+  return fail(c, SHAPE_E_UNSUPPORTED, "%s synchronises and cannot run during graph capture",
+              what);
+}
+
 uint2 key_of(uint64_t seed) { return make_uint2((uint32_t)seed, (uint32_t)(seed >> 32)); }
 
 // Brackets the dominant kernel of a call with HIP events when timing is on.
@@ -147,7 +171,7 @@ struct KernelTimer {
   hipStream_t st;
   hipEvent_t a = nullptr, b = nullptr;
   KernelTimer(shape_ctx* c_, hipStream_t st_) : c(c_), st(st_) {
-    if (!c->timing) return;
+    if (!c->timing || c->capturing) return;
     if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess ||
         hipEventRecord(a, st) != hipSuccess) {
       a = b = nullptr;
@@ -160,9 +184,91 @@ struct KernelTimer {
   }
 };
 
+// Validation, molecule preparation and the query-side sample cache of a
+// screen; fills the kernel arguments (a->n_pairs = 0: nothing to launch).
+int screen_setup(shape_ctx* c, const shape_mols* query, const shape_mols* lib,
+                 const int32_t* pairs, int32_t n_pairs, const shape_screen_params* prm,
+                 hipStream_t st, const shape_screen_out* out, shape::ScreenArgs* a) {
+  int rc;
+  if ((rc = check_mols(c, query, "query", true))) return rc;
+  if ((rc = check_mols(c, lib, "lib", false))) return rc;
+  if (!prm || !out) return fail(c, SHAPE_E_INVAL, "params or out is NULL");
+  if (n_pairs < 0) return fail(c, SHAPE_E_RANGE, "n_pairs < 0");
+  if (n_pairs > 0 && (!out->T || !out->se_T))
+    return fail(c, SHAPE_E_INVAL, "out->T and out->se_T are required");
+  if (!pairs && n_pairs > lib->n_mols)
+    return fail(c, SHAPE_E_RANGE, "n_pairs = %d exceeds lib->n_mols = %d", n_pairs,
+                lib->n_mols);
+  int64_t n_fixed = 0, cap = 0;
+  int round_side = 0;
+  if (prm->mode == SHAPE_SCREEN_FIXED) {
+    if (prm->n_per_side < 64 || prm->n_per_side > (1 << 20) || prm->n_per_side % 64)
+      return fail(c, SHAPE_E_RANGE, "n_per_side must be a multiple of 64 in [64, 2^20]");
+    n_fixed = prm->n_per_side;
+    round_side = (int)(n_fixed % 256 == 0 ? 256 : 64);
+  } else if (prm->mode == SHAPE_SCREEN_ADAPTIVE) {
+    if (prm->round_per_pair < 128 || prm->round_per_pair > 8192 || prm->round_per_pair % 128)
+      return fail(c, SHAPE_E_RANGE, "round_per_pair must be a multiple of 128 in [128, 8192]");
+    if (prm->cap_per_pair < prm->round_per_pair || prm->cap_per_pair > (1 << 21) ||
+        prm->cap_per_pair % prm->round_per_pair)
+      return fail(c, SHAPE_E_RANGE,
+                  "cap_per_pair must be a multiple of round_per_pair, at most 2^21");
+    if (!(prm->tau > 0.0) || !isfinite(prm->tau))
+      return fail(c, SHAPE_E_RANGE, "tau must be finite and > 0");
+    round_side = prm->round_per_pair / 2;
+    cap = prm->cap_per_pair;
+  } else {
+    return fail(c, SHAPE_E_INVAL, "unknown mode %d", prm->mode);
+  }
+  if (n_pairs == 0) {
+    a->n_pairs = 0;
+    return SHAPE_OK;
+  }
+  if ((rc = set_device(c))) return rc;
+  shape::Prepared PQ, PL;
+  if ((rc = prepare(c, query, true, st, &PQ))) return rc;
+  if ((rc = prepare(c, lib, false, st, &PL))) return rc;
+  const int64_t n_cache = prm->mode == SHAPE_SCREEN_FIXED ? n_fixed : cap / 2;
+  void *qs, *qf2;
+  if ((rc = ensure(c, S_QS, (size_t)n_cache * sizeof(float4), &qs))) return rc;
+  if ((rc = ensure(c, S_QF2, (size_t)n_cache * sizeof(float), &qf2))) return rc;
+  const uint2 key = key_of(prm->seed);
+  HIP_TRY(c, shape::launch_query_cache(PQ, query->atom_offset, n_cache, key, (float4*)qs,
+                                       (float*)qf2, st),
+          "query cache kernel");
+  a->Q = PQ;
+  a->offQ = query->atom_offset;
+  a->max_q = query->max_atoms;
+  a->L = PL;
+  a->offL = lib->atom_offset;
+  a->n_lib = lib->n_mols;
+  a->max_b = lib->max_atoms;
+  a->qs = (const float4*)qs;
+  a->qf2 = (const float*)qf2;
+  a->pairs = pairs;
+  a->n_pairs = n_pairs;
+  a->mode = prm->mode;
+  a->n_fixed = n_fixed;
+  a->round_side = round_side;
+  a->cap_pair = cap;
+  a->tau = prm->tau;
+  a->key = key;
+  a->n_start = prm->mode == SHAPE_SCREEN_ADAPTIVE ? prm->n_start : nullptr;
+  a->T = out->T;
+  a->se_T = out->se_T;
+  a->O_ab = out->O_ab;
+  a->O_aa = out->O_aa;
+  a->O_bb = out->O_bb;
+  a->n_used = out->n_used;
+  return SHAPE_OK;
+}
+
+int screen_variant_of(const shape_ctx* c) { return c->screen_variant < 0 ? 0 : c->screen_variant; }
+
 }  // namespace
 
 extern "C" {
+
 
 const char* shape_version(void) { return SHAPE_VERSION_STR; }
 
@@ -240,6 +346,7 @@ int shape_alpha_from_radius(shape_ctx* c, const float* radius, int64_t n, double
 int shape_estimate(shape_ctx* c, const shape_mols* A, const shape_mols* B, int64_t n_a,
                    int64_t n_b, uint64_t seed, void* stream, shape_result* out) {
   if (!c) return SHAPE_E_INVAL;
+  if (c->capturing) return refuse_in_capture(c, "shape_estimate");
   try {
     int rc;
     if ((rc = check_mols(c, A, "A", true))) return rc;
@@ -287,84 +394,87 @@ int shape_screen(shape_ctx* c, const shape_mols* query, const shape_mols* lib,
                  void* stream, const shape_screen_out* out) {
   if (!c) return SHAPE_E_INVAL;
   try {
-    int rc;
-    if ((rc = check_mols(c, query, "query", true))) return rc;
-    if ((rc = check_mols(c, lib, "lib", false))) return rc;
-    if (!prm || !out) return fail(c, SHAPE_E_INVAL, "params or out is NULL");
-    if (n_pairs < 0) return fail(c, SHAPE_E_RANGE, "n_pairs < 0");
-    if (n_pairs > 0 && (!out->T || !out->se_T))
-      return fail(c, SHAPE_E_INVAL, "out->T and out->se_T are required");
-    if (!pairs && n_pairs > lib->n_mols)
-      return fail(c, SHAPE_E_RANGE, "n_pairs = %d exceeds lib->n_mols = %d", n_pairs,
-                  lib->n_mols);
-    int64_t n_fixed = 0, cap = 0;
-    int round_side = 0;
-    if (prm->mode == SHAPE_SCREEN_FIXED) {
-      if (prm->n_per_side < 64 || prm->n_per_side > (1 << 20) || prm->n_per_side % 64)
-        return fail(c, SHAPE_E_RANGE, "n_per_side must be a multiple of 64 in [64, 2^20]");
-      n_fixed = prm->n_per_side;
-      round_side = (int)(n_fixed % 256 == 0 ? 256 : 64);
-    } else if (prm->mode == SHAPE_SCREEN_ADAPTIVE) {
-      if (prm->round_per_pair < 128 || prm->round_per_pair > 8192 || prm->round_per_pair % 128)
-        return fail(c, SHAPE_E_RANGE, "round_per_pair must be a multiple of 128 in [128, 8192]");
-      if (prm->cap_per_pair < prm->round_per_pair || prm->cap_per_pair > (1 << 21) ||
-          prm->cap_per_pair % prm->round_per_pair)
-        return fail(c, SHAPE_E_RANGE,
-                    "cap_per_pair must be a multiple of round_per_pair, at most 2^21");
-      if (!(prm->tau > 0.0) || !isfinite(prm->tau))
-        return fail(c, SHAPE_E_RANGE, "tau must be finite and > 0");
-      round_side = prm->round_per_pair / 2;
-      cap = prm->cap_per_pair;
-    } else {
-      return fail(c, SHAPE_E_INVAL, "unknown mode %d", prm->mode);
-    }
-    if (n_pairs == 0) return SHAPE_OK;
-    if ((rc = set_device(c))) return rc;
     hipStream_t st = (hipStream_t)stream;
-    shape::Prepared PQ, PL;
-    if ((rc = prepare(c, query, true, st, &PQ))) return rc;
-    if ((rc = prepare(c, lib, false, st, &PL))) return rc;
-    const int64_t n_cache = prm->mode == SHAPE_SCREEN_FIXED ? n_fixed : cap / 2;
-    void *qs, *qf2;
-    if ((rc = ensure(c, S_QS, (size_t)n_cache * sizeof(float4), &qs))) return rc;
-    if ((rc = ensure(c, S_QF2, (size_t)n_cache * sizeof(float), &qf2))) return rc;
-    const uint2 key = key_of(prm->seed);
-    HIP_TRY(c, shape::launch_query_cache(PQ, query->atom_offset, n_cache, key, (float4*)qs,
-                                         (float*)qf2, st),
-            "query cache kernel");
     shape::ScreenArgs a;
-    a.Q = PQ;
-    a.offQ = query->atom_offset;
-    a.max_q = query->max_atoms;
-    a.L = PL;
-    a.offL = lib->atom_offset;
-    a.n_lib = lib->n_mols;
-    a.max_b = lib->max_atoms;
-    a.qs = (const float4*)qs;
-    a.qf2 = (const float*)qf2;
-    a.pairs = pairs;
-    a.n_pairs = n_pairs;
-    a.mode = prm->mode;
-    a.n_fixed = n_fixed;
-    a.round_side = round_side;
-    a.cap_pair = cap;
-    a.tau = prm->tau;
-    a.key = key;
-    a.n_start = prm->mode == SHAPE_SCREEN_ADAPTIVE ? prm->n_start : nullptr;
-    a.T = out->T;
-    a.se_T = out->se_T;
-    a.O_ab = out->O_ab;
-    a.O_aa = out->O_aa;
-    a.O_bb = out->O_bb;
-    a.n_used = out->n_used;
+    int rc = screen_setup(c, query, lib, pairs, n_pairs, prm, st, out, &a);
+    if (rc || a.n_pairs == 0) return rc;
     KernelTimer timer(c, st);
-    HIP_TRY(c, shape::launch_screen(a, st), "screen kernel");
+    HIP_TRY(c, shape::launch_screen(a, screen_variant_of(c), st), "screen kernel");
     timer.stop();
     return SHAPE_OK;
   } catch (...) {
     return fail(c, SHAPE_E_HIP, "internal error");
   }
 }
+
+int shape_screen_tune(shape_ctx* c, const shape_mols* query, const shape_mols* lib,
+                      const int32_t* pairs, int32_t n_pairs, const shape_screen_params* prm,
+                      void* stream, float* ms, int32_t* best) {
+  if (!c) return SHAPE_E_INVAL;
+  if (c->capturing) return refuse_in_capture(c, "shape_screen_tune");
+  try {
+    hipStream_t st = (hipStream_t)stream;
+    void* scratch;
+    int rc;
+    if (n_pairs < 0) return fail(c, SHAPE_E_RANGE, "n_pairs < 0");
+    if ((rc = ensure(c, S_TUNE, (size_t)(n_pairs > 0 ? n_pairs : 1) * 2 * sizeof(float),
+                     &scratch)))
+      return rc;
+    shape_screen_out o{};
+    o.T = (float*)scratch;
+    o.se_T = (float*)scratch + (n_pairs > 0 ? n_pairs : 1);
+    shape::ScreenArgs a;
+    if ((rc = screen_setup(c, query, lib, pairs, n_pairs, prm, st, &o, &a))) return rc;
+    float t[shape::kScreenVariants];
+    int pick = 0;
+    if (a.n_pairs > 0) {
+      hipEvent_t e0, e1;
+      HIP_TRY(c, hipEventCreate(&e0), "hipEventCreate");
+      hipError_t e = hipEventCreate(&e1);
+      if (e != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return hip_fail(c, e, "hipEventCreate");
+      }
+      e = shape::launch_screen(a, 0, st);  // warm-up
+      for (int v = 0; v < shape::kScreenVariants && e == hipSuccess; ++v) {
+        t[v] = 3.0e38f;
+        for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
+          float dt = 0.0f;
+          e = hipEventRecord(e0, st);
+          if (e == hipSuccess) e = shape::launch_screen(a, v, st);
+          if (e == hipSuccess) e = hipEventRecord(e1, st);
+          if (e == hipSuccess) e = hipEventSynchronize(e1);
+          if (e == hipSuccess) e = hipEventElapsedTime(&dt, e0, e1);
+          if (e == hipSuccess && dt < t[v]) t[v] = dt;
+        }
+        if (e == hipSuccess && t[v] < t[pick]) pick = v;
+      }
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      if (e != hipSuccess) return hip_fail(c, e, "screen tuning");
+    } else {
+      for (int v = 0; v < shape::kScreenVariants; ++v) t[v] = 0.0f;
+    }
+    c->screen_variant = pick;
+    if (ms)
+      for (int v = 0; v < shape::kScreenVariants; ++v) ms[v] = t[v];
+    if (best) *best = pick;
+    return SHAPE_OK;
+  } catch (...) {
+    return fail(c, SHAPE_E_HIP, "internal error");
+  }
+}
+
+int shape_screen_set_variant(shape_ctx* c, int32_t variant) {
+  if (!c) return SHAPE_E_INVAL;
+  if (variant < -1 || variant >= shape::kScreenVariants)
+    return fail(c, SHAPE_E_RANGE, "variant %d outside [-1, %d)", variant,
+                shape::kScreenVariants);
+  c->screen_variant = variant;
+  return SHAPE_OK;
+}
+
+int32_t shape_screen_get_variant(const shape_ctx* c) { return c ? c->screen_variant : -1; }
 
 int shape_self_overlap(shape_ctx* c, const shape_mols* M, int32_t n_samples, uint64_t seed,
                        void* stream, float* O_self) {
@@ -677,6 +787,7 @@ int shape_timing_enable(shape_ctx* c, int enable) {
 }
 
 int shape_timing_read(shape_ctx* c, double* total_ms, int64_t* launches, int reset) {
+  if (c && c->capturing) return refuse_in_capture(c, "shape_timing_read");
   if (!c) return SHAPE_E_INVAL;
   int rc = set_device(c);
   if (rc) return rc;
@@ -700,6 +811,7 @@ int shape_timing_read(shape_ctx* c, double* total_ms, int64_t* launches, int res
 }
 
 int shape_check_data(shape_ctx* c, void* stream) {
+  if (c && c->capturing) return refuse_in_capture(c, "shape_check_data");
   if (!c) return SHAPE_E_INVAL;
   int rc = set_device(c);
   if (rc) return rc;
@@ -713,6 +825,77 @@ int shape_check_data(shape_ctx* c, void* stream) {
     return fail(c, SHAPE_E_DATA, "invalid molecule data seen since the last check");
   }
   return SHAPE_OK;
+}
+
+int shape_graph_begin(shape_ctx* c, void* stream) {
+  if (!c) return SHAPE_E_INVAL;
+  if (!stream) return fail(c, SHAPE_E_INVAL, "the null stream cannot be captured");
+  if (c->capturing) return fail(c, SHAPE_E_UNSUPPORTED, "a graph capture is already open");
+  int rc = set_device(c);
+  if (rc) return rc;
+  HIP_TRY(c, hipStreamBeginCapture((hipStream_t)stream, hipStreamCaptureModeRelaxed),
+          "hipStreamBeginCapture");
+  c->capturing = true;
+  c->capture_failed = false;
+  c->capture_stream = (hipStream_t)stream;
+  return SHAPE_OK;
+}
+
+int shape_graph_end(shape_ctx* c, void* stream, shape_graph** out) {
+  if (!c) return SHAPE_E_INVAL;
+  if (out) *out = nullptr;
+  if (!c->capturing || c->capture_stream != (hipStream_t)stream)
+    return fail(c, SHAPE_E_INVAL, "no graph capture is open on this stream");
+  c->capturing = false;
+  c->capture_stream = nullptr;
+  hipGraph_t g = nullptr;
+  HIP_TRY(c, hipStreamEndCapture((hipStream_t)stream, &g), "hipStreamEndCapture");
+  if (c->capture_failed) {
+    (void)hipGraphDestroy(g);
+    return fail(c, SHAPE_E_UNSUPPORTED, "a call failed during capture (capture discarded): %s",
+                c->err.c_str());
+  }
+  if (!out) {
+    (void)hipGraphDestroy(g);
+    return fail(c, SHAPE_E_INVAL, "out is NULL (capture discarded)");
+  }
+  shape_graph* sg = new (std::nothrow) shape_graph();
+  if (!sg) {
+    (void)hipGraphDestroy(g);
+    return fail(c, SHAPE_E_NOMEM, "graph allocation failed");
+  }
+  hipError_t e = hipGraphInstantiate(&sg->exec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    delete sg;
+    return hip_fail(c, e, "hipGraphInstantiate");
+  }
+  sg->device = c->device;
+  *out = sg;
+  return SHAPE_OK;
+}
+
+int shape_graph_launch(shape_ctx* c, shape_graph* g, void* stream) {
+  if (!c) return SHAPE_E_INVAL;
+  if (!g || !g->exec) return fail(c, SHAPE_E_INVAL, "graph is NULL");
+  if (g->device != c->device)
+    return fail(c, SHAPE_E_INVAL, "graph belongs to device %d, context to %d", g->device,
+                c->device);
+  if (c->capturing) return fail(c, SHAPE_E_UNSUPPORTED, "graph launch during capture");
+  int rc = set_device(c);
+  if (rc) return rc;
+  HIP_TRY(c, hipGraphLaunch(g->exec, (hipStream_t)stream), "hipGraphLaunch");
+  return SHAPE_OK;
+}
+
+void shape_graph_destroy(shape_graph* g) {
+  if (!g) return;
+  if (g->exec) {
+    (void)hipSetDevice(g->device);
+    (void)hipDeviceSynchronize();  // no replay of it is still queued
+    (void)hipGraphExecDestroy(g->exec);
+  }
+  delete g;
 }
 
 }  // extern "C"

@@ -334,13 +334,19 @@ __global__ __launch_bounds__(256) void k_query_cache(Prepared Qp, const int* __r
 // Adaptive mode takes the stopping decision on SE(T) in FP64 after every
 // round; the decision is read from the first lane so the branch is scalar.
 // ---------------------------------------------------------------------------
-constexpr int kSA = 4;  // side-A points per lane evaluated together
-constexpr int kSB = 2;  // side-B points per lane evaluated together
+// Work granularity of the screening kernel: kSA (kSB) side-A (side-B) points
+// per lane are evaluated together against each atom record read from LDS.
+// Every variant assigns the same samples to the same lanes and accumulates
+// them in the same order, so all variants give bit-identical results; the
+// autotuner picks the fastest for a workload.
+const int kScreenVariantShape[kScreenVariants][2] = {
+    {4, 2}, {2, 2}, {4, 1}, {4, 4}, {8, 2}, {2, 1}, {8, 4}, {2, 4}};
 
 __device__ __forceinline__ double se_tanimoto(double n, double Za, double Zb, double a1,
                                               double a11, double a2, double b1, double b11,
                                               double b2, double* T_out, double* Oab_out,
                                               double* Oaa_out, double* Obb_out) {
+#pragma clang fp contract(off)
   const double xa = Za * a1 / n, xb = Zb * b1 / n;
   double va = (a11 - a1 * a1 / n) / (n - 1.0);
   double vb = (b11 - b1 * b1 / n) / (n - 1.0);
@@ -358,7 +364,11 @@ __device__ __forceinline__ double se_tanimoto(double n, double Za, double Zb, do
   return fabs(S / (D * D)) * se_O;
 }
 
+template <int kSA, int kSB>
 __global__ __launch_bounds__(64) void k_screen(ScreenArgs a) {
+  // No implicit multiply-add contraction: the fused operations are written
+  // out, so every tile variant rounds identically.
+#pragma clang fp contract(off)
   // LDS (per pair, n = atoms):
   //   sBF   [max_b] Atom          library atoms in the library frame (sampling)
   //   sBS   [max_b] AtomSampling  their sampling records
@@ -567,9 +577,24 @@ size_t screen_lds_bytes(int max_q, int max_b) {
          (size_t)max_q * (sizeof(AtomRec) + sizeof(float));
 }
 
-hipError_t launch_screen(const ScreenArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(k_screen, dim3((unsigned)a.n_pairs), dim3(kWave),
+template <int A, int B>
+static void launch_screen_t(const ScreenArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL((k_screen<A, B>), dim3((unsigned)a.n_pairs), dim3(kWave),
                      screen_lds_bytes(a.max_q, a.max_b), st, a);
+}
+
+hipError_t launch_screen(const ScreenArgs& a, int variant, hipStream_t st) {
+  switch (variant) {
+    case 0: launch_screen_t<4, 2>(a, st); break;
+    case 1: launch_screen_t<2, 2>(a, st); break;
+    case 2: launch_screen_t<4, 1>(a, st); break;
+    case 3: launch_screen_t<4, 4>(a, st); break;
+    case 4: launch_screen_t<8, 2>(a, st); break;
+    case 5: launch_screen_t<2, 1>(a, st); break;
+    case 6: launch_screen_t<8, 4>(a, st); break;
+    case 7: launch_screen_t<2, 4>(a, st); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

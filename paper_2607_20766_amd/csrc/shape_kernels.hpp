@@ -134,6 +134,8 @@ hipError_t launch_estimate(const Prepared& A, const Prepared& B, const int* offA
 hipError_t launch_query_cache(const Prepared& Q, const int* offQ, int64_t n, uint2 key,
                               float4* qs, float* qf2, hipStream_t st);
 size_t screen_lds_bytes(int max_q, int max_b);
-hipError_t launch_screen(const ScreenArgs& a, hipStream_t st);
+constexpr int kScreenVariants = 8;
+extern const int kScreenVariantShape[kScreenVariants][2];  // {kSA, kSB}
+hipError_t launch_screen(const ScreenArgs& a, int variant, hipStream_t st);
 
 }  // namespace shape

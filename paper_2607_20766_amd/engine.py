@@ -20,6 +20,8 @@ SHAPE_OK = 0
 SHAPE_SCREEN_FIXED = 0
 SHAPE_SCREEN_ADAPTIVE = 1
 SHAPE_MAX_ATOMS = 256
+SHAPE_SCREEN_VARIANTS = 8
+SHAPE_E_UNSUPPORTED = -5
 
 # Eq. occ width convention of the synthetic workloads: a Gaussian height
 # p = 2.7 in the Grant-Pickup width corresponds to lambda = p^(-2/3).
@@ -92,6 +94,17 @@ def load_library():
                                    vp, i32, ctypes.POINTER(ShapeScreenParams), vp,
                                    ctypes.POINTER(ShapeScreenOut)]
         L.shape_check_data.argtypes = [vp, vp]
+        L.shape_screen_tune.argtypes = [vp, ctypes.POINTER(ShapeMols),
+                                        ctypes.POINTER(ShapeMols), vp, i32,
+                                        ctypes.POINTER(ShapeScreenParams), vp, vp, vp]
+        L.shape_screen_set_variant.argtypes = [vp, i32]
+        L.shape_screen_get_variant.argtypes = [vp]
+        L.shape_screen_get_variant.restype = i32
+        L.shape_graph_begin.argtypes = [vp, vp]
+        L.shape_graph_end.argtypes = [vp, vp, ctypes.POINTER(vp)]
+        L.shape_graph_launch.argtypes = [vp, vp, vp]
+        L.shape_graph_destroy.argtypes = [vp]
+        L.shape_graph_destroy.restype = None
         L.shape_self_overlap.argtypes = [vp, ctypes.POINTER(ShapeMols), i32, u64, vp, vp]
         L.shape_align_grad.argtypes = [vp, ctypes.POINTER(ShapeMols), ctypes.POINTER(ShapeMols),
                                        i32, vp, vp, vp, i32, u64, vp, vp, vp]
@@ -214,6 +227,21 @@ class Engine:
         out["n_a"], out["n_b"] = res.n_a, res.n_b
         return out
 
+    @staticmethod
+    def _screen_params(mode, n_per_side, round_per_pair, cap_per_pair, tau, seed, n_start):
+        if n_start is not None:
+            n_start = n_start.to(torch.int32).contiguous()
+        prm = ShapeScreenParams(mode, n_per_side, round_per_pair, cap_per_pair, tau, seed,
+                                None if n_start is None else n_start.data_ptr())
+        return prm, n_start
+
+    @staticmethod
+    def _screen_pairs(lib, pairs, n_pairs):
+        if pairs is not None:
+            pairs = pairs.to(torch.int32).contiguous()
+            return pairs, int(pairs.numel())
+        return None, lib.n_mols if n_pairs is None else int(n_pairs)
+
     def shape_screen(self, query: Molecules, lib: Molecules, *, mode: int = SHAPE_SCREEN_FIXED,
                      n_per_side: int = 4096, round_per_pair: int = 512,
                      cap_per_pair: int = 65536, tau: float = 0.005, seed: int = 0,
@@ -222,20 +250,14 @@ class Engine:
                      stream=None) -> dict:
         """Screen the query against library molecules; returns device tensors
         T, se_T, O_ab, O_aa, O_bb (float32) and n_used (int32) per pair."""
-        if pairs is not None:
-            pairs = pairs.to(torch.int32).contiguous()
-            n = int(pairs.numel())
-        else:
-            n = lib.n_mols if n_pairs is None else int(n_pairs)
+        pairs, n = self._screen_pairs(lib, pairs, n_pairs)
         if out is None:
             dev = self.torch_device
             out = {k: torch.empty(n, dtype=torch.float32, device=dev)
                    for k in ("T", "se_T", "O_ab", "O_aa", "O_bb")}
             out["n_used"] = torch.empty(n, dtype=torch.int32, device=dev)
-        if n_start is not None:
-            n_start = n_start.to(torch.int32).contiguous()
-        prm = ShapeScreenParams(mode, n_per_side, round_per_pair, cap_per_pair, tau, seed,
-                                None if n_start is None else n_start.data_ptr())
+        prm, n_start = self._screen_params(mode, n_per_side, round_per_pair, cap_per_pair, tau,
+                                           seed, n_start)
         o = ShapeScreenOut(*(out[k].data_ptr() if out.get(k) is not None else None
                              for k in ("T", "se_T", "O_ab", "O_aa", "O_bb", "n_used")))
         q, l_ = query.c_struct(), lib.c_struct()
@@ -243,6 +265,60 @@ class Engine:
                                                 _ptr(pairs), n, ctypes.byref(prm),
                                                 _stream(stream), ctypes.byref(o)))
         return out
+
+    def shape_screen_tune(self, query: Molecules, lib: Molecules, *,
+                          mode: int = SHAPE_SCREEN_ADAPTIVE, n_per_side: int = 4096,
+                          round_per_pair: int = 512, cap_per_pair: int = 65536,
+                          tau: float = 0.005, seed: int = 0, pairs: torch.Tensor | None = None,
+                          n_pairs: int | None = None, n_start: torch.Tensor | None = None,
+                          stream=None):
+        """Time every tile variant of the screening kernel on this workload,
+        keep the fastest for later screens; returns (best, [ms per variant])."""
+        pairs, n = self._screen_pairs(lib, pairs, n_pairs)
+        prm, n_start = self._screen_params(mode, n_per_side, round_per_pair, cap_per_pair, tau,
+                                           seed, n_start)
+        ms = (ctypes.c_float * SHAPE_SCREEN_VARIANTS)()
+        best = ctypes.c_int32(-1)
+        q, l_ = query.c_struct(), lib.c_struct()
+        self._check(load_library().shape_screen_tune(
+            self._ctx, ctypes.byref(q), ctypes.byref(l_), _ptr(pairs), n, ctypes.byref(prm),
+            _stream(stream), ms, ctypes.byref(best)))
+        return int(best.value), [float(x) for x in ms]
+
+    def screen_variant(self, variant: int | None = None) -> int:
+        """Select the screening tile variant (-1 = default) if given; return
+        the current one."""
+        L = load_library()
+        if variant is not None:
+            self._check(L.shape_screen_set_variant(self._ctx, int(variant)))
+        return int(L.shape_screen_get_variant(self._ctx))
+
+    # -- graphs ----------------------------------------------------------------
+    def capture(self, fn, stream=None, warmup: bool = True) -> "Graph":
+        """Record the library calls that fn() makes into a HIP graph.
+
+        fn must only issue calls of this engine (and torch kernels) on the
+        current stream, reading and writing tensors allocated beforehand and
+        kept alive as long as the graph: a replay reuses the captured device
+        addresses.  With warmup, fn runs once uncaptured first so that the
+        library's scratch is already large enough."""
+        if warmup:
+            fn()
+        torch.cuda.synchronize(self.torch_device)
+        s = stream if stream is not None else torch.cuda.Stream(self.torch_device)
+        L = load_library()
+        handle = ctypes.c_void_p()
+        with torch.cuda.stream(s):
+            self._check(L.shape_graph_begin(self._ctx, _stream(s)))
+            try:
+                fn()
+            except BaseException:
+                L.shape_graph_end(self._ctx, _stream(s), ctypes.byref(handle))
+                if handle:
+                    L.shape_graph_destroy(handle)
+                raise
+            self._check(L.shape_graph_end(self._ctx, _stream(s), ctypes.byref(handle)))
+        return Graph(self, handle)
 
     # -- alignment -------------------------------------------------------------
     def shape_self_overlap(self, M: Molecules, n_samples: int = 2048, seed: int = 0,
@@ -389,3 +465,28 @@ class ShapeAlignFn(torch.autograd.Function):
     def backward(ctx, grad_T):
         (g,) = ctx.saved_tensors
         return grad_T.unsqueeze(-1) * g, None, None, None, None, None, None, None
+
+
+class Graph:
+    """An executable HIP graph of engine calls (see Engine.capture)."""
+
+    def __init__(self, eng: Engine, handle: ctypes.c_void_p):
+        self._eng = eng
+        self._handle = handle
+
+    def replay(self, stream=None):
+        if not self._handle:
+            raise ValueError("graph is closed")
+        self._eng._check(load_library().shape_graph_launch(self._eng._ctx, self._handle,
+                                                           _stream(stream)))
+
+    def close(self):
+        if self._handle:
+            load_library().shape_graph_destroy(self._handle)
+            self._handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

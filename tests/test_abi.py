@@ -53,6 +53,13 @@ def test_null_arguments_are_rejected_without_device():
     assert lib.shape_estimate(None, None, None, 10, 10, 0, None, None) == -1
     assert lib.shape_screen(None, None, None, None, 0, None, None, None) == -1
     assert lib.shape_check_data(None, None) == -1
+    assert lib.shape_screen_tune(None, None, None, None, 0, None, None, None, None) == -1
+    assert lib.shape_screen_set_variant(None, 0) == -1
+    assert lib.shape_screen_get_variant(None) == -1
+    assert lib.shape_graph_begin(None, None) == -1
+    assert lib.shape_graph_end(None, None, None) == -1
+    assert lib.shape_graph_launch(None, None, None) == -1
+    lib.shape_graph_destroy(None)
     lib.shape_destroy(None)
 
 

@@ -1,0 +1,144 @@
+"""Work-granularity autotuning of the screening kernel (every tile variant
+gives bit-identical results) and HIP-graph capture of library calls (replays
+equal the direct calls, also after the inputs change in place)."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2607_20766_amd import molgen
+from paper_2607_20766_amd.engine import (SHAPE_E_UNSUPPORTED, SHAPE_SCREEN_ADAPTIVE,
+                                         SHAPE_SCREEN_FIXED, SHAPE_SCREEN_VARIANTS, Engine,
+                                         ShapeError)
+from tests.gpu_common import require_gpu
+
+pytestmark = pytest.mark.gpu
+
+QUERY_ID = 0xFFFFFF00
+KEYS = ("T", "se_T", "O_ab", "O_aa", "O_bb", "n_used")
+
+
+@pytest.fixture(scope="module")
+def eng():
+    require_gpu()
+    e = Engine(0)
+    yield e
+    e.screen_variant(-1)
+
+
+@pytest.fixture(scope="module")
+def data(eng):
+    q = molgen.molecule(1, 0, 30)
+    L = molgen.library(11, 203, 10, 50, workers=1)  # ragged count, uneven atoms
+    return eng.molecules(q, mol_id=[QUERY_ID]), eng.molecules(L)
+
+
+def _alloc(n, dev):
+    out = {k: torch.empty(n, dtype=torch.float32, device=dev) for k in KEYS[:5]}
+    out["n_used"] = torch.empty(n, dtype=torch.int32, device=dev)
+    return out
+
+
+def _np(out):
+    return {k: v.cpu().numpy().copy() for k, v in out.items()}
+
+
+def _same(a, b):
+    for k in KEYS:
+        assert np.array_equal(a[k], b[k], equal_nan=True), k
+
+
+@pytest.mark.parametrize("kw", [
+    dict(mode=SHAPE_SCREEN_ADAPTIVE, round_per_pair=512, cap_per_pair=8192, tau=0.005),
+    dict(mode=SHAPE_SCREEN_FIXED, n_per_side=4096),
+    dict(mode=SHAPE_SCREEN_FIXED, n_per_side=320),   # 64-sample rounds: partial tiles
+])
+def test_all_variants_bit_identical(eng, data, kw):
+    Q, lib = data
+    print(f"case: tile variants, {kw}", flush=True)
+    ref = None
+    for v in range(SHAPE_SCREEN_VARIANTS):
+        assert eng.screen_variant(v) == v
+        got = _np(eng.shape_screen(Q, lib, seed=3, **kw))
+        if ref is None:
+            ref = got
+        else:
+            _same(ref, got)
+    eng.screen_variant(-1)
+    assert np.all(np.isfinite(ref["T"]))
+
+
+def test_tuner_picks_a_variant(eng, data):
+    Q, lib = data
+    before = _np(eng.shape_screen(Q, lib, mode=SHAPE_SCREEN_ADAPTIVE, seed=5))
+    best, ms = eng.shape_screen_tune(Q, lib, mode=SHAPE_SCREEN_ADAPTIVE, seed=5)
+    assert 0 <= best < SHAPE_SCREEN_VARIANTS
+    assert eng.screen_variant() == best
+    assert all(t > 0 for t in ms) and ms[best] == min(ms)
+    _same(before, _np(eng.shape_screen(Q, lib, mode=SHAPE_SCREEN_ADAPTIVE, seed=5)))
+    with pytest.raises(ShapeError):
+        eng.screen_variant(SHAPE_SCREEN_VARIANTS)
+    eng.screen_variant(-1)
+
+
+def test_graph_replays_match_direct_calls(eng, data):
+    Q, lib = data
+    dev = eng.torch_device
+    n = lib.n_mols
+    out = _alloc(n, dev)
+    other = _alloc(n, dev)
+    kw = dict(mode=SHAPE_SCREEN_ADAPTIVE, round_per_pair=512, cap_per_pair=8192, seed=7)
+
+    def step():
+        eng.shape_screen(Q, lib, out=out, **kw)
+
+    direct = _np(eng.shape_screen(Q, lib, **kw))
+    g = eng.capture(step)
+    try:
+        for rep in range(3):
+            for v in out.values():
+                v.fill_(-1)   # replays must rewrite every output
+            print(f"case: graph replay {rep}", flush=True)
+            g.replay()
+            torch.cuda.synchronize()
+            _same(direct, _np(out))
+            # eager work of the program between replays
+            eng.shape_screen(Q, lib, mode=SHAPE_SCREEN_FIXED, n_per_side=256, seed=1, out=other)
+            torch.cuda.synchronize()
+        # inputs changed in place: rotate the query by a quarter turn about z
+        xyz = Q.xyz.clone()
+        Q.xyz[:, 0], Q.xyz[:, 1] = -xyz[:, 1], xyz[:, 0].clone()
+        g.replay()
+        torch.cuda.synchronize()
+        moved = _np(out)
+        _same(_np(eng.shape_screen(Q, lib, **kw)), moved)
+        assert not np.array_equal(moved["T"], direct["T"])
+        Q.xyz.copy_(xyz)
+        g.replay()
+        torch.cuda.synchronize()
+        _same(direct, _np(out))
+    finally:
+        g.close()
+
+
+def test_capture_refuses_sync_calls_and_growth(eng, data):
+    Q, lib = data
+    big = molgen.library(12, 2 * lib.n_mols + 500, 10, 50, workers=1)
+    Lbig = eng.molecules(big)
+    out = _alloc(Lbig.n_mols, eng.torch_device)
+
+    def grows():
+        eng.shape_screen(Q, Lbig, mode=SHAPE_SCREEN_FIXED, n_per_side=2 ** 20, seed=1, out=out)
+
+    with pytest.raises(ShapeError) as ei:
+        eng.capture(grows, warmup=False)
+    assert ei.value.code == SHAPE_E_UNSUPPORTED
+
+    def syncs():
+        eng.shape_check_data()
+
+    with pytest.raises(ShapeError) as ei:
+        eng.capture(syncs, warmup=False)
+    assert ei.value.code == SHAPE_E_UNSUPPORTED
+    # the engine still works after a discarded capture
+    got = _np(eng.shape_screen(Q, lib, mode=SHAPE_SCREEN_FIXED, n_per_side=256, seed=1))
+    assert np.all(np.isfinite(got["T"]))
