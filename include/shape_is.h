@@ -330,6 +330,20 @@ int shape_pair_features(shape_ctx* ctx, const float* f_q, const float* f_lib,
                         const float* fo_cross, const float* mean, const float* inv_std,
                         void* stream, float* out);
 
+/* Fused surrogate inference (learned triage): the standardised pair
+ * features of shape_pair_features (same arguments) fed through the
+ * 96-256-256-256-2 ReLU network whose parameters are params (device float,
+ * packed W_0, b_0, W_1, b_1, ... with W_l row-major [in][out]), BF16
+ * operands and FP32 accumulation; out: device float [n][2].  Bit-identical
+ * to shape_pair_features followed by one BF16 shape_gemm per layer (ReLU on
+ * the hidden layers); the features and activations stay on chip.  Uses
+ * context scratch for the weights packed to BF16.  Asynchronous.
+ * Errors: SHAPE_E_INVAL, SHAPE_E_RANGE, SHAPE_E_NOMEM, SHAPE_E_HIP. */
+int shape_mlp_infer(shape_ctx* ctx, const float* f_q, const float* f_lib,
+                    const int32_t* qidx, const int32_t* idx, int32_t n,
+                    const float* fo_cross, const float* mean, const float* inv_std,
+                    const float* params, void* stream, float* out);
+
 #define SHAPE_GEMM_BF16 1u  /* round A and B to bfloat16 (else FP32 operands) */
 #define SHAPE_GEMM_RELU 2u  /* epilogue ReLU after the bias */
 
@@ -365,6 +379,19 @@ int shape_adam(shape_ctx* ctx, float* p, const float* g, float* m, float* v, int
  * int32 [k]).  1 <= k <= n.  Asynchronous. */
 int shape_topk(shape_ctx* ctx, const float* score, int32_t n, int32_t k, void* stream,
                int32_t* idx);
+
+/* Seeded sample budgets for surrogate-triaged screening: for i < k, with
+ * r = idx[i] (idx NULL: r = i), the network's standardised log-scale output
+ * s = raw[r*ld + 1] gives the per-sample SE scale sigma = exp(s y_std +
+ * y_mean) and the budget n = (sigma / tau)^2, rounded up to a multiple of
+ * round_per_pair and kept within [round_per_pair, cap_per_pair] (NaN: cap);
+ * n_start: device int32 [k], for shape_screen_params.n_start.  FP64.
+ * raw: device float [*][ld]; idx: device int32 [k] or NULL.  Asynchronous.
+ * Errors: SHAPE_E_INVAL, SHAPE_E_RANGE, SHAPE_E_HIP. */
+int shape_seed_budget(shape_ctx* ctx, const float* raw, int64_t ld, const int32_t* idx,
+                      int32_t k, double y_mean, double y_std, double tau,
+                      int32_t round_per_pair, int32_t cap_per_pair, void* stream,
+                      int32_t* n_start);
 
 /* Kernel timing (measurement support, not part of the method).  While
  * enabled, every call records a pair of HIP events on its stream around its

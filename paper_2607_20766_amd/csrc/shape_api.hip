@@ -28,7 +28,7 @@ enum Slot {
   S_L_ATOM, S_L_SAMP, S_L_Z, S_L_ID, S_L_BAD, S_L_CENTRE,
   S_PARTIALS, S_RESULT, S_QS, S_QF2,
   S_SELF_A, S_SELF_B, S_ADAM_M, S_ADAM_V, S_ADAM_STEP, S_GRAD,
-  S_MSE, S_TOPK_SEL, S_TOPK_HIST, S_TOPK_GT, S_TOPK_EQ, S_COLSUM, S_TUNE,
+  S_MSE, S_TOPK_SEL, S_TOPK_HIST, S_TOPK_GT, S_TOPK_EQ, S_COLSUM, S_TUNE, S_MLP_PACK,
   S_COUNT
 };
 
@@ -697,6 +697,50 @@ int shape_pair_features(shape_ctx* c, const float* f_q, const float* f_lib, cons
   HIP_TRY(c, shape::launch_pair_features(f_q, f_lib, qidx, idx, n, fo_cross, mean, inv_std,
                                          out, (hipStream_t)stream),
           "pair features kernel");
+  return SHAPE_OK;
+}
+
+int shape_mlp_infer(shape_ctx* c, const float* f_q, const float* f_lib, const int32_t* qidx,
+                    const int32_t* idx, int32_t n, const float* fo_cross, const float* mean,
+                    const float* inv_std, const float* params, void* stream, float* out) {
+  if (!c) return SHAPE_E_INVAL;
+  try {
+    if (n < 0) return fail(c, SHAPE_E_RANGE, "n < 0");
+    if (n == 0) return SHAPE_OK;
+    if (!f_q || !f_lib || !mean || !inv_std || !params || !out)
+      return fail(c, SHAPE_E_INVAL, "NULL array");
+    int rc = set_device(c);
+    if (rc) return rc;
+    void* packed;
+    if ((rc = ensure(c, S_MLP_PACK, shape::mlp_pack_bytes(), &packed))) return rc;
+    KernelTimer timer(c, (hipStream_t)stream);
+    HIP_TRY(c, shape::launch_mlp_infer(f_q, f_lib, qidx, idx, n, fo_cross, mean, inv_std, params,
+                                       packed, out, (hipStream_t)stream),
+            "surrogate inference kernel");
+    timer.stop();
+    return SHAPE_OK;
+  } catch (...) {
+    return fail(c, SHAPE_E_HIP, "internal error");
+  }
+}
+
+int shape_seed_budget(shape_ctx* c, const float* raw, int64_t ld, const int32_t* idx, int32_t k,
+                      double y_mean, double y_std, double tau, int32_t round_per_pair,
+                      int32_t cap_per_pair, void* stream, int32_t* n_start) {
+  if (!c) return SHAPE_E_INVAL;
+  if (k < 0) return fail(c, SHAPE_E_RANGE, "k < 0");
+  if (k == 0) return SHAPE_OK;
+  if (!raw || !n_start) return fail(c, SHAPE_E_INVAL, "NULL array");
+  if (ld < 2) return fail(c, SHAPE_E_RANGE, "ld must be >= 2");
+  if (!(tau > 0.0) || !isfinite(tau) || !isfinite(y_mean) || !isfinite(y_std))
+    return fail(c, SHAPE_E_RANGE, "tau, y_mean, y_std must be finite (tau > 0)");
+  if (round_per_pair < 1 || cap_per_pair < round_per_pair)
+    return fail(c, SHAPE_E_RANGE, "need 1 <= round_per_pair <= cap_per_pair");
+  int rc = set_device(c);
+  if (rc) return rc;
+  HIP_TRY(c, shape::launch_seed_budget(raw, ld, idx, k, y_mean, y_std, tau, round_per_pair,
+                                       cap_per_pair, n_start, (hipStream_t)stream),
+          "seed budget kernel");
   return SHAPE_OK;
 }
 

@@ -102,6 +102,14 @@ hipError_t launch_fo_cross(const Prepared& Q, const int* offQ, const float* alph
                            const Prepared& L, const int* offL, const float* alphaL,
                            const int* pairs, int n_pairs, int n_lib, float* out, hipStream_t st);
 hipError_t launch_gemm(const GemmArgs& g, hipStream_t st);
+size_t mlp_pack_bytes();
+hipError_t launch_seed_budget(const float* raw, int64_t ld, const int* idx, int k, double y_mean,
+                              double y_std, double tau, int round, int cap, int* n_start,
+                              hipStream_t st);
+hipError_t launch_mlp_infer(const float* fq, const float* flib, const int* qidx, const int* idx,
+                            int n, const float* fo_cross, const float* mean,
+                            const float* inv_std, const float* params, void* packed,
+                            float* out, hipStream_t st);
 int colsum_chunks(int M);
 hipError_t launch_colsum(const float* A, int M, int N, int64_t lda, float* part, float* out,
                          hipStream_t st);

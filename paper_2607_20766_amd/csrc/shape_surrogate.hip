@@ -189,16 +189,11 @@ __global__ __launch_bounds__(64) void k_fo_cross(Prepared Q, const int* __restri
 // self-overlaps (|.| and product of feature 23) carry the pair's first-order
 // Tanimoto O_qm / (O_qq + O_mm - O_qm) and O_qm itself.  One thread per
 // output element.
-__global__ void k_pair_features(const float* __restrict__ fq, const float* __restrict__ flib,
-                                const int* __restrict__ qidx, const int* __restrict__ idx, int n,
-                                const float* __restrict__ fo_cross,
-                                const float* __restrict__ mean,
-                                const float* __restrict__ inv_std, float* __restrict__ out) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (int64_t)n * 96) return;
-  const int p = (int)(t / 96), j = (int)(t % 96);
-  const int m = idx ? idx[p] : p;
-  const int q = qidx ? qidx[p] : 0;
+__device__ __forceinline__ float pair_feature(const float* __restrict__ fq,
+                                              const float* __restrict__ flib, int q, int m,
+                                              int j, const float* __restrict__ fo_cross, int p,
+                                              const float* __restrict__ mean,
+                                              const float* __restrict__ inv_std) {
   const int k = j % 24;
   const float a = fq[(size_t)q * 24 + k], b = flib[(size_t)m * 24 + k];
   float raw;
@@ -212,7 +207,20 @@ __global__ void k_pair_features(const float* __restrict__ fq, const float* __res
     const float o = fo_cross[p];
     raw = (j < 72) ? o / (a + b - o) : o;
   }
-  out[t] = (raw - mean[j]) * inv_std[j];
+  return (raw - mean[j]) * inv_std[j];
+}
+
+__global__ void k_pair_features(const float* __restrict__ fq, const float* __restrict__ flib,
+                                const int* __restrict__ qidx, const int* __restrict__ idx, int n,
+                                const float* __restrict__ fo_cross,
+                                const float* __restrict__ mean,
+                                const float* __restrict__ inv_std, float* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)n * 96) return;
+  const int p = (int)(t / 96), j = (int)(t % 96);
+  const int m = idx ? idx[p] : p;
+  const int q = qidx ? qidx[p] : 0;
+  out[t] = pair_feature(fq, flib, q, m, j, fo_cross, p, mean, inv_std);
 }
 
 // ---------------------------------------------------------------------------
@@ -400,6 +408,175 @@ __global__ __launch_bounds__(256) void k_gemm_bf16_tiled(GemmArgs g) {
           g.C[(int64_t)m * g.scm + n] = v;
         }
       }
+}
+
+// ---------------------------------------------------------------------------
+// Fused surrogate inference for the 96-256-256-256-2 network: pair features,
+// standardisation and all four layers in one kernel, activations resident in
+// LDS.  The arithmetic is that of shape_pair_features followed by one
+// shape_gemm per layer (BF16 operands rounded to nearest even, FP32
+// accumulation over k in steps of 16 in increasing order, bias then ReLU in
+// FP32), so the outputs agree bit for bit; only the HBM round trips of the
+// features and activations are gone.
+//
+// Weights are first packed to BF16 in MFMA fragment order: for layer l,
+// block (kb, nb) of 16 x 16 holds 64 lanes x 4 values, lane = 16 (k%16 / 4) +
+// n%16, value k%4, so one wave reads a B fragment as 512 contiguous bytes.
+// The last layer's 2 outputs are padded to 16 columns with zeros.
+// ---------------------------------------------------------------------------
+constexpr int kMlpIn = 96, kMlpHid = 256, kMlpOut = 2;
+constexpr int kMlpRows = 128;           // pairs per workgroup
+constexpr int kMlpLd = kMlpHid + 8;     // LDS row stride (bf16 elements)
+
+__host__ __device__ constexpr int mlp_pack_offset(int layer) {
+  // fragment blocks of 16 x 16 (256 bf16) per layer: 6x16, 16x16, 16x16, 16x1
+  return layer == 0 ? 0
+       : layer == 1 ? 6 * 16 * 256
+       : layer == 2 ? (6 * 16 + 16 * 16) * 256
+                    : (6 * 16 + 2 * 16 * 16) * 256;
+}
+constexpr int kMlpPackElems = (6 * 16 + 2 * 16 * 16 + 16) * 256;
+
+__global__ void k_mlp_pack(const float* __restrict__ params, short* __restrict__ packed) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= kMlpPackElems) return;
+  int layer = 3;
+  while (layer > 0 && t < mlp_pack_offset(layer)) --layer;
+  const int local = t - mlp_pack_offset(layer);
+  const int n_in = layer == 0 ? kMlpIn : kMlpHid;
+  const int n_out = layer == 3 ? kMlpOut : kMlpHid;
+  const int nbs = layer == 3 ? 1 : kMlpHid / 16;   // column blocks
+  const int blk = local / 256, within = local % 256;
+  const int kb = blk / nbs, nb = blk % nbs;
+  const int lane = within / 4, e = within % 4;
+  const int k = kb * 16 + 4 * (lane >> 4) + e;
+  const int n = nb * 16 + (lane & 15);
+  // offset of W_layer in the flat W0, b0, W1, b1, ... vector
+  int off = 0;
+  for (int l = 0; l < layer; ++l) {
+    const int i_ = l == 0 ? kMlpIn : kMlpHid;
+    const int o_ = l == 3 ? kMlpOut : kMlpHid;
+    off += i_ * o_ + o_;
+  }
+  const float v = (n < n_out && k < n_in) ? params[off + k * n_out + n] : 0.0f;
+  packed[t] = to_bf16(v);
+}
+
+struct MlpArgs {
+  const float* fq;
+  const float* flib;
+  const int* qidx;
+  const int* idx;
+  int n;
+  const float* fo_cross;
+  const float* mean;
+  const float* inv_std;
+  const v4s* W;        // packed weights (kMlpPackElems bf16)
+  const float* b[4];   // biases of the four layers
+  float* out;          // [n][2]
+};
+
+__global__ __launch_bounds__(256, 2) void k_mlp_infer(MlpArgs a) {
+  __shared__ short H[kMlpRows * kMlpLd];
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+  const int li = lane & 15, lk = lane >> 4;
+  const int row0 = blockIdx.x * kMlpRows;
+  // standardised pair features, rounded to bf16 (rows beyond n are zero)
+  for (int t = tid; t < kMlpRows * kMlpIn; t += 256) {
+    const int r = t / kMlpIn, j = t % kMlpIn;
+    const int p = row0 + r;
+    float v = 0.0f;
+    if (p < a.n) {
+      const int m = a.idx ? a.idx[p] : p;
+      const int q = a.qidx ? a.qidx[p] : 0;
+      v = pair_feature(a.fq, a.flib, q, m, j, a.fo_cross, p, a.mean, a.inv_std);
+    }
+    H[r * kMlpLd + j] = to_bf16(v);
+  }
+  __syncthreads();
+  // three hidden layers: wave w computes all 128 rows x columns [64 w, 64 w + 64)
+#pragma unroll 1
+  for (int l = 0; l < 3; ++l) {
+    const int kbs = (l == 0 ? kMlpIn : kMlpHid) / 16;
+    const v4s* W = a.W + mlp_pack_offset(l) / 4;
+    v4f acc[8][4];
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int kb = 0; kb < kbs; ++kb) {
+      v4s b[4], x[8];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = W[(kb * 16 + wave * 4 + j) * kWave + lane];
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+        x[i] = *reinterpret_cast<const v4s*>(&H[(16 * i + li) * kMlpLd + kb * 16 + 4 * lk]);
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(x[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();  // every wave has read this layer's input
+    const float* bias = a.b[l];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int col = wave * 64 + 16 * j + li;
+      const float bc = bias[col];
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          float v = acc[i][j][r] + bc;
+          v = v > 0.f ? v : 0.f;
+          H[(16 * i + 4 * lk + r) * kMlpLd + col] = to_bf16(v);
+        }
+    }
+    __syncthreads();
+  }
+  // output layer (2 columns, padded to 16): wave w computes rows [32 w, 32 w + 32)
+  {
+    const v4s* W = a.W + mlp_pack_offset(3) / 4;
+    v4f acc[2] = {v4f{0.f, 0.f, 0.f, 0.f}, v4f{0.f, 0.f, 0.f, 0.f}};
+    for (int kb = 0; kb < kMlpHid / 16; ++kb) {
+      const v4s b = W[kb * kWave + lane];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const v4s x = *reinterpret_cast<const v4s*>(
+            &H[(32 * wave + 16 * i + li) * kMlpLd + kb * 16 + 4 * lk]);
+        acc[i] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(x, b, acc[i], 0, 0, 0);
+      }
+    }
+    if (li < kMlpOut) {
+      const float bc = a.b[3][li];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int p = row0 + 32 * wave + 16 * i + 4 * lk + r;
+          if (p < a.n) a.out[(size_t)p * kMlpOut + li] = acc[i][r] + bc;
+        }
+    }
+  }
+}
+
+// Seeded sample budgets of the refined pairs: the network's standardised
+// log-scale output s (column 1 of raw row idx[i]) becomes
+// sigma = exp(s y_std + y_mean), the per-sample SE scale of T, and the budget
+// n = (sigma / tau)^2 is rounded up to whole rounds and kept within
+// [round, cap] (NaN: cap).  FP64.
+__global__ void k_seed_budget(const float* __restrict__ raw, int64_t ld,
+                              const int* __restrict__ idx, int k, double y_mean, double y_std,
+                              double tau, int round, int cap, int* __restrict__ n_start) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= k) return;
+  const int r = idx ? idx[i] : i;
+  const double s = (double)raw[(int64_t)r * ld + 1] * y_std + y_mean;
+  const double n = exp(2.0 * s) / (tau * tau);
+  double b = ceil(n / (double)round) * (double)round;
+  if (!(b <= (double)cap)) b = (double)cap;  // also NaN
+  if (b < (double)round) b = (double)round;
+  n_start[i] = (int)b;
 }
 
 // Column sums of A[M][N] (row stride lda), deterministic: stage 1 sums
@@ -644,6 +821,48 @@ hipError_t launch_gemm(const GemmArgs& g, hipStream_t st) {
     const dim3 grid((unsigned)((g.N + 63) / 64), (unsigned)((g.M + 63) / 64));
     hipLaunchKernelGGL(k_gemm<false>, grid, dim3(256), 0, st, g);
   }
+  return hipGetLastError();
+}
+
+size_t mlp_pack_bytes() { return (size_t)kMlpPackElems * sizeof(short); }
+
+hipError_t launch_mlp_infer(const float* fq, const float* flib, const int* qidx, const int* idx,
+                            int n, const float* fo_cross, const float* mean,
+                            const float* inv_std, const float* params, void* packed,
+                            float* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_mlp_pack, dim3((kMlpPackElems + 255) / 256), dim3(256), 0, st, params,
+                     (short*)packed);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || n == 0) return e;
+  MlpArgs a;
+  a.fq = fq;
+  a.flib = flib;
+  a.qidx = qidx;
+  a.idx = idx;
+  a.n = n;
+  a.fo_cross = fo_cross;
+  a.mean = mean;
+  a.inv_std = inv_std;
+  a.W = (const v4s*)packed;
+  int off = 0;
+  for (int l = 0; l < 4; ++l) {
+    const int i_ = l == 0 ? kMlpIn : kMlpHid;
+    const int o_ = l == 3 ? kMlpOut : kMlpHid;
+    off += i_ * o_;
+    a.b[l] = params + off;
+    off += o_;
+  }
+  a.out = out;
+  hipLaunchKernelGGL(k_mlp_infer, dim3((unsigned)((n + kMlpRows - 1) / kMlpRows)), dim3(256), 0,
+                     st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_seed_budget(const float* raw, int64_t ld, const int* idx, int k, double y_mean,
+                              double y_std, double tau, int round, int cap, int* n_start,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(k_seed_budget, dim3((k + 255) / 256), dim3(256), 0, st, raw, ld, idx, k,
+                     y_mean, y_std, tau, round, cap, n_start);
   return hipGetLastError();
 }
 

@@ -21,6 +21,9 @@ SHAPE_SCREEN_FIXED = 0
 SHAPE_SCREEN_ADAPTIVE = 1
 SHAPE_MAX_ATOMS = 256
 SHAPE_SCREEN_VARIANTS = 8
+# (side-A, side-B) points per lane of each screening-kernel tile variant, in
+# the library's variant order (names the kernel instance in profiles)
+SCREEN_VARIANT_SHAPES = ((4, 2), (2, 2), (4, 1), (4, 4), (8, 2), (2, 1), (8, 4), (2, 4))
 SHAPE_E_UNSUPPORTED = -5
 
 # Eq. occ width convention of the synthetic workloads: a Gaussian height
@@ -114,6 +117,7 @@ def load_library():
                                   vp, i32, i32, ctypes.c_float, u64, vp, vp, vp]
         L.shape_features.argtypes = [vp, ctypes.POINTER(ShapeMols), vp, vp]
         L.shape_pair_features.argtypes = [vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp]
+        L.shape_mlp_infer.argtypes = [vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp]
         L.shape_fo_overlap.argtypes = [vp, ctypes.POINTER(ShapeMols), ctypes.POINTER(ShapeMols),
                                        vp, i32, vp, vp]
         L.shape_gemm.argtypes = [vp, i32, i32, i32, vp, i64, i64, vp, i64, i64, vp, i64, vp, vp,
@@ -123,6 +127,7 @@ def load_library():
         L.shape_adam.argtypes = [vp, vp, vp, vp, vp, i64, vp, ctypes.c_float, ctypes.c_float,
                                  ctypes.c_float, ctypes.c_float, vp]
         L.shape_topk.argtypes = [vp, vp, i32, i32, vp, vp]
+        L.shape_seed_budget.argtypes = [vp, vp, i64, vp, i32, d, d, d, i32, i32, vp, vp]
         L.shape_timing_enable.argtypes = [vp, ctypes.c_int]
         L.shape_timing_read.argtypes = [vp, ctypes.POINTER(d), ctypes.POINTER(i64), ctypes.c_int]
         _lib = L
@@ -366,8 +371,9 @@ class Engine:
         return T, best
 
     # -- learned triage ----------------------------------------------------------
-    def shape_features(self, M: Molecules, stream=None) -> torch.Tensor:
-        out = torch.empty(M.n_mols, 24, dtype=torch.float32, device=self.torch_device)
+    def shape_features(self, M: Molecules, out=None, stream=None) -> torch.Tensor:
+        if out is None:
+            out = torch.empty(M.n_mols, 24, dtype=torch.float32, device=self.torch_device)
         m = M.c_struct()
         self._check(load_library().shape_features(self._ctx, ctypes.byref(m), _stream(stream),
                                                   _ptr(out)))
@@ -403,6 +409,24 @@ class Engine:
             int(n), _ptr(fo_cross), _ptr(mean), _ptr(inv_std), _stream(stream), _ptr(out)))
         return out
 
+    def shape_mlp_infer(self, f_q, f_lib, mean, inv_std, params, idx=None, qidx=None, n=None,
+                        fo_cross=None, out=None, stream=None) -> torch.Tensor:
+        """Fused pair features + 96-256-256-256-2 network (BF16): [n, 2]."""
+        if idx is not None:
+            idx = idx.to(torch.int32).contiguous()
+            n = idx.numel()
+        elif n is None:
+            n = f_lib.shape[0]
+        if qidx is not None:
+            qidx = qidx.to(torch.int32).contiguous()
+        if out is None:
+            out = torch.empty(n, 2, dtype=torch.float32, device=self.torch_device)
+        self._check(load_library().shape_mlp_infer(
+            self._ctx, _ptr(f_q.contiguous()), _ptr(f_lib.contiguous()), _ptr(qidx), _ptr(idx),
+            int(n), _ptr(fo_cross), _ptr(mean), _ptr(inv_std), _ptr(params), _stream(stream),
+            _ptr(out)))
+        return out
+
     def shape_gemm(self, M, N, K, A, sam, sak, B, sbk, sbn, C, scm, bias=None, gate=None, sgm=0,
                    bf16=True, relu=False, stream=None):
         flags = (1 if bf16 else 0) | (2 if relu else 0)
@@ -430,6 +454,24 @@ class Engine:
             out = torch.empty(int(k), dtype=torch.int32, device=self.torch_device)
         self._check(load_library().shape_topk(self._ctx, _ptr(score.contiguous()),
                                               score.numel(), int(k), _stream(stream), _ptr(out)))
+        return out
+
+    def shape_seed_budget(self, raw, y_mean, y_std, tau, round_per_pair, cap_per_pair, idx=None,
+                          k=None, out=None, stream=None) -> torch.Tensor:
+        """Sample budgets n = (exp(raw[:, 1] y_std + y_mean) / tau)^2 in whole
+        rounds within [round, cap], for rows idx (device int32 [k])."""
+        if idx is not None:
+            idx = idx.to(torch.int32).contiguous()
+            k = idx.numel()
+        elif k is None:
+            k = raw.shape[0]
+        if out is None:
+            out = torch.empty(int(k), dtype=torch.int32, device=self.torch_device)
+        assert raw.stride(1) == 1 and raw.shape[1] >= 2
+        self._check(load_library().shape_seed_budget(
+            self._ctx, _ptr(raw), int(raw.stride(0)), _ptr(idx), int(k), float(y_mean),
+            float(y_std), float(tau), int(round_per_pair), int(cap_per_pair), _stream(stream),
+            _ptr(out)))
         return out
 
     def shape_timing_enable(self, enable: bool = True):

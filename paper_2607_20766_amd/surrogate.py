@@ -239,12 +239,19 @@ class Triage:
                 log(f"epoch {ep}: loss {history[-1]:.4f}")
         return history
 
-    def predict_raw(self, f_q, f_lib, fo=None, chunk: int = 65536):
+    def predict_raw(self, f_q, f_lib, fo=None, chunk: int = 65536, fused: bool = True,
+                    out=None):
         """Standardised network outputs [n, 2] on the device for the query
-        against every library row (fo: first-order cross-overlaps, device)."""
+        against every library row (fo: first-order cross-overlaps, device).
+        fused: one kernel for features and all layers (BF16 network of the
+        standard width); otherwise features, then one GEMM per layer."""
         dev = self.eng.torch_device
         n = f_lib.shape[0]
-        out = torch.empty(n, 2, dtype=torch.float32, device=dev)
+        if out is None:
+            out = torch.empty(n, 2, dtype=torch.float32, device=dev)
+        if fused and self.mlp.bf16 and self.mlp.width == WIDTH:
+            return self.eng.shape_mlp_infer(f_q, f_lib, self.mean, self.inv_std,
+                                            self.mlp.params, n=n, fo_cross=fo, out=out)
         xb = torch.empty(min(chunk, n), 96, dtype=torch.float32, device=dev)
         for s in range(0, n, chunk):
             e = min(s + chunk, n)
@@ -261,28 +268,47 @@ class Triage:
 
     # -- screening ---------------------------------------------------------------
     def seed_budget(self, log_scale: np.ndarray) -> np.ndarray:
-        """n = (sigma / tau)^2 samples per pair, in whole rounds within
-        [round, cap]."""
+        """Host statement of the budget rule that shape_seed_budget applies on
+        the device (used to check it): n = (sigma / tau)^2 samples per pair,
+        in whole rounds within [round, cap]."""
         n = np.exp(2.0 * log_scale) / self.tau ** 2
         n = np.ceil(n / self.round_per_pair) * self.round_per_pair
         return np.clip(n, self.round_per_pair, self.cap_per_pair).astype(np.int32)
 
+    def screen_buffers(self, n: int, frac: float = 0.05) -> dict:
+        """Device buffers of one screen of an n-molecule library (for calls
+        that must not allocate, e.g. inside a captured graph)."""
+        dev = self.eng.torch_device
+        k = max(1, int(round(frac * n)))
+        f32 = dict(dtype=torch.float32, device=dev)
+        out = {key: torch.empty(k, **f32) for key in ("T", "se_T", "O_ab", "O_aa", "O_bb")}
+        out["n_used"] = torch.empty(k, dtype=torch.int32, device=dev)
+        return {"n": n, "k": k, "fo": torch.empty(n, **f32) if self.use_fo else None,
+                "raw": torch.empty(n, 2, **f32), "score": torch.empty(n, **f32),
+                "top": torch.empty(k, dtype=torch.int32, device=dev),
+                "budget": torch.empty(k, dtype=torch.int32, device=dev), "out": out}
+
     def screen(self, query: Molecules, lib: Molecules, f_q, f_lib, frac: float = 0.05,
-               seed: int = 0):
+               seed: int = 0, bufs: dict | None = None):
         """Rank the library by predicted T, refine the top `frac` by adaptive
         IS with budgets seeded from the predicted SE scale.  Returns
         (refined library indices [k] (device, increasing), IS outputs, raw
-        network outputs [n, 2])."""
+        network outputs [n, 2]).  Every step runs on the device without a
+        host round trip; bufs (from screen_buffers) receives the results."""
         n = lib.n_mols
-        k = max(1, int(round(frac * n)))
-        raw = self.predict_raw(f_q, f_lib, self.fo_overlap(query, lib))
-        score = torch.empty(n, dtype=torch.float32, device=raw.device)
-        score.copy_(raw[:, 0])
-        top = self.eng.shape_topk(score, k)
-        sel_raw = torch.index_select(raw, 0, top.long()).cpu().numpy()
-        budget = torch.from_numpy(self.seed_budget(self.to_labels(sel_raw)[1])).to(raw.device)
+        if bufs is None:
+            bufs = self.screen_buffers(n, frac)
+        assert bufs["n"] == n
+        k = bufs["k"]
+        fo = (self.eng.shape_fo_overlap(query, lib, out=bufs["fo"]) if self.use_fo else None)
+        raw = self.predict_raw(f_q, f_lib, fo, out=bufs["raw"])
+        bufs["score"].copy_(raw[:, 0])
+        top = self.eng.shape_topk(bufs["score"], k, out=bufs["top"])
+        budget = self.eng.shape_seed_budget(raw, self.y_mean[1], self.y_std[1], self.tau,
+                                            self.round_per_pair, self.cap_per_pair, idx=top,
+                                            out=bufs["budget"])
         out = self.eng.shape_screen(query, lib, mode=SHAPE_SCREEN_ADAPTIVE, pairs=top,
                                     round_per_pair=self.round_per_pair,
                                     cap_per_pair=self.cap_per_pair, tau=self.tau, seed=seed,
-                                    n_start=budget)
+                                    n_start=budget, out=bufs["out"])
         return top, out, raw

@@ -196,3 +196,60 @@ def test_triage_gain(eng):
     se = out["se_T"].cpu().numpy()
     n_used = out["n_used"].cpu().numpy()
     assert np.all((se <= 0.005 * (1 + 1e-6)) | (n_used == 65536))
+
+
+@pytest.mark.parametrize("n,with_fo,with_idx", [(1000, True, False), (300, False, True),
+                                                (128, True, True), (1, False, False)])
+def test_fused_inference_matches_layers(eng, n, with_fo, with_idx):
+    """shape_mlp_infer equals shape_pair_features + one BF16 GEMM per layer,
+    bit for bit (same roundings, same accumulation order)."""
+    rng = np.random.default_rng(n)
+    n_lib = n + 37
+    f_q = rng.normal(size=(3, 24)).astype(np.float32)
+    f_lib = rng.normal(size=(n_lib, 24)).astype(np.float32)
+    f_q[:, 23] = rng.uniform(50, 100, 3)
+    f_lib[:, 23] = rng.uniform(50, 100, n_lib)
+    mean = rng.normal(size=96).astype(np.float32)
+    inv_std = rng.uniform(0.5, 2.0, 96).astype(np.float32)
+    params = init_params(7)
+    params[params.size // 2:] *= 1.5   # nonzero biases somewhere
+    params = params + rng.normal(scale=0.01, size=params.size).astype(np.float32)
+    d = lambda x: torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    fq, fl, mu, isd = d(f_q), d(f_lib), d(mean), d(inv_std)
+    idx = d(rng.integers(0, n_lib, n).astype(np.int32)) if with_idx else None
+    qidx = d(rng.integers(0, 3, n).astype(np.int32)) if with_idx else None
+    fo = d(rng.uniform(1, 40, n).astype(np.float32)) if with_fo else None
+    print(f"case: fused inference n={n} fo={with_fo} idx={with_idx}", flush=True)
+    x = eng.shape_pair_features(fq, fl, mu, isd, idx=idx, qidx=qidx, n=n, fo_cross=fo)
+    net = MLP(eng, params, bf16=True)
+    y_layers = net.forward(x).clone()
+    y_fused = eng.shape_mlp_infer(fq, fl, mu, isd, net.params, idx=idx, qidx=qidx, n=n,
+                                  fo_cross=fo)
+    torch.cuda.synchronize()
+    assert y_fused.shape == (n, 2)
+    assert torch.equal(y_fused, y_layers)
+    assert torch.isfinite(y_fused).all()
+
+
+def test_seed_budget_matches_host_rule(eng):
+    tr = Triage(eng, seed=0)
+    tr.y_mean = np.array([0.3, -1.7])
+    tr.y_std = np.array([0.2, 0.8])
+    rng = np.random.default_rng(9)
+    raw = rng.normal(scale=2.0, size=(5000, 2)).astype(np.float32)
+    raw[17, 1] = np.nan
+    raw[18, 1] = 1e30
+    raw[19, 1] = -1e30
+    idx = rng.permutation(5000)[:1234].astype(np.int32)
+    draw = torch.from_numpy(raw).cuda()
+    got = eng.shape_seed_budget(draw, tr.y_mean[1], tr.y_std[1], tr.tau, tr.round_per_pair,
+                                tr.cap_per_pair, idx=torch.from_numpy(idx).cuda())
+    ls = raw[idx].astype(np.float64)[:, 1] * tr.y_std[1] + tr.y_mean[1]
+    with np.errstate(over="ignore", invalid="ignore"):
+        want = tr.seed_budget(ls)
+    want[np.isnan(ls)] = tr.cap_per_pair
+    assert np.array_equal(got.cpu().numpy(), want)
+    full = eng.shape_seed_budget(draw, tr.y_mean[1], tr.y_std[1], tr.tau, tr.round_per_pair,
+                                 tr.cap_per_pair).cpu().numpy()
+    assert full[17] == tr.cap_per_pair and full[18] == tr.cap_per_pair
+    assert full[19] == tr.round_per_pair

@@ -142,3 +142,41 @@ def test_capture_refuses_sync_calls_and_growth(eng, data):
     # the engine still works after a discarded capture
     got = _np(eng.shape_screen(Q, lib, mode=SHAPE_SCREEN_FIXED, n_per_side=256, seed=1))
     assert np.all(np.isfinite(got["T"]))
+
+
+def test_triage_screen_as_graph(eng, data):
+    """The whole surrogate-triaged screen (features, first-order overlaps,
+    fused network, top-k, seeded budgets, adaptive IS) replays as one graph."""
+    from paper_2607_20766_amd.surrogate import Triage
+    Q, lib = data
+    tr = Triage(eng, seed=0)
+    n = lib.n_mols
+    dev = eng.torch_device
+    f_q = torch.empty(1, 24, dtype=torch.float32, device=dev)
+    f_l = torch.empty(n, 24, dtype=torch.float32, device=dev)
+    bufs = tr.screen_buffers(n, frac=0.1)
+
+    def step():
+        eng.shape_features(Q, out=f_q)
+        eng.shape_features(lib, out=f_l)
+        tr.screen(Q, lib, f_q, f_l, frac=0.1, bufs=bufs)
+
+    top, out, raw = tr.screen(Q, lib, eng.shape_features(Q), eng.shape_features(lib), frac=0.1)
+    ref = (top.cpu().numpy(), _np(out), raw.cpu().numpy())
+    g = eng.capture(step)
+    try:
+        for rep in range(3):
+            bufs["top"].fill_(-1)
+            bufs["raw"].fill_(0)
+            for v in bufs["out"].values():
+                v.fill_(-1)
+            print(f"case: triage graph replay {rep}", flush=True)
+            g.replay()
+            torch.cuda.synchronize()
+            assert np.array_equal(bufs["top"].cpu().numpy(), ref[0])
+            assert np.array_equal(bufs["raw"].cpu().numpy(), ref[2])
+            _same(ref[1], _np(bufs["out"]))
+            eng.shape_screen(Q, lib, mode=SHAPE_SCREEN_FIXED, n_per_side=256, seed=2)
+            torch.cuda.synchronize()
+    finally:
+        g.close()
