@@ -188,10 +188,13 @@ def bench_triage(eng, n_lib, n_queries=256, n_train_lib=3907, epochs=10):
 
     def run_triage():
         # library features are recomputed each time (query-independent, but
-        # counted here)
+        # counted here); each molecule set is prepared once per screen
+        eng.prepare_cache(True)
         eng.shape_features(Q, out=f_qt)
         eng.shape_features(lib, out=f_l)
-        return tr.screen(Q, lib, f_qt, f_l, frac=0.05, bufs=bufs)
+        r = tr.screen(Q, lib, f_qt, f_l, frac=0.05, bufs=bufs)
+        eng.prepare_cache(False)
+        return r
 
     def run_plain():
         return eng.shape_screen(Q, lib, mode=SHAPE_SCREEN_ADAPTIVE, round_per_pair=ROUND,

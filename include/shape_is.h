@@ -197,6 +197,21 @@ int shape_screen(shape_ctx* ctx, const shape_mols* query, const shape_mols* lib,
  * (SHAPE_OK); clears the flag. */
 int shape_check_data(shape_ctx* ctx, void* stream);
 
+/* Reuse of molecule preparation across calls (a pipeline that hands the
+ * same molecule set to several calls, e.g. shape_features, shape_fo_overlap
+ * and shape_screen of one library).  Every call prepares its molecule sets
+ * (mixture weights, sampling thresholds, frames) into context scratch, one
+ * set on the query side and one on the library side.  While the cache is
+ * enabled, a set whose arrays (device pointers) and sizes equal those of the
+ * set last prepared on the same side is not prepared again.  The caller
+ * guarantees that the arrays are not written while the cache is enabled;
+ * shape_prepare_cache(ctx, 1) also forgets earlier preparations, so a
+ * pipeline that starts with it prepares each set once (also when captured in
+ * a graph: the replay repeats that one preparation).  enable = 0 turns the
+ * reuse off.  Invalid molecules are still reported by shape_check_data.
+ * Errors: SHAPE_E_INVAL. */
+int shape_prepare_cache(shape_ctx* ctx, int enable);
+
 /* Work-granularity autotuning of the screening kernel (adaptive batching,
  * section "Confidence-bounded screening": the rounds and the stopping rule
  * are fixed by the method; only how many points a lane evaluates per atom

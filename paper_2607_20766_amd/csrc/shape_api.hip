@@ -28,11 +28,25 @@ enum Slot {
   S_L_ATOM, S_L_SAMP, S_L_Z, S_L_ID, S_L_BAD, S_L_CENTRE,
   S_PARTIALS, S_RESULT, S_QS, S_QF2,
   S_SELF_A, S_SELF_B, S_ADAM_M, S_ADAM_V, S_ADAM_STEP, S_GRAD,
-  S_MSE, S_TOPK_SEL, S_TOPK_HIST, S_TOPK_GT, S_TOPK_EQ, S_COLSUM, S_TUNE, S_MLP_PACK,
+  S_MSE, S_TOPK_SEL, S_TOPK_HIST, S_TOPK_GT, S_TOPK_EQ, S_COLSUM, S_TUNE, S_MLP_PACK, S_FEAT_MOM,
   S_COUNT
 };
 
 }  // namespace
+
+// Identity of the molecule set last prepared into one family of slots.
+struct PrepKey {
+  bool valid = false;
+  const void *off = nullptr, *xyz = nullptr, *alpha = nullptr, *id = nullptr;
+  int64_t n_atoms = 0;
+  int32_t n_mols = 0, max_atoms = 0;
+  shape::Prepared P{};
+  bool same(const shape_mols* m) const {
+    return valid && off == m->atom_offset && xyz == m->xyz && alpha == m->alpha &&
+           id == m->mol_id && n_atoms == m->n_atoms && n_mols == m->n_mols &&
+           max_atoms == m->max_atoms;
+  }
+};
 
 struct shape_ctx {
   int device = -1;
@@ -40,7 +54,9 @@ struct shape_ctx {
   size_t lds_per_block = 0;
   std::string err;
   Buffer buf[S_COUNT];
-  int* flag = nullptr;  // invalid-data flag (device int)
+  int* flag = nullptr;  // device int[3]: invalid-data flag, then one per slot family
+  bool prep_cache = false;  // reuse the last preparation of an unchanged set
+  PrepKey prepared[2];      // query-side and library-side slot families
   bool timing = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
   int screen_variant = -1;        // -1: default tile shape
@@ -136,6 +152,14 @@ int check_mols(shape_ctx* c, const shape_mols* m, const char* name, bool single)
 // Prepare a molecule set into the query (q = true) or library slots.
 int prepare(shape_ctx* c, const shape_mols* m, bool q, hipStream_t st, shape::Prepared* P) {
   const int base = q ? S_Q_ATOM : S_L_ATOM;
+  PrepKey& key = c->prepared[q ? 0 : 1];
+  int* set_flag = c->flag + (q ? 1 : 2);
+  if (c->prep_cache && key.same(m)) {
+    *P = key.P;
+    HIP_TRY(c, shape::launch_flag_or(c->flag, set_flag, st), "flag kernel");
+    return SHAPE_OK;
+  }
+  key.valid = false;
   void* p[6];
   int rc;
   const size_t na = (size_t)m->n_atoms, nm = (size_t)m->n_mols;
@@ -153,7 +177,20 @@ int prepare(shape_ctx* c, const shape_mols* m, bool q, hipStream_t st, shape::Pr
   P->centre = (float4*)p[5];
   shape::MolsDev in{m->n_mols, m->max_atoms, m->n_atoms, m->atom_offset, m->xyz, m->alpha,
                     m->mol_id};
-  HIP_TRY(c, shape::launch_prepare(in, *P, c->flag, st), "prepare kernel");
+  if (c->prep_cache) HIP_TRY(c, shape::launch_fill_int(set_flag, 1, 0, st), "flag reset");
+  HIP_TRY(c, shape::launch_prepare(in, *P, c->flag, c->prep_cache ? set_flag : nullptr, st),
+          "prepare kernel");
+  if (c->prep_cache) {
+    key.off = m->atom_offset;
+    key.xyz = m->xyz;
+    key.alpha = m->alpha;
+    key.id = m->mol_id;
+    key.n_atoms = m->n_atoms;
+    key.n_mols = m->n_mols;
+    key.max_atoms = m->max_atoms;
+    key.P = *P;
+    key.valid = true;
+  }
   return SHAPE_OK;
 }
 
@@ -295,8 +332,8 @@ int shape_create(shape_ctx** out, int device) {
   c->n_cu = prop.multiProcessorCount;
   c->lds_per_block = prop.sharedMemPerBlock;
   e = hipSetDevice(device);
-  if (e == hipSuccess) e = hipMalloc(&c->flag, sizeof(int));
-  if (e == hipSuccess) e = hipMemset(c->flag, 0, sizeof(int));
+  if (e == hipSuccess) e = hipMalloc(&c->flag, 3 * sizeof(int));
+  if (e == hipSuccess) e = hipMemset(c->flag, 0, 3 * sizeof(int));
   if (e != hipSuccess) {
     delete c;
     return fail(nullptr, SHAPE_E_HIP, "context set-up: %s", hipGetErrorString(e));
@@ -463,6 +500,14 @@ int shape_screen_tune(shape_ctx* c, const shape_mols* query, const shape_mols* l
   } catch (...) {
     return fail(c, SHAPE_E_HIP, "internal error");
   }
+}
+
+int shape_prepare_cache(shape_ctx* c, int enable) {
+  if (!c) return SHAPE_E_INVAL;
+  c->prep_cache = enable != 0;
+  c->prepared[0].valid = false;
+  c->prepared[1].valid = false;
+  return SHAPE_OK;
 }
 
 int shape_screen_set_variant(shape_ctx* c, int32_t variant) {
@@ -649,8 +694,11 @@ int shape_features(shape_ctx* c, const shape_mols* M, void* stream, float* out) 
     hipStream_t st = (hipStream_t)stream;
     shape::Prepared P;
     if ((rc = prepare(c, M, false, st, &P))) return rc;
+    void* mom;
+    if ((rc = ensure(c, S_FEAT_MOM, (size_t)M->n_mols * 6 * sizeof(float), &mom))) return rc;
     KernelTimer timer(c, st);
-    HIP_TRY(c, shape::launch_features(P, M->atom_offset, M->alpha, M->n_mols, out, st),
+    HIP_TRY(c, shape::launch_features(P, M->atom_offset, M->alpha, M->n_mols, out, (float*)mom,
+                                      st),
             "features kernel");
     timer.stop();
     return SHAPE_OK;

@@ -32,7 +32,8 @@ __global__ void k_alpha_from_radius(const float* __restrict__ R, int64_t n, doub
 // ---------------------------------------------------------------------------
 constexpr int kPrepWaves = 4;
 
-__global__ __launch_bounds__(256) void k_prepare(MolsDev in, Prepared out, int* __restrict__ flag) {
+__global__ __launch_bounds__(256) void k_prepare(MolsDev in, Prepared out, int* __restrict__ flag,
+                                                 int* __restrict__ set_flag) {
   // FP64 without contraction: Z and the thresholds are the values the plain
   // expressions define, bit for bit.
 #pragma clang fp contract(off)
@@ -70,6 +71,7 @@ __global__ __launch_bounds__(256) void k_prepare(MolsDev in, Prepared out, int* 
       out.Z[m] = __builtin_nan("");
       out.centre[m] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
       atomicOr(flag, 1);
+      if (set_flag) atomicOr(set_flag, 1);
     }
     return;
   }
@@ -111,6 +113,12 @@ __global__ __launch_bounds__(256) void k_prepare(MolsDev in, Prepared out, int* 
     }
     out.samp[a0 + i] = smp;
   }
+}
+
+// Re-raises the invalid-data flag for a molecule set reused from an earlier
+// preparation that found invalid molecules.
+__global__ void k_flag_or(int* __restrict__ flag, const int* __restrict__ set_flag) {
+  if (threadIdx.x == 0 && *set_flag) atomicOr(flag, 1);
 }
 
 __global__ void k_fill_int(int* __restrict__ p, int n, int v) {
@@ -538,9 +546,15 @@ hipError_t launch_alpha_from_radius(const float* R, int64_t n, double kappa, dou
   return hipGetLastError();
 }
 
-hipError_t launch_prepare(const MolsDev& in, const Prepared& out, int* flag, hipStream_t st) {
+hipError_t launch_prepare(const MolsDev& in, const Prepared& out, int* flag, int* set_flag,
+                          hipStream_t st) {
   const int blocks = (in.n_mols + kPrepWaves - 1) / kPrepWaves;
-  hipLaunchKernelGGL(k_prepare, dim3(blocks), dim3(256), 0, st, in, out, flag);
+  hipLaunchKernelGGL(k_prepare, dim3(blocks), dim3(256), 0, st, in, out, flag, set_flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_flag_or(int* flag, const int* set_flag, hipStream_t st) {
+  hipLaunchKernelGGL(k_flag_or, dim3(1), dim3(64), 0, st, flag, set_flag);
   return hipGetLastError();
 }
 

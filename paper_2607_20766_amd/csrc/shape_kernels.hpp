@@ -94,7 +94,7 @@ struct GemmArgs {
 };
 
 hipError_t launch_features(const Prepared& M, const int* off, const float* alpha, int n_mols,
-                           float* out, hipStream_t st);
+                           float* out, float* mom, hipStream_t st);
 hipError_t launch_pair_features(const float* fq, const float* flib, const int* qidx,
                                 const int* idx, int n, const float* fo_cross, const float* mean,
                                 const float* inv_std, float* out, hipStream_t st);
@@ -133,7 +133,9 @@ hipError_t launch_best_start(const float* T, int n_pairs, int n_starts, int* bes
 
 hipError_t launch_alpha_from_radius(const float* R, int64_t n, double kappa, double lambda,
                                     float* alpha, hipStream_t st);
-hipError_t launch_prepare(const MolsDev& in, const Prepared& out, int* flag, hipStream_t st);
+hipError_t launch_prepare(const MolsDev& in, const Prepared& out, int* flag, int* set_flag,
+                          hipStream_t st);
+hipError_t launch_flag_or(int* flag, const int* set_flag, hipStream_t st);
 hipError_t launch_fill_int(int* p, int n, int v, hipStream_t st);
 int est_blocks(int64_t n);
 hipError_t launch_estimate(const Prepared& A, const Prepared& B, const int* offA,

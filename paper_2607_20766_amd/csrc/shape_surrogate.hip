@@ -62,7 +62,8 @@ __device__ __forceinline__ float fo_term(float a, float b, float d2) {
 
 __global__ __launch_bounds__(64) void k_features(Prepared M, const int* __restrict__ off,
                                                  const float* __restrict__ alpha, int n_mols,
-                                                 float* __restrict__ out) {
+                                                 float* __restrict__ out,
+                                                 float* __restrict__ mom) {
   __shared__ float4 sC[SHAPE_MAX_ATOMS];  // x, y, z, alpha
   const int mol = blockIdx.x;
   const int lane = threadIdx.x;
@@ -136,12 +137,27 @@ __global__ __launch_bounds__(64) void k_features(Prepared M, const int* __restri
   const double fo_sum = wave_sum((double)fo);
   if (lane < 16) f[lane] = (float)hist_mine;
   if (lane < 4) f[19 + lane] = (float)cls_mine;
+  // the covariance goes to k_features_eigen, which diagonalises one matrix
+  // per lane rather than one per wave
+  float* mm = mom + (size_t)mol * 6;
   if (lane == 0) {
-    double ev[3];
-    sym3_eigen_desc(sxx, syy, szz, sxy, sxz, syz, ev);
-    for (int k = 0; k < 3; ++k) f[16 + k] = (float)sqrt(ev[k] > 0.0 ? ev[k] : 0.0);
+    mm[0] = sxx; mm[1] = syy; mm[2] = szz;
+    mm[3] = sxy; mm[4] = sxz; mm[5] = syz;
     f[23] = (float)fo_sum;
   }
+}
+
+// Features [16..18]: square roots of the descending eigenvalues of each
+// molecule's mixture covariance (FP64 closed form), one molecule per thread.
+__global__ void k_features_eigen(const Prepared M, int n_mols, const float* __restrict__ mom,
+                                 float* __restrict__ out) {
+  const int mol = blockIdx.x * blockDim.x + threadIdx.x;
+  if (mol >= n_mols || M.bad[mol] != 0) return;
+  const float* mm = mom + (size_t)mol * 6;
+  double ev[3];
+  sym3_eigen_desc(mm[0], mm[1], mm[2], mm[3], mm[4], mm[5], ev);
+  float* f = out + (size_t)mol * 24;
+  for (int k = 0; k < 3; ++k) f[16 + k] = (float)sqrt(ev[k] > 0.0 ? ev[k] : 0.0);
 }
 
 // First-order cross-overlap of (query, library molecule) pairs at their
@@ -783,9 +799,13 @@ __global__ __launch_bounds__(256) void k_select_write(const float* __restrict__ 
 // Launchers.
 // ---------------------------------------------------------------------------
 hipError_t launch_features(const Prepared& M, const int* off, const float* alpha, int n_mols,
-                           float* out, hipStream_t st) {
+                           float* out, float* mom, hipStream_t st) {
   hipLaunchKernelGGL(k_features, dim3((unsigned)n_mols), dim3(kWave), 0, st, M, off, alpha,
-                     n_mols, out);
+                     n_mols, out, mom);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_features_eigen, dim3((unsigned)((n_mols + 255) / 256)), dim3(256), 0, st,
+                     M, n_mols, mom, out);
   return hipGetLastError();
 }
 

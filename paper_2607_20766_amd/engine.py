@@ -100,6 +100,7 @@ def load_library():
         L.shape_screen_tune.argtypes = [vp, ctypes.POINTER(ShapeMols),
                                         ctypes.POINTER(ShapeMols), vp, i32,
                                         ctypes.POINTER(ShapeScreenParams), vp, vp, vp]
+        L.shape_prepare_cache.argtypes = [vp, ctypes.c_int]
         L.shape_screen_set_variant.argtypes = [vp, i32]
         L.shape_screen_get_variant.argtypes = [vp]
         L.shape_screen_get_variant.restype = i32
@@ -289,6 +290,11 @@ class Engine:
             self._ctx, ctypes.byref(q), ctypes.byref(l_), _ptr(pairs), n, ctypes.byref(prm),
             _stream(stream), ms, ctypes.byref(best)))
         return int(best.value), [float(x) for x in ms]
+
+    def prepare_cache(self, enable: bool = True):
+        """Reuse the preparation of an unchanged molecule set across calls
+        (see shape_prepare_cache); enabling also forgets earlier ones."""
+        self._check(load_library().shape_prepare_cache(self._ctx, int(enable)))
 
     def screen_variant(self, variant: int | None = None) -> int:
         """Select the screening tile variant (-1 = default) if given; return

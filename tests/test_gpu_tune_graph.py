@@ -157,9 +157,11 @@ def test_triage_screen_as_graph(eng, data):
     bufs = tr.screen_buffers(n, frac=0.1)
 
     def step():
+        eng.prepare_cache(True)   # each set is prepared once per screen
         eng.shape_features(Q, out=f_q)
         eng.shape_features(lib, out=f_l)
         tr.screen(Q, lib, f_q, f_l, frac=0.1, bufs=bufs)
+        eng.prepare_cache(False)
 
     top, out, raw = tr.screen(Q, lib, eng.shape_features(Q), eng.shape_features(lib), frac=0.1)
     ref = (top.cpu().numpy(), _np(out), raw.cpu().numpy())
@@ -180,3 +182,50 @@ def test_triage_screen_as_graph(eng, data):
             torch.cuda.synchronize()
     finally:
         g.close()
+
+
+def test_prepare_cache_reuses_unchanged_sets(eng, data):
+    from paper_2607_20766_amd.engine import SHAPE_SCREEN_ADAPTIVE as AD
+    Q, lib = data
+    kw = dict(mode=AD, round_per_pair=512, cap_per_pair=8192, seed=4)
+
+    def run():
+        f = eng.shape_features(lib).cpu().numpy()
+        fo = eng.shape_fo_overlap(Q, lib).cpu().numpy()
+        return f, fo, _np(eng.shape_screen(Q, lib, **kw))
+
+    ref = run()
+    eng.prepare_cache(True)
+    try:
+        got = run()
+        assert np.array_equal(ref[0], got[0], equal_nan=True)
+        assert np.array_equal(ref[1], got[1], equal_nan=True)
+        _same(ref[2], got[2])
+        # forgetting after an in-place change prepares the new data
+        xyz = lib.xyz.clone()
+        lib.xyz.mul_(1.1)
+        eng.prepare_cache(True)
+        moved = _np(eng.shape_screen(Q, lib, **kw))
+        assert not np.array_equal(moved["T"], ref[2]["T"])
+        lib.xyz.copy_(xyz)
+        eng.prepare_cache(True)
+        _same(ref[2], _np(eng.shape_screen(Q, lib, **kw)))
+    finally:
+        eng.prepare_cache(False)
+
+
+def test_prepare_cache_still_reports_invalid_data(eng, data):
+    Q, _ = data
+    L = molgen.library(13, 20, 10, 50, workers=1)
+    L.xyz[L.offsets[5] + 2, 1] = np.nan
+    bad = eng.molecules(L)
+    eng.prepare_cache(True)
+    try:
+        for rep in range(2):   # the second call reuses the preparation
+            out = _np(eng.shape_screen(Q, bad, mode=SHAPE_SCREEN_FIXED, n_per_side=256, seed=1))
+            assert np.isnan(out["T"][5]) and np.isfinite(np.delete(out["T"], 5)).all()
+            with pytest.raises(ShapeError):
+                eng.shape_check_data()
+    finally:
+        eng.prepare_cache(False)
+    eng.shape_check_data()
