@@ -88,7 +88,7 @@ __global__ __launch_bounds__(64) void k_features(Prepared M, const int* __restri
     const float pi = t * sqrtf(t) * iZ;
     mx = fmaf(pi, c.x, mx); my = fmaf(pi, c.y, my); mz = fmaf(pi, c.z, mz);
   }
-  mx = wave_sumf(mx); my = wave_sumf(my); mz = wave_sumf(mz);
+  mx = wave_sum_dpp(mx); my = wave_sum_dpp(my); mz = wave_sum_dpp(mz);
   // pass 2: centred second moments, radial histogram, width classes
   float sxx = 0.f, syy = 0.f, szz = 0.f, sxy = 0.f, sxz = 0.f, syz = 0.f;
   int hist_mine = 0, cls_mine = 0;  // lane b < 16 keeps bin b, lane c < 4 class c
@@ -117,8 +117,8 @@ __global__ __launch_bounds__(64) void k_features(Prepared M, const int* __restri
       if (lane == b) cls_mine += cnt;
     }
   }
-  sxx = wave_sumf(sxx); syy = wave_sumf(syy); szz = wave_sumf(szz);
-  sxy = wave_sumf(sxy); sxz = wave_sumf(sxz); syz = wave_sumf(syz);
+  sxx = wave_sum_dpp(sxx); syy = wave_sum_dpp(syy); szz = wave_sum_dpp(szz);
+  sxy = wave_sum_dpp(sxy); sxz = wave_sum_dpp(sxz); syz = wave_sum_dpp(syz);
   // first-order self-overlap: diagonal + 2 x the i < j triangle, flattened
   float fo = 0.f;
   for (int i = lane; i < n; i += kWave) fo += fo_term(sC[i].w, sC[i].w, 0.f);
@@ -134,7 +134,7 @@ __global__ __launch_bounds__(64) void k_features(Prepared M, const int* __restri
     const float dx = ci.x - cj.x, dy = ci.y - cj.y, dz = ci.z - cj.z;
     fo = fmaf(2.0f, fo_term(ci.w, cj.w, fmaf(dx, dx, fmaf(dy, dy, dz * dz))), fo);
   }
-  const double fo_sum = wave_sum((double)fo);
+  const float fo_sum = wave_sum_dpp(fo);
   if (lane < 16) f[lane] = (float)hist_mine;
   if (lane < 4) f[19 + lane] = (float)cls_mine;
   // the covariance goes to k_features_eigen, which diagonalises one matrix
@@ -143,7 +143,7 @@ __global__ __launch_bounds__(64) void k_features(Prepared M, const int* __restri
   if (lane == 0) {
     mm[0] = sxx; mm[1] = syy; mm[2] = szz;
     mm[3] = sxy; mm[4] = sxz; mm[5] = syz;
-    f[23] = (float)fo_sum;
+    f[23] = fo_sum;
   }
 }
 
@@ -162,14 +162,16 @@ __global__ void k_features_eigen(const Prepared M, int n_mols, const float* __re
 
 // First-order cross-overlap of (query, library molecule) pairs at their
 // current poses, Eq. fo: sum_ij (pi/(a_i+a_j))^(3/2)
-// exp(-a_i a_j/(a_i+a_j) |c_i - c_j|^2); one wave per pair, lanes over the
-// query atoms, FP32 per lane, FP64 across lanes.
+// exp(-a_i a_j/(a_i+a_j) |c_i - c_j|^2); one wave per pair, the N_q N_b atom
+// pairs spread over all 64 lanes (row i = p / N_b stepped incrementally),
+// FP32 sums, DPP wave sum.
 __global__ __launch_bounds__(64) void k_fo_cross(Prepared Q, const int* __restrict__ offQ,
                                                  const float* __restrict__ alphaQ, Prepared L,
                                                  const int* __restrict__ offL,
                                                  const float* __restrict__ alphaL,
                                                  const int* __restrict__ pairs, int n_pairs,
                                                  int n_lib, float* __restrict__ out) {
+  __shared__ float4 sA[SHAPE_MAX_ATOMS];
   __shared__ float4 sB[SHAPE_MAX_ATOMS];
   const int p = blockIdx.x, lane = threadIdx.x;
   if (p >= n_pairs) return;
@@ -180,31 +182,33 @@ __global__ __launch_bounds__(64) void k_fo_cross(Prepared Q, const int* __restri
   }
   const int q0 = offQ[0], nq = offQ[1] - q0;
   const int b0 = offL[m], nb = offL[m + 1] - b0;
+  for (int i = lane; i < nq; i += kWave) {
+    const Atom at = Q.atom[q0 + i];
+    sA[i] = make_float4(at.x, at.y, at.z, alphaQ[q0 + i]);
+  }
   for (int j = lane; j < nb; j += kWave) {
     const Atom at = L.atom[b0 + j];
     sB[j] = make_float4(at.x, at.y, at.z, alphaL[b0 + j]);
   }
   __syncthreads();
+  const int di = kWave / nb, dj = kWave % nb;
+  int i = lane / nb, j = lane % nb;
   float acc = 0.0f;
-  for (int i = lane; i < nq; i += kWave) {
-    const Atom ai = Q.atom[q0 + i];
-    const float al = alphaQ[q0 + i];
-    for (int j = 0; j < nb; ++j) {
-      const float4 cj = sB[j];
-      const float dx = ai.x - cj.x, dy = ai.y - cj.y, dz = ai.z - cj.z;
-      acc += fo_term(al, cj.w, fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
+  for (; i < nq;) {
+    const float4 ci = sA[i], cj = sB[j];
+    const float dx = ci.x - cj.x, dy = ci.y - cj.y, dz = ci.z - cj.z;
+    acc += fo_term(ci.w, cj.w, fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
+    i += di;
+    j += dj;
+    if (j >= nb) {
+      j -= nb;
+      ++i;
     }
   }
-  const double s = wave_sum((double)acc);
-  if (lane == 0) out[p] = (float)s;
+  const float s = wave_sum_dpp(acc);
+  if (lane == 0) out[p] = s;
 }
 
-// Pair features standardised, x_j = (raw_j - mean_j) * inv_std_j, with
-// raw = [f_q, f_m, |f_q - f_m|, f_q * f_m]; when the pair's first-order
-// cross-overlap O_qm is given, the two slots that would combine the two
-// self-overlaps (|.| and product of feature 23) carry the pair's first-order
-// Tanimoto O_qm / (O_qq + O_mm - O_qm) and O_qm itself.  One thread per
-// output element.
 __device__ __forceinline__ float pair_feature(const float* __restrict__ fq,
                                               const float* __restrict__ flib, int q, int m,
                                               int j, const float* __restrict__ fo_cross, int p,
@@ -744,20 +748,47 @@ __global__ __launch_bounds__(256) void k_select_count(const float* __restrict__ 
   }
 }
 
-// One thread: exclusive scans of the block counts; equal keys are admitted
-// in index order up to the number still needed.
-__global__ void k_select_scan(int* __restrict__ cnt_gt, int* __restrict__ cnt_eq, int nblk,
-                              const uint32_t* __restrict__ sel) {
-  if (blockIdx.x != 0 || threadIdx.x != 0) return;
-  int need_eq = (int)sel[1];
-  int pos = 0;
-  for (int b = 0; b < nblk; ++b) {
-    const int g = cnt_gt[b], e = cnt_eq[b];
-    const int take = e < need_eq ? e : need_eq;
-    need_eq -= take;
-    cnt_gt[b] = pos;   // output offset of the block
-    cnt_eq[b] = take;  // equal keys the block may emit
-    pos += g + take;
+// Exclusive scans of the block counts in one workgroup of 1024 threads (each
+// thread owns a contiguous run of blocks; Hillis-Steele scan of the run
+// totals in LDS).  Equal keys are admitted in index order up to the number
+// still needed: with G, E the counts above and equal before block b,
+// block b writes from G + min(E, need) and admits min(e_b, need - E) equal
+// keys (at least 0).
+constexpr int kScanThreads = 1024;
+
+__global__ __launch_bounds__(kScanThreads) void k_select_scan(int* __restrict__ cnt_gt,
+                                                              int* __restrict__ cnt_eq,
+                                                              int nblk,
+                                                              const uint32_t* __restrict__ sel) {
+  __shared__ int sg[kScanThreads], se[kScanThreads];
+  const int t = threadIdx.x;
+  const int per = (nblk + kScanThreads - 1) / kScanThreads;
+  const int b0 = t * per, b1 = min(nblk, b0 + per);
+  int g = 0, e = 0;
+  for (int b = b0; b < b1; ++b) {
+    g += cnt_gt[b];
+    e += cnt_eq[b];
+  }
+  sg[t] = g;
+  se[t] = e;
+  __syncthreads();
+  for (int d = 1; d < kScanThreads; d <<= 1) {
+    const int vg = t >= d ? sg[t - d] : 0, ve = t >= d ? se[t - d] : 0;
+    __syncthreads();
+    sg[t] += vg;
+    se[t] += ve;
+    __syncthreads();
+  }
+  const int need = (int)sel[1];
+  int G = sg[t] - g, E = se[t] - e;  // exclusive prefixes of this thread's run
+  for (int b = b0; b < b1; ++b) {
+    const int gb = cnt_gt[b], eb = cnt_eq[b];
+    const int left = need - E;
+    const int take = left <= 0 ? 0 : (eb < left ? eb : left);
+    cnt_gt[b] = G + (E < need ? E : need);  // output offset of the block
+    cnt_eq[b] = take;                       // equal keys the block may emit
+    G += gb;
+    E += eb;
   }
 }
 
@@ -940,7 +971,7 @@ hipError_t launch_topk(const float* s, int n, int k, uint32_t* sel, uint32_t* hi
   }
   const int nb = topk_blocks(n);
   hipLaunchKernelGGL(k_select_count, dim3(nb), dim3(256), 0, st, s, n, sel, cnt_gt, cnt_eq);
-  hipLaunchKernelGGL(k_select_scan, dim3(1), dim3(1), 0, st, cnt_gt, cnt_eq, nb, sel);
+  hipLaunchKernelGGL(k_select_scan, dim3(1), dim3(kScanThreads), 0, st, cnt_gt, cnt_eq, nb, sel);
   hipLaunchKernelGGL(k_select_write, dim3(nb), dim3(256), 0, st, s, n, sel, cnt_gt, cnt_eq, out);
   return hipGetLastError();
 }
