@@ -28,7 +28,7 @@ enum Slot {
   S_L_ATOM, S_L_SAMP, S_L_Z, S_L_ID, S_L_BAD, S_L_CENTRE,
   S_PARTIALS, S_RESULT, S_QS, S_QF2,
   S_SELF_A, S_SELF_B, S_ADAM_M, S_ADAM_V, S_ADAM_STEP, S_GRAD,
-  S_MSE, S_TOPK_SEL, S_TOPK_HIST, S_TOPK_GT, S_TOPK_EQ, S_COLSUM, S_TUNE, S_MLP_PACK, S_FEAT_MOM,
+  S_MSE, S_TOPK_SEL, S_TOPK_HIST, S_TOPK_GT, S_TOPK_EQ, S_COLSUM, S_TUNE, S_MLP_PACK, S_FEAT_MOM, S_GEMM_PART,
   S_COUNT
 };
 
@@ -802,6 +802,12 @@ int shape_gemm(shape_ctx* c, int32_t M, int32_t N, int32_t K, const float* A, in
   int rc = set_device(c);
   if (rc) return rc;
   shape::GemmArgs g{M, N, K, A, sam, sak, B, sbk, sbn, C, scm, bias, gate, sgm, (int)flags};
+  const int splits = shape::gemm_splits(g);
+  if (splits > 1) {
+    void* part;
+    if ((rc = ensure(c, S_GEMM_PART, (size_t)splits * M * N * sizeof(float), &part))) return rc;
+    g.part = (float*)part;
+  }
   HIP_TRY(c, shape::launch_gemm(g, (hipStream_t)stream), "gemm kernel");
   return SHAPE_OK;
 }

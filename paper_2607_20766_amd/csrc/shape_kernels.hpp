@@ -91,7 +91,16 @@ struct GemmArgs {
   const float* gate;
   int64_t sgm;
   int flags;
+  // split-K: when part is set, workgroup z covers k in [z k_chunk, (z+1) k_chunk)
+  // and writes its raw partial tile to part[z][M][N]; a reduction adds the
+  // partials in z order and applies the epilogue
+  int k_chunk = 0;
+  float* part = nullptr;
 };
+
+// Number of K splits launch_gemm will use for this product (1 = none) and
+// the scratch it then needs (splits * M * N floats).
+int gemm_splits(const GemmArgs& g);
 
 hipError_t launch_features(const Prepared& M, const int* off, const float* alpha, int n_mols,
                            float* out, float* mom, hipStream_t st);

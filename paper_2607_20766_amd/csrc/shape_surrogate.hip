@@ -276,7 +276,9 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
   const int kstep = BF16 ? 16 : 4;
-  for (int k0 = 0; k0 < g.K; k0 += kstep) {
+  const int kb = g.part ? blockIdx.z * g.k_chunk : 0;
+  const int ke = g.part ? min(g.K, kb + g.k_chunk) : g.K;
+  for (int k0 = kb; k0 < ke; k0 += kstep) {
     if (BF16) {
       v4s a[2], b[2];
 #pragma unroll
@@ -285,7 +287,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const int k = k0 + 4 * lk + e;
-          const float v = (m < g.M && k < g.K) ? g.A[(int64_t)m * g.sam + (int64_t)k * g.sak] : 0.f;
+          const float v = (m < g.M && k < ke) ? g.A[(int64_t)m * g.sam + (int64_t)k * g.sak] : 0.f;
           a[i][e] = to_bf16(v);
         }
       }
@@ -295,7 +297,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const int k = k0 + 4 * lk + e;
-          const float v = (n < g.N && k < g.K) ? g.B[(int64_t)k * g.sbk + (int64_t)n * g.sbn] : 0.f;
+          const float v = (n < g.N && k < ke) ? g.B[(int64_t)k * g.sbk + (int64_t)n * g.sbn] : 0.f;
           b[j][e] = to_bf16(v);
         }
       }
@@ -310,12 +312,12 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
         const int m = m0 + 16 * i + li;
-        a[i] = (m < g.M && k < g.K) ? g.A[(int64_t)m * g.sam + (int64_t)k * g.sak] : 0.f;
+        a[i] = (m < g.M && k < ke) ? g.A[(int64_t)m * g.sam + (int64_t)k * g.sak] : 0.f;
       }
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
         const int n = n0 + 16 * j + li;
-        b[j] = (n < g.N && k < g.K) ? g.B[(int64_t)k * g.sbk + (int64_t)n * g.sbn] : 0.f;
+        b[j] = (n < g.N && k < ke) ? g.B[(int64_t)k * g.sbk + (int64_t)n * g.sbn] : 0.f;
       }
 #pragma unroll
       for (int i = 0; i < 2; ++i)
@@ -332,7 +334,9 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
       for (int r = 0; r < 4; ++r) {
         const int m = m0 + 16 * i + 4 * lk + r;
         const int n = n0 + 16 * j + li;
-        if (m < g.M && n < g.N) {
+        if (m < g.M && n < g.N && g.part) {
+          g.part[((int64_t)blockIdx.z * g.M + m) * g.N + n] = acc[i][j][r];
+        } else if (m < g.M && n < g.N) {
           float v = acc[i][j][r];
           if (g.bias) v += g.bias[n];
           if (g.flags & SHAPE_GEMM_RELU) v = v > 0.f ? v : 0.f;
@@ -363,7 +367,9 @@ __global__ __launch_bounds__(256) void k_gemm_bf16_tiled(GemmArgs g) {
     for (int j = 0; j < 4; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
   const bool a_kfast = g.sak == 1;
   const bool b_nfast = g.sbn == 1;
-  for (int k0 = 0; k0 < g.K; k0 += kTK) {
+  const int kb = g.part ? blockIdx.z * g.k_chunk : 0;
+  const int ke = g.part ? min(g.K, kb + g.k_chunk) : g.K;
+  for (int k0 = kb; k0 < ke; k0 += kTK) {
     // stage A: 128 x 32 elements, 16 per thread
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
@@ -376,7 +382,7 @@ __global__ __launch_bounds__(256) void k_gemm_bf16_tiled(GemmArgs g) {
         k = (tid >> 7) + 2 * r;
       }
       const int gm = bm + m, gk = k0 + k;
-      const float v = (gm < g.M && gk < g.K) ? g.A[(int64_t)gm * g.sam + (int64_t)gk * g.sak] : 0.f;
+      const float v = (gm < g.M && gk < ke) ? g.A[(int64_t)gm * g.sam + (int64_t)gk * g.sak] : 0.f;
       As[m * kLdk + k] = to_bf16(v);
     }
     // stage B: 32 x 128 elements, stored transposed as Bs[n][k]
@@ -391,7 +397,7 @@ __global__ __launch_bounds__(256) void k_gemm_bf16_tiled(GemmArgs g) {
         n = (tid >> 5) + 8 * r;
       }
       const int gn = bn + n, gk = k0 + k;
-      const float v = (gn < g.N && gk < g.K) ? g.B[(int64_t)gk * g.sbk + (int64_t)gn * g.sbn] : 0.f;
+      const float v = (gn < g.N && gk < ke) ? g.B[(int64_t)gk * g.sbk + (int64_t)gn * g.sbn] : 0.f;
       Bs[n * kLdk + k] = to_bf16(v);
     }
     __syncthreads();
@@ -420,7 +426,9 @@ __global__ __launch_bounds__(256) void k_gemm_bf16_tiled(GemmArgs g) {
       for (int r = 0; r < 4; ++r) {
         const int m = bm + wm + 16 * i + 4 * lk + r;
         const int n = bn + wn + 16 * j + li;
-        if (m < g.M && n < g.N) {
+        if (m < g.M && n < g.N && g.part) {
+          g.part[((int64_t)blockIdx.z * g.M + m) * g.N + n] = acc[i][j][r];
+        } else if (m < g.M && n < g.N) {
           float v = acc[i][j][r];
           if (g.bias) v += g.bias[n];
           if (g.flags & SHAPE_GEMM_RELU) v = v > 0.f ? v : 0.f;
@@ -428,6 +436,19 @@ __global__ __launch_bounds__(256) void k_gemm_bf16_tiled(GemmArgs g) {
           g.C[(int64_t)m * g.scm + n] = v;
         }
       }
+}
+
+// Split-K reduction: C[m][n] = epilogue(sum_z part[z][m][n]), z in order.
+__global__ void k_splitk_reduce(GemmArgs g, int splits) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)g.M * g.N) return;
+  const int m = (int)(t / g.N), n = (int)(t % g.N);
+  float v = 0.0f;
+  for (int z = 0; z < splits; ++z) v += g.part[(int64_t)z * g.M * g.N + t];
+  if (g.bias) v += g.bias[n];
+  if (g.flags & SHAPE_GEMM_RELU) v = v > 0.f ? v : 0.f;
+  if (g.gate && !(g.gate[(int64_t)m * g.sgm + n] > 0.f)) v = 0.f;
+  g.C[(int64_t)m * g.scm + n] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -858,20 +879,52 @@ hipError_t launch_fo_cross(const Prepared& Q, const int* offQ, const float* alph
   return hipGetLastError();
 }
 
-hipError_t launch_gemm(const GemmArgs& g, hipStream_t st) {
-  if (g.flags & SHAPE_GEMM_BF16) {
-    // narrow outputs keep the 64 x 64 kernel (a 128-wide tile would idle)
-    if (g.N >= 64) {
-      const dim3 grid((unsigned)((g.N + kTN - 1) / kTN), (unsigned)((g.M + kTM - 1) / kTM));
-      hipLaunchKernelGGL(k_gemm_bf16_tiled, grid, dim3(256), 0, st, g);
-    } else {
-      const dim3 grid((unsigned)((g.N + 63) / 64), (unsigned)((g.M + 63) / 64));
-      hipLaunchKernelGGL(k_gemm<true>, grid, dim3(256), 0, st, g);
-    }
+// Workgroup grid of launch_gemm without splitting.
+static dim3 gemm_grid(const GemmArgs& g, bool tiled) {
+  const int tm = tiled ? kTM : 64, tn = tiled ? kTN : 64;
+  return dim3((unsigned)((g.N + tn - 1) / tn), (unsigned)((g.M + tm - 1) / tm));
+}
+
+static bool gemm_tiled(const GemmArgs& g) { return (g.flags & SHAPE_GEMM_BF16) && g.N >= 64; }
+
+// Products whose output tiles cannot fill the chip (the weight gradients:
+// M x N = layer size, K = batch) split K so that >= 512 workgroups run,
+// each over at least 128 values of k.
+int gemm_splits(const GemmArgs& g) {
+  const dim3 grid = gemm_grid(g, gemm_tiled(g));
+  const int tiles = (int)(grid.x * grid.y);
+  if (tiles >= 128 || g.K < 512) return 1;
+  int s = (512 + tiles - 1) / tiles;
+  const int by_k = g.K / 128;
+  return s < by_k ? s : by_k;
+}
+
+hipError_t launch_gemm(const GemmArgs& g0, hipStream_t st) {
+  GemmArgs g = g0;
+  const bool tiled = gemm_tiled(g);
+  dim3 grid = gemm_grid(g, tiled);
+  int splits = g.part ? gemm_splits(g) : 1;
+  if (splits > 1) {
+    g.k_chunk = ((g.K + splits - 1) / splits + kTK - 1) / kTK * kTK;
+    splits = (g.K + g.k_chunk - 1) / g.k_chunk;
+    grid.z = (unsigned)splits;
   } else {
-    const dim3 grid((unsigned)((g.N + 63) / 64), (unsigned)((g.M + 63) / 64));
+    g.part = nullptr;
+    g.k_chunk = 0;
+  }
+  if (tiled) {
+    hipLaunchKernelGGL(k_gemm_bf16_tiled, grid, dim3(256), 0, st, g);
+  } else if (g.flags & SHAPE_GEMM_BF16) {
+    // narrow outputs keep the 64 x 64 kernel (a 128-wide tile would idle)
+    hipLaunchKernelGGL(k_gemm<true>, grid, dim3(256), 0, st, g);
+  } else {
     hipLaunchKernelGGL(k_gemm<false>, grid, dim3(256), 0, st, g);
   }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || splits <= 1) return e;
+  const int64_t tot = (int64_t)g.M * g.N;
+  hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, g,
+                     splits);
   return hipGetLastError();
 }
 
