@@ -128,6 +128,8 @@ __global__ __launch_bounds__(kAlignThreads) void k_align(AlignArgs a) {
         r2[s] = norm2(c.x, c.y, c.z);
         P[s] = 1.f; S0[s] = 0.f; Sx[s] = 0.f; Sy[s] = 0.f; Sz[s] = 0.f;
       }
+      // unrolled by two: no loop-carried register copies between atoms
+#pragma unroll 2
       for (int j = 0; j < nb; ++j) {
         const AtomRec b = wR[j];
         const float aj = wa[j];
