@@ -70,6 +70,12 @@ def lib():
         L.or_align_adam.argtypes = [_i, _f32p, _f32p, _u32, _i, _f32p, _f32p, _u32,
                                     _i64, _u64, ctypes.c_int32, _f64p, ctypes.c_int32, _d,
                                     _f64p, _f64p]
+        L.or_fo_align_grad.argtypes = [_i, _f32p, _f32p, _i, _f32p, _f32p, ctypes.c_int32,
+                                       _f64p, _f64p, _vp]
+        L.or_fo_align_adam.argtypes = [_i, _f32p, _f32p, _i, _f32p, _f32p, ctypes.c_int32,
+                                       _f64p, ctypes.c_int32, _d, _f64p, _f64p]
+        L.or_fo_starts.argtypes = [_i, _f32p, _f32p, _i, _f32p, _f32p, _u32, ctypes.c_int32,
+                                   _u64, _f64p]
         L.or_features.argtypes = [ctypes.c_int32, _i32p, _f32p, _f32p, _f64p]
         L.or_mlp_nparams.argtypes = [_i, _i32p]
         L.or_mlp_nparams.restype = _i64
@@ -241,6 +247,45 @@ def align_adam(A, B, pose0, n_steps=60, lr=0.05, n_samples=2048, seed=0, id_a=0,
         raise RuntimeError("oracle align_adam failed")
     return pose, T
 
+
+
+def fo_align_grad(A, B, poses):
+    """First-order aligned Tanimoto T_FO and dT_FO/dpose at each pose [P, 7]
+    (hybrid pipeline: the alignment objective)."""
+    xa, aa = _mol(*A)
+    xb, ab = _mol(*B)
+    poses = np.ascontiguousarray(poses, np.float64).reshape(-1, 7)
+    T = np.zeros(poses.shape[0])
+    g = np.zeros((poses.shape[0], 7))
+    if lib().or_fo_align_grad(aa.size, xa, aa, ab.size, xb, ab, poses.shape[0], poses, T,
+                              g.ctypes.data_as(ctypes.c_void_p)):
+        raise RuntimeError("oracle fo_align_grad failed")
+    return T, g
+
+
+def fo_align_adam(A, B, pose0, n_steps=60, lr=0.05):
+    """Adam on -T_FO from each start [S, 7]: final poses and T_FO there."""
+    xa, aa = _mol(*A)
+    xb, ab = _mol(*B)
+    pose0 = np.ascontiguousarray(pose0, np.float64).reshape(-1, 7)
+    pose = np.zeros_like(pose0)
+    T = np.zeros(pose0.shape[0])
+    if lib().or_fo_align_adam(aa.size, xa, aa, ab.size, xb, ab, pose0.shape[0], pose0,
+                              int(n_steps), float(lr), pose, T):
+        raise RuntimeError("oracle fo_align_adam failed")
+    return pose, T
+
+
+def fo_starts(A, B, pair_id=0, n_random=3, seed=0):
+    """Alignment starts [5 + n_random, 7]: identity, the four proper
+    principal-axis alignments, random rotations about B's mean."""
+    xa, aa = _mol(*A)
+    xb, ab = _mol(*B)
+    out = np.zeros((5 + int(n_random), 7))
+    if lib().or_fo_starts(aa.size, xa, aa, ab.size, xb, ab, int(pair_id), int(n_random),
+                          int(seed), out):
+        raise RuntimeError("oracle fo_starts failed")
+    return out
 
 def num_threads() -> int:
     return lib().or_num_threads()

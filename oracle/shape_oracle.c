@@ -801,6 +801,254 @@ int or_align_adam(int na, const float* xyz_a, const float* alpha_a, uint32_t id_
   return 0;
 }
 
+/* ------------------------------------------------------------------------- */
+/* Hybrid pipeline (section "Differentiable alignment and the hybrid          */
+/* pipeline"): align on the first-order overlap, then score with the union    */
+/* estimator.                                                                 */
+/* ------------------------------------------------------------------------- */
+
+/* T_FO(xi) = O(xi) / (O_AA + O_BB - O(xi)) with O(xi) = sum_ij K_ij,
+ * K_ij = (pi/(a_i+a_j))^(3/2) exp(-a_i a_j/(a_i+a_j) |c_i - c''_j|^2) (Eq. fo)
+ * and c''_j = R(q/|q|) c_j + t (Eq. pose, quaternion form).  Gradient with
+ * respect to the seven pose parameters through dR/dq_hat and the
+ * normalisation of q (the same parameterisation as the IS alignment). */
+static void or_fo_align_eval(const or_mol* A, const or_mol* B, double O_aa, double O_bb,
+                             const double pose[7], double* T_out, double grad[7]) {
+  double qn = sqrt(pose[0] * pose[0] + pose[1] * pose[1] + pose[2] * pose[2] + pose[3] * pose[3]);
+  double qh[4] = {pose[0] / qn, pose[1] / qn, pose[2] / qn, pose[3] / qn};
+  double R[9], dR[4][9];
+  or_quat_matrix(qh, R);
+  or_quat_matrix_grad(qh, dR);
+  double O = 0.0, gc[4] = {0}, gt[3] = {0};
+  for (int j = 0; j < B->n; ++j) {
+    const double* cb = B->c + 3 * j;
+    double cp[3];
+    for (int a = 0; a < 3; ++a)
+      cp[a] = R[3 * a] * cb[0] + R[3 * a + 1] * cb[1] + R[3 * a + 2] * cb[2] + pose[4 + a];
+    double g[3] = {0, 0, 0};  /* d O / d c''_j */
+    for (int i = 0; i < A->n; ++i) {
+      const double* ca = A->c + 3 * i;
+      double ai = A->alpha[i], aj = B->alpha[j];
+      double s = ai + aj, kap = ai * aj / s;
+      double d[3] = {ca[0] - cp[0], ca[1] - cp[1], ca[2] - cp[2]};
+      double d2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+      double K = pow(OR_PI / s, 1.5) * exp(-kap * d2);
+      O += K;
+      for (int a = 0; a < 3; ++a) g[a] += 2.0 * kap * K * d[a];
+    }
+    for (int a = 0; a < 3; ++a) gt[a] += g[a];
+    for (int i = 0; i < 4; ++i)
+      for (int a = 0; a < 3; ++a)
+        gc[i] += g[a] * (dR[i][3 * a] * cb[0] + dR[i][3 * a + 1] * cb[1] +
+                         dR[i][3 * a + 2] * cb[2]);
+  }
+  double S = O_aa + O_bb, D = S - O;
+  *T_out = O / D;
+  if (grad) {
+    double dT_dO = S / (D * D);
+    for (int kk = 0; kk < 4; ++kk) {
+      double acc = 0.0;
+      for (int i = 0; i < 4; ++i) acc += gc[i] * (((i == kk) ? 1.0 : 0.0) - qh[i] * qh[kk]) / qn;
+      grad[kk] = dT_dO * acc;
+    }
+    for (int a = 0; a < 3; ++a) grad[4 + a] = dT_dO * gt[a];
+  }
+}
+
+/* exported: T_FO and dT_FO/dpose for poses [n_poses][7] of one pair */
+int or_fo_align_grad(int na, const float* xyz_a, const float* alpha_a, int nb,
+                     const float* xyz_b, const float* alpha_b, int32_t n_poses,
+                     const double* poses, double* T_out, double* grad_out) {
+  or_mol A, B;
+  if (or_mol_init(&A, na, xyz_a, alpha_a)) return -1;
+  if (or_mol_init(&B, nb, xyz_b, alpha_b)) { or_mol_free(&A); return -1; }
+  double O_aa = or_fo_overlap(na, xyz_a, alpha_a, na, xyz_a, alpha_a);
+  double O_bb = or_fo_overlap(nb, xyz_b, alpha_b, nb, xyz_b, alpha_b);
+  for (int32_t p = 0; p < n_poses; ++p)
+    or_fo_align_eval(&A, &B, O_aa, O_bb, poses + 7 * p, T_out + p,
+                     grad_out ? grad_out + 7 * p : NULL);
+  or_mol_free(&A); or_mol_free(&B);
+  return 0;
+}
+
+/* exported: Adam on -T_FO from each start (the update of or_align_adam:
+ * betas 0.9, 0.999, eps 1e-8, q renormalised after each step); final poses
+ * and T_FO at them. */
+int or_fo_align_adam(int na, const float* xyz_a, const float* alpha_a, int nb,
+                     const float* xyz_b, const float* alpha_b, int32_t n_starts,
+                     const double* pose0, int32_t n_steps, double lr, double* pose_out,
+                     double* T_out) {
+  or_mol A, B;
+  if (or_mol_init(&A, na, xyz_a, alpha_a)) return -1;
+  if (or_mol_init(&B, nb, xyz_b, alpha_b)) { or_mol_free(&A); return -1; }
+  double O_aa = or_fo_overlap(na, xyz_a, alpha_a, na, xyz_a, alpha_a);
+  double O_bb = or_fo_overlap(nb, xyz_b, alpha_b, nb, xyz_b, alpha_b);
+  const double b1 = 0.9, b2 = 0.999, eps = 1e-8;
+  for (int32_t s = 0; s < n_starts; ++s) {
+    double x[7], m[7] = {0}, v[7] = {0}, g[7], T;
+    memcpy(x, pose0 + 7 * s, sizeof x);
+    for (int32_t it = 1; it <= n_steps; ++it) {
+      or_fo_align_eval(&A, &B, O_aa, O_bb, x, &T, g);
+      for (int i = 0; i < 7; ++i) {
+        double gi = -g[i];
+        m[i] = b1 * m[i] + (1 - b1) * gi;
+        v[i] = b2 * v[i] + (1 - b2) * gi * gi;
+        double mh = m[i] / (1 - pow(b1, it));
+        double vh = v[i] / (1 - pow(b2, it));
+        x[i] -= lr * mh / (sqrt(vh) + eps);
+      }
+      double qn = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2] + x[3] * x[3]);
+      for (int i = 0; i < 4; ++i) x[i] /= qn;
+    }
+    or_fo_align_eval(&A, &B, O_aa, O_bb, x, &T, NULL);
+    memcpy(pose_out + 7 * s, x, sizeof x);
+    T_out[s] = T;
+  }
+  or_mol_free(&A); or_mol_free(&B);
+  return 0;
+}
+
+/* Symmetric 3x3 eigen-decomposition by cyclic Jacobi rotations: eigenvalues
+ * descending in ev, unit eigenvectors in the columns of V (row-major). */
+static void or_sym3_eigvec(double a[3][3], double ev[3], double V[9]) {
+  double U[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = fabs(a[0][1]) + fabs(a[0][2]) + fabs(a[1][2]);
+    if (off < 1e-300) break;
+    for (int p = 0; p < 2; ++p)
+      for (int q = p + 1; q < 3; ++q) {
+        if (a[p][q] == 0.0) continue;
+        double theta = (a[q][q] - a[p][p]) / (2.0 * a[p][q]);
+        double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+        double c = 1.0 / sqrt(t * t + 1.0), sn = t * c;
+        for (int k = 0; k < 3; ++k) {
+          double akp = a[k][p], akq = a[k][q];
+          a[k][p] = c * akp - sn * akq;
+          a[k][q] = sn * akp + c * akq;
+        }
+        for (int k = 0; k < 3; ++k) {
+          double apk = a[p][k], aqk = a[q][k];
+          a[p][k] = c * apk - sn * aqk;
+          a[q][k] = sn * apk + c * aqk;
+        }
+        for (int k = 0; k < 3; ++k) {
+          double ukp = U[k][p], ukq = U[k][q];
+          U[k][p] = c * ukp - sn * ukq;
+          U[k][q] = sn * ukp + c * ukq;
+        }
+      }
+  }
+  int idx[3] = {0, 1, 2};
+  for (int i = 0; i < 3; ++i)
+    for (int j = i + 1; j < 3; ++j)
+      if (a[idx[j]][idx[j]] > a[idx[i]][idx[i]]) { int t = idx[i]; idx[i] = idx[j]; idx[j] = t; }
+  for (int c = 0; c < 3; ++c) {
+    ev[c] = a[idx[c]][idx[c]];
+    for (int r = 0; r < 3; ++r) V[3 * r + c] = U[r][idx[c]];
+  }
+}
+
+/* Principal frame of a molecule's mixture: mean mu = sum pi_i c_i and the
+ * eigenvectors of sum pi_i (c_i - mu)(c_i - mu)^T (pi_i = v_i / Z), as the
+ * columns of U: descending eigenvalues, the largest-magnitude component of
+ * the first two made positive, the third their cross product (right-handed). */
+static void or_principal_frame(const or_mol* M, double mu[3], double U[9]) {
+  mu[0] = mu[1] = mu[2] = 0.0;
+  for (int i = 0; i < M->n; ++i)
+    for (int d = 0; d < 3; ++d) mu[d] += M->v[i] / M->Z * M->c[3 * i + d];
+  double C[3][3] = {{0}};
+  for (int i = 0; i < M->n; ++i) {
+    double w = M->v[i] / M->Z;
+    double x[3] = {M->c[3 * i] - mu[0], M->c[3 * i + 1] - mu[1], M->c[3 * i + 2] - mu[2]};
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) C[r][c] += w * x[r] * x[c];
+  }
+  double ev[3];
+  or_sym3_eigvec(C, ev, U);
+  for (int c = 0; c < 2; ++c) {
+    int big = 0;
+    for (int r = 1; r < 3; ++r)
+      if (fabs(U[3 * r + c]) > fabs(U[3 * big + c])) big = r;
+    if (U[3 * big + c] < 0)
+      for (int r = 0; r < 3; ++r) U[3 * r + c] = -U[3 * r + c];
+  }
+  U[2] = U[3] * U[7] - U[6] * U[4];
+  U[5] = U[6] * U[1] - U[0] * U[7];
+  U[8] = U[0] * U[4] - U[3] * U[1];
+}
+
+/* Unit quaternion (w, x, y, z), w >= 0, of a rotation matrix (Shepperd). */
+static void or_matrix_quat(const double R[9], double q[4]) {
+  double tr = R[0] + R[4] + R[8];
+  double w, x, y, z;
+  if (tr >= R[0] && tr >= R[4] && tr >= R[8]) {
+    double s = sqrt(1.0 + tr) * 2.0;
+    w = 0.25 * s; x = (R[7] - R[5]) / s; y = (R[2] - R[6]) / s; z = (R[3] - R[1]) / s;
+  } else if (R[0] >= R[4] && R[0] >= R[8]) {
+    double s = sqrt(1.0 + R[0] - R[4] - R[8]) * 2.0;
+    w = (R[7] - R[5]) / s; x = 0.25 * s; y = (R[1] + R[3]) / s; z = (R[2] + R[6]) / s;
+  } else if (R[4] >= R[8]) {
+    double s = sqrt(1.0 + R[4] - R[0] - R[8]) * 2.0;
+    w = (R[2] - R[6]) / s; x = (R[1] + R[3]) / s; y = 0.25 * s; z = (R[5] + R[7]) / s;
+  } else {
+    double s = sqrt(1.0 + R[8] - R[0] - R[4]) * 2.0;
+    w = (R[3] - R[1]) / s; x = (R[2] + R[6]) / s; y = (R[5] + R[7]) / s; z = 0.25 * s;
+  }
+  double sg = w < 0 ? -1.0 : 1.0;
+  q[0] = sg * w; q[1] = sg * x; q[2] = sg * y; q[3] = sg * z;
+}
+
+/* exported: the alignment starts of one pair, [5 + n_random][7]: the given
+ * pose (identity), the four proper principal-axis alignments
+ * R = U_A D U_B^T with D = diag(1,1,1), diag(1,-1,-1), diag(-1,1,-1),
+ * diag(-1,-1,1) and t = mu_A - R mu_B, then n_random uniformly random
+ * rotations about B's mean (Shoemake's construction from the three 24-bit
+ * uniforms of Philox block (s, pair_id, 0x5157A27, 0) under the key seed)
+ * with the same centring translation. */
+int or_fo_starts(int na, const float* xyz_a, const float* alpha_a, int nb,
+                 const float* xyz_b, const float* alpha_b, uint32_t pair_id, int32_t n_random,
+                 uint64_t seed, double* poses) {
+  or_mol A, B;
+  if (or_mol_init(&A, na, xyz_a, alpha_a)) return -1;
+  if (or_mol_init(&B, nb, xyz_b, alpha_b)) { or_mol_free(&A); return -1; }
+  double muA[3], UA[9], muB[3], UB[9];
+  or_principal_frame(&A, muA, UA);
+  or_principal_frame(&B, muB, UB);
+  double* p0 = poses;
+  p0[0] = 1.0; p0[1] = p0[2] = p0[3] = 0.0; p0[4] = p0[5] = p0[6] = 0.0;
+  static const double Ds[4][3] = {{1, 1, 1}, {1, -1, -1}, {-1, 1, -1}, {-1, -1, 1}};
+  for (int s = 0; s < 4 + n_random; ++s) {
+    double R[9];
+    if (s < 4) {
+      for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+          double acc = 0.0;
+          for (int k = 0; k < 3; ++k) acc += UA[3 * r + k] * Ds[s][k] * UB[3 * c + k];
+          R[3 * r + c] = acc;
+        }
+    } else {
+      uint32_t ctr[4] = {(uint32_t)(s - 4), pair_id, 0x5157A27u, 0u};
+      uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+      uint32_t x[4];
+      or_philox4x32_10(ctr, key, x);
+      double u1 = ((double)(x[0] >> 8) + 0.5) / 16777216.0;
+      double u2 = ((double)(x[1] >> 8) + 0.5) / 16777216.0;
+      double u3 = ((double)(x[2] >> 8) + 0.5) / 16777216.0;
+      double q[4] = {sqrt(u1) * cos(2 * OR_PI * u3), sqrt(1 - u1) * sin(2 * OR_PI * u2),
+                     sqrt(1 - u1) * cos(2 * OR_PI * u2), sqrt(u1) * sin(2 * OR_PI * u3)};
+      or_quat_matrix(q, R);
+    }
+    double q[4];
+    or_matrix_quat(R, q);
+    double* out = poses + 7 * (1 + s);
+    for (int i = 0; i < 4; ++i) out[i] = q[i];
+    for (int a = 0; a < 3; ++a)
+      out[4 + a] = muA[a] - (R[3 * a] * muB[0] + R[3 * a + 1] * muB[1] + R[3 * a + 2] * muB[2]);
+  }
+  or_mol_free(&A); or_mol_free(&B);
+  return 0;
+}
+
 int or_num_threads(void) {
 #ifdef _OPENMP
   return omp_get_max_threads();
