@@ -135,6 +135,76 @@ def bench_align(eng, n_pairs, n_starts=16, n_steps=60, n_samples=2048, lr=0.05):
     }
 
 
+def bench_hybrid(eng, Q, lib, n_random=3, n_steps=50):
+    """Hybrid pipeline (section "Differentiable alignment and the hybrid
+    pipeline"): each library molecule aligned on the query by first-order
+    Adam (the given pose, 4 principal-axis and n_random random starts,
+    n_steps steps, lr 0.05), best start kept, superposed pair scored by
+    adaptive union IS.  The whole pipeline is one HIP graph."""
+    import torch
+
+    from paper_2607_20766_amd.engine import SHAPE_SCREEN_ADAPTIVE
+    from paper_2607_20766_amd.hybrid import HybridScreen
+
+    n = lib.n_mols
+    hs = HybridScreen(eng, n_random=n_random, n_steps=n_steps, lr=0.05, seed=0, tau=TAU,
+                      round_per_pair=ROUND, cap_per_pair=CAP)
+    bufs = hs.buffers(lib)
+    log("hybrid: first-order alignment + union IS")
+    hs.screen(Q, lib, bufs)
+    torch.cuda.synchronize()
+    g = eng.capture(lambda: hs.screen(Q, lib, bufs))
+    t = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        g.replay()
+        torch.cuda.synchronize()
+        t.append(time.perf_counter() - t0)
+    g.close()
+    t_all = float(np.median(t))
+    # stage times (direct launches, HIP events on the current stream)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ev[0].record()
+    eng.shape_fo_starts(Q, lib, n_random, 0, out=bufs["pose"])
+    eng.shape_fo_align(Q, lib, bufs["pose"], n_steps, 0.05, T=bufs["T_fo"])
+    ev[1].record()
+    eng.shape_best_pose(bufs["T_fo"], bufs["pose"], best_pose=bufs["best_pose"],
+                        best_T=bufs["best_T_fo"])
+    eng.shape_apply_pose(lib, bufs["best_pose"], out=bufs["xyz"])
+    ev[2].record()
+    out = eng.shape_screen(Q, hs.moved(lib, bufs), mode=SHAPE_SCREEN_ADAPTIVE,
+                           round_per_pair=ROUND, cap_per_pair=CAP, tau=TAU, seed=0,
+                           out=bufs["out"])
+    ev[3].record()
+    torch.cuda.synchronize()
+    ident = torch.zeros(n, 1, 7, device=eng.torch_device)
+    ident[:, 0, 0] = 1.0
+    T0, _ = eng.shape_fo_align(Q, lib, ident, n_steps=0)
+    plain = eng.shape_screen(Q, lib, mode=SHAPE_SCREEN_ADAPTIVE, round_per_pair=ROUND,
+                             cap_per_pair=CAP, tau=TAU, seed=0)
+    T_al = out["T"].cpu().numpy()
+    T_pl = plain["T"].cpu().numpy()
+    n_starts = 5 + n_random
+    fo_terms = float(n_starts * (n_steps + 1)) * float(
+        (Q.n_atoms * (lib.offsets[1:] - lib.offsets[:-1]).to(torch.int64)).sum().item())
+    return {
+        "workload": f"{n} library molecules vs a 30-atom query: first-order alignment from "
+                    f"{n_starts} starts x {n_steps} Adam steps (lr 0.05), best start, then "
+                    f"adaptive union IS (tau {TAU}) of the superposed pairs; one HIP graph",
+        "pairs_per_s": n / t_all,
+        "ms_per_screen": t_all * 1e3,
+        "ms_alignment": ev[0].elapsed_time(ev[1]),
+        "ms_best_and_move": ev[1].elapsed_time(ev[2]),
+        "ms_union_is": ev[2].elapsed_time(ev[3]),
+        "fo_pair_terms_per_s": fo_terms / (ev[0].elapsed_time(ev[1]) * 1e-3),
+        "mean_T_fo_given_pose": float(T0.mean().item()),
+        "mean_T_fo_aligned": float(bufs["best_T_fo"].mean().item()),
+        "mean_T_union_given_pose": float(np.nanmean(T_pl)),
+        "mean_T_union_aligned": float(np.nanmean(T_al)),
+        "is_samples_aligned": int(out["n_used"].cpu().numpy().astype(np.int64).sum()),
+    }
+
+
 def bench_triage(eng, n_lib, n_queries=256, n_train_lib=3907, epochs=10):
     """Learned triage: a BF16 MLP trained on ~10^6 IS-labelled pairs (256
     queries x 3907 molecules) ranks an n_lib-molecule library against a
@@ -145,7 +215,7 @@ def bench_triage(eng, n_lib, n_queries=256, n_train_lib=3907, epochs=10):
     import torch
 
     from paper_2607_20766_amd import molgen
-    from paper_2607_20766_amd.engine import SHAPE_SCREEN_ADAPTIVE
+    from paper_2607_20766_amd.engine import SHAPE_SCREEN_ADAPTIVE, SHAPE_SCREEN_FIXED
     from paper_2607_20766_amd.surrogate import Triage
 
     log("triage: training set labels")
@@ -211,7 +281,33 @@ def bench_triage(eng, n_lib, n_queries=256, n_train_lib=3907, epochs=10):
             t.append(time.perf_counter() - t0)
         return float(np.median(t)), r
 
+    # plain fixed-budget comparator: the smallest multiple of 512 samples per
+    # side at which >= 99 % of a 10^4-pair pilot reach SE(T) <= tau (the
+    # pilot at 4096 per side predicts it by the n^-1/2 law; it is then
+    # checked and raised by 512 until the pilot meets it)
+    log("triage: fixed-budget comparator")
+    n_pilot = min(10000, n_lib)
+    pilot = eng.shape_screen(Q, lib, mode=SHAPE_SCREEN_FIXED, n_per_side=4096, seed=3,
+                             n_pairs=n_pilot)
+    se_p = pilot["se_T"].cpu().numpy().astype(np.float64)
+    need = 4096.0 * (se_p / TAU) ** 2
+    n_fix = int(np.ceil(np.nanquantile(need, 0.99) / 512.0) * 512)
+    n_fix = max(512, min(n_fix, 1 << 20))
+    while True:
+        chk = eng.shape_screen(Q, lib, mode=SHAPE_SCREEN_FIXED, n_per_side=n_fix, seed=3,
+                               n_pairs=n_pilot)
+        frac_ok = float(np.mean(chk["se_T"].cpu().numpy() <= TAU))
+        if frac_ok >= 0.99 or n_fix >= (1 << 20):
+            break
+        n_fix += 512
+    fixed_out = {k: torch.empty_like(v) for k, v in plain_out.items()}
+
+    def run_fixed():
+        return eng.shape_screen(Q, lib, mode=SHAPE_SCREEN_FIXED, n_per_side=n_fix, seed=0,
+                                out=fixed_out)
+
     # direct launches, then each pipeline as one HIP graph
+    t_fixed, _ = wall(run_fixed, reps=1)
     t_plain_direct, _ = wall(run_plain)
     t_tri_direct, _ = wall(run_triage)
     g_plain = eng.capture(run_plain)
@@ -244,6 +340,10 @@ def bench_triage(eng, n_lib, n_queries=256, n_train_lib=3907, epochs=10):
         "pairs_per_s_surrogate_is": n_lib / t_tri,
         "pairs_per_s_plain_adaptive_is": n_lib / t_plain,
         "speedup": t_plain / t_tri,
+        "fixed_budget_per_side": n_fix,
+        "fixed_budget_pilot_frac_at_tau": frac_ok,
+        "pairs_per_s_plain_fixed_is": n_lib / t_fixed,
+        "speedup_vs_fixed": t_fixed / t_tri,
         "ms_surrogate_is": t_tri * 1e3,
         "ms_plain_adaptive_is": t_plain * 1e3,
         "ms_surrogate_is_direct_launches": t_tri_direct * 1e3,
@@ -273,6 +373,8 @@ def main():
     ap.add_argument("--no-align", action="store_true", help="skip the alignment workload")
     ap.add_argument("--align-pairs", type=int, default=10000)
     ap.add_argument("--no-triage", action="store_true", help="skip the learned-triage workload")
+    ap.add_argument("--no-hybrid", action="store_true",
+                    help="skip the first-order-alignment + union-IS workload")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB device to device three times (a plain copy of known "
                          "size for scaling the FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -452,6 +554,9 @@ def main():
 
     if not args.no_align:
         res["align"] = bench_align(eng, args.align_pairs)
+
+    if not args.no_hybrid:
+        res["hybrid"] = bench_hybrid(eng, Q, lib)
 
     if not args.no_triage:
         res["triage"] = bench_triage(eng, args.triage_library)

@@ -311,6 +311,58 @@ int shape_align(shape_ctx* ctx, const shape_mols* A, const shape_mols* B, int32_
                 void* stream, float* T_final, int32_t* best);
 
 /* ------------------------------------------------------------------------
+ * Hybrid pipeline (section "Differentiable alignment and the hybrid
+ * pipeline"): rigid alignment on the analytic first-order overlap (Eq. fo)
+ * from multiple starts, then union scoring of the superposed pairs with
+ * shape_screen.  Pairs: B holds one molecule per pair (n_pairs = B->n_mols),
+ * A one per pair or a single molecule shared by all pairs.  Poses as in
+ * shape_align_grad: (qw, qx, qy, qz, tx, ty, tz), B's atoms moved to
+ * R(q/|q|) c + t.  Invalid molecules give NaN and are reported by
+ * shape_check_data.
+ * ---------------------------------------------------------------------- */
+
+/* Alignment starts per pair, pose: device float [n_pairs][5 + n_random][7]:
+ * the given pose (identity), the four proper principal-axis alignments
+ * R = U_A D U_B^T (U: principal axes of the mixture covariance, descending,
+ * right-handed, sign-fixed; D = diag(1,1,1), diag(1,-1,-1), diag(-1,1,-1),
+ * diag(-1,-1,1)) with t = mu_A - R mu_B (mixture means), then n_random
+ * uniformly random rotations about B's mean (Shoemake, uniforms from Philox
+ * block (s, pair, 0x5157A27, 0) under the key seed), same centring.  FP64.
+ * Asynchronous.  Errors: SHAPE_E_INVAL, SHAPE_E_RANGE, SHAPE_E_NOMEM,
+ * SHAPE_E_HIP. */
+int shape_fo_starts(shape_ctx* ctx, const shape_mols* A, const shape_mols* B,
+                    int32_t n_random, uint64_t seed, void* stream, float* pose);
+
+/* First-order aligned Tanimoto T_FO = O/(O_AA + O_BB - O), O the
+ * first-order overlap of A and the moved B (Eq. fo), maximised by Adam
+ * (betas 0.9, 0.999, eps 1e-8, q renormalised after each step, the rule
+ * of shape_adam_pose with hardware reciprocals) for n_steps steps from each
+ * start.  pose: device float
+ * [n_pairs][n_starts][7], starts in, final poses out; T: device float
+ * [n_pairs][n_starts], T_FO at the final poses; grad (device float
+ * [n_pairs][n_starts][7] or NULL): dT_FO/dpose there.  n_steps = 0
+ * evaluates T_FO and its gradient at the given poses.  FP32, one wave per
+ * (pair, start), the whole optimisation in one launch.  Asynchronous.
+ * Errors: SHAPE_E_INVAL, SHAPE_E_RANGE (also molecules too large for the
+ * kernel's LDS), SHAPE_E_NOMEM, SHAPE_E_HIP. */
+int shape_fo_align(shape_ctx* ctx, const shape_mols* A, const shape_mols* B, int32_t n_starts,
+                   float* pose, int32_t n_steps, float lr, void* stream, float* T,
+                   float* grad);
+
+/* Per pair, the start with the largest T (lowest index on ties; NaN never
+ * wins): best_pose device float [n_pairs][7], best_T device float [n_pairs]
+ * (may be NULL).  T: [n_pairs][n_starts], pose: [n_pairs][n_starts][7].
+ * Asynchronous.  Errors: SHAPE_E_INVAL, SHAPE_E_RANGE, SHAPE_E_HIP. */
+int shape_best_pose(shape_ctx* ctx, int32_t n_pairs, int32_t n_starts, const float* T,
+                    const float* pose, void* stream, float* best_pose, float* best_T);
+
+/* Moved coordinates of every molecule of M by its pose (device float
+ * [n_mols][7]): xyz_out (device float [n_atoms][3]) = R(q/|q|) xyz + t.
+ * Asynchronous.  Errors: SHAPE_E_INVAL, SHAPE_E_RANGE, SHAPE_E_HIP. */
+int shape_apply_pose(shape_ctx* ctx, const shape_mols* M, const float* pose, void* stream,
+                     float* xyz_out);
+
+/* ------------------------------------------------------------------------
  * Learned triage (an addition to the paper's method: a surrogate that ranks a
  * library cheaply so that confidence-bounded IS refines only the head of the
  * ranking; IS stays the judge of every reported value).

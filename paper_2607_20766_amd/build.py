@@ -13,7 +13,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libshape_is.so")
-SOURCES = ["shape_kernels.hip", "shape_align.hip", "shape_surrogate.hip", "shape_api.hip"]
+SOURCES = ["shape_kernels.hip", "shape_align.hip", "shape_surrogate.hip", "shape_hybrid.hip",
+           "shape_api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 

@@ -684,6 +684,102 @@ int shape_align(shape_ctx* c, const shape_mols* A, const shape_mols* B, int32_t 
   }
 }
 
+// Pairs of the hybrid pipeline: B holds one molecule per pair, A one
+// molecule per pair or a single molecule shared by all pairs.
+int fo_pairs_check(shape_ctx* c, const shape_mols* A, const shape_mols* B) {
+  int rc;
+  if ((rc = check_mols(c, A, "A", false))) return rc;
+  if ((rc = check_mols(c, B, "B", false))) return rc;
+  if (A->n_mols != 1 && A->n_mols != B->n_mols)
+    return fail(c, SHAPE_E_RANGE, "A->n_mols = %d must be 1 or B->n_mols = %d", A->n_mols,
+                B->n_mols);
+  return SHAPE_OK;
+}
+
+shape::MolsDev mols_dev(const shape_mols* m) {
+  return shape::MolsDev{m->n_mols, m->max_atoms, m->n_atoms, m->atom_offset, m->xyz, m->alpha,
+                        m->mol_id};
+}
+
+int shape_fo_starts(shape_ctx* c, const shape_mols* A, const shape_mols* B, int32_t n_random,
+                    uint64_t seed, void* stream, float* pose) {
+  if (!c) return SHAPE_E_INVAL;
+  try {
+    int rc;
+    if ((rc = fo_pairs_check(c, A, B))) return rc;
+    if (n_random < 0 || n_random > 1024) return fail(c, SHAPE_E_RANGE, "n_random outside [0, 1024]");
+    if (!pose) return fail(c, SHAPE_E_INVAL, "pose is NULL");
+    if ((rc = set_device(c))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    shape::Prepared PA, PB;
+    if ((rc = prepare(c, A, true, st, &PA))) return rc;
+    if ((rc = prepare(c, B, false, st, &PB))) return rc;
+    HIP_TRY(c, shape::launch_fo_starts(mols_dev(A), mols_dev(B), PA.bad, PB.bad, n_random,
+                                       key_of(seed), pose, st),
+            "alignment starts kernel");
+    return SHAPE_OK;
+  } catch (...) {
+    return fail(c, SHAPE_E_HIP, "internal error");
+  }
+}
+
+int shape_fo_align(shape_ctx* c, const shape_mols* A, const shape_mols* B, int32_t n_starts,
+                   float* pose, int32_t n_steps, float lr, void* stream, float* T,
+                   float* grad) {
+  if (!c) return SHAPE_E_INVAL;
+  try {
+    int rc;
+    if ((rc = fo_pairs_check(c, A, B))) return rc;
+    if (n_starts < 1) return fail(c, SHAPE_E_RANGE, "n_starts < 1");
+    if ((int64_t)B->n_mols * n_starts > 0x7FFFFFFF)
+      return fail(c, SHAPE_E_RANGE, "pairs x starts exceeds 2^31 - 1");
+    if (n_steps < 0 || n_steps > 100000) return fail(c, SHAPE_E_RANGE, "n_steps outside [0, 1e5]");
+    if (n_steps > 0 && !(lr > 0.f)) return fail(c, SHAPE_E_RANGE, "lr must be > 0");
+    if (!pose || !T) return fail(c, SHAPE_E_INVAL, "pose and T are required");
+    if (shape::fo_align_lds_bytes(A->max_atoms, B->max_atoms) > c->lds_per_block)
+      return fail(c, SHAPE_E_RANGE, "molecules too large for the alignment kernel's LDS");
+    if ((rc = set_device(c))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    shape::Prepared PA, PB;
+    if ((rc = prepare(c, A, true, st, &PA))) return rc;
+    if ((rc = prepare(c, B, false, st, &PB))) return rc;
+    KernelTimer timer(c, st);
+    HIP_TRY(c, shape::launch_fo_align(mols_dev(A), mols_dev(B), PA.bad, PB.bad, n_starts,
+                                      n_steps, lr, pose, T, grad, st),
+            "first-order alignment kernel");
+    timer.stop();
+    return SHAPE_OK;
+  } catch (...) {
+    return fail(c, SHAPE_E_HIP, "internal error");
+  }
+}
+
+int shape_best_pose(shape_ctx* c, int32_t n_pairs, int32_t n_starts, const float* T,
+                    const float* pose, void* stream, float* best_pose, float* best_T) {
+  if (!c) return SHAPE_E_INVAL;
+  if (n_pairs < 0 || n_starts < 1) return fail(c, SHAPE_E_RANGE, "n_pairs < 0 or n_starts < 1");
+  if (n_pairs == 0) return SHAPE_OK;
+  if (!T || !pose || !best_pose) return fail(c, SHAPE_E_INVAL, "NULL array");
+  int rc = set_device(c);
+  if (rc) return rc;
+  HIP_TRY(c, shape::launch_best_pose(T, pose, n_pairs, n_starts, best_pose, best_T,
+                                     (hipStream_t)stream),
+          "best pose kernel");
+  return SHAPE_OK;
+}
+
+int shape_apply_pose(shape_ctx* c, const shape_mols* M, const float* pose, void* stream,
+                     float* xyz_out) {
+  if (!c) return SHAPE_E_INVAL;
+  int rc;
+  if ((rc = check_mols(c, M, "M", false))) return rc;
+  if (!pose || !xyz_out) return fail(c, SHAPE_E_INVAL, "NULL array");
+  if ((rc = set_device(c))) return rc;
+  HIP_TRY(c, shape::launch_apply_pose(mols_dev(M), pose, xyz_out, (hipStream_t)stream),
+          "apply pose kernel");
+  return SHAPE_OK;
+}
+
 int shape_features(shape_ctx* c, const shape_mols* M, void* stream, float* out) {
   if (!c) return SHAPE_E_INVAL;
   try {

@@ -112,6 +112,17 @@ hipError_t launch_fo_cross(const Prepared& Q, const int* offQ, const float* alph
                            const int* pairs, int n_pairs, int n_lib, float* out, hipStream_t st);
 hipError_t launch_gemm(const GemmArgs& g, hipStream_t st);
 size_t mlp_pack_bytes();
+// hybrid pipeline (first-order alignment)
+hipError_t launch_fo_starts(const MolsDev& A, const MolsDev& B, const int* badA,
+                            const int* badB, int n_random, uint2 key, float* pose,
+                            hipStream_t st);
+size_t fo_align_lds_bytes(int max_a, int max_b);
+hipError_t launch_fo_align(const MolsDev& A, const MolsDev& B, const int* badA, const int* badB,
+                           int n_starts, int n_steps, float lr, float* pose, float* T,
+                           float* grad, hipStream_t st);
+hipError_t launch_best_pose(const float* T, const float* pose, int n_pairs, int n_starts,
+                            float* best_pose, float* best_T, hipStream_t st);
+hipError_t launch_apply_pose(const MolsDev& M, const float* pose, float* out, hipStream_t st);
 hipError_t launch_seed_budget(const float* raw, int64_t ld, const int* idx, int k, double y_mean,
                               double y_std, double tau, int round, int cap, int* n_start,
                               hipStream_t st);

@@ -116,6 +116,12 @@ def load_library():
                                       ctypes.c_float, ctypes.c_float, ctypes.c_float, vp]
         L.shape_align.argtypes = [vp, ctypes.POINTER(ShapeMols), ctypes.POINTER(ShapeMols), i32,
                                   vp, i32, i32, ctypes.c_float, u64, vp, vp, vp]
+        L.shape_fo_starts.argtypes = [vp, ctypes.POINTER(ShapeMols), ctypes.POINTER(ShapeMols),
+                                      i32, u64, vp, vp]
+        L.shape_fo_align.argtypes = [vp, ctypes.POINTER(ShapeMols), ctypes.POINTER(ShapeMols),
+                                     i32, vp, i32, ctypes.c_float, vp, vp, vp]
+        L.shape_best_pose.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp]
+        L.shape_apply_pose.argtypes = [vp, ctypes.POINTER(ShapeMols), vp, vp, vp]
         L.shape_features.argtypes = [vp, ctypes.POINTER(ShapeMols), vp, vp]
         L.shape_pair_features.argtypes = [vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp]
         L.shape_mlp_infer.argtypes = [vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp]
@@ -377,6 +383,58 @@ class Engine:
         return T, best
 
     # -- learned triage ----------------------------------------------------------
+    # -- hybrid pipeline: first-order alignment ---------------------------------
+    def shape_fo_starts(self, A: Molecules, B: Molecules, n_random: int = 3, seed: int = 0,
+                        out=None, stream=None) -> torch.Tensor:
+        """Alignment starts [pairs, 5 + n_random, 7]: given pose, four
+        principal-axis alignments, random rotations."""
+        if out is None:
+            out = torch.empty(B.n_mols, 5 + int(n_random), 7, dtype=torch.float32,
+                              device=self.torch_device)
+        a, b = A.c_struct(), B.c_struct()
+        self._check(load_library().shape_fo_starts(self._ctx, ctypes.byref(a), ctypes.byref(b),
+                                                   int(n_random), int(seed), _stream(stream),
+                                                   _ptr(out)))
+        return out
+
+    def shape_fo_align(self, A: Molecules, B: Molecules, pose: torch.Tensor, n_steps: int = 50,
+                       lr: float = 0.05, T=None, need_grad: bool = False, stream=None):
+        """Adam on the first-order Tanimoto from each start; pose
+        [pairs, starts, 7] is updated in place.  Returns (T [pairs, starts],
+        dT/dpose at the final poses or None)."""
+        assert pose.is_contiguous() and pose.dtype == torch.float32
+        pairs, starts = pose.shape[0], pose.shape[1]
+        if T is None:
+            T = torch.empty(pairs, starts, dtype=torch.float32, device=self.torch_device)
+        g = (torch.empty(pairs, starts, 7, dtype=torch.float32, device=self.torch_device)
+             if need_grad else None)
+        a, b = A.c_struct(), B.c_struct()
+        self._check(load_library().shape_fo_align(self._ctx, ctypes.byref(a), ctypes.byref(b),
+                                                  starts, _ptr(pose), int(n_steps), float(lr),
+                                                  _stream(stream), _ptr(T), _ptr(g)))
+        return T, g
+
+    def shape_best_pose(self, T: torch.Tensor, pose: torch.Tensor, best_pose=None, best_T=None,
+                        stream=None):
+        pairs, starts = T.shape
+        if best_pose is None:
+            best_pose = torch.empty(pairs, 7, dtype=torch.float32, device=self.torch_device)
+        if best_T is None:
+            best_T = torch.empty(pairs, dtype=torch.float32, device=self.torch_device)
+        self._check(load_library().shape_best_pose(self._ctx, pairs, starts, _ptr(T), _ptr(pose),
+                                                   _stream(stream), _ptr(best_pose),
+                                                   _ptr(best_T)))
+        return best_pose, best_T
+
+    def shape_apply_pose(self, M: Molecules, pose: torch.Tensor, out=None,
+                         stream=None) -> torch.Tensor:
+        if out is None:
+            out = torch.empty_like(M.xyz)
+        m = M.c_struct()
+        self._check(load_library().shape_apply_pose(self._ctx, ctypes.byref(m), _ptr(pose),
+                                                    _stream(stream), _ptr(out)))
+        return out
+
     def shape_features(self, M: Molecules, out=None, stream=None) -> torch.Tensor:
         if out is None:
             out = torch.empty(M.n_mols, 24, dtype=torch.float32, device=self.torch_device)

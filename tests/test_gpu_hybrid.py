@@ -1,0 +1,172 @@
+"""GPU parity of the hybrid pipeline (first-order alignment, then union
+scoring) against the FP64 oracle: T_FO and its pose gradient, the alignment
+starts, Adam trajectories, best start, moved coordinates, and the pipeline
+end to end."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2607_20766_amd import molgen
+from paper_2607_20766_amd.engine import SHAPE_SCREEN_ADAPTIVE, Engine, ShapeError
+from paper_2607_20766_amd.hybrid import HybridScreen
+from tests.gpu_common import oracle_mol, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+QUERY_ID = 0xFFFFFF00
+
+
+@pytest.fixture(scope="module")
+def eng():
+    require_gpu()
+    return Engine(0)
+
+
+@pytest.fixture(scope="module")
+def pairs():
+    A = molgen.library(61, 6, 15, 45, workers=1)
+    B = molgen.library(62, 6, 15, 45, workers=1)
+    return A, B
+
+
+def _rot(q):
+    w, x, y, z = np.asarray(q, np.float64) / np.linalg.norm(q)
+    return np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
+                     [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
+                     [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)]])
+
+
+def _poses(n_pairs, n_starts, seed=3):
+    p = molgen.random_poses(seed, n_pairs, n_starts).astype(np.float32)
+    p[..., 4:] *= 0.5
+    return p
+
+
+def test_value_and_gradient_match_oracle(eng, pairs):
+    A, B = pairs
+    dA, dB = eng.molecules(A), eng.molecules(B)
+    poses = _poses(A.n_mols, 4)
+    dp = torch.from_numpy(poses.copy()).cuda()
+    print("case: T_FO and gradient, 6 pairs x 4 poses", flush=True)
+    T, g = eng.shape_fo_align(dA, dB, dp, n_steps=0, need_grad=True)
+    T, g = T.cpu().numpy(), g.cpu().numpy()
+    assert np.array_equal(dp.cpu().numpy(), poses)   # no step: poses unchanged
+    for p in range(A.n_mols):
+        Tr, gr = O.fo_align_grad(oracle_mol(O, A.mol(p)), oracle_mol(O, B.mol(p)),
+                                 poses[p].astype(np.float64))
+        assert np.abs(T[p] - Tr).max() <= 1e-5 * np.abs(Tr).max()
+        assert np.abs(g[p] - gr).max() <= 1e-4 * np.abs(gr).max(), (p, g[p], gr)
+
+
+def test_starts_match_oracle(eng, pairs):
+    A, B = pairs
+    dA, dB = eng.molecules(A), eng.molecules(B)
+    st = eng.shape_fo_starts(dA, dB, n_random=3, seed=9).cpu().numpy()
+    assert st.shape == (A.n_mols, 8, 7)
+    for p in range(A.n_mols):
+        ref = O.fo_starts(oracle_mol(O, A.mol(p)), oracle_mol(O, B.mol(p)), pair_id=p,
+                          n_random=3, seed=9)
+        for s in range(8):
+            assert np.abs(_rot(st[p, s, :4]) - _rot(ref[s, :4])).max() <= 1e-5, (p, s)
+            assert np.abs(st[p, s, 4:] - ref[s, 4:]).max() <= 1e-4, (p, s)
+
+
+def test_shared_query_broadcasts(eng, pairs):
+    """A single A molecule serves every pair, as the same molecule repeated."""
+    _, B = pairs
+    q = molgen.molecule(1, 0, 30)
+    Q = eng.molecules(q)
+    Qrep = eng.molecules(molgen.MolSet.concat([q] * B.n_mols))
+    dB = eng.molecules(B)
+    s1 = eng.shape_fo_starts(Q, dB, n_random=2, seed=1)
+    s2 = eng.shape_fo_starts(Qrep, dB, n_random=2, seed=1)
+    assert torch.equal(s1, s2)
+    T1, _ = eng.shape_fo_align(Q, dB, s1, n_steps=5)
+    T2, _ = eng.shape_fo_align(Qrep, dB, s2, n_steps=5)
+    assert torch.equal(T1, T2) and torch.equal(s1, s2)
+
+
+@pytest.mark.parametrize("steps", [10, 60])
+def test_adam_matches_oracle(eng, pairs, steps):
+    A, B = pairs
+    dA, dB = eng.molecules(A), eng.molecules(B)
+    poses = _poses(A.n_mols, 3, seed=5)
+    dp = torch.from_numpy(poses.copy()).cuda()
+    print(f"case: first-order Adam, {steps} steps", flush=True)
+    T, _ = eng.shape_fo_align(dA, dB, dp, n_steps=steps, lr=0.05)
+    T, pg = T.cpu().numpy(), dp.cpu().numpy()
+    for p in range(A.n_mols):
+        pr, Tr = O.fo_align_adam(oracle_mol(O, A.mol(p)), oracle_mol(O, B.mol(p)),
+                                 poses[p].astype(np.float64), n_steps=steps, lr=0.05)
+        if steps <= 10:
+            # FP32 and FP64 trajectories stay together over a few steps
+            assert np.abs(pg[p] - pr).max() <= 1e-3, (p, pg[p], pr)
+            assert np.abs(T[p] - Tr).max() <= 1e-4
+        # and reach the same optimum value from every start
+        assert np.abs(T[p].max() - Tr.max()) <= 2e-3
+        assert np.all(T[p] >= O.fo_align_grad(oracle_mol(O, A.mol(p)), oracle_mol(O, B.mol(p)),
+                                              poses[p].astype(np.float64))[0] - 1e-3)
+
+
+def test_best_pose_and_apply_pose(eng, pairs):
+    _, B = pairs
+    rng = np.random.default_rng(2)
+    T = rng.uniform(size=(B.n_mols, 5)).astype(np.float32)
+    T[1, :] = np.nan
+    T[2, 3] = np.nan
+    T[3, 1] = T[3, 4] = 2.0       # tie: the lower index wins
+    pose = _poses(B.n_mols, 5, seed=8)
+    bp, bT = eng.shape_best_pose(torch.from_numpy(T).cuda(), torch.from_numpy(pose).cuda())
+    bp, bT = bp.cpu().numpy(), bT.cpu().numpy()
+    for p in range(B.n_mols):
+        key = np.where(np.isnan(T[p]), -np.inf, T[p])
+        b = int(np.argmax(key)) if np.isfinite(key).any() else 0
+        assert np.array_equal(bp[p], pose[p, b]), p
+    dB = eng.molecules(B)
+    moved = eng.shape_apply_pose(dB, torch.from_numpy(pose[:, 0].copy()).cuda()).cpu().numpy()
+    for p in range(B.n_mols):
+        a0, a1 = B.offsets[p], B.offsets[p + 1]
+        want = B.xyz[a0:a1].astype(np.float64) @ _rot(pose[p, 0, :4]).T + pose[p, 0, 4:]
+        assert np.abs(moved[a0:a1] - want).max() <= 1e-5
+
+
+def test_hybrid_screen_end_to_end(eng):
+    q = molgen.molecule(1, 0, 30)
+    L = molgen.library(63, 77, 10, 50, workers=1)
+    Q = eng.molecules(q, mol_id=[QUERY_ID])
+    lib = eng.molecules(L)
+    hs = HybridScreen(eng, n_random=3, n_steps=40, lr=0.05, seed=2)
+    print("case: hybrid screen, 77 molecules", flush=True)
+    bufs = hs.screen(Q, lib)
+    out = {k: v.cpu().numpy() for k, v in bufs["out"].items()}
+    # the scores are those of the union screen of the superposed library
+    direct = eng.shape_screen(Q, hs.moved(lib, bufs), mode=SHAPE_SCREEN_ADAPTIVE, seed=2)
+    for k in out:
+        assert np.array_equal(out[k], direct[k].cpu().numpy()), k
+    # alignment raised the first-order Tanimoto over the given pose for every pair
+    ident = torch.zeros(L.n_mols, 1, 7, device="cuda")
+    ident[:, 0, 0] = 1.0
+    T0, _ = eng.shape_fo_align(Q, lib, ident, n_steps=0)
+    bT = bufs["best_T_fo"].cpu().numpy()
+    assert np.all(bT >= T0.cpu().numpy()[:, 0] - 1e-6)
+    # and the union Tanimoto on average
+    plain = eng.shape_screen(Q, lib, mode=SHAPE_SCREEN_ADAPTIVE, seed=2)["T"].cpu().numpy()
+    assert out["T"].mean() > plain.mean()
+    assert np.all(np.abs(out["se_T"]) <= 0.005 * (1 + 1e-6) + (out["n_used"] == 65536))
+
+
+def test_invalid_molecule_gives_nan(eng, pairs):
+    A, B = pairs
+    Bbad = molgen.MolSet.concat([B.mol(p) for p in range(B.n_mols)])
+    Bbad.xyz[Bbad.offsets[2] + 1, 0] = np.nan
+    dA, dB = eng.molecules(A), eng.molecules(Bbad)
+    st = eng.shape_fo_starts(dA, dB, n_random=1)
+    T, _ = eng.shape_fo_align(dA, dB, st, n_steps=3)
+    T = T.cpu().numpy()
+    assert np.all(np.isnan(T[2])) and np.isfinite(np.delete(T, 2, axis=0)).all()
+    with pytest.raises(ShapeError):
+        eng.shape_check_data()
+    with pytest.raises(ShapeError):
+        eng.shape_fo_align(dA, eng.molecules(molgen.library(1, 3, 10, 20, workers=1)), st[:3],
+                           n_steps=1)
