@@ -310,6 +310,19 @@ int shape_align(shape_ctx* ctx, const shape_mols* A, const shape_mols* B, int32_
                 float* pose, int32_t n_samples, int32_t n_steps, float lr, uint64_t seed,
                 void* stream, float* T_final, int32_t* best);
 
+/* Dense-grid quadrature reference (the grid ground truth of the paper's
+ * accuracy comparison): for one pair A, B (n_mols == 1 each), the trapezoid
+ * rule on the cubic grid of spacing h over the box of all atom centres
+ * grown by pad on every side (ceil(extent/h) + 1 points per axis, end
+ * planes weighted 1/2), FP64.  out8 (HOST double[8]): int uA uB, int uA^2,
+ * int uB^2, int uA, int uB, int mA mB, int mA^2, int mB^2 (u the union
+ * occupancy, m the first-order density).  Synchronises `stream`.
+ * Errors: SHAPE_E_INVAL, SHAPE_E_RANGE (grid or molecules too large),
+ * SHAPE_E_DATA, SHAPE_E_NOMEM, SHAPE_E_HIP; SHAPE_E_UNSUPPORTED during
+ * graph capture. */
+int shape_grid_integrals(shape_ctx* ctx, const shape_mols* A, const shape_mols* B, double h,
+                         double pad, void* stream, double* out8);
+
 /* ------------------------------------------------------------------------
  * Hybrid pipeline (section "Differentiable alignment and the hybrid
  * pipeline"): rigid alignment on the analytic first-order overlap (Eq. fo)

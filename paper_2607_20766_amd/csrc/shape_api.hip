@@ -29,6 +29,7 @@ enum Slot {
   S_PARTIALS, S_RESULT, S_QS, S_QF2,
   S_SELF_A, S_SELF_B, S_ADAM_M, S_ADAM_V, S_ADAM_STEP, S_GRAD,
   S_MSE, S_TOPK_SEL, S_TOPK_HIST, S_TOPK_GT, S_TOPK_EQ, S_COLSUM, S_TUNE, S_MLP_PACK, S_FEAT_MOM, S_GEMM_PART,
+  S_GRID_BOX, S_GRID_TAB, S_GRID_PART,
   S_COUNT
 };
 
@@ -778,6 +779,84 @@ int shape_apply_pose(shape_ctx* c, const shape_mols* M, const float* pose, void*
   HIP_TRY(c, shape::launch_apply_pose(mols_dev(M), pose, xyz_out, (hipStream_t)stream),
           "apply pose kernel");
   return SHAPE_OK;
+}
+
+int shape_grid_integrals(shape_ctx* c, const shape_mols* A, const shape_mols* B, double h,
+                         double pad, void* stream, double* out8) {
+  if (!c) return SHAPE_E_INVAL;
+  if (c->capturing) return refuse_in_capture(c, "shape_grid_integrals");
+  try {
+    int rc;
+    if ((rc = check_mols(c, A, "A", true))) return rc;
+    if ((rc = check_mols(c, B, "B", true))) return rc;
+    if (!out8) return fail(c, SHAPE_E_INVAL, "out is NULL");
+    if (!(h > 0.0) || !isfinite(h) || !(pad >= 0.0) || !isfinite(pad))
+      return fail(c, SHAPE_E_RANGE, "h must be > 0 and pad >= 0 (finite)");
+    if ((rc = set_device(c))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    // invalid molecules are reported before the grid reads them
+    shape::Prepared PA, PB;
+    if ((rc = prepare(c, A, true, st, &PA))) return rc;
+    if ((rc = prepare(c, B, false, st, &PB))) return rc;
+    int bad[2] = {0, 0}, offA[2] = {0, 0}, offB[2] = {0, 0};
+    HIP_TRY(c, hipMemcpyAsync(&bad[0], PA.bad, sizeof(int), hipMemcpyDeviceToHost, st), "copy");
+    HIP_TRY(c, hipMemcpyAsync(&bad[1], PB.bad, sizeof(int), hipMemcpyDeviceToHost, st), "copy");
+    HIP_TRY(c, hipMemcpyAsync(offA, A->atom_offset, sizeof offA, hipMemcpyDeviceToHost, st),
+            "copy");
+    HIP_TRY(c, hipMemcpyAsync(offB, B->atom_offset, sizeof offB, hipMemcpyDeviceToHost, st),
+            "copy");
+    HIP_TRY(c, hipStreamSynchronize(st), "hipStreamSynchronize");
+    if (bad[0] || bad[1]) {
+      HIP_TRY(c, shape::launch_fill_int(c->flag, 1, 0, st), "flag reset");
+      return fail(c, SHAPE_E_DATA, "invalid molecule data in %s", bad[0] ? "A" : "B");
+    }
+    // the preparation has validated both ranges
+    const int na = offA[1] - offA[0], nb = offB[1] - offB[0];
+    const float* xa = A->xyz + 3 * (size_t)offA[0];
+    const float* aa = A->alpha + offA[0];
+    const float* xb = B->xyz + 3 * (size_t)offB[0];
+    const float* ab = B->alpha + offB[0];
+    void *box_d, *tab, *part;
+    if ((rc = ensure(c, S_GRID_BOX, 16 * sizeof(double), &box_d))) return rc;
+    HIP_TRY(c, shape::launch_grid_box(xa, na, xb, nb, (double*)box_d, st), "grid box");
+    double box[6];
+    HIP_TRY(c, hipMemcpyAsync(box, box_d, sizeof box, hipMemcpyDeviceToHost, st), "copy");
+    HIP_TRY(c, hipStreamSynchronize(st), "hipStreamSynchronize");
+    shape::GridDims g;
+    g.h = h;
+    g.nmax = 0;
+    int64_t points = 1;
+    for (int d = 0; d < 3; ++d) {
+      g.lo[d] = box[d] - pad;
+      const double hi = box[3 + d] + pad;
+      const double nd = ceil((hi - g.lo[d]) / h) + 1.0;
+      if (nd > 65536.0) return fail(c, SHAPE_E_RANGE, "grid exceeds 65,536 points per axis");
+      g.n[d] = (int)nd;
+      g.nmax = g.n[d] > g.nmax ? g.n[d] : g.nmax;
+      points *= g.n[d];
+    }
+    if (points > ((int64_t)1 << 36)) return fail(c, SHAPE_E_RANGE, "grid exceeds 2^36 points");
+    const int64_t cols = (int64_t)g.n[0] * g.n[1];
+    if (cols > 0x7FFFFFFF) return fail(c, SHAPE_E_RANGE, "grid has too many columns");
+    const size_t lds = (size_t)(na + nb) * sizeof(double);
+    if (lds + 8 * 4 * sizeof(double) > c->lds_per_block)
+      return fail(c, SHAPE_E_RANGE, "molecules too large for the grid kernel's LDS");
+    if ((rc = ensure(c, S_GRID_TAB, (size_t)3 * (na + nb) * g.nmax * sizeof(double), &tab)))
+      return rc;
+    if ((rc = ensure(c, S_GRID_PART, (size_t)cols * 8 * sizeof(double), &part))) return rc;
+    KernelTimer timer(c, st);
+    HIP_TRY(c, shape::launch_grid(xa, aa, na, xb, ab, nb, g, (double*)tab, (double*)part,
+                                  (double*)box_d + 8, st),
+            "grid kernels");
+    timer.stop();
+    HIP_TRY(c, hipMemcpyAsync(out8, (double*)box_d + 8, 8 * sizeof(double),
+                              hipMemcpyDeviceToHost, st),
+            "result copy");
+    HIP_TRY(c, hipStreamSynchronize(st), "hipStreamSynchronize");
+    return SHAPE_OK;
+  } catch (...) {
+    return fail(c, SHAPE_E_HIP, "internal error");
+  }
 }
 
 int shape_features(shape_ctx* c, const shape_mols* M, void* stream, float* out) {

@@ -112,6 +112,18 @@ hipError_t launch_fo_cross(const Prepared& Q, const int* offQ, const float* alph
                            const int* pairs, int n_pairs, int n_lib, float* out, hipStream_t st);
 hipError_t launch_gemm(const GemmArgs& g, hipStream_t st);
 size_t mlp_pack_bytes();
+// dense-grid quadrature
+struct GridDims {
+  double lo[3];
+  double h;
+  int n[3];
+  int nmax;
+};
+hipError_t launch_grid_box(const float* xa, int na, const float* xb, int nb, double* box,
+                           hipStream_t st);
+hipError_t launch_grid(const float* xa, const float* aa, int na, const float* xb,
+                       const float* ab, int nb, const GridDims& g, double* tables, double* part,
+                       double* out, hipStream_t st);
 // hybrid pipeline (first-order alignment)
 hipError_t launch_fo_starts(const MolsDev& A, const MolsDev& B, const int* badA,
                             const int* badB, int n_random, uint2 key, float* pose,

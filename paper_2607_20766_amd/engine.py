@@ -53,6 +53,10 @@ RESULT_FIELDS = ("O_ab", "O_aa", "O_bb", "V_a", "V_b", "T",
                  "Ofo_aa_is", "Ofo_bb_is")
 
 
+# shape_grid_integrals outputs: union overlaps, union volumes, first-order overlaps
+GRID_FIELDS = ("O_ab", "O_aa", "O_bb", "V_a", "V_b", "Ofo_ab", "Ofo_aa", "Ofo_bb")
+
+
 class ShapeResult(ctypes.Structure):
     _fields_ = [(f, ctypes.c_double) for f in RESULT_FIELDS] + [
         ("n_a", ctypes.c_int64), ("n_b", ctypes.c_int64)]
@@ -116,6 +120,9 @@ def load_library():
                                       ctypes.c_float, ctypes.c_float, ctypes.c_float, vp]
         L.shape_align.argtypes = [vp, ctypes.POINTER(ShapeMols), ctypes.POINTER(ShapeMols), i32,
                                   vp, i32, i32, ctypes.c_float, u64, vp, vp, vp]
+        L.shape_grid_integrals.argtypes = [vp, ctypes.POINTER(ShapeMols),
+                                           ctypes.POINTER(ShapeMols), d, d, vp,
+                                           ctypes.POINTER(d)]
         L.shape_fo_starts.argtypes = [vp, ctypes.POINTER(ShapeMols), ctypes.POINTER(ShapeMols),
                                       i32, u64, vp, vp]
         L.shape_fo_align.argtypes = [vp, ctypes.POINTER(ShapeMols), ctypes.POINTER(ShapeMols),
@@ -383,6 +390,17 @@ class Engine:
         return T, best
 
     # -- learned triage ----------------------------------------------------------
+    # -- grid reference ------------------------------------------------------------
+    def shape_grid_integrals(self, A: Molecules, B: Molecules, h: float = 0.2,
+                             pad: float = 6.5, stream=None) -> dict:
+        """Trapezoid-rule integrals of one pair on a cubic grid (FP64)."""
+        out = (ctypes.c_double * 8)()
+        a, b = A.c_struct(), B.c_struct()
+        self._check(load_library().shape_grid_integrals(self._ctx, ctypes.byref(a),
+                                                        ctypes.byref(b), float(h), float(pad),
+                                                        _stream(stream), out))
+        return dict(zip(GRID_FIELDS, list(out)))
+
     # -- hybrid pipeline: first-order alignment ---------------------------------
     def shape_fo_starts(self, A: Molecules, B: Molecules, n_random: int = 3, seed: int = 0,
                         out=None, stream=None) -> torch.Tensor:
