@@ -369,6 +369,17 @@ int shape_fo_align(shape_ctx* ctx, const shape_mols* A, const shape_mols* B, int
 int shape_best_pose(shape_ctx* ctx, int32_t n_pairs, int32_t n_starts, const float* T,
                     const float* pose, void* stream, float* best_pose, float* best_T);
 
+/* Conformer ensembles (max over conformers, the paper's accuracy lever):
+ * for each group g of consecutive entries [group_offset[g],
+ * group_offset[g+1]) of T (device float, e.g. one shape_screen output over a
+ * library holding every conformer), best_T[g] = the largest T (device float
+ * [n_groups]) and best_idx[g] its entry (device int32 [n_groups] or NULL);
+ * lowest entry on ties, NaN never wins (all NaN: NaN and -1).
+ * group_offset: device int32 [n_groups + 1], non-decreasing.  Asynchronous.
+ * Errors: SHAPE_E_INVAL, SHAPE_E_RANGE, SHAPE_E_HIP. */
+int shape_group_max(shape_ctx* ctx, const float* T, const int32_t* group_offset,
+                    int32_t n_groups, void* stream, float* best_T, int32_t* best_idx);
+
 /* Moved coordinates of every molecule of M by its pose (device float
  * [n_mols][7]): xyz_out (device float [n_atoms][3]) = R(q/|q|) xyz + t.
  * Asynchronous.  Errors: SHAPE_E_INVAL, SHAPE_E_RANGE, SHAPE_E_HIP. */

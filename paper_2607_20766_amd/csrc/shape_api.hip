@@ -769,6 +769,20 @@ int shape_best_pose(shape_ctx* c, int32_t n_pairs, int32_t n_starts, const float
   return SHAPE_OK;
 }
 
+int shape_group_max(shape_ctx* c, const float* T, const int32_t* group_offset, int32_t n_groups,
+                    void* stream, float* best_T, int32_t* best_idx) {
+  if (!c) return SHAPE_E_INVAL;
+  if (n_groups < 0) return fail(c, SHAPE_E_RANGE, "n_groups < 0");
+  if (n_groups == 0) return SHAPE_OK;
+  if (!T || !group_offset || !best_T) return fail(c, SHAPE_E_INVAL, "NULL array");
+  int rc = set_device(c);
+  if (rc) return rc;
+  HIP_TRY(c, shape::launch_group_max(T, group_offset, n_groups, best_T, best_idx,
+                                     (hipStream_t)stream),
+          "group max kernel");
+  return SHAPE_OK;
+}
+
 int shape_apply_pose(shape_ctx* c, const shape_mols* M, const float* pose, void* stream,
                      float* xyz_out) {
   if (!c) return SHAPE_E_INVAL;

@@ -388,6 +388,26 @@ __global__ void k_best_pose(const float* __restrict__ T, const float* __restrict
   if (best_T) best_T[p] = T[(size_t)p * n_starts + b];
 }
 
+// Conformer ensembles: the largest T of each group of consecutive entries
+// (max over conformers); lowest index on ties, NaN never wins (a group of
+// NaN gives NaN and index -1).
+__global__ void k_group_max(const float* __restrict__ T, const int* __restrict__ goff,
+                            int n_groups, float* __restrict__ best_T, int* __restrict__ best_idx) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n_groups) return;
+  int b = -1;
+  float bv = -INFINITY;
+  for (int e = goff[g]; e < goff[g + 1]; ++e) {
+    const float t = T[e];
+    if (t > bv || (b < 0 && t == bv)) {
+      bv = t;
+      b = e;
+    }
+  }
+  best_T[g] = b < 0 ? __builtin_nanf("") : bv;
+  if (best_idx) best_idx[g] = b;
+}
+
 // Moved coordinates xyz_out = R(q/|q|) xyz + t, one wave per molecule.
 __global__ __launch_bounds__(64) void k_apply_pose(MolsDev M, const float* __restrict__ pose,
                                                    float* __restrict__ out) {
@@ -439,6 +459,13 @@ hipError_t launch_best_pose(const float* T, const float* pose, int n_pairs, int 
                             float* best_pose, float* best_T, hipStream_t st) {
   hipLaunchKernelGGL(k_best_pose, dim3((n_pairs + 255) / 256), dim3(256), 0, st, T, pose,
                      n_pairs, n_starts, best_pose, best_T);
+  return hipGetLastError();
+}
+
+hipError_t launch_group_max(const float* T, const int* goff, int n_groups, float* best_T,
+                            int* best_idx, hipStream_t st) {
+  hipLaunchKernelGGL(k_group_max, dim3((n_groups + 255) / 256), dim3(256), 0, st, T, goff,
+                     n_groups, best_T, best_idx);
   return hipGetLastError();
 }
 

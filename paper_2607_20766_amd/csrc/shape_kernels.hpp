@@ -135,6 +135,8 @@ hipError_t launch_fo_align(const MolsDev& A, const MolsDev& B, const int* badA, 
 hipError_t launch_best_pose(const float* T, const float* pose, int n_pairs, int n_starts,
                             float* best_pose, float* best_T, hipStream_t st);
 hipError_t launch_apply_pose(const MolsDev& M, const float* pose, float* out, hipStream_t st);
+hipError_t launch_group_max(const float* T, const int* goff, int n_groups, float* best_T,
+                            int* best_idx, hipStream_t st);
 hipError_t launch_seed_budget(const float* raw, int64_t ld, const int* idx, int k, double y_mean,
                               double y_std, double tau, int round, int cap, int* n_start,
                               hipStream_t st);

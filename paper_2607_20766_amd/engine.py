@@ -129,6 +129,7 @@ def load_library():
                                      i32, vp, i32, ctypes.c_float, vp, vp, vp]
         L.shape_best_pose.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp]
         L.shape_apply_pose.argtypes = [vp, ctypes.POINTER(ShapeMols), vp, vp, vp]
+        L.shape_group_max.argtypes = [vp, vp, vp, i32, vp, vp, vp]
         L.shape_features.argtypes = [vp, ctypes.POINTER(ShapeMols), vp, vp]
         L.shape_pair_features.argtypes = [vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp]
         L.shape_mlp_infer.argtypes = [vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp]
@@ -443,6 +444,21 @@ class Engine:
                                                    _stream(stream), _ptr(best_pose),
                                                    _ptr(best_T)))
         return best_pose, best_T
+
+    def shape_group_max(self, T: torch.Tensor, group_offset: torch.Tensor, best_T=None,
+                        best_idx=None, stream=None):
+        """Max over each group of consecutive entries (conformer ensembles):
+        (best T [groups], its entry [groups])."""
+        group_offset = group_offset.to(torch.int32).contiguous()
+        g = group_offset.numel() - 1
+        if best_T is None:
+            best_T = torch.empty(g, dtype=torch.float32, device=self.torch_device)
+        if best_idx is None:
+            best_idx = torch.empty(g, dtype=torch.int32, device=self.torch_device)
+        self._check(load_library().shape_group_max(self._ctx, _ptr(T.contiguous()),
+                                                   _ptr(group_offset), g, _stream(stream),
+                                                   _ptr(best_T), _ptr(best_idx)))
+        return best_T, best_idx
 
     def shape_apply_pose(self, M: Molecules, pose: torch.Tensor, out=None,
                          stream=None) -> torch.Tensor:

@@ -64,3 +64,51 @@ class HybridScreen:
                        round_per_pair=self.round_per_pair, cap_per_pair=self.cap_per_pair,
                        tau=self.tau, seed=self.seed, out=bufs["out"])
         return bufs
+
+
+class EnsembleScreen:
+    """Conformer ensembles (max over conformers, the paper's accuracy lever):
+    every conformer of every library molecule is scored against the query —
+    at its given pose, or first aligned by the hybrid pipeline — and each
+    molecule keeps its best conformer (shape_group_max)."""
+
+    def __init__(self, eng: Engine, hybrid: HybridScreen | None = None, tau: float = 0.005,
+                 round_per_pair: int = 512, cap_per_pair: int = 65536, seed: int = 0):
+        self.eng = eng
+        self.hybrid = hybrid
+        self.tau = tau
+        self.round_per_pair = round_per_pair
+        self.cap_per_pair = cap_per_pair
+        self.seed = seed
+
+    def buffers(self, conf_lib: Molecules, n_mols: int) -> dict:
+        dev = self.eng.torch_device
+        n = conf_lib.n_mols
+        if self.hybrid is not None:
+            b = self.hybrid.buffers(conf_lib)
+        else:
+            f32 = dict(dtype=torch.float32, device=dev)
+            out = {k: torch.empty(n, **f32) for k in ("T", "se_T", "O_ab", "O_aa", "O_bb")}
+            out["n_used"] = torch.empty(n, dtype=torch.int32, device=dev)
+            b = {"out": out}
+        b["best_T"] = torch.empty(n_mols, dtype=torch.float32, device=dev)
+        b["best_entry"] = torch.empty(n_mols, dtype=torch.int32, device=dev)
+        return b
+
+    def screen(self, query: Molecules, conf_lib: Molecules, group_offset: torch.Tensor,
+               bufs: dict | None = None) -> dict:
+        """Returns bufs with best_T and best_entry per molecule and the
+        per-conformer IS outputs in out."""
+        n_mols = group_offset.numel() - 1
+        if bufs is None:
+            bufs = self.buffers(conf_lib, n_mols)
+        if self.hybrid is not None:
+            self.hybrid.screen(query, conf_lib, bufs)
+        else:
+            self.eng.shape_screen(query, conf_lib, mode=SHAPE_SCREEN_ADAPTIVE,
+                                  round_per_pair=self.round_per_pair,
+                                  cap_per_pair=self.cap_per_pair, tau=self.tau, seed=self.seed,
+                                  out=bufs["out"])
+        self.eng.shape_group_max(bufs["out"]["T"], group_offset, best_T=bufs["best_T"],
+                                 best_idx=bufs["best_entry"])
+        return bufs

@@ -124,17 +124,29 @@ def _random_perp(rng, u):
             return g / n
 
 
-def _grow_batch(rng: np.random.Generator, sizes: np.ndarray) -> np.ndarray:
-    """Grow len(sizes) chains at once; returns positions [M, max(sizes), 3]."""
+def _grow_batch(rng: np.random.Generator, sizes: np.ndarray, fixed_parents=None,
+                parents_out=None):
+    """Grow len(sizes) chains at once; returns positions [M, max(sizes), 3].
+
+    fixed_parents [M, nmax] (optional) fixes the bonded parent of every atom,
+    so the chains keep a given topology and only bond angles and torsions
+    are redrawn (conformers); a chain whose atom finds no acceptable
+    placement in 300 draws is abandoned and flagged in the second return
+    value.  parents_out [M, nmax] (optional) receives the parents chosen.
+    """
     M = sizes.size
     nmax = int(sizes.max())
     pos = np.zeros((M, nmax, 3))
     nbr = np.full((M, nmax, 4), -1, np.int32)
     deg = np.zeros((M, nmax), np.int32)
     topo = np.zeros((M, nmax, nmax), np.int16)
+    failed = np.zeros(M, bool)
+
+    def done():
+        return pos if fixed_parents is None else (pos, failed)
 
     if nmax == 1:
-        return pos
+        return done()
     # atom 1: random direction from atom 0
     act = np.nonzero(sizes > 1)[0]
     d = _unit(rng.standard_normal((act.size, 3)))
@@ -145,21 +157,27 @@ def _grow_batch(rng: np.random.Generator, sizes: np.ndarray) -> np.ndarray:
     deg[act, 1] = 1
     topo[act, 0, 1] = topo[act, 1, 0] = 1
 
+    if parents_out is not None:
+        parents_out[:, :2] = [-1, 0]
     for t in range(2, nmax):
-        act = np.nonzero(sizes > t)[0]
-        # parent choice
-        newest_ok = deg[act, t - 1] < 4
-        extend = (rng.random(act.size) < 0.75) & newest_ok
+        act = np.nonzero((sizes > t) & ~failed)[0]
 
         def pick_random_parent(idx):
             free = deg[idx, :t] < 4
             r = rng.random((idx.size, t)) * free
             return np.argmax(r, axis=1).astype(np.int32)
 
-        parent = np.where(extend, t - 1, 0).astype(np.int32)
-        nr = ~extend
-        if nr.any():
-            parent[nr] = pick_random_parent(act[nr])
+        if fixed_parents is None:
+            # parent choice
+            newest_ok = deg[act, t - 1] < 4
+            extend = (rng.random(act.size) < 0.75) & newest_ok
+            parent = np.where(extend, t - 1, 0).astype(np.int32)
+            nr = ~extend
+            if nr.any():
+                parent[nr] = pick_random_parent(act[nr])
+        else:
+            parent = fixed_parents[act, t].astype(np.int32)
+        restarts = np.zeros(act.size, np.int32)
         tries = np.zeros(act.size, np.int32)
         todo = np.arange(act.size)
         guard = 0
@@ -195,7 +213,7 @@ def _grow_batch(rng: np.random.Generator, sizes: np.ndarray) -> np.ndarray:
             w = np.cross(u, v)
             # K consecutive draws per molecule are evaluated at once; the first
             # acceptable one (in draw order) is taken, as if drawn one by one.
-            K = 1 if todo.size > 512 else KBATCH
+            K = 1 if todo.size > 512 else (KBATCH if fixed_parents is None else 5 * KBATCH)
             theta = rng.uniform(ANGLE_LO, ANGLE_HI, (todo.size, K))
             phi = rng.uniform(-math.pi, math.pi, (todo.size, K))
             dvec = (np.cos(theta)[..., None] * u[:, None] + np.sin(theta)[..., None]
@@ -233,14 +251,23 @@ def _grow_batch(rng: np.random.Generator, sizes: np.ndarray) -> np.ndarray:
                 deg[am, t] = 1
                 topo[am, t, :t] = topo[am, ap, :t] + 1
                 topo[am, :t, t] = topo[am, t, :t]
+                if parents_out is not None:
+                    parents_out[am, t] = ap
             rej = todo[~ok]
             tries[rej] = np.minimum(tries[rej] + K, TORSION_TRIES)
             re = rej[tries[rej] >= TORSION_TRIES]
             if re.size:
-                parent[re] = pick_random_parent(act[re])
                 tries[re] = 0
+                if fixed_parents is None:
+                    parent[re] = pick_random_parent(act[re])
+                else:
+                    restarts[re] += 1
+                    dead = re[restarts[re] >= 6]
+                    if dead.size:
+                        failed[act[dead]] = True
+                        rej = np.setdiff1d(rej, dead)
             todo = rej
-    return pos
+    return done()
 
 
 def principal_frame(xyz: np.ndarray, radius: np.ndarray) -> np.ndarray:
@@ -326,6 +353,74 @@ def library(config_seed: int, n_mols: int, lo: int, hi: int,
     else:
         parts = [_batch(e, s) for e, s in jobs]
     return MolSet.concat(parts)
+
+
+CONF_CHUNK = 1024
+
+
+def _conformer_chunk(config_seed: int, chunk: int, sizes: np.ndarray, n_conf: int):
+    nm = sizes.size
+    nmax = int(sizes.max())
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(
+        [int(config_seed), 0xC0F, int(chunk)])))
+    par = np.full((nm, nmax), -1, np.int32)
+    base = _grow_batch(rng, sizes, parents_out=par)
+    elem = rng.choice(len(ELEMENTS), size=(nm, nmax), p=ELEMENT_P)
+    confs = [base]
+    for c in range(1, n_conf):
+        pos = np.zeros_like(base)
+        todo = np.arange(nm)
+        for attempt in range(20):
+            r = np.random.Generator(np.random.PCG64(np.random.SeedSequence(
+                [int(config_seed), 0xC0F, int(chunk), c, attempt])))
+            p, failed = _grow_batch(r, sizes[todo], fixed_parents=par[todo])
+            good = ~failed
+            pos[todo[good], :p.shape[1]] = p[good]
+            todo = todo[failed]
+            if todo.size == 0:
+                break
+        pos[todo] = base[todo]  # not completed in 20 attempts: the grown shape
+        confs.append(pos)
+    allpos = np.stack(confs, 1).reshape(nm * n_conf, nmax, 3)
+    el_all = np.repeat(elem, n_conf, axis=0)
+    sz_all = np.repeat(sizes, n_conf)
+    mask = np.arange(nmax)[None, :] < sz_all[:, None]
+    frame = principal_frame_batch(allpos, VDW_RADIUS[el_all] * mask)
+    off = np.zeros(sz_all.size + 1, np.int64)
+    np.cumsum(sz_all, out=off[1:])
+    el = el_all[mask].astype(np.int8)
+    return MolSet(off.astype(np.int32), frame[mask].astype(np.float32),
+                  VDW_RADIUS[el].astype(np.float32), el)
+
+
+def conformer_library(config_seed: int, n_mols: int, lo: int, hi: int, n_conf: int,
+                      workers=None) -> tuple[MolSet, np.ndarray]:
+    """n_mols molecules with n_conf conformers each (the conformer-ensemble
+    workload: the paper's accuracy lever is the max over conformers).
+
+    Molecules come in chunks of CONF_CHUNK; atom counts are U{lo..hi} from
+    seed sequence [seed, 0xC0F5].  Conformer 0 is the molecule as grown
+    ([seed, 0xC0F, chunk]); conformers 1.. keep its topology and elements and
+    redraw every bond angle and torsion under the same acceptance rules
+    ([seed, 0xC0F, chunk, c, attempt]; a chain that cannot be completed is
+    redrawn with the next attempt).  Each conformer is put into its own
+    principal frame.  Returns the set (molecule-major: entry m n_conf + c)
+    and group offsets [n_mols + 1] (multiples of n_conf).
+    """
+    sizes = np.random.Generator(np.random.PCG64(np.random.SeedSequence(
+        [int(config_seed), 0xC0F5]))).integers(lo, hi + 1, size=n_mols).astype(np.int64)
+    nch = (n_mols + CONF_CHUNK - 1) // CONF_CHUNK
+    jobs = [(int(config_seed), c, sizes[c * CONF_CHUNK:(c + 1) * CONF_CHUNK], int(n_conf))
+            for c in range(nch)]
+    if workers is None:
+        workers = min(nch, 16, os.cpu_count() or 1)
+    if workers > 1 and nch > 1:
+        ctx = multiprocessing.get_context("fork")
+        with concurrent.futures.ProcessPoolExecutor(workers, mp_context=ctx) as ex:
+            parts = list(ex.map(_conformer_chunk, *zip(*jobs)))
+    else:
+        parts = [_conformer_chunk(*j) for j in jobs]
+    return MolSet.concat(parts), np.arange(0, n_mols * n_conf + 1, n_conf, dtype=np.int32)
 
 
 def random_poses(config_seed: int, n_pairs: int, n_starts: int,

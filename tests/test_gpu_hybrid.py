@@ -170,3 +170,41 @@ def test_invalid_molecule_gives_nan(eng, pairs):
     with pytest.raises(ShapeError):
         eng.shape_fo_align(dA, eng.molecules(molgen.library(1, 3, 10, 20, workers=1)), st[:3],
                            n_steps=1)
+
+
+def test_group_max(eng):
+    rng = np.random.default_rng(4)
+    T = rng.uniform(size=40).astype(np.float32)
+    T[3:6] = np.nan                   # group 1 all NaN
+    T[7] = np.nan
+    T[10] = T[12] = 5.0               # tie in group 3: the lower entry
+    off = np.array([0, 3, 6, 6, 10, 15, 40], np.int32)   # group 2 empty
+    bT, bi = eng.shape_group_max(torch.from_numpy(T).cuda(), torch.from_numpy(off).cuda())
+    bT, bi = bT.cpu().numpy(), bi.cpu().numpy()
+    for gi in range(off.size - 1):
+        seg = T[off[gi]:off[gi + 1]]
+        key = np.where(np.isnan(seg), -np.inf, seg)
+        if seg.size == 0 or np.all(np.isnan(seg)):
+            assert np.isnan(bT[gi]) and bi[gi] == -1
+        else:
+            j = int(np.argmax(key))
+            assert bi[gi] == off[gi] + j and bT[gi] == seg[j]
+
+
+@pytest.mark.parametrize("aligned", [False, True])
+def test_ensemble_screen_takes_the_best_conformer(eng, aligned):
+    from paper_2607_20766_amd.hybrid import EnsembleScreen
+    C, goff = molgen.conformer_library(5, 40, 10, 40, 4, workers=1)
+    q = molgen.molecule(1, 0, 30)
+    Q = eng.molecules(q, mol_id=[QUERY_ID])
+    lib = eng.molecules(C)
+    hs = HybridScreen(eng, n_random=1, n_steps=20, seed=1) if aligned else None
+    es = EnsembleScreen(eng, hybrid=hs, seed=1)
+    print(f"case: conformer ensemble, aligned={aligned}", flush=True)
+    bufs = es.screen(Q, lib, torch.from_numpy(goff).cuda())
+    T = bufs["out"]["T"].cpu().numpy().reshape(40, 4)
+    best = bufs["best_T"].cpu().numpy()
+    ent = bufs["best_entry"].cpu().numpy()
+    assert np.array_equal(best, T.max(1))
+    assert np.array_equal(ent, np.arange(40) * 4 + T.argmax(1))
+    assert np.all(best >= T[:, 0])
