@@ -50,12 +50,14 @@ def lib():
         L.or_norm_inv.restype = _d
         L.or_alpha_from_radius.argtypes = [_f32p, _i64, _d, _f32p]
         L.or_mol_prep.argtypes = [_i, _f32p, _f32p, _f64p, _f64p, _u32p]
-        L.or_sample_points.argtypes = [_i, _f32p, _f32p, _u32, _u64, _u64, _i64, _f64p, _vp]
+        L.or_sample_points.argtypes = [_i, _f32p, _f32p, _u32, _u64, _u64, _i64, _i, _f64p,
+                                       _vp]
         L.or_densities.argtypes = [_i, _f32p, _f32p, _i64, _f64p, _f64p, _f64p]
         L.or_estimate.argtypes = [_i, _f32p, _f32p, _u32, _i, _f32p, _f32p, _u32,
-                                  _i64, _i64, _u64, _f64p]
+                                  _i64, _i64, _u64, _i, _f64p]
         L.or_screen.argtypes = [_i, _f32p, _f32p, _u32, _i32p, _f32p, _f32p, _vp, _vp,
-                                ctypes.c_int32, _i, _i64, _i64, _i64, _d, _u64, _i, _vp, _f64p]
+                                ctypes.c_int32, _i, _i64, _i64, _i64, _d, _u64, _i, _vp, _i,
+                                _f64p]
         L.or_fo_overlap.argtypes = [_i, _f32p, _f32p, _i, _f32p, _f32p]
         L.or_fo_overlap.restype = _d
         L.or_fo_second_moment.argtypes = [_i, _f32p, _f32p, _i, _f32p, _f32p]
@@ -124,12 +126,12 @@ def mol_prep(xyz, alpha):
     return v, float(Z[0]), thr[: n - 1]
 
 
-def sample_points(xyz, alpha, mol_id, seed, k0, n, return_component=False):
+def sample_points(xyz, alpha, mol_id, seed, k0, n, return_component=False, antithetic=False):
     xyz, alpha = _mol(xyz, alpha)
     r = np.zeros((n, 3))
     comp = np.zeros(n, np.int32)
-    lib().or_sample_points(alpha.size, xyz, alpha, mol_id, seed, k0, n, r,
-                           comp.ctypes.data)
+    lib().or_sample_points(alpha.size, xyz, alpha, mol_id, seed, k0, n, int(bool(antithetic)),
+                           r, comp.ctypes.data)
     return (r, comp) if return_component else r
 
 
@@ -142,13 +144,15 @@ def densities(xyz, alpha, r):
     return m, u
 
 
-def estimate(A, B, n_a, n_b, seed=0, id_a=0, id_b=1) -> dict:
-    """A, B: (xyz, alpha) tuples.  Returns the FP64 result fields."""
+def estimate(A, B, n_a, n_b, seed=0, id_a=0, id_b=1, antithetic=False) -> dict:
+    """A, B: (xyz, alpha) tuples.  Returns the FP64 result fields.
+    antithetic: samples 2p, 2p+1 are a draw and its reflection; standard
+    errors from the pair means."""
     xa, aa = _mol(*A)
     xb, ab = _mol(*B)
     out = np.zeros(20)
     rc = lib().or_estimate(aa.size, xa, aa, id_a, ab.size, xb, ab, id_b, n_a, n_b,
-                           seed, out)
+                           seed, int(bool(antithetic)), out)
     if rc:
         raise RuntimeError(f"oracle estimate failed ({rc})")
     d = dict(zip(RESULT_FIELDS, out.tolist()))
@@ -159,7 +163,7 @@ def estimate(A, B, n_a, n_b, seed=0, id_a=0, id_b=1) -> dict:
 
 def screen(query, id_q, lib_off, lib_xyz, lib_alpha, lib_id=None, pairs=None,
            mode=0, n_fixed=4096, round_per_pair=512, cap_per_pair=65536,
-           tau=0.005, seed=0, n_threads=0, n_start=None):
+           tau=0.005, seed=0, n_threads=0, n_start=None, antithetic=False):
     """Returns [n_pairs, 6] = T, se_T, O_ab, O_aa, O_bb, n_used (pair total)."""
     xq, aq = _mol(*query)
     off = np.ascontiguousarray(lib_off, np.int32)
@@ -174,7 +178,8 @@ def screen(query, id_q, lib_off, lib_xyz, lib_alpha, lib_id=None, pairs=None,
                          None if ids is None else ids.ctypes.data,
                          None if pr is None else pr.ctypes.data, n_pairs, mode,
                          n_fixed, round_per_pair, cap_per_pair, tau, seed,
-                         n_threads, None if ns is None else ns.ctypes.data, out)
+                         n_threads, None if ns is None else ns.ctypes.data,
+                         int(bool(antithetic)), out)
     if rc:
         raise RuntimeError("oracle screen failed")
     return out

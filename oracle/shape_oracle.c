@@ -190,14 +190,30 @@ static int or_sample(const or_mol* M, uint32_t mol_id, uint64_t k, uint64_t seed
   return j;
 }
 
+/* Antithetic sample k (section "Importance-sampling estimator": each Gaussian
+ * draw c_j + L eps is paired with its reflection c_j - L eps): samples 2p and
+ * 2p+1 share the component and normal draws of Philox block p and take the
+ * signs + and -. */
+static int or_sample_anti(const or_mol* M, uint32_t mol_id, uint64_t k, uint64_t seed,
+                          double r[3]) {
+  double c[3];
+  int j = or_sample(M, mol_id, k >> 1, seed, r);
+  if (k & 1) {
+    for (int d = 0; d < 3; ++d) c[d] = M->c[3 * j + d];
+    for (int d = 0; d < 3; ++d) r[d] = c[d] - (r[d] - c[d]);
+  }
+  return j;
+}
+
 /* exported: sample points of one molecule for counters k0..k0+n-1 */
 int or_sample_points(int n_atoms, const float* xyz, const float* alpha,
-                     uint32_t mol_id, uint64_t seed, uint64_t k0, int64_t n,
+                     uint32_t mol_id, uint64_t seed, uint64_t k0, int64_t n, int anti,
                      double* r_out, int32_t* comp_out) {
   or_mol M;
   if (or_mol_init(&M, n_atoms, xyz, alpha)) return -1;
   for (int64_t k = 0; k < n; ++k) {
-    int j = or_sample(&M, mol_id, k0 + (uint64_t)k, seed, r_out + 3 * k);
+    int j = anti ? or_sample_anti(&M, mol_id, k0 + (uint64_t)k, seed, r_out + 3 * k)
+                 : or_sample(&M, mol_id, k0 + (uint64_t)k, seed, r_out + 3 * k);
     if (comp_out) comp_out[k] = j;
   }
   or_mol_free(&M);
@@ -237,11 +253,14 @@ enum { F_PQ = 0, F_PP = 1, F_V = 2, F_FOPQ = 3, F_FOPP = 4, NF = 5 };
 
 /* per-sample integrands for counters [k0, k1) into f[NF][k1-k0] */
 static void or_side_integrands(const or_mol* P, const or_mol* Q, uint32_t id_p,
-                               uint64_t seed, int64_t k0, int64_t k1, double* f) {
+                               uint64_t seed, int64_t k0, int64_t k1, int anti, double* f) {
   int64_t n = k1 - k0;
   for (int64_t k = k0; k < k1; ++k) {
     double r[3], mP, uP, mQ, uQ;
-    or_sample(P, id_p, (uint64_t)k, seed, r);
+    if (anti)
+      or_sample_anti(P, id_p, (uint64_t)k, seed, r);
+    else
+      or_sample(P, id_p, (uint64_t)k, seed, r);
     or_density(P, r, &mP, &uP);
     or_density(Q, r, &mQ, &uQ);
     double w = (mP > 0.0) ? uP / mP : 0.0;
@@ -261,23 +280,33 @@ typedef struct {
   int64_t n;
 } or_side_stats;
 
-static void or_stats(const double* f, int64_t n, or_side_stats* s) {
+/* Means over the n samples; variances (n-1) and the covariance of f_PQ and
+ * f_PP over the independent terms: the samples themselves, or for
+ * antithetic sampling the n/2 pair means g = (f(r_2p) + f(r_2p+1))/2,
+ * stored as 2 var(g) so that SE = Z sqrt(var / n) = Z sqrt(var(g) / (n/2)). */
+static void or_stats(const double* f, int64_t n, int anti, or_side_stats* s) {
   s->n = n;
+  int64_t c = anti ? n / 2 : n;
+  double* g = (double*)malloc(sizeof(double) * NF * (size_t)(c > 0 ? c : 1));
+  for (int a = 0; a < NF; ++a)
+    for (int64_t i = 0; i < c; ++i)
+      g[a * c + i] = anti ? 0.5 * (f[a * n + 2 * i] + f[a * n + 2 * i + 1]) : f[a * n + i];
   for (int a = 0; a < NF; ++a) {
     double sum = 0.0;
-    for (int64_t i = 0; i < n; ++i) sum += f[a * n + i];
-    s->mean[a] = sum / (double)n;
+    for (int64_t i = 0; i < c; ++i) sum += g[a * c + i];
+    s->mean[a] = sum / (double)c;
     double ss = 0.0;
-    for (int64_t i = 0; i < n; ++i) {
-      double d = f[a * n + i] - s->mean[a];
+    for (int64_t i = 0; i < c; ++i) {
+      double d = g[a * c + i] - s->mean[a];
       ss += d * d;
     }
-    s->var[a] = (n > 1) ? ss / (double)(n - 1) : 0.0;
+    s->var[a] = (c > 1) ? ss / (double)(c - 1) * (double)n / (double)c : 0.0;
   }
   double cs = 0.0;
-  for (int64_t i = 0; i < n; ++i)
-    cs += (f[F_PQ * n + i] - s->mean[F_PQ]) * (f[F_PP * n + i] - s->mean[F_PP]);
-  s->cov12 = (n > 1) ? cs / (double)(n - 1) : 0.0;
+  for (int64_t i = 0; i < c; ++i)
+    cs += (g[F_PQ * c + i] - s->mean[F_PQ]) * (g[F_PP * c + i] - s->mean[F_PP]);
+  s->cov12 = (c > 1) ? cs / (double)(c - 1) * (double)n / (double)c : 0.0;
+  free(g);
 }
 
 /* Result of one pair (all FP64). */
@@ -325,16 +354,16 @@ static void or_combine(double Za, double Zb, const or_side_stats* A,
 }
 
 static int or_pair_estimate(const or_mol* A, const or_mol* B, uint32_t id_a,
-                            uint32_t id_b, int64_t n_a, int64_t n_b, uint64_t seed,
+                            uint32_t id_b, int64_t n_a, int64_t n_b, uint64_t seed, int anti,
                             or_result* out) {
   double* fa = (double*)malloc(sizeof(double) * NF * (size_t)n_a);
   double* fb = (double*)malloc(sizeof(double) * NF * (size_t)n_b);
   if (!fa || !fb) { free(fa); free(fb); return -1; }
-  or_side_integrands(A, B, id_a, seed, 0, n_a, fa);
-  or_side_integrands(B, A, id_b, seed, 0, n_b, fb);
+  or_side_integrands(A, B, id_a, seed, 0, n_a, anti, fa);
+  or_side_integrands(B, A, id_b, seed, 0, n_b, anti, fb);
   or_side_stats sa, sb;
-  or_stats(fa, n_a, &sa);
-  or_stats(fb, n_b, &sb);
+  or_stats(fa, n_a, anti, &sa);
+  or_stats(fb, n_b, anti, &sb);
   or_combine(A->Z, B->Z, &sa, &sb, out);
   free(fa); free(fb);
   return 0;
@@ -343,13 +372,14 @@ static int or_pair_estimate(const or_mol* A, const or_mol* B, uint32_t id_a,
 /* exported: single pair estimate */
 int or_estimate(int na_atoms, const float* xyz_a, const float* alpha_a, uint32_t id_a,
                 int nb_atoms, const float* xyz_b, const float* alpha_b, uint32_t id_b,
-                int64_t n_a, int64_t n_b, uint64_t seed, double* out20) {
+                int64_t n_a, int64_t n_b, uint64_t seed, int anti, double* out20) {
   if (na_atoms < 1 || nb_atoms < 1 || n_a < 2 || n_b < 2) return -2;
+  if (anti && ((n_a & 1) || (n_b & 1) || n_a < 4 || n_b < 4)) return -2;
   or_mol A, B;
   if (or_mol_init(&A, na_atoms, xyz_a, alpha_a)) return -1;
   if (or_mol_init(&B, nb_atoms, xyz_b, alpha_b)) { or_mol_free(&A); return -1; }
   or_result r;
-  int rc = or_pair_estimate(&A, &B, id_a, id_b, n_a, n_b, seed, &r);
+  int rc = or_pair_estimate(&A, &B, id_a, id_b, n_a, n_b, seed, anti, &r);
   memcpy(out20, &r, sizeof(double) * 18);
   out20[18] = (double)r.n_a;
   out20[19] = (double)r.n_b;
@@ -367,7 +397,7 @@ int or_screen(int nq, const float* xyz_q, const float* alpha_q, uint32_t id_q,
               const uint32_t* lib_id, const int32_t* pairs, int32_t n_pairs,
               int mode, int64_t n_fixed, int64_t round_per_pair, int64_t cap_per_pair,
               double tau, uint64_t seed, int n_threads, const int32_t* n_start,
-              double* out6) {
+              int anti, double* out6) {
   or_mol Q;
   if (or_mol_init(&Q, nq, xyz_q, alpha_q)) return -1;
   int err = 0;
@@ -383,7 +413,7 @@ int or_screen(int nq, const float* xyz_q, const float* alpha_q, uint32_t id_q,
     if (or_mol_init(&B, a1 - a0, lib_xyz + 3 * (size_t)a0, lib_alpha + a0)) { err |= 1; continue; }
     or_result r;
     if (mode == 0) {
-      if (or_pair_estimate(&Q, &B, id_q, idm, n_fixed, n_fixed, seed, &r)) err |= 1;
+      if (or_pair_estimate(&Q, &B, id_q, idm, n_fixed, n_fixed, seed, anti, &r)) err |= 1;
     } else {
       int64_t side_round = round_per_pair / 2;
       int64_t max_side = cap_per_pair / 2;
@@ -397,8 +427,8 @@ int or_screen(int nq, const float* xyz_q, const float* alpha_q, uint32_t id_q,
         /* round: samples [n, n + side_round) on each side */
         double* ra = (double*)malloc(sizeof(double) * NF * (size_t)side_round);
         double* rb = (double*)malloc(sizeof(double) * NF * (size_t)side_round);
-        or_side_integrands(&Q, &B, id_q, seed, n, n + side_round, ra);
-        or_side_integrands(&B, &Q, idm, seed, n, n + side_round, rb);
+        or_side_integrands(&Q, &B, id_q, seed, n, n + side_round, anti, ra);
+        or_side_integrands(&B, &Q, idm, seed, n, n + side_round, anti, rb);
         int64_t nn = n + side_round;
         /* re-pack [NF][nn] */
         for (int a = 0; a < NF; ++a) {
@@ -413,8 +443,8 @@ int or_screen(int nq, const float* xyz_q, const float* alpha_q, uint32_t id_q,
         memcpy(fb, tb, sizeof(double) * NF * (size_t)nn);
         n = nn;
         or_side_stats sa, sb;
-        or_stats(fa, n, &sa);
-        or_stats(fb, n, &sb);
+        or_stats(fa, n, anti, &sa);
+        or_stats(fb, n, anti, &sb);
         or_combine(Q.Z, B.Z, &sa, &sb, &r);
         /* a seeded budget defers the first stop test until it is spent */
         if (n_start && 2 * n < (int64_t)n_start[p] && 2 * n < cap_per_pair) continue;

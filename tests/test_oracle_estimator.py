@@ -216,3 +216,55 @@ def test_screen_adaptive_stopping(oracle):
             r0 = oracle.estimate(Q, (L.xyz[a:b], la[a:b]), n // 2 - 256, n // 2 - 256,
                                  seed=3, id_a=999, id_b=p)
             assert r0["se_T"] > tau
+
+
+# --- antithetic sampling (section "Importance-sampling estimator": each draw
+# paired with its reflection about its component's centre) -----------------
+
+def test_antithetic_pairs_are_reflections(oracle):
+    m = cases.small(3, 9)
+    xyz, al = cases.oracle_mol(oracle, m)
+    r, comp = oracle.sample_points(xyz, al, 5, 7, 0, 2000, return_component=True,
+                                   antithetic=True)
+    iid, comp_iid = oracle.sample_points(xyz, al, 5, 7, 0, 1000, return_component=True)
+    assert np.array_equal(comp[0::2], comp[1::2])
+    assert np.array_equal(comp[0::2], comp_iid)        # pair p uses Philox block p
+    assert np.array_equal(r[0::2], iid)
+    c = xyz.astype(np.float64)[comp[0::2]]
+    assert np.allclose(r[0::2] + r[1::2], 2 * c, rtol=0, atol=1e-12)
+
+
+def test_antithetic_fo_channel_unbiased(oracle):
+    """Over many seeds the antithetic first-order estimate scatters about
+    the closed form (Eq. fo) with no bias beyond its replicate error."""
+    a, b = cases.small(4, 5), cases.small(5, 6)
+    A, B = cases.oracle_mol(oracle, a), cases.oracle_mol(oracle, b)
+    exact = oracle.fo_overlap(A, B)
+    d = np.asarray([oracle.estimate(A, B, 400, 400, seed=seed, antithetic=True)["Ofo_ab_is"]
+                    - exact for seed in range(600)])
+    assert abs(d.mean()) < 4.5 * d.std(ddof=1) / np.sqrt(d.size)
+
+
+def test_antithetic_union_within_se_of_grid(oracle):
+    a, b = cases.config0()
+    A, B = cases.oracle_mol(oracle, a), cases.oracle_mol(oracle, b)
+    g = oracle.grid_integrals(A, B, h=0.2, pad=6.5)
+    r = oracle.estimate(A, B, 40000, 40000, seed=3, antithetic=True)
+    assert abs(r["O_ab"] - g["uAuB"]) <= 4.5 * r["se_O_ab"]
+    assert abs(r["V_a"] - g["uA"]) <= 4.5 * r["se_V_a"]
+    assert abs(r["O_aa"] - g["uA2"]) <= 4.5 * r["se_O_aa"]
+
+
+def test_antithetic_se_calibrated_on_union(oracle):
+    """z-scores of the antithetic union overlap against a long reference run
+    have unit spread over seeds."""
+    a, b = cases.small(6, 5), cases.small(7, 5)
+    A, B = cases.oracle_mol(oracle, a), cases.oracle_mol(oracle, b)
+    ref = oracle.estimate(A, B, 2000000, 2000000, seed=10**6, antithetic=True)["O_ab"]
+    z = []
+    for seed in range(500):
+        r = oracle.estimate(A, B, 512, 512, seed=seed, antithetic=True)
+        z.append((r["O_ab"] - ref) / r["se_O_ab"])
+    z = np.asarray(z)
+    assert abs(z.mean()) < 0.2
+    assert 0.88 < z.std(ddof=1) < 1.12
