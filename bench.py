@@ -630,6 +630,28 @@ def main():
         },
     }
 
+    # antithetic sampling (the paper's second standard variance control):
+    # same rounds, stopping rule and cap; standard errors from pair means
+    log("timing adaptive screen, antithetic sampling")
+    eng.sampling(True)
+    out_a = {k: torch.empty_like(v) for k, v in out.items()}
+
+    def adaptive_anti():
+        eng.shape_screen(Q, lib, mode=SHAPE_SCREEN_ADAPTIVE, round_per_pair=ROUND,
+                         cap_per_pair=CAP, tau=TAU, seed=0, out=out_a)
+
+    ms_anti, kern_anti = timed(adaptive_anti, args.steps, args.warmup)
+    eng.sampling(False)
+    n_used_a = out_a["n_used"].cpu().numpy().astype(np.int64)
+    res["antithetic"] = {
+        "pairs_per_s": n / (ms_anti * 1e-3),
+        "ms_per_step": ms_anti,
+        "kernel_ms": kern_anti,
+        "samples_per_step": int(n_used_a.sum()),
+        "samples_vs_iid": float(n_used_a.sum() / n_used.sum()),
+        "pairs_at_tau": float(np.mean(out_a["se_T"].cpu().numpy() <= TAU)),
+    }
+
     if not args.no_quality:
         # converged ranking: 2^16 samples per side (untimed)
         log("converged reference ranking")

@@ -197,6 +197,21 @@ int shape_screen(shape_ctx* ctx, const shape_mols* query, const shape_mols* lib,
  * (SHAPE_OK); clears the flag. */
 int shape_check_data(shape_ctx* ctx, void* stream);
 
+/* Sampling scheme of shape_estimate and shape_screen (section
+ * "Importance-sampling estimator").  SHAPE_SAMPLING_IID (default): sample k
+ * of a molecule is Philox block k.  SHAPE_SAMPLING_ANTITHETIC: samples 2p
+ * and 2p+1 share Philox block p (component and normals) and are the draw
+ * c_j + z sd_j and its reflection c_j - z sd_j; means are unchanged, and the
+ * standard errors come from the variance of the pair means.  Needs even
+ * sample counts (>= 4) in shape_estimate, n_per_side a multiple of 128 and
+ * round_per_pair a multiple of 256 in shape_screen (else SHAPE_E_RANGE).
+ * shape_get_sampling returns the current scheme (-1 if ctx is NULL).
+ * Errors: SHAPE_E_INVAL. */
+#define SHAPE_SAMPLING_IID 0
+#define SHAPE_SAMPLING_ANTITHETIC 1
+int shape_set_sampling(shape_ctx* ctx, int32_t sampling);
+int32_t shape_get_sampling(const shape_ctx* ctx);
+
 /* Reuse of molecule preparation across calls (a pipeline that hands the
  * same molecule set to several calls, e.g. shape_features, shape_fo_overlap
  * and shape_screen of one library).  Every call prepares its molecule sets

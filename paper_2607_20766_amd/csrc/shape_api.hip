@@ -61,6 +61,7 @@ struct shape_ctx {
   bool timing = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
   int screen_variant = -1;        // -1: default tile shape
+  int sampling = SHAPE_SAMPLING_IID;
   bool capturing = false;         // a graph capture is open on capture_stream
   bool capture_failed = false;    // a call failed while capturing
   hipStream_t capture_stream = nullptr;
@@ -239,14 +240,19 @@ int screen_setup(shape_ctx* c, const shape_mols* query, const shape_mols* lib,
                 lib->n_mols);
   int64_t n_fixed = 0, cap = 0;
   int round_side = 0;
+  const bool anti = c->sampling == SHAPE_SAMPLING_ANTITHETIC;
   if (prm->mode == SHAPE_SCREEN_FIXED) {
     if (prm->n_per_side < 64 || prm->n_per_side > (1 << 20) || prm->n_per_side % 64)
       return fail(c, SHAPE_E_RANGE, "n_per_side must be a multiple of 64 in [64, 2^20]");
+    if (anti && prm->n_per_side % 128)
+      return fail(c, SHAPE_E_RANGE, "antithetic sampling needs n_per_side a multiple of 128");
     n_fixed = prm->n_per_side;
-    round_side = (int)(n_fixed % 256 == 0 ? 256 : 64);
+    round_side = (int)(n_fixed % 256 == 0 ? 256 : (anti ? 128 : 64));
   } else if (prm->mode == SHAPE_SCREEN_ADAPTIVE) {
     if (prm->round_per_pair < 128 || prm->round_per_pair > 8192 || prm->round_per_pair % 128)
       return fail(c, SHAPE_E_RANGE, "round_per_pair must be a multiple of 128 in [128, 8192]");
+    if (anti && prm->round_per_pair % 256)
+      return fail(c, SHAPE_E_RANGE, "antithetic sampling needs round_per_pair a multiple of 256");
     if (prm->cap_per_pair < prm->round_per_pair || prm->cap_per_pair > (1 << 21) ||
         prm->cap_per_pair % prm->round_per_pair)
       return fail(c, SHAPE_E_RANGE,
@@ -271,7 +277,8 @@ int screen_setup(shape_ctx* c, const shape_mols* query, const shape_mols* lib,
   if ((rc = ensure(c, S_QS, (size_t)n_cache * sizeof(float4), &qs))) return rc;
   if ((rc = ensure(c, S_QF2, (size_t)n_cache * sizeof(float), &qf2))) return rc;
   const uint2 key = key_of(prm->seed);
-  HIP_TRY(c, shape::launch_query_cache(PQ, query->atom_offset, n_cache, key, (float4*)qs,
+  HIP_TRY(c, shape::launch_query_cache(PQ, query->atom_offset, n_cache, key, anti ? 1 : 0,
+                                       (float4*)qs,
                                        (float*)qf2, st),
           "query cache kernel");
   a->Q = PQ;
@@ -292,6 +299,7 @@ int screen_setup(shape_ctx* c, const shape_mols* query, const shape_mols* lib,
   a->tau = prm->tau;
   a->key = key;
   a->n_start = prm->mode == SHAPE_SCREEN_ADAPTIVE ? prm->n_start : nullptr;
+  a->anti = anti ? 1 : 0;
   a->T = out->T;
   a->se_T = out->se_T;
   a->O_ab = out->O_ab;
@@ -392,12 +400,16 @@ int shape_estimate(shape_ctx* c, const shape_mols* A, const shape_mols* B, int64
     if (!out) return fail(c, SHAPE_E_INVAL, "out is NULL");
     if (n_a < 2 || n_b < 2 || n_a > (int64_t)1 << 31 || n_b > (int64_t)1 << 31)
       return fail(c, SHAPE_E_RANGE, "sample counts must lie in [2, 2^31]");
+    const int anti = c->sampling == SHAPE_SAMPLING_ANTITHETIC ? 1 : 0;
+    if (anti && (n_a % 2 || n_b % 2 || n_a < 4 || n_b < 4))
+      return fail(c, SHAPE_E_RANGE, "antithetic sampling needs even sample counts >= 4");
     if ((rc = set_device(c))) return rc;
     hipStream_t st = (hipStream_t)stream;
     shape::Prepared PA, PB;
     if ((rc = prepare(c, A, true, st, &PA))) return rc;
     if ((rc = prepare(c, B, false, st, &PB))) return rc;
-    const int nblk = shape::est_blocks(n_a > n_b ? n_a : n_b);
+    const int64_t units = (n_a > n_b ? n_a : n_b) / (anti ? 2 : 1);
+    const int nblk = shape::est_blocks(units);
     void *partials, *res;
     if ((rc = ensure(c, S_PARTIALS, (size_t)2 * nblk * shape::kEstSums * sizeof(double),
                      &partials)))
@@ -414,7 +426,7 @@ int shape_estimate(shape_ctx* c, const shape_mols* A, const shape_mols* B, int64
     }
     KernelTimer timer(c, st);
     HIP_TRY(c, shape::launch_estimate(PA, PB, A->atom_offset, B->atom_offset, n_a, n_b,
-                                      key_of(seed), (double*)partials, nblk,
+                                      key_of(seed), anti, (double*)partials, nblk,
                                       (shape_result*)res, st),
             "estimate kernels");
     timer.stop();
@@ -502,6 +514,16 @@ int shape_screen_tune(shape_ctx* c, const shape_mols* query, const shape_mols* l
     return fail(c, SHAPE_E_HIP, "internal error");
   }
 }
+
+int shape_set_sampling(shape_ctx* c, int32_t sampling) {
+  if (!c) return SHAPE_E_INVAL;
+  if (sampling != SHAPE_SAMPLING_IID && sampling != SHAPE_SAMPLING_ANTITHETIC)
+    return fail(c, SHAPE_E_INVAL, "unknown sampling %d", sampling);
+  c->sampling = sampling;
+  return SHAPE_OK;
+}
+
+int32_t shape_get_sampling(const shape_ctx* c) { return c ? c->sampling : -1; }
 
 int shape_prepare_cache(shape_ctx* c, int enable) {
   if (!c) return SHAPE_E_INVAL;

@@ -109,6 +109,41 @@ __device__ __forceinline__ void sample_point(const Atom* atoms, const AtomSampli
   rz = fmaf(normal_from_bits(x.w), sd, c.z);
 }
 
+// Antithetic sample k (each draw paired with its reflection about its
+// component's centre): samples 2p and 2p+1 use Philox block p; the odd one
+// takes the normals with the opposite sign.
+__device__ __forceinline__ void sample_point_anti(const Atom* atoms, const AtomSampling* samp,
+                                                  int n, uint32_t mol_id, uint64_t k, uint2 key,
+                                                  float& rx, float& ry, float& rz) {
+  const uint64_t p = k >> 1;
+  const float sg = (k & 1) ? -1.0f : 1.0f;
+  const uint4 x = philox4x32_10(make_uint4((uint32_t)p, (uint32_t)(p >> 32), mol_id, 0u), key);
+  const int j = select_component(samp, n, x.x);
+  const Atom c = atoms[j];
+  const float sd = samp[j].sd;
+  rx = fmaf(sg * normal_from_bits(x.y), sd, c.x);
+  ry = fmaf(sg * normal_from_bits(x.z), sd, c.y);
+  rz = fmaf(sg * normal_from_bits(x.w), sd, c.z);
+}
+
+// Both members of antithetic pair p from one Philox block.
+__device__ __forceinline__ void sample_pair(const Atom* atoms, const AtomSampling* samp, int n,
+                                            uint32_t mol_id, uint64_t p, uint2 key, float& ax,
+                                            float& ay, float& az, float& bx, float& by,
+                                            float& bz) {
+  const uint4 x = philox4x32_10(make_uint4((uint32_t)p, (uint32_t)(p >> 32), mol_id, 0u), key);
+  const int j = select_component(samp, n, x.x);
+  const Atom c = atoms[j];
+  const float sd = samp[j].sd;
+  const float zx = normal_from_bits(x.y), zy = normal_from_bits(x.z), zz = normal_from_bits(x.w);
+  ax = fmaf(zx, sd, c.x);
+  ay = fmaf(zy, sd, c.y);
+  az = fmaf(zz, sd, c.z);
+  bx = fmaf(-zx, sd, c.x);
+  by = fmaf(-zy, sd, c.y);
+  bz = fmaf(-zz, sd, c.z);
+}
+
 __device__ __forceinline__ float occupancy(const Atom& a, float rx, float ry, float rz) {
   const float dx = rx - a.x, dy = ry - a.y, dz = rz - a.z;
   const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));

@@ -160,7 +160,7 @@ __device__ void block_sum(double (&v)[K], double* lds /* [4][K] */) {
 constexpr int kEstSPT = 8;
 
 __global__ __launch_bounds__(256) void k_est_partials(Prepared A, Prepared B, int64_t n_a,
-                                                      int64_t n_b, uint2 key,
+                                                      int64_t n_b, uint2 key, int anti,
                                                       double* __restrict__ partials,
                                                       int nblk, const int* __restrict__ offA,
                                                       const int* __restrict__ offB) {
@@ -174,6 +174,7 @@ __global__ __launch_bounds__(256) void k_est_partials(Prepared A, Prepared B, in
   const int* offP = side ? offB : offA;
   const int* offQ = side ? offA : offB;
   const int64_t n = side ? n_b : n_a;
+  const int64_t units = anti ? n / 2 : n;  // independent terms: samples or pairs
   const int p0 = offP[0], np = offP[1] - offP[0];
   const int q0 = offQ[0], nq = offQ[1] - offQ[0];
   const uint32_t idp = P.id[0];
@@ -188,22 +189,33 @@ __global__ __launch_bounds__(256) void k_est_partials(Prepared A, Prepared B, in
   for (int j = 0; j < kEstSums; ++j) acc[j] = 0.0f;
   const int64_t base = (int64_t)blockIdx.x * blockDim.x * kEstSPT;
   for (int s = 0; s < kEstSPT; ++s) {
-    const int64_t k = base + (int64_t)s * blockDim.x + threadIdx.x;
-    if (k >= n) break;
-    float rx[1], ry[1], rz[1];
-    sample_point(sP, sS, np, idp, (uint64_t)k, key, rx[0], ry[0], rz[0]);
-    float mp[1] = {0.0f}, qp[1] = {1.0f}, mq[1] = {0.0f}, qq[1] = {1.0f};
-    eval_density<1>(sP, np, rx, ry, rz, mp, qp);
-    eval_density<1>(sQ, nq, rx, ry, rz, mq, qq);
-    const float uP = 1.0f - qp[0], uQ = 1.0f - qq[0];
-    const float w = bounded_weight(uP, mp[0]);
-    const float f1 = w * uQ, f2 = w * uP, f3 = w, f4 = mq[0], f5 = mp[0];
-    acc[0] += f1; acc[1] += f1 * f1;
-    acc[2] += f2; acc[3] += f2 * f2;
-    acc[4] += f3; acc[5] += f3 * f3;
-    acc[6] += f4; acc[7] += f4 * f4;
-    acc[8] += f5; acc[9] += f5 * f5;
-    acc[10] += f1 * f2;
+    const int64_t u = base + (int64_t)s * blockDim.x + threadIdx.x;
+    if (u >= units) break;
+    // the unit's term: the sample itself, or the mean over an antithetic pair
+    float f[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+    const int members = anti ? 2 : 1;
+    for (int mbr = 0; mbr < members; ++mbr) {
+      float rx[1], ry[1], rz[1];
+      if (anti)
+        sample_point_anti(sP, sS, np, idp, (uint64_t)(2 * u + mbr), key, rx[0], ry[0], rz[0]);
+      else
+        sample_point(sP, sS, np, idp, (uint64_t)u, key, rx[0], ry[0], rz[0]);
+      float mp[1] = {0.0f}, qp[1] = {1.0f}, mq[1] = {0.0f}, qq[1] = {1.0f};
+      eval_density<1>(sP, np, rx, ry, rz, mp, qp);
+      eval_density<1>(sQ, nq, rx, ry, rz, mq, qq);
+      const float uP = 1.0f - qp[0], uQ = 1.0f - qq[0];
+      const float w = bounded_weight(uP, mp[0]);
+      f[0] += w * uQ; f[1] += w * uP; f[2] += w; f[3] += mq[0]; f[4] += mp[0];
+    }
+    if (anti)
+#pragma unroll
+      for (int j = 0; j < 5; ++j) f[j] *= 0.5f;
+    acc[0] += f[0]; acc[1] += f[0] * f[0];
+    acc[2] += f[1]; acc[3] += f[1] * f[1];
+    acc[4] += f[2]; acc[5] += f[2] * f[2];
+    acc[6] += f[3]; acc[7] += f[3] * f[3];
+    acc[8] += f[4]; acc[9] += f[4] * f[4];
+    acc[10] += f[0] * f[1];
   }
   double v[kEstSums];
 #pragma unroll
@@ -228,7 +240,7 @@ struct Moments {
 
 __global__ __launch_bounds__(256) void k_est_finalize(const double* __restrict__ partials,
                                                       int nblk, Prepared A, Prepared B,
-                                                      int64_t n_a, int64_t n_b,
+                                                      int64_t n_a, int64_t n_b, int anti,
                                                       shape_result* __restrict__ out) {
   __shared__ double red[4 * 2 * kEstSums];
   double v[2 * kEstSums];
@@ -244,7 +256,8 @@ __global__ __launch_bounds__(256) void k_est_finalize(const double* __restrict__
   block_sum<2 * kEstSums>(v, red);
   if (threadIdx.x != 0) return;
   const double Za = A.Z[0], Zb = B.Z[0];
-  const double na = (double)n_a, nb = (double)n_b;
+  // independent terms per side: samples, or antithetic pair means
+  const double na = (double)(anti ? n_a / 2 : n_a), nb = (double)(anti ? n_b / 2 : n_b);
   const double* a = v;
   const double* b = v + kEstSums;
   auto mom = [](double n, const double* s, int j) { return Moments{n, s[2 * j], s[2 * j + 1]}; };
@@ -294,7 +307,7 @@ __global__ __launch_bounds__(256) void k_est_finalize(const double* __restrict__
 // kernel builds, so a library copy of the query reproduces them bit for bit.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_query_cache(Prepared Qp, const int* __restrict__ offQ,
-                                                     int64_t n, uint2 key,
+                                                     int64_t n, uint2 key, int anti,
                                                      float4* __restrict__ qs,
                                                      float* __restrict__ qf2) {
   __shared__ Atom sF[SHAPE_MAX_ATOMS];          // frame coordinates for sampling
@@ -320,7 +333,10 @@ __global__ __launch_bounds__(256) void k_query_cache(Prepared Qp, const int* __r
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   float rx[1], ry[1], rz[1], r2[1];
-  sample_point(sF, sS, nq, Qp.id[0], (uint64_t)k, key, rx[0], ry[0], rz[0]);
+  if (anti)
+    sample_point_anti(sF, sS, nq, Qp.id[0], (uint64_t)k, key, rx[0], ry[0], rz[0]);
+  else
+    sample_point(sF, sS, nq, Qp.id[0], (uint64_t)k, key, rx[0], ry[0], rz[0]);
   r2[0] = norm2(rx[0], ry[0], rz[0]);
   float m[1] = {0.0f}, q[1] = {1.0f};
   eval_density_x<1>(sR, sA, nq, rx, ry, rz, r2, m, q);
@@ -440,6 +456,13 @@ __global__ __launch_bounds__(64) void k_screen(ScreenArgs a) {
   int64_t n_side = 0;
   const int64_t first_check = a.n_start ? (int64_t)a.n_start[p] : 0;
   const double tau2x4 = 4.0 * a.tau * a.tau;
+  // Slot i of a lane in a round holds sample n_side + lane + 64 i (i.i.d.),
+  // or for antithetic sampling member i & 1 of pair n_side/2 + lane +
+  // 64 (i >> 1), i.e. sample n_side + 2 lane + 128 (i >> 1) + (i & 1); the
+  // pair's two members sit in consecutive slots of one lane and enter the
+  // sums as one term, their mean (pend* holds the first member).
+  const bool anti = a.anti != 0;
+  float pa1 = 0.f, pa2 = 0.f, pb1 = 0.f, pb2 = 0.f;
   for (;;) {
     float fa[3] = {0.f, 0.f, 0.f};
     float fb[3] = {0.f, 0.f, 0.f};
@@ -449,7 +472,9 @@ __global__ __launch_bounds__(64) void k_screen(ScreenArgs a) {
 #pragma unroll
       for (int s = 0; s < kSA; ++s) {
         const bool ok = (t + s) < per_lane;
-        const int k = (int)n_side + lane + kWave * (ok ? t + s : t);
+        const int i = ok ? t + s : t;
+        const int k = anti ? (int)n_side + 2 * lane + 2 * kWave * (i >> 1) + (i & 1)
+                           : (int)n_side + lane + kWave * i;
         const float4 c = a.qs[k];
         rx[s] = c.x; ry[s] = c.y; rz[s] = c.z; w[s] = c.w;
         r2[s] = norm2(c.x, c.y, c.z);
@@ -461,8 +486,17 @@ __global__ __launch_bounds__(64) void k_screen(ScreenArgs a) {
 #pragma unroll
       for (int s = 0; s < kSA; ++s) {
         const float f1 = w[s] * (1.0f - q[s]) * valid[s];
-        fa[0] += f1; fa[1] = fmaf(f1, f1, fa[1]);
-        fa[2] = fmaf(f2[s], valid[s], fa[2]);
+        if (!anti) {
+          fa[0] += f1; fa[1] = fmaf(f1, f1, fa[1]);
+          fa[2] = fmaf(f2[s], valid[s], fa[2]);
+        } else if (((t + s) & 1) == 0) {
+          pa1 = f1;
+          pa2 = f2[s] * valid[s];
+        } else {
+          const float g1 = 0.5f * (pa1 + f1), g2 = 0.5f * (pa2 + f2[s] * valid[s]);
+          fa[0] += g1; fa[1] = fmaf(g1, g1, fa[1]);
+          fa[2] += g2;
+        }
       }
     }
     // side B: library samples drawn here (library frame), partner = query
@@ -471,11 +505,28 @@ __global__ __launch_bounds__(64) void k_screen(ScreenArgs a) {
 #pragma unroll
       for (int s = 0; s < kSB; ++s) {
         const bool ok = (t + s) < per_lane;
-        const int64_t k = n_side + (int64_t)lane + (int64_t)kWave * (ok ? t + s : t);
-        sample_point(sBF, sBS, nb, idb, (uint64_t)k, a.key, rx[s], ry[s], rz[s]);
+        const int i = ok ? t + s : t;
+        if (!anti) {
+          const int64_t k = n_side + (int64_t)lane + (int64_t)kWave * i;
+          sample_point(sBF, sBS, nb, idb, (uint64_t)k, a.key, rx[s], ry[s], rz[s]);
+        } else if (kSB % 2 == 0) {
+          // both members of the pair from one Philox block (t and s even)
+          if ((s & 1) == 0) {
+            const int64_t pr = n_side / 2 + (int64_t)lane + (int64_t)kWave * (i >> 1);
+            sample_pair(sBF, sBS, nb, idb, (uint64_t)pr, a.key, rx[s], ry[s], rz[s],
+                        rx[s + 1 < kSB ? s + 1 : s], ry[s + 1 < kSB ? s + 1 : s],
+                        rz[s + 1 < kSB ? s + 1 : s]);
+          }
+        } else {
+          const int64_t k = n_side + 2 * (int64_t)lane + 2 * (int64_t)kWave * (i >> 1) + (i & 1);
+          sample_point_anti(sBF, sBS, nb, idb, (uint64_t)k, a.key, rx[s], ry[s], rz[s]);
+        }
+        valid[s] = ok ? 1.0f : 0.0f;
+      }
+#pragma unroll
+      for (int s = 0; s < kSB; ++s) {
         r2[s] = norm2(rx[s], ry[s], rz[s]);
         mb[s] = 0.0f; qb[s] = 1.0f; qa[s] = 1.0f;
-        valid[s] = ok ? 1.0f : 0.0f;
       }
       eval_density_x<kSB>(sBB, aBB, nb, rx, ry, rz, r2, mb, qb);
       eval_union_x<kSB>(sAB, aAB, nq, rx, ry, rz, r2, qa);
@@ -484,8 +535,17 @@ __global__ __launch_bounds__(64) void k_screen(ScreenArgs a) {
         const float ub = 1.0f - qb[s];
         const float w = bounded_weight(ub, mb[s]) * valid[s];
         const float f1 = w * (1.0f - qa[s]);
-        fb[0] += f1; fb[1] = fmaf(f1, f1, fb[1]);
-        fb[2] = fmaf(w, ub, fb[2]);
+        if (!anti) {
+          fb[0] += f1; fb[1] = fmaf(f1, f1, fb[1]);
+          fb[2] = fmaf(w, ub, fb[2]);
+        } else if (((t + s) & 1) == 0) {
+          pb1 = f1;
+          pb2 = w * ub;
+        } else {
+          const float g1 = 0.5f * (pb1 + f1), g2 = 0.5f * (pb2 + w * ub);
+          fb[0] += g1; fb[1] = fmaf(g1, g1, fb[1]);
+          fb[2] += g2;
+        }
       }
     }
 #pragma unroll
@@ -507,7 +567,7 @@ __global__ __launch_bounds__(64) void k_screen(ScreenArgs a) {
         //   SE(T)^2 = S'^2 (Za^2 Va + Zb^2 Vb) / (4 (n-1) D'^4),
         // so the test is S'^2 (Za^2 Va + Zb^2 Vb) <= 4 tau^2 (n-1) D'^4 with
         // D' != 0 (NaN sums never stop).
-        const double n = (double)n_side;
+        const double n = (double)(anti ? n_side / 2 : n_side);  // independent terms
         const double Sp = Za * S[2] + Zb * S[5];
         const double Dp = Sp - 0.5 * (Za * S[0] + Zb * S[3]);
         const double Va = fmax(n * S[1] - S[0] * S[0], 0.0);
@@ -523,8 +583,8 @@ __global__ __launch_bounds__(64) void k_screen(ScreenArgs a) {
   }
   if (lane == 0) {
     double T, O_ab, O_aa, O_bb;
-    const double se = se_tanimoto((double)n_side, Za, Zb, S[0], S[1], S[2], S[3], S[4], S[5],
-                                  &T, &O_ab, &O_aa, &O_bb);
+    const double se = se_tanimoto((double)(anti ? n_side / 2 : n_side), Za, Zb, S[0], S[1],
+                                  S[2], S[3], S[4], S[5], &T, &O_ab, &O_aa, &O_bb);
     a.T[p] = (float)T;
     a.se_T[p] = (float)se;
     if (a.O_ab) a.O_ab[p] = (float)O_ab;
@@ -563,25 +623,27 @@ hipError_t launch_fill_int(int* p, int n, int v, hipStream_t st) {
   return hipGetLastError();
 }
 
-int est_blocks(int64_t n) { return (int)((n + 256 * kEstSPT - 1) / (256 * kEstSPT)); }
+int est_blocks(int64_t n_units) {
+  return (int)((n_units + 256 * kEstSPT - 1) / (256 * kEstSPT));
+}
 
 hipError_t launch_estimate(const Prepared& A, const Prepared& B, const int* offA,
-                           const int* offB, int64_t n_a, int64_t n_b, uint2 key,
+                           const int* offB, int64_t n_a, int64_t n_b, uint2 key, int anti,
                            double* partials, int nblk, shape_result* out_dev, hipStream_t st) {
-  hipLaunchKernelGGL(k_est_partials, dim3(nblk, 2), dim3(256), 0, st, A, B, n_a, n_b, key,
+  hipLaunchKernelGGL(k_est_partials, dim3(nblk, 2), dim3(256), 0, st, A, B, n_a, n_b, key, anti,
                      partials, nblk, offA, offB);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_est_finalize, dim3(1), dim3(256), 0, st, partials, nblk, A, B, n_a, n_b,
-                     out_dev);
+                     anti, out_dev);
   return hipGetLastError();
 }
 
-hipError_t launch_query_cache(const Prepared& Q, const int* offQ, int64_t n, uint2 key,
+hipError_t launch_query_cache(const Prepared& Q, const int* offQ, int64_t n, uint2 key, int anti,
                               float4* qs, float* qf2, hipStream_t st) {
   const int64_t blocks = (n + 255) / 256;
   hipLaunchKernelGGL(k_query_cache, dim3((unsigned)blocks), dim3(256), 0, st, Q, offQ, n, key,
-                     qs, qf2);
+                     anti, qs, qf2);
   return hipGetLastError();
 }
 

@@ -52,6 +52,7 @@ struct ScreenArgs {
   double tau;
   uint2 key;
   const int* n_start;  // optional per-pair budgets (adaptive)
+  int anti;            // antithetic sampling: terms are pair means
   float* T;
   float* se_T;
   float* O_ab;
@@ -171,11 +172,11 @@ hipError_t launch_prepare(const MolsDev& in, const Prepared& out, int* flag, int
                           hipStream_t st);
 hipError_t launch_flag_or(int* flag, const int* set_flag, hipStream_t st);
 hipError_t launch_fill_int(int* p, int n, int v, hipStream_t st);
-int est_blocks(int64_t n);
+int est_blocks(int64_t n_units);
 hipError_t launch_estimate(const Prepared& A, const Prepared& B, const int* offA,
-                           const int* offB, int64_t n_a, int64_t n_b, uint2 key,
+                           const int* offB, int64_t n_a, int64_t n_b, uint2 key, int anti,
                            double* partials, int nblk, shape_result* out_dev, hipStream_t st);
-hipError_t launch_query_cache(const Prepared& Q, const int* offQ, int64_t n, uint2 key,
+hipError_t launch_query_cache(const Prepared& Q, const int* offQ, int64_t n, uint2 key, int anti,
                               float4* qs, float* qf2, hipStream_t st);
 size_t screen_lds_bytes(int max_q, int max_b);
 constexpr int kScreenVariants = 8;

@@ -105,6 +105,9 @@ def load_library():
                                         ctypes.POINTER(ShapeMols), vp, i32,
                                         ctypes.POINTER(ShapeScreenParams), vp, vp, vp]
         L.shape_prepare_cache.argtypes = [vp, ctypes.c_int]
+        L.shape_set_sampling.argtypes = [vp, i32]
+        L.shape_get_sampling.argtypes = [vp]
+        L.shape_get_sampling.restype = i32
         L.shape_screen_set_variant.argtypes = [vp, i32]
         L.shape_screen_get_variant.argtypes = [vp]
         L.shape_screen_get_variant.restype = i32
@@ -304,6 +307,14 @@ class Engine:
             self._ctx, ctypes.byref(q), ctypes.byref(l_), _ptr(pairs), n, ctypes.byref(prm),
             _stream(stream), ms, ctypes.byref(best)))
         return int(best.value), [float(x) for x in ms]
+
+    def sampling(self, antithetic: bool | None = None) -> bool:
+        """Select antithetic (True) or i.i.d. (False) sampling if given;
+        return whether antithetic sampling is on."""
+        L = load_library()
+        if antithetic is not None:
+            self._check(L.shape_set_sampling(self._ctx, 1 if antithetic else 0))
+        return int(L.shape_get_sampling(self._ctx)) == 1
 
     def prepare_cache(self, enable: bool = True):
         """Reuse the preparation of an unchanged molecule set across calls
