@@ -128,14 +128,24 @@ __global__ __launch_bounds__(kGridThreads) void k_grid_columns(const double* __r
   }
 }
 
-// Column partials summed in column order (one thread per integral), times h^3.
-__global__ void k_grid_final(const double* __restrict__ part, int n_cols, double h3,
-                             double* __restrict__ out) {
-  const int q = threadIdx.x;
-  if (q >= kGridSums) return;
+// Column partials summed in a fixed order, times h^3: workgroup q sums
+// integral q; thread t takes columns [t c/256, (t+1) c/256), then the 256
+// thread sums are added in thread order.
+__global__ __launch_bounds__(256) void k_grid_final(const double* __restrict__ part, int n_cols,
+                                                    double h3, double* __restrict__ out) {
+  __shared__ double red[256];
+  const int q = blockIdx.x, t = threadIdx.x;
+  const int per = (n_cols + 255) / 256;
+  const int c0 = t * per, c1 = min(n_cols, c0 + per);
   double v = 0.0;
-  for (int c = 0; c < n_cols; ++c) v += part[(int64_t)c * kGridSums + q];
-  out[q] = v * h3;
+  for (int c = c0; c < c1; ++c) v += part[(int64_t)c * kGridSums + q];
+  red[t] = v;
+  __syncthreads();
+  if (t == 0) {
+    double s = 0.0;
+    for (int i = 0; i < 256; ++i) s += red[i];
+    out[q] = s * h3;
+  }
 }
 
 hipError_t launch_grid_box(const float* xa, int na, const float* xb, int nb, double* box,
@@ -158,7 +168,8 @@ hipError_t launch_grid(const float* xa, const float* aa, int na, const float* xb
                      (size_t)n * sizeof(double), st, tables, na, nb, g, part);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_grid_final, dim3(1), dim3(64), 0, st, part, cols, g.h * g.h * g.h, out);
+  hipLaunchKernelGGL(k_grid_final, dim3(kGridSums), dim3(256), 0, st, part, cols, g.h * g.h * g.h,
+                     out);
   return hipGetLastError();
 }
 

@@ -621,9 +621,10 @@ __global__ void k_seed_budget(const float* __restrict__ raw, int64_t ld,
 }
 
 // Column sums of A[M][N] (row stride lda), deterministic: stage 1 sums
-// chunks of kColRows rows per column (threads along columns, coalesced), stage
-// 2 adds the chunk partials in order.
-constexpr int kColRows = 256;
+// chunks of kColRows rows per column (threads along columns, coalesced; many
+// chunks so that a 4096-row batch fills the chip), stage 2 adds the chunk
+// partials in order.
+constexpr int kColRows = 32;
 
 __global__ void k_colsum_partial(const float* __restrict__ A, int M, int N, int64_t lda,
                                  float* __restrict__ part) {
