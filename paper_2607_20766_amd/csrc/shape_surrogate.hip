@@ -52,12 +52,14 @@ __device__ void sym3_eigen_desc(double a00, double a11, double a22, double a01, 
       }
 }
 
-// (pi / (a + b))^(3/2) exp(-a b / (a + b) d2), with hardware reciprocal,
-// square root and exp2 (a feature, not an estimate: ~1e-6 relative).
+// (pi / (a + b))^(3/2) exp(-a b / (a + b) d2): rs = 1/sqrt(a + b) gives
+// (pi/(a+b))^(3/2) = pi^(3/2) rs^3 and 1/(a+b) = rs^2 from one hardware
+// rsqrt; exp by exp2 (a feature, not an estimate: ~1e-6 relative).
 __device__ __forceinline__ float fo_term(float a, float b, float d2) {
-  const float ir = __builtin_amdgcn_rcpf(a + b);
-  const float t = 3.14159265358979f * ir;
-  return t * __builtin_amdgcn_sqrtf(t) * __builtin_amdgcn_exp2f(-1.44269504088896f * a * b * ir * d2);
+  const float rs = __builtin_amdgcn_rsqf(a + b);
+  const float ir = rs * rs;
+  return 5.56832799683170785f * ir * rs *
+         __builtin_amdgcn_exp2f(-1.44269504088896f * a * b * ir * d2);
 }
 
 __global__ __launch_bounds__(64) void k_features(Prepared M, const int* __restrict__ off,
@@ -122,17 +124,23 @@ __global__ __launch_bounds__(64) void k_features(Prepared M, const int* __restri
   // first-order self-overlap: diagonal + 2 x the i < j triangle, flattened
   float fo = 0.f;
   for (int i = lane; i < n; i += kWave) fo += fo_term(sC[i].w, sC[i].w, 0.f);
-  const int P = n * (n - 1) / 2;
-  for (int p = lane; p < P; p += kWave) {
-    // row i of the strict upper triangle holding flat index p
-    int i = n - 2 - (int)floorf(sqrtf((float)(-8 * p + 4 * n * (n - 1) - 7)) * 0.5f - 0.5f);
-    i = i < 0 ? 0 : (i > n - 2 ? n - 2 : i);
-    while (i > 0 && i * n - i * (i + 1) / 2 > p) --i;
-    while (i < n - 2 && (i + 1) * n - (i + 1) * (i + 2) / 2 <= p) ++i;
-    const int j = p - (i * n - i * (i + 1) / 2) + i + 1;
+  // strict upper triangle i < j in row-major order, flat index p = lane +
+  // 64 t: the first position from the row lengths, then stepped by 64
+  // (row i holds j = i+1 .. n-1)
+  int i = 0, j = 1 + lane;
+  while (i < n - 1 && j >= n) {
+    j -= n - i - 2;  // j - n + (i + 2): onto the next row
+    ++i;
+  }
+  while (i < n - 1) {
     const float4 ci = sC[i], cj = sC[j];
     const float dx = ci.x - cj.x, dy = ci.y - cj.y, dz = ci.z - cj.z;
     fo = fmaf(2.0f, fo_term(ci.w, cj.w, fmaf(dx, dx, fmaf(dy, dy, dz * dz))), fo);
+    j += kWave;
+    while (i < n - 1 && j >= n) {
+      j -= n - i - 2;
+      ++i;
+    }
   }
   const float fo_sum = wave_sum_dpp(fo);
   if (lane < 16) f[lane] = (float)hist_mine;
