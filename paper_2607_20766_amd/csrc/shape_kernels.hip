@@ -25,40 +25,68 @@ __global__ void k_alpha_from_radius(const float* __restrict__ R, int64_t n, doub
 
 // ---------------------------------------------------------------------------
 // Molecule preparation, one wave per molecule (four per workgroup), FP64:
-// mixture weights v_i = (pi/alpha_i)^(3/2) (= t sqrt t, t = pi/alpha_i) per
-// lane, then Z = sum v_i and the running sums for the thresholds
-// floor(2^32 cumsum(v)/Z) in atom order by one lane, so both are the plain
-// sequential sums bit for bit; records are written by all lanes.
+// mixture weights v_i = (pi/alpha_i)^(3/2) (= t sqrt t, t = pi/alpha_i), one
+// atom per lane and chunk of 64; Z = sum v_i and the running sums behind the
+// thresholds floor(2^32 cumsum(v)/Z) are the plain sequential sums in atom
+// order, bit for bit: the wave adds the weights one lane at a time (read
+// across lanes, no LDS round trips) and each lane keeps the running sum that
+// ends at its own atom.  Inputs stay in registers between the two phases.
 // ---------------------------------------------------------------------------
 constexpr int kPrepWaves = 4;
+constexpr int kPrepChunks = SHAPE_MAX_ATOMS / kWave;
+
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)b, l);
+  const long long hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double((hi << 32) | lo);
+}
 
 __global__ __launch_bounds__(256) void k_prepare(MolsDev in, Prepared out, int* __restrict__ flag,
                                                  int* __restrict__ set_flag) {
   // FP64 without contraction: Z and the thresholds are the values the plain
   // expressions define, bit for bit.
 #pragma clang fp contract(off)
-  __shared__ double sv[kPrepWaves][SHAPE_MAX_ATOMS];
-  __shared__ double sZ[kPrepWaves];
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
   const int m = blockIdx.x * kPrepWaves + w;
   if (m >= in.n_mols) return;
   const int a0 = in.off[m], a1 = in.off[m + 1];
   const int n = a1 - a0;
   const bool range_bad = !(a0 >= 0 && (int64_t)a1 <= in.n_atoms && n >= 1 && n <= in.max_atoms);
+  const int n_ok = range_bad ? 0 : n;  // n_ok <= SHAPE_MAX_ATOMS
   bool bad = range_bad;
-  double* v = sv[w];
-  double cx = 0.0, cy = 0.0, cz = 0.0;
-  if (!range_bad) {
-    for (int i = lane; i < n; i += kWave) {
-      const double al = (double)in.alpha[a0 + i];
+  float px[kPrepChunks], py[kPrepChunks], pz[kPrepChunks], pa[kPrepChunks];
+  double run[kPrepChunks];  // running sum through this lane's atom of each chunk
+  float cx = 0.0f, cy = 0.0f, cz = 0.0f;
+  double cum = 0.0;
+#pragma unroll
+  for (int c = 0; c < kPrepChunks; ++c) {
+    px[c] = py[c] = pz[c] = 0.0f;
+    pa[c] = 1.0f;
+    run[c] = 0.0;
+    if (c * kWave >= n_ok) continue;  // uniform
+    const int i = c * kWave + lane;
+    double v = 0.0;
+    if (i < n_ok) {
+      const float al = in.alpha[a0 + i];
       const float x = in.xyz[3 * (a0 + i)], y = in.xyz[3 * (a0 + i) + 1],
                   z = in.xyz[3 * (a0 + i) + 2];
-      if (!(al > 0.0) || !isfinite(al) || !isfinite(x) || !isfinite(y) || !isfinite(z)) bad = true;
-      const double t = M_PI / al;
-      v[i] = t * sqrt(t);
-      cx += (double)x;
-      cy += (double)y;
-      cz += (double)z;
+      if (!(al > 0.0f) || !isfinite(al) || !isfinite(x) || !isfinite(y) || !isfinite(z))
+        bad = true;
+      const double t = M_PI / (double)al;
+      v = t * sqrt(t);
+      px[c] = x;
+      py[c] = y;
+      pz[c] = z;
+      pa[c] = al;
+      cx += x;
+      cy += y;
+      cz += z;
+    }
+    const int cnt = min(kWave, n_ok - c * kWave);
+    for (int j = 0; j < cnt; ++j) {
+      cum += readlane_f64(v, j);
+      if (lane == j) run[c] = cum;
     }
   }
   bad = __ballot(bad) != 0;
@@ -75,37 +103,30 @@ __global__ __launch_bounds__(256) void k_prepare(MolsDev in, Prepared out, int* 
     }
     return;
   }
-  cx = wave_sum(cx);
-  cy = wave_sum(cy);
-  cz = wave_sum(cz);
-  wave_lds_sync();
+  // the centre is only the origin of the molecule's frame: FP32 sums
+  const float scx = wave_sum_dpp(cx), scy = wave_sum_dpp(cy), scz = wave_sum_dpp(cz);
+  const double Z = cum;
   if (lane == 0) {
-    double Z = 0.0;
-    for (int i = 0; i < n; ++i) Z += v[i];
-    double cum = 0.0;
-    for (int i = 0; i < n; ++i) {
-      cum += v[i];
-      v[i] = cum;  // running sums replace the weights
-    }
-    sZ[w] = Z;
     out.Z[m] = Z;
-    out.centre[m] = make_float4((float)(cx / n), (float)(cy / n), (float)(cz / n), 0.0f);
+    const float inv_n = 1.0f / (float)n;
+    out.centre[m] = make_float4(scx * inv_n, scy * inv_n, scz * inv_n, 0.0f);
   }
-  wave_lds_sync();
-  const double Z = sZ[w];
   const double log2e = 1.4426950408889634074;
-  for (int i = lane; i < n; i += kWave) {
-    const double al = (double)in.alpha[a0 + i];
+#pragma unroll
+  for (int c = 0; c < kPrepChunks; ++c) {
+    const int i = c * kWave + lane;
+    if (i >= n) continue;
+    const double al = (double)pa[c];
     Atom a;
-    a.x = in.xyz[3 * (a0 + i)];
-    a.y = in.xyz[3 * (a0 + i) + 1];
-    a.z = in.xyz[3 * (a0 + i) + 2];
+    a.x = px[c];
+    a.y = py[c];
+    a.z = pz[c];
     a.a2 = (float)(al * log2e);
     out.atom[a0 + i] = a;
     AtomSampling smp;
     smp.sd = (float)(1.0 / sqrt(2.0 * al));
     if (i + 1 < n) {
-      double f = floor(4294967296.0 * (v[i] / Z));
+      double f = floor(4294967296.0 * (run[c] / Z));
       if (f > 4294967295.0) f = 4294967295.0;
       smp.thr = (uint32_t)f;
     } else {
