@@ -71,17 +71,20 @@ __global__ __launch_bounds__(64) void k_features(Prepared M, const int* __restri
   const int lane = threadIdx.x;
   if (mol >= n_mols) return;
   float* f = out + (size_t)mol * 24;
-  if (M.bad[mol] != 0) {
+  // the per-molecule words are loaded together, ahead of the branch
+  const int bad = M.bad[mol], a0 = off[mol], a1 = off[mol + 1];
+  const double Zm = M.Z[mol];
+  if (bad != 0) {
     for (int k = lane; k < 24; k += kWave) f[k] = __builtin_nanf("");
     return;
   }
-  const int a0 = off[mol], n = off[mol + 1] - a0;
+  const int n = a1 - a0;
   for (int i = lane; i < n; i += kWave) {
     const Atom at = M.atom[a0 + i];
     sC[i] = make_float4(at.x, at.y, at.z, alpha[a0 + i]);
   }
-  __syncthreads();
-  const float iZ = (float)(1.0 / M.Z[mol]);
+  wave_lds_sync();
+  const float iZ = (float)(1.0 / Zm);
   // pass 1: mixture mean
   float mx = 0.f, my = 0.f, mz = 0.f;
   for (int i = lane; i < n; i += kWave) {
@@ -170,35 +173,50 @@ __global__ void k_features_eigen(const Prepared M, int n_mols, const float* __re
 
 // First-order cross-overlap of (query, library molecule) pairs at their
 // current poses, Eq. fo: sum_ij (pi/(a_i+a_j))^(3/2)
-// exp(-a_i a_j/(a_i+a_j) |c_i - c_j|^2); one wave per pair, the N_q N_b atom
+// exp(-a_i a_j/(a_i+a_j) |c_i - c_j|^2); one wave per pair (four per
+// workgroup, sharing the query's atoms in LDS), the N_q N_b atom
 // pairs spread over all 64 lanes (row i = p / N_b stepped incrementally),
 // FP32 sums, DPP wave sum.
-__global__ __launch_bounds__(64) void k_fo_cross(Prepared Q, const int* __restrict__ offQ,
-                                                 const float* __restrict__ alphaQ, Prepared L,
-                                                 const int* __restrict__ offL,
-                                                 const float* __restrict__ alphaL,
-                                                 const int* __restrict__ pairs, int n_pairs,
-                                                 int n_lib, float* __restrict__ out) {
+constexpr int kFoWaves = 4;
+
+__global__ __launch_bounds__(kWave * kFoWaves) void k_fo_cross(
+    Prepared Q, const int* __restrict__ offQ, const float* __restrict__ alphaQ, Prepared L,
+    const int* __restrict__ offL, const float* __restrict__ alphaL, const int* __restrict__ pairs,
+    int n_pairs, int n_lib, float* __restrict__ out) {
+  // the query's atoms once per workgroup, each wave's library molecule apart
   __shared__ float4 sA[SHAPE_MAX_ATOMS];
-  __shared__ float4 sB[SHAPE_MAX_ATOMS];
-  const int p = blockIdx.x, lane = threadIdx.x;
-  if (p >= n_pairs) return;
-  const int m = pairs ? pairs[p] : p;
-  if (Q.bad[0] != 0 || m < 0 || m >= n_lib || L.bad[m] != 0) {
-    if (lane == 0) out[p] = __builtin_nanf("");
+  __shared__ float4 sBall[kFoWaves][SHAPE_MAX_ATOMS];
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  const int p = blockIdx.x * kFoWaves + w;
+  if (Q.bad[0] != 0) {  // grid-uniform
+    if (p < n_pairs && lane == 0) out[p] = __builtin_nanf("");
     return;
   }
   const int q0 = offQ[0], nq = offQ[1] - q0;
-  const int b0 = offL[m], nb = offL[m + 1] - b0;
-  for (int i = lane; i < nq; i += kWave) {
+  for (int i = threadIdx.x; i < nq; i += kWave * kFoWaves) {
     const Atom at = Q.atom[q0 + i];
     sA[i] = make_float4(at.x, at.y, at.z, alphaQ[q0 + i]);
   }
+  __syncthreads();  // reached by every wave: no return before it
+  if (p >= n_pairs) return;
+  const int m = pairs ? pairs[p] : p;
+  int bad = 1, b0 = 0, b1 = 0;  // the molecule's words are loaded together
+  if (m >= 0 && m < n_lib) {
+    bad = L.bad[m];
+    b0 = offL[m];
+    b1 = offL[m + 1];
+  }
+  if (bad != 0) {
+    if (lane == 0) out[p] = __builtin_nanf("");
+    return;
+  }
+  float4* sB = sBall[w];
+  const int nb = b1 - b0;
   for (int j = lane; j < nb; j += kWave) {
     const Atom at = L.atom[b0 + j];
     sB[j] = make_float4(at.x, at.y, at.z, alphaL[b0 + j]);
   }
-  __syncthreads();
+  wave_lds_sync();
   const int di = kWave / nb, dj = kWave % nb;
   int i = lane / nb, j = lane % nb;
   float acc = 0.0f;
@@ -530,17 +548,57 @@ __global__ __launch_bounds__(256, 2) void k_mlp_infer(MlpArgs a) {
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
   const int li = lane & 15, lk = lane >> 4;
   const int row0 = blockIdx.x * kMlpRows;
-  // standardised pair features, rounded to bf16 (rows beyond n are zero)
-  for (int t = tid; t < kMlpRows * kMlpIn; t += 256) {
-    const int r = t / kMlpIn, j = t % kMlpIn;
+  // standardised pair features, rounded to bf16 (rows beyond n are zero):
+  // thread (half h, row r) writes features [48 h, 48 h + 48) of row r from
+  // the two molecules' 24 features; h is uniform per wave, so the statistics
+  // are scalar loads.  Same expressions as pair_feature.
+  {
+    const int r = tid & (kMlpRows - 1);
+    const int h = __builtin_amdgcn_readfirstlane(tid / kMlpRows);
     const int p = row0 + r;
-    float v = 0.0f;
+    float raw[48];
     if (p < a.n) {
       const int m = a.idx ? a.idx[p] : p;
       const int q = a.qidx ? a.qidx[p] : 0;
-      v = pair_feature(a.fq, a.flib, q, m, j, a.fo_cross, p, a.mean, a.inv_std);
+      const float* fa = a.fq + (size_t)q * 24;
+      const float* fb = a.flib + (size_t)m * 24;
+      float va[24], vb[24];
+#pragma unroll
+      for (int k = 0; k < 24; ++k) {
+        va[k] = fa[k];
+        vb[k] = fb[k];
+      }
+      if (h == 0) {
+#pragma unroll
+        for (int k = 0; k < 24; ++k) {
+          raw[k] = va[k];
+          raw[24 + k] = vb[k];
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < 24; ++k) {
+          raw[k] = fabsf(va[k] - vb[k]);
+          raw[24 + k] = va[k] * vb[k];
+        }
+        if (a.fo_cross) {
+          const float o = a.fo_cross[p];
+          raw[23] = o / (va[23] + vb[23] - o);
+          raw[47] = o;
+        }
+      }
+      const float* mu = a.mean + 48 * h;
+      const float* is = a.inv_std + 48 * h;
+#pragma unroll
+      for (int t = 0; t < 48; ++t) raw[t] = (raw[t] - mu[t]) * is[t];
+    } else {
+#pragma unroll
+      for (int t = 0; t < 48; ++t) raw[t] = 0.0f;
     }
-    H[r * kMlpLd + j] = to_bf16(v);
+    v4s* dst = reinterpret_cast<v4s*>(&H[r * kMlpLd + 48 * h]);
+#pragma unroll
+    for (int c = 0; c < 12; ++c)
+      dst[c] = v4s{to_bf16(raw[4 * c]), to_bf16(raw[4 * c + 1]), to_bf16(raw[4 * c + 2]),
+                   to_bf16(raw[4 * c + 3])};
   }
   __syncthreads();
   // three hidden layers: wave w computes all 128 rows x columns [64 w, 64 w + 64)
@@ -553,10 +611,18 @@ __global__ __launch_bounds__(256, 2) void k_mlp_infer(MlpArgs a) {
     for (int i = 0; i < 8; ++i)
 #pragma unroll
       for (int j = 0; j < 4; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+    // weight fragments one k-block ahead of the products
+    v4s bn[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) bn[j] = W[(wave * 4 + j) * kWave + lane];
     for (int kb = 0; kb < kbs; ++kb) {
       v4s b[4], x[8];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = W[(kb * 16 + wave * 4 + j) * kWave + lane];
+      for (int j = 0; j < 4; ++j) b[j] = bn[j];
+      if (kb + 1 < kbs) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) bn[j] = W[((kb + 1) * 16 + wave * 4 + j) * kWave + lane];
+      }
 #pragma unroll
       for (int i = 0; i < 8; ++i)
         x[i] = *reinterpret_cast<const v4s*>(&H[(16 * i + li) * kMlpLd + kb * 16 + 4 * lk]);
@@ -883,8 +949,9 @@ hipError_t launch_fo_cross(const Prepared& Q, const int* offQ, const float* alph
                            const Prepared& L, const int* offL, const float* alphaL,
                            const int* pairs, int n_pairs, int n_lib, float* out,
                            hipStream_t st) {
-  hipLaunchKernelGGL(k_fo_cross, dim3((unsigned)n_pairs), dim3(kWave), 0, st, Q, offQ, alphaQ,
-                     L, offL, alphaL, pairs, n_pairs, n_lib, out);
+  hipLaunchKernelGGL(k_fo_cross, dim3((unsigned)((n_pairs + kFoWaves - 1) / kFoWaves)),
+                     dim3(kWave * kFoWaves), 0, st, Q, offQ, alphaQ, L, offL, alphaL, pairs,
+                     n_pairs, n_lib, out);
   return hipGetLastError();
 }
 
