@@ -326,6 +326,18 @@ __device__ __forceinline__ float wave_sumf(float v) {
   return v;
 }
 
+// Workgroups go to the chip's eight XCDs, each with its own L2, in
+// round-robin order of blockIdx.  xcd_chunk(b, G) renumbers them so that each
+// XCD takes one contiguous range of [0, G): neighbouring molecules, whose
+// records share cache lines, then meet in the same L2 instead of being
+// fetched by two.  A bijection on [0, G) for any G (checked on the host).
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_chunk(int b, int G) {
+  const int q = G / kXcds, r = G % kXcds;
+  const int x = b % kXcds, k = b / kXcds;
+  return x * q + (x < r ? x : r) + k;
+}
+
 // Orders LDS writes of this wave before its later LDS reads (wave-private
 // staging needs no workgroup barrier).
 __device__ __forceinline__ void wave_lds_sync() {

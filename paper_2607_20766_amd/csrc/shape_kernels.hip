@@ -371,7 +371,8 @@ __global__ __launch_bounds__(256) void k_query_cache(Prepared Qp, const int* __r
 // Screening kernel: one single-wave workgroup per (query, library) pair, so
 // the pair index comes from blockIdx and is uniform by construction (no
 // cross-lane broadcast); the hardware dispatcher balances pairs of uneven
-// size.  Per round, `round_side` samples on each side:
+// size.  Pairs are renumbered so that each XCD screens one contiguous range
+// of the library (xcd_chunk).  Per round, `round_side` samples on each side:
 //   side A (query samples, from the cache): f1 = w_A u_B, f2 = w_A u_A
 //   side B (library samples, drawn here):   f1 = w_B u_A, f2 = w_B u_B
 // FP32 in-lane sums per round, FP64 lane accumulators across rounds, wave
@@ -432,7 +433,7 @@ __global__ __launch_bounds__(64) void k_screen(ScreenArgs a) {
   float* aBA = aBB + a.max_b;
   float* aAB = aBA + a.max_b;
   const int lane = threadIdx.x;
-  const int p = blockIdx.x;
+  const int p = xcd_chunk(blockIdx.x, gridDim.x);  // grid = n_pairs
   if (p >= a.n_pairs) return;
   const int m = a.pairs ? a.pairs[p] : p;
   const bool bad = a.Q.bad[0] != 0 || m < 0 || m >= a.n_lib || a.L.bad[m] != 0;

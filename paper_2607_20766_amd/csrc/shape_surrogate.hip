@@ -67,7 +67,7 @@ __global__ __launch_bounds__(64) void k_features(Prepared M, const int* __restri
                                                  float* __restrict__ out,
                                                  float* __restrict__ mom) {
   __shared__ float4 sC[SHAPE_MAX_ATOMS];  // x, y, z, alpha
-  const int mol = blockIdx.x;
+  const int mol = xcd_chunk(blockIdx.x, gridDim.x);  // grid = n_mols
   const int lane = threadIdx.x;
   if (mol >= n_mols) return;
   float* f = out + (size_t)mol * 24;
@@ -187,7 +187,7 @@ __global__ __launch_bounds__(kWave * kFoWaves) void k_fo_cross(
   __shared__ float4 sA[SHAPE_MAX_ATOMS];
   __shared__ float4 sBall[kFoWaves][SHAPE_MAX_ATOMS];
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-  const int p = blockIdx.x * kFoWaves + w;
+  const int p = xcd_chunk(blockIdx.x, gridDim.x) * kFoWaves + w;
   if (Q.bad[0] != 0) {  // grid-uniform
     if (p < n_pairs && lane == 0) out[p] = __builtin_nanf("");
     return;
