@@ -330,7 +330,9 @@ __device__ __forceinline__ float wave_sumf(float v) {
 // round-robin order of blockIdx.  xcd_chunk(b, G) renumbers them so that each
 // XCD takes one contiguous range of [0, G): neighbouring molecules, whose
 // records share cache lines, then meet in the same L2 instead of being
-// fetched by two.  A bijection on [0, G) for any G (checked on the host).
+// fetched by two.  A bijection on [0, G) for any G: XCD x holds the
+// q + [x < r] blocks b = x, x + 8, ... (q = G / 8, r = G % 8) and numbers
+// them from x q + min(x, r) on, which is where XCD x - 1's range ends.
 constexpr int kXcds = 8;
 __device__ __forceinline__ int xcd_chunk(int b, int G) {
   const int q = G / kXcds, r = G % kXcds;
