@@ -413,6 +413,7 @@ def bench_triage(eng, n_lib, n_queries=256, n_train_lib=3907, epochs=10):
     k1 = n_lib // 100
     true_top = set(np.argsort(-T_plain, kind="stable")[:k1].tolist())
     top = top.cpu().numpy()
+    n_plain_top = int(plain["n_used"].cpu().numpy().astype(np.int64)[top].sum())
     T_ref = out["T"].cpu().numpy()
     got = set(top[np.argsort(-T_ref, kind="stable")[:k1]].tolist())
     T_hat, _ = tr.to_labels(raw.cpu().numpy())
@@ -439,6 +440,9 @@ def bench_triage(eng, n_lib, n_queries=256, n_train_lib=3907, epochs=10):
         "ms_plain_adaptive_is_direct_launches": t_plain_direct * 1e3,
         "is_samples_surrogate_is": n_tri,
         "is_samples_plain": n_plain,
+        # plain adaptive IS's samples on the same refined pairs: the seeded
+        # budgets' overshoot (or saving) against rounds from the start
+        "is_samples_plain_on_refined_pairs": n_plain_top,
         "recall_top1pct": len(true_top & got) / k1,
         "mae_T_surrogate_vs_is": float(np.abs(T_hat - T_plain).mean()),
         "spearman_surrogate_vs_is": float(scipy.stats.spearmanr(T_hat, T_plain)[0]),
