@@ -327,17 +327,22 @@ __device__ __forceinline__ float wave_sumf(float v) {
 }
 
 // Workgroups go to the chip's eight XCDs, each with its own L2, in
-// round-robin order of blockIdx.  xcd_chunk(b, G) renumbers them so that each
-// XCD takes one contiguous range of [0, G): neighbouring molecules, whose
-// records share cache lines, then meet in the same L2 instead of being
-// fetched by two.  A bijection on [0, G) for any G: XCD x holds the
-// q + [x < r] blocks b = x, x + 8, ... (q = G / 8, r = G % 8) and numbers
-// them from x q + min(x, r) on, which is where XCD x - 1's range ends.
+// round-robin order of blockIdx.  xcd_chunk(b, G) renumbers them so that
+// tiles of kXcdTile consecutive items are each handled by one XCD (tile t on
+// XCD t mod 8): neighbouring molecules, whose records share cache lines, then
+// meet in one L2 instead of being fetched by two, and a tile's outputs fill
+// whole lines.  Tiles, not one contiguous range per XCD, keep the XCDs evenly
+// loaded when the work per item drifts along the index (a sorted library).
+// A bijection on [0, G): below F = G - G mod (8 kXcdTile) block b = 8 k + x
+// (XCD x, its k-th block) takes item (8 (k / T) + x) T + k mod T, which runs
+// over [0, F) once; blocks from F on keep their index.
 constexpr int kXcds = 8;
+constexpr int kXcdTile = 64;
 __device__ __forceinline__ int xcd_chunk(int b, int G) {
-  const int q = G / kXcds, r = G % kXcds;
+  const int F = G - G % (kXcds * kXcdTile);
+  if (b >= F) return b;
   const int x = b % kXcds, k = b / kXcds;
-  return x * q + (x < r ? x : r) + k;
+  return ((k / kXcdTile) * kXcds + x) * kXcdTile + k % kXcdTile;
 }
 
 // Orders LDS writes of this wave before its later LDS reads (wave-private

@@ -371,8 +371,8 @@ __global__ __launch_bounds__(256) void k_query_cache(Prepared Qp, const int* __r
 // Screening kernel: one single-wave workgroup per (query, library) pair, so
 // the pair index comes from blockIdx and is uniform by construction (no
 // cross-lane broadcast); the hardware dispatcher balances pairs of uneven
-// size.  Pairs are renumbered so that each XCD screens one contiguous range
-// of the library (xcd_chunk).  Per round, `round_side` samples on each side:
+// size.  Pairs are renumbered so that each XCD screens tiles of consecutive
+// library molecules (xcd_chunk).  Per round, `round_side` samples on each side:
 //   side A (query samples, from the cache): f1 = w_A u_B, f2 = w_A u_A
 //   side B (library samples, drawn here):   f1 = w_B u_A, f2 = w_B u_B
 // FP32 in-lane sums per round, FP64 lane accumulators across rounds, wave
