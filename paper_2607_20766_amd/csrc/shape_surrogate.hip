@@ -89,8 +89,9 @@ __global__ __launch_bounds__(64) void k_features(Prepared M, const int* __restri
   float mx = 0.f, my = 0.f, mz = 0.f;
   for (int i = lane; i < n; i += kWave) {
     const float4 c = sC[i];
-    const float t = 3.14159265358979f / c.w;
-    const float pi = t * sqrtf(t) * iZ;
+    // descriptors, not estimates: hardware reciprocal and square root (1 ulp)
+    const float t = 3.14159265358979f * __builtin_amdgcn_rcpf(c.w);
+    const float pi = t * __builtin_amdgcn_sqrtf(t) * iZ;
     mx = fmaf(pi, c.x, mx); my = fmaf(pi, c.y, my); mz = fmaf(pi, c.z, mz);
   }
   mx = wave_sum_dpp(mx); my = wave_sum_dpp(my); mz = wave_sum_dpp(mz);
@@ -102,13 +103,14 @@ __global__ __launch_bounds__(64) void k_features(Prepared M, const int* __restri
     int bin = -1, cls = -1;
     if (i < n) {
       const float4 c = sC[i];
-      const float t = 3.14159265358979f / c.w;
-      const float pi = t * sqrtf(t) * iZ;
-      const float x = c.x - mx, y = c.y - my, z = c.z - mz, h = 0.5f / c.w;
+      const float ia = __builtin_amdgcn_rcpf(c.w);
+      const float t = 3.14159265358979f * ia;
+      const float pi = t * __builtin_amdgcn_sqrtf(t) * iZ;
+      const float x = c.x - mx, y = c.y - my, z = c.z - mz, h = 0.5f * ia;
       sxx = fmaf(pi, fmaf(x, x, h), sxx); syy = fmaf(pi, fmaf(y, y, h), syy);
       szz = fmaf(pi, fmaf(z, z, h), szz);
       sxy = fmaf(pi * x, y, sxy); sxz = fmaf(pi * x, z, sxz); syz = fmaf(pi * y, z, syz);
-      const float r = sqrtf(fmaf(x, x, fmaf(y, y, z * z)));
+      const float r = __builtin_amdgcn_sqrtf(fmaf(x, x, fmaf(y, y, z * z)));
       bin = (int)floorf(r * 2.0f);
       bin = bin > 15 ? 15 : bin;
       cls = c.w < 0.767f ? 0 : (c.w < 0.893f ? 1 : (c.w < 0.995f ? 2 : 3));
