@@ -381,7 +381,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
 // waves computes a 64 x 64 sub-tile as 4 x 4 MFMA 16x16x16 tiles.
 constexpr int kTM = 128, kTN = 128, kTK = 32, kLdk = kTK + 8;
 
-__global__ __launch_bounds__(256) void k_gemm_bf16_tiled(GemmArgs g) {
+__global__ __launch_bounds__(256, 2) void k_gemm_bf16_tiled(GemmArgs g) {
   __shared__ short As[kTM * kLdk];
   __shared__ short Bs[kTN * kLdk];
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
@@ -397,10 +397,12 @@ __global__ __launch_bounds__(256) void k_gemm_bf16_tiled(GemmArgs g) {
   const bool b_nfast = g.sbn == 1;
   const int kb = g.part ? blockIdx.z * g.k_chunk : 0;
   const int ke = g.part ? min(g.K, kb + g.k_chunk) : g.K;
-  for (int k0 = kb; k0 < ke; k0 += kTK) {
-    // stage A: 128 x 32 elements, 16 per thread
+  // Slabs of kTK values of k: slab s+1 is read from global memory into
+  // registers while the matrix cores work on slab s from LDS.
+  float pa[16], pb[16];
+  auto load_slab = [&](int k0) {
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
+    for (int r = 0; r < 16; ++r) {  // A: 128 x 32 elements, 16 per thread
       int m, k;
       if (a_kfast) {
         k = tid & 31;
@@ -410,12 +412,10 @@ __global__ __launch_bounds__(256) void k_gemm_bf16_tiled(GemmArgs g) {
         k = (tid >> 7) + 2 * r;
       }
       const int gm = bm + m, gk = k0 + k;
-      const float v = (gm < g.M && gk < ke) ? g.A[(int64_t)gm * g.sam + (int64_t)gk * g.sak] : 0.f;
-      As[m * kLdk + k] = to_bf16(v);
+      pa[r] = (gm < g.M && gk < ke) ? g.A[(int64_t)gm * g.sam + (int64_t)gk * g.sak] : 0.f;
     }
-    // stage B: 32 x 128 elements, stored transposed as Bs[n][k]
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
+    for (int r = 0; r < 16; ++r) {  // B: 32 x 128 elements
       int n, k;
       if (b_nfast) {
         n = tid & 127;
@@ -425,10 +425,28 @@ __global__ __launch_bounds__(256) void k_gemm_bf16_tiled(GemmArgs g) {
         n = (tid >> 5) + 8 * r;
       }
       const int gn = bn + n, gk = k0 + k;
-      const float v = (gn < g.N && gk < ke) ? g.B[(int64_t)gk * g.sbk + (int64_t)gn * g.sbn] : 0.f;
-      Bs[n * kLdk + k] = to_bf16(v);
+      pb[r] = (gn < g.N && gk < ke) ? g.B[(int64_t)gk * g.sbk + (int64_t)gn * g.sbn] : 0.f;
     }
+  };
+  auto store_slab = [&]() {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int m = a_kfast ? (tid >> 5) + 8 * r : tid & 127;
+      const int k = a_kfast ? tid & 31 : (tid >> 7) + 2 * r;
+      As[m * kLdk + k] = to_bf16(pa[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {  // stored transposed as Bs[n][k]
+      const int n = b_nfast ? tid & 127 : (tid >> 5) + 8 * r;
+      const int k = b_nfast ? (tid >> 7) + 2 * r : tid & 31;
+      Bs[n * kLdk + k] = to_bf16(pb[r]);
+    }
+  };
+  if (kb < ke) load_slab(kb);
+  for (int k0 = kb; k0 < ke; k0 += kTK) {
+    store_slab();
     __syncthreads();
+    if (k0 + kTK < ke) load_slab(k0 + kTK);
 #pragma unroll
     for (int kk = 0; kk < kTK; kk += 16) {
       v4s a[4], b[4];
