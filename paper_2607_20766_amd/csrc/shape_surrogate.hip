@@ -735,8 +735,17 @@ __global__ void k_colsum_final(const float* __restrict__ part, int chunks, int N
                                float* __restrict__ out) {
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= N) return;
+  // chunk order; the loads of eight chunks are issued before their adds
   double s = 0.0;
-  for (int c = 0; c < chunks; ++c) s += part[(size_t)c * N + n];
+  int c = 0;
+  for (; c + 8 <= chunks; c += 8) {
+    float v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = part[(size_t)(c + u) * N + n];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += v[u];
+  }
+  for (; c < chunks; ++c) s += part[(size_t)c * N + n];
   out[n] = (float)s;
 }
 

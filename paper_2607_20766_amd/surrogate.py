@@ -206,8 +206,13 @@ class Triage:
     # -- training --------------------------------------------------------------------
     def train(self, f_q, f_lib, qidx: np.ndarray, midx: np.ndarray, Y: np.ndarray,
               fo: np.ndarray | None = None, epochs: int = 8, batch: int = 4096,
-              lr: float = 1e-3, seed: int = 0, log=None):
-        """Minibatch Adam on the weighted MSE of standardised labels Y [n, 2]."""
+              lr: float = 1e-3, seed: int = 0, log=None, graph: bool = True):
+        """Minibatch Adam on the weighted MSE of standardised labels Y [n, 2].
+
+        Each epoch's shuffled rows are copied into fixed device buffers, so
+        after the first (eager) epoch the whole epoch of steps is captured
+        once as a HIP graph and replayed (graph=True): identical kernels and
+        results, without a host round trip per launch."""
         dev = self.eng.torch_device
         self.y_mean = Y.mean(0)
         self.y_std = Y.std(0)
@@ -218,14 +223,13 @@ class Triage:
         rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([int(seed), 0x7EA])))
         xb = torch.empty(batch, 96, dtype=torch.float32, device=dev)
         losses = torch.empty(max(nb, 1), dtype=torch.float32, device=dev)
-        history = []
-        for ep in range(epochs):
-            perm = rng.permutation(n)[: nb * batch]
-            q_ep = torch.from_numpy(qidx[perm].astype(np.int32)).to(dev)
-            m_ep = torch.from_numpy(midx[perm].astype(np.int32)).to(dev)
-            y_ep = torch.from_numpy(np.ascontiguousarray(Ys[perm])).to(dev)
-            fo_ep = (torch.from_numpy(np.ascontiguousarray(fo[perm], np.float32)).to(dev)
-                     if self.use_fo else None)
+        rows = nb * batch
+        q_ep = torch.empty(rows, dtype=torch.int32, device=dev)
+        m_ep = torch.empty(rows, dtype=torch.int32, device=dev)
+        y_ep = torch.empty(rows, 2, dtype=torch.float32, device=dev)
+        fo_ep = torch.empty(rows, dtype=torch.float32, device=dev) if self.use_fo else None
+
+        def epoch_steps():
             for b in range(nb):
                 s, e = b * batch, (b + 1) * batch
                 self.eng.shape_pair_features(f_q, f_lib, self.mean, self.inv_std,
@@ -234,9 +238,29 @@ class Triage:
                 loss = self.mlp.loss_grad(xb, y_ep[s:e], lw)
                 self.mlp.adam_step(lr)
                 losses[b:b + 1].copy_(loss)
-            history.append(float(losses.cpu().numpy().mean()))
-            if log:
-                log(f"epoch {ep}: loss {history[-1]:.4f}")
+
+        g = None
+        history = []
+        try:
+            for ep in range(epochs):
+                perm = rng.permutation(n)[:rows]
+                q_ep.copy_(torch.from_numpy(qidx[perm].astype(np.int32)))
+                m_ep.copy_(torch.from_numpy(midx[perm].astype(np.int32)))
+                y_ep.copy_(torch.from_numpy(np.ascontiguousarray(Ys[perm])))
+                if fo_ep is not None:
+                    fo_ep.copy_(torch.from_numpy(np.ascontiguousarray(fo[perm], np.float32)))
+                if graph and ep > 0 and nb > 0:
+                    if g is None:
+                        g = self.eng.capture(epoch_steps, warmup=False)
+                    g.replay()
+                else:
+                    epoch_steps()
+                history.append(float(losses.cpu().numpy().mean()))
+                if log:
+                    log(f"epoch {ep}: loss {history[-1]:.4f}")
+        finally:
+            if g is not None:
+                g.close()
         return history
 
     def predict_raw(self, f_q, f_lib, fo=None, chunk: int = 65536, fused: bool = True,

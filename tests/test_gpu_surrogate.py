@@ -231,6 +231,30 @@ def test_fused_inference_matches_layers(eng, n, with_fo, with_idx):
     assert torch.isfinite(y_fused).all()
 
 
+def test_graph_training_equals_eager(eng):
+    """Epochs replayed from one captured HIP graph train exactly as eager
+    launches do (loss history and final parameters bit for bit)."""
+    rng = np.random.default_rng(21)
+    n_q, n_l, n = 3, 700, 5000
+    f_q = rng.normal(size=(n_q, 24)).astype(np.float32)
+    f_l = rng.normal(size=(n_l, 24)).astype(np.float32)
+    f_q[:, 23] = rng.uniform(50, 100, n_q)
+    f_l[:, 23] = rng.uniform(50, 100, n_l)
+    fq, fl = torch.from_numpy(f_q).cuda(), torch.from_numpy(f_l).cuda()
+    qi, mi = rng.integers(0, n_q, n), rng.integers(0, n_l, n)
+    Y = rng.normal(size=(n, 2))
+    FO = rng.uniform(1, 40, n)
+    res = []
+    for graph in (False, True):
+        print(f"case: training, graph={graph}", flush=True)
+        tr = Triage(eng, seed=3)
+        tr.fit_standardisation(fq, fl, qi, mi, fo=FO)
+        hist = tr.train(fq, fl, qi, mi, Y, fo=FO, epochs=3, batch=1024, lr=1e-3, graph=graph)
+        res.append((hist, tr.mlp.params.cpu().numpy().copy()))
+    assert res[0][0] == res[1][0]
+    assert np.array_equal(res[0][1], res[1][1])
+
+
 def test_seed_budget_matches_host_rule(eng):
     tr = Triage(eng, seed=0)
     tr.y_mean = np.array([0.3, -1.7])
