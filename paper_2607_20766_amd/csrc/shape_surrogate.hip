@@ -276,11 +276,11 @@ __global__ void k_pair_features(const float* __restrict__ fq, const float* __res
 //   C[m][n] = epilogue( sum_k A[m][k] B[k][n] )
 // A(m, k) = A[m sam + k sak], B(k, n) = B[k sbk + n sbn] (any transposition),
 // epilogue: + bias[n], then ReLU, or multiplication by 1[gate[m][n] > 0]
-// (ReLU backward).  Workgroup tile 64 x 64 (4 waves x 32 x 32, each 2 x 2
-// MFMA 16 x 16 tiles).  BF16: v_mfma_f32_16x16x16bf16_1k, operands rounded to
-// nearest even; FP32: v_mfma_f32_16x16x4f32.  Lane l supplies row (or column)
-// l mod 16 and k-group l / 16; result element (4 (l/16) + r, l mod 16) sits in
-// accumulator r of lane l.
+// (ReLU backward).  BF16: v_mfma_f32_16x16x16bf16_1k, operands rounded to
+// nearest even (LDS-tiled kernel below); FP32: v_mfma_f32_16x16x4f32
+// (workgroup tile 64 x 64, 4 waves x 32 x 32, each 2 x 2 MFMA 16 x 16 tiles).
+// Lane l supplies row (or column) l mod 16 and k-group l / 16; result element
+// (4 (l/16) + r, l mod 16) sits in accumulator r of lane l.
 // ---------------------------------------------------------------------------
 typedef short v4s __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
@@ -292,8 +292,9 @@ __device__ __forceinline__ short to_bf16(float x) {
   return (short)(u >> 16);
 }
 
-template <bool BF16>
-__global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
+// FP32 products (tight-parity mode): operands read straight from global
+// memory, one v_mfma_f32_16x16x4f32 step per 4 values of k.
+__global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs g) {
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   const int m0 = blockIdx.y * 64 + (wave >> 1) * 32;
   const int n0 = blockIdx.x * 64 + (wave & 1) * 32;
@@ -303,56 +304,26 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
-  const int kstep = BF16 ? 16 : 4;
   const int kb = g.part ? blockIdx.z * g.k_chunk : 0;
   const int ke = g.part ? min(g.K, kb + g.k_chunk) : g.K;
-  for (int k0 = kb; k0 < ke; k0 += kstep) {
-    if (BF16) {
-      v4s a[2], b[2];
+  for (int k0 = kb; k0 < ke; k0 += 4) {
+    float a[2], b[2];
+    const int k = k0 + lk;
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        const int m = m0 + 16 * i + li;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int k = k0 + 4 * lk + e;
-          const float v = (m < g.M && k < ke) ? g.A[(int64_t)m * g.sam + (int64_t)k * g.sak] : 0.f;
-          a[i][e] = to_bf16(v);
-        }
-      }
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const int n = n0 + 16 * j + li;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int k = k0 + 4 * lk + e;
-          const float v = (n < g.N && k < ke) ? g.B[(int64_t)k * g.sbk + (int64_t)n * g.sbn] : 0.f;
-          b[j][e] = to_bf16(v);
-        }
-      }
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
-    } else {
-      float a[2], b[2];
-      const int k = k0 + lk;
-#pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        const int m = m0 + 16 * i + li;
-        a[i] = (m < g.M && k < ke) ? g.A[(int64_t)m * g.sam + (int64_t)k * g.sak] : 0.f;
-      }
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const int n = n0 + 16 * j + li;
-        b[j] = (n < g.N && k < ke) ? g.B[(int64_t)k * g.sbk + (int64_t)n * g.sbn] : 0.f;
-      }
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+    for (int i = 0; i < 2; ++i) {
+      const int m = m0 + 16 * i + li;
+      a[i] = (m < g.M && k < ke) ? g.A[(int64_t)m * g.sam + (int64_t)k * g.sak] : 0.f;
     }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int n = n0 + 16 * j + li;
+      b[j] = (n < g.N && k < ke) ? g.B[(int64_t)k * g.sbk + (int64_t)n * g.sbn] : 0.f;
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
   }
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -374,52 +345,58 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
       }
 }
 
-// BF16 dense layer with LDS tiling: workgroup tile 128 x 128, k-slab 32.
+// BF16 dense layer with LDS tiling: workgroup tile TM x TN (128 x 128, or
+// 64 x 64 for products whose large tiles would leave CUs idle), k-slab 32.
 // Both operands are staged as bfloat16 with k contiguous (A_s[m][k],
 // B_s[n][k]), loaded from global memory along whichever dimension is
 // contiguous there, so every wave reads whole cache lines.  Each of the four
-// waves computes a 64 x 64 sub-tile as 4 x 4 MFMA 16x16x16 tiles.
-constexpr int kTM = 128, kTN = 128, kTK = 32, kLdk = kTK + 8;
+// waves computes a (TM/2) x (TN/2) sub-tile of MFMA 16x16x16 tiles.  Every
+// output element accumulates k in the same order (slabs of 32, two MFMA
+// steps of 16) whatever the tile size, so both sizes give the same bits.
+constexpr int kTK = 32, kLdk = kTK + 8;
 
+template <int TM, int TN>
 __global__ __launch_bounds__(256, 2) void k_gemm_bf16_tiled(GemmArgs g) {
-  __shared__ short As[kTM * kLdk];
-  __shared__ short Bs[kTN * kLdk];
+  constexpr int FM = TM / 32, FN = TN / 32;           // MFMA tiles per wave
+  constexpr int RA = TM * kTK / 256, RB = TN * kTK / 256;  // staged values per thread
+  __shared__ short As[TM * kLdk];
+  __shared__ short Bs[TN * kLdk];
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
-  const int bm = blockIdx.y * kTM, bn = blockIdx.x * kTN;
-  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  const int bm = blockIdx.y * TM, bn = blockIdx.x * TN;
+  const int wm = (wave >> 1) * (TM / 2), wn = (wave & 1) * (TN / 2);
   const int li = lane & 15, lk = lane >> 4;
-  v4f acc[4][4];
+  v4f acc[FM][FN];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < FN; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
   const bool a_kfast = g.sak == 1;
   const bool b_nfast = g.sbn == 1;
   const int kb = g.part ? blockIdx.z * g.k_chunk : 0;
   const int ke = g.part ? min(g.K, kb + g.k_chunk) : g.K;
   // Slabs of kTK values of k: slab s+1 is read from global memory into
   // registers while the matrix cores work on slab s from LDS.
-  float pa[16], pb[16];
+  float pa[RA], pb[RB];
   auto load_slab = [&](int k0) {
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {  // A: 128 x 32 elements, 16 per thread
+    for (int r = 0; r < RA; ++r) {  // A: TM x 32 elements
       int m, k;
       if (a_kfast) {
         k = tid & 31;
         m = (tid >> 5) + 8 * r;
       } else {
-        m = tid & 127;
-        k = (tid >> 7) + 2 * r;
+        m = tid % TM;
+        k = tid / TM + (256 / TM) * r;
       }
       const int gm = bm + m, gk = k0 + k;
       pa[r] = (gm < g.M && gk < ke) ? g.A[(int64_t)gm * g.sam + (int64_t)gk * g.sak] : 0.f;
     }
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {  // B: 32 x 128 elements
+    for (int r = 0; r < RB; ++r) {  // B: 32 x TN elements
       int n, k;
       if (b_nfast) {
-        n = tid & 127;
-        k = (tid >> 7) + 2 * r;
+        n = tid % TN;
+        k = tid / TN + (256 / TN) * r;
       } else {
         k = tid & 31;
         n = (tid >> 5) + 8 * r;
@@ -430,15 +407,15 @@ __global__ __launch_bounds__(256, 2) void k_gemm_bf16_tiled(GemmArgs g) {
   };
   auto store_slab = [&]() {
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int m = a_kfast ? (tid >> 5) + 8 * r : tid & 127;
-      const int k = a_kfast ? tid & 31 : (tid >> 7) + 2 * r;
+    for (int r = 0; r < RA; ++r) {
+      const int m = a_kfast ? (tid >> 5) + 8 * r : tid % TM;
+      const int k = a_kfast ? tid & 31 : tid / TM + (256 / TM) * r;
       As[m * kLdk + k] = to_bf16(pa[r]);
     }
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {  // stored transposed as Bs[n][k]
-      const int n = b_nfast ? tid & 127 : (tid >> 5) + 8 * r;
-      const int k = b_nfast ? (tid >> 7) + 2 * r : tid & 31;
+    for (int r = 0; r < RB; ++r) {  // stored transposed as Bs[n][k]
+      const int n = b_nfast ? tid % TN : (tid >> 5) + 8 * r;
+      const int k = b_nfast ? tid / TN + (256 / TN) * r : tid & 31;
       Bs[n * kLdk + k] = to_bf16(pb[r]);
     }
   };
@@ -449,25 +426,25 @@ __global__ __launch_bounds__(256, 2) void k_gemm_bf16_tiled(GemmArgs g) {
     if (k0 + kTK < ke) load_slab(k0 + kTK);
 #pragma unroll
     for (int kk = 0; kk < kTK; kk += 16) {
-      v4s a[4], b[4];
+      v4s a[FM], b[FN];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < FM; ++i)
         a[i] = *reinterpret_cast<const v4s*>(&As[(wm + 16 * i + li) * kLdk + kk + 4 * lk]);
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
+      for (int j = 0; j < FN; ++j)
         b[j] = *reinterpret_cast<const v4s*>(&Bs[(wn + 16 * j + li) * kLdk + kk + 4 * lk]);
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < FN; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < FN; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int m = bm + wm + 16 * i + 4 * lk + r;
@@ -984,19 +961,28 @@ hipError_t launch_fo_cross(const Prepared& Q, const int* offQ, const float* alph
   return hipGetLastError();
 }
 
-// Workgroup grid of launch_gemm without splitting.
-static dim3 gemm_grid(const GemmArgs& g, bool tiled) {
-  const int tm = tiled ? kTM : 64, tn = tiled ? kTN : 64;
-  return dim3((unsigned)((g.N + tn - 1) / tn), (unsigned)((g.M + tm - 1) / tm));
+// Workgroup tile of launch_gemm: BF16 products use the LDS-tiled kernel,
+// with 128 x 128 tiles when those give at least one workgroup per CU (256)
+// and 64 x 64 tiles otherwise; FP32 products use the 64 x 64 kernel without
+// LDS.
+static bool gemm_tiled(const GemmArgs& g) { return (g.flags & SHAPE_GEMM_BF16) != 0; }
+
+static int gemm_tile(const GemmArgs& g) {
+  if (!gemm_tiled(g)) return 64;
+  const int64_t big = (int64_t)((g.N + 127) / 128) * ((g.M + 127) / 128);
+  return big >= 256 ? 128 : 64;
 }
 
-static bool gemm_tiled(const GemmArgs& g) { return (g.flags & SHAPE_GEMM_BF16) && g.N >= 64; }
+static dim3 gemm_grid(const GemmArgs& g) {
+  const int t = gemm_tile(g);
+  return dim3((unsigned)((g.N + t - 1) / t), (unsigned)((g.M + t - 1) / t));
+}
 
 // Products whose output tiles cannot fill the chip (the weight gradients:
 // M x N = layer size, K = batch) split K so that >= 512 workgroups run,
 // each over at least 128 values of k.
 int gemm_splits(const GemmArgs& g) {
-  const dim3 grid = gemm_grid(g, gemm_tiled(g));
+  const dim3 grid = gemm_grid(g);
   const int tiles = (int)(grid.x * grid.y);
   if (tiles >= 128 || g.K < 512) return 1;
   int s = (512 + tiles - 1) / tiles;
@@ -1007,7 +993,8 @@ int gemm_splits(const GemmArgs& g) {
 hipError_t launch_gemm(const GemmArgs& g0, hipStream_t st) {
   GemmArgs g = g0;
   const bool tiled = gemm_tiled(g);
-  dim3 grid = gemm_grid(g, tiled);
+  const int tile = gemm_tile(g);
+  dim3 grid = gemm_grid(g);
   int splits = g.part ? gemm_splits(g) : 1;
   if (splits > 1) {
     g.k_chunk = ((g.K + splits - 1) / splits + kTK - 1) / kTK * kTK;
@@ -1017,13 +1004,12 @@ hipError_t launch_gemm(const GemmArgs& g0, hipStream_t st) {
     g.part = nullptr;
     g.k_chunk = 0;
   }
-  if (tiled) {
-    hipLaunchKernelGGL(k_gemm_bf16_tiled, grid, dim3(256), 0, st, g);
-  } else if (g.flags & SHAPE_GEMM_BF16) {
-    // narrow outputs keep the 64 x 64 kernel (a 128-wide tile would idle)
-    hipLaunchKernelGGL(k_gemm<true>, grid, dim3(256), 0, st, g);
+  if (tiled && tile == 128) {
+    hipLaunchKernelGGL((k_gemm_bf16_tiled<128, 128>), grid, dim3(256), 0, st, g);
+  } else if (tiled) {
+    hipLaunchKernelGGL((k_gemm_bf16_tiled<64, 64>), grid, dim3(256), 0, st, g);
   } else {
-    hipLaunchKernelGGL(k_gemm<false>, grid, dim3(256), 0, st, g);
+    hipLaunchKernelGGL(k_gemm_f32, grid, dim3(256), 0, st, g);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || splits <= 1) return e;
