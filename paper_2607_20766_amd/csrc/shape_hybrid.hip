@@ -198,32 +198,93 @@ struct FoAlignArgs {
 
 // One pass over the N_A x N_B atom pairs spread over the lanes (the row of
 // flat index p stepped incrementally, as in the cross-overlap kernel):
-// O, dO/dt and the torque about B's origin, summed over the wave.  Per term:
-// rs = 1/sqrt(a_i + a_j) gives both (pi/(a_i+a_j))^(3/2) = pi^(3/2) rs^3 and
-// k_ij = a_i a_j rs^2 from one transcendental; the torque is accumulated as
-// sum c''_j x f and shifted by -t x sum f once at the end.
-__device__ __forceinline__ void fo_pass(const float4* sA, int na, const float4* sM, int nb,
-                                        float tx, float ty, float tz, float (&r)[7]) {
+// O, dO/dt and the torque about B's origin, summed over the wave.  Per term,
+// the pose-independent factors come from the widths alone: with
+// rs = 1/sqrt(a_i + a_j), (pi/(a_i+a_j))^(3/2) = pi^(3/2) rs^3 and
+// k_ij = a_i a_j rs^2.  A lane's first kFoCache terms keep them in registers
+// for the whole optimisation (fo_term_consts, filled once per wave); later
+// terms derive them on the spot from one rsqrt.  The torque is accumulated
+// as sum c''_j x f and shifted by -t x sum f once at the end.
+constexpr int kFoCache = 16;
+
+struct FoTermConsts {
+  float kk[kFoCache];   // -log2(e) k_ij
+  float pre[kFoCache];  // pi^(3/2) (a_i + a_j)^(-3/2)
+  float f2[kFoCache];   // 2 k_ij
+};
+
+__device__ __forceinline__ void fo_consts(float ai, float aj, float& kk, float& pre, float& f2) {
+  const float rs = __builtin_amdgcn_rsqf(ai + aj);
+  const float ir = rs * rs;
+  const float k = ai * aj * ir;
+  kk = -1.44269504088896f * k;
+  pre = 5.56832799683170785f * ir * rs;
+  f2 = 2.f * k;
+}
+
+__device__ __forceinline__ void fo_term_consts(const float4* sA, int na, const float4* sB,
+                                               int nb, FoTermConsts& c) {
   const int lane = threadIdx.x & (kWave - 1);
   const int di = kWave / nb, dj = kWave % nb;
   int i = lane / nb, j = lane % nb;
+#pragma unroll
+  for (int t = 0; t < kFoCache; ++t) {
+    c.kk[t] = 0.f;
+    c.pre[t] = 0.f;
+    c.f2[t] = 0.f;
+    if (i < na) {
+      fo_consts(sA[i].w, sB[j].w, c.kk[t], c.pre[t], c.f2[t]);
+      i += di;
+      j += dj;
+      if (j >= nb) {
+        j -= nb;
+        ++i;
+      }
+    }
+  }
+}
+
+struct FoAcc {
   float O = 0.f, gx = 0.f, gy = 0.f, gz = 0.f, rx = 0.f, ry = 0.f, rz = 0.f;
-  for (; i < na;) {
-    const float4 ci = sA[i], cj = sM[j];
-    const float rs = __builtin_amdgcn_rsqf(ci.w + cj.w);
-    const float ir = rs * rs;
-    const float k = ci.w * cj.w * ir;
+  __device__ __forceinline__ void add(const float4& ci, const float4& cj, float kk, float pre,
+                                      float f2) {
     const float dx = ci.x - cj.x, dy = ci.y - cj.y, dz = ci.z - cj.z;
     const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-    const float K = 5.56832799683170785f * ir * rs *  // pi^(3/2)
-                    __builtin_amdgcn_exp2f(-1.44269504088896f * k * d2);
+    const float K = pre * __builtin_amdgcn_exp2f(kk * d2);
     O += K;
-    const float f = 2.f * k * K;
+    const float f = f2 * K;
     const float fx = f * dx, fy = f * dy, fz = f * dz;  // dO/dc''_j from this term
     gx += fx; gy += fy; gz += fz;
     rx = fmaf(cj.y, fz, fmaf(-cj.z, fy, rx));
     ry = fmaf(cj.z, fx, fmaf(-cj.x, fz, ry));
     rz = fmaf(cj.x, fy, fmaf(-cj.y, fx, rz));
+  }
+};
+
+__device__ __forceinline__ void fo_pass(const float4* sA, int na, const float4* sM, int nb,
+                                        float tx, float ty, float tz, const FoTermConsts& c,
+                                        float (&r)[7]) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int di = kWave / nb, dj = kWave % nb;
+  int i = lane / nb, j = lane % nb;
+  FoAcc acc;
+#pragma unroll
+  for (int t = 0; t < kFoCache; ++t) {
+    if (i < na) {
+      acc.add(sA[i], sM[j], c.kk[t], c.pre[t], c.f2[t]);
+      i += di;
+      j += dj;
+      if (j >= nb) {
+        j -= nb;
+        ++i;
+      }
+    }
+  }
+  for (; i < na;) {
+    const float4 ci = sA[i], cj = sM[j];
+    float kk, pre, f2;
+    fo_consts(ci.w, cj.w, kk, pre, f2);
+    acc.add(ci, cj, kk, pre, f2);
     i += di;
     j += dj;
     if (j >= nb) {
@@ -231,12 +292,12 @@ __device__ __forceinline__ void fo_pass(const float4* sA, int na, const float4* 
       ++i;
     }
   }
-  r[0] = wave_sum_dpp(O);
-  r[1] = wave_sum_dpp(gx); r[2] = wave_sum_dpp(gy); r[3] = wave_sum_dpp(gz);
+  r[0] = wave_sum_dpp(acc.O);
+  r[1] = wave_sum_dpp(acc.gx); r[2] = wave_sum_dpp(acc.gy); r[3] = wave_sum_dpp(acc.gz);
   // torque about B's origin: sum (c''_j - t) x f = sum c''_j x f - t x sum f
-  r[4] = wave_sum_dpp(rx) - (ty * r[3] - tz * r[2]);
-  r[5] = wave_sum_dpp(ry) - (tz * r[1] - tx * r[3]);
-  r[6] = wave_sum_dpp(rz) - (tx * r[2] - ty * r[1]);
+  r[4] = wave_sum_dpp(acc.rx) - (ty * r[3] - tz * r[2]);
+  r[5] = wave_sum_dpp(acc.ry) - (tz * r[1] - tx * r[3]);
+  r[6] = wave_sum_dpp(acc.rz) - (tx * r[2] - ty * r[1]);
 }
 
 // sum_ij K_ij of a molecule with itself (pose invariant), over all lanes.
@@ -291,6 +352,8 @@ __global__ __launch_bounds__(64) void k_fo_align(FoAlignArgs a) {
                         a.B.xyz[3 * (b0 + j) + 2], a.B.alpha[b0 + j]);
   wave_lds_sync();
   const float S = fo_self(sA, na) + fo_self(sB, nb);  // O_AA + O_BB
+  FoTermConsts tc;
+  fo_term_consts(sA, na, sB, nb, tc);
   float x[7], m[7], v[7];
   float* ps = a.pose + (size_t)item * 7;
 #pragma unroll
@@ -320,7 +383,7 @@ __global__ __launch_bounds__(64) void k_fo_align(FoAlignArgs a) {
     }
     wave_lds_sync();
     float r[7];
-    fo_pass(sA, na, sM, nb, x[4], x[5], x[6], r);
+    fo_pass(sA, na, sM, nb, x[4], x[5], x[6], tc, r);
     wave_lds_sync();  // sM is rewritten next step
     const float D = S - r[0];
     T = r[0] / D;
