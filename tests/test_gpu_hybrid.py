@@ -172,6 +172,32 @@ def test_invalid_molecule_gives_nan(eng, pairs):
                            n_steps=1)
 
 
+def test_degenerate_molecules(eng):
+    """1-, 2- and 3-atom molecules (isotropic or axial mixtures: the principal
+    frame is not unique) and the 256-atom maximum: starts and first-order
+    Adam stay finite, never end below their start, and from the given pose
+    (a unique trajectory) end at the oracle's T within 1e-3.  (Looser than
+    for drug-sized molecules: rotations about a symmetry axis have a zero
+    gradient, whose FP32 rounding noise Adam rescales to full steps.)"""
+    q = molgen.molecule(8, 0, 3)
+    L = molgen.MolSet.concat([molgen.molecule(9, i, n) for i, n in enumerate((1, 2, 3, 40, 256))])
+    Q = eng.molecules(q, mol_id=[QUERY_ID])
+    lib = eng.molecules(L)
+    print("case: degenerate molecules, first-order alignment", flush=True)
+    st = eng.shape_fo_starts(Q, lib, 3, 0)
+    st0 = st.cpu().numpy().copy()
+    T, _ = eng.shape_fo_align(Q, lib, st, 10, 0.05)
+    T, pg = T.cpu().numpy(), st.cpu().numpy()
+    assert np.all(np.isfinite(st0)) and np.all(np.isfinite(T)) and np.all(np.isfinite(pg))
+    oq = oracle_mol(O, q)
+    for p in range(L.n_mols):
+        om = oracle_mol(O, L.mol(p))
+        T0 = O.fo_align_grad(oq, om, st0[p].astype(np.float64))[0]
+        assert np.all(T[p] >= T0 - 1e-3), (p, T[p], T0)
+        pr, Tr = O.fo_align_adam(oq, om, st0[p, :1].astype(np.float64), n_steps=10, lr=0.05)
+        assert abs(T[p, 0] - Tr[0]) <= 1e-3, (p, T[p, 0], Tr[0])
+
+
 def test_group_max(eng):
     rng = np.random.default_rng(4)
     T = rng.uniform(size=40).astype(np.float32)

@@ -158,6 +158,36 @@ def test_invalid_molecules_flagged(eng, small_lib):
     assert out["T"].numel() == 0
 
 
+@pytest.mark.parametrize("q_atoms", [1, 256])
+def test_extreme_sizes_every_tile_variant(eng, q_atoms):
+    """1- and 256-atom molecules (the minimum and SHAPE_MAX_ATOMS) on both
+    sides, sizes around the 64-lane width, every tile variant of the
+    screening kernel, adaptive rounds: identical across variants and equal to
+    the oracle."""
+    from paper_2607_20766_amd.engine import SHAPE_SCREEN_VARIANTS
+    q = molgen.molecule(3, 1, q_atoms)
+    L = molgen.MolSet.concat([molgen.molecule(4, i, n)
+                              for i, n in enumerate((1, 2, 63, 64, 65, 256, 7, 128))])
+    Q = eng.molecules(q, mol_id=[QUERY_ID])
+    lib = eng.molecules(L)
+    kw = dict(mode=SHAPE_SCREEN_ADAPTIVE, round_per_pair=512, cap_per_pair=4096, tau=0.005,
+              seed=6)
+    print(f"case: extreme sizes, query {q_atoms} atoms", flush=True)
+    ref = None
+    for v in range(SHAPE_SCREEN_VARIANTS):
+        eng.screen_variant(v)
+        g = _to_np(eng.shape_screen(Q, lib, **kw))
+        if ref is None:
+            ref = g
+        for k in g:
+            assert np.array_equal(g[k], ref[k]), (v, k)
+    eng.screen_variant(-1)
+    r = _oracle_screen(q, L, mode=1, round_per_pair=512, cap_per_pair=4096, tau=0.005, seed=6)
+    same = ref["n_used"] == r[:, 5]
+    assert same.mean() >= 0.75
+    _compare(ref, r[same], idx=np.nonzero(same)[0])
+
+
 def test_odd_atom_counts(eng):
     """Odd query and library sizes (LDS arrays of 8-byte records after odd
     counts of 4-byte ones must stay aligned)."""
