@@ -317,7 +317,10 @@ int shape_adam_pose(shape_ctx* ctx, float* pose, const float* dT_dpose, float* m
 
 /* Multi-start alignment driver: self-overlaps, then n_steps of
  * (shape_align_grad, shape_adam_pose) from the given starts, then T at the
- * final poses and the best start of each pair (largest final T).
+ * final poses and the best start of each pair (largest final T).  The steps
+ * run inside one kernel launch (A's samples drawn once per pair, each
+ * start's Adam state in registers) with the same arithmetic as calling the
+ * two entry points in turn.
  * pose: device float [pairs][n_starts][7], updated in place.  T_final:
  * device float [pairs][n_starts].  best: device int32 [pairs] or NULL.
  * Adam uses beta1 = 0.9, beta2 = 0.999, eps = 1e-8.  Asynchronous. */

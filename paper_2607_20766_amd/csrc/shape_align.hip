@@ -60,6 +60,30 @@ __device__ void align_samples(const AlignArgs& a, int pair, float4* sSamp, Atom*
   __syncthreads();
 }
 
+// One Adam (Kingma and Ba) ascent step on T for a pose x[7] with moments
+// m, v: step number t (from 1), gradient dT; the quaternion is renormalised.
+// Shared by the fused optimisation in k_align and by k_adam_pose, so both
+// take the same roundings.
+__device__ __forceinline__ void adam_pose_step(float (&x)[7], float (&m)[7], float (&v)[7],
+                                               const float (&dT)[7], int t, float lr, float b1,
+                                               float b2, float eps) {
+#pragma clang fp contract(off)
+  const float c1 = 1.f - powf(b1, (float)t), c2 = 1.f - powf(b2, (float)t);
+  float xn[7];
+#pragma unroll
+  for (int c = 0; c < 7; ++c) {
+    const float g = -dT[c];  // minimise -T
+    m[c] = fmaf(b1, m[c], (1.f - b1) * g);
+    v[c] = fmaf(b2, v[c], (1.f - b2) * g * g);
+    xn[c] = x[c] - lr * (m[c] / c1) / (sqrtf(v[c] / c2) + eps);
+  }
+  const float inv = rsqrtf(xn[0] * xn[0] + xn[1] * xn[1] + xn[2] * xn[2] + xn[3] * xn[3]);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) x[c] = xn[c] * inv;
+#pragma unroll
+  for (int c = 4; c < 7; ++c) x[c] = xn[c];
+}
+
 __global__ __launch_bounds__(kAlignThreads) void k_align(AlignArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   // 16-byte arrays first, then 8-byte, then 4-byte: each stays aligned.
@@ -98,86 +122,96 @@ __global__ __launch_bounds__(kAlignThreads) void k_align(AlignArgs a) {
 
   for (int st = wave; st < a.n_starts; st += kAlignWaves) {
     const size_t o = (size_t)pair * a.n_starts + st;
-    const float* ps = a.pose + o * 7;
-    float R[9], inv_norm;
-    quat_rotation(ps[0], ps[1], ps[2], ps[3], R, inv_norm);
-    // B's origin in A's frame (the rotation centre)
-    const float tx = ps[4] - cA.x, ty = ps[5] - cA.y, tz = ps[6] - cA.z;
-    for (int i = lane; i < nb; i += kWave) {
-      const Atom at = a.B.atom[b0 + i];
-      Atom moved = at;
-      moved.x = fmaf(R[0], at.x, fmaf(R[1], at.y, fmaf(R[2], at.z, tx)));
-      moved.y = fmaf(R[3], at.x, fmaf(R[4], at.y, fmaf(R[5], at.z, ty)));
-      moved.z = fmaf(R[6], at.x, fmaf(R[7], at.y, fmaf(R[8], at.z, tz)));
-      make_rec(moved, 0.f, 0.f, 0.f, wR[i], wa[i]);
-      // 2 alpha = 2 a2 ln 2
-      wC[i] = make_float4(moved.x, moved.y, moved.z, 2.0f * 0.693147180559945309f * at.a2);
-    }
-    wave_lds_sync();
-    float accO = 0.f, gtx = 0.f, gty = 0.f, gtz = 0.f, grx = 0.f, gry = 0.f, grz = 0.f;
-    for (int t = 0; t < per_lane; t += kAS) {
-      float rx[kAS], ry[kAS], rz[kAS], r2[kAS], w[kAS];
-      float P[kAS], S0[kAS], Sx[kAS], Sy[kAS], Sz[kAS];
+    float ps[7], am[7], av[7];
 #pragma unroll
-      for (int s = 0; s < kAS; ++s) {
-        const int k = lane + kWave * (t + s);
-        const bool ok = (t + s) < per_lane && k < a.n_samples;
-        const float4 c = sSamp[ok ? k : 0];
-        rx[s] = c.x; ry[s] = c.y; rz[s] = c.z;
-        w[s] = ok ? c.w : 0.f;
-        r2[s] = norm2(c.x, c.y, c.z);
-        P[s] = 1.f; S0[s] = 0.f; Sx[s] = 0.f; Sy[s] = 0.f; Sz[s] = 0.f;
+    for (int c = 0; c < 7; ++c) {
+      ps[c] = a.pose[o * 7 + c];
+      am[c] = 0.f;
+      av[c] = 0.f;
+    }
+    for (int it = 0;; ++it) {  // it = Adam steps taken
+      float R[9], inv_norm;
+      quat_rotation(ps[0], ps[1], ps[2], ps[3], R, inv_norm);
+      // B's origin in A's frame (the rotation centre)
+      const float tx = ps[4] - cA.x, ty = ps[5] - cA.y, tz = ps[6] - cA.z;
+      for (int i = lane; i < nb; i += kWave) {
+        const Atom at = a.B.atom[b0 + i];
+        Atom moved = at;
+        moved.x = fmaf(R[0], at.x, fmaf(R[1], at.y, fmaf(R[2], at.z, tx)));
+        moved.y = fmaf(R[3], at.x, fmaf(R[4], at.y, fmaf(R[5], at.z, ty)));
+        moved.z = fmaf(R[6], at.x, fmaf(R[7], at.y, fmaf(R[8], at.z, tz)));
+        make_rec(moved, 0.f, 0.f, 0.f, wR[i], wa[i]);
+        // 2 alpha = 2 a2 ln 2
+        wC[i] = make_float4(moved.x, moved.y, moved.z, 2.0f * 0.693147180559945309f * at.a2);
       }
-      // unrolled by two: no loop-carried register copies between atoms
-#pragma unroll 2
-      for (int j = 0; j < nb; ++j) {
-        const AtomRec b = wR[j];
-        const float aj = wa[j];
-        const float4 cj = wC[j];
+      wave_lds_sync();
+      float accO = 0.f, gtx = 0.f, gty = 0.f, gtz = 0.f, grx = 0.f, gry = 0.f, grz = 0.f;
+      for (int t = 0; t < per_lane; t += kAS) {
+        float rx[kAS], ry[kAS], rz[kAS], r2[kAS], w[kAS];
+        float P[kAS], S0[kAS], Sx[kAS], Sy[kAS], Sz[kAS];
 #pragma unroll
         for (int s = 0; s < kAS; ++s) {
-          const float oj = occupancy_x(b, aj, rx[s], ry[s], rz[s], r2[s]);
-          const float omo = 1.f - oj;
-          const float gp = cj.w * oj * P[s];
-          S0[s] = fmaf(S0[s], omo, gp);
-          Sx[s] = fmaf(Sx[s], omo, gp * cj.x);
-          Sy[s] = fmaf(Sy[s], omo, gp * cj.y);
-          Sz[s] = fmaf(Sz[s], omo, gp * cj.z);
-          P[s] *= omo;
+          const int k = lane + kWave * (t + s);
+          const bool ok = (t + s) < per_lane && k < a.n_samples;
+          const float4 c = sSamp[ok ? k : 0];
+          rx[s] = c.x; ry[s] = c.y; rz[s] = c.z;
+          w[s] = ok ? c.w : 0.f;
+          r2[s] = norm2(c.x, c.y, c.z);
+          P[s] = 1.f; S0[s] = 0.f; Sx[s] = 0.f; Sy[s] = 0.f; Sz[s] = 0.f;
+        }
+        // unrolled by two: no loop-carried register copies between atoms
+#pragma unroll 2
+        for (int j = 0; j < nb; ++j) {
+          const AtomRec b = wR[j];
+          const float aj = wa[j];
+          const float4 cj = wC[j];
+#pragma unroll
+          for (int s = 0; s < kAS; ++s) {
+            const float oj = occupancy_x(b, aj, rx[s], ry[s], rz[s], r2[s]);
+            const float omo = 1.f - oj;
+            const float gp = cj.w * oj * P[s];
+            S0[s] = fmaf(S0[s], omo, gp);
+            Sx[s] = fmaf(Sx[s], omo, gp * cj.x);
+            Sy[s] = fmaf(Sy[s], omo, gp * cj.y);
+            Sz[s] = fmaf(Sz[s], omo, gp * cj.z);
+            P[s] *= omo;
+          }
+        }
+#pragma unroll
+        for (int s = 0; s < kAS; ++s) {
+          // translation gradient of u at this point and the torque about B's origin
+          const float gx = fmaf(S0[s], rx[s], -Sx[s]);
+          const float gy = fmaf(S0[s], ry[s], -Sy[s]);
+          const float gz = fmaf(S0[s], rz[s], -Sz[s]);
+          const float cxr_x = Sy[s] * rz[s] - Sz[s] * ry[s];
+          const float cxr_y = Sz[s] * rx[s] - Sx[s] * rz[s];
+          const float cxr_z = Sx[s] * ry[s] - Sy[s] * rx[s];
+          const float txg_x = ty * gz - tz * gy;
+          const float txg_y = tz * gx - tx * gz;
+          const float txg_z = tx * gy - ty * gx;
+          accO = fmaf(w[s], 1.f - P[s], accO);
+          gtx = fmaf(w[s], gx, gtx);
+          gty = fmaf(w[s], gy, gty);
+          gtz = fmaf(w[s], gz, gtz);
+          grx = fmaf(w[s], cxr_x - txg_x, grx);
+          gry = fmaf(w[s], cxr_y - txg_y, gry);
+          grz = fmaf(w[s], cxr_z - txg_z, grz);
         }
       }
-#pragma unroll
-      for (int s = 0; s < kAS; ++s) {
-        // translation gradient of u at this point and the torque about B's origin
-        const float gx = fmaf(S0[s], rx[s], -Sx[s]);
-        const float gy = fmaf(S0[s], ry[s], -Sy[s]);
-        const float gz = fmaf(S0[s], rz[s], -Sz[s]);
-        const float cxr_x = Sy[s] * rz[s] - Sz[s] * ry[s];
-        const float cxr_y = Sz[s] * rx[s] - Sx[s] * rz[s];
-        const float cxr_z = Sx[s] * ry[s] - Sy[s] * rx[s];
-        const float txg_x = ty * gz - tz * gy;
-        const float txg_y = tz * gx - tx * gz;
-        const float txg_z = tx * gy - ty * gx;
-        accO = fmaf(w[s], 1.f - P[s], accO);
-        gtx = fmaf(w[s], gx, gtx);
-        gty = fmaf(w[s], gy, gty);
-        gtz = fmaf(w[s], gz, gtz);
-        grx = fmaf(w[s], cxr_x - txg_x, grx);
-        gry = fmaf(w[s], cxr_y - txg_y, gry);
-        grz = fmaf(w[s], cxr_z - txg_z, grz);
-      }
-    }
-    const double sO = wave_sum((double)accO);
-    const double s_tx = wave_sum((double)gtx), s_ty = wave_sum((double)gty),
-                 s_tz = wave_sum((double)gtz);
-    const double s_rx = wave_sum((double)grx), s_ry = wave_sum((double)gry),
-                 s_rz = wave_sum((double)grz);
-    if (lane == 0) {
+      // butterfly sums: every lane holds the totals, so T and its gradient
+      // are wave-uniform and the Adam state can stay in registers
+      const double sO = wave_sum((double)accO);
+      const double s_tx = wave_sum((double)gtx), s_ty = wave_sum((double)gty),
+                   s_tz = wave_sum((double)gtz);
+      const double s_rx = wave_sum((double)grx), s_ry = wave_sum((double)gry),
+                   s_rz = wave_sum((double)grz);
       const double scale = Za / (double)a.n_samples;
       const double O = scale * sO;
       const double D = S - O;
-      a.T[o] = (float)(O / D);
-      if (a.grad) {
+      const float T = (float)(O / D);
+      const bool last = it >= a.n_steps;
+      float g[7];
+      if (a.grad || !last) {
         const double k = scale * S / (D * D);  // dT/dO * Z_A/n
         const double gth[3] = {k * s_rx, k * s_ry, k * s_rz};
         // dT/dq = (2/|q|) [ -v.g ; w g - v x g ] with (w, v) = q/|q|
@@ -187,7 +221,6 @@ __global__ __launch_bounds__(kAlignThreads) void k_align(AlignArgs a) {
         const double vxg_x = vy * gth[2] - vz * gth[1];
         const double vxg_y = vz * gth[0] - vx * gth[2];
         const double vxg_z = vx * gth[1] - vy * gth[0];
-        float* g = a.grad + o * 7;
         g[0] = (float)(2.0 * in * (-vdg));
         g[1] = (float)(2.0 * in * (w * gth[0] - vxg_x));
         g[2] = (float)(2.0 * in * (w * gth[1] - vxg_y));
@@ -196,8 +229,19 @@ __global__ __launch_bounds__(kAlignThreads) void k_align(AlignArgs a) {
         g[5] = (float)(k * s_ty);
         g[6] = (float)(k * s_tz);
       }
+      wave_lds_sync();  // this pose's records are read before the next move
+      if (last) {
+        if (lane == 0) {
+          a.T[o] = T;
+          if (a.grad)
+            for (int c = 0; c < 7; ++c) a.grad[o * 7 + c] = g[c];
+          if (a.n_steps > 0)
+            for (int c = 0; c < 7; ++c) a.pose_out[o * 7 + c] = ps[c];
+        }
+        break;
+      }
+      adam_pose_step(ps, am, av, g, it + 1, a.lr, 0.9f, 0.999f, 1e-8f);
     }
-    wave_lds_sync();
   }
 }
 
@@ -257,23 +301,21 @@ __global__ void k_adam_pose(float* __restrict__ pose, const float* __restrict__ 
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int t = *step + 1;
   if (i < n_poses) {
-    const float c1 = 1.f - powf(b1, (float)t), c2 = 1.f - powf(b2, (float)t);
-    float* x = pose + i * 7;
-    float xn[7];
+    float x[7], mi[7], vi[7], g[7];
 #pragma unroll
     for (int c = 0; c < 7; ++c) {
-      const float g = -dT[i * 7 + c];  // minimise -T
-      const float mi = fmaf(b1, m[i * 7 + c], (1.f - b1) * g);
-      const float vi = fmaf(b2, v[i * 7 + c], (1.f - b2) * g * g);
-      m[i * 7 + c] = mi;
-      v[i * 7 + c] = vi;
-      xn[c] = x[c] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+      x[c] = pose[i * 7 + c];
+      mi[c] = m[i * 7 + c];
+      vi[c] = v[i * 7 + c];
+      g[c] = dT[i * 7 + c];
     }
-    const float inv = rsqrtf(xn[0] * xn[0] + xn[1] * xn[1] + xn[2] * xn[2] + xn[3] * xn[3]);
+    adam_pose_step(x, mi, vi, g, t, lr, b1, b2, eps);
 #pragma unroll
-    for (int c = 0; c < 4; ++c) x[c] = xn[c] * inv;
-#pragma unroll
-    for (int c = 4; c < 7; ++c) x[c] = xn[c];
+    for (int c = 0; c < 7; ++c) {
+      pose[i * 7 + c] = x[c];
+      m[i * 7 + c] = mi[c];
+      v[i * 7 + c] = vi[c];
+    }
   }
 }
 

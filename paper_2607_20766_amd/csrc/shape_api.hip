@@ -604,6 +604,9 @@ int align_launch(shape_ctx* c, const shape_mols* A, const shape_mols* B,
   a.O_bb = O_bb;
   a.T = T;
   a.grad = grad;
+  a.n_steps = 0;
+  a.lr = 0.f;
+  a.pose_out = nullptr;
   HIP_TRY(c, shape::launch_align(a, A->n_mols, st), "alignment kernel");
   return SHAPE_OK;
 }
@@ -664,15 +667,10 @@ int shape_align(shape_ctx* c, const shape_mols* A, const shape_mols* B, int32_t 
     if ((rc = set_device(c))) return rc;
     hipStream_t st = (hipStream_t)stream;
     const int pairs = A->n_mols;
-    const int64_t n_poses = (int64_t)pairs * n_starts;
     shape::Prepared PA, PB;
-    void *saa, *sbb, *mm, *vv, *stp, *grad;
+    void *saa, *sbb;
     if ((rc = ensure(c, S_SELF_A, (size_t)pairs * sizeof(float), &saa))) return rc;
     if ((rc = ensure(c, S_SELF_B, (size_t)pairs * sizeof(float), &sbb))) return rc;
-    if ((rc = ensure(c, S_ADAM_M, (size_t)n_poses * 7 * sizeof(float), &mm))) return rc;
-    if ((rc = ensure(c, S_ADAM_V, (size_t)n_poses * 7 * sizeof(float), &vv))) return rc;
-    if ((rc = ensure(c, S_ADAM_STEP, sizeof(int), &stp))) return rc;
-    if ((rc = ensure(c, S_GRAD, (size_t)n_poses * 7 * sizeof(float), &grad))) return rc;
     // self-overlaps use the library slots; prepare both sets afterwards
     if ((rc = prepare(c, A, false, st, &PB))) return rc;
     HIP_TRY(c, shape::launch_self_overlap(PB, A->atom_offset, pairs, n_samples, key_of(seed),
@@ -683,22 +681,29 @@ int shape_align(shape_ctx* c, const shape_mols* A, const shape_mols* B, int32_t 
                                           (float*)sbb, st),
             "self-overlap kernel");
     if ((rc = prepare(c, A, true, st, &PA))) return rc;
-    HIP_TRY(c, shape::launch_fill_int((int*)mm, (int)(n_poses * 7), 0, st), "state reset");
-    HIP_TRY(c, shape::launch_fill_int((int*)vv, (int)(n_poses * 7), 0, st), "state reset");
-    HIP_TRY(c, shape::launch_fill_int((int*)stp, 1, 0, st), "state reset");
-    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    // the whole optimisation in one launch: A's samples are drawn once per
+    // pair, each start's Adam state stays in registers (the same steps as
+    // shape_align_grad followed by shape_adam_pose, n_steps times)
+    shape::AlignArgs a;
+    a.A = PA;
+    a.offA = A->atom_offset;
+    a.max_a = A->max_atoms;
+    a.B = PB;
+    a.offB = B->atom_offset;
+    a.max_b = B->max_atoms;
+    a.n_starts = n_starts;
+    a.n_samples = n_samples;
+    a.key = key_of(seed);
+    a.pose = pose;
+    a.O_aa = (const float*)saa;
+    a.O_bb = (const float*)sbb;
+    a.T = T_final;
+    a.grad = nullptr;
+    a.n_steps = n_steps;
+    a.lr = lr;
+    a.pose_out = pose;
     KernelTimer timer(c, st);
-    for (int it = 0; it < n_steps; ++it) {
-      if ((rc = align_launch(c, A, B, PA, PB, n_starts, pose, (const float*)saa,
-                             (const float*)sbb, n_samples, seed, st, T_final, (float*)grad)))
-        return rc;
-      HIP_TRY(c, shape::launch_adam_pose(pose, (const float*)grad, (float*)mm, (float*)vv,
-                                         n_poses, (int*)stp, lr, b1, b2, eps, st),
-              "Adam kernel");
-    }
-    if ((rc = align_launch(c, A, B, PA, PB, n_starts, pose, (const float*)saa,
-                           (const float*)sbb, n_samples, seed, st, T_final, nullptr)))
-      return rc;
+    HIP_TRY(c, shape::launch_align(a, pairs, st), "alignment kernel");
     timer.stop();
     if (best) HIP_TRY(c, shape::launch_best_start(T_final, pairs, n_starts, best, st), "best");
     return SHAPE_OK;

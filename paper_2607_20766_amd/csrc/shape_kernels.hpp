@@ -77,6 +77,11 @@ struct AlignArgs {
   const float* O_bb;  // [pairs]
   float* T;           // [pairs][starts]
   float* grad;        // [pairs][starts][7] or nullptr
+  // n_steps > 0: Adam ascent on T inside the kernel (pose updated in place,
+  // T and grad then at the final pose); 0: one evaluation at the given pose.
+  int n_steps;
+  float lr;
+  float* pose_out;    // the pose array again (written when n_steps > 0)
 };
 
 // Dense layer C = epilogue(A B) with strided operands (see shape_gemm).

@@ -113,6 +113,31 @@ def test_adam_matches_oracle(eng):
         assert best[p] == int(np.argmax(T[p]))
 
 
+def test_fused_optimisation_equals_step_by_step(eng):
+    """shape_align runs all Adam steps inside one launch; the same steps as
+    shape_align_grad + shape_adam_pose in turn give the same bits."""
+    n_pairs, n_starts, steps = 5, 6, 12
+    A, B = _pairs(n_pairs, seed=13)
+    gA, gB, _, _ = _gpu_sets(eng, A, B)
+    poses = molgen.random_poses(13, n_pairs, n_starts)
+    fused = torch.from_numpy(poses.copy()).cuda()
+    print("case: fused alignment vs step by step", flush=True)
+    T_f, best = eng.shape_align(gA, gB, fused, n_samples=NS, n_steps=steps, lr=0.05, seed=2)
+    pose = torch.from_numpy(poses.copy()).cuda()
+    Oaa = eng.shape_self_overlap(gA, NS, seed=2)
+    Obb = eng.shape_self_overlap(gB, NS, seed=2)
+    m, v = torch.zeros_like(pose), torch.zeros_like(pose)
+    step = torch.zeros(1, dtype=torch.int32, device="cuda")
+    for _ in range(steps):
+        _, g = eng.shape_align_grad(gA, gB, pose, Oaa, Obb, NS, seed=2)
+        eng.shape_adam_pose(pose, g, m, v, step, lr=0.05)
+    T_s, _ = eng.shape_align_grad(gA, gB, pose, Oaa, Obb, NS, seed=2, need_grad=False)
+    torch.cuda.synchronize()
+    assert torch.equal(fused, pose)
+    assert torch.equal(T_f, T_s)
+    assert torch.equal(best.long(), T_s.argmax(dim=1))
+
+
 def test_displaced_copy_recovered(eng):
     """B = A under a random rotation; 16 starts, 60 Adam steps: best T ~ 1
     (the molecule of the oracle's displaced-copy pin)."""
