@@ -354,14 +354,13 @@ __global__ __launch_bounds__(64) void k_fo_align(FoAlignArgs a) {
   const float S = fo_self(sA, na) + fo_self(sB, nb);  // O_AA + O_BB
   FoTermConsts tc;
   fo_term_consts(sA, na, sB, nb, tc);
-  float x[7], m[7], v[7];
+  // pose x (wave-uniform); lane c < 7 holds component c of the Adam state
+  float x[7];
   float* ps = a.pose + (size_t)item * 7;
 #pragma unroll
-  for (int c = 0; c < 7; ++c) {
-    x[c] = ps[c];
-    m[c] = 0.f;
-    v[c] = 0.f;
-  }
+  for (int c = 0; c < 7; ++c) x[c] = ps[c];
+  const int mine = lane < 7 ? lane : 6;
+  float m_l = 0.f, v_l = 0.f;
   const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
   float b1t = 1.f, b2t = 1.f;  // b1^t, b2^t as running products
   float T = 0.f, g[7];
@@ -401,19 +400,26 @@ __global__ __launch_bounds__(64) void k_fo_align(FoAlignArgs a) {
     g[6] = dTdO * r[3];
     if (it == a.n_steps) break;
     // Adam on -T (bias-corrected moments, betas 0.9 / 0.999), q renormalised;
-    // reciprocals by the hardware (a step of length ~lr tolerates 1 ulp)
+    // reciprocals by the hardware (a step of length ~lr tolerates 1 ulp).
+    // Lane c < 7 updates component c; the new pose is gathered by readlane.
     b1t *= b1;
     b2t *= b2;
     const float ic1 = __builtin_amdgcn_rcpf(1.f - b1t), ic2 = __builtin_amdgcn_rcpf(1.f - b2t);
+    float g_l = g[0], x_l = x[0];
+#pragma unroll
+    for (int c = 1; c < 7; ++c) {
+      g_l = mine == c ? g[c] : g_l;
+      x_l = mine == c ? x[c] : x_l;
+    }
+    const float gc = -g_l;
+    m_l = fmaf(b1, m_l, (1.f - b1) * gc);
+    v_l = fmaf(b2, v_l, (1.f - b2) * gc * gc);
+    const float den = __builtin_amdgcn_sqrtf(v_l * ic2) + eps;
+    const float xn_l = x_l - a.lr * (m_l * ic1) * __builtin_amdgcn_rcpf(den);
     float xn[7];
 #pragma unroll
-    for (int c = 0; c < 7; ++c) {
-      const float gc = -g[c];
-      m[c] = fmaf(b1, m[c], (1.f - b1) * gc);
-      v[c] = fmaf(b2, v[c], (1.f - b2) * gc * gc);
-      const float den = __builtin_amdgcn_sqrtf(v[c] * ic2) + eps;
-      xn[c] = x[c] - a.lr * (m[c] * ic1) * __builtin_amdgcn_rcpf(den);
-    }
+    for (int c = 0; c < 7; ++c)
+      xn[c] = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, xn_l), c));
     const float inv = rsqrtf(xn[0] * xn[0] + xn[1] * xn[1] + xn[2] * xn[2] + xn[3] * xn[3]);
 #pragma unroll
     for (int c = 0; c < 4; ++c) x[c] = xn[c] * inv;
