@@ -27,7 +27,7 @@ enum Slot {
   S_Q_ATOM, S_Q_SAMP, S_Q_Z, S_Q_ID, S_Q_BAD, S_Q_CENTRE,
   S_L_ATOM, S_L_SAMP, S_L_Z, S_L_ID, S_L_BAD, S_L_CENTRE,
   S_PARTIALS, S_RESULT, S_QS, S_QF2,
-  S_SELF_A, S_SELF_B, S_ADAM_M, S_ADAM_V, S_ADAM_STEP, S_GRAD,
+  S_SELF_A, S_SELF_B,
   S_MSE, S_TOPK_SEL, S_TOPK_HIST, S_TOPK_GT, S_TOPK_EQ, S_COLSUM, S_TUNE, S_MLP_PACK, S_FEAT_MOM, S_GEMM_PART,
   S_GRID_BOX, S_GRID_TAB, S_GRID_PART,
   S_COUNT
