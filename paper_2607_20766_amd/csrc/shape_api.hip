@@ -152,7 +152,12 @@ int check_mols(shape_ctx* c, const shape_mols* m, const char* name, bool single)
 }
 
 // Prepare a molecule set into the query (q = true) or library slots.
-int prepare(shape_ctx* c, const shape_mols* m, bool q, hipStream_t st, shape::Prepared* P) {
+// subset (device int32 [n_subset], optional): prepare only these molecules
+// (records at their usual places; the rest of the slots stay as they were),
+// for calls that read no other molecule.  Such a partial preparation is
+// never kept for reuse.
+int prepare(shape_ctx* c, const shape_mols* m, bool q, hipStream_t st, shape::Prepared* P,
+            const int32_t* subset = nullptr, int32_t n_subset = 0) {
   const int base = q ? S_Q_ATOM : S_L_ATOM;
   PrepKey& key = c->prepared[q ? 0 : 1];
   int* set_flag = c->flag + (q ? 1 : 2);
@@ -179,6 +184,11 @@ int prepare(shape_ctx* c, const shape_mols* m, bool q, hipStream_t st, shape::Pr
   P->centre = (float4*)p[5];
   shape::MolsDev in{m->n_mols, m->max_atoms, m->n_atoms, m->atom_offset, m->xyz, m->alpha,
                     m->mol_id};
+  if (subset) {
+    HIP_TRY(c, shape::launch_prepare(in, *P, c->flag, nullptr, st, subset, n_subset),
+            "prepare kernel");
+    return SHAPE_OK;
+  }
   if (c->prep_cache) HIP_TRY(c, shape::launch_fill_int(set_flag, 1, 0, st), "flag reset");
   HIP_TRY(c, shape::launch_prepare(in, *P, c->flag, c->prep_cache ? set_flag : nullptr, st),
           "prepare kernel");
@@ -271,7 +281,12 @@ int screen_setup(shape_ctx* c, const shape_mols* query, const shape_mols* lib,
   if ((rc = set_device(c))) return rc;
   shape::Prepared PQ, PL;
   if ((rc = prepare(c, query, true, st, &PQ))) return rc;
-  if ((rc = prepare(c, lib, false, st, &PL))) return rc;
+  // a screen of a small subset of a large library prepares only that subset
+  // (unless the whole set is already prepared for reuse)
+  const bool subset = pairs && (int64_t)n_pairs * 4 < lib->n_mols &&
+                      !(c->prep_cache && c->prepared[1].same(lib));
+  if ((rc = prepare(c, lib, false, st, &PL, subset ? pairs : nullptr, subset ? n_pairs : 0)))
+    return rc;
   const int64_t n_cache = prm->mode == SHAPE_SCREEN_FIXED ? n_fixed : cap / 2;
   void *qs, *qf2;
   if ((rc = ensure(c, S_QS, (size_t)n_cache * sizeof(float4), &qs))) return rc;
@@ -908,13 +923,10 @@ int shape_features(shape_ctx* c, const shape_mols* M, void* stream, float* out) 
     if (!out) return fail(c, SHAPE_E_INVAL, "out is NULL");
     if ((rc = set_device(c))) return rc;
     hipStream_t st = (hipStream_t)stream;
-    shape::Prepared P;
-    if ((rc = prepare(c, M, false, st, &P))) return rc;
     void* mom;
     if ((rc = ensure(c, S_FEAT_MOM, (size_t)M->n_mols * 6 * sizeof(float), &mom))) return rc;
     KernelTimer timer(c, st);
-    HIP_TRY(c, shape::launch_features(P, M->atom_offset, M->alpha, M->n_mols, out, (float*)mom,
-                                      st),
+    HIP_TRY(c, shape::launch_features(mols_dev(M), c->flag, out, (float*)mom, st),
             "features kernel");
     timer.stop();
     return SHAPE_OK;
@@ -937,11 +949,8 @@ int shape_fo_overlap(shape_ctx* c, const shape_mols* query, const shape_mols* li
     if (!out) return fail(c, SHAPE_E_INVAL, "out is NULL");
     if ((rc = set_device(c))) return rc;
     hipStream_t st = (hipStream_t)stream;
-    shape::Prepared PQ, PL;
-    if ((rc = prepare(c, query, true, st, &PQ))) return rc;
-    if ((rc = prepare(c, lib, false, st, &PL))) return rc;
-    HIP_TRY(c, shape::launch_fo_cross(PQ, query->atom_offset, query->alpha, PL, lib->atom_offset,
-                                      lib->alpha, pairs, n_pairs, lib->n_mols, out, st),
+    HIP_TRY(c, shape::launch_fo_cross(mols_dev(query), mols_dev(lib), pairs, n_pairs, c->flag,
+                                      out, st),
             "first-order overlap kernel");
     return SHAPE_OK;
   } catch (...) {

@@ -345,6 +345,14 @@ __device__ __forceinline__ int xcd_chunk(int b, int G) {
   return ((k / kXcdTile) * kXcds + x) * kXcdTile + k % kXcdTile;
 }
 
+// Lane l's FP64 value, read by every lane (l wave-uniform).
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)b, l);
+  const long long hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double((hi << 32) | lo);
+}
+
 // Orders LDS writes of this wave before its later LDS reads (wave-private
 // staging needs no workgroup barrier).
 __device__ __forceinline__ void wave_lds_sync() {

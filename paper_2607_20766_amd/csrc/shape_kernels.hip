@@ -35,21 +35,17 @@ __global__ void k_alpha_from_radius(const float* __restrict__ R, int64_t n, doub
 constexpr int kPrepWaves = 4;
 constexpr int kPrepChunks = SHAPE_MAX_ATOMS / kWave;
 
-__device__ __forceinline__ double readlane_f64(double v, int l) {
-  const long long b = __double_as_longlong(v);
-  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)b, l);
-  const long long hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
-  return __longlong_as_double((hi << 32) | lo);
-}
-
 __global__ __launch_bounds__(256) void k_prepare(MolsDev in, Prepared out, int* __restrict__ flag,
-                                                 int* __restrict__ set_flag) {
+                                                 int* __restrict__ set_flag,
+                                                 const int* __restrict__ which, int n_which) {
   // FP64 without contraction: Z and the thresholds are the values the plain
   // expressions define, bit for bit.
 #pragma clang fp contract(off)
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-  const int m = blockIdx.x * kPrepWaves + w;
-  if (m >= in.n_mols) return;
+  const int idx = blockIdx.x * kPrepWaves + w;
+  if (idx >= n_which) return;
+  const int m = which ? which[idx] : idx;  // a listed index may repeat
+  if (m < 0 || m >= in.n_mols) return;     // or lie outside: the screen flags it
   const int a0 = in.off[m], a1 = in.off[m + 1];
   const int n = a1 - a0;
   const bool range_bad = !(a0 >= 0 && (int64_t)a1 <= in.n_atoms && n >= 1 && n <= in.max_atoms);
@@ -629,9 +625,12 @@ hipError_t launch_alpha_from_radius(const float* R, int64_t n, double kappa, dou
 }
 
 hipError_t launch_prepare(const MolsDev& in, const Prepared& out, int* flag, int* set_flag,
-                          hipStream_t st) {
-  const int blocks = (in.n_mols + kPrepWaves - 1) / kPrepWaves;
-  hipLaunchKernelGGL(k_prepare, dim3(blocks), dim3(256), 0, st, in, out, flag, set_flag);
+                          hipStream_t st, const int* which, int n_which) {
+  const int n = which ? n_which : in.n_mols;
+  if (n <= 0) return hipSuccess;
+  const int blocks = (n + kPrepWaves - 1) / kPrepWaves;
+  hipLaunchKernelGGL(k_prepare, dim3(blocks), dim3(256), 0, st, in, out, flag, set_flag, which,
+                     n);
   return hipGetLastError();
 }
 

@@ -108,14 +108,15 @@ struct GemmArgs {
 // the scratch it then needs (splits * M * N floats).
 int gemm_splits(const GemmArgs& g);
 
-hipError_t launch_features(const Prepared& M, const int* off, const float* alpha, int n_mols,
-                           float* out, float* mom, hipStream_t st);
+// Features and first-order cross-overlaps read the caller's arrays directly;
+// invalid molecules give NaN and raise *flag.
+hipError_t launch_features(const MolsDev& M, int* flag, float* out, float* mom,
+                           hipStream_t st);
 hipError_t launch_pair_features(const float* fq, const float* flib, const int* qidx,
                                 const int* idx, int n, const float* fo_cross, const float* mean,
                                 const float* inv_std, float* out, hipStream_t st);
-hipError_t launch_fo_cross(const Prepared& Q, const int* offQ, const float* alphaQ,
-                           const Prepared& L, const int* offL, const float* alphaL,
-                           const int* pairs, int n_pairs, int n_lib, float* out, hipStream_t st);
+hipError_t launch_fo_cross(const MolsDev& Q, const MolsDev& L, const int* pairs, int n_pairs,
+                           int* flag, float* out, hipStream_t st);
 hipError_t launch_gemm(const GemmArgs& g, hipStream_t st);
 size_t mlp_pack_bytes();
 // dense-grid quadrature
@@ -173,8 +174,9 @@ hipError_t launch_best_start(const float* T, int n_pairs, int n_starts, int* bes
 
 hipError_t launch_alpha_from_radius(const float* R, int64_t n, double kappa, double lambda,
                                     float* alpha, hipStream_t st);
+// which (optional, [n_which]): prepare only these molecules.
 hipError_t launch_prepare(const MolsDev& in, const Prepared& out, int* flag, int* set_flag,
-                          hipStream_t st);
+                          hipStream_t st, const int* which = nullptr, int n_which = 0);
 hipError_t launch_flag_or(int* flag, const int* set_flag, hipStream_t st);
 hipError_t launch_fill_int(int* p, int n, int v, hipStream_t st);
 int est_blocks(int64_t n_units);

@@ -62,29 +62,43 @@ __device__ __forceinline__ float fo_term(float a, float b, float d2) {
          __builtin_amdgcn_exp2f(-1.44269504088896f * a * b * ir * d2);
 }
 
-__global__ __launch_bounds__(64) void k_features(Prepared M, const int* __restrict__ off,
-                                                 const float* __restrict__ alpha, int n_mols,
+// The caller's arrays are read directly (no preparation pass): validity as
+// in the preparation (offsets in range, 1..max_atoms atoms, alpha > 0, all
+// values finite; otherwise NaN features and the data-error flag), and
+// Z = sum (pi/alpha_i)^(3/2) as an FP32 wave sum (a descriptor's scale, not
+// an estimate).
+__global__ __launch_bounds__(64) void k_features(MolsDev in, int* __restrict__ flag,
                                                  float* __restrict__ out,
                                                  float* __restrict__ mom) {
   __shared__ float4 sC[SHAPE_MAX_ATOMS];  // x, y, z, alpha
   const int mol = xcd_chunk(blockIdx.x, gridDim.x);  // grid = n_mols
   const int lane = threadIdx.x;
-  if (mol >= n_mols) return;
+  if (mol >= in.n_mols) return;
   float* f = out + (size_t)mol * 24;
-  // the per-molecule words are loaded together, ahead of the branch
-  const int bad = M.bad[mol], a0 = off[mol], a1 = off[mol + 1];
-  const double Zm = M.Z[mol];
-  if (bad != 0) {
+  const int a0 = in.off[mol], a1 = in.off[mol + 1];
+  const int n = a1 - a0;
+  const bool range_bad = !(a0 >= 0 && (int64_t)a1 <= in.n_atoms && n >= 1 && n <= in.max_atoms);
+  const int n_ok = range_bad ? 0 : n;  // <= SHAPE_MAX_ATOMS
+  bool bad = range_bad;
+  float zl = 0.f;
+  for (int i = lane; i < n_ok; i += kWave) {
+    const float al = in.alpha[a0 + i];
+    const float x = in.xyz[3 * (a0 + i)], y = in.xyz[3 * (a0 + i) + 1],
+                z = in.xyz[3 * (a0 + i) + 2];
+    if (!(al > 0.0f) || !isfinite(al) || !isfinite(x) || !isfinite(y) || !isfinite(z))
+      bad = true;
+    sC[i] = make_float4(x, y, z, al);
+    const float t = 3.14159265358979f * __builtin_amdgcn_rcpf(al);
+    zl += t * __builtin_amdgcn_sqrtf(t);
+  }
+  if (__ballot(bad) != 0) {
     for (int k = lane; k < 24; k += kWave) f[k] = __builtin_nanf("");
+    if (lane < 6) mom[(size_t)mol * 6 + lane] = __builtin_nanf("");
+    if (lane == 0) atomicOr(flag, 1);
     return;
   }
-  const int n = a1 - a0;
-  for (int i = lane; i < n; i += kWave) {
-    const Atom at = M.atom[a0 + i];
-    sC[i] = make_float4(at.x, at.y, at.z, alpha[a0 + i]);
-  }
   wave_lds_sync();
-  const float iZ = (float)(1.0 / Zm);
+  const float iZ = 1.0f / wave_sum_dpp(zl);
   // pass 1: mixture mean
   float mx = 0.f, my = 0.f, mz = 0.f;
   for (int i = lane; i < n; i += kWave) {
@@ -162,11 +176,12 @@ __global__ __launch_bounds__(64) void k_features(Prepared M, const int* __restri
 
 // Features [16..18]: square roots of the descending eigenvalues of each
 // molecule's mixture covariance (FP64 closed form), one molecule per thread.
-__global__ void k_features_eigen(const Prepared M, int n_mols, const float* __restrict__ mom,
+__global__ void k_features_eigen(int n_mols, const float* __restrict__ mom,
                                  float* __restrict__ out) {
   const int mol = blockIdx.x * blockDim.x + threadIdx.x;
-  if (mol >= n_mols || M.bad[mol] != 0) return;
+  if (mol >= n_mols) return;
   const float* mm = mom + (size_t)mol * 6;
+  if (isnan(mm[0])) return;  // invalid molecule: its features are NaN already
   double ev[3];
   sym3_eigen_desc(mm[0], mm[1], mm[2], mm[3], mm[4], mm[5], ev);
   float* f = out + (size_t)mol * 24;
@@ -181,42 +196,69 @@ __global__ void k_features_eigen(const Prepared M, int n_mols, const float* __re
 // FP32 sums, DPP wave sum.
 constexpr int kFoWaves = 4;
 
+__device__ __forceinline__ bool atom_ok(float al, float x, float y, float z) {
+  return al > 0.0f && isfinite(al) && isfinite(x) && isfinite(y) && isfinite(z);
+}
+
+// The caller's arrays are read directly (no preparation pass); a molecule
+// with invalid data (offsets out of range, alpha <= 0, non-finite values)
+// gives NaN and raises the data-error flag; a pair index outside the
+// library gives NaN.
 __global__ __launch_bounds__(kWave * kFoWaves) void k_fo_cross(
-    Prepared Q, const int* __restrict__ offQ, const float* __restrict__ alphaQ, Prepared L,
-    const int* __restrict__ offL, const float* __restrict__ alphaL, const int* __restrict__ pairs,
-    int n_pairs, int n_lib, float* __restrict__ out) {
+    MolsDev Q, MolsDev L, const int* __restrict__ pairs, int n_pairs, int* __restrict__ flag,
+    float* __restrict__ out) {
   // the query's atoms once per workgroup, each wave's library molecule apart
   __shared__ float4 sA[SHAPE_MAX_ATOMS];
   __shared__ float4 sBall[kFoWaves][SHAPE_MAX_ATOMS];
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
   const int p = xcd_chunk(blockIdx.x, gridDim.x) * kFoWaves + w;
-  if (Q.bad[0] != 0) {  // grid-uniform
+  const int q0 = Q.off[0], q1 = Q.off[1], nq = q1 - q0;
+  const bool q_range = q0 >= 0 && (int64_t)q1 <= Q.n_atoms && nq >= 1 && nq <= Q.max_atoms;
+  int q_bad = q_range ? 0 : 1;
+  if (q_range) {
+    for (int i = threadIdx.x; i < nq; i += kWave * kFoWaves) {
+      const float al = Q.alpha[q0 + i];
+      const float x = Q.xyz[3 * (q0 + i)], y = Q.xyz[3 * (q0 + i) + 1],
+                  z = Q.xyz[3 * (q0 + i) + 2];
+      if (!atom_ok(al, x, y, z)) q_bad = 1;
+      sA[i] = make_float4(x, y, z, al);
+    }
+  }
+  // reached by every wave (no return before it); the outcome is grid-uniform
+  if (__syncthreads_or(q_bad)) {
     if (p < n_pairs && lane == 0) out[p] = __builtin_nanf("");
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(flag, 1);
     return;
   }
-  const int q0 = offQ[0], nq = offQ[1] - q0;
-  for (int i = threadIdx.x; i < nq; i += kWave * kFoWaves) {
-    const Atom at = Q.atom[q0 + i];
-    sA[i] = make_float4(at.x, at.y, at.z, alphaQ[q0 + i]);
-  }
-  __syncthreads();  // reached by every wave: no return before it
   if (p >= n_pairs) return;
   const int m = pairs ? pairs[p] : p;
-  int bad = 1, b0 = 0, b1 = 0;  // the molecule's words are loaded together
-  if (m >= 0 && m < n_lib) {
-    bad = L.bad[m];
-    b0 = offL[m];
-    b1 = offL[m + 1];
-  }
-  if (bad != 0) {
-    if (lane == 0) out[p] = __builtin_nanf("");
-    return;
+  bool m_bad = !(m >= 0 && m < L.n_mols);
+  int b0 = 0, nb = 0;
+  if (!m_bad) {
+    b0 = L.off[m];
+    const int b1 = L.off[m + 1];
+    nb = b1 - b0;
+    m_bad = !(b0 >= 0 && (int64_t)b1 <= L.n_atoms && nb >= 1 && nb <= L.max_atoms);
   }
   float4* sB = sBall[w];
-  const int nb = b1 - b0;
-  for (int j = lane; j < nb; j += kWave) {
-    const Atom at = L.atom[b0 + j];
-    sB[j] = make_float4(at.x, at.y, at.z, alphaL[b0 + j]);
+  bool a_bad = false;
+  if (!m_bad) {
+    for (int j = lane; j < nb; j += kWave) {
+      const float al = L.alpha[b0 + j];
+      const float x = L.xyz[3 * (b0 + j)], y = L.xyz[3 * (b0 + j) + 1],
+                  z = L.xyz[3 * (b0 + j) + 2];
+      if (!atom_ok(al, x, y, z)) a_bad = true;
+      sB[j] = make_float4(x, y, z, al);
+    }
+  }
+  const bool data_bad = __ballot(a_bad) != 0;
+  if (m_bad || data_bad) {
+    if (lane == 0) {
+      out[p] = __builtin_nanf("");
+      // invalid data is flagged; an index outside the library only gives NaN
+      if (data_bad || (m >= 0 && m < L.n_mols)) atomicOr(flag, 1);
+    }
+    return;
   }
   wave_lds_sync();
   const int di = kWave / nb, dj = kWave % nb;
@@ -931,14 +973,14 @@ __global__ __launch_bounds__(256) void k_select_write(const float* __restrict__ 
 // ---------------------------------------------------------------------------
 // Launchers.
 // ---------------------------------------------------------------------------
-hipError_t launch_features(const Prepared& M, const int* off, const float* alpha, int n_mols,
-                           float* out, float* mom, hipStream_t st) {
-  hipLaunchKernelGGL(k_features, dim3((unsigned)n_mols), dim3(kWave), 0, st, M, off, alpha,
-                     n_mols, out, mom);
+hipError_t launch_features(const MolsDev& M, int* flag, float* out, float* mom,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(k_features, dim3((unsigned)M.n_mols), dim3(kWave), 0, st, M, flag, out,
+                     mom);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_features_eigen, dim3((unsigned)((n_mols + 255) / 256)), dim3(256), 0, st,
-                     M, n_mols, mom, out);
+  hipLaunchKernelGGL(k_features_eigen, dim3((unsigned)((M.n_mols + 255) / 256)), dim3(256), 0,
+                     st, M.n_mols, mom, out);
   return hipGetLastError();
 }
 
@@ -951,13 +993,10 @@ hipError_t launch_pair_features(const float* fq, const float* flib, const int* q
   return hipGetLastError();
 }
 
-hipError_t launch_fo_cross(const Prepared& Q, const int* offQ, const float* alphaQ,
-                           const Prepared& L, const int* offL, const float* alphaL,
-                           const int* pairs, int n_pairs, int n_lib, float* out,
-                           hipStream_t st) {
+hipError_t launch_fo_cross(const MolsDev& Q, const MolsDev& L, const int* pairs, int n_pairs,
+                           int* flag, float* out, hipStream_t st) {
   hipLaunchKernelGGL(k_fo_cross, dim3((unsigned)((n_pairs + kFoWaves - 1) / kFoWaves)),
-                     dim3(kWave * kFoWaves), 0, st, Q, offQ, alphaQ, L, offL, alphaL, pairs,
-                     n_pairs, n_lib, out);
+                     dim3(kWave * kFoWaves), 0, st, Q, L, pairs, n_pairs, flag, out);
   return hipGetLastError();
 }
 

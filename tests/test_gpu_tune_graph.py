@@ -229,3 +229,64 @@ def test_prepare_cache_still_reports_invalid_data(eng, data):
     finally:
         eng.prepare_cache(False)
     eng.shape_check_data()
+
+
+def test_subset_screens_prepare_only_their_molecules(eng):
+    """A screen of a small pair subset prepares only the listed molecules;
+    its results equal the whole-library screen's for those pairs, with or
+    without a reusable whole-set preparation, and a whole-library screen
+    afterwards is not misled by the partial one."""
+    from paper_2607_20766_amd.engine import SHAPE_SCREEN_ADAPTIVE as AD
+    q = molgen.molecule(1, 0, 30)
+    L = molgen.library(19, 400, 10, 50, workers=1)
+    Q = eng.molecules(q, mol_id=[QUERY_ID])
+    lib = eng.molecules(L)
+    kw = dict(mode=AD, round_per_pair=512, cap_per_pair=8192, seed=4)
+    full = _np(eng.shape_screen(Q, lib, **kw))
+    sub = np.array([399, 7, 7, 0, 123, 250], dtype=np.int32)
+    pairs = torch.from_numpy(sub).cuda()
+    part = _np(eng.shape_screen(Q, lib, pairs=pairs, **kw))
+    for k in part:
+        assert np.array_equal(part[k], full[k][sub]), k
+    eng.prepare_cache(True)
+    try:
+        again = _np(eng.shape_screen(Q, lib, **kw))     # whole set, prepared for reuse
+        part2 = _np(eng.shape_screen(Q, lib, pairs=pairs, **kw))  # reuses it
+        part3 = _np(eng.shape_screen(Q, lib, pairs=pairs, **kw))
+        eng.prepare_cache(True)                          # forget
+        part4 = _np(eng.shape_screen(Q, lib, pairs=pairs, **kw))  # subset again
+        whole = _np(eng.shape_screen(Q, lib, **kw))      # must prepare everything
+    finally:
+        eng.prepare_cache(False)
+    _same(full, again)
+    _same(full, whole)
+    for p_ in (part2, part3, part4):
+        for k in p_:
+            assert np.array_equal(p_[k], full[k][sub]), k
+
+
+def test_features_and_first_order_flag_invalid_data(eng):
+    """Features and first-order overlaps read the caller's arrays directly:
+    an invalid molecule gives NaN and raises the data-error flag."""
+    q = molgen.molecule(1, 0, 30)
+    L = molgen.library(20, 30, 10, 50, workers=1)
+    L.xyz[L.offsets[4] + 1, 2] = np.inf
+    Q = eng.molecules(q, mol_id=[QUERY_ID])
+    lib = eng.molecules(L)
+    lib.alpha[int(L.offsets[9])] = 0.0
+    f = eng.shape_features(lib).cpu().numpy()
+    assert np.isnan(f[4]).all() and np.isnan(f[9]).all()
+    assert np.isfinite(np.delete(f, [4, 9], 0)).all()
+    with pytest.raises(ShapeError):
+        eng.shape_check_data()
+    eng.shape_check_data()
+    fo = eng.shape_fo_overlap(Q, lib).cpu().numpy()
+    assert np.isnan(fo[[4, 9]]).all() and np.isfinite(np.delete(fo, [4, 9])).all()
+    with pytest.raises(ShapeError):
+        eng.shape_check_data()
+    eng.shape_check_data()
+    # an index outside the library gives NaN without flagging the data
+    bad_idx = torch.tensor([2, 30, -1], dtype=torch.int32, device="cuda")
+    fo2 = eng.shape_fo_overlap(Q, lib, pairs=bad_idx).cpu().numpy()
+    assert np.isfinite(fo2[0]) and np.isnan(fo2[1:]).all()
+    eng.shape_check_data()
