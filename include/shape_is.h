@@ -213,10 +213,14 @@ int shape_set_sampling(shape_ctx* ctx, int32_t sampling);
 int32_t shape_get_sampling(const shape_ctx* ctx);
 
 /* Reuse of molecule preparation across calls (a pipeline that hands the
- * same molecule set to several calls, e.g. shape_features, shape_fo_overlap
- * and shape_screen of one library).  Every call prepares its molecule sets
- * (mixture weights, sampling thresholds, frames) into context scratch, one
- * set on the query side and one on the library side.  While the cache is
+ * same molecule set to several calls, e.g. shape_screen and shape_estimate
+ * of one library).  Every sampling call prepares its molecule sets (mixture
+ * weights, sampling thresholds, frames) into context scratch, one set on the
+ * query side and one on the library side; a shape_screen whose pairs list
+ * names fewer than a quarter of the library prepares only those molecules,
+ * and such a partial preparation is never reused.  shape_features and
+ * shape_fo_overlap read the caller's arrays and prepare nothing.  While the
+ * cache is
  * enabled, a set whose arrays (device pointers) and sizes equal those of the
  * set last prepared on the same side is not prepared again.  The caller
  * guarantees that the arrays are not written while the cache is enabled;
@@ -416,13 +420,17 @@ int shape_apply_pose(shape_ctx* ctx, const shape_mols* M, const float* pose, voi
  * eigenvalues of the mixture covariance sum pi_i (c_i c_i^T + I/(2 alpha_i))
  * - mu mu^T; [19..22] atoms per width class (alpha < 0.767, < 0.893, < 0.995,
  * otherwise); [23] the first-order self-overlap (Eq. fo with B = A).
- * Invalid molecules give NaN rows.  Asynchronous. */
+ * Reads the caller's arrays directly; invalid molecules (as in shape_screen)
+ * give NaN rows and raise the flag that shape_check_data reports.
+ * Asynchronous. */
 int shape_features(shape_ctx* ctx, const shape_mols* M, void* stream, float* out);
 
 /* First-order cross-overlap (Eq. fo) of the query with library molecules at
  * their given poses: out[p] = O^FO(query, lib[m]), m = pairs[p] (pairs NULL:
- * m = p).  O(N_q N_m) per pair.  out: device float [n_pairs].  Asynchronous;
- * invalid molecules give NaN. */
+ * m = p).  O(N_q N_m) per pair.  out: device float [n_pairs].  Asynchronous.
+ * Reads the caller's arrays directly; an invalid molecule gives NaN and
+ * raises the flag that shape_check_data reports; a pairs entry outside the
+ * library gives NaN. */
 int shape_fo_overlap(shape_ctx* ctx, const shape_mols* query, const shape_mols* lib,
                      const int32_t* pairs, int32_t n_pairs, void* stream, float* out);
 
