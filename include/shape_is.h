@@ -183,7 +183,8 @@ typedef struct {
 /* Screen one query molecule against library molecules.
  * query: n_mols == 1.  lib: the library.  pairs: device int32 [n_pairs]
  * library indices to score, or NULL to score lib molecule p for p < n_pairs
- * (then n_pairs <= lib->n_mols).  Outputs are indexed by pair.
+ * (then n_pairs <= lib->n_mols).  Outputs are indexed by pair; an index
+ * outside [0, lib->n_mols) gives NaN outputs and n_used 0.
  * Asynchronous.  Invalid molecules produce NaN outputs and are reported by
  * shape_check_data.  Errors: SHAPE_E_INVAL, SHAPE_E_RANGE, SHAPE_E_NOMEM,
  * SHAPE_E_HIP. */

@@ -263,6 +263,13 @@ def test_subset_screens_prepare_only_their_molecules(eng):
     for p_ in (part2, part3, part4):
         for k in p_:
             assert np.array_equal(p_[k], full[k][sub]), k
+    # indices outside the library: NaN and no samples, the rest unaffected
+    odd = torch.tensor([5, 400, -3, 9], dtype=torch.int32, device="cuda")
+    g = _np(eng.shape_screen(Q, lib, pairs=odd, **kw))
+    assert np.isnan(g["T"][[1, 2]]).all() and (g["n_used"][[1, 2]] == 0).all()
+    for k in g:
+        assert np.array_equal(g[k][[0, 3]], full[k][[5, 9]]), k
+    eng.shape_check_data()
 
 
 def test_features_and_first_order_flag_invalid_data(eng):
