@@ -318,14 +318,24 @@ __global__ void k_pair_features(const float* __restrict__ fq, const float* __res
 //   C[m][n] = epilogue( sum_k A[m][k] B[k][n] )
 // A(m, k) = A[m sam + k sak], B(k, n) = B[k sbk + n sbn] (any transposition),
 // epilogue: + bias[n], then ReLU, or multiplication by 1[gate[m][n] > 0]
-// (ReLU backward).  BF16: v_mfma_f32_16x16x16bf16_1k, operands rounded to
+// (ReLU backward).  BF16: v_mfma_f32_16x16x32_bf16, operands rounded to
 // nearest even (LDS-tiled kernel below); FP32: v_mfma_f32_16x16x4f32
 // (workgroup tile 64 x 64, 4 waves x 32 x 32, each 2 x 2 MFMA 16 x 16 tiles).
 // Lane l supplies row (or column) l mod 16 and k-group l / 16; result element
 // (4 (l/16) + r, l mod 16) sits in accumulator r of lane l.
 // ---------------------------------------------------------------------------
 typedef short v4s __attribute__((ext_vector_type(4)));
+typedef short v8s __attribute__((ext_vector_type(8)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef float v4f __attribute__((ext_vector_type(4)));
+
+// D += A B for a 16 x 32 by 32 x 16 BF16 tile on v_mfma_f32_16x16x32_bf16:
+// lane l supplies row (or column) l mod 16 and k = 8 (l / 16) .. 8 (l / 16) + 7
+// (layout checked on the GPU); the result layout is that of the 16x16x16 form.
+__device__ __forceinline__ v4f mfma_bf16_k32(v8s a, v8s b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a),
+                                                 __builtin_bit_cast(v8bf, b), c, 0, 0, 0);
+}
 
 __device__ __forceinline__ short to_bf16(float x) {
   uint32_t u = __float_as_uint(x);
@@ -392,17 +402,18 @@ __global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs g) {
 // Both operands are staged as bfloat16 with k contiguous (A_s[m][k],
 // B_s[n][k]), loaded from global memory along whichever dimension is
 // contiguous there, so every wave reads whole cache lines.  Each of the four
-// waves computes a (TM/2) x (TN/2) sub-tile of MFMA 16x16x16 tiles.  Every
-// output element accumulates k in the same order (slabs of 32, two MFMA
-// steps of 16) whatever the tile size, so both sizes give the same bits.
+// waves computes a (TM/2) x (TN/2) sub-tile of 16 x 16 MFMA tiles, one
+// v_mfma_f32_16x16x32_bf16 per tile and slab.  Every output element
+// accumulates k in the same order (slabs of 32, increasing) whatever the tile
+// size, so both sizes give the same bits.
 constexpr int kTK = 32, kLdk = kTK + 8;
 
 template <int TM, int TN>
 __global__ __launch_bounds__(256, 2) void k_gemm_bf16_tiled(GemmArgs g) {
   constexpr int FM = TM / 32, FN = TN / 32;           // MFMA tiles per wave
   constexpr int RA = TM * kTK / 256, RB = TN * kTK / 256;  // staged values per thread
-  __shared__ short As[TM * kLdk];
-  __shared__ short Bs[TN * kLdk];
+  __shared__ __align__(16) short As[TM * kLdk];
+  __shared__ __align__(16) short Bs[TN * kLdk];
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
   const int bm = blockIdx.y * TM, bn = blockIdx.x * TN;
   const int wm = (wave >> 1) * (TM / 2), wn = (wave & 1) * (TN / 2);
@@ -466,20 +477,18 @@ __global__ __launch_bounds__(256, 2) void k_gemm_bf16_tiled(GemmArgs g) {
     store_slab();
     __syncthreads();
     if (k0 + kTK < ke) load_slab(k0 + kTK);
-#pragma unroll
-    for (int kk = 0; kk < kTK; kk += 16) {
-      v4s a[FM], b[FN];
+    {
+      v8s a[FM], b[FN];
 #pragma unroll
       for (int i = 0; i < FM; ++i)
-        a[i] = *reinterpret_cast<const v4s*>(&As[(wm + 16 * i + li) * kLdk + kk + 4 * lk]);
+        a[i] = *reinterpret_cast<const v8s*>(&As[(wm + 16 * i + li) * kLdk + 8 * lk]);
 #pragma unroll
       for (int j = 0; j < FN; ++j)
-        b[j] = *reinterpret_cast<const v4s*>(&Bs[(wn + 16 * j + li) * kLdk + kk + 4 * lk]);
+        b[j] = *reinterpret_cast<const v8s*>(&Bs[(wn + 16 * j + li) * kLdk + 8 * lk]);
 #pragma unroll
       for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int j = 0; j < FN; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < FN; ++j) acc[i][j] = mfma_bf16_k32(a[i], b[j], acc[i][j]);
     }
     __syncthreads();
   }
@@ -521,27 +530,27 @@ __global__ void k_splitk_reduce(GemmArgs g, int splits) {
 // standardisation and all four layers in one kernel, activations resident in
 // LDS.  The arithmetic is that of shape_pair_features followed by one
 // shape_gemm per layer (BF16 operands rounded to nearest even, FP32
-// accumulation over k in steps of 16 in increasing order, bias then ReLU in
-// FP32), so the outputs agree bit for bit; only the HBM round trips of the
-// features and activations are gone.
+// accumulation over k in steps of 32 in increasing order on the same matrix
+// instruction, bias then ReLU in FP32), so the outputs agree bit for bit; only
+// the HBM round trips of the features and activations are gone.
 //
 // Weights are first packed to BF16 in MFMA fragment order: for layer l,
-// block (kb, nb) of 16 x 16 holds 64 lanes x 4 values, lane = 16 (k%16 / 4) +
-// n%16, value k%4, so one wave reads a B fragment as 512 contiguous bytes.
-// The last layer's 2 outputs are padded to 16 columns with zeros.
+// block (kb, nb) of 32 x 16 holds 64 lanes x 8 values, lane = 16 (k%32 / 8) +
+// n%16, value k%8, so one wave reads a B fragment as 1 KB of contiguous
+// bytes.  The last layer's 2 outputs are padded to 16 columns with zeros.
 // ---------------------------------------------------------------------------
 constexpr int kMlpIn = 96, kMlpHid = 256, kMlpOut = 2;
 constexpr int kMlpRows = 128;           // pairs per workgroup
 constexpr int kMlpLd = kMlpHid + 8;     // LDS row stride (bf16 elements)
 
 __host__ __device__ constexpr int mlp_pack_offset(int layer) {
-  // fragment blocks of 16 x 16 (256 bf16) per layer: 6x16, 16x16, 16x16, 16x1
+  // fragment blocks of 32 x 16 (512 bf16) per layer: 3x16, 8x16, 8x16, 8x1
   return layer == 0 ? 0
-       : layer == 1 ? 6 * 16 * 256
-       : layer == 2 ? (6 * 16 + 16 * 16) * 256
-                    : (6 * 16 + 2 * 16 * 16) * 256;
+       : layer == 1 ? 3 * 16 * 512
+       : layer == 2 ? (3 * 16 + 8 * 16) * 512
+                    : (3 * 16 + 2 * 8 * 16) * 512;
 }
-constexpr int kMlpPackElems = (6 * 16 + 2 * 16 * 16 + 16) * 256;
+constexpr int kMlpPackElems = (3 * 16 + 2 * 8 * 16 + 8) * 512;
 
 __global__ void k_mlp_pack(const float* __restrict__ params, short* __restrict__ packed) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -552,10 +561,10 @@ __global__ void k_mlp_pack(const float* __restrict__ params, short* __restrict__
   const int n_in = layer == 0 ? kMlpIn : kMlpHid;
   const int n_out = layer == 3 ? kMlpOut : kMlpHid;
   const int nbs = layer == 3 ? 1 : kMlpHid / 16;   // column blocks
-  const int blk = local / 256, within = local % 256;
+  const int blk = local / 512, within = local % 512;
   const int kb = blk / nbs, nb = blk % nbs;
-  const int lane = within / 4, e = within % 4;
-  const int k = kb * 16 + 4 * (lane >> 4) + e;
+  const int lane = within / 8, e = within % 8;
+  const int k = kb * 32 + 8 * (lane >> 4) + e;
   const int n = nb * 16 + (lane & 15);
   // offset of W_layer in the flat W0, b0, W1, b1, ... vector
   int off = 0;
@@ -577,13 +586,13 @@ struct MlpArgs {
   const float* fo_cross;
   const float* mean;
   const float* inv_std;
-  const v4s* W;        // packed weights (kMlpPackElems bf16)
+  const v8s* W;        // packed weights (kMlpPackElems bf16)
   const float* b[4];   // biases of the four layers
   float* out;          // [n][2]
 };
 
 __global__ __launch_bounds__(256, 2) void k_mlp_infer(MlpArgs a) {
-  __shared__ short H[kMlpRows * kMlpLd];
+  __shared__ __align__(16) short H[kMlpRows * kMlpLd];
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
   const int li = lane & 15, lk = lane >> 4;
   const int row0 = blockIdx.x * kMlpRows;
@@ -643,19 +652,19 @@ __global__ __launch_bounds__(256, 2) void k_mlp_infer(MlpArgs a) {
   // three hidden layers: wave w computes all 128 rows x columns [64 w, 64 w + 64)
 #pragma unroll 1
   for (int l = 0; l < 3; ++l) {
-    const int kbs = (l == 0 ? kMlpIn : kMlpHid) / 16;
-    const v4s* W = a.W + mlp_pack_offset(l) / 4;
+    const int kbs = (l == 0 ? kMlpIn : kMlpHid) / 32;
+    const v8s* W = a.W + mlp_pack_offset(l) / 8;
     v4f acc[8][4];
 #pragma unroll
     for (int i = 0; i < 8; ++i)
 #pragma unroll
       for (int j = 0; j < 4; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
     // weight fragments one k-block ahead of the products
-    v4s bn[4];
+    v8s bn[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) bn[j] = W[(wave * 4 + j) * kWave + lane];
     for (int kb = 0; kb < kbs; ++kb) {
-      v4s b[4], x[8];
+      v8s b[4], x[8];
 #pragma unroll
       for (int j = 0; j < 4; ++j) b[j] = bn[j];
       if (kb + 1 < kbs) {
@@ -664,12 +673,11 @@ __global__ __launch_bounds__(256, 2) void k_mlp_infer(MlpArgs a) {
       }
 #pragma unroll
       for (int i = 0; i < 8; ++i)
-        x[i] = *reinterpret_cast<const v4s*>(&H[(16 * i + li) * kMlpLd + kb * 16 + 4 * lk]);
+        x[i] = *reinterpret_cast<const v8s*>(&H[(16 * i + li) * kMlpLd + kb * 32 + 8 * lk]);
 #pragma unroll
       for (int i = 0; i < 8; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(x[i], b[j], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < 4; ++j) acc[i][j] = mfma_bf16_k32(x[i], b[j], acc[i][j]);
     }
     __syncthreads();  // every wave has read this layer's input
     const float* bias = a.b[l];
@@ -690,15 +698,15 @@ __global__ __launch_bounds__(256, 2) void k_mlp_infer(MlpArgs a) {
   }
   // output layer (2 columns, padded to 16): wave w computes rows [32 w, 32 w + 32)
   {
-    const v4s* W = a.W + mlp_pack_offset(3) / 4;
+    const v8s* W = a.W + mlp_pack_offset(3) / 8;
     v4f acc[2] = {v4f{0.f, 0.f, 0.f, 0.f}, v4f{0.f, 0.f, 0.f, 0.f}};
-    for (int kb = 0; kb < kMlpHid / 16; ++kb) {
-      const v4s b = W[kb * kWave + lane];
+    for (int kb = 0; kb < kMlpHid / 32; ++kb) {
+      const v8s b = W[kb * kWave + lane];
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
-        const v4s x = *reinterpret_cast<const v4s*>(
-            &H[(32 * wave + 16 * i + li) * kMlpLd + kb * 16 + 4 * lk]);
-        acc[i] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(x, b, acc[i], 0, 0, 0);
+        const v8s x = *reinterpret_cast<const v8s*>(
+            &H[(32 * wave + 16 * i + li) * kMlpLd + kb * 32 + 8 * lk]);
+        acc[i] = mfma_bf16_k32(x, b, acc[i]);
       }
     }
     if (li < kMlpOut) {
@@ -1077,7 +1085,7 @@ hipError_t launch_mlp_infer(const float* fq, const float* flib, const int* qidx,
   a.fo_cross = fo_cross;
   a.mean = mean;
   a.inv_std = inv_std;
-  a.W = (const v4s*)packed;
+  a.W = (const v8s*)packed;
   int off = 0;
   for (int l = 0; l < 4; ++l) {
     const int i_ = l == 0 ? kMlpIn : kMlpHid;
