@@ -310,6 +310,19 @@ __device__ __forceinline__ float dpp_step(float v) {
   const int s = __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), Ctrl, RowMask, 0xf, true);
   return v + __builtin_bit_cast(float, s);
 }
+// Sum over each row of 16 lanes, returned to all 16 lanes of the row: XOR
+// partners 1 and 2 inside each quad (quad_perm), then the mirror lane of the
+// other quad (row_half_mirror) and of the other half row (row_mirror).  Each
+// step adds two partials that the partner lane adds in the other order, and
+// the sum of two floats does not depend on their order, so every lane of a
+// row ends with the same bits.
+__device__ __forceinline__ float row_sum16(float v) {
+  v = dpp_step<0xB1, 0xf>(v);   // quad_perm [1,0,3,2]
+  v = dpp_step<0x4E, 0xf>(v);   // quad_perm [2,3,0,1]
+  v = dpp_step<0x141, 0xf>(v);  // row_half_mirror
+  v = dpp_step<0x140, 0xf>(v);  // row_mirror
+  return v;
+}
 __device__ __forceinline__ float wave_sum_dpp(float v) {
   v = dpp_step<0x111, 0xf>(v);  // row_shr:1
   v = dpp_step<0x112, 0xf>(v);  // row_shr:2

@@ -185,6 +185,16 @@ __global__ void k_fo_starts(MolsDev A, MolsDev B, const int* __restrict__ badA,
 // First-order alignment: one wave per (pair, start); Adam runs inside the
 // kernel, the pose and its moments stay in registers (wave-uniform).
 // ---------------------------------------------------------------------------
+// Row layout: at most kFoRowsStarts starts (rows of 16 lanes) per
+// workgroup; moved-atom arrays of the rows at a stride of s float4 with
+// s = 2 (mod 8), so the four rows of a wave read their broadcast atoms from
+// four disjoint groups of LDS banks.
+constexpr int kFoRowsStarts = 16;
+constexpr size_t kFoRowsLdsMax = 48 * 1024;
+__host__ __device__ inline int fo_rows_stride(int max_b) {
+  return max_b + (((2 - max_b) % 8) + 8) % 8;
+}
+
 struct FoAlignArgs {
   MolsDev A, B;
   const int* badA;  // invalid-molecule flags of the prepared sets
@@ -436,6 +446,191 @@ __global__ __launch_bounds__(64) void k_fo_align(FoAlignArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// First-order alignment, row layout: one workgroup per pair and up to 16
+// starts, one start per 16-lane row of a wave, so the per-step work that
+// does not scale with the atom pairs (rotation, reductions, Adam) is shared
+// by four starts per wave instruction.  Lane l of a row owns A's atoms
+// i = l + 16 r (r < RA; rows past N_A are padding whose constants are 0, so
+// their terms add exactly 0) and walks all of B's moved atoms, read as LDS
+// broadcasts.  The pose-independent constants (-log2(e) k_ij, (pi/(a_i+a_j))^(3/2))
+// of every atom pair sit in an LDS table filled once per workgroup.
+// Per term: K = pre exp2(kk |d|^2), d = c_i - c''_j; the lane keeps
+// O_i = sum_j K and F_i = sum_j kk K d.  Since dO/dc''_j is parallel to d,
+// c''_j x (s d) = c_i x (s d), so the torque about B's origin is
+// sum_i c_i x F_i less t x sum F, formed once per lane instead of per term;
+// dO/dc''_j = 2 k K d = -2 ln(2) kk K d scales F once at the end.
+// Every lane of a row holds the same pose, moments and gradient (row sums
+// leave identical bits in all 16 lanes), so Adam runs redundantly per lane.
+// ---------------------------------------------------------------------------
+template <int RA>
+__global__ __launch_bounds__(256) void k_fo_align_rows(FoAlignArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  constexpr int RA16 = RA * 16;
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+  const int l16 = lane & 15, row = lane >> 4;
+  const int pair = xcd_chunk(blockIdx.x, gridDim.x);
+  const int s_raw = blockIdx.y * kFoRowsStarts + wave * 4 + row;
+  const bool live = s_raw < a.n_starts;
+  const int s = live ? s_raw : a.n_starts - 1;  // spare rows repeat the last start
+  const size_t item = (size_t)pair * a.n_starts + s;
+  const int ma = a.A.n_mols == 1 ? 0 : pair;
+  if (a.badA[ma] != 0 || a.badB[pair] != 0) {
+    if (live && l16 == 0) {
+      a.T[item] = __builtin_nanf("");
+      if (a.grad)
+        for (int c = 0; c < 7; ++c) a.grad[item * 7 + c] = __builtin_nanf("");
+    }
+    return;
+  }
+  const int a0 = a.A.off[ma], na = a.A.off[ma + 1] - a0;
+  const int b0 = a.B.off[pair], nb = a.B.off[pair + 1] - b0;
+  const int stride = fo_rows_stride(a.B.max_atoms);
+  const int n_rows = (int)(blockDim.x / 16);
+  float4* sA = reinterpret_cast<float4*>(smem);  // [max_a] x, y, z, alpha
+  float4* sB = sA + a.A.max_atoms;               // [max_b] B as given
+  float4* sM = sB + a.B.max_atoms;               // [rows][stride] B moved, per start
+  float2* tab = reinterpret_cast<float2*>(sM + (size_t)n_rows * stride);  // [max_b][RA16]
+  for (int i = tid; i < na; i += blockDim.x)
+    sA[i] = make_float4(a.A.xyz[3 * (a0 + i)], a.A.xyz[3 * (a0 + i) + 1],
+                        a.A.xyz[3 * (a0 + i) + 2], a.A.alpha[a0 + i]);
+  for (int j = tid; j < nb; j += blockDim.x)
+    sB[j] = make_float4(a.B.xyz[3 * (b0 + j)], a.B.xyz[3 * (b0 + j) + 1],
+                        a.B.xyz[3 * (b0 + j) + 2], a.B.alpha[b0 + j]);
+  __syncthreads();
+  for (int e = tid; e < nb * RA16; e += blockDim.x) {
+    const int j = e / RA16, i = e % RA16;
+    float kk = 0.f, pre = 0.f, f2;
+    if (i < na) fo_consts(sA[i].w, sB[j].w, kk, pre, f2);
+    tab[e] = make_float2(kk, pre);
+  }
+  __syncthreads();
+  const float S = fo_self(sA, na) + fo_self(sB, nb);  // O_AA + O_BB
+  float cx[RA], cy[RA], cz[RA];
+#pragma unroll
+  for (int r = 0; r < RA; ++r) {
+    const int i = l16 + 16 * r;
+    const float4 c = i < na ? sA[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+    cx[r] = c.x;
+    cy[r] = c.y;
+    cz[r] = c.z;
+  }
+  float4* mine = sM + (size_t)(wave * 4 + row) * stride;
+  const float2* trow = tab + l16;
+  float x[7], m[7], v[7];
+  float* ps = a.pose + item * 7;
+#pragma unroll
+  for (int c = 0; c < 7; ++c) {
+    x[c] = ps[c];
+    m[c] = 0.f;
+    v[c] = 0.f;
+  }
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  float b1t = 1.f, b2t = 1.f;
+  float T = 0.f, g[7];
+  for (int it = 0; it <= a.n_steps; ++it) {
+    const float n2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2] + x[3] * x[3];
+    const float in = rsqrtf(n2);
+    const float qw = x[0] * in, qx = x[1] * in, qy = x[2] * in, qz = x[3] * in;
+    const float R0 = 1.f - 2.f * (qy * qy + qz * qz), R1 = 2.f * (qx * qy - qw * qz),
+                R2 = 2.f * (qx * qz + qw * qy), R3 = 2.f * (qx * qy + qw * qz),
+                R4 = 1.f - 2.f * (qx * qx + qz * qz), R5 = 2.f * (qy * qz - qw * qx),
+                R6 = 2.f * (qx * qz - qw * qy), R7 = 2.f * (qy * qz + qw * qx),
+                R8 = 1.f - 2.f * (qx * qx + qy * qy);
+    for (int j = l16; j < nb; j += 16) {
+      const float4 c = sB[j];
+      mine[j] = make_float4(fmaf(R0, c.x, fmaf(R1, c.y, fmaf(R2, c.z, x[4]))),
+                            fmaf(R3, c.x, fmaf(R4, c.y, fmaf(R5, c.z, x[5]))),
+                            fmaf(R6, c.x, fmaf(R7, c.y, fmaf(R8, c.z, x[6]))), 0.f);
+    }
+    wave_lds_sync();
+    float O[RA], Fx[RA], Fy[RA], Fz[RA];
+#pragma unroll
+    for (int r = 0; r < RA; ++r) O[r] = Fx[r] = Fy[r] = Fz[r] = 0.f;
+#pragma unroll 2
+    for (int j = 0; j < nb; ++j) {
+      const float4 cj = mine[j];
+#pragma unroll
+      for (int r = 0; r < RA; ++r) {
+        const float2 kp = trow[j * RA16 + 16 * r];
+        const float dx = cx[r] - cj.x, dy = cy[r] - cj.y, dz = cz[r] - cj.z;
+        const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+        const float K = kp.y * __builtin_amdgcn_exp2f(kp.x * d2);
+        O[r] += K;
+        const float fs = kp.x * K;
+        Fx[r] = fmaf(fs, dx, Fx[r]);
+        Fy[r] = fmaf(fs, dy, Fy[r]);
+        Fz[r] = fmaf(fs, dz, Fz[r]);
+      }
+    }
+    wave_lds_sync();  // this start's moved atoms are rewritten next step
+    float o = O[0], fx = Fx[0], fy = Fy[0], fz = Fz[0];
+    float tx = cy[0] * Fz[0] - cz[0] * Fy[0], ty = cz[0] * Fx[0] - cx[0] * Fz[0],
+          tz = cx[0] * Fy[0] - cy[0] * Fx[0];
+#pragma unroll
+    for (int r = 1; r < RA; ++r) {
+      o += O[r];
+      fx += Fx[r];
+      fy += Fy[r];
+      fz += Fz[r];
+      tx += cy[r] * Fz[r] - cz[r] * Fy[r];
+      ty += cz[r] * Fx[r] - cx[r] * Fz[r];
+      tz += cx[r] * Fy[r] - cy[r] * Fx[r];
+    }
+    const float sc = -1.38629436111989061f;  // -2 ln 2
+    float r7[7];
+    r7[0] = row_sum16(o);
+    r7[1] = sc * row_sum16(fx);
+    r7[2] = sc * row_sum16(fy);
+    r7[3] = sc * row_sum16(fz);
+    // torque about B's origin: sum c_i x F_i - t x sum F
+    r7[4] = sc * row_sum16(tx) - (x[5] * r7[3] - x[6] * r7[2]);
+    r7[5] = sc * row_sum16(ty) - (x[6] * r7[1] - x[4] * r7[3]);
+    r7[6] = sc * row_sum16(tz) - (x[4] * r7[2] - x[5] * r7[1]);
+    const float D = S - r7[0];
+    T = r7[0] / D;
+    const float iD = __builtin_amdgcn_rcpf(D);
+    const float dTdO = S * iD * iD;
+    const float gth[3] = {dTdO * r7[4], dTdO * r7[5], dTdO * r7[6]};
+    const float vdg = qx * gth[0] + qy * gth[1] + qz * gth[2];
+    g[0] = 2.f * in * (-vdg);
+    g[1] = 2.f * in * (qw * gth[0] - (qy * gth[2] - qz * gth[1]));
+    g[2] = 2.f * in * (qw * gth[1] - (qz * gth[0] - qx * gth[2]));
+    g[3] = 2.f * in * (qw * gth[2] - (qx * gth[1] - qy * gth[0]));
+    g[4] = dTdO * r7[1];
+    g[5] = dTdO * r7[2];
+    g[6] = dTdO * r7[3];
+    if (it == a.n_steps) break;
+    // Adam on -T, as in the one-start-per-wave kernel, every component in
+    // every lane of the row
+    b1t *= b1;
+    b2t *= b2;
+    const float ic1 = __builtin_amdgcn_rcpf(1.f - b1t), ic2 = __builtin_amdgcn_rcpf(1.f - b2t);
+    float xn[7];
+#pragma unroll
+    for (int c = 0; c < 7; ++c) {
+      const float gc = -g[c];
+      m[c] = fmaf(b1, m[c], (1.f - b1) * gc);
+      v[c] = fmaf(b2, v[c], (1.f - b2) * gc * gc);
+      const float den = __builtin_amdgcn_sqrtf(v[c] * ic2) + eps;
+      xn[c] = x[c] - a.lr * (m[c] * ic1) * __builtin_amdgcn_rcpf(den);
+    }
+    const float inv = rsqrtf(xn[0] * xn[0] + xn[1] * xn[1] + xn[2] * xn[2] + xn[3] * xn[3]);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) x[c] = xn[c] * inv;
+#pragma unroll
+    for (int c = 4; c < 7; ++c) x[c] = xn[c];
+  }
+  if (live && l16 == 0) {
+#pragma unroll
+    for (int c = 0; c < 7; ++c) ps[c] = x[c];
+    a.T[item] = T;
+    if (a.grad)
+#pragma unroll
+      for (int c = 0; c < 7; ++c) a.grad[item * 7 + c] = g[c];
+  }
+}
+
 // Best start per pair (largest T; lowest index on ties; NaN never wins):
 // its pose and T.
 __global__ void k_best_pose(const float* __restrict__ T, const float* __restrict__ pose,
@@ -514,10 +709,44 @@ size_t fo_align_lds_bytes(int max_a, int max_b) {
   return (size_t)(max_a + 2 * max_b) * sizeof(float4);
 }
 
+// Row-layout launch shape: rows (starts) per workgroup and its LDS bytes, or
+// 0 when the row kernel does not apply (A over 64 atoms, or LDS beyond
+// kFoRowsLdsMax) and the one-start-per-wave kernel runs instead.
+static int fo_rows_per_block(int n_starts) {
+  return n_starts >= kFoRowsStarts ? kFoRowsStarts : ((n_starts + 3) / 4) * 4;
+}
+static size_t fo_rows_lds_bytes(int max_a, int max_b, int n_starts) {
+  const int ra = (max_a + 15) / 16;
+  if (ra > 4) return 0;
+  const size_t bytes = (size_t)(max_a + max_b) * sizeof(float4) +
+                       (size_t)fo_rows_per_block(n_starts) * fo_rows_stride(max_b) *
+                           sizeof(float4) +
+                       (size_t)ra * 16 * max_b * sizeof(float2);
+  return bytes <= kFoRowsLdsMax ? bytes : 0;
+}
+
+template <int RA>
+static void launch_fo_rows_t(const FoAlignArgs& a, size_t lds, hipStream_t st) {
+  const int rows = fo_rows_per_block(a.n_starts);
+  const int blocks_y = (a.n_starts + kFoRowsStarts - 1) / kFoRowsStarts;
+  hipLaunchKernelGGL((k_fo_align_rows<RA>), dim3((unsigned)a.B.n_mols, (unsigned)blocks_y),
+                     dim3(rows / 4 * kWave), lds, st, a);
+}
+
 hipError_t launch_fo_align(const MolsDev& A, const MolsDev& B, const int* badA, const int* badB,
                            int n_starts, int n_steps, float lr, float* pose, float* T,
                            float* grad, hipStream_t st) {
   FoAlignArgs a{A, B, badA, badB, n_starts, n_steps, lr, pose, T, grad};
+  const size_t lds = fo_rows_lds_bytes(A.max_atoms, B.max_atoms, n_starts);
+  if (lds > 0) {
+    switch ((A.max_atoms + 15) / 16) {
+      case 1: launch_fo_rows_t<1>(a, lds, st); break;
+      case 2: launch_fo_rows_t<2>(a, lds, st); break;
+      case 3: launch_fo_rows_t<3>(a, lds, st); break;
+      default: launch_fo_rows_t<4>(a, lds, st); break;
+    }
+    return hipGetLastError();
+  }
   const int64_t items = (int64_t)B.n_mols * n_starts;
   hipLaunchKernelGGL(k_fo_align, dim3((unsigned)items), dim3(kWave),
                      fo_align_lds_bytes(A.max_atoms, B.max_atoms), st, a);

@@ -234,3 +234,33 @@ def test_ensemble_screen_takes_the_best_conformer(eng, aligned):
     assert np.array_equal(best, T.max(1))
     assert np.array_equal(ent, np.arange(40) * 4 + T.argmax(1))
     assert np.all(best >= T[:, 0])
+
+
+@pytest.mark.parametrize("a_atoms,n_starts", [((3, 16), 1), ((50, 64), 6), ((20, 30), 19),
+                                              ((70, 80), 5)])
+def test_every_launch_shape_matches_oracle(eng, a_atoms, n_starts):
+    """The alignment kernel's launch shapes: one start per 16-lane row with
+    A's atoms in 1 to 4 rows per lane (up to 16, 32, 48, 64 atoms), start
+    counts that leave spare rows or need a second workgroup (19 = 16 + 3),
+    and molecules past 64 atoms, which take the one-start-per-wave kernel.
+    T_FO and the gradient at the given poses, then 5 Adam steps, against the
+    oracle."""
+    A = molgen.library(64, 3, *a_atoms, workers=1)
+    B = molgen.library(65, 3, 10, 50, workers=1)
+    dA, dB = eng.molecules(A), eng.molecules(B)
+    poses = _poses(A.n_mols, n_starts, seed=11)
+    print(f"case: first-order alignment, A {a_atoms} atoms, {n_starts} starts", flush=True)
+    T, g = eng.shape_fo_align(dA, dB, torch.from_numpy(poses.copy()).cuda(), n_steps=0,
+                              need_grad=True)
+    T, g = T.cpu().numpy(), g.cpu().numpy()
+    dp = torch.from_numpy(poses.copy()).cuda()
+    T5, _ = eng.shape_fo_align(dA, dB, dp, n_steps=5, lr=0.05)
+    T5, p5 = T5.cpu().numpy(), dp.cpu().numpy()
+    for p in range(A.n_mols):
+        oa, ob = oracle_mol(O, A.mol(p)), oracle_mol(O, B.mol(p))
+        Tr, gr = O.fo_align_grad(oa, ob, poses[p].astype(np.float64))
+        assert np.abs(T[p] - Tr).max() <= 1e-5 * np.abs(Tr).max(), (p, T[p], Tr)
+        assert np.abs(g[p] - gr).max() <= 1e-4 * np.abs(gr).max(), (p, g[p], gr)
+        pr, Tr5 = O.fo_align_adam(oa, ob, poses[p].astype(np.float64), n_steps=5, lr=0.05)
+        assert np.abs(p5[p] - pr).max() <= 1e-3, (p, p5[p], pr)
+        assert np.abs(T5[p] - Tr5).max() <= 1e-4, (p, T5[p], Tr5)
