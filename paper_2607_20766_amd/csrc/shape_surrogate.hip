@@ -65,23 +65,36 @@ __device__ __forceinline__ float fo_term(float a, float b, float d2) {
 // The caller's arrays are read directly (no preparation pass): validity as
 // in the preparation (offsets in range, 1..max_atoms atoms, alpha > 0, all
 // values finite; otherwise NaN features and the data-error flag), and
-// Z = sum (pi/alpha_i)^(3/2) as an FP32 wave sum (a descriptor's scale, not
-// an estimate).
+// Z = sum (pi/alpha_i)^(3/2) as an FP32 sum (a descriptor's scale, not an
+// estimate).
+// One molecule per 16-lane row, four per wave: a drug-sized molecule fills
+// its row's lanes, and each sum is a 16-lane row sum (row_sum16, the same
+// bits in every lane of the row).  Histogram and width-class counts are
+// integer LDS atomics (exact, independent of their order).  The overlap
+// triangle i < j is flattened over the row's 16 lanes.
+constexpr int kFeatRows = 4;
+
 __global__ __launch_bounds__(64) void k_features(MolsDev in, int* __restrict__ flag,
                                                  float* __restrict__ out,
                                                  float* __restrict__ mom) {
-  __shared__ float4 sC[SHAPE_MAX_ATOMS];  // x, y, z, alpha
-  const int mol = xcd_chunk(blockIdx.x, gridDim.x);  // grid = n_mols
-  const int lane = threadIdx.x;
-  if (mol >= in.n_mols) return;
-  float* f = out + (size_t)mol * 24;
-  const int a0 = in.off[mol], a1 = in.off[mol + 1];
-  const int n = a1 - a0;
-  const bool range_bad = !(a0 >= 0 && (int64_t)a1 <= in.n_atoms && n >= 1 && n <= in.max_atoms);
-  const int n_ok = range_bad ? 0 : n;  // <= SHAPE_MAX_ATOMS
-  bool bad = range_bad;
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int sCount[kFeatRows][20];  // 16 radial bins, 4 width classes
+  const int lane = threadIdx.x, l16 = lane & 15, row = lane >> 4;
+  const int mol = xcd_chunk(blockIdx.x, gridDim.x) * kFeatRows + row;
+  float4* sC = reinterpret_cast<float4*>(smem) + (size_t)row * in.max_atoms;  // x, y, z, alpha
+  const bool live = mol < in.n_mols;
+  int a0 = 0, n = 0;
+  bool bad = false;
+  if (live) {
+    a0 = in.off[mol];
+    const int a1 = in.off[mol + 1];
+    n = a1 - a0;
+    bad = !(a0 >= 0 && (int64_t)a1 <= in.n_atoms && n >= 1 && n <= in.max_atoms);
+    if (bad) n = 0;
+  }
+  for (int k = l16; k < 20; k += 16) sCount[row][k] = 0;
   float zl = 0.f;
-  for (int i = lane; i < n_ok; i += kWave) {
+  for (int i = l16; i < n; i += 16) {
     const float al = in.alpha[a0 + i];
     const float x = in.xyz[3 * (a0 + i)], y = in.xyz[3 * (a0 + i) + 1],
                 z = in.xyz[3 * (a0 + i) + 2];
@@ -91,62 +104,49 @@ __global__ __launch_bounds__(64) void k_features(MolsDev in, int* __restrict__ f
     const float t = 3.14159265358979f * __builtin_amdgcn_rcpf(al);
     zl += t * __builtin_amdgcn_sqrtf(t);
   }
-  if (__ballot(bad) != 0) {
-    for (int k = lane; k < 24; k += kWave) f[k] = __builtin_nanf("");
-    if (lane < 6) mom[(size_t)mol * 6 + lane] = __builtin_nanf("");
-    if (lane == 0) atomicOr(flag, 1);
-    return;
-  }
+  // a row is bad if any of its lanes saw bad data: OR over the row's bits
+  const uint64_t bb = __ballot(bad);
+  bad = ((bb >> (16 * row)) & 0xFFFFull) != 0;
+  if (bad) n = 0;  // the row skips every pass and writes NaN below
   wave_lds_sync();
-  const float iZ = 1.0f / wave_sum_dpp(zl);
+  const float iZ = 1.0f / row_sum16(zl);
   // pass 1: mixture mean
   float mx = 0.f, my = 0.f, mz = 0.f;
-  for (int i = lane; i < n; i += kWave) {
+  for (int i = l16; i < n; i += 16) {
     const float4 c = sC[i];
     // descriptors, not estimates: hardware reciprocal and square root (1 ulp)
     const float t = 3.14159265358979f * __builtin_amdgcn_rcpf(c.w);
     const float pi = t * __builtin_amdgcn_sqrtf(t) * iZ;
     mx = fmaf(pi, c.x, mx); my = fmaf(pi, c.y, my); mz = fmaf(pi, c.z, mz);
   }
-  mx = wave_sum_dpp(mx); my = wave_sum_dpp(my); mz = wave_sum_dpp(mz);
+  mx = row_sum16(mx); my = row_sum16(my); mz = row_sum16(mz);
   // pass 2: centred second moments, radial histogram, width classes
   float sxx = 0.f, syy = 0.f, szz = 0.f, sxy = 0.f, sxz = 0.f, syz = 0.f;
-  int hist_mine = 0, cls_mine = 0;  // lane b < 16 keeps bin b, lane c < 4 class c
-  for (int base = 0; base < n; base += kWave) {
-    const int i = base + lane;
-    int bin = -1, cls = -1;
-    if (i < n) {
-      const float4 c = sC[i];
-      const float ia = __builtin_amdgcn_rcpf(c.w);
-      const float t = 3.14159265358979f * ia;
-      const float pi = t * __builtin_amdgcn_sqrtf(t) * iZ;
-      const float x = c.x - mx, y = c.y - my, z = c.z - mz, h = 0.5f * ia;
-      sxx = fmaf(pi, fmaf(x, x, h), sxx); syy = fmaf(pi, fmaf(y, y, h), syy);
-      szz = fmaf(pi, fmaf(z, z, h), szz);
-      sxy = fmaf(pi * x, y, sxy); sxz = fmaf(pi * x, z, sxz); syz = fmaf(pi * y, z, syz);
-      const float r = __builtin_amdgcn_sqrtf(fmaf(x, x, fmaf(y, y, z * z)));
-      bin = (int)floorf(r * 2.0f);
-      bin = bin > 15 ? 15 : bin;
-      cls = c.w < 0.767f ? 0 : (c.w < 0.893f ? 1 : (c.w < 0.995f ? 2 : 3));
-    }
-    for (int b = 0; b < 16; ++b) {
-      const int cnt = __popcll(__ballot(bin == b));
-      if (lane == b) hist_mine += cnt;
-    }
-    for (int b = 0; b < 4; ++b) {
-      const int cnt = __popcll(__ballot(cls == b));
-      if (lane == b) cls_mine += cnt;
-    }
+  for (int i = l16; i < n; i += 16) {
+    const float4 c = sC[i];
+    const float ia = __builtin_amdgcn_rcpf(c.w);
+    const float t = 3.14159265358979f * ia;
+    const float pi = t * __builtin_amdgcn_sqrtf(t) * iZ;
+    const float x = c.x - mx, y = c.y - my, z = c.z - mz, h = 0.5f * ia;
+    sxx = fmaf(pi, fmaf(x, x, h), sxx); syy = fmaf(pi, fmaf(y, y, h), syy);
+    szz = fmaf(pi, fmaf(z, z, h), szz);
+    sxy = fmaf(pi * x, y, sxy); sxz = fmaf(pi * x, z, sxz); syz = fmaf(pi * y, z, syz);
+    const float r = __builtin_amdgcn_sqrtf(fmaf(x, x, fmaf(y, y, z * z)));
+    int bin = (int)floorf(r * 2.0f);
+    bin = bin > 15 ? 15 : bin;
+    const int cls = c.w < 0.767f ? 0 : (c.w < 0.893f ? 1 : (c.w < 0.995f ? 2 : 3));
+    atomicAdd(&sCount[row][bin], 1);
+    atomicAdd(&sCount[row][16 + cls], 1);
   }
-  sxx = wave_sum_dpp(sxx); syy = wave_sum_dpp(syy); szz = wave_sum_dpp(szz);
-  sxy = wave_sum_dpp(sxy); sxz = wave_sum_dpp(sxz); syz = wave_sum_dpp(syz);
+  sxx = row_sum16(sxx); syy = row_sum16(syy); szz = row_sum16(szz);
+  sxy = row_sum16(sxy); sxz = row_sum16(sxz); syz = row_sum16(syz);
   // first-order self-overlap: diagonal + 2 x the i < j triangle, flattened
   float fo = 0.f;
-  for (int i = lane; i < n; i += kWave) fo += fo_term(sC[i].w, sC[i].w, 0.f);
-  // strict upper triangle i < j in row-major order, flat index p = lane +
-  // 64 t: the first position from the row lengths, then stepped by 64
+  for (int i = l16; i < n; i += 16) fo += fo_term(sC[i].w, sC[i].w, 0.f);
+  // strict upper triangle i < j in row-major order, flat index p = l16 +
+  // 16 t: the first position from the row lengths, then stepped by 16
   // (row i holds j = i+1 .. n-1)
-  int i = 0, j = 1 + lane;
+  int i = 0, j = 1 + l16;
   while (i < n - 1 && j >= n) {
     j -= n - i - 2;  // j - n + (i + 2): onto the next row
     ++i;
@@ -155,19 +155,28 @@ __global__ __launch_bounds__(64) void k_features(MolsDev in, int* __restrict__ f
     const float4 ci = sC[i], cj = sC[j];
     const float dx = ci.x - cj.x, dy = ci.y - cj.y, dz = ci.z - cj.z;
     fo = fmaf(2.0f, fo_term(ci.w, cj.w, fmaf(dx, dx, fmaf(dy, dy, dz * dz))), fo);
-    j += kWave;
+    j += 16;
     while (i < n - 1 && j >= n) {
       j -= n - i - 2;
       ++i;
     }
   }
-  const float fo_sum = wave_sum_dpp(fo);
-  if (lane < 16) f[lane] = (float)hist_mine;
-  if (lane < 4) f[19 + lane] = (float)cls_mine;
-  // the covariance goes to k_features_eigen, which diagonalises one matrix
-  // per lane rather than one per wave
+  const float fo_sum = row_sum16(fo);
+  wave_lds_sync();  // the counts are complete
+  if (!live) return;
+  float* f = out + (size_t)mol * 24;
   float* mm = mom + (size_t)mol * 6;
-  if (lane == 0) {
+  if (bad) {
+    for (int k = l16; k < 24; k += 16) f[k] = __builtin_nanf("");
+    if (l16 < 6) mm[l16] = __builtin_nanf("");
+    if (l16 == 0) atomicOr(flag, 1);
+    return;
+  }
+  f[l16] = (float)sCount[row][l16];
+  if (l16 < 4) f[19 + l16] = (float)sCount[row][16 + l16];
+  // the covariance goes to k_features_eigen, which diagonalises one matrix
+  // per lane rather than one per row
+  if (l16 == 0) {
     mm[0] = sxx; mm[1] = syy; mm[2] = szz;
     mm[3] = sxy; mm[4] = sxz; mm[5] = syz;
     f[23] = fo_sum;
@@ -983,8 +992,10 @@ __global__ __launch_bounds__(256) void k_select_write(const float* __restrict__ 
 // ---------------------------------------------------------------------------
 hipError_t launch_features(const MolsDev& M, int* flag, float* out, float* mom,
                            hipStream_t st) {
-  hipLaunchKernelGGL(k_features, dim3((unsigned)M.n_mols), dim3(kWave), 0, st, M, flag, out,
-                     mom);
+  if (M.n_mols <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_features, dim3((unsigned)((M.n_mols + kFeatRows - 1) / kFeatRows)),
+                     dim3(kWave), (size_t)kFeatRows * M.max_atoms * sizeof(float4), st, M, flag,
+                     out, mom);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_features_eigen, dim3((unsigned)((M.n_mols + 255) / 256)), dim3(256), 0,
