@@ -141,8 +141,9 @@ __global__ __launch_bounds__(kAlignThreads) void k_align(AlignArgs a) {
         moved.y = fmaf(R[3], at.x, fmaf(R[4], at.y, fmaf(R[5], at.z, ty)));
         moved.z = fmaf(R[6], at.x, fmaf(R[7], at.y, fmaf(R[8], at.z, tz)));
         make_rec(moved, 0.f, 0.f, 0.f, wR[i], wa[i]);
-        // 2 alpha = 2 a2 ln 2
-        wC[i] = make_float4(moved.x, moved.y, moved.z, 2.0f * 0.693147180559945309f * at.a2);
+        // 2 alpha_j (c''_j, 1), with 2 alpha = 2 a2 ln 2
+        const float two_al = 2.0f * 0.693147180559945309f * at.a2;
+        wC[i] = make_float4(two_al * moved.x, two_al * moved.y, two_al * moved.z, two_al);
       }
       wave_lds_sync();
       float accO = 0.f, gtx = 0.f, gty = 0.f, gtz = 0.f, grx = 0.f, gry = 0.f, grz = 0.f;
@@ -167,14 +168,14 @@ __global__ __launch_bounds__(kAlignThreads) void k_align(AlignArgs a) {
           const float4 cj = wC[j];
 #pragma unroll
           for (int s = 0; s < kAS; ++s) {
+            // S <- S (1 - o) + o P c  written as  S + o (c P - S): two fused
+            // operations per component, and P <- P - o P
             const float oj = occupancy_x(b, aj, rx[s], ry[s], rz[s], r2[s]);
-            const float omo = 1.f - oj;
-            const float gp = cj.w * oj * P[s];
-            S0[s] = fmaf(S0[s], omo, gp);
-            Sx[s] = fmaf(Sx[s], omo, gp * cj.x);
-            Sy[s] = fmaf(Sy[s], omo, gp * cj.y);
-            Sz[s] = fmaf(Sz[s], omo, gp * cj.z);
-            P[s] *= omo;
+            S0[s] = fmaf(oj, fmaf(cj.w, P[s], -S0[s]), S0[s]);
+            Sx[s] = fmaf(oj, fmaf(cj.x, P[s], -Sx[s]), Sx[s]);
+            Sy[s] = fmaf(oj, fmaf(cj.y, P[s], -Sy[s]), Sy[s]);
+            Sz[s] = fmaf(oj, fmaf(cj.z, P[s], -Sz[s]), Sz[s]);
+            P[s] = fmaf(-oj, P[s], P[s]);
           }
         }
 #pragma unroll
