@@ -727,14 +727,15 @@ size_t fo_align_lds_bytes(int max_a, int max_b) {
 }
 
 // Row-layout launch shape: rows (starts) per workgroup and its LDS bytes, or
-// 0 when the row kernel does not apply (A over 64 atoms, or LDS beyond
-// kFoRowsLdsMax) and the one-start-per-wave kernel runs instead.
+// 0 when the row kernel does not apply (A over 64 atoms, LDS beyond
+// kFoRowsLdsMax, or more start blocks than a grid's y extent) and the
+// one-start-per-wave kernel runs instead.
 static int fo_rows_per_block(int n_starts) {
   return n_starts >= kFoRowsStarts ? kFoRowsStarts : ((n_starts + 3) / 4) * 4;
 }
 static size_t fo_rows_lds_bytes(int max_a, int max_b, int n_starts) {
   const int ra = (max_a + 15) / 16;
-  if (ra > 4) return 0;
+  if (ra > 4 || (n_starts + kFoRowsStarts - 1) / kFoRowsStarts > 65535) return 0;
   const size_t bytes = (size_t)(max_a + max_b) * sizeof(float4) +
                        (size_t)fo_rows_per_block(n_starts) * fo_rows_stride(max_b) *
                            sizeof(float4) +

@@ -52,15 +52,9 @@ __device__ void sym3_eigen_desc(double a00, double a11, double a22, double a01, 
       }
 }
 
-// (pi / (a + b))^(3/2) exp(-a b / (a + b) d2): rs = 1/sqrt(a + b) gives
-// (pi/(a+b))^(3/2) = pi^(3/2) rs^3 and 1/(a+b) = rs^2 from one hardware
-// rsqrt; exp by exp2 (a feature, not an estimate: ~1e-6 relative).
-__device__ __forceinline__ float fo_term(float a, float b, float d2) {
-  const float rs = __builtin_amdgcn_rsqf(a + b);
-  const float ir = rs * rs;
-  return 5.56832799683170785f * ir * rs *
-         __builtin_amdgcn_exp2f(-1.44269504088896f * a * b * ir * d2);
-}
+// First-order Gaussian pair terms (pi/(a+b))^(3/2) exp(-a b/(a+b) d2) below:
+// rs = 1/sqrt(a+b) from one hardware rsqrt gives (a+b)^(-3/2) = rs^3 and
+// 1/(a+b) = rs^2; exp by exp2 (features, not estimates: ~1e-6 relative).
 
 // The caller's arrays are read directly (no preparation pass): validity as
 // in the preparation (offsets in range, 1..max_atoms atoms, alpha > 0, all
@@ -140,9 +134,14 @@ __global__ __launch_bounds__(64) void k_features(MolsDev in, int* __restrict__ f
   }
   sxx = row_sum16(sxx); syy = row_sum16(syy); szz = row_sum16(szz);
   sxy = row_sum16(sxy); sxz = row_sum16(sxz); syz = row_sum16(syz);
-  // first-order self-overlap: diagonal + 2 x the i < j triangle, flattened
-  float fo = 0.f;
-  for (int i = l16; i < n; i += 16) fo += fo_term(sC[i].w, sC[i].w, 0.f);
+  // first-order self-overlap: diagonal + 2 x the i < j triangle, flattened.
+  // Terms are summed as (a+b)^(-3/2) exp(-ab/(a+b) d2); pi^(3/2) and the
+  // triangle's factor 2 are applied to the row sums.
+  float fo = 0.f, tri = 0.f;
+  for (int i = l16; i < n; i += 16) {
+    const float a = sC[i].w, rs = __builtin_amdgcn_rsqf(a + a);
+    fo = fmaf(rs * rs, rs, fo);
+  }
   // strict upper triangle i < j in row-major order, flat index p = l16 +
   // 16 t: the first position from the row lengths, then stepped by 16
   // (row i holds j = i+1 .. n-1)
@@ -154,14 +153,18 @@ __global__ __launch_bounds__(64) void k_features(MolsDev in, int* __restrict__ f
   while (i < n - 1) {
     const float4 ci = sC[i], cj = sC[j];
     const float dx = ci.x - cj.x, dy = ci.y - cj.y, dz = ci.z - cj.z;
-    fo = fmaf(2.0f, fo_term(ci.w, cj.w, fmaf(dx, dx, fmaf(dy, dy, dz * dz))), fo);
+    const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+    const float rs = __builtin_amdgcn_rsqf(ci.w + cj.w);
+    const float ir = rs * rs;
+    const float e = __builtin_amdgcn_exp2f((-1.44269504088896f * ci.w) * cj.w * ir * d2);
+    tri = fmaf(ir * rs, e, tri);
     j += 16;
     while (i < n - 1 && j >= n) {
       j -= n - i - 2;
       ++i;
     }
   }
-  const float fo_sum = row_sum16(fo);
+  const float fo_sum = 5.56832799683170785f * (row_sum16(fo) + 2.0f * row_sum16(tri));
   wave_lds_sync();  // the counts are complete
   if (!live) return;
   float* f = out + (size_t)mol * 24;
@@ -230,7 +233,7 @@ __global__ __launch_bounds__(kWave * kFoWaves) void k_fo_cross(
       const float x = Q.xyz[3 * (q0 + i)], y = Q.xyz[3 * (q0 + i) + 1],
                   z = Q.xyz[3 * (q0 + i) + 2];
       if (!atom_ok(al, x, y, z)) q_bad = 1;
-      sA[i] = make_float4(x, y, z, al);
+      sA[i] = make_float4(x, y, z, 1.44269504088896f * al);
     }
   }
   // reached by every wave (no return before it); the outcome is grid-uniform
@@ -257,7 +260,7 @@ __global__ __launch_bounds__(kWave * kFoWaves) void k_fo_cross(
       const float x = L.xyz[3 * (b0 + j)], y = L.xyz[3 * (b0 + j) + 1],
                   z = L.xyz[3 * (b0 + j) + 2];
       if (!atom_ok(al, x, y, z)) a_bad = true;
-      sB[j] = make_float4(x, y, z, al);
+      sB[j] = make_float4(x, y, z, 1.44269504088896f * al);
     }
   }
   const bool data_bad = __ballot(a_bad) != 0;
@@ -272,11 +275,18 @@ __global__ __launch_bounds__(kWave * kFoWaves) void k_fo_cross(
   wave_lds_sync();
   const int di = kWave / nb, dj = kWave % nb;
   int i = lane / nb, j = lane % nb;
+  // With widths a' = log2(e) a in LDS, s = a'_i + a'_j = log2(e) (a_i + a_j):
+  // a'_i a'_j / s = log2(e) a_i a_j / (a_i + a_j), the exp2 exponent per unit
+  // d2, and s^(-3/2) = log2(e)^(-3/2) (a_i + a_j)^(-3/2); the constant
+  // (pi log2(e))^(3/2) is applied to the wave sum.
   float acc = 0.0f;
   for (; i < nq;) {
     const float4 ci = sA[i], cj = sB[j];
     const float dx = ci.x - cj.x, dy = ci.y - cj.y, dz = ci.z - cj.z;
-    acc += fo_term(ci.w, cj.w, fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
+    const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+    const float rs = __builtin_amdgcn_rsqf(ci.w + cj.w);
+    const float ir = rs * rs;
+    acc = fmaf(ir * rs, __builtin_amdgcn_exp2f(-(ci.w * cj.w * ir * d2)), acc);
     i += di;
     j += dj;
     if (j >= nb) {
@@ -284,7 +294,7 @@ __global__ __launch_bounds__(kWave * kFoWaves) void k_fo_cross(
       ++i;
     }
   }
-  const float s = wave_sum_dpp(acc);
+  const float s = 9.64909578231936f * wave_sum_dpp(acc);  // (pi log2(e))^(3/2)
   if (lane == 0) out[p] = s;
 }
 
