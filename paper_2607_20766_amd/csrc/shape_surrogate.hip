@@ -347,6 +347,8 @@ typedef short v4s __attribute__((ext_vector_type(4)));
 typedef short v8s __attribute__((ext_vector_type(8)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef float v2f __attribute__((ext_vector_type(2)));
+typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
 
 // D += A B for a 16 x 32 by 32 x 16 BF16 tile on v_mfma_f32_16x16x32_bf16:
 // lane l supplies row (or column) l mod 16 and k = 8 (l / 16) .. 8 (l / 16) + 7
@@ -361,6 +363,12 @@ __device__ __forceinline__ short to_bf16(float x) {
   if ((u & 0x7F800000u) == 0x7F800000u) return (short)(u >> 16);  // inf / nan
   u += 0x7FFFu + ((u >> 16) & 1u);
   return (short)(u >> 16);
+}
+
+// Two floats to packed bf16 (x in the low half) by gfx950's
+// v_cvt_pk_bf16_f32: round to nearest even, as to_bf16 for finite values.
+__device__ __forceinline__ uint32_t to_bf16x2(float x, float y) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector((v2f{x, y}), v2bf));
 }
 
 // FP32 products (tight-parity mode): operands read straight from global
@@ -661,14 +669,17 @@ __global__ __launch_bounds__(256, 2) void k_mlp_infer(MlpArgs a) {
 #pragma unroll
       for (int t = 0; t < 48; ++t) raw[t] = 0.0f;
     }
-    v4s* dst = reinterpret_cast<v4s*>(&H[r * kMlpLd + 48 * h]);
+    uint2* dst = reinterpret_cast<uint2*>(&H[r * kMlpLd + 48 * h]);
 #pragma unroll
     for (int c = 0; c < 12; ++c)
-      dst[c] = v4s{to_bf16(raw[4 * c]), to_bf16(raw[4 * c + 1]), to_bf16(raw[4 * c + 2]),
-                   to_bf16(raw[4 * c + 3])};
+      dst[c] = make_uint2(to_bf16x2(raw[4 * c], raw[4 * c + 1]),
+                          to_bf16x2(raw[4 * c + 2], raw[4 * c + 3]));
   }
   __syncthreads();
   // three hidden layers: wave w computes all 128 rows x columns [64 w, 64 w + 64)
+  // as the transposed product (weights as the A operand, activations as B),
+  // so a lane's four results are four consecutive columns of one row: one
+  // 8-byte LDS store each after bias, ReLU and a packed bf16 conversion
 #pragma unroll 1
   for (int l = 0; l < 3; ++l) {
     const int kbs = (l == 0 ? kMlpIn : kMlpHid) / 32;
@@ -696,22 +707,26 @@ __global__ __launch_bounds__(256, 2) void k_mlp_infer(MlpArgs a) {
 #pragma unroll
       for (int i = 0; i < 8; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = mfma_bf16_k32(x[i], b[j], acc[i][j]);
+        for (int j = 0; j < 4; ++j) acc[i][j] = mfma_bf16_k32(b[j], x[i], acc[i][j]);
     }
     __syncthreads();  // every wave has read this layer's input
     const float* bias = a.b[l];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int col = wave * 64 + 16 * j + li;
-      const float bc = bias[col];
+      // lane (li, lk) holds row 16 i + li, columns col0 .. col0 + 3
+      const int col0 = wave * 64 + 16 * j + 4 * lk;
+      const float4 bc = make_float4(bias[col0], bias[col0 + 1], bias[col0 + 2], bias[col0 + 3]);
 #pragma unroll
-      for (int i = 0; i < 8; ++i)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          float v = acc[i][j][r] + bc;
-          v = v > 0.f ? v : 0.f;
-          H[(16 * i + 4 * lk + r) * kMlpLd + col] = to_bf16(v);
-        }
+      for (int i = 0; i < 8; ++i) {
+        float v0 = acc[i][j][0] + bc.x, v1 = acc[i][j][1] + bc.y;
+        float v2 = acc[i][j][2] + bc.z, v3 = acc[i][j][3] + bc.w;
+        v0 = v0 > 0.f ? v0 : 0.f;
+        v1 = v1 > 0.f ? v1 : 0.f;
+        v2 = v2 > 0.f ? v2 : 0.f;
+        v3 = v3 > 0.f ? v3 : 0.f;
+        *reinterpret_cast<uint2*>(&H[(16 * i + li) * kMlpLd + col0]) =
+            make_uint2(to_bf16x2(v0, v1), to_bf16x2(v2, v3));
+      }
     }
     __syncthreads();
   }
