@@ -462,6 +462,22 @@ int shape_mlp_infer(shape_ctx* ctx, const float* f_q, const float* f_lib,
                     const float* fo_cross, const float* mean, const float* inv_std,
                     const float* params, void* stream, float* out);
 
+/* Training forward of the surrogate: shape_mlp_infer (same arguments,
+ * same bits in out) that also writes what the backward pass reads — the
+ * standardised pair features x (device float [n][96], the values of
+ * shape_pair_features) and the hidden activations after ReLU h1, h2, h3
+ * (device float [n][256] each, FP32: the outputs the per-layer BF16
+ * shape_gemm calls would have written).  One kernel instead of five
+ * launches per minibatch.  x, h1, h2, h3 must be 16-byte aligned.
+ * Uses context scratch for the weights packed to BF16.  Asynchronous.
+ * Errors: SHAPE_E_INVAL (NULL or misaligned array), SHAPE_E_RANGE,
+ * SHAPE_E_NOMEM, SHAPE_E_HIP. */
+int shape_mlp_forward(shape_ctx* ctx, const float* f_q, const float* f_lib,
+                      const int32_t* qidx, const int32_t* idx, int32_t n,
+                      const float* fo_cross, const float* mean, const float* inv_std,
+                      const float* params, void* stream, float* x, float* h1, float* h2,
+                      float* h3, float* out);
+
 #define SHAPE_GEMM_BF16 1u  /* round A and B to bfloat16 (else FP32 operands) */
 #define SHAPE_GEMM_RELU 2u  /* epilogue ReLU after the bias */
 

@@ -997,6 +997,34 @@ int shape_mlp_infer(shape_ctx* c, const float* f_q, const float* f_lib, const in
   }
 }
 
+int shape_mlp_forward(shape_ctx* c, const float* f_q, const float* f_lib, const int32_t* qidx,
+                      const int32_t* idx, int32_t n, const float* fo_cross, const float* mean,
+                      const float* inv_std, const float* params, void* stream, float* x,
+                      float* h1, float* h2, float* h3, float* out) {
+  if (!c) return SHAPE_E_INVAL;
+  try {
+    if (n < 0) return fail(c, SHAPE_E_RANGE, "n < 0");
+    if (n == 0) return SHAPE_OK;
+    if (!f_q || !f_lib || !mean || !inv_std || !params || !out || !x || !h1 || !h2 || !h3)
+      return fail(c, SHAPE_E_INVAL, "NULL array");
+    if ((((uintptr_t)x) | ((uintptr_t)h1) | ((uintptr_t)h2) | ((uintptr_t)h3)) & 15u)
+      return fail(c, SHAPE_E_INVAL, "x, h1, h2, h3 must be 16-byte aligned");
+    int rc = set_device(c);
+    if (rc) return rc;
+    void* packed;
+    if ((rc = ensure(c, S_MLP_PACK, shape::mlp_pack_bytes(), &packed))) return rc;
+    float* const h[3] = {h1, h2, h3};
+    KernelTimer timer(c, (hipStream_t)stream);
+    HIP_TRY(c, shape::launch_mlp_infer(f_q, f_lib, qidx, idx, n, fo_cross, mean, inv_std, params,
+                                       packed, out, (hipStream_t)stream, x, h),
+            "surrogate forward kernel");
+    timer.stop();
+    return SHAPE_OK;
+  } catch (...) {
+    return fail(c, SHAPE_E_HIP, "internal error");
+  }
+}
+
 int shape_seed_budget(shape_ctx* c, const float* raw, int64_t ld, const int32_t* idx, int32_t k,
                       double y_mean, double y_std, double tau, int32_t round_per_pair,
                       int32_t cap_per_pair, void* stream, int32_t* n_start) {

@@ -150,7 +150,8 @@ hipError_t launch_seed_budget(const float* raw, int64_t ld, const int* idx, int 
 hipError_t launch_mlp_infer(const float* fq, const float* flib, const int* qidx, const int* idx,
                             int n, const float* fo_cross, const float* mean,
                             const float* inv_std, const float* params, void* packed,
-                            float* out, hipStream_t st);
+                            float* out, hipStream_t st, float* x_out = nullptr,
+                            float* const* h_out = nullptr);
 int colsum_chunks(int M);
 hipError_t launch_colsum(const float* A, int M, int N, int64_t lda, float* part, float* out,
                          hipStream_t st);

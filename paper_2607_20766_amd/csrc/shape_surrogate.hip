@@ -616,8 +616,14 @@ struct MlpArgs {
   const v8s* W;        // packed weights (kMlpPackElems bf16)
   const float* b[4];   // biases of the four layers
   float* out;          // [n][2]
+  float* x_out;        // training forward: standardised features [n][96]
+  float* h_out[3];     // and the hidden activations [n][256] (FP32, after ReLU)
 };
 
+// kAct (training forward): the FP32 standardised features and hidden
+// activations are also written out (the backward's inputs), the same values
+// that shape_pair_features and the per-layer products would have written.
+template <bool kAct>
 __global__ __launch_bounds__(256, 2) void k_mlp_infer(MlpArgs a) {
   __shared__ __align__(16) short H[kMlpRows * kMlpLd];
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
@@ -665,6 +671,12 @@ __global__ __launch_bounds__(256, 2) void k_mlp_infer(MlpArgs a) {
       const float* is = a.inv_std + 48 * h;
 #pragma unroll
       for (int t = 0; t < 48; ++t) raw[t] = (raw[t] - mu[t]) * is[t];
+      if (kAct) {
+        float4* xo = reinterpret_cast<float4*>(a.x_out + (size_t)p * kMlpIn + 48 * h);
+#pragma unroll
+        for (int c = 0; c < 12; ++c)
+          xo[c] = make_float4(raw[4 * c], raw[4 * c + 1], raw[4 * c + 2], raw[4 * c + 3]);
+      }
     } else {
 #pragma unroll
       for (int t = 0; t < 48; ++t) raw[t] = 0.0f;
@@ -726,6 +738,9 @@ __global__ __launch_bounds__(256, 2) void k_mlp_infer(MlpArgs a) {
         v3 = v3 > 0.f ? v3 : 0.f;
         *reinterpret_cast<uint2*>(&H[(16 * i + li) * kMlpLd + col0]) =
             make_uint2(to_bf16x2(v0, v1), to_bf16x2(v2, v3));
+        if (kAct && row0 + 16 * i + li < a.n)
+          *reinterpret_cast<float4*>(a.h_out[l] + (size_t)(row0 + 16 * i + li) * kMlpHid +
+                                     col0) = make_float4(v0, v1, v2, v3);
       }
     }
     __syncthreads();
@@ -1107,7 +1122,8 @@ size_t mlp_pack_bytes() { return (size_t)kMlpPackElems * sizeof(short); }
 hipError_t launch_mlp_infer(const float* fq, const float* flib, const int* qidx, const int* idx,
                             int n, const float* fo_cross, const float* mean,
                             const float* inv_std, const float* params, void* packed,
-                            float* out, hipStream_t st) {
+                            float* out, hipStream_t st, float* x_out,
+                            float* const* h_out) {
   hipLaunchKernelGGL(k_mlp_pack, dim3((kMlpPackElems + 255) / 256), dim3(256), 0, st, params,
                      (short*)packed);
   hipError_t e = hipGetLastError();
@@ -1131,8 +1147,13 @@ hipError_t launch_mlp_infer(const float* fq, const float* flib, const int* qidx,
     off += o_;
   }
   a.out = out;
-  hipLaunchKernelGGL(k_mlp_infer, dim3((unsigned)((n + kMlpRows - 1) / kMlpRows)), dim3(256), 0,
-                     st, a);
+  a.x_out = x_out;
+  for (int l = 0; l < 3; ++l) a.h_out[l] = h_out ? h_out[l] : nullptr;
+  const dim3 grid((unsigned)((n + kMlpRows - 1) / kMlpRows));
+  if (x_out)
+    hipLaunchKernelGGL(k_mlp_infer<true>, grid, dim3(256), 0, st, a);
+  else
+    hipLaunchKernelGGL(k_mlp_infer<false>, grid, dim3(256), 0, st, a);
   return hipGetLastError();
 }
 

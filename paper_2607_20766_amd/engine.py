@@ -136,6 +136,8 @@ def load_library():
         L.shape_features.argtypes = [vp, ctypes.POINTER(ShapeMols), vp, vp]
         L.shape_pair_features.argtypes = [vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp]
         L.shape_mlp_infer.argtypes = [vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp]
+        L.shape_mlp_forward.argtypes = [vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp,
+                                        vp, vp, vp]
         L.shape_fo_overlap.argtypes = [vp, ctypes.POINTER(ShapeMols), ctypes.POINTER(ShapeMols),
                                        vp, i32, vp, vp]
         L.shape_gemm.argtypes = [vp, i32, i32, i32, vp, i64, i64, vp, i64, i64, vp, i64, vp, vp,
@@ -534,6 +536,24 @@ class Engine:
             self._ctx, _ptr(f_q.contiguous()), _ptr(f_lib.contiguous()), _ptr(qidx), _ptr(idx),
             int(n), _ptr(fo_cross), _ptr(mean), _ptr(inv_std), _ptr(params), _stream(stream),
             _ptr(out)))
+        return out
+
+    def shape_mlp_forward(self, f_q, f_lib, mean, inv_std, params, x, h, out, idx=None,
+                          qidx=None, n=None, fo_cross=None, stream=None):
+        """Training forward: shape_mlp_infer's output in out [n, 2], plus the
+        standardised features x [n, 96] and hidden activations h[0..2]
+        [n, 256] (FP32, after ReLU) that the backward pass reads."""
+        if idx is not None:
+            idx = idx.to(torch.int32).contiguous()
+            n = idx.numel()
+        elif n is None:
+            n = f_lib.shape[0]
+        if qidx is not None:
+            qidx = qidx.to(torch.int32).contiguous()
+        self._check(load_library().shape_mlp_forward(
+            self._ctx, _ptr(f_q.contiguous()), _ptr(f_lib.contiguous()), _ptr(qidx), _ptr(idx),
+            int(n), _ptr(fo_cross), _ptr(mean), _ptr(inv_std), _ptr(params), _stream(stream),
+            _ptr(x), _ptr(h[0]), _ptr(h[1]), _ptr(h[2]), _ptr(out)))
         return out
 
     def shape_gemm(self, M, N, K, A, sam, sak, B, sbk, sbn, C, scm, bias=None, gate=None, sgm=0,

@@ -121,10 +121,16 @@ class MLP:
 
     def loss_grad(self, x, target, loss_weights):
         """Forward, weighted MSE and backward; returns the loss tensor [1]."""
-        y = self.forward(x)
+        self.forward(x)
+        return self.loss_grad_after_forward(x, target, loss_weights)
+
+    def loss_grad_after_forward(self, x, target, loss_weights):
+        """Weighted MSE and backward, given that the activation buffers of
+        batch x.shape[0] hold the forward of x (forward, or the fused
+        shape_mlp_forward); returns the loss tensor [1]."""
         buf = self._buffers(x.shape[0])
         dout = buf["d"][-1]
-        self.eng.shape_mse(y, target, loss_weights, dout, buf["loss"])
+        self.eng.shape_mse(buf["h"][-1], target, loss_weights, dout, buf["loss"])
         self.backward(x, dout)
         return buf["loss"]
 
@@ -206,13 +212,17 @@ class Triage:
     # -- training --------------------------------------------------------------------
     def train(self, f_q, f_lib, qidx: np.ndarray, midx: np.ndarray, Y: np.ndarray,
               fo: np.ndarray | None = None, epochs: int = 8, batch: int = 4096,
-              lr: float = 1e-3, seed: int = 0, log=None, graph: bool = True):
+              lr: float = 1e-3, seed: int = 0, log=None, graph: bool = True,
+              fused_forward: bool = True):
         """Minibatch Adam on the weighted MSE of standardised labels Y [n, 2].
 
         Each epoch's shuffled rows are copied into fixed device buffers, so
         after the first (eager) epoch the whole epoch of steps is captured
         once as a HIP graph and replayed (graph=True): identical kernels and
-        results, without a host round trip per launch."""
+        results, without a host round trip per launch.  fused_forward: each
+        minibatch's features and forward in one kernel (shape_mlp_forward,
+        BF16 network of the default widths), the same bits as the pair
+        features and one product per layer."""
         dev = self.eng.torch_device
         self.y_mean = Y.mean(0)
         self.y_std = Y.std(0)
@@ -229,13 +239,23 @@ class Triage:
         y_ep = torch.empty(rows, 2, dtype=torch.float32, device=dev)
         fo_ep = torch.empty(rows, dtype=torch.float32, device=dev) if self.use_fo else None
 
+        fused = fused_forward and self.mlp.bf16 and self.mlp.width == WIDTH
+
         def epoch_steps():
             for b in range(nb):
                 s, e = b * batch, (b + 1) * batch
-                self.eng.shape_pair_features(f_q, f_lib, self.mean, self.inv_std,
-                                             idx=m_ep[s:e], qidx=q_ep[s:e], out=xb,
-                                             fo_cross=None if fo_ep is None else fo_ep[s:e])
-                loss = self.mlp.loss_grad(xb, y_ep[s:e], lw)
+                fo_b = None if fo_ep is None else fo_ep[s:e]
+                if fused:
+                    acts = self.mlp._buffers(batch)["h"]
+                    self.eng.shape_mlp_forward(f_q, f_lib, self.mean, self.inv_std,
+                                               self.mlp.params, xb, acts[:3], acts[3],
+                                               idx=m_ep[s:e], qidx=q_ep[s:e], fo_cross=fo_b)
+                    loss = self.mlp.loss_grad_after_forward(xb, y_ep[s:e], lw)
+                else:
+                    self.eng.shape_pair_features(f_q, f_lib, self.mean, self.inv_std,
+                                                 idx=m_ep[s:e], qidx=q_ep[s:e], out=xb,
+                                                 fo_cross=fo_b)
+                    loss = self.mlp.loss_grad(xb, y_ep[s:e], lw)
                 self.mlp.adam_step(lr)
                 losses[b:b + 1].copy_(loss)
 

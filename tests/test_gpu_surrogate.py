@@ -229,6 +229,44 @@ def test_fused_inference_matches_layers(eng, n, with_fo, with_idx):
     assert y_fused.shape == (n, 2)
     assert torch.equal(y_fused, y_layers)
     assert torch.isfinite(y_fused).all()
+    # the training forward: same output, plus the features and activations
+    # that the layers wrote
+    h_layers = [h[:n].clone() for h in net._buffers(n)["h"][:3]]
+    xf = torch.full((n, 96), np.nan, device="cuda")
+    hf = [torch.full((n, 256), np.nan, device="cuda") for _ in range(3)]
+    yf = torch.full((n, 2), np.nan, device="cuda")
+    eng.shape_mlp_forward(fq, fl, mu, isd, net.params, xf, hf, yf, idx=idx, qidx=qidx, n=n,
+                          fo_cross=fo)
+    torch.cuda.synchronize()
+    assert torch.equal(yf, y_layers) and torch.equal(xf, x)
+    for l in range(3):
+        assert torch.equal(hf[l], h_layers[l]), l
+
+
+def test_training_with_fused_forward_equals_layers(eng):
+    """Training whose minibatch forward is one shape_mlp_forward kernel
+    gives the loss history and parameters of the per-layer path, bit for
+    bit (the backward reads identical activations)."""
+    rng = np.random.default_rng(23)
+    n_q, n_l, n = 3, 700, 5000
+    f_q = rng.normal(size=(n_q, 24)).astype(np.float32)
+    f_l = rng.normal(size=(n_l, 24)).astype(np.float32)
+    f_q[:, 23] = rng.uniform(50, 100, n_q)
+    f_l[:, 23] = rng.uniform(50, 100, n_l)
+    fq, fl = torch.from_numpy(f_q).cuda(), torch.from_numpy(f_l).cuda()
+    qi, mi = rng.integers(0, n_q, n), rng.integers(0, n_l, n)
+    Y = rng.normal(size=(n, 2))
+    FO = rng.uniform(1, 40, n)
+    res = []
+    for fused in (False, True):
+        print(f"case: training, fused forward={fused}", flush=True)
+        tr = Triage(eng, seed=4)
+        tr.fit_standardisation(fq, fl, qi, mi, fo=FO)
+        hist = tr.train(fq, fl, qi, mi, Y, fo=FO, epochs=2, batch=1024, lr=1e-3,
+                        fused_forward=fused)
+        res.append((hist, tr.mlp.params.cpu().numpy().copy()))
+    assert res[0][0] == res[1][0]
+    assert np.array_equal(res[0][1], res[1][1])
 
 
 def test_graph_training_equals_eager(eng):
