@@ -495,6 +495,16 @@ int shape_gemm(shape_ctx* ctx, int32_t M, int32_t N, int32_t K, const float* A, 
 int shape_colsum(shape_ctx* ctx, int32_t M, int32_t N, const float* A, int64_t lda,
                  float* out, void* stream);
 
+/* The column sums of n_mats (1..8) matrices in one launch: for t < n_mats,
+ * out[t][n] = sum_m A[t][m*lda[t] + n], m < M[t], n < N[t], each with the
+ * bits shape_colsum gives (the bias gradients of all layers of a backward
+ * pass at once).  M, N, A, lda, out: host arrays of n_mats entries; A[t] and
+ * out[t] device float.  Asynchronous.  Errors: SHAPE_E_INVAL (NULL),
+ * SHAPE_E_RANGE (n_mats, M or N out of range), SHAPE_E_HIP. */
+int shape_colsum_set(shape_ctx* ctx, int32_t n_mats, const int32_t* M, const int32_t* N,
+                     const float* const* A, const int64_t* lda, float* const* out,
+                     void* stream);
+
 /* Weighted mean squared error of predictions y against targets t (device
  * float [B][N]) with per-output weights w (device float [N]):
  * loss = sum_j w_j mean_b (y - t)^2 (device float [1]), grad = dloss/dy

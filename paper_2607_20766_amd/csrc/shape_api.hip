@@ -1080,6 +1080,27 @@ int shape_colsum(shape_ctx* c, int32_t M, int32_t N, const float* A, int64_t lda
   return SHAPE_OK;
 }
 
+int shape_colsum_set(shape_ctx* c, int32_t n_mats, const int32_t* M, const int32_t* N,
+                     const float* const* A, const int64_t* lda, float* const* out,
+                     void* stream) {
+  if (!c) return SHAPE_E_INVAL;
+  if (n_mats < 1 || n_mats > shape::kColSetMax)
+    return fail(c, SHAPE_E_RANGE, "n_mats must be in 1..%d", shape::kColSetMax);
+  if (!M || !N || !A || !lda || !out) return fail(c, SHAPE_E_INVAL, "NULL array");
+  int64_t blocks = 0;
+  for (int t = 0; t < n_mats; ++t) {
+    if (M[t] < 1 || N[t] < 1) return fail(c, SHAPE_E_RANGE, "M, N must be >= 1");
+    if (!A[t] || !out[t]) return fail(c, SHAPE_E_INVAL, "NULL array");
+    blocks += (N[t] + 15) / 16;
+  }
+  if (blocks > 0x7FFFFFFF) return fail(c, SHAPE_E_RANGE, "too many columns");
+  int rc = set_device(c);
+  if (rc) return rc;
+  HIP_TRY(c, shape::launch_colsum_set(n_mats, M, N, A, lda, out, (hipStream_t)stream),
+          "colsum kernel");
+  return SHAPE_OK;
+}
+
 int shape_mse(shape_ctx* c, int32_t B, int32_t N, const float* y, const float* t, const float* w,
               void* stream, float* grad, float* loss) {
   if (!c) return SHAPE_E_INVAL;

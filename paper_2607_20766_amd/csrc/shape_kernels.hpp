@@ -153,6 +153,9 @@ hipError_t launch_mlp_infer(const float* fq, const float* flib, const int* qidx,
                             float* out, hipStream_t st, float* x_out = nullptr,
                             float* const* h_out = nullptr);
 int colsum_chunks(int M);
+constexpr int kColSetMax = 8;
+hipError_t launch_colsum_set(int n, const int* M, const int* N, const float* const* A,
+                             const int64_t* lda, float* const* out, hipStream_t st);
 hipError_t launch_colsum(const float* A, int M, int N, int64_t lda, float* part, float* out,
                          hipStream_t st);
 int mse_blocks(int B, int N);

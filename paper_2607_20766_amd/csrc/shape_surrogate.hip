@@ -825,6 +825,56 @@ __global__ void k_colsum_final(const float* __restrict__ part, int chunks, int N
   out[n] = (float)s;
 }
 
+// Column sums of up to kColSetMax matrices in one launch, each column with
+// exactly the operations of k_colsum_partial + k_colsum_final: FP32 sums over
+// chunks of kColRows rows, then the chunk sums added in order in FP64.  A
+// workgroup takes 16 columns of one matrix; its 64 groups of 16 threads form
+// 64 chunk sums at a time (a chunk's 32 loads issued together, the adds in
+// row order), which the first group then adds in chunk order.
+struct ColsumSet {
+  int n;
+  int M[kColSetMax], N[kColSetMax];
+  int64_t lda[kColSetMax];
+  const float* A[kColSetMax];
+  float* out[kColSetMax];
+  int blk0[kColSetMax + 1];  // first workgroup of each matrix
+};
+
+__global__ __launch_bounds__(1024) void k_colsum_set(ColsumSet s) {
+  __shared__ float part[64][16];
+  int t = 0;
+  while (t + 1 < s.n && (int)blockIdx.x >= s.blk0[t + 1]) ++t;  // uniform
+  const int c = threadIdx.x & 15, g = threadIdx.x >> 4;
+  const int n = ((int)blockIdx.x - s.blk0[t]) * 16 + c;
+  const int M = s.M[t], N = s.N[t];
+  const int64_t lda = s.lda[t];
+  const float* __restrict__ A = s.A[t];
+  const int chunks = (M + kColRows - 1) / kColRows;
+  double S = 0.0;
+  for (int c0 = 0; c0 < chunks; c0 += 64) {
+    const int ch = c0 + g;
+    float v = 0.f;
+    if (n < N && ch < chunks) {
+      const int m0 = ch * kColRows;
+      float x[kColRows];
+#pragma unroll
+      for (int r = 0; r < kColRows; ++r)
+        x[r] = m0 + r < M ? A[(int64_t)(m0 + r) * lda + n] : 0.f;
+#pragma unroll
+      for (int r = 0; r < kColRows; ++r)
+        if (m0 + r < M) v += x[r];
+    }
+    part[g][c] = v;
+    __syncthreads();
+    if (g == 0 && n < N) {
+      const int u1 = min(64, chunks - c0);
+      for (int u = 0; u < u1; ++u) S += part[u][c];
+    }
+    __syncthreads();
+  }
+  if (g == 0 && n < N) s.out[t][n] = (float)S;
+}
+
 // Weighted mean squared error over a batch: loss = sum_j w_j mean_b (y - t)^2,
 // grad = 2 w_j (y - t) / B.  Loss partials per block, then one block sums them
 // in order.
@@ -1176,6 +1226,25 @@ hipError_t launch_colsum(const float* A, int M, int N, int64_t lda, float* part,
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_colsum_final, dim3((N + 255) / 256), dim3(256), 0, st, part, chunks, N,
                      out);
+  return hipGetLastError();
+}
+
+hipError_t launch_colsum_set(int n, const int* M, const int* N, const float* const* A,
+                             const int64_t* lda, float* const* out, hipStream_t st) {
+  ColsumSet s{};
+  s.n = n;
+  int blocks = 0;
+  for (int t = 0; t < n; ++t) {
+    s.M[t] = M[t];
+    s.N[t] = N[t];
+    s.lda[t] = lda[t];
+    s.A[t] = A[t];
+    s.out[t] = out[t];
+    s.blk0[t] = blocks;
+    blocks += (N[t] + 15) / 16;
+  }
+  s.blk0[n] = blocks;
+  hipLaunchKernelGGL(k_colsum_set, dim3((unsigned)blocks), dim3(1024), 0, st, s);
   return hipGetLastError();
 }
 

@@ -143,6 +143,7 @@ def load_library():
         L.shape_gemm.argtypes = [vp, i32, i32, i32, vp, i64, i64, vp, i64, i64, vp, i64, vp, vp,
                                  i64, ctypes.c_uint32, vp]
         L.shape_colsum.argtypes = [vp, i32, i32, vp, i64, vp, vp]
+        L.shape_colsum_set.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
         L.shape_mse.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp, vp]
         L.shape_adam.argtypes = [vp, vp, vp, vp, vp, i64, vp, ctypes.c_float, ctypes.c_float,
                                  ctypes.c_float, ctypes.c_float, vp]
@@ -567,6 +568,19 @@ class Engine:
     def shape_colsum(self, A, M, N, lda, out, stream=None):
         self._check(load_library().shape_colsum(self._ctx, int(M), int(N), _ptr(A), int(lda),
                                                 _ptr(out), _stream(stream)))
+
+    def shape_colsum_set(self, mats, stream=None):
+        """Column sums of several matrices in one launch: mats is a list of
+        (A, M, N, lda, out) with device float tensors A and out."""
+        n = len(mats)
+        Ms = (ctypes.c_int32 * n)(*[int(m[1]) for m in mats])
+        Ns = (ctypes.c_int32 * n)(*[int(m[2]) for m in mats])
+        ldas = (ctypes.c_int64 * n)(*[int(m[3]) for m in mats])
+        As = (ctypes.c_void_p * n)(*[m[0].data_ptr() for m in mats])
+        outs = (ctypes.c_void_p * n)(*[m[4].data_ptr() for m in mats])
+        v = lambda a: ctypes.cast(a, ctypes.c_void_p)
+        self._check(load_library().shape_colsum_set(self._ctx, n, v(Ms), v(Ns), v(As), v(ldas),
+                                                    v(outs), _stream(stream)))
 
     def shape_mse(self, y, t, w, grad, loss, stream=None):
         B, N = y.shape

@@ -8,7 +8,7 @@ import torch
 
 import oracle as O
 from paper_2607_20766_amd import molgen
-from paper_2607_20766_amd.engine import LAMBDA_P27, SHAPE_SCREEN_ADAPTIVE, Engine
+from paper_2607_20766_amd.engine import LAMBDA_P27, SHAPE_SCREEN_ADAPTIVE, Engine, ShapeError
 from paper_2607_20766_amd.surrogate import MLP, WIDTH, Triage, init_params
 from tests.gpu_common import require_gpu
 
@@ -241,6 +241,29 @@ def test_fused_inference_matches_layers(eng, n, with_fo, with_idx):
     assert torch.equal(yf, y_layers) and torch.equal(xf, x)
     for l in range(3):
         assert torch.equal(hf[l], h_layers[l]), l
+
+
+def test_colsum_set_equals_colsum(eng):
+    """One launch for several matrices gives each column sum the bits of
+    shape_colsum: row counts below, at and far above the 16 chunks of 32 rows
+    a workgroup forms at once, ragged column counts, a padded row stride."""
+    rng = np.random.default_rng(31)
+    shapes = [(4096, 256, 256), (4096, 2, 2), (37, 70, 75), (1, 1, 1), (513, 129, 130),
+              (20000, 65, 65)]
+    mats, want = [], []
+    for M, N, lda in shapes:
+        A = torch.from_numpy(rng.normal(size=(M, lda)).astype(np.float32)).cuda()
+        ref = torch.empty(N, dtype=torch.float32, device="cuda")
+        eng.shape_colsum(A, M, N, lda, ref)
+        mats.append((A, M, N, lda, torch.full((N,), np.nan, device="cuda")))
+        want.append(ref)
+    print("case: column sums of 6 matrices in one launch", flush=True)
+    eng.shape_colsum_set(mats)
+    torch.cuda.synchronize()
+    for (A, M, N, lda, out), ref in zip(mats, want):
+        assert torch.equal(out, ref), (M, N, lda)
+    with pytest.raises(ShapeError):
+        eng.shape_colsum_set(mats + mats[:3])   # 9 > 8 matrices
 
 
 def test_training_with_fused_forward_equals_layers(eng):
