@@ -123,20 +123,23 @@ class MLP:
         for i in range(0, len(bias_grads), 8):
             self.eng.shape_colsum_set(bias_grads[i:i + 8])
 
-    def loss_grad(self, x, target, loss_weights):
-        """Forward, weighted MSE and backward; returns the loss tensor [1]."""
+    def loss_grad(self, x, target, loss_weights, loss_out=None):
+        """Forward, weighted MSE and backward; returns the loss tensor [1]
+        (loss_out if given)."""
         self.forward(x)
-        return self.loss_grad_after_forward(x, target, loss_weights)
+        return self.loss_grad_after_forward(x, target, loss_weights, loss_out)
 
-    def loss_grad_after_forward(self, x, target, loss_weights):
+    def loss_grad_after_forward(self, x, target, loss_weights, loss_out=None):
         """Weighted MSE and backward, given that the activation buffers of
         batch x.shape[0] hold the forward of x (forward, or the fused
-        shape_mlp_forward); returns the loss tensor [1]."""
+        shape_mlp_forward); returns the loss tensor [1] (loss_out if given:
+        the loss is written there directly)."""
         buf = self._buffers(x.shape[0])
         dout = buf["d"][-1]
-        self.eng.shape_mse(buf["h"][-1], target, loss_weights, dout, buf["loss"])
+        loss = buf["loss"] if loss_out is None else loss_out
+        self.eng.shape_mse(buf["h"][-1], target, loss_weights, dout, loss)
         self.backward(x, dout)
-        return buf["loss"]
+        return loss
 
     def adam_step(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):
         self.eng.shape_adam(self.params, self.grad, self.m, self.v, self.step, lr, beta1, beta2,
@@ -254,14 +257,13 @@ class Triage:
                     self.eng.shape_mlp_forward(f_q, f_lib, self.mean, self.inv_std,
                                                self.mlp.params, xb, acts[:3], acts[3],
                                                idx=m_ep[s:e], qidx=q_ep[s:e], fo_cross=fo_b)
-                    loss = self.mlp.loss_grad_after_forward(xb, y_ep[s:e], lw)
+                    self.mlp.loss_grad_after_forward(xb, y_ep[s:e], lw, losses[b:b + 1])
                 else:
                     self.eng.shape_pair_features(f_q, f_lib, self.mean, self.inv_std,
                                                  idx=m_ep[s:e], qidx=q_ep[s:e], out=xb,
                                                  fo_cross=fo_b)
-                    loss = self.mlp.loss_grad(xb, y_ep[s:e], lw)
+                    self.mlp.loss_grad(xb, y_ep[s:e], lw, losses[b:b + 1])
                 self.mlp.adam_step(lr)
-                losses[b:b + 1].copy_(loss)
 
         g = None
         history = []
