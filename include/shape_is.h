@@ -491,6 +491,27 @@ int shape_gemm(shape_ctx* ctx, int32_t M, int32_t N, int32_t K, const float* A, 
                int64_t sak, const float* B, int64_t sbk, int64_t sbn, float* C, int64_t scm,
                const float* bias, const float* gate, int64_t sgm, uint32_t flags, void* stream);
 
+/* One product of shape_gemm_set: the arguments of shape_gemm. */
+typedef struct shape_gemm_desc {
+  const float* A;
+  const float* B;
+  float* C;
+  const float* bias;
+  const float* gate;
+  int64_t sam, sak, sbk, sbn, scm, sgm;
+  int32_t M, N, K;
+  uint32_t flags;
+} shape_gemm_desc;
+
+/* n (1..8) independent products, each with exactly the result shape_gemm
+ * gives for its arguments (the weight gradients of all layers of a backward
+ * pass at once).  BF16 products that shape_gemm runs with 64 x 64 tiles go
+ * into one launch (plus one launch for their split-K reductions); any other
+ * product is run as by shape_gemm.  d: host array of n descriptors.  Uses
+ * context scratch for the split-K partials.  Asynchronous.  Errors as
+ * shape_gemm; SHAPE_E_RANGE for n outside 1..8. */
+int shape_gemm_set(shape_ctx* ctx, int32_t n, const shape_gemm_desc* d, void* stream);
+
 /* Column sums out[n] = sum_m A[m*lda + n] (device float).  Asynchronous. */
 int shape_colsum(shape_ctx* ctx, int32_t M, int32_t N, const float* A, int64_t lda,
                  float* out, void* stream);

@@ -1065,6 +1065,49 @@ int shape_gemm(shape_ctx* c, int32_t M, int32_t N, int32_t K, const float* A, in
   return SHAPE_OK;
 }
 
+int shape_gemm_set(shape_ctx* c, int32_t n, const shape_gemm_desc* d, void* stream) {
+  if (!c) return SHAPE_E_INVAL;
+  if (n < 1 || n > shape::kGemmSetMax)
+    return fail(c, SHAPE_E_RANGE, "n must be in 1..%d", shape::kGemmSetMax);
+  if (!d) return fail(c, SHAPE_E_INVAL, "NULL descriptor array");
+  try {
+    shape::GemmArgs set[shape::kGemmSetMax];
+    int n_set = 0;
+    size_t part_elems = 0;
+    for (int t = 0; t < n; ++t) {
+      const shape_gemm_desc& q = d[t];
+      if (q.M < 1 || q.N < 1 || q.K < 1) return fail(c, SHAPE_E_RANGE, "M, N, K must be >= 1");
+      if (!q.A || !q.B || !q.C) return fail(c, SHAPE_E_INVAL, "NULL array");
+      if (q.flags & ~(SHAPE_GEMM_BF16 | SHAPE_GEMM_RELU))
+        return fail(c, SHAPE_E_INVAL, "bad flags");
+    }
+    int rc = set_device(c);
+    if (rc) return rc;
+    for (int t = 0; t < n; ++t) {
+      const shape_gemm_desc& q = d[t];
+      shape::GemmArgs g{q.M,   q.N,   q.K,    q.A,    q.sam,  q.sak,  q.B,         q.sbk,
+                        q.sbn, q.C,   q.scm,  q.bias, q.gate, q.sgm,  (int)q.flags};
+      if (shape::gemm_set_fits(g)) {
+        set[n_set++] = g;
+        part_elems += shape::gemm_set_part_elems(g);
+      } else if ((rc = shape_gemm(c, q.M, q.N, q.K, q.A, q.sam, q.sak, q.B, q.sbk, q.sbn, q.C,
+                                  q.scm, q.bias, q.gate, q.sgm, q.flags, stream))) {
+        return rc;
+      }
+    }
+    if (n_set == 0) return SHAPE_OK;
+    void* part = nullptr;
+    if (part_elems > 0 &&
+        (rc = ensure(c, S_GEMM_PART, part_elems * sizeof(float), &part)))
+      return rc;
+    HIP_TRY(c, shape::launch_gemm_set(n_set, set, (float*)part, (hipStream_t)stream),
+            "gemm set kernels");
+    return SHAPE_OK;
+  } catch (...) {
+    return fail(c, SHAPE_E_HIP, "internal error");
+  }
+}
+
 int shape_colsum(shape_ctx* c, int32_t M, int32_t N, const float* A, int64_t lda, float* out,
                  void* stream) {
   if (!c) return SHAPE_E_INVAL;

@@ -118,6 +118,12 @@ hipError_t launch_pair_features(const float* fq, const float* flib, const int* q
 hipError_t launch_fo_cross(const MolsDev& Q, const MolsDev& L, const int* pairs, int n_pairs,
                            int* flag, float* out, hipStream_t st);
 hipError_t launch_gemm(const GemmArgs& g, hipStream_t st);
+// several BF16 products with 64 x 64 tiles in one launch (plus one split-K
+// reduction launch); part holds the sum of gemm_set_part_elems of the set
+constexpr int kGemmSetMax = 8;
+bool gemm_set_fits(const GemmArgs& g);
+size_t gemm_set_part_elems(const GemmArgs& g);
+hipError_t launch_gemm_set(int n, const GemmArgs* gs, float* part, hipStream_t st);
 size_t mlp_pack_bytes();
 // dense-grid quadrature
 struct GridDims {

@@ -435,14 +435,16 @@ __global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs g) {
 // size, so both sizes give the same bits.
 constexpr int kTK = 32, kLdk = kTK + 8;
 
+// One output tile (bx, by) of split bz: the body of k_gemm_bf16_tiled, also
+// run by k_gemm_set for each product of a batch.
 template <int TM, int TN>
-__global__ __launch_bounds__(256, 2) void k_gemm_bf16_tiled(GemmArgs g) {
+__device__ __forceinline__ void gemm_bf16_tile(const GemmArgs& g, int bx, int by, int bz) {
   constexpr int FM = TM / 32, FN = TN / 32;           // MFMA tiles per wave
   constexpr int RA = TM * kTK / 256, RB = TN * kTK / 256;  // staged values per thread
   __shared__ __align__(16) short As[TM * kLdk];
   __shared__ __align__(16) short Bs[TN * kLdk];
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
-  const int bm = blockIdx.y * TM, bn = blockIdx.x * TN;
+  const int bm = by * TM, bn = bx * TN;
   const int wm = (wave >> 1) * (TM / 2), wn = (wave & 1) * (TN / 2);
   const int li = lane & 15, lk = lane >> 4;
   v4f acc[FM][FN];
@@ -452,7 +454,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_bf16_tiled(GemmArgs g) {
     for (int j = 0; j < FN; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
   const bool a_kfast = g.sak == 1;
   const bool b_nfast = g.sbn == 1;
-  const int kb = g.part ? blockIdx.z * g.k_chunk : 0;
+  const int kb = g.part ? bz * g.k_chunk : 0;
   const int ke = g.part ? min(g.K, kb + g.k_chunk) : g.K;
   // Slabs of kTK values of k: slab s+1 is read from global memory into
   // registers while the matrix cores work on slab s from LDS.
@@ -528,7 +530,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_bf16_tiled(GemmArgs g) {
         const int m = bm + wm + 16 * i + 4 * lk + r;
         const int n = bn + wn + 16 * j + li;
         if (m < g.M && n < g.N && g.part) {
-          g.part[((int64_t)blockIdx.z * g.M + m) * g.N + n] = acc[i][j][r];
+          g.part[((int64_t)bz * g.M + m) * g.N + n] = acc[i][j][r];
         } else if (m < g.M && n < g.N) {
           float v = acc[i][j][r];
           if (g.bias) v += g.bias[n];
@@ -540,12 +542,56 @@ __global__ __launch_bounds__(256, 2) void k_gemm_bf16_tiled(GemmArgs g) {
 }
 
 // Split-K reduction: C[m][n] = epilogue(sum_z part[z][m][n]), z in order.
+template <int TM, int TN>
+__global__ __launch_bounds__(256, 2) void k_gemm_bf16_tiled(GemmArgs g) {
+  gemm_bf16_tile<TM, TN>(g, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+// Up to kGemmSetMax BF16 products with 64 x 64 tiles in one launch (the
+// weight gradients of all layers): workgroup b runs tile b - blk0[t] of
+// product t, numbered split-major like the single launch's grid, so every
+// product gets exactly its single-launch arithmetic.
+struct GemmSet {
+  int n;
+  GemmArgs g[kGemmSetMax];
+  int tx[kGemmSetMax], ty[kGemmSetMax], splits[kGemmSetMax];
+  int blk0[kGemmSetMax + 1];   // first workgroup of each product
+  int64_t el0[kGemmSetMax + 1];  // first reduced element of each product (split ones)
+};
+
+__global__ __launch_bounds__(256, 2) void k_gemm_set(GemmSet s) {
+  int t = 0;
+  while (t + 1 < s.n && (int)blockIdx.x >= s.blk0[t + 1]) ++t;  // uniform
+  const int local = (int)blockIdx.x - s.blk0[t];
+  const int per = s.tx[t] * s.ty[t];
+  const int r = local % per;
+  gemm_bf16_tile<64, 64>(s.g[t], r % s.tx[t], r / s.tx[t], local / per);
+}
+
 __global__ void k_splitk_reduce(GemmArgs g, int splits) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (int64_t)g.M * g.N) return;
   const int m = (int)(t / g.N), n = (int)(t % g.N);
   float v = 0.0f;
   for (int z = 0; z < splits; ++z) v += g.part[(int64_t)z * g.M * g.N + t];
+  if (g.bias) v += g.bias[n];
+  if (g.flags & SHAPE_GEMM_RELU) v = v > 0.f ? v : 0.f;
+  if (g.gate && !(g.gate[(int64_t)m * g.sgm + n] > 0.f)) v = 0.f;
+  g.C[(int64_t)m * g.scm + n] = v;
+}
+
+// The split-K reductions of a GemmSet in one launch (k_splitk_reduce's
+// arithmetic per element).
+__global__ void k_splitk_reduce_set(GemmSet s) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= s.el0[s.n]) return;
+  int t = 0;
+  while (t + 1 < s.n && e >= s.el0[t + 1]) ++t;
+  const GemmArgs& g = s.g[t];
+  const int64_t q = e - s.el0[t];
+  const int m = (int)(q / g.N), n = (int)(q % g.N);
+  float v = 0.0f;
+  for (int z = 0; z < s.splits[t]; ++z) v += g.part[(int64_t)z * g.M * g.N + q];
   if (g.bias) v += g.bias[n];
   if (g.flags & SHAPE_GEMM_RELU) v = v > 0.f ? v : 0.f;
   if (g.gate && !(g.gate[(int64_t)m * g.sgm + n] > 0.f)) v = 0.f;
@@ -1164,6 +1210,51 @@ hipError_t launch_gemm(const GemmArgs& g0, hipStream_t st) {
   const int64_t tot = (int64_t)g.M * g.N;
   hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, g,
                      splits);
+  return hipGetLastError();
+}
+
+bool gemm_set_fits(const GemmArgs& g) { return gemm_tiled(g) && gemm_tile(g) == 64; }
+
+size_t gemm_set_part_elems(const GemmArgs& g) {
+  const int splits = gemm_splits(g);
+  return splits > 1 ? (size_t)splits * g.M * g.N : 0;
+}
+
+hipError_t launch_gemm_set(int n, const GemmArgs* gs, float* part, hipStream_t st) {
+  GemmSet s{};
+  s.n = n;
+  int blocks = 0;
+  int64_t el = 0;
+  size_t off = 0;
+  for (int t = 0; t < n; ++t) {
+    GemmArgs g = gs[t];
+    const dim3 grid = gemm_grid(g);
+    int splits = gemm_splits(g);
+    if (splits > 1) {
+      g.k_chunk = ((g.K + splits - 1) / splits + kTK - 1) / kTK * kTK;
+      splits = (g.K + g.k_chunk - 1) / g.k_chunk;
+      g.part = part + off;
+      off += (size_t)splits * g.M * g.N;
+    } else {
+      g.part = nullptr;
+      g.k_chunk = 0;
+    }
+    s.g[t] = g;
+    s.tx[t] = (int)grid.x;
+    s.ty[t] = (int)grid.y;
+    s.splits[t] = splits;
+    s.blk0[t] = blocks;
+    s.el0[t] = el;
+    blocks += (int)(grid.x * grid.y) * splits;
+    if (splits > 1) el += (int64_t)g.M * g.N;
+  }
+  s.blk0[n] = blocks;
+  s.el0[n] = el;
+  hipLaunchKernelGGL(k_gemm_set, dim3((unsigned)blocks), dim3(256), 0, st, s);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || el == 0) return e;
+  hipLaunchKernelGGL(k_splitk_reduce_set, dim3((unsigned)((el + 255) / 256)), dim3(256), 0, st,
+                     s);
   return hipGetLastError();
 }
 

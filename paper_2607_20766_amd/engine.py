@@ -144,6 +144,7 @@ def load_library():
                                  i64, ctypes.c_uint32, vp]
         L.shape_colsum.argtypes = [vp, i32, i32, vp, i64, vp, vp]
         L.shape_colsum_set.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
+        L.shape_gemm_set.argtypes = [vp, i32, ctypes.POINTER(ShapeGemmDesc), vp]
         L.shape_mse.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp, vp]
         L.shape_adam.argtypes = [vp, vp, vp, vp, vp, i64, vp, ctypes.c_float, ctypes.c_float,
                                  ctypes.c_float, ctypes.c_float, vp]
@@ -153,6 +154,16 @@ def load_library():
         L.shape_timing_read.argtypes = [vp, ctypes.POINTER(d), ctypes.POINTER(i64), ctypes.c_int]
         _lib = L
     return _lib
+
+
+class ShapeGemmDesc(ctypes.Structure):
+    """shape_gemm_desc: one product of shape_gemm_set."""
+    _fields_ = [("A", ctypes.c_void_p), ("B", ctypes.c_void_p), ("C", ctypes.c_void_p),
+                ("bias", ctypes.c_void_p), ("gate", ctypes.c_void_p),
+                ("sam", ctypes.c_int64), ("sak", ctypes.c_int64), ("sbk", ctypes.c_int64),
+                ("sbn", ctypes.c_int64), ("scm", ctypes.c_int64), ("sgm", ctypes.c_int64),
+                ("M", ctypes.c_int32), ("N", ctypes.c_int32), ("K", ctypes.c_int32),
+                ("flags", ctypes.c_uint32)]
 
 
 def _ptr(t):
@@ -564,6 +575,22 @@ class Engine:
             self._ctx, int(M), int(N), int(K), _ptr(A), int(sam), int(sak), _ptr(B), int(sbk),
             int(sbn), _ptr(C), int(scm), _ptr(bias), _ptr(gate), int(sgm), flags,
             _stream(stream)))
+
+    def shape_gemm_set(self, products, stream=None):
+        """Several products in one call (shape_gemm_set): products is a list
+        of dicts with shape_gemm's arguments (M, N, K, A, sam, sak, B, sbk,
+        sbn, C, scm and optionally bias, gate, sgm, bf16, relu)."""
+        n = len(products)
+        arr = (ShapeGemmDesc * n)()
+        for d, p in zip(arr, products):
+            d.A, d.B, d.C = p["A"].data_ptr(), p["B"].data_ptr(), p["C"].data_ptr()
+            d.bias = p["bias"].data_ptr() if p.get("bias") is not None else None
+            d.gate = p["gate"].data_ptr() if p.get("gate") is not None else None
+            d.sam, d.sak, d.sbk, d.sbn = int(p["sam"]), int(p["sak"]), int(p["sbk"]), int(p["sbn"])
+            d.scm, d.sgm = int(p["scm"]), int(p.get("sgm", 0))
+            d.M, d.N, d.K = int(p["M"]), int(p["N"]), int(p["K"])
+            d.flags = (1 if p.get("bf16", True) else 0) | (2 if p.get("relu", False) else 0)
+        self._check(load_library().shape_gemm_set(self._ctx, n, arr, _stream(stream)))
 
     def shape_colsum(self, A, M, N, lda, out, stream=None):
         self._check(load_library().shape_colsum(self._ctx, int(M), int(N), _ptr(A), int(lda),

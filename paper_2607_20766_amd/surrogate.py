@@ -103,14 +103,14 @@ class MLP:
         Ws = self._views(self.params)
         Gs = self._views(self.grad)
         dz = dout
-        bias_grads = []
+        bias_grads, weight_grads = [], []
         for l in range(L - 1, -1, -1):
             n_in, n_out = self.width[l], self.width[l + 1]
             h_in = x if l == 0 else buf["h"][l - 1]
             gW, gb = Gs[l]
-            # dW[i][o] = sum_b h_in[b][i] dz[b][o]
-            self.eng.shape_gemm(n_in, n_out, B, h_in, 1, n_in, dz, n_out, 1, gW, n_out,
-                                bf16=self.bf16)
+            # dW[i][o] = sum_b h_in[b][i] dz[b][o]: all layers in one launch below
+            weight_grads.append(dict(M=n_in, N=n_out, K=B, A=h_in, sam=1, sak=n_in, B=dz,
+                                     sbk=n_out, sbn=1, C=gW, scm=n_out, bf16=self.bf16))
             bias_grads.append((dz, B, n_out, n_out, gb))
             if l > 0:
                 # dh[b][i] = sum_o dz[b][o] W[i][o], through the ReLU of layer l-1
@@ -119,7 +119,10 @@ class MLP:
                 self.eng.shape_gemm(B, n_in, n_out, dz, n_out, 1, W, 1, n_out, dnext, n_in,
                                     gate=buf["h"][l - 1], sgm=n_in, bf16=self.bf16)
                 dz = dnext
-        # db = column sums of each layer's dz, all layers in one launch (up to 8)
+        # dW and db of every layer (8 per launch): the products of the weight
+        # gradients, then the column sums of each layer's dz
+        for i in range(0, len(weight_grads), 8):
+            self.eng.shape_gemm_set(weight_grads[i:i + 8])
         for i in range(0, len(bias_grads), 8):
             self.eng.shape_colsum_set(bias_grads[i:i + 8])
 

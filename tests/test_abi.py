@@ -44,6 +44,8 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(engine.ShapeResult) == 18 * 8 + 2 * 8
     assert ctypes.sizeof(engine.ShapeScreenParams) == 4 * 4 + 8 + 8 + 8
     assert ctypes.sizeof(engine.ShapeScreenOut) == 6 * 8
+    # shape_gemm_desc: 5 pointers + 6 int64 + 3 int32 + uint32
+    assert ctypes.sizeof(engine.ShapeGemmDesc) == 5 * 8 + 6 * 8 + 4 * 4
 
 
 def test_null_arguments_are_rejected_without_device():

@@ -243,6 +243,49 @@ def test_fused_inference_matches_layers(eng, n, with_fo, with_idx):
         assert torch.equal(hf[l], h_layers[l]), l
 
 
+def test_gemm_set_equals_gemm(eng):
+    """Several products in one shape_gemm_set call give each product
+    shape_gemm's bits: weight-gradient shapes (split K), a product without
+    split K with bias, ReLU and gate, and two that do not fit the batched
+    kernel (FP32 operands; 128 x 128 tiles) and run as by shape_gemm."""
+    rng = np.random.default_rng(41)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
+    specs = [
+        dict(M=256, N=256, K=4096, at=True, bf16=True),     # Xt dZ, split K
+        dict(M=96, N=256, K=4096, at=True, bf16=True),
+        dict(M=256, N=2, K=4096, at=True, bf16=True),
+        dict(M=300, N=70, K=45, at=False, bf16=True, bias=True, relu=True, gate=True),
+        dict(M=64, N=64, K=100, at=False, bf16=False),      # FP32: shape_gemm path
+        dict(M=4096, N=512, K=64, at=False, bf16=True),     # 128 x 128 tiles
+    ]
+    prods, refs = [], []
+    for sp in specs:
+        M, N, K = sp["M"], sp["N"], sp["K"]
+        if sp["at"]:   # A(m, k) = X[k][m]
+            A = d(rng.normal(size=(K, M)))
+            sam, sak = 1, M
+        else:
+            A = d(rng.normal(size=(M, K)))
+            sam, sak = K, 1
+        B = d(rng.normal(size=(K, N)))
+        bias = d(rng.normal(size=N)) if sp.get("bias") else None
+        gate = d(rng.normal(size=(M, N))) if sp.get("gate") else None
+        ref = torch.empty(M, N, device="cuda")
+        eng.shape_gemm(M, N, K, A, sam, sak, B, N, 1, ref, N, bias=bias, gate=gate,
+                       sgm=N, bf16=sp["bf16"], relu=sp.get("relu", False))
+        refs.append(ref)
+        prods.append(dict(M=M, N=N, K=K, A=A, sam=sam, sak=sak, B=B, sbk=N, sbn=1,
+                          C=torch.full((M, N), np.nan, device="cuda"), scm=N, bias=bias,
+                          gate=gate, sgm=N, bf16=sp["bf16"], relu=sp.get("relu", False)))
+    print("case: 6 products in one shape_gemm_set call", flush=True)
+    eng.shape_gemm_set(prods)
+    torch.cuda.synchronize()
+    for p, ref in zip(prods, refs):
+        assert torch.equal(p["C"], ref), (p["M"], p["N"], p["K"])
+    with pytest.raises(ShapeError):
+        eng.shape_gemm_set(prods + prods[:3])   # 9 > 8 products
+
+
 def test_colsum_set_equals_colsum(eng):
     """One launch for several matrices gives each column sum the bits of
     shape_colsum: row counts below, at and far above the 16 chunks of 32 rows
