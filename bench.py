@@ -467,7 +467,7 @@ def bench_triage(eng, n_lib, n_queries=256, n_train_lib=3907, epochs=10):
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--library", type=int, default=N_LIB)
     ap.add_argument("--no-cpu-baseline", action="store_true")
