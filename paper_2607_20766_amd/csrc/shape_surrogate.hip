@@ -273,8 +273,12 @@ __global__ __launch_bounds__(kWave * kFoWaves) void k_fo_cross(
     return;
   }
   wave_lds_sync();
-  const int di = kWave / nb, dj = kWave % nb;
-  int i = lane / nb, j = lane % nb;
+  // x / nb for x <= 64 and nb <= 256 from the hardware reciprocal: x * (1/nb)
+  // is within 2^-15 of the quotient, which is an integer or at least 2^-8
+  // below the next one, so adding 2^-12 and truncating is exact
+  const float inv_nb = __builtin_amdgcn_rcpf((float)nb);
+  const int di = (int)fmaf((float)kWave, inv_nb, 0x1p-12f), dj = kWave - di * nb;
+  int i = (int)fmaf((float)lane, inv_nb, 0x1p-12f), j = lane - i * nb;
   // With widths a' = log2(e) a in LDS, s = a'_i + a'_j = log2(e) (a_i + a_j):
   // a'_i a'_j / s = log2(e) a_i a_j / (a_i + a_j), the exp2 exponent per unit
   // d2, and s^(-3/2) = log2(e)^(-3/2) (a_i + a_j)^(-3/2); the constant
