@@ -236,20 +236,25 @@ def test_ensemble_screen_takes_the_best_conformer(eng, aligned):
     assert np.all(best >= T[:, 0])
 
 
-@pytest.mark.parametrize("a_atoms,n_starts", [((3, 16), 1), ((50, 64), 6), ((20, 30), 19),
-                                              ((70, 80), 5)])
-def test_every_launch_shape_matches_oracle(eng, a_atoms, n_starts):
+@pytest.mark.parametrize("a_atoms,b_atoms,n_starts", [((3, 16), (10, 50), 1),
+                                                      ((50, 64), (10, 50), 6),
+                                                      ((20, 30), (10, 50), 19),
+                                                      ((3, 16), (70, 90), 8),
+                                                      ((70, 80), (10, 50), 5)])
+def test_every_launch_shape_matches_oracle(eng, a_atoms, b_atoms, n_starts):
     """The alignment kernel's launch shapes: one start per 16-lane row with
     A's atoms in 1 to 4 rows per lane (up to 16, 32, 48, 64 atoms), start
     counts that leave spare rows or need a second workgroup (19 = 16 + 3),
-    and molecules past 64 atoms, which take the one-start-per-wave kernel.
-    T_FO and the gradient at the given poses, then 5 Adam steps, against the
-    oracle."""
+    library molecules past 64 atoms (70-90; four or more atoms per lane in
+    the moves), and A past 64 atoms, which takes the one-start-per-wave
+    kernel.  T_FO and the gradient at the given poses, then 5 Adam steps,
+    against the oracle."""
     A = molgen.library(64, 3, *a_atoms, workers=1)
-    B = molgen.library(65, 3, 10, 50, workers=1)
+    B = molgen.library(65, 3, *b_atoms, workers=1)
     dA, dB = eng.molecules(A), eng.molecules(B)
     poses = _poses(A.n_mols, n_starts, seed=11)
-    print(f"case: first-order alignment, A {a_atoms} atoms, {n_starts} starts", flush=True)
+    print(f"case: first-order alignment, A {a_atoms}, B {b_atoms} atoms, {n_starts} starts",
+          flush=True)
     T, g = eng.shape_fo_align(dA, dB, torch.from_numpy(poses.copy()).cuda(), n_steps=0,
                               need_grad=True)
     T, g = T.cpu().numpy(), g.cpu().numpy()
