@@ -1074,6 +1074,7 @@ int shape_gemm_set(shape_ctx* c, int32_t n, const shape_gemm_desc* d, void* stre
     shape::GemmArgs set[shape::kGemmSetMax];
     int n_set = 0;
     size_t part_elems = 0;
+    int64_t set_blocks = 0;  // one grid: at most 2^31 - 1 workgroups
     for (int t = 0; t < n; ++t) {
       const shape_gemm_desc& q = d[t];
       if (q.M < 1 || q.N < 1 || q.K < 1) return fail(c, SHAPE_E_RANGE, "M, N, K must be >= 1");
@@ -1087,9 +1088,10 @@ int shape_gemm_set(shape_ctx* c, int32_t n, const shape_gemm_desc* d, void* stre
       const shape_gemm_desc& q = d[t];
       shape::GemmArgs g{q.M,   q.N,   q.K,    q.A,    q.sam,  q.sak,  q.B,         q.sbk,
                         q.sbn, q.C,   q.scm,  q.bias, q.gate, q.sgm,  (int)q.flags};
-      if (shape::gemm_set_fits(g)) {
+      if (shape::gemm_set_fits(g) && set_blocks + shape::gemm_set_blocks(g) <= 0x7FFFFFFF) {
         set[n_set++] = g;
         part_elems += shape::gemm_set_part_elems(g);
+        set_blocks += shape::gemm_set_blocks(g);
       } else if ((rc = shape_gemm(c, q.M, q.N, q.K, q.A, q.sam, q.sak, q.B, q.sbk, q.sbn, q.C,
                                   q.scm, q.bias, q.gate, q.sgm, q.flags, stream))) {
         return rc;

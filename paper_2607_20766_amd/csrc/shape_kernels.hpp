@@ -123,6 +123,7 @@ hipError_t launch_gemm(const GemmArgs& g, hipStream_t st);
 constexpr int kGemmSetMax = 8;
 bool gemm_set_fits(const GemmArgs& g);
 size_t gemm_set_part_elems(const GemmArgs& g);
+int64_t gemm_set_blocks(const GemmArgs& g);
 hipError_t launch_gemm_set(int n, const GemmArgs* gs, float* part, hipStream_t st);
 size_t mlp_pack_bytes();
 // dense-grid quadrature

@@ -1219,6 +1219,11 @@ hipError_t launch_gemm(const GemmArgs& g0, hipStream_t st) {
 
 bool gemm_set_fits(const GemmArgs& g) { return gemm_tiled(g) && gemm_tile(g) == 64; }
 
+int64_t gemm_set_blocks(const GemmArgs& g) {
+  const dim3 grid = gemm_grid(g);
+  return (int64_t)grid.x * grid.y * gemm_splits(g);
+}
+
 size_t gemm_set_part_elems(const GemmArgs& g) {
   const int splits = gemm_splits(g);
   return splits > 1 ? (size_t)splits * g.M * g.N : 0;
