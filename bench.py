@@ -326,15 +326,14 @@ def bench_triage(eng, n_lib, n_queries=256, n_train_lib=3907, epochs=10):
     f_q = eng.shape_features(eng.molecules(Qs))
     tr = Triage(eng, seed=0)
     t0 = time.perf_counter()
-    qi, mi, Y, FO = [], [], [], []
-    for i in range(Qs.n_mols):
-        q = eng.molecules(Qs.mol(i), mol_id=[0xFFFF0000 + i])
-        T, s_, _ = tr.labels(q, lib_t)
-        FO.append(eng.shape_fo_overlap(q, lib_t).cpu().numpy())
-        qi.append(np.full(Lt.n_mols, i))
-        mi.append(np.arange(Lt.n_mols))
-        Y.append(np.stack([T, s_], 1))
-    qi, mi, Y, FO = (np.concatenate(x) for x in (qi, mi, Y, FO))
+    # one adaptive screen per training query (query-major rows), spread over
+    # four contexts and streams
+    qs = [eng.molecules(Qs.mol(i), mol_id=[0xFFFF0000 + i]) for i in range(Qs.n_mols)]
+    T, s_, _, FO = tr.labels_many(qs, lib_t, fo=True)
+    qi = np.repeat(np.arange(Qs.n_mols), Lt.n_mols)
+    mi = np.tile(np.arange(Lt.n_mols), Qs.n_mols)
+    Y = np.stack([T.ravel(), s_.ravel()], 1)
+    FO = FO.ravel()
     t_labels = time.perf_counter() - t0
     tr.fit_standardisation(f_q, f_lib_t, qi, mi, fo=FO)
     t0 = time.perf_counter()

@@ -192,6 +192,57 @@ class Triage:
         n = out["n_used"].cpu().numpy().astype(np.float64)
         return T, np.log(se * np.sqrt(n)), n
 
+    def labels_many(self, queries, lib: Molecules, seed: int = 0, n_streams: int = 4,
+                    fo: bool = False):
+        """labels() for several queries (Molecules, each one molecule) at
+        once: the screens go round-robin to n_streams library contexts on
+        their own streams, so one screen's ramp and tail overlap the next
+        one's work, with one synchronisation at the end.  Same kernels, seeds
+        and tile variant as labels(), so the same values.  Returns T, the
+        log scale and n_used as [n_queries, n_lib] arrays (and the
+        first-order cross-overlaps if fo)."""
+        dev = self.eng.torch_device
+        n_q, n = len(queries), lib.n_mols
+        f32 = dict(dtype=torch.float32, device=dev)
+        T = torch.empty(n_q, n, **f32)
+        se = torch.empty(n_q, n, **f32)
+        nu = torch.empty(n_q, n, dtype=torch.int32, device=dev)
+        fo_out = torch.empty(n_q, n, **f32) if fo else None
+        helpers = [Engine(self.eng.device) for _ in range(max(n_streams, 1) - 1)]
+        engs = [self.eng] + helpers
+        for e in helpers:
+            e.screen_variant(self.eng.screen_variant())
+            e.sampling(self.eng.sampling())
+        streams = [torch.cuda.Stream(device=dev) for _ in engs]
+        cur = torch.cuda.current_stream(dev)
+        for st in streams:
+            st.wait_stream(cur)   # the uploads of the queries and the library
+        try:
+            for e in engs:
+                e.prepare_cache(True)   # the library is prepared once per context
+            for i, q in enumerate(queries):
+                k = i % len(engs)
+                out = {"T": T[i], "se_T": se[i], "n_used": nu[i]}
+                engs[k].shape_screen(q, lib, mode=SHAPE_SCREEN_ADAPTIVE,
+                                     round_per_pair=self.round_per_pair,
+                                     cap_per_pair=self.cap_per_pair, tau=self.tau, seed=seed,
+                                     out=out, stream=streams[k])
+                if fo:
+                    engs[k].shape_fo_overlap(q, lib, out=fo_out[i], stream=streams[k])
+            for st in streams:
+                cur.wait_stream(st)
+            torch.cuda.synchronize(dev)
+        finally:
+            for e in engs:
+                e.prepare_cache(False)
+            for e in helpers:
+                e.close()
+        Tn = T.cpu().numpy().astype(np.float64)
+        sen = se.cpu().numpy().astype(np.float64)
+        nn = nu.cpu().numpy().astype(np.float64)
+        res = (Tn, np.log(sen * np.sqrt(nn)), nn)
+        return res + (fo_out.cpu().numpy(),) if fo else res
+
     def fo_overlap(self, query: Molecules, lib: Molecules):
         """First-order cross-overlaps of the query with every library molecule
         (device) when the model uses them, else None."""

@@ -286,6 +286,23 @@ def test_gemm_set_equals_gemm(eng):
         eng.shape_gemm_set(prods + prods[:3])   # 9 > 8 products
 
 
+def test_labels_many_equals_labels(eng):
+    """Label screens spread over several contexts and streams give each
+    query the values of its own labels() call."""
+    Lt = molgen.library(42, 300, 10, 50, workers=1)
+    Qs = molgen.library(43, 6, 10, 50, workers=1)
+    lib = eng.molecules(Lt)
+    qs = [eng.molecules(Qs.mol(i), mol_id=[0xFFFF0000 + i]) for i in range(Qs.n_mols)]
+    tr = Triage(eng, seed=0)
+    print("case: labels of 6 queries on 4 streams", flush=True)
+    T, ls, n, fo = tr.labels_many(qs, lib, fo=True)
+    for i, q in enumerate(qs):
+        Ti, lsi, ni = tr.labels(q, lib)
+        assert np.array_equal(T[i], Ti) and np.array_equal(n[i], ni), i
+        assert np.array_equal(ls[i], lsi), i
+        assert np.array_equal(fo[i], eng.shape_fo_overlap(q, lib).cpu().numpy()), i
+
+
 def test_colsum_set_equals_colsum(eng):
     """One launch for several matrices gives each column sum the bits of
     shape_colsum: row counts below, at and far above the 16 chunks of 32 rows
