@@ -93,3 +93,22 @@ def test_torch_adam_through_the_function_recovers_a_displaced_copy():
         opt.step()
     T1 = float(ShapeAlignFn.apply(pose.detach(), eng, A, B, None, None, 512, 0))
     assert T0 < 0.8 and T1 > 0.95, (T0, T1)
+
+
+def test_seed_budget_rule():
+    """Budgets from a predicted per-sample SE scale sigma: SE(T) = sigma / sqrt(n)
+    reaches tau at n = (sigma / tau)^2, taken in whole rounds within
+    [round, cap]."""
+    from types import SimpleNamespace
+
+    from paper_2607_20766_amd.surrogate import Triage
+
+    cfg = SimpleNamespace(tau=0.005, round_per_pair=512, cap_per_pair=65536)
+    need = np.array([1.0, 511.0, 512.5, 4095.0, 4097.0, 65535.0, 1e6])
+    sigma = cfg.tau * np.sqrt(need)
+    n = Triage.seed_budget(cfg, np.log(sigma))
+    want = np.array([512, 512, 1024, 4096, 4608, 65536, 65536])
+    assert np.array_equal(n, want), n
+    # every budget meets the target at its own sigma, unless capped
+    se = sigma / np.sqrt(n)
+    assert np.all((se <= cfg.tau * (1 + 1e-12)) | (n == cfg.cap_per_pair))
