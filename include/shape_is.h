@@ -412,7 +412,7 @@ int shape_apply_pose(shape_ctx* ctx, const shape_mols* M, const float* pose, voi
 /* ------------------------------------------------------------------------
  * Learned triage (an addition to the paper's method: a surrogate that ranks a
  * library cheaply so that confidence-bounded IS refines only the head of the
- * ranking; IS stays the judge of every reported value).
+ * ranking; IS stays the arbiter of every reported value).
  * ------------------------------------------------------------------------ */
 
 /* Per-molecule features, 24 floats each (out: device float [n_mols][24]):

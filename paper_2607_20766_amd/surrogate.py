@@ -7,7 +7,7 @@ standard error, log(SE(T) sqrt(n)).  Trained on labels produced by the IS
 screening kernel itself, it ranks a library so that confidence-bounded IS
 refines only the head of the ranking, with per-pair sample budgets seeded
 from the predicted scale (n = (sigma / tau)^2).  IS is both the fallback and
-the judge: every reported Tanimoto comes from IS.
+the arbiter: every reported Tanimoto comes from IS.
 
 Every arithmetic step runs in the HIP library (features, pair features,
 dense layers, loss, Adam, top-k, IS); this module orders the calls.  Small

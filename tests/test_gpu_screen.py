@@ -121,7 +121,7 @@ def test_adaptive_tiny_and_huge_tau(eng, small_lib):
 
 
 def test_full_library_sampled_pairs(eng):
-    """configs[1] workload: 30-atom query vs 100,000 molecules (10-50 atoms),
+    """The 100,000-molecule screen: 30-atom query vs 100,000 molecules (10-50 atoms),
     4096 samples per side; 96 pairs spread over the library checked against
     the oracle one by one."""
     q = molgen.molecule(1, 0, 30)
