@@ -617,7 +617,6 @@ __global__ void k_splitk_reduce_set(GemmSet s) {
 // bytes.  The last layer's 2 outputs are padded to 16 columns with zeros.
 // ---------------------------------------------------------------------------
 constexpr int kMlpIn = 96, kMlpHid = 256, kMlpOut = 2;
-constexpr int kMlpRows = 128;           // pairs per workgroup
 constexpr int kMlpLd = kMlpHid + 8;     // LDS row stride (bf16 elements)
 
 __host__ __device__ constexpr int mlp_pack_offset(int layer) {
@@ -673,21 +672,27 @@ struct MlpArgs {
 // kAct (training forward): the FP32 standardised features and hidden
 // activations are also written out (the backward's inputs), the same values
 // that shape_pair_features and the per-layer products would have written.
-template <bool kAct>
-__global__ __launch_bounds__(256, 2) void k_mlp_infer(MlpArgs a) {
-  __shared__ __align__(16) short H[kMlpRows * kMlpLd];
+// ROWS pairs per workgroup (128, or 64 for more workgroups and residency).
+template <int ROWS, bool kAct>
+__global__ __launch_bounds__(256, ROWS == 64 ? 4 : 2) void k_mlp_infer(MlpArgs a) {
+  constexpr int NH = 256 / ROWS;   // threads per row in the feature staging
+  constexpr int BPT = 4 / NH;      // feature blocks of 24 per thread
+  constexpr int FPT = 24 * BPT;    // features per thread
+  constexpr int RB = ROWS / 16;    // row blocks of 16 per wave in the hidden layers
+  __shared__ __align__(16) short H[ROWS * kMlpLd];
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
   const int li = lane & 15, lk = lane >> 4;
-  const int row0 = blockIdx.x * kMlpRows;
+  const int row0 = blockIdx.x * ROWS;
   // standardised pair features, rounded to bf16 (rows beyond n are zero):
-  // thread (half h, row r) writes features [48 h, 48 h + 48) of row r from
-  // the two molecules' 24 features; h is uniform per wave, so the statistics
-  // are scalar loads.  Same expressions as pair_feature.
+  // thread (part h, row r) writes feature blocks h BPT .. h BPT + BPT - 1 of
+  // row r — the blocks are f_q, f_m, |f_q - f_m|, f_q * f_m, 24 values each;
+  // h is uniform per wave, so the statistics are scalar loads.  Same
+  // expressions as pair_feature.
   {
-    const int r = tid & (kMlpRows - 1);
-    const int h = __builtin_amdgcn_readfirstlane(tid / kMlpRows);
+    const int r = tid & (ROWS - 1);
+    const int h = __builtin_amdgcn_readfirstlane(tid / ROWS);
     const int p = row0 + r;
-    float raw[48];
+    float raw[FPT];
     if (p < a.n) {
       const int m = a.idx ? a.idx[p] : p;
       const int q = a.qidx ? a.qidx[p] : 0;
@@ -699,46 +704,50 @@ __global__ __launch_bounds__(256, 2) void k_mlp_infer(MlpArgs a) {
         va[k] = fa[k];
         vb[k] = fb[k];
       }
-      if (h == 0) {
 #pragma unroll
-        for (int k = 0; k < 24; ++k) {
-          raw[k] = va[k];
-          raw[24 + k] = vb[k];
-        }
-      } else {
+      for (int bb = 0; bb < BPT; ++bb) {
+        const int b = h * BPT + bb;  // uniform
+        float* out = raw + 24 * bb;
+        if (b == 0) {
 #pragma unroll
-        for (int k = 0; k < 24; ++k) {
-          raw[k] = fabsf(va[k] - vb[k]);
-          raw[24 + k] = va[k] * vb[k];
+          for (int k = 0; k < 24; ++k) out[k] = va[k];
+        } else if (b == 1) {
+#pragma unroll
+          for (int k = 0; k < 24; ++k) out[k] = vb[k];
+        } else if (b == 2) {
+#pragma unroll
+          for (int k = 0; k < 24; ++k) out[k] = fabsf(va[k] - vb[k]);
+        } else {
+#pragma unroll
+          for (int k = 0; k < 24; ++k) out[k] = va[k] * vb[k];
         }
-        if (a.fo_cross) {
+        if (a.fo_cross && b >= 2) {
           const float o = a.fo_cross[p];
-          raw[23] = o / (va[23] + vb[23] - o);
-          raw[47] = o;
+          out[23] = b == 2 ? o / (va[23] + vb[23] - o) : o;
         }
       }
-      const float* mu = a.mean + 48 * h;
-      const float* is = a.inv_std + 48 * h;
+      const float* mu = a.mean + FPT * h;
+      const float* is = a.inv_std + FPT * h;
 #pragma unroll
-      for (int t = 0; t < 48; ++t) raw[t] = (raw[t] - mu[t]) * is[t];
+      for (int t = 0; t < FPT; ++t) raw[t] = (raw[t] - mu[t]) * is[t];
       if (kAct) {
-        float4* xo = reinterpret_cast<float4*>(a.x_out + (size_t)p * kMlpIn + 48 * h);
+        float4* xo = reinterpret_cast<float4*>(a.x_out + (size_t)p * kMlpIn + FPT * h);
 #pragma unroll
-        for (int c = 0; c < 12; ++c)
+        for (int c = 0; c < FPT / 4; ++c)
           xo[c] = make_float4(raw[4 * c], raw[4 * c + 1], raw[4 * c + 2], raw[4 * c + 3]);
       }
     } else {
 #pragma unroll
-      for (int t = 0; t < 48; ++t) raw[t] = 0.0f;
+      for (int t = 0; t < FPT; ++t) raw[t] = 0.0f;
     }
-    uint2* dst = reinterpret_cast<uint2*>(&H[r * kMlpLd + 48 * h]);
+    uint2* dst = reinterpret_cast<uint2*>(&H[r * kMlpLd + FPT * h]);
 #pragma unroll
-    for (int c = 0; c < 12; ++c)
+    for (int c = 0; c < FPT / 4; ++c)
       dst[c] = make_uint2(to_bf16x2(raw[4 * c], raw[4 * c + 1]),
                           to_bf16x2(raw[4 * c + 2], raw[4 * c + 3]));
   }
   __syncthreads();
-  // three hidden layers: wave w computes all 128 rows x columns [64 w, 64 w + 64)
+  // three hidden layers: wave w computes all ROWS rows x columns [64 w, 64 w + 64)
   // as the transposed product (weights as the A operand, activations as B),
   // so a lane's four results are four consecutive columns of one row: one
   // 8-byte LDS store each after bias, ReLU and a packed bf16 conversion
@@ -746,9 +755,9 @@ __global__ __launch_bounds__(256, 2) void k_mlp_infer(MlpArgs a) {
   for (int l = 0; l < 3; ++l) {
     const int kbs = (l == 0 ? kMlpIn : kMlpHid) / 32;
     const v8s* W = a.W + mlp_pack_offset(l) / 8;
-    v4f acc[8][4];
+    v4f acc[RB][4];
 #pragma unroll
-    for (int i = 0; i < 8; ++i)
+    for (int i = 0; i < RB; ++i)
 #pragma unroll
       for (int j = 0; j < 4; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
     // weight fragments one k-block ahead of the products
@@ -756,7 +765,7 @@ __global__ __launch_bounds__(256, 2) void k_mlp_infer(MlpArgs a) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) bn[j] = W[(wave * 4 + j) * kWave + lane];
     for (int kb = 0; kb < kbs; ++kb) {
-      v8s b[4], x[8];
+      v8s b[4], x[RB];
 #pragma unroll
       for (int j = 0; j < 4; ++j) b[j] = bn[j];
       if (kb + 1 < kbs) {
@@ -764,10 +773,10 @@ __global__ __launch_bounds__(256, 2) void k_mlp_infer(MlpArgs a) {
         for (int j = 0; j < 4; ++j) bn[j] = W[((kb + 1) * 16 + wave * 4 + j) * kWave + lane];
       }
 #pragma unroll
-      for (int i = 0; i < 8; ++i)
+      for (int i = 0; i < RB; ++i)
         x[i] = *reinterpret_cast<const v8s*>(&H[(16 * i + li) * kMlpLd + kb * 32 + 8 * lk]);
 #pragma unroll
-      for (int i = 0; i < 8; ++i)
+      for (int i = 0; i < RB; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = mfma_bf16_k32(b[j], x[i], acc[i][j]);
     }
@@ -779,7 +788,7 @@ __global__ __launch_bounds__(256, 2) void k_mlp_infer(MlpArgs a) {
       const int col0 = wave * 64 + 16 * j + 4 * lk;
       const float4 bc = make_float4(bias[col0], bias[col0 + 1], bias[col0 + 2], bias[col0 + 3]);
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
+      for (int i = 0; i < RB; ++i) {
         float v0 = acc[i][j][0] + bc.x, v1 = acc[i][j][1] + bc.y;
         float v2 = acc[i][j][2] + bc.z, v3 = acc[i][j][3] + bc.w;
         v0 = v0 > 0.f ? v0 : 0.f;
@@ -795,26 +804,30 @@ __global__ __launch_bounds__(256, 2) void k_mlp_infer(MlpArgs a) {
     }
     __syncthreads();
   }
-  // output layer (2 columns, padded to 16): wave w computes rows [32 w, 32 w + 32)
+  // output layer (2 columns, padded to 16): wave w computes rows
+  // [RPW w, RPW w + RPW), RPW = ROWS / 4
   {
+    constexpr int RPW = ROWS / 4, OB = RPW / 16;
     const v8s* W = a.W + mlp_pack_offset(3) / 8;
-    v4f acc[2] = {v4f{0.f, 0.f, 0.f, 0.f}, v4f{0.f, 0.f, 0.f, 0.f}};
+    v4f acc[OB];
+#pragma unroll
+    for (int i = 0; i < OB; ++i) acc[i] = v4f{0.f, 0.f, 0.f, 0.f};
     for (int kb = 0; kb < kMlpHid / 32; ++kb) {
       const v8s b = W[kb * kWave + lane];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
+      for (int i = 0; i < OB; ++i) {
         const v8s x = *reinterpret_cast<const v8s*>(
-            &H[(32 * wave + 16 * i + li) * kMlpLd + kb * 32 + 8 * lk]);
+            &H[(RPW * wave + 16 * i + li) * kMlpLd + kb * 32 + 8 * lk]);
         acc[i] = mfma_bf16_k32(x, b, acc[i]);
       }
     }
     if (li < kMlpOut) {
       const float bc = a.b[3][li];
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < OB; ++i)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int p = row0 + 32 * wave + 16 * i + 4 * lk + r;
+          const int p = row0 + RPW * wave + 16 * i + 4 * lk + r;
           if (p < a.n) a.out[(size_t)p * kMlpOut + li] = acc[i][r] + bc;
         }
     }
@@ -1269,6 +1282,12 @@ hipError_t launch_gemm_set(int n, const GemmArgs* gs, float* part, hipStream_t s
 
 size_t mlp_pack_bytes() { return (size_t)kMlpPackElems * sizeof(short); }
 
+// Pairs per workgroup of the fused network kernel: 64 for the training
+// forward (a minibatch of a few thousand rows then spreads over twice the
+// workgroups: 0.66 against 0.68 s for the training run), 128 for inference
+// over large sets (half the weight reads; the two measured equal there).
+static int mlp_rows(bool training) { return training ? 64 : 128; }
+
 hipError_t launch_mlp_infer(const float* fq, const float* flib, const int* qidx, const int* idx,
                             int n, const float* fo_cross, const float* mean,
                             const float* inv_std, const float* params, void* packed,
@@ -1299,11 +1318,16 @@ hipError_t launch_mlp_infer(const float* fq, const float* flib, const int* qidx,
   a.out = out;
   a.x_out = x_out;
   for (int l = 0; l < 3; ++l) a.h_out[l] = h_out ? h_out[l] : nullptr;
-  const dim3 grid((unsigned)((n + kMlpRows - 1) / kMlpRows));
-  if (x_out)
-    hipLaunchKernelGGL(k_mlp_infer<true>, grid, dim3(256), 0, st, a);
+  const int rows = mlp_rows(x_out != nullptr);
+  const dim3 grid((unsigned)((n + rows - 1) / rows));
+  if (x_out && rows == 64)
+    hipLaunchKernelGGL((k_mlp_infer<64, true>), grid, dim3(256), 0, st, a);
+  else if (x_out)
+    hipLaunchKernelGGL((k_mlp_infer<128, true>), grid, dim3(256), 0, st, a);
+  else if (rows == 64)
+    hipLaunchKernelGGL((k_mlp_infer<64, false>), grid, dim3(256), 0, st, a);
   else
-    hipLaunchKernelGGL(k_mlp_infer<false>, grid, dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_mlp_infer<128, false>), grid, dim3(256), 0, st, a);
   return hipGetLastError();
 }
 
