@@ -137,6 +137,25 @@ int shape_estimate(shape_ctx* ctx, const shape_mols* A, const shape_mols* B,
                    int64_t n_a, int64_t n_b, uint64_t seed, void* stream,
                    shape_result* out);
 
+/* Allocation-free variant of shape_estimate, for callers that cannot allocate
+ * device memory (code that must not call hipMalloc: tight serving loops,
+ * harnesses that forbid allocation).  Same arguments, checks, kernels and
+ * results (bit for bit) as shape_estimate, but the call allocates nothing:
+ * the prepared molecule records, the per-block partial sums and the device
+ * copy of the result live in a fixed array of the library's device code
+ * (about 1.5 MiB, one copy per GPU, held until the process ends), and the
+ * context's own scratch is neither used nor grown.  Limits: n_a and n_b at
+ * most SHAPE_NOALLOC_MAX_SAMPLES, and A->n_atoms, B->n_atoms at most
+ * SHAPE_MAX_ATOMS (else SHAPE_E_RANGE).  Every call on one GPU, from any
+ * context, shares that GPU's array: calls that overlap in time on one GPU
+ * (several host threads, or streams whose work interleaves) race and must be
+ * serialised by the caller.  Synchronises `stream`; SHAPE_E_UNSUPPORTED
+ * during graph capture.  Errors: as shape_estimate. */
+#define SHAPE_NOALLOC_MAX_SAMPLES ((int64_t)1 << 24)
+int shape_estimate_noalloc(shape_ctx* ctx, const shape_mols* A, const shape_mols* B,
+                           int64_t n_a, int64_t n_b, uint64_t seed, void* stream,
+                           shape_result* out);
+
 #define SHAPE_SCREEN_FIXED 0
 #define SHAPE_SCREEN_ADAPTIVE 1
 

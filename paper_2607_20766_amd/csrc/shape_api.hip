@@ -65,12 +65,56 @@ struct shape_ctx {
   bool capturing = false;         // a graph capture is open on capture_stream
   bool capture_failed = false;    // a call failed while capturing
   hipStream_t capture_stream = nullptr;
+  void* noalloc = nullptr;        // device address of this GPU's copy of `scratch`
 };
 
 struct shape_graph {
   hipGraphExec_t exec = nullptr;
   int device = -1;
 };
+
+// ---------------------------------------------------------------------------
+// Fixed scratch of shape_estimate_noalloc: a file-scope device array, one copy
+// per GPU (each GPU's copy has its own address, looked up once per context at
+// creation), held until the process ends.  Host code never passes the array's
+// name to a kernel: in host code it is only a stand-in symbol.  Layout: the
+// prepared records of the two one-molecule sets (at most SHAPE_MAX_ATOMS atoms
+// each), the per-block partial sums of est_blocks(SHAPE_NOALLOC_MAX_SAMPLES)
+// blocks per side, and the device copy of the result.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct NoallocLayout {
+  size_t atom[2], samp[2], Z, id, bad, centre, partials, result, total;
+  int max_blocks;
+  NoallocLayout() {
+    size_t o = 0;
+    auto take = [&o](size_t bytes) {
+      const size_t at = o;
+      o += (bytes + 255) & ~(size_t)255;
+      return at;
+    };
+    for (int s = 0; s < 2; ++s) {
+      atom[s] = take(SHAPE_MAX_ATOMS * sizeof(shape::Atom));
+      samp[s] = take(SHAPE_MAX_ATOMS * sizeof(shape::AtomSampling));
+    }
+    Z = take(2 * sizeof(double));
+    id = take(2 * sizeof(uint32_t));
+    bad = take(2 * sizeof(int));
+    centre = take(2 * sizeof(float4));
+    max_blocks = shape::est_blocks(SHAPE_NOALLOC_MAX_SAMPLES);
+    partials = take((size_t)2 * max_blocks * shape::kEstSums * sizeof(double));
+    result = take(sizeof(shape_result));
+    total = o;
+  }
+};
+
+// 2 x 8192 blocks x 11 doubles of partials dominate: 1.39 MiB in all
+constexpr size_t kNoallocScratchBytes = (size_t)3 << 19;  // 1.5 MiB
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
 
 namespace {
 
@@ -358,7 +402,11 @@ int shape_create(shape_ctx** out, int device) {
   e = hipSetDevice(device);
   if (e == hipSuccess) e = hipMalloc(&c->flag, 3 * sizeof(int));
   if (e == hipSuccess) e = hipMemset(c->flag, 0, 3 * sizeof(int));
+  // this device's copy of the allocation-free entry point's scratch (the
+  // device is current here; every GPU holds the array at its own address)
+  if (e == hipSuccess) e = hipGetSymbolAddress(&c->noalloc, HIP_SYMBOL(scratch));
   if (e != hipSuccess) {
+    if (c->flag) (void)hipFree(c->flag);
     delete c;
     return fail(nullptr, SHAPE_E_HIP, "context set-up: %s", hipGetErrorString(e));
   }
@@ -404,20 +452,37 @@ int shape_alpha_from_radius(shape_ctx* c, const float* radius, int64_t n, double
   }
 }
 
+}  // extern "C"
+
+namespace {
+
+// Argument checks shared by shape_estimate and shape_estimate_noalloc.
+int estimate_check(shape_ctx* c, const shape_mols* A, const shape_mols* B, int64_t n_a,
+                   int64_t n_b, const shape_result* out, int64_t max_n) {
+  int rc;
+  if ((rc = check_mols(c, A, "A", true))) return rc;
+  if ((rc = check_mols(c, B, "B", true))) return rc;
+  if (!out) return fail(c, SHAPE_E_INVAL, "out is NULL");
+  if (n_a < 2 || n_b < 2 || n_a > max_n || n_b > max_n)
+    return fail(c, SHAPE_E_RANGE, "sample counts must lie in [2, %lld]", (long long)max_n);
+  const int anti = c->sampling == SHAPE_SAMPLING_ANTITHETIC ? 1 : 0;
+  if (anti && (n_a % 2 || n_b % 2 || n_a < 4 || n_b < 4))
+    return fail(c, SHAPE_E_RANGE, "antithetic sampling needs even sample counts >= 4");
+  return SHAPE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int shape_estimate(shape_ctx* c, const shape_mols* A, const shape_mols* B, int64_t n_a,
                    int64_t n_b, uint64_t seed, void* stream, shape_result* out) {
   if (!c) return SHAPE_E_INVAL;
   if (c->capturing) return refuse_in_capture(c, "shape_estimate");
   try {
     int rc;
-    if ((rc = check_mols(c, A, "A", true))) return rc;
-    if ((rc = check_mols(c, B, "B", true))) return rc;
-    if (!out) return fail(c, SHAPE_E_INVAL, "out is NULL");
-    if (n_a < 2 || n_b < 2 || n_a > (int64_t)1 << 31 || n_b > (int64_t)1 << 31)
-      return fail(c, SHAPE_E_RANGE, "sample counts must lie in [2, 2^31]");
+    if ((rc = estimate_check(c, A, B, n_a, n_b, out, (int64_t)1 << 31))) return rc;
     const int anti = c->sampling == SHAPE_SAMPLING_ANTITHETIC ? 1 : 0;
-    if (anti && (n_a % 2 || n_b % 2 || n_a < 4 || n_b < 4))
-      return fail(c, SHAPE_E_RANGE, "antithetic sampling needs even sample counts >= 4");
     if ((rc = set_device(c))) return rc;
     hipStream_t st = (hipStream_t)stream;
     shape::Prepared PA, PB;
@@ -445,6 +510,67 @@ int shape_estimate(shape_ctx* c, const shape_mols* A, const shape_mols* B, int64
                                       (shape_result*)res, st),
             "estimate kernels");
     timer.stop();
+    HIP_TRY(c, hipMemcpyAsync(out, res, sizeof(shape_result), hipMemcpyDeviceToHost, st),
+            "result copy");
+    HIP_TRY(c, hipStreamSynchronize(st), "hipStreamSynchronize");
+    return SHAPE_OK;
+  } catch (...) {
+    return fail(c, SHAPE_E_HIP, "internal error");
+  }
+}
+
+int shape_estimate_noalloc(shape_ctx* c, const shape_mols* A, const shape_mols* B,
+                           int64_t n_a, int64_t n_b, uint64_t seed, void* stream,
+                           shape_result* out) {
+  if (!c) return SHAPE_E_INVAL;
+  if (c->capturing) return refuse_in_capture(c, "shape_estimate_noalloc");
+  try {
+    int rc;
+    if ((rc = estimate_check(c, A, B, n_a, n_b, out, SHAPE_NOALLOC_MAX_SAMPLES))) return rc;
+    // records are written at atom_offset[0] + i < n_atoms: the whole set must
+    // fit the fixed per-side staging
+    if (A->n_atoms > SHAPE_MAX_ATOMS || B->n_atoms > SHAPE_MAX_ATOMS)
+      return fail(c, SHAPE_E_RANGE, "n_atoms of A and B must be at most %d here",
+                  SHAPE_MAX_ATOMS);
+    const NoallocLayout L;
+    if (L.total > kNoallocScratchBytes || !c->noalloc)
+      return fail(c, SHAPE_E_HIP, "fixed scratch unavailable");
+    const int anti = c->sampling == SHAPE_SAMPLING_ANTITHETIC ? 1 : 0;
+    if ((rc = set_device(c))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    char* base = (char*)c->noalloc;  // this GPU's copy, never the symbol's name
+    shape::Prepared P[2];
+    const shape_mols* M[2] = {A, B};
+    for (int s = 0; s < 2; ++s) {
+      P[s].atom = (shape::Atom*)(base + L.atom[s]);
+      P[s].samp = (shape::AtomSampling*)(base + L.samp[s]);
+      P[s].Z = (double*)(base + L.Z) + s;
+      P[s].id = (uint32_t*)(base + L.id) + s;
+      P[s].bad = (int*)(base + L.bad) + s;
+      P[s].centre = (float4*)(base + L.centre) + s;
+      const shape::MolsDev in{M[s]->n_mols,     M[s]->max_atoms, M[s]->n_atoms,
+                              M[s]->atom_offset, M[s]->xyz,       M[s]->alpha,
+                              M[s]->mol_id};
+      // every record the kernels read below is written here (the one
+      // molecule's Z, id, flag, centre and its atoms): nothing has to start
+      // at zero
+      HIP_TRY(c, shape::launch_prepare(in, P[s], c->flag, nullptr, st), "prepare kernel");
+    }
+    const int64_t units = (n_a > n_b ? n_a : n_b) / (anti ? 2 : 1);
+    const int nblk = shape::est_blocks(units);  // <= L.max_blocks by the range check
+    int bad[2] = {0, 0};
+    HIP_TRY(c, hipMemcpyAsync(bad, base + L.bad, sizeof bad, hipMemcpyDeviceToHost, st),
+            "copy");
+    HIP_TRY(c, hipStreamSynchronize(st), "hipStreamSynchronize");
+    if (bad[0] || bad[1]) {
+      HIP_TRY(c, shape::launch_fill_int(c->flag, 1, 0, st), "flag reset");
+      return fail(c, SHAPE_E_DATA, "invalid molecule data in %s", bad[0] ? "A" : "B");
+    }
+    shape_result* res = (shape_result*)(base + L.result);
+    HIP_TRY(c, shape::launch_estimate(P[0], P[1], A->atom_offset, B->atom_offset, n_a, n_b,
+                                      key_of(seed), anti, (double*)(base + L.partials), nblk,
+                                      res, st),
+            "estimate kernels");
     HIP_TRY(c, hipMemcpyAsync(out, res, sizeof(shape_result), hipMemcpyDeviceToHost, st),
             "result copy");
     HIP_TRY(c, hipStreamSynchronize(st), "hipStreamSynchronize");

@@ -97,6 +97,9 @@ def load_library():
         L.shape_alpha_from_radius.argtypes = [vp, vp, i64, d, vp, vp]
         L.shape_estimate.argtypes = [vp, ctypes.POINTER(ShapeMols), ctypes.POINTER(ShapeMols),
                                      i64, i64, u64, vp, ctypes.POINTER(ShapeResult)]
+        L.shape_estimate_noalloc.argtypes = [vp, ctypes.POINTER(ShapeMols),
+                                             ctypes.POINTER(ShapeMols), i64, i64, u64, vp,
+                                             ctypes.POINTER(ShapeResult)]
         L.shape_screen.argtypes = [vp, ctypes.POINTER(ShapeMols), ctypes.POINTER(ShapeMols),
                                    vp, i32, ctypes.POINTER(ShapeScreenParams), vp,
                                    ctypes.POINTER(ShapeScreenOut)]
@@ -260,6 +263,19 @@ class Engine:
         self._check(load_library().shape_estimate(self._ctx, ctypes.byref(a), ctypes.byref(b),
                                                   int(n_a), int(n_b), int(seed),
                                                   _stream(stream), ctypes.byref(res)))
+        out = {f: getattr(res, f) for f in RESULT_FIELDS}
+        out["n_a"], out["n_b"] = res.n_a, res.n_b
+        return out
+
+    def shape_estimate_noalloc(self, A: Molecules, B: Molecules, n_a: int, n_b: int,
+                               seed: int = 0, stream=None) -> dict:
+        """shape_estimate through the allocation-free entry point (fixed
+        scratch in the library; n_a, n_b <= 2^24, at most 256 atoms per set)."""
+        res = ShapeResult()
+        a, b = A.c_struct(), B.c_struct()
+        self._check(load_library().shape_estimate_noalloc(
+            self._ctx, ctypes.byref(a), ctypes.byref(b), int(n_a), int(n_b), int(seed),
+            _stream(stream), ctypes.byref(res)))
         out = {f: getattr(res, f) for f in RESULT_FIELDS}
         out["n_a"], out["n_b"] = res.n_a, res.n_b
         return out
