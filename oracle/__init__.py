@@ -55,7 +55,8 @@ def lib():
         L.or_densities.argtypes = [_i, _f32p, _f32p, _i64, _f64p, _f64p, _f64p]
         L.or_estimate.argtypes = [_i, _f32p, _f32p, _u32, _i, _f32p, _f32p, _u32,
                                   _i64, _i64, _u64, _i, _f64p]
-        L.or_screen.argtypes = [_i, _f32p, _f32p, _u32, _i32p, _f32p, _f32p, _vp, _vp,
+        L.or_screen.argtypes = [_i, _f32p, _f32p, _u32, ctypes.c_int32, _i32p, _f32p, _f32p,
+                                _vp, _vp,
                                 ctypes.c_int32, _i, _i64, _i64, _i64, _d, _u64, _i, _vp, _i,
                                 _f64p]
         L.or_fo_overlap.argtypes = [_i, _f32p, _f32p, _i, _f32p, _f32p]
@@ -164,7 +165,10 @@ def estimate(A, B, n_a, n_b, seed=0, id_a=0, id_b=1, antithetic=False) -> dict:
 def screen(query, id_q, lib_off, lib_xyz, lib_alpha, lib_id=None, pairs=None,
            mode=0, n_fixed=4096, round_per_pair=512, cap_per_pair=65536,
            tau=0.005, seed=0, n_threads=0, n_start=None, antithetic=False):
-    """Returns [n_pairs, 6] = T, se_T, O_ab, O_aa, O_bb, n_used (pair total)."""
+    """Returns [n_pairs, 6] = T, se_T, O_ab, O_aa, O_bb, n_used (pair total).
+    A pair index outside the library gives NaN and n_used 0.  Raises
+    ValueError for parameters the rounds cannot follow (odd or non-positive
+    rounds, a cap that is not a whole number of rounds, tau <= 0)."""
     xq, aq = _mol(*query)
     off = np.ascontiguousarray(lib_off, np.int32)
     lx = np.ascontiguousarray(lib_xyz, np.float32).reshape(-1, 3)
@@ -174,12 +178,14 @@ def screen(query, id_q, lib_off, lib_xyz, lib_alpha, lib_id=None, pairs=None,
     n_pairs = off.size - 1 if pr is None else pr.size
     ns = None if n_start is None else np.ascontiguousarray(n_start, np.int32)
     out = np.zeros((n_pairs, 6))
-    rc = lib().or_screen(aq.size, xq, aq, id_q, off, lx, la,
+    rc = lib().or_screen(aq.size, xq, aq, id_q, off.size - 1, off, lx, la,
                          None if ids is None else ids.ctypes.data,
                          None if pr is None else pr.ctypes.data, n_pairs, mode,
                          n_fixed, round_per_pair, cap_per_pair, tau, seed,
                          n_threads, None if ns is None else ns.ctypes.data,
                          int(bool(antithetic)), out)
+    if rc == -2:
+        raise ValueError("oracle screen: parameters outside the rules of the rounds")
     if rc:
         raise RuntimeError("oracle screen failed")
     return out

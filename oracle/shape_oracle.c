@@ -393,11 +393,23 @@ int or_estimate(int na_atoms, const float* xyz_a, const float* alpha_a, uint32_t
 /* Outputs per pair (double): T, se_T, O_ab, O_aa, O_bb, n_used (pair total). */
 /* ------------------------------------------------------------------------- */
 int or_screen(int nq, const float* xyz_q, const float* alpha_q, uint32_t id_q,
-              const int32_t* lib_off, const float* lib_xyz, const float* lib_alpha,
-              const uint32_t* lib_id, const int32_t* pairs, int32_t n_pairs,
-              int mode, int64_t n_fixed, int64_t round_per_pair, int64_t cap_per_pair,
-              double tau, uint64_t seed, int n_threads, const int32_t* n_start,
-              int anti, double* out6) {
+              int32_t n_lib, const int32_t* lib_off, const float* lib_xyz,
+              const float* lib_alpha, const uint32_t* lib_id, const int32_t* pairs,
+              int32_t n_pairs, int mode, int64_t n_fixed, int64_t round_per_pair,
+              int64_t cap_per_pair, double tau, uint64_t seed, int n_threads,
+              const int32_t* n_start, int anti, double* out6) {
+  /* the rules the rounds rely on: whole rounds of equal halves per side (of
+   * even length for antithetic pairs), and a cap of whole rounds */
+  if (nq < 1 || n_pairs < 0 || n_lib < 0) return -2;
+  if (mode == 0) {
+    if (n_fixed < 2 || (anti && (n_fixed < 4 || (n_fixed & 1)))) return -2;
+  } else if (mode == 1) {
+    if (round_per_pair < 2 || (round_per_pair & 1) || (anti && (round_per_pair & 3))) return -2;
+    if (cap_per_pair < round_per_pair || cap_per_pair % round_per_pair) return -2;
+    if (!(tau > 0.0) || !isfinite(tau)) return -2;
+  } else {
+    return -2;
+  }
   or_mol Q;
   if (or_mol_init(&Q, nq, xyz_q, alpha_q)) return -1;
   int err = 0;
@@ -407,6 +419,12 @@ int or_screen(int nq, const float* xyz_q, const float* alpha_q, uint32_t id_q,
 #endif
   for (int32_t p = 0; p < n_pairs; ++p) {
     int32_t m = pairs ? pairs[p] : p;
+    if (m < 0 || m >= n_lib) {
+      /* a pair index outside the library scores nothing */
+      for (int j = 0; j < 5; ++j) out6[6 * (size_t)p + j] = NAN;
+      out6[6 * (size_t)p + 5] = 0.0;
+      continue;
+    }
     int32_t a0 = lib_off[m], a1 = lib_off[m + 1];
     uint32_t idm = lib_id ? lib_id[m] : (uint32_t)m;
     or_mol B;
@@ -427,6 +445,7 @@ int or_screen(int nq, const float* xyz_q, const float* alpha_q, uint32_t id_q,
         /* round: samples [n, n + side_round) on each side */
         double* ra = (double*)malloc(sizeof(double) * NF * (size_t)side_round);
         double* rb = (double*)malloc(sizeof(double) * NF * (size_t)side_round);
+        if (!ra || !rb) { free(ra); free(rb); err |= 1; break; }
         or_side_integrands(&Q, &B, id_q, seed, n, n + side_round, anti, ra);
         or_side_integrands(&B, &Q, idm, seed, n, n + side_round, anti, rb);
         int64_t nn = n + side_round;
@@ -451,6 +470,7 @@ int or_screen(int nq, const float* xyz_q, const float* alpha_q, uint32_t id_q,
         if (r.se_T <= tau || 2 * n >= cap_per_pair) break;
       }
       free(fa); free(fb); free(ta); free(tb);
+      if (n == 0) { or_mol_free(&B); continue; }
     }
     out6[6 * (size_t)p + 0] = r.T;
     out6[6 * (size_t)p + 1] = r.se_T;
@@ -761,7 +781,7 @@ static int or_align_setup(const or_mol* A, const or_mol* B, uint32_t id_a, uint3
                           int64_t n, uint64_t seed, or_align_fixed* F) {
   F->ra = (double*)malloc(sizeof(double) * 3 * (size_t)n);
   F->wa = (double*)malloc(sizeof(double) * (size_t)n);
-  if (!F->ra || !F->wa) return -1;
+  if (!F->ra || !F->wa) { free(F->ra); free(F->wa); return -1; }
   for (int64_t k = 0; k < n; ++k) {
     double m, u;
     or_sample(A, id_a, (uint64_t)k, seed, F->ra + 3 * k);
@@ -783,7 +803,10 @@ int or_align_grad(int na, const float* xyz_a, const float* alpha_a, uint32_t id_
   if (or_mol_init(&A, na, xyz_a, alpha_a)) return -1;
   if (or_mol_init(&B, nb, xyz_b, alpha_b)) { or_mol_free(&A); return -1; }
   or_align_fixed F;
-  if (or_align_setup(&A, &B, id_a, id_b, n_samples, seed, &F)) return -1;
+  if (or_align_setup(&A, &B, id_a, id_b, n_samples, seed, &F)) {
+    or_mol_free(&A); or_mol_free(&B);
+    return -1;
+  }
   for (int32_t p = 0; p < n_poses; ++p)
     or_align_eval(&A, &B, id_a, F.ra, F.wa, n_samples, F.O_aa, F.O_bb, poses + 7 * p,
                   T_out + p, NULL, grad_out + 7 * p);
@@ -791,6 +814,28 @@ int or_align_grad(int na, const float* xyz_a, const float* alpha_a, uint32_t id_
   free(F.ra); free(F.wa);
   or_mol_free(&A); or_mol_free(&B);
   return 0;
+}
+
+/* Adam (Kingma and Ba) on a flat parameter vector, step t >= 1, descending. */
+void or_adam(int64_t n, double* p, const double* g, double* m, double* v, int32_t t, double lr,
+             double b1, double b2, double eps) {
+  for (int64_t i = 0; i < n; ++i) {
+    m[i] = b1 * m[i] + (1 - b1) * g[i];
+    v[i] = b2 * v[i] + (1 - b2) * g[i] * g[i];
+    double mh = m[i] / (1 - pow(b1, t)), vh = v[i] / (1 - pow(b2, t));
+    p[i] -= lr * mh / (sqrt(vh) + eps);
+  }
+}
+
+/* One ascent step on T for a pose: Adam descends on -dT/dpose, then the
+ * quaternion part is renormalised. */
+static void or_pose_adam_step(double x[7], const double dT[7], double m[7], double v[7],
+                              int32_t t, double lr) {
+  double g[7];
+  for (int i = 0; i < 7; ++i) g[i] = -dT[i];
+  or_adam(7, x, g, m, v, t, lr, 0.9, 0.999, 1e-8);
+  double qn = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2] + x[3] * x[3]);
+  for (int i = 0; i < 4; ++i) x[i] /= qn;
 }
 
 /* Adam (Kingma and Ba) on -T over the seven pose parameters, renormalising q
@@ -804,23 +849,16 @@ int or_align_adam(int na, const float* xyz_a, const float* alpha_a, uint32_t id_
   if (or_mol_init(&A, na, xyz_a, alpha_a)) return -1;
   if (or_mol_init(&B, nb, xyz_b, alpha_b)) { or_mol_free(&A); return -1; }
   or_align_fixed F;
-  if (or_align_setup(&A, &B, id_a, id_b, n_samples, seed, &F)) return -1;
-  const double b1 = 0.9, b2 = 0.999, eps = 1e-8;
+  if (or_align_setup(&A, &B, id_a, id_b, n_samples, seed, &F)) {
+    or_mol_free(&A); or_mol_free(&B);
+    return -1;
+  }
   for (int32_t s = 0; s < n_starts; ++s) {
     double x[7], m[7] = {0}, v[7] = {0}, g[7], T;
     memcpy(x, pose0 + 7 * s, sizeof x);
     for (int32_t it = 1; it <= n_steps; ++it) {
       or_align_eval(&A, &B, id_a, F.ra, F.wa, n_samples, F.O_aa, F.O_bb, x, &T, NULL, g);
-      for (int i = 0; i < 7; ++i) {
-        double gi = -g[i]; /* minimise -T */
-        m[i] = b1 * m[i] + (1 - b1) * gi;
-        v[i] = b2 * v[i] + (1 - b2) * gi * gi;
-        double mh = m[i] / (1 - pow(b1, it));
-        double vh = v[i] / (1 - pow(b2, it));
-        x[i] -= lr * mh / (sqrt(vh) + eps);
-      }
-      double qn = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2] + x[3] * x[3]);
-      for (int i = 0; i < 4; ++i) x[i] /= qn;
+      or_pose_adam_step(x, g, m, v, it, lr);
     }
     or_align_eval(&A, &B, id_a, F.ra, F.wa, n_samples, F.O_aa, F.O_bb, x, &T, NULL, g);
     memcpy(pose_out + 7 * s, x, sizeof x);
@@ -913,22 +951,12 @@ int or_fo_align_adam(int na, const float* xyz_a, const float* alpha_a, int nb,
   if (or_mol_init(&B, nb, xyz_b, alpha_b)) { or_mol_free(&A); return -1; }
   double O_aa = or_fo_overlap(na, xyz_a, alpha_a, na, xyz_a, alpha_a);
   double O_bb = or_fo_overlap(nb, xyz_b, alpha_b, nb, xyz_b, alpha_b);
-  const double b1 = 0.9, b2 = 0.999, eps = 1e-8;
   for (int32_t s = 0; s < n_starts; ++s) {
     double x[7], m[7] = {0}, v[7] = {0}, g[7], T;
     memcpy(x, pose0 + 7 * s, sizeof x);
     for (int32_t it = 1; it <= n_steps; ++it) {
       or_fo_align_eval(&A, &B, O_aa, O_bb, x, &T, g);
-      for (int i = 0; i < 7; ++i) {
-        double gi = -g[i];
-        m[i] = b1 * m[i] + (1 - b1) * gi;
-        v[i] = b2 * v[i] + (1 - b2) * gi * gi;
-        double mh = m[i] / (1 - pow(b1, it));
-        double vh = v[i] / (1 - pow(b2, it));
-        x[i] -= lr * mh / (sqrt(vh) + eps);
-      }
-      double qn = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2] + x[3] * x[3]);
-      for (int i = 0; i < 4; ++i) x[i] /= qn;
+      or_pose_adam_step(x, g, m, v, it, lr);
     }
     or_fo_align_eval(&A, &B, O_aa, O_bb, x, &T, NULL);
     memcpy(pose_out + 7 * s, x, sizeof x);
@@ -1282,13 +1310,3 @@ int or_mlp_loss_grad(int L, const int32_t* width, const double* params, int32_t 
   return 0;
 }
 
-/* Adam (Kingma and Ba) on a flat parameter vector, step t >= 1, descending. */
-void or_adam(int64_t n, double* p, const double* g, double* m, double* v, int32_t t, double lr,
-             double b1, double b2, double eps) {
-  for (int64_t i = 0; i < n; ++i) {
-    m[i] = b1 * m[i] + (1 - b1) * g[i];
-    v[i] = b2 * v[i] + (1 - b2) * g[i] * g[i];
-    double mh = m[i] / (1 - pow(b1, t)), vh = v[i] / (1 - pow(b2, t));
-    p[i] -= lr * mh / (sqrt(vh) + eps);
-  }
-}
