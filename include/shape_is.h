@@ -156,6 +156,30 @@ int shape_estimate_noalloc(shape_ctx* ctx, const shape_mols* A, const shape_mols
                            int64_t n_a, int64_t n_b, uint64_t seed, void* stream,
                            shape_result* out);
 
+/* The sampling steps of one molecule, exported for exact comparison of the
+ * integer work (section "Importance-sampling estimator": exact draws from the
+ * normalised mixture q = m/Z by integer thresholds, and the reading of the
+ * random-number stream given at the top of this header).  M: a molecule set
+ * (prepared into context scratch like any sampling call); mol: the molecule,
+ * 0 <= mol < M->n_mols; samples k0 .. k0+n-1 (0 <= n <= 2^24, 0 <= k0 <=
+ * 2^62) under the context's sampling scheme (shape_set_sampling).  Outputs,
+ * each a device array or NULL:
+ *   thr    uint32 [atoms of mol]: thresholds floor(2^32 (v_0+..+v_i)/Z) of
+ *          the prepared molecule (the last entry, never compared, is
+ *          0xFFFFFFFF)
+ *   words  uint32 [n][4]: the Philox block of each sample (antithetic
+ *          sampling: block k/2)
+ *   comp   int32 [n]: the selected component #{i < N-1 : words[k][0] >= thr_i}
+ *   r      float32 [n][3]: the sample point c_j + z sd_j (coordinates of M)
+ * The same device functions as every sampling kernel compute these.
+ * Synchronises `stream` once (validity of the molecule) and then queues the
+ * export asynchronously.  Errors: SHAPE_E_INVAL, SHAPE_E_RANGE, SHAPE_E_DATA
+ * (invalid molecule), SHAPE_E_NOMEM, SHAPE_E_HIP; SHAPE_E_UNSUPPORTED during
+ * graph capture. */
+int shape_sample_points(shape_ctx* ctx, const shape_mols* M, int32_t mol, int64_t k0,
+                        int32_t n, uint64_t seed, void* stream, uint32_t* thr,
+                        uint32_t* words, int32_t* comp, float* r);
+
 #define SHAPE_SCREEN_FIXED 0
 #define SHAPE_SCREEN_ADAPTIVE 1
 

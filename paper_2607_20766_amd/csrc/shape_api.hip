@@ -580,6 +580,40 @@ int shape_estimate_noalloc(shape_ctx* c, const shape_mols* A, const shape_mols* 
   }
 }
 
+int shape_sample_points(shape_ctx* c, const shape_mols* M, int32_t mol, int64_t k0, int32_t n,
+                        uint64_t seed, void* stream, uint32_t* thr, uint32_t* words,
+                        int32_t* comp, float* r) {
+  if (!c) return SHAPE_E_INVAL;
+  if (c->capturing) return refuse_in_capture(c, "shape_sample_points");
+  try {
+    int rc;
+    if ((rc = check_mols(c, M, "M", false))) return rc;
+    if (mol < 0 || mol >= M->n_mols)
+      return fail(c, SHAPE_E_RANGE, "mol = %d outside [0, %d)", mol, M->n_mols);
+    if (n < 0 || n > (1 << 24) || k0 < 0 || k0 > ((int64_t)1 << 62))
+      return fail(c, SHAPE_E_RANGE, "need 0 <= n <= 2^24 and 0 <= k0 <= 2^62");
+    if ((rc = set_device(c))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    shape::Prepared P;
+    if ((rc = prepare(c, M, false, st, &P))) return rc;
+    int bad = 0;
+    HIP_TRY(c, hipMemcpyAsync(&bad, P.bad + mol, sizeof(int), hipMemcpyDeviceToHost, st),
+            "copy");
+    HIP_TRY(c, hipStreamSynchronize(st), "hipStreamSynchronize");
+    if (bad) {
+      HIP_TRY(c, shape::launch_fill_int(c->flag, 1, 0, st), "flag reset");
+      return fail(c, SHAPE_E_DATA, "molecule %d is invalid data", mol);
+    }
+    const int anti = c->sampling == SHAPE_SAMPLING_ANTITHETIC ? 1 : 0;
+    HIP_TRY(c, shape::launch_sample_points(P, M->atom_offset, mol, M->max_atoms, k0, n,
+                                           key_of(seed), anti, thr, words, (int*)comp, r, st),
+            "sample points kernel");
+    return SHAPE_OK;
+  } catch (...) {
+    return fail(c, SHAPE_E_HIP, "internal error");
+  }
+}
+
 int shape_screen(shape_ctx* c, const shape_mols* query, const shape_mols* lib,
                  const int32_t* pairs, int32_t n_pairs, const shape_screen_params* prm,
                  void* stream, const shape_screen_out* out) {

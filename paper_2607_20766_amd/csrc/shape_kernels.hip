@@ -613,6 +613,44 @@ __global__ __launch_bounds__(64) void k_screen(ScreenArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Export of the sampling steps of one prepared molecule (section
+// "Importance-sampling estimator": exact draws from the normalised mixture),
+// for exact comparison of the integer steps: the molecule's thresholds, and
+// for samples k0 .. k0+n-1 the Philox block, the selected component and the
+// point, computed by the same device functions as every sampling kernel.
+// One thread per sample (and per atom for the thresholds); records from HBM.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_sample_points(Prepared P, const int* __restrict__ off,
+                                                       int mol, int64_t k0, int n, uint2 key,
+                                                       int anti, uint32_t* __restrict__ thr,
+                                                       uint32_t* __restrict__ words,
+                                                       int* __restrict__ comp,
+                                                       float* __restrict__ r) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int a0 = off[mol], na = off[mol + 1] - a0;
+  const Atom* atoms = P.atom + a0;
+  const AtomSampling* samp = P.samp + a0;
+  if (thr && i < na) thr[i] = samp[i].thr;
+  if (i >= n) return;
+  const uint64_t k = (uint64_t)(k0 + i);
+  const uint64_t blk = anti ? k >> 1 : k;
+  const uint4 x =
+      philox4x32_10(make_uint4((uint32_t)blk, (uint32_t)(blk >> 32), P.id[mol], 0u), key);
+  if (words) reinterpret_cast<uint4*>(words)[i] = x;
+  if (comp) comp[i] = select_component(samp, na, x.x);
+  if (r) {
+    float rx, ry, rz;
+    if (anti)
+      sample_point_anti(atoms, samp, na, P.id[mol], k, key, rx, ry, rz);
+    else
+      sample_point(atoms, samp, na, P.id[mol], k, key, rx, ry, rz);
+    r[3 * (size_t)i] = rx;
+    r[3 * (size_t)i + 1] = ry;
+    r[3 * (size_t)i + 2] = rz;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Host-side launchers.
 // ---------------------------------------------------------------------------
 hipError_t launch_alpha_from_radius(const float* R, int64_t n, double kappa, double lambda,
@@ -665,6 +703,16 @@ hipError_t launch_query_cache(const Prepared& Q, const int* offQ, int64_t n, uin
   const int64_t blocks = (n + 255) / 256;
   hipLaunchKernelGGL(k_query_cache, dim3((unsigned)blocks), dim3(256), 0, st, Q, offQ, n, key,
                      anti, qs, qf2);
+  return hipGetLastError();
+}
+
+hipError_t launch_sample_points(const Prepared& P, const int* off, int mol, int max_atoms,
+                               int64_t k0, int n, uint2 key, int anti, uint32_t* thr,
+                               uint32_t* words, int* comp, float* r, hipStream_t st) {
+  const int threads = n > max_atoms ? n : max_atoms;
+  const int blocks = (threads + 255) / 256;
+  hipLaunchKernelGGL(k_sample_points, dim3(blocks), dim3(256), 0, st, P, off, mol, k0, n, key,
+                     anti, thr, words, comp, r);
   return hipGetLastError();
 }
 

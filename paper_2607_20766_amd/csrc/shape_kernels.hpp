@@ -196,6 +196,11 @@ hipError_t launch_estimate(const Prepared& A, const Prepared& B, const int* offA
                            double* partials, int nblk, shape_result* out_dev, hipStream_t st);
 hipError_t launch_query_cache(const Prepared& Q, const int* offQ, int64_t n, uint2 key, int anti,
                               float4* qs, float* qf2, hipStream_t st);
+// sampling steps of one prepared molecule (thresholds, Philox words,
+// components, points); n samples from counter k0
+hipError_t launch_sample_points(const Prepared& P, const int* off, int mol, int max_atoms,
+                               int64_t k0, int n, uint2 key, int anti, uint32_t* thr,
+                               uint32_t* words, int* comp, float* r, hipStream_t st);
 size_t screen_lds_bytes(int max_q, int max_b);
 constexpr int kScreenVariants = 8;
 extern const int kScreenVariantShape[kScreenVariants][2];  // {kSA, kSB}

@@ -100,6 +100,8 @@ def load_library():
         L.shape_estimate_noalloc.argtypes = [vp, ctypes.POINTER(ShapeMols),
                                              ctypes.POINTER(ShapeMols), i64, i64, u64, vp,
                                              ctypes.POINTER(ShapeResult)]
+        L.shape_sample_points.argtypes = [vp, ctypes.POINTER(ShapeMols), i32, i64, i32, u64,
+                                          vp, vp, vp, vp, vp]
         L.shape_screen.argtypes = [vp, ctypes.POINTER(ShapeMols), ctypes.POINTER(ShapeMols),
                                    vp, i32, ctypes.POINTER(ShapeScreenParams), vp,
                                    ctypes.POINTER(ShapeScreenOut)]
@@ -278,6 +280,27 @@ class Engine:
             _stream(stream), ctypes.byref(res)))
         out = {f: getattr(res, f) for f in RESULT_FIELDS}
         out["n_a"], out["n_b"] = res.n_a, res.n_b
+        return out
+
+    def shape_sample_points(self, M: Molecules, mol: int, k0: int, n: int, seed: int = 0,
+                            stream=None) -> dict:
+        """The GPU's sampling steps for molecule `mol` of M, samples k0..k0+n-1:
+        thresholds (uint32 bit patterns in int32 [atoms]), Philox words
+        [n, 4], components [n] and points [n, 3] (device tensors)."""
+        dev = self.torch_device
+        na = (int(M.offsets[mol + 1].item() - M.offsets[mol].item())
+              if 0 <= mol < M.n_mols else 1)
+        out = {"thr": torch.empty(max(na, 1), dtype=torch.int32, device=dev),
+               "words": torch.empty(max(n, 1), 4, dtype=torch.int32, device=dev),
+               "comp": torch.empty(max(n, 1), dtype=torch.int32, device=dev),
+               "r": torch.empty(max(n, 1), 3, dtype=torch.float32, device=dev)}
+        m = M.c_struct()
+        self._check(load_library().shape_sample_points(
+            self._ctx, ctypes.byref(m), int(mol), int(k0), int(n), int(seed), _stream(stream),
+            _ptr(out["thr"]), _ptr(out["words"]), _ptr(out["comp"]), _ptr(out["r"])))
+        out["thr"] = out["thr"][:na]
+        for k in ("words", "comp", "r"):
+            out[k] = out[k][:n]
         return out
 
     @staticmethod

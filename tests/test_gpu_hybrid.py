@@ -8,9 +8,9 @@ import torch
 
 import oracle as O
 from paper_2607_20766_amd import molgen
-from paper_2607_20766_amd.engine import SHAPE_SCREEN_ADAPTIVE, Engine, ShapeError
+from paper_2607_20766_amd.engine import LAMBDA_P27, SHAPE_SCREEN_ADAPTIVE, Engine, ShapeError
 from paper_2607_20766_amd.hybrid import HybridScreen
-from tests.gpu_common import oracle_mol, require_gpu
+from tests.gpu_common import compare_adaptive, oracle_mol, require_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -156,6 +156,54 @@ def test_hybrid_screen_end_to_end(eng):
     assert np.all(np.abs(out["se_T"]) <= 0.005 * (1 + 1e-6) + (out["n_used"] == 65536))
 
 
+def _oracle_hybrid_poses(q, L, n_random, n_steps, lr, seed):
+    """The first stage of the hybrid pipeline in the oracle: the starts of
+    each pair, first-order Adam from every start, the best final start."""
+    oq = oracle_mol(O, q)
+    poses = np.empty((L.n_mols, 7))
+    for m in range(L.n_mols):
+        om = oracle_mol(O, L.mol(m))
+        st = O.fo_starts(oq, om, pair_id=m, n_random=n_random, seed=seed)
+        pr, Tr = O.fo_align_adam(oq, om, st, n_steps=n_steps, lr=lr)
+        poses[m] = pr[int(np.argmax(Tr))]
+    return poses
+
+
+def test_superposed_union_scores_match_oracle(eng):
+    """The union stage of the hybrid pipeline on superposed pairs: poses from
+    the oracle's own first-order alignment, applied by shape_apply_pose and
+    scored by the adaptive union screen on the GPU; the oracle moves the
+    library itself (FP64 rotation of the same FP32 pose) and screens it.
+    Parity as for any adaptive screen, at poses far from the given ones."""
+    q = molgen.molecule(1, 0, 30)
+    L = molgen.library(63, 40, 10, 50, workers=1)
+    tau, cap, seed = 0.005, 65536, 2
+    print("case: union IS of superposed pairs (oracle alignment)", flush=True)
+    poses = _oracle_hybrid_poses(q, L, 3, 40, 0.05, seed).astype(np.float32)
+    Q = eng.molecules(q, mol_id=[QUERY_ID])
+    lib = eng.molecules(L)
+    hs = HybridScreen(eng, seed=seed)
+    bufs = hs.buffers(lib)
+    bufs["best_pose"].copy_(torch.from_numpy(poses))
+    eng.shape_apply_pose(lib, bufs["best_pose"], out=bufs["xyz"])
+    g = eng.shape_screen(Q, hs.moved(lib, bufs), mode=SHAPE_SCREEN_ADAPTIVE, tau=tau,
+                         cap_per_pair=cap, seed=seed)
+    g = {k: v.cpu().numpy() for k, v in g.items()}
+    moved = L.xyz.astype(np.float64).copy()
+    for m in range(L.n_mols):
+        a0, a1 = L.offsets[m], L.offsets[m + 1]
+        moved[a0:a1] = moved[a0:a1] @ _rot(poses[m, :4]).T + poses[m, 4:].astype(np.float64)
+    Lm = molgen.MolSet(L.offsets, moved.astype(np.float32), L.radius, L.element)
+    la = O.alpha_from_radius(L.radius, LAMBDA_P27)
+    r = O.screen(oracle_mol(O, q), QUERY_ID, Lm.offsets, Lm.xyz, la, mode=1, round_per_pair=512,
+                 cap_per_pair=cap, tau=tau, seed=seed)
+    compare_adaptive(g, r, q, Lm, tau, cap, seed, QUERY_ID)
+    # the superposition raised the union Tanimoto over the given poses
+    plain = O.screen(oracle_mol(O, q), QUERY_ID, L.offsets, L.xyz, la, mode=1, tau=tau,
+                     cap_per_pair=cap, seed=seed)
+    assert r[:, 0].mean() > plain[:, 0].mean()
+
+
 def test_invalid_molecule_gives_nan(eng, pairs):
     A, B = pairs
     Bbad = molgen.MolSet.concat([B.mol(p) for p in range(B.n_mols)])
@@ -234,6 +282,22 @@ def test_ensemble_screen_takes_the_best_conformer(eng, aligned):
     assert np.array_equal(best, T.max(1))
     assert np.array_equal(ent, np.arange(40) * 4 + T.argmax(1))
     assert np.all(best >= T[:, 0])
+    if not aligned:
+        # every conformer's union score against the oracle, and the maximum
+        # over each molecule's conformers against the host maximum of the
+        # oracle's scores (section on limitations: max over conformers)
+        out = {k: v.cpu().numpy() for k, v in bufs["out"].items()}
+        la = O.alpha_from_radius(C.radius, LAMBDA_P27)
+        r = O.screen(oracle_mol(O, q), QUERY_ID, C.offsets, C.xyz, la, mode=1, tau=0.005,
+                     cap_per_pair=65536, seed=1)
+        compare_adaptive(out, r, q, C, 0.005, 65536, 1, QUERY_ID)
+        Tr = r[:, 0].reshape(40, 4)
+        assert np.all(np.abs(best - Tr.max(1)) <= 1e-5 * np.abs(Tr.max(1)))
+        # the same conformer wins unless the oracle's top two lie within the
+        # parity tolerance of each other
+        top2 = np.sort(Tr, 1)[:, -2:]
+        clear = top2[:, 1] - top2[:, 0] > 2e-5 * top2[:, 1]
+        assert np.array_equal((ent - np.arange(40) * 4)[clear], Tr.argmax(1)[clear])
 
 
 @pytest.mark.parametrize("a_atoms,b_atoms,n_starts", [((3, 16), (10, 50), 1),

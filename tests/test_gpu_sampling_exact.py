@@ -1,0 +1,107 @@
+"""Bit-exact parity of the integer steps of sampling (section
+"Importance-sampling estimator": exact draws from the normalised mixture q =
+m/Z) between the HIP path and the FP64 oracle, through shape_sample_points:
+the uint32 thresholds, the Philox blocks and the selected component indices
+are compared exactly; the points within the bound their floating-point steps
+allow.  Molecules of 1, 2, 63, 64, 65 and 256 atoms (a single component, one
+threshold, sizes about the 64-lane width, SHAPE_MAX_ATOMS), counters on both
+sides of 2^32, a molecule that is not the first of its set, and antithetic
+sampling."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2607_20766_amd import molgen
+from paper_2607_20766_amd.engine import Engine
+from tests.gpu_common import oracle_mol, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+SIZES = (1, 2, 63, 64, 65, 256)
+
+
+@pytest.fixture(scope="module")
+def eng():
+    require_gpu()
+    return Engine(0)
+
+
+def _oracle_words(mol_id, seed, k0, n, anti):
+    key = np.array([seed & 0xFFFFFFFF, seed >> 32], np.uint32)
+    out = np.empty((n, 4), np.uint32)
+    for i in range(n):
+        k = k0 + i
+        b = k >> 1 if anti else k
+        out[i] = O.philox(np.array([b & 0xFFFFFFFF, b >> 32, mol_id, 0], np.uint32), key)
+    return out
+
+
+def _check(eng, ms, M, mol, mol_id, seed, k0, n, anti):
+    g = eng.shape_sample_points(M, mol, k0, n, seed=seed)
+    thr_g = g["thr"].cpu().numpy().view(np.uint32)
+    words_g = g["words"].cpu().numpy().view(np.uint32)
+    comp_g = g["comp"].cpu().numpy()
+    r_g = g["r"].cpu().numpy().astype(np.float64)
+    xyz, alpha = oracle_mol(O, ms)
+    _, _, thr_o = O.mol_prep(xyz, alpha)
+    assert thr_g.size == ms.n_atoms
+    assert np.array_equal(thr_g[:-1], thr_o) and thr_g[-1] == 0xFFFFFFFF
+    assert np.array_equal(words_g, _oracle_words(mol_id, seed, k0, n, anti))
+    r_o, comp_o = O.sample_points(xyz, alpha, mol_id, seed, k0, n, return_component=True,
+                                  antithetic=anti)
+    assert np.array_equal(comp_g, comp_o)
+    # r = c_j + z sd_j: the FP32 inverse normal is within 3.1e-7 of z, sd_j is
+    # rounded once to FP32 (2^-24) and the fused multiply-add rounds once
+    # (2^-24 |r|)
+    c = xyz.astype(np.float64)[comp_o]
+    tol = 4e-7 * np.abs(r_o - c) + 1.2e-7 * np.abs(r_o) + 1e-12
+    assert np.all(np.abs(r_g - r_o) <= tol), np.max(np.abs(r_g - r_o) / tol)
+
+
+@pytest.mark.parametrize("n_atoms", SIZES)
+def test_thresholds_words_components_points_exact(eng, n_atoms):
+    ms = molgen.molecule(70, n_atoms, n_atoms)
+    mol_id = 1000 + n_atoms
+    M = eng.molecules(ms, mol_id=[mol_id])
+    seed = 0x0123_4567_89AB_CDEF
+    print(f"case: sampling steps, {n_atoms} atoms", flush=True)
+    _check(eng, ms, M, 0, mol_id, seed, 0, 4096, False)
+    # counters whose low word wraps: (k mod 2^32, k div 2^32)
+    _check(eng, ms, M, 0, mol_id, seed, (1 << 32) - 1000, 2000, False)
+
+
+def test_molecule_inside_a_set(eng):
+    """A molecule at a non-zero offset of a library set, keyed by its id."""
+    L = molgen.MolSet.concat([molgen.molecule(71, i, n) for i, n in enumerate((5, 40, 17, 65))])
+    ids = np.array([7, 123456789, 0xFFFFFFFF, 42], np.uint32)
+    M = eng.molecules(L, mol_id=ids)
+    print("case: sampling steps, molecules inside a set", flush=True)
+    for m in range(L.n_mols):
+        _check(eng, L.mol(m), M, m, int(ids[m]), 5, 77, 1500, False)
+
+
+def test_antithetic_blocks_and_reflections(eng):
+    ms = molgen.molecule(72, 0, 30)
+    M = eng.molecules(ms, mol_id=[9])
+    print("case: sampling steps, antithetic", flush=True)
+    eng.sampling(True)
+    try:
+        _check(eng, ms, M, 0, 9, 3, 0, 2048, True)
+        _check(eng, ms, M, 0, 9, 3, 1001, 999, True)   # odd start: a pair split
+    finally:
+        eng.sampling(False)
+
+
+def test_invalid_molecule_and_ranges(eng):
+    from paper_2607_20766_amd.engine import ShapeError
+    ms = molgen.molecule(73, 0, 12)
+    M = eng.molecules(ms, mol_id=[1])
+    with pytest.raises(ShapeError) as e:
+        eng.shape_sample_points(M, 1, 0, 10)
+    assert e.value.code == -2
+    M.alpha[3] = float("nan")
+    with pytest.raises(ShapeError) as e:
+        eng.shape_sample_points(M, 0, 0, 10)
+    assert e.value.code == -6
+    torch.cuda.synchronize()

@@ -116,11 +116,23 @@ def test_mlp_matches_oracle(eng, bf16, tol):
     assert loss == pytest.approx(lr_, rel=tol)
     assert np.abs(g - gr).max() <= tol * np.abs(gr).max()
     assert np.dot(g, gr) / (np.linalg.norm(g) * np.linalg.norm(gr)) > 1 - tol
+    if not bf16:
+        # element by element: relative to each entry, with a floor for entries
+        # that are themselves sums cancelling to near zero (FP32 accumulation
+        # over the 300-row batch leaves ~1e-6 of the layer's largest entry)
+        off = 0
+        for i, o in zip(width[:-1], width[1:]):
+            for n_el in (i * o, o):
+                seg = slice(off, off + n_el)
+                floor = 1e-6 * np.abs(gr[seg]).max()
+                assert np.all(np.abs(g[seg] - gr[seg]) <= 2e-5 * np.abs(gr[seg]) + floor), \
+                    (i, o, n_el, np.max(np.abs(g[seg] - gr[seg]) / (np.abs(gr[seg]) + 1e-30)))
+                off += n_el
 
 
 def test_topk_exact(eng):
     rng = np.random.default_rng(6)
-    for n, k in ((1000, 37), (70000, 3500), (5, 5), (300, 1)):
+    for n, k in ((1000, 37), (70000, 3500), (5, 5), (300, 1), (1000000, 50000)):
         s = rng.normal(size=n).astype(np.float32)
         s[rng.integers(0, n, n // 10)] = 0.5   # ties
         s[rng.integers(0, n, 3)] = np.nan
@@ -189,7 +201,7 @@ def test_triage_gain(eng):
     mae = float(np.abs(T_hat - T_plain).mean())
     print(f"recall@1% {recall:.3f}  MAE {mae:.4f}  samples {n_tri} vs {n_plain}", flush=True)
     assert n_tri < 0.2 * n_plain
-    assert recall >= 0.95
+    assert recall >= 0.98
     # far better than predicting the mean (whose MAE is ~0.8 of the spread)
     assert mae < 0.5 * float(T_plain.std())
     # every refined pair met the target or its cap
