@@ -314,13 +314,27 @@ int32_t shape_screen_get_variant(const shape_ctx* ctx);
  * (shape_estimate, shape_check_data, shape_screen_tune, shape_timing_read)
  * return SHAPE_E_UNSUPPORTED.  Kernel timing is suspended while capturing.
  * A failed call inside the capture leaves it open; shape_graph_end then
- * discards it and returns the error.  Errors: SHAPE_E_INVAL, SHAPE_E_HIP,
- * SHAPE_E_UNSUPPORTED. */
+ * discards it and returns the error.  Scratch that an eager call grows while
+ * a graph of the context is alive is not freed: the superseded buffer is
+ * kept (retired) for the graphs that captured its address and released when
+ * the last of them is destroyed, so a graph stays valid whatever eager calls
+ * follow.  shape_graph_begin and shape_graph_end forget the molecule
+ * preparations of shape_prepare_cache: a preparation made before a capture
+ * is not reused inside it, nor one recorded inside it afterwards.  A graph
+ * can only be launched with the context that captured it.  Errors:
+ * SHAPE_E_INVAL, SHAPE_E_HIP, SHAPE_E_UNSUPPORTED. */
 typedef struct shape_graph shape_graph;
 int shape_graph_begin(shape_ctx* ctx, void* stream);
 int shape_graph_end(shape_ctx* ctx, void* stream, shape_graph** out);
 int shape_graph_launch(shape_ctx* ctx, shape_graph* graph, void* stream);
 void shape_graph_destroy(shape_graph* graph);
+
+/* Device memory held by the context (host pointers, each may be NULL): the
+ * scratch in use, the retired scratch kept for live graphs, and the number
+ * of executable graphs of this context not yet destroyed.  Errors:
+ * SHAPE_E_INVAL. */
+int shape_memory_info(const shape_ctx* ctx, int64_t* scratch_bytes, int64_t* retired_bytes,
+                      int32_t* live_graphs);
 
 /* ------------------------------------------------------------------------
  * Differentiable rigid alignment (section "Differentiable alignment and the

@@ -7,6 +7,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <memory>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -49,8 +51,22 @@ struct PrepKey {
   }
 };
 
+// Executable graphs replay the device addresses they captured.  A scratch
+// buffer that grows while any graph of its context is alive is therefore not
+// freed but retired, and retired buffers are released once the last of those
+// graphs is destroyed (or with the context).  Shared by the context and its
+// graphs, so a graph may outlive its context.
+struct GraphLife {
+  std::mutex m;
+  int device = -1;
+  int live = 0;                 // graphs instantiated and not yet destroyed
+  std::vector<void*> retired;   // buffers replaced while graphs were alive
+  size_t retired_bytes = 0;
+};
+
 struct shape_ctx {
   int device = -1;
+  std::shared_ptr<GraphLife> life;
   int n_cu = 0;
   size_t lds_per_block = 0;
   std::string err;
@@ -71,6 +87,7 @@ struct shape_ctx {
 struct shape_graph {
   hipGraphExec_t exec = nullptr;
   int device = -1;
+  std::shared_ptr<GraphLife> life;  // the capturing context's graph bookkeeping
 };
 
 // ---------------------------------------------------------------------------
@@ -155,9 +172,16 @@ int ensure(shape_ctx* c, Slot s, size_t bytes, void** out) {
                   "scratch would grow during graph capture: make the same calls once "
                   "before capturing");
     if (b.ptr) {
-      hipError_t e = hipDeviceSynchronize();
-      if (e != hipSuccess) return hip_fail(c, e, "hipDeviceSynchronize");
-      (void)hipFree(b.ptr);
+      std::lock_guard<std::mutex> lk(c->life->m);
+      if (c->life->live > 0) {
+        // a live graph may still replay with this address
+        c->life->retired.push_back(b.ptr);
+        c->life->retired_bytes += b.bytes;
+      } else {
+        hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) return hip_fail(c, e, "hipDeviceSynchronize");
+        (void)hipFree(b.ptr);
+      }
       b.ptr = nullptr;
       b.bytes = 0;
     }
@@ -396,6 +420,13 @@ int shape_create(shape_ctx** out, int device) {
                 prop.gcnArchName);
   shape_ctx* c = new (std::nothrow) shape_ctx();
   if (!c) return fail(nullptr, SHAPE_E_NOMEM, "context allocation failed");
+  try {
+    c->life = std::make_shared<GraphLife>();
+  } catch (...) {
+    delete c;
+    return fail(nullptr, SHAPE_E_NOMEM, "context allocation failed");
+  }
+  c->life->device = device;
   c->device = device;
   c->n_cu = prop.multiProcessorCount;
   c->lds_per_block = prop.sharedMemPerBlock;
@@ -420,6 +451,14 @@ void shape_destroy(shape_ctx* c) {
   (void)hipDeviceSynchronize();
   for (auto& b : c->buf)
     if (b.ptr) (void)hipFree(b.ptr);
+  {
+    // graphs that outlive the context can no longer be launched (a launch
+    // needs the context), so nothing replays with these addresses again
+    std::lock_guard<std::mutex> lk(c->life->m);
+    for (void* p : c->life->retired) (void)hipFree(p);
+    c->life->retired.clear();
+    c->life->retired_bytes = 0;
+  }
   for (auto& e : c->events) {
     (void)hipEventDestroy(e.first);
     (void)hipEventDestroy(e.second);
@@ -1415,6 +1454,11 @@ int shape_graph_begin(shape_ctx* c, void* stream) {
   c->capturing = true;
   c->capture_failed = false;
   c->capture_stream = (hipStream_t)stream;
+  // a preparation done before the capture is not part of the graph, and one
+  // recorded inside it does not run now: neither may be reused across the
+  // capture boundary
+  c->prepared[0].valid = false;
+  c->prepared[1].valid = false;
   return SHAPE_OK;
 }
 
@@ -1425,6 +1469,8 @@ int shape_graph_end(shape_ctx* c, void* stream, shape_graph** out) {
     return fail(c, SHAPE_E_INVAL, "no graph capture is open on this stream");
   c->capturing = false;
   c->capture_stream = nullptr;
+  c->prepared[0].valid = false;
+  c->prepared[1].valid = false;
   hipGraph_t g = nullptr;
   HIP_TRY(c, hipStreamEndCapture((hipStream_t)stream, &g), "hipStreamEndCapture");
   if (c->capture_failed) {
@@ -1448,6 +1494,11 @@ int shape_graph_end(shape_ctx* c, void* stream, shape_graph** out) {
     return hip_fail(c, e, "hipGraphInstantiate");
   }
   sg->device = c->device;
+  sg->life = c->life;
+  {
+    std::lock_guard<std::mutex> lk(c->life->m);
+    ++c->life->live;
+  }
   *out = sg;
   return SHAPE_OK;
 }
@@ -1455,9 +1506,8 @@ int shape_graph_end(shape_ctx* c, void* stream, shape_graph** out) {
 int shape_graph_launch(shape_ctx* c, shape_graph* g, void* stream) {
   if (!c) return SHAPE_E_INVAL;
   if (!g || !g->exec) return fail(c, SHAPE_E_INVAL, "graph is NULL");
-  if (g->device != c->device)
-    return fail(c, SHAPE_E_INVAL, "graph belongs to device %d, context to %d", g->device,
-                c->device);
+  if (g->life != c->life)
+    return fail(c, SHAPE_E_INVAL, "the graph was captured on another context");
   if (c->capturing) return fail(c, SHAPE_E_UNSUPPORTED, "graph launch during capture");
   int rc = set_device(c);
   if (rc) return rc;
@@ -1472,7 +1522,28 @@ void shape_graph_destroy(shape_graph* g) {
     (void)hipDeviceSynchronize();  // no replay of it is still queued
     (void)hipGraphExecDestroy(g->exec);
   }
+  if (g->life) {
+    std::lock_guard<std::mutex> lk(g->life->m);
+    if (--g->life->live == 0) {
+      // the last graph that could address the retired buffers is gone
+      for (void* p : g->life->retired) (void)hipFree(p);
+      g->life->retired.clear();
+      g->life->retired_bytes = 0;
+    }
+  }
   delete g;
+}
+
+int shape_memory_info(const shape_ctx* c, int64_t* scratch_bytes, int64_t* retired_bytes,
+                      int32_t* live_graphs) {
+  if (!c) return SHAPE_E_INVAL;
+  size_t held = 0;
+  for (const auto& b : c->buf) held += b.bytes;
+  std::lock_guard<std::mutex> lk(c->life->m);
+  if (scratch_bytes) *scratch_bytes = (int64_t)held;
+  if (retired_bytes) *retired_bytes = (int64_t)c->life->retired_bytes;
+  if (live_graphs) *live_graphs = c->life->live;
+  return SHAPE_OK;
 }
 
 }  // extern "C"

@@ -121,6 +121,8 @@ def load_library():
         L.shape_graph_launch.argtypes = [vp, vp, vp]
         L.shape_graph_destroy.argtypes = [vp]
         L.shape_graph_destroy.restype = None
+        L.shape_memory_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64),
+                                        ctypes.POINTER(i32)]
         L.shape_self_overlap.argtypes = [vp, ctypes.POINTER(ShapeMols), i32, u64, vp, vp]
         L.shape_align_grad.argtypes = [vp, ctypes.POINTER(ShapeMols), ctypes.POINTER(ShapeMols),
                                        i32, vp, vp, vp, i32, u64, vp, vp, vp]
@@ -181,6 +183,62 @@ def _stream(stream):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
+def _shape_ok(t, shape):
+    return t.dim() == len(shape) and all(s is None or t.shape[i] == s
+                                         for i, s in enumerate(shape))
+
+
+def _check_out(t, name, dtype, shape, device):
+    """An output the library writes: it must already be what the kernel
+    writes (no converted copy could carry the results back)."""
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a tensor")
+    if not _shape_ok(t, shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} has dtype {t.dtype}, expected {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.device != device:
+        raise ValueError(f"{name} is on {t.device}, expected {device}")
+    return t
+
+
+class _Args:
+    """Input tensors of one library call on one stream: shapes and devices
+    checked, dtype and layout converted on the device if needed; every
+    converted copy is tied to the stream (record_stream) so that its memory
+    is not reused before the queued work that reads it has run."""
+
+    def __init__(self, eng: "Engine", stream):
+        self.device = eng.torch_device
+        self.stream = stream   # None: the device's current stream
+
+    def __call__(self, t, name, dtype, shape=None, numel=None, optional=False):
+        if t is None:
+            if optional:
+                return None
+            raise ValueError(f"{name} is required")
+        if not isinstance(t, torch.Tensor):
+            raise TypeError(f"{name} must be a tensor")
+        if shape is not None and not _shape_ok(t, shape):
+            raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+        if numel is not None and t.numel() != numel:
+            raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
+        if t.device != self.device:
+            raise ValueError(f"{name} is on {t.device}, expected {self.device}")
+        c = t.to(dtype).contiguous()
+        if c.data_ptr() != t.data_ptr() or c.dtype != t.dtype:
+            c.record_stream(self.stream if self.stream is not None
+                            else torch.cuda.current_stream(self.device))
+        return c
+
+    def out(self, t, name, dtype, shape):
+        return _check_out(t, name, dtype, shape, self.device)
+
+
 @dataclasses.dataclass
 class Molecules:
     """A molecule set resident on the device (CSR layout, see shape_mols)."""
@@ -198,6 +256,22 @@ class Molecules:
     @property
     def n_atoms(self) -> int:
         return int(self.xyz.shape[0])
+
+    def validate(self, device, name="molecules"):
+        """The layout the C ABI reads: int32 offsets [n_mols + 1], float32
+        xyz [n_atoms, 3] and alpha [n_atoms], int32 ids [n_mols] or None,
+        contiguous on `device` (values are checked by the kernels)."""
+        n = self.n_mols
+        if n < 1:
+            raise ValueError(f"{name}: no molecules")
+        if not 1 <= int(self.max_atoms) <= SHAPE_MAX_ATOMS:
+            raise ValueError(f"{name}: max_atoms {self.max_atoms} outside [1, {SHAPE_MAX_ATOMS}]")
+        _check_out(self.offsets, f"{name}.offsets", torch.int32, (n + 1,), device)
+        _check_out(self.xyz, f"{name}.xyz", torch.float32, (None, 3), device)
+        _check_out(self.alpha, f"{name}.alpha", torch.float32, (self.n_atoms,), device)
+        if self.mol_id is not None:
+            _check_out(self.mol_id, f"{name}.mol_id", torch.int32, (n,), device)
+        return self
 
     def c_struct(self) -> ShapeMols:
         return ShapeMols(self.n_mols, self.max_atoms, self.n_atoms,
@@ -233,10 +307,13 @@ class Engine:
         if rc != SHAPE_OK:
             raise ShapeError(rc, load_library().shape_last_error(self._ctx).decode())
 
+    def _mols(self, *sets):
+        return [m.validate(self.torch_device, name).c_struct() for name, m in sets]
+
     # -- molecule upload -------------------------------------------------------
     def alpha_from_radius(self, radius: torch.Tensor, lam: float = LAMBDA_P27,
                           stream=None) -> torch.Tensor:
-        radius = radius.contiguous()
+        radius = _Args(self, stream)(radius, "radius", torch.float32)
         alpha = torch.empty_like(radius)
         self._check(load_library().shape_alpha_from_radius(
             self._ctx, _ptr(radius), radius.numel(), float(lam), _ptr(alpha), _stream(stream)))
@@ -261,7 +338,7 @@ class Engine:
     def shape_estimate(self, A: Molecules, B: Molecules, n_a: int, n_b: int,
                        seed: int = 0, stream=None) -> dict:
         res = ShapeResult()
-        a, b = A.c_struct(), B.c_struct()
+        a, b = self._mols(("A", A), ("B", B))
         self._check(load_library().shape_estimate(self._ctx, ctypes.byref(a), ctypes.byref(b),
                                                   int(n_a), int(n_b), int(seed),
                                                   _stream(stream), ctypes.byref(res)))
@@ -274,7 +351,7 @@ class Engine:
         """shape_estimate through the allocation-free entry point (fixed
         scratch in the library; n_a, n_b <= 2^24, at most 256 atoms per set)."""
         res = ShapeResult()
-        a, b = A.c_struct(), B.c_struct()
+        a, b = self._mols(("A", A), ("B", B))
         self._check(load_library().shape_estimate_noalloc(
             self._ctx, ctypes.byref(a), ctypes.byref(b), int(n_a), int(n_b), int(seed),
             _stream(stream), ctypes.byref(res)))
@@ -287,6 +364,7 @@ class Engine:
         """The GPU's sampling steps for molecule `mol` of M, samples k0..k0+n-1:
         thresholds (uint32 bit patterns in int32 [atoms]), Philox words
         [n, 4], components [n] and points [n, 3] (device tensors)."""
+        (m,) = self._mols(("M", M))
         dev = self.torch_device
         na = (int(M.offsets[mol + 1].item() - M.offsets[mol].item())
               if 0 <= mol < M.n_mols else 1)
@@ -294,7 +372,6 @@ class Engine:
                "words": torch.empty(max(n, 1), 4, dtype=torch.int32, device=dev),
                "comp": torch.empty(max(n, 1), dtype=torch.int32, device=dev),
                "r": torch.empty(max(n, 1), 3, dtype=torch.float32, device=dev)}
-        m = M.c_struct()
         self._check(load_library().shape_sample_points(
             self._ctx, ctypes.byref(m), int(mol), int(k0), int(n), int(seed), _stream(stream),
             _ptr(out["thr"]), _ptr(out["words"]), _ptr(out["comp"]), _ptr(out["r"])))
@@ -303,20 +380,18 @@ class Engine:
             out[k] = out[k][:n]
         return out
 
-    @staticmethod
-    def _screen_params(mode, n_per_side, round_per_pair, cap_per_pair, tau, seed, n_start):
-        if n_start is not None:
-            n_start = n_start.to(torch.int32).contiguous()
-        prm = ShapeScreenParams(mode, n_per_side, round_per_pair, cap_per_pair, tau, seed,
-                                None if n_start is None else n_start.data_ptr())
-        return prm, n_start
-
-    @staticmethod
-    def _screen_pairs(lib, pairs, n_pairs):
+    def _screen_call(self, query, lib, pairs, n_pairs, n_start, stream):
+        """Checked pair list and budgets of a screen: (pairs or None, n,
+        n_start or None, molecule structs)."""
+        arg = _Args(self, stream)
+        q, l_ = self._mols(("query", query), ("lib", lib))
         if pairs is not None:
-            pairs = pairs.to(torch.int32).contiguous()
-            return pairs, int(pairs.numel())
-        return None, lib.n_mols if n_pairs is None else int(n_pairs)
+            pairs = arg(pairs, "pairs", torch.int32, shape=(None,))
+            n = int(pairs.numel())
+        else:
+            n = lib.n_mols if n_pairs is None else int(n_pairs)
+        n_start = arg(n_start, "n_start", torch.int32, numel=n, optional=True)
+        return pairs, n, n_start, q, l_
 
     def shape_screen(self, query: Molecules, lib: Molecules, *, mode: int = SHAPE_SCREEN_FIXED,
                      n_per_side: int = 4096, round_per_pair: int = 512,
@@ -326,17 +401,21 @@ class Engine:
                      stream=None) -> dict:
         """Screen the query against library molecules; returns device tensors
         T, se_T, O_ab, O_aa, O_bb (float32) and n_used (int32) per pair."""
-        pairs, n = self._screen_pairs(lib, pairs, n_pairs)
+        pairs, n, n_start, q, l_ = self._screen_call(query, lib, pairs, n_pairs, n_start, stream)
+        dev = self.torch_device
         if out is None:
-            dev = self.torch_device
             out = {k: torch.empty(n, dtype=torch.float32, device=dev)
                    for k in ("T", "se_T", "O_ab", "O_aa", "O_bb")}
             out["n_used"] = torch.empty(n, dtype=torch.int32, device=dev)
-        prm, n_start = self._screen_params(mode, n_per_side, round_per_pair, cap_per_pair, tau,
-                                           seed, n_start)
+        for k in ("T", "se_T", "O_ab", "O_aa", "O_bb", "n_used"):
+            if k in ("T", "se_T") and out.get(k) is None:
+                raise ValueError(f"out[{k!r}] is required")
+            _check_out(out.get(k), f"out[{k!r}]",
+                       torch.int32 if k == "n_used" else torch.float32, (n,), dev)
+        prm = ShapeScreenParams(mode, n_per_side, round_per_pair, cap_per_pair, tau, seed,
+                                None if n_start is None else n_start.data_ptr())
         o = ShapeScreenOut(*(out[k].data_ptr() if out.get(k) is not None else None
                              for k in ("T", "se_T", "O_ab", "O_aa", "O_bb", "n_used")))
-        q, l_ = query.c_struct(), lib.c_struct()
         self._check(load_library().shape_screen(self._ctx, ctypes.byref(q), ctypes.byref(l_),
                                                 _ptr(pairs), n, ctypes.byref(prm),
                                                 _stream(stream), ctypes.byref(o)))
@@ -350,12 +429,11 @@ class Engine:
                           stream=None):
         """Time every tile variant of the screening kernel on this workload,
         keep the fastest for later screens; returns (best, [ms per variant])."""
-        pairs, n = self._screen_pairs(lib, pairs, n_pairs)
-        prm, n_start = self._screen_params(mode, n_per_side, round_per_pair, cap_per_pair, tau,
-                                           seed, n_start)
+        pairs, n, n_start, q, l_ = self._screen_call(query, lib, pairs, n_pairs, n_start, stream)
+        prm = ShapeScreenParams(mode, n_per_side, round_per_pair, cap_per_pair, tau, seed,
+                                None if n_start is None else n_start.data_ptr())
         ms = (ctypes.c_float * SHAPE_SCREEN_VARIANTS)()
         best = ctypes.c_int32(-1)
-        q, l_ = query.c_struct(), lib.c_struct()
         self._check(load_library().shape_screen_tune(
             self._ctx, ctypes.byref(q), ctypes.byref(l_), _ptr(pairs), n, ctypes.byref(prm),
             _stream(stream), ms, ctypes.byref(best)))
@@ -409,11 +487,20 @@ class Engine:
             self._check(L.shape_graph_end(self._ctx, _stream(s), ctypes.byref(handle)))
         return Graph(self, handle)
 
+    def memory_info(self) -> dict:
+        """Scratch bytes in use, retired scratch kept for live graphs, and
+        the number of live graphs of this context."""
+        held, retired, live = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
+        self._check(load_library().shape_memory_info(self._ctx, ctypes.byref(held),
+                                                     ctypes.byref(retired), ctypes.byref(live)))
+        return {"scratch_bytes": held.value, "retired_bytes": retired.value,
+                "live_graphs": live.value}
+
     # -- alignment -------------------------------------------------------------
     def shape_self_overlap(self, M: Molecules, n_samples: int = 2048, seed: int = 0,
                            stream=None) -> torch.Tensor:
+        (m,) = self._mols(("M", M))
         out = torch.empty(M.n_mols, dtype=torch.float32, device=self.torch_device)
-        m = M.c_struct()
         self._check(load_library().shape_self_overlap(self._ctx, ctypes.byref(m), int(n_samples),
                                                       int(seed), _stream(stream), _ptr(out)))
         return out
@@ -422,20 +509,30 @@ class Engine:
                          O_aa: torch.Tensor, O_bb: torch.Tensor, n_samples: int = 2048,
                          seed: int = 0, need_grad: bool = True, stream=None):
         """T [pairs, starts] and dT/dpose [pairs, starts, 7] (None if not needed)."""
-        pose = pose.contiguous()
-        pairs, starts = pose.shape[0], pose.shape[1]
+        arg = _Args(self, stream)
+        a, b = self._mols(("A", A), ("B", B))
+        pairs = A.n_mols
+        pose = arg(pose, "pose", torch.float32, shape=(pairs, None, 7))
+        starts = pose.shape[1]
+        O_aa = arg(O_aa, "O_aa", torch.float32, numel=pairs)
+        O_bb = arg(O_bb, "O_bb", torch.float32, numel=pairs)
         T = torch.empty(pairs, starts, dtype=torch.float32, device=self.torch_device)
         g = (torch.empty(pairs, starts, 7, dtype=torch.float32, device=self.torch_device)
              if need_grad else None)
-        a, b = A.c_struct(), B.c_struct()
         self._check(load_library().shape_align_grad(
-            self._ctx, ctypes.byref(a), ctypes.byref(b), starts, _ptr(pose),
-            _ptr(O_aa.contiguous()), _ptr(O_bb.contiguous()), int(n_samples), int(seed),
-            _stream(stream), _ptr(T), _ptr(g)))
+            self._ctx, ctypes.byref(a), ctypes.byref(b), starts, _ptr(pose), _ptr(O_aa),
+            _ptr(O_bb), int(n_samples), int(seed), _stream(stream), _ptr(T), _ptr(g)))
         return T, g
 
     def shape_adam_pose(self, pose, dT, m, v, step, lr=0.05, beta1=0.9, beta2=0.999, eps=1e-8,
                         stream=None):
+        arg = _Args(self, stream)
+        shape = (None, 7) if pose.dim() == 2 else (None, None, 7)
+        pose = arg.out(pose, "pose", torch.float32, shape)
+        m = arg.out(m, "m", torch.float32, tuple(pose.shape))
+        v = arg.out(v, "v", torch.float32, tuple(pose.shape))
+        step = arg.out(step, "step", torch.int32, (1,))
+        dT = arg(dT, "dT_dpose", torch.float32, numel=pose.numel())
         self._check(load_library().shape_adam_pose(
             self._ctx, _ptr(pose), _ptr(dT), _ptr(m), _ptr(v), pose.numel() // 7, _ptr(step),
             float(lr), float(beta1), float(beta2), float(eps), _stream(stream)))
@@ -444,23 +541,23 @@ class Engine:
                     n_steps: int = 60, lr: float = 0.05, seed: int = 0, stream=None):
         """Multi-start Adam alignment in place on `pose` [pairs, starts, 7];
         returns (T at the final poses [pairs, starts], best start [pairs])."""
-        assert pose.is_contiguous() and pose.dtype == torch.float32
-        pairs, starts = pose.shape[0], pose.shape[1]
+        a, b = self._mols(("A", A), ("B", B))
+        pairs = A.n_mols
+        _check_out(pose, "pose", torch.float32, (pairs, None, 7), self.torch_device)
+        starts = pose.shape[1]
         T = torch.empty(pairs, starts, dtype=torch.float32, device=self.torch_device)
         best = torch.empty(pairs, dtype=torch.int32, device=self.torch_device)
-        a, b = A.c_struct(), B.c_struct()
         self._check(load_library().shape_align(
             self._ctx, ctypes.byref(a), ctypes.byref(b), starts, _ptr(pose), int(n_samples),
             int(n_steps), float(lr), int(seed), _stream(stream), _ptr(T), _ptr(best)))
         return T, best
 
-    # -- learned triage ----------------------------------------------------------
     # -- grid reference ------------------------------------------------------------
     def shape_grid_integrals(self, A: Molecules, B: Molecules, h: float = 0.2,
                              pad: float = 6.5, stream=None) -> dict:
         """Trapezoid-rule integrals of one pair on a cubic grid (FP64)."""
         out = (ctypes.c_double * 8)()
-        a, b = A.c_struct(), B.c_struct()
+        a, b = self._mols(("A", A), ("B", B))
         self._check(load_library().shape_grid_integrals(self._ctx, ctypes.byref(a),
                                                         ctypes.byref(b), float(h), float(pad),
                                                         _stream(stream), out))
@@ -471,10 +568,11 @@ class Engine:
                         out=None, stream=None) -> torch.Tensor:
         """Alignment starts [pairs, 5 + n_random, 7]: given pose, four
         principal-axis alignments, random rotations."""
+        a, b = self._mols(("A", A), ("B", B))
+        shape = (B.n_mols, 5 + int(n_random), 7)
         if out is None:
-            out = torch.empty(B.n_mols, 5 + int(n_random), 7, dtype=torch.float32,
-                              device=self.torch_device)
-        a, b = A.c_struct(), B.c_struct()
+            out = torch.empty(*shape, dtype=torch.float32, device=self.torch_device)
+        _check_out(out, "out", torch.float32, shape, self.torch_device)
         self._check(load_library().shape_fo_starts(self._ctx, ctypes.byref(a), ctypes.byref(b),
                                                    int(n_random), int(seed), _stream(stream),
                                                    _ptr(out)))
@@ -485,13 +583,15 @@ class Engine:
         """Adam on the first-order Tanimoto from each start; pose
         [pairs, starts, 7] is updated in place.  Returns (T [pairs, starts],
         dT/dpose at the final poses or None)."""
-        assert pose.is_contiguous() and pose.dtype == torch.float32
+        a, b = self._mols(("A", A), ("B", B))
+        dev = self.torch_device
+        _check_out(pose, "pose", torch.float32, (B.n_mols, None, 7), dev)
         pairs, starts = pose.shape[0], pose.shape[1]
         if T is None:
-            T = torch.empty(pairs, starts, dtype=torch.float32, device=self.torch_device)
-        g = (torch.empty(pairs, starts, 7, dtype=torch.float32, device=self.torch_device)
+            T = torch.empty(pairs, starts, dtype=torch.float32, device=dev)
+        _check_out(T, "T", torch.float32, (pairs, starts), dev)
+        g = (torch.empty(pairs, starts, 7, dtype=torch.float32, device=dev)
              if need_grad else None)
-        a, b = A.c_struct(), B.c_struct()
         self._check(load_library().shape_fo_align(self._ctx, ctypes.byref(a), ctypes.byref(b),
                                                   starts, _ptr(pose), int(n_steps), float(lr),
                                                   _stream(stream), _ptr(T), _ptr(g)))
@@ -499,11 +599,16 @@ class Engine:
 
     def shape_best_pose(self, T: torch.Tensor, pose: torch.Tensor, best_pose=None, best_T=None,
                         stream=None):
+        arg = _Args(self, stream)
+        T = arg(T, "T", torch.float32, shape=(None, None))
         pairs, starts = T.shape
+        pose = arg(pose, "pose", torch.float32, shape=(pairs, starts, 7))
         if best_pose is None:
             best_pose = torch.empty(pairs, 7, dtype=torch.float32, device=self.torch_device)
         if best_T is None:
             best_T = torch.empty(pairs, dtype=torch.float32, device=self.torch_device)
+        arg.out(best_pose, "best_pose", torch.float32, (pairs, 7))
+        arg.out(best_T, "best_T", torch.float32, (pairs,))
         self._check(load_library().shape_best_pose(self._ctx, pairs, starts, _ptr(T), _ptr(pose),
                                                    _stream(stream), _ptr(best_pose),
                                                    _ptr(best_T)))
@@ -512,81 +617,110 @@ class Engine:
     def shape_group_max(self, T: torch.Tensor, group_offset: torch.Tensor, best_T=None,
                         best_idx=None, stream=None):
         """Max over each group of consecutive entries (conformer ensembles):
-        (best T [groups], its entry [groups])."""
-        group_offset = group_offset.to(torch.int32).contiguous()
+        (best T [groups], its entry [groups]).  The last offset must not
+        exceed T's length (checked on the host: one small device read)."""
+        arg = _Args(self, stream)
+        group_offset = arg(group_offset, "group_offset", torch.int32, shape=(None,))
+        T = arg(T, "T", torch.float32)
         g = group_offset.numel() - 1
+        if g > 0 and int(group_offset[-1].item()) > T.numel():
+            raise ValueError("group_offset runs past the end of T")
         if best_T is None:
             best_T = torch.empty(g, dtype=torch.float32, device=self.torch_device)
         if best_idx is None:
             best_idx = torch.empty(g, dtype=torch.int32, device=self.torch_device)
-        self._check(load_library().shape_group_max(self._ctx, _ptr(T.contiguous()),
-                                                   _ptr(group_offset), g, _stream(stream),
-                                                   _ptr(best_T), _ptr(best_idx)))
+        arg.out(best_T, "best_T", torch.float32, (g,))
+        arg.out(best_idx, "best_idx", torch.int32, (g,))
+        self._check(load_library().shape_group_max(self._ctx, _ptr(T), _ptr(group_offset), g,
+                                                   _stream(stream), _ptr(best_T),
+                                                   _ptr(best_idx)))
         return best_T, best_idx
 
     def shape_apply_pose(self, M: Molecules, pose: torch.Tensor, out=None,
                          stream=None) -> torch.Tensor:
+        arg = _Args(self, stream)
+        (m,) = self._mols(("M", M))
+        pose = arg(pose, "pose", torch.float32, shape=(M.n_mols, 7))
         if out is None:
             out = torch.empty_like(M.xyz)
-        m = M.c_struct()
+        arg.out(out, "out", torch.float32, tuple(M.xyz.shape))
         self._check(load_library().shape_apply_pose(self._ctx, ctypes.byref(m), _ptr(pose),
                                                     _stream(stream), _ptr(out)))
         return out
 
     def shape_features(self, M: Molecules, out=None, stream=None) -> torch.Tensor:
+        (m,) = self._mols(("M", M))
         if out is None:
             out = torch.empty(M.n_mols, 24, dtype=torch.float32, device=self.torch_device)
-        m = M.c_struct()
+        _check_out(out, "out", torch.float32, (M.n_mols, 24), self.torch_device)
         self._check(load_library().shape_features(self._ctx, ctypes.byref(m), _stream(stream),
                                                   _ptr(out)))
         return out
 
     def shape_fo_overlap(self, query: Molecules, lib: Molecules, pairs=None, n_pairs=None,
                          out=None, stream=None) -> torch.Tensor:
+        arg = _Args(self, stream)
+        q, l_ = self._mols(("query", query), ("lib", lib))
         if pairs is not None:
-            pairs = pairs.to(torch.int32).contiguous()
+            pairs = arg(pairs, "pairs", torch.int32, shape=(None,))
             n = pairs.numel()
         else:
             n = lib.n_mols if n_pairs is None else int(n_pairs)
         if out is None:
             out = torch.empty(n, dtype=torch.float32, device=self.torch_device)
-        q, l_ = query.c_struct(), lib.c_struct()
+        arg.out(out, "out", torch.float32, (n,))
         self._check(load_library().shape_fo_overlap(self._ctx, ctypes.byref(q), ctypes.byref(l_),
                                                     _ptr(pairs), n, _stream(stream), _ptr(out)))
         return out
 
-    def shape_pair_features(self, f_q, f_lib, mean, inv_std, idx=None, qidx=None, n=None,
-                            fo_cross=None, out=None, stream=None) -> torch.Tensor:
+    def _pair_args(self, arg, f_q, f_lib, mean, inv_std, idx, qidx, n, fo_cross, params=None):
+        """Checked inputs of the pair-feature calls; returns them with n."""
+        f_q = arg(f_q, "f_q", torch.float32, shape=(None, 24))
+        f_lib = arg(f_lib, "f_lib", torch.float32, shape=(None, 24))
         if idx is not None:
-            idx = idx.to(torch.int32).contiguous()
+            idx = arg(idx, "idx", torch.int32, shape=(None,))
             n = idx.numel()
         elif n is None:
             n = f_lib.shape[0]
-        if qidx is not None:
-            qidx = qidx.to(torch.int32).contiguous()
+        elif int(n) > f_lib.shape[0]:
+            raise ValueError(f"n = {n} exceeds the {f_lib.shape[0]} rows of f_lib")
+        n = int(n)
+        qidx = arg(qidx, "qidx", torch.int32, numel=n, optional=True)
+        if qidx is None and f_q.shape[0] < 1:
+            raise ValueError("f_q has no row")
+        fo_cross = arg(fo_cross, "fo_cross", torch.float32, numel=n, optional=True)
+        mean = arg(mean, "mean", torch.float32, numel=96)
+        inv_std = arg(inv_std, "inv_std", torch.float32, numel=96)
+        if params is not None:
+            from .surrogate import n_params
+            params = arg(params, "params", torch.float32, numel=n_params())
+        return f_q, f_lib, mean, inv_std, idx, qidx, n, fo_cross, params
+
+    def shape_pair_features(self, f_q, f_lib, mean, inv_std, idx=None, qidx=None, n=None,
+                            fo_cross=None, out=None, stream=None) -> torch.Tensor:
+        arg = _Args(self, stream)
+        f_q, f_lib, mean, inv_std, idx, qidx, n, fo_cross, _ = self._pair_args(
+            arg, f_q, f_lib, mean, inv_std, idx, qidx, n, fo_cross)
         if out is None:
             out = torch.empty(n, 96, dtype=torch.float32, device=self.torch_device)
+        arg.out(out, "out", torch.float32, (n, 96))
         self._check(load_library().shape_pair_features(
-            self._ctx, _ptr(f_q.contiguous()), _ptr(f_lib.contiguous()), _ptr(qidx), _ptr(idx),
-            int(n), _ptr(fo_cross), _ptr(mean), _ptr(inv_std), _stream(stream), _ptr(out)))
+            self._ctx, _ptr(f_q), _ptr(f_lib), _ptr(qidx), _ptr(idx), n, _ptr(fo_cross),
+            _ptr(mean), _ptr(inv_std), _stream(stream), _ptr(out)))
         return out
 
     def shape_mlp_infer(self, f_q, f_lib, mean, inv_std, params, idx=None, qidx=None, n=None,
                         fo_cross=None, out=None, stream=None) -> torch.Tensor:
         """Fused pair features + 96-256-256-256-2 network (BF16): [n, 2]."""
-        if idx is not None:
-            idx = idx.to(torch.int32).contiguous()
-            n = idx.numel()
-        elif n is None:
-            n = f_lib.shape[0]
-        if qidx is not None:
-            qidx = qidx.to(torch.int32).contiguous()
+        arg = _Args(self, stream)
+        f_q, f_lib, mean, inv_std, idx, qidx, n, fo_cross, params = self._pair_args(
+            arg, f_q, f_lib, mean, inv_std, idx, qidx, n, fo_cross, params)
         if out is None:
             out = torch.empty(n, 2, dtype=torch.float32, device=self.torch_device)
+        arg.out(out, "out", torch.float32, (n, 2))
         self._check(load_library().shape_mlp_infer(
-            self._ctx, _ptr(f_q.contiguous()), _ptr(f_lib.contiguous()), _ptr(qidx), _ptr(idx),
-            int(n), _ptr(fo_cross), _ptr(mean), _ptr(inv_std), _ptr(params), _stream(stream),
-            _ptr(out)))
+            self._ctx, _ptr(f_q), _ptr(f_lib), _ptr(qidx), _ptr(idx), n, _ptr(fo_cross),
+            _ptr(mean), _ptr(inv_std), _ptr(params), _stream(stream), _ptr(out)))
         return out
 
     def shape_mlp_forward(self, f_q, f_lib, mean, inv_std, params, x, h, out, idx=None,
@@ -594,21 +728,55 @@ class Engine:
         """Training forward: shape_mlp_infer's output in out [n, 2], plus the
         standardised features x [n, 96] and hidden activations h[0..2]
         [n, 256] (FP32, after ReLU) that the backward pass reads."""
-        if idx is not None:
-            idx = idx.to(torch.int32).contiguous()
-            n = idx.numel()
-        elif n is None:
-            n = f_lib.shape[0]
-        if qidx is not None:
-            qidx = qidx.to(torch.int32).contiguous()
+        arg = _Args(self, stream)
+        f_q, f_lib, mean, inv_std, idx, qidx, n, fo_cross, params = self._pair_args(
+            arg, f_q, f_lib, mean, inv_std, idx, qidx, n, fo_cross, params)
+        arg.out(out, "out", torch.float32, (n, 2))
+        arg.out(x, "x", torch.float32, (n, 96))
+        for i in range(3):
+            arg.out(h[i], f"h[{i}]", torch.float32, (n, 256))
         self._check(load_library().shape_mlp_forward(
-            self._ctx, _ptr(f_q.contiguous()), _ptr(f_lib.contiguous()), _ptr(qidx), _ptr(idx),
-            int(n), _ptr(fo_cross), _ptr(mean), _ptr(inv_std), _ptr(params), _stream(stream),
-            _ptr(x), _ptr(h[0]), _ptr(h[1]), _ptr(h[2]), _ptr(out)))
+            self._ctx, _ptr(f_q), _ptr(f_lib), _ptr(qidx), _ptr(idx), n, _ptr(fo_cross),
+            _ptr(mean), _ptr(inv_std), _ptr(params), _stream(stream), _ptr(x), _ptr(h[0]),
+            _ptr(h[1]), _ptr(h[2]), _ptr(out)))
         return out
+
+    def _strided(self, t, name, rows, cols, s_row, s_col, optional=False):
+        """An operand addressed by the caller's own strides from its first
+        element: float32 on the engine's device, used as it is (no copy,
+        which would change what the strides address), and every element
+        (r s_row + c s_col) inside the memory behind the tensor."""
+        if t is None:
+            if optional:
+                return None
+            raise ValueError(f"{name} is required")
+        if not isinstance(t, torch.Tensor):
+            raise TypeError(f"{name} must be a tensor")
+        if t.dtype != torch.float32:
+            raise ValueError(f"{name} has dtype {t.dtype}, expected torch.float32")
+        if s_row < 0 or s_col < 0:
+            raise ValueError(f"{name}: negative stride")
+        avail = t.untyped_storage().nbytes() // 4 - t.storage_offset()
+        last = (rows - 1) * s_row + (cols - 1) * s_col
+        if last >= avail:
+            raise ValueError(f"{name}: element {last} lies past the {avail} elements behind it")
+        if t.device != self.torch_device:
+            raise ValueError(f"{name} is on {t.device}, expected {self.torch_device}")
+        return t
+
+    def _gemm_checked(self, M, N, K, A, sam, sak, B, sbk, sbn, C, scm, bias, gate, sgm):
+        M, N, K = int(M), int(N), int(K)
+        A = self._strided(A, "A", M, K, int(sam), int(sak))
+        B = self._strided(B, "B", K, N, int(sbk), int(sbn))
+        self._strided(C, "C", M, N, int(scm), 1)
+        bias = self._strided(bias, "bias", 1, N, 0, 1, optional=True)
+        gate = self._strided(gate, "gate", M, N, int(sgm), 1, optional=True)
+        return A, B, bias, gate
 
     def shape_gemm(self, M, N, K, A, sam, sak, B, sbk, sbn, C, scm, bias=None, gate=None, sgm=0,
                    bf16=True, relu=False, stream=None):
+        A, B, bias, gate = self._gemm_checked(M, N, K, A, sam, sak, B, sbk, sbn, C, scm, bias,
+                                              gate, sgm)
         flags = (1 if bf16 else 0) | (2 if relu else 0)
         self._check(load_library().shape_gemm(
             self._ctx, int(M), int(N), int(K), _ptr(A), int(sam), int(sak), _ptr(B), int(sbk),
@@ -622,9 +790,12 @@ class Engine:
         n = len(products)
         arr = (ShapeGemmDesc * n)()
         for d, p in zip(arr, products):
-            d.A, d.B, d.C = p["A"].data_ptr(), p["B"].data_ptr(), p["C"].data_ptr()
-            d.bias = p["bias"].data_ptr() if p.get("bias") is not None else None
-            d.gate = p["gate"].data_ptr() if p.get("gate") is not None else None
+            A, B, bias, gate = self._gemm_checked(
+                p["M"], p["N"], p["K"], p["A"], p["sam"], p["sak"], p["B"], p["sbk"],
+                p["sbn"], p["C"], p["scm"], p.get("bias"), p.get("gate"), p.get("sgm", 0))
+            d.A, d.B, d.C = A.data_ptr(), B.data_ptr(), p["C"].data_ptr()
+            d.bias = bias.data_ptr() if bias is not None else None
+            d.gate = gate.data_ptr() if gate is not None else None
             d.sam, d.sak, d.sbk, d.sbn = int(p["sam"]), int(p["sak"]), int(p["sbk"]), int(p["sbn"])
             d.scm, d.sgm = int(p["scm"]), int(p.get("sgm", 0))
             d.M, d.N, d.K = int(p["M"]), int(p["N"]), int(p["K"])
@@ -632,13 +803,20 @@ class Engine:
         self._check(load_library().shape_gemm_set(self._ctx, n, arr, _stream(stream)))
 
     def shape_colsum(self, A, M, N, lda, out, stream=None):
+        arg = _Args(self, stream)
+        A = self._strided(A, "A", int(M), int(N), int(lda), 1)
+        arg.out(out, "out", torch.float32, (int(N),))
         self._check(load_library().shape_colsum(self._ctx, int(M), int(N), _ptr(A), int(lda),
                                                 _ptr(out), _stream(stream)))
 
     def shape_colsum_set(self, mats, stream=None):
         """Column sums of several matrices in one launch: mats is a list of
         (A, M, N, lda, out) with device float tensors A and out."""
+        arg = _Args(self, stream)
         n = len(mats)
+        for A, M, N, lda, out in mats:
+            self._strided(A, "A", int(M), int(N), int(lda), 1)
+            arg.out(out, "out", torch.float32, (int(N),))
         Ms = (ctypes.c_int32 * n)(*[int(m[1]) for m in mats])
         Ns = (ctypes.c_int32 * n)(*[int(m[2]) for m in mats])
         ldas = (ctypes.c_int64 * n)(*[int(m[3]) for m in mats])
@@ -649,34 +827,55 @@ class Engine:
                                                     v(outs), _stream(stream)))
 
     def shape_mse(self, y, t, w, grad, loss, stream=None):
+        arg = _Args(self, stream)
+        y = arg(y, "y", torch.float32, shape=(None, None))
         B, N = y.shape
+        t = arg(t, "t", torch.float32, shape=(B, N))
+        w = arg(w, "w", torch.float32, numel=N)
+        arg.out(grad, "grad", torch.float32, (B, N))
+        arg.out(loss, "loss", torch.float32, (1,))
         self._check(load_library().shape_mse(self._ctx, int(B), int(N), _ptr(y), _ptr(t),
                                              _ptr(w), _stream(stream), _ptr(grad), _ptr(loss)))
 
     def shape_adam(self, p, g, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        arg = _Args(self, stream)
+        arg.out(p, "p", torch.float32, tuple(p.shape))
+        arg.out(m, "m", torch.float32, tuple(p.shape))
+        arg.out(v, "v", torch.float32, tuple(p.shape))
+        arg.out(step, "step", torch.int32, (1,))
+        g = arg(g, "g", torch.float32, numel=p.numel())
         self._check(load_library().shape_adam(self._ctx, _ptr(p), _ptr(g), _ptr(m), _ptr(v),
                                                p.numel(), _ptr(step), float(lr), float(beta1),
                                                float(beta2), float(eps), _stream(stream)))
 
     def shape_topk(self, score, k, out=None, stream=None) -> torch.Tensor:
+        arg = _Args(self, stream)
+        score = arg(score, "score", torch.float32)
         if out is None:
             out = torch.empty(int(k), dtype=torch.int32, device=self.torch_device)
-        self._check(load_library().shape_topk(self._ctx, _ptr(score.contiguous()),
-                                              score.numel(), int(k), _stream(stream), _ptr(out)))
+        arg.out(out, "out", torch.int32, (int(k),))
+        self._check(load_library().shape_topk(self._ctx, _ptr(score), score.numel(), int(k),
+                                              _stream(stream), _ptr(out)))
         return out
 
     def shape_seed_budget(self, raw, y_mean, y_std, tau, round_per_pair, cap_per_pair, idx=None,
                           k=None, out=None, stream=None) -> torch.Tensor:
         """Sample budgets n = (exp(raw[:, 1] y_std + y_mean) / tau)^2 in whole
         rounds within [round, cap], for rows idx (device int32 [k])."""
+        arg = _Args(self, stream)
+        _check_out(raw, "raw", torch.float32, (None, None), self.torch_device)
+        if raw.shape[1] < 2:
+            raise ValueError("raw needs at least two columns")
         if idx is not None:
-            idx = idx.to(torch.int32).contiguous()
+            idx = arg(idx, "idx", torch.int32, shape=(None,))
             k = idx.numel()
         elif k is None:
             k = raw.shape[0]
+        elif int(k) > raw.shape[0]:
+            raise ValueError("k exceeds the rows of raw")
         if out is None:
             out = torch.empty(int(k), dtype=torch.int32, device=self.torch_device)
-        assert raw.stride(1) == 1 and raw.shape[1] >= 2
+        arg.out(out, "out", torch.int32, (int(k),))
         self._check(load_library().shape_seed_budget(
             self._ctx, _ptr(raw), int(raw.stride(0)), _ptr(idx), int(k), float(y_mean),
             float(y_std), float(tau), int(round_per_pair), int(cap_per_pair), _stream(stream),

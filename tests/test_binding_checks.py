@@ -1,0 +1,139 @@
+"""The Python binding checks every tensor it hands to the C ABI as a raw
+device pointer (device, dtype, layout, size) and raises before any library
+call, so that no kernel can be given a host pointer or too short an array.
+Runs on the CPU: the engines below have no library context.  One expects
+its tensors on cuda:0 and is handed host tensors (the device check must
+fire); the other expects them on the host, so that the shape, dtype and
+size checks are the ones that fire."""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2607_20766_amd.engine import Engine, Molecules
+
+
+def _engine(device):
+    e = Engine.__new__(Engine)
+    e.device = 0
+    e._ctx = ctypes.c_void_p()
+    e.torch_device = torch.device(device)
+    return e
+
+
+@pytest.fixture
+def eng():
+    return _engine("cpu")
+
+
+@pytest.fixture
+def eng_cuda():
+    return _engine("cuda:0")
+
+
+def _mols(n_mols=3, atoms=4, dev="cpu"):
+    off = torch.arange(0, (n_mols + 1) * atoms, atoms, dtype=torch.int32, device=dev)
+    xyz = torch.zeros(n_mols * atoms, 3, dtype=torch.float32, device=dev)
+    alpha = torch.ones(n_mols * atoms, dtype=torch.float32, device=dev)
+    return Molecules(off, xyz, alpha, None, atoms)
+
+
+def test_host_tensors_are_refused(eng_cuda):
+    with pytest.raises(ValueError, match="query.offsets is on cpu"):
+        eng_cuda.shape_screen(_mols(1), _mols())
+    with pytest.raises(ValueError, match="A is on cpu"):
+        eng_cuda.shape_gemm(10, 4, 8, torch.zeros(10, 8), 8, 1, torch.zeros(8, 4), 4, 1,
+                            torch.zeros(10, 4), 4)
+    with pytest.raises(ValueError, match="f_q is on cpu"):
+        eng_cuda.shape_pair_features(torch.zeros(1, 24), torch.zeros(5, 24), torch.zeros(96),
+                                     torch.ones(96))
+
+
+def test_molecule_layout(eng):
+    M = _mols()
+    M.offsets = M.offsets.to(torch.int64)
+    with pytest.raises(ValueError, match="offsets has dtype"):
+        eng.shape_features(M)
+    M = _mols()
+    M.alpha = M.alpha[:-1]
+    with pytest.raises(ValueError, match="alpha has shape"):
+        eng.shape_features(M)
+    M = _mols()
+    M.xyz = M.xyz.t().contiguous().t()
+    with pytest.raises(ValueError, match="xyz must be contiguous"):
+        eng.shape_features(M)
+    M = _mols()
+    M.max_atoms = 300
+    with pytest.raises(ValueError, match="max_atoms"):
+        eng.shape_features(M)
+
+
+def test_budgets_and_outputs_must_match_the_pairs(eng, eng_cuda):
+    Q, L = _mols(1), _mols(5)
+    with pytest.raises(ValueError, match="n_start has 4 elements, expected 5"):
+        eng.shape_screen(Q, L, n_start=torch.zeros(4, dtype=torch.int32))
+    with pytest.raises(ValueError, match="pairs has shape"):
+        eng.shape_screen(Q, L, pairs=torch.zeros(2, 2, dtype=torch.int32))
+    with pytest.raises(ValueError, match="n_start is on meta"):
+        eng.shape_screen(Q, L, n_start=torch.zeros(5, dtype=torch.int32, device="meta"))
+    bad_out = {k: torch.empty(4) for k in ("T", "se_T", "O_ab", "O_aa", "O_bb")}
+    bad_out["n_used"] = torch.empty(4, dtype=torch.int32)
+    with pytest.raises(ValueError, match=r"out\['T'\] has shape"):
+        eng.shape_screen(Q, L, n_pairs=5, out=bad_out)
+    with pytest.raises(ValueError, match=r"out\['T'\] is required"):
+        eng.shape_screen(Q, L, n_pairs=5, out={"se_T": torch.empty(5)})
+
+
+def test_alignment_arguments(eng):
+    A, B = _mols(3), _mols(3)
+    with pytest.raises(ValueError, match="pose has shape"):
+        eng.shape_align_grad(A, B, torch.zeros(2, 4, 7), torch.zeros(3), torch.zeros(3))
+    with pytest.raises(ValueError, match="O_aa has 2 elements"):
+        eng.shape_align_grad(A, B, torch.zeros(3, 4, 7), torch.zeros(2), torch.zeros(3))
+    with pytest.raises(ValueError, match="pose has shape"):
+        eng.shape_fo_align(A, B, torch.zeros(3, 4, 6))
+    with pytest.raises(ValueError, match="pose has dtype"):
+        eng.shape_align(A, B, torch.zeros(3, 4, 7, dtype=torch.float64))
+    with pytest.raises(ValueError, match="out has shape"):
+        eng.shape_fo_starts(A, B, n_random=3, out=torch.zeros(3, 7, 7))
+    with pytest.raises(ValueError, match="pose has shape"):
+        eng.shape_apply_pose(A, torch.zeros(2, 7))
+
+
+def test_strided_operands_stay_inside_their_memory(eng):
+    A = torch.zeros(10, 8)
+    B = torch.zeros(8, 4)
+    C = torch.zeros(10, 4)
+    with pytest.raises(ValueError, match="A: element 86 lies past the 80"):
+        eng.shape_gemm(10, 4, 8, A, 8, 2, B, 4, 1, C, 4)        # column stride too big
+    with pytest.raises(ValueError, match="C: element"):
+        eng.shape_gemm(11, 4, 8, torch.zeros(11, 8), 8, 1, B, 4, 1, C, 4)
+    with pytest.raises(ValueError, match="bias: element"):
+        eng.shape_gemm(10, 4, 8, A, 8, 1, B, 4, 1, C, 4, bias=torch.zeros(3))
+    with pytest.raises(ValueError, match="has dtype"):
+        eng.shape_gemm(10, 4, 8, A.double(), 8, 1, B, 4, 1, C, 4)
+    # a view's strides count from its own first element
+    view = torch.zeros(100)[90:]
+    with pytest.raises(ValueError, match="lies past the 10 elements"):
+        eng.shape_colsum(view, 3, 4, 4, torch.zeros(4))
+
+
+def test_triage_arguments(eng):
+    f_q, f_l = torch.zeros(1, 24), torch.zeros(50, 24)
+    mean, isd = torch.zeros(96), torch.ones(96)
+    with pytest.raises(ValueError, match="f_lib has shape"):
+        eng.shape_pair_features(f_q, torch.zeros(50, 23), mean, isd)
+    with pytest.raises(ValueError, match="n = 60 exceeds"):
+        eng.shape_pair_features(f_q, f_l, mean, isd, n=60)
+    with pytest.raises(ValueError, match="fo_cross has 49 elements"):
+        eng.shape_pair_features(f_q, f_l, mean, isd, fo_cross=torch.zeros(49))
+    with pytest.raises(ValueError, match="params has"):
+        eng.shape_mlp_infer(f_q, f_l, mean, isd, torch.zeros(10))
+    with pytest.raises(ValueError, match="k exceeds"):
+        eng.shape_seed_budget(torch.zeros(5, 2), 0.0, 1.0, 0.005, 512, 65536, k=6)
+    with pytest.raises(ValueError, match="w has 3 elements"):
+        eng.shape_mse(torch.zeros(5, 2), torch.zeros(5, 2), torch.zeros(3), torch.zeros(5, 2),
+                      torch.zeros(1))
+    with pytest.raises(ValueError, match="out has shape"):
+        eng.shape_topk(torch.zeros(20), 5, out=torch.zeros(4, dtype=torch.int32))

@@ -144,6 +144,51 @@ def test_capture_refuses_sync_calls_and_growth(eng, data):
     assert np.all(np.isfinite(got["T"]))
 
 
+def test_graph_survives_scratch_growth(eng, data):
+    """An eager call that grows the context's scratch while a graph is alive
+    retires the old buffers instead of freeing them, so the graph's replays
+    still address live memory and give the captured calls' results; the
+    retired buffers go with the last graph.  The replay below runs only once
+    the context reports the retirement."""
+    Q, lib = data
+    n = lib.n_mols
+    out = _alloc(n, eng.torch_device)
+    kw = dict(mode=SHAPE_SCREEN_ADAPTIVE, round_per_pair=512, cap_per_pair=8192, seed=7)
+    direct = _np(eng.shape_screen(Q, lib, **kw))
+    g = eng.capture(lambda: eng.shape_screen(Q, lib, out=out, **kw))
+    try:
+        info = eng.memory_info()
+        assert info["live_graphs"] == 1 and info["retired_bytes"] == 0
+        big = molgen.library(13, 4 * n + 700, 10, 50, workers=1)
+        Lbig = eng.molecules(big)
+        print("case: eager screen growing scratch under a live graph", flush=True)
+        eng.shape_screen(Q, Lbig, mode=SHAPE_SCREEN_FIXED, n_per_side=1 << 16, seed=1)
+        torch.cuda.synchronize()
+        info = eng.memory_info()
+        assert info["retired_bytes"] > 0 and info["live_graphs"] == 1
+        for v in out.values():
+            v.fill_(-1)
+        print("case: replay after growth", flush=True)
+        g.replay()
+        torch.cuda.synchronize()
+        _same(direct, _np(out))
+        # a graph launches only with the context that captured it
+        other = Engine(0)
+        with pytest.raises(ShapeError) as ei:
+            load_library_graph_launch(other, g)
+        assert ei.value.code == -1
+        other.close()
+    finally:
+        g.close()
+    info = eng.memory_info()
+    assert info["live_graphs"] == 0 and info["retired_bytes"] == 0
+
+
+def load_library_graph_launch(e, g):
+    from paper_2607_20766_amd.engine import _stream, load_library
+    e._check(load_library().shape_graph_launch(e._ctx, g._handle, _stream(None)))
+
+
 def test_triage_screen_as_graph(eng, data):
     """The whole surrogate-triaged screen (features, first-order overlaps,
     fused network, top-k, seeded budgets, adaptive IS) replays as one graph."""
