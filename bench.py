@@ -34,20 +34,23 @@ ROUND = 512
 CAP = 65536
 N_FIXED = 4096
 
-# ALU roofline of the density loop.  Algorithmic work of one atom
-# evaluation (o_i at one point plus its m/u update): 9 FP32 VALU operations
-# (3 sub, 1 mul + 2 fma for |r-c|^2, 1 mul by alpha log2 e, 1 add for m, 1 fma
-# for the union product) and one v_exp_f32, which occupies EXP_SLOTS FMA issue
-# slots on gfx950 (measured: 3.1).  Peak: the published FP32 vector rate,
-# 157.3 TFLOP/s = 78.65e12 FMA lane-operations/s.
-VALU_PER_EVAL = 9
-EXP_SLOTS = 3
-OPS_PER_EVAL = VALU_PER_EVAL + EXP_SLOTS
-PEAK_LANE_OPS = 157.3e12 / 2
-# Measured HBM traffic of the adaptive screening kernel per launch (counters,
-# scaled by a plain copy); valid for the kernel version it was taken on, None
-# until the current version has been measured.
-TRAFFIC_BYTES = 79.9e6 + 2.4e6
+# Roofline of the density loop (bound by FP32 vector arithmetic, not HBM).
+# Algorithmic work of one atom evaluation (o_i at one point plus its m/u
+# update): 13 FP32 flops -- r - c (3 sub), |r - c|^2 (1 mul + 2 fma = 5),
+# times alpha (1 mul), m += o (1 add), u + o (1 - u) (1 sub + 1 fma = 3) --
+# and one exponential, which is not counted as a flop.  Peak: the published
+# FP32 vector rate of the MI355X, 157.3 TFLOP/s.
+FLOPS_PER_EVAL = 13
+PEAK_FP32_TFLOPS = 157.3
+# Per launch of the adaptive screening kernel on this workload (deterministic
+# for a given kernel build), from the rocprofv3 summaries in profiles/:
+# HBM bytes (FETCH_SIZE x2.0 + WRITE_SIZE x1.0, scaled by a 1 GiB copy of
+# known size) and executed wave instructions (SQ_INSTS_VALU,
+# SQ_INSTS_VALU_TRANS_F32).  None until taken on the current kernel.
+TRAFFIC_BYTES = 38986.6 * 1024 * 2.0 + 2370.0 * 1024 * 1.0
+VALU_INSTS = 6605088384
+TRANS_INSTS = 744223320
+COUNTER_SOURCE = "profiles/k_screen_100k_library_counters.md"
 
 
 def log(msg):
@@ -92,11 +95,41 @@ def cpu_baseline(q, L, target_s=15.0):
         done1 += idx.size
     dt1 = time.perf_counter() - t1
     return {"value": done / dt, "unit": "pairs/s", "cores": threads, "kind": "oracle",
+            "cpu_model": host_cpu_model(),
             "sample": f"adaptive screen (tau {TAU}, rounds of {ROUND}, cap {CAP}) of "
                       f"library molecules 0..{done - 1} ({done} pairs) against the "
                       f"30-atom query, FP64, {dt:.1f} s on {threads} threads",
             "value_one_thread": done1 / dt1,
             "sample_one_thread": f"molecules 0..{done1 - 1} ({done1} pairs), {dt1:.1f} s"}
+
+
+def issue_fraction(kernel_ms, peaks):
+    """Issue-slot use of the screening kernel: executed VALU wave
+    instructions per launch (counters), the transcendental ones weighted by
+    the measured cost of v_exp_f32 in FMA issue slots, x 64 lanes, per second
+    of kernel time, against the measured FMA issue rate of the same chip."""
+    exp_cost = peaks["fma_lane_ops_per_s"] / peaks["exp_lane_ops_per_s"]
+    out = {"peak_fma_lane_ops_per_s": peaks["fma_lane_ops_per_s"],
+           "exp_cost_fma_slots": exp_cost, "counters": COUNTER_SOURCE}
+    if VALU_INSTS is None or TRANS_INSTS is None:
+        out.update({"valu_insts_per_launch": None, "frac": None})
+        return out
+    slots = (VALU_INSTS - TRANS_INSTS) + TRANS_INSTS * exp_cost
+    rate = slots * 64 / (kernel_ms * 1e-3)
+    out.update({"valu_insts_per_launch": VALU_INSTS, "trans_insts_per_launch": TRANS_INSTS,
+                "issue_lane_slots_per_s": rate, "frac": rate / peaks["fma_lane_ops_per_s"]})
+    return out
+
+
+def host_cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def bench_align(eng, n_pairs, n_starts=16, n_steps=60, n_samples=2048, lr=0.05):
@@ -486,6 +519,12 @@ def main():
                     help="only copy 1 GiB device to device three times (a plain copy of known "
                          "size for scaling the FETCH_SIZE / WRITE_SIZE counters) and exit")
     ap.add_argument("--triage-library", type=int, default=1000000)
+    ap.add_argument("--peaks", action="store_true",
+                    help="only measure the instruction issue rates (FP32 FMA, v_exp_f32, "
+                         "v_mad_u64_u32, LDS reads) and exit")
+    ap.add_argument("--only", choices=("align", "hybrid", "triage", "ensemble", "accuracy"),
+                    help="run one secondary workload alone (for profiling) and print its "
+                         "section")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the engine has no multi-GPU path in this "
@@ -507,6 +546,21 @@ def main():
     from paper_2607_20766_amd.engine import (SCREEN_VARIANT_SHAPES, SHAPE_SCREEN_ADAPTIVE,
                                              SHAPE_SCREEN_FIXED, Engine)
 
+    if args.peaks:
+        eng = Engine(0)
+        r = eng.peak_rates()
+        r["device"] = torch.cuda.get_device_name(0)
+        r["compute_units"] = torch.cuda.get_device_properties(0).multi_processor_count
+        print(json.dumps(r), flush=True)
+        return
+    if args.only in ("align", "accuracy", "triage"):
+        eng = Engine(0)
+        fn = {"align": lambda: bench_align(eng, args.align_pairs),
+              "accuracy": lambda: bench_accuracy(eng),
+              "triage": lambda: bench_triage(eng, args.triage_library)}[args.only]
+        print(json.dumps({"section": args.only, args.only: fn()}), flush=True)
+        return
+
     log("generating workload")
     q = molgen.molecule(1, 0, 30)
     L = molgen.library(1, args.library, 10, 50)
@@ -518,6 +572,11 @@ def main():
     Q = eng.molecules(q, mol_id=[QUERY_ID])
     lib = eng.molecules(L)
     dev = eng.torch_device
+    if args.only in ("hybrid", "ensemble"):
+        fn = {"hybrid": lambda: bench_hybrid(eng, Q, lib),
+              "ensemble": lambda: bench_ensemble(eng, Q)}[args.only]
+        print(json.dumps({"section": args.only, args.only: fn()}), flush=True)
+        return
     n = L.n_mols
     out = {k: torch.empty(n, dtype=torch.float32, device=dev)
            for k in ("T", "se_T", "O_ab", "O_aa", "O_bb")}
@@ -552,6 +611,8 @@ def main():
 
     # work granularity of the screening kernel, autotuned on this workload
     # (every variant gives bit-identical results; untimed set-up)
+    log("measuring instruction issue rates")
+    peaks = eng.peak_rates()
     log("tuning the screening kernel")
     best, tune_ms = eng.shape_screen_tune(Q, lib, mode=SHAPE_SCREEN_ADAPTIVE,
                                           round_per_pair=ROUND, cap_per_pair=CAP, tau=TAU,
@@ -576,9 +637,8 @@ def main():
     n_side = n_used // 2
     other, own, plain = atom_evals(n_side, na, sizes)
     ev_other, ev_own, ev_plain = int(other.sum()), int(own.sum()), int(plain.sum())
-    ops = (ev_other + ev_own) * OPS_PER_EVAL
-    achieved = ops / (kern_ms * 1e-3) / 1e12
-    peak = PEAK_LANE_OPS / 1e12
+    evals = ev_other + ev_own
+    achieved = evals * FLOPS_PER_EVAL / (kern_ms * 1e-3) / 1e12
 
     log("timing fixed-budget screen")
     ms_fixed, kern_fixed = timed(fixed, args.steps, args.warmup)
@@ -618,19 +678,18 @@ def main():
             "kernel": "k_screen<%d, %d> (adaptive)" % SCREEN_VARIANT_SHAPES[best],
             "bound": "alu",
             "achieved": achieved,
-            "peak": peak,
-            "unit": "TOP/s",
-            "frac": achieved / peak,
-            # HBM bytes per launch from rocprofv3 FETCH_SIZE (x2.0) and
-            # WRITE_SIZE (x1.0) scaled by a 1 GiB copy of known size (the
-            # traffic summary in profiles/)
+            "peak": PEAK_FP32_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_TFLOPS,
             "traffic": TRAFFIC_BYTES,
             "kernel_ms": kern_ms,
-            "atom_evals_per_launch": ev_other + ev_own,
-            "ops_per_atom_eval": OPS_PER_EVAL,
-            "note": f"{VALU_PER_EVAL} FP32 VALU ops + v_exp_f32 at {EXP_SLOTS} FMA "
-                    "slots per atom evaluation x evaluations per launch / HIP-event "
-                    "kernel time; peak = published 157.3 TFLOP/s FP32 vector / 2",
+            "atom_evals_per_launch": evals,
+            "flops_per_atom_eval": FLOPS_PER_EVAL,
+            "note": f"{FLOPS_PER_EVAL} algorithmic FP32 flops per atom evaluation x "
+                    "evaluations per launch / HIP-event kernel time, against the published "
+                    "157.3 TFLOP/s FP32 vector peak (which counts packed FMAs); traffic = "
+                    "HBM bytes per launch from rocprofv3 counters scaled by a plain copy",
+            "issue": issue_fraction(kern_ms, peaks),
         },
         "fixed_budget": {
             "n_per_side": N_FIXED,
@@ -695,6 +754,7 @@ def main():
 
     if not args.no_triage:
         res["triage"] = bench_triage(eng, args.triage_library)
+    res["peaks"] = peaks
 
     if not args.no_cpu_baseline:
         log("CPU oracle baseline")

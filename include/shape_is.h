@@ -451,13 +451,15 @@ int shape_best_pose(shape_ctx* ctx, int32_t n_pairs, int32_t n_starts, const flo
 
 /* Conformer ensembles (max over conformers, the paper's accuracy lever):
  * for each group g of consecutive entries [group_offset[g],
- * group_offset[g+1]) of T (device float, e.g. one shape_screen output over a
- * library holding every conformer), best_T[g] = the largest T (device float
- * [n_groups]) and best_idx[g] its entry (device int32 [n_groups] or NULL);
- * lowest entry on ties, NaN never wins (all NaN: NaN and -1).
- * group_offset: device int32 [n_groups + 1], non-decreasing.  Asynchronous.
- * Errors: SHAPE_E_INVAL, SHAPE_E_RANGE, SHAPE_E_HIP. */
-int shape_group_max(shape_ctx* ctx, const float* T, const int32_t* group_offset,
+ * group_offset[g+1]) of T (device float [n_T], e.g. one shape_screen output
+ * over a library holding every conformer), best_T[g] = the largest T (device
+ * float [n_groups]) and best_idx[g] its entry (device int32 [n_groups] or
+ * NULL); lowest entry on ties, NaN never wins (all NaN or empty: NaN and -1).
+ * group_offset: device int32 [n_groups + 1], non-decreasing.  A group that
+ * is reversed or reaches outside [0, n_T) reads nothing: NaN and -1, and
+ * shape_check_data reports it.  Asynchronous.  Errors: SHAPE_E_INVAL,
+ * SHAPE_E_RANGE, SHAPE_E_HIP. */
+int shape_group_max(shape_ctx* ctx, const float* T, int64_t n_T, const int32_t* group_offset,
                     int32_t n_groups, void* stream, float* best_T, int32_t* best_idx);
 
 /* Moved coordinates of every molecule of M by its pose (device float
@@ -614,6 +616,17 @@ int shape_seed_budget(shape_ctx* ctx, const float* raw, int64_t ld, const int32_
                       int32_t k, double y_mean, double y_std, double tau,
                       int32_t round_per_pair, int32_t cap_per_pair, void* stream,
                       int32_t* n_start);
+
+/* Issue-rate microbenchmarks of the instructions the kernels are made of
+ * (measurement support, not part of the method): rates (HOST double[5]) =
+ * FP32 fused multiply-adds, v_exp_f32 exponentials and v_mad_u64_u32 integer
+ * multiply-adds per second, counted per lane (one wave instruction = 64),
+ * LDS bytes read per second, and FP32 fused multiply-adds per second with
+ * SGPR operands, each the best of three timed launches of
+ * sixteen workgroups of 256 lanes per compute unit with independent chains
+ * in every lane (the FMA operands in VGPRs: the full-rate form).  Synchronises `stream`.  Errors: SHAPE_E_INVAL, SHAPE_E_NOMEM,
+ * SHAPE_E_HIP; SHAPE_E_UNSUPPORTED during graph capture. */
+int shape_peak_rates(shape_ctx* ctx, void* stream, double* rates);
 
 /* Kernel timing (measurement support, not part of the method).  While
  * enabled, every call records a pair of HIP events on its stream around its

@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libshape_is.so")
 SOURCES = ["shape_kernels.hip", "shape_align.hip", "shape_surrogate.hip", "shape_hybrid.hip",
-           "shape_grid.hip", "shape_api.hip"]
+           "shape_grid.hip", "shape_peaks.hip", "shape_api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 

@@ -31,7 +31,7 @@ enum Slot {
   S_PARTIALS, S_RESULT, S_QS, S_QF2,
   S_SELF_A, S_SELF_B,
   S_MSE, S_TOPK_SEL, S_TOPK_HIST, S_TOPK_GT, S_TOPK_EQ, S_COLSUM, S_TUNE, S_MLP_PACK, S_FEAT_MOM, S_GEMM_PART,
-  S_GRID_BOX, S_GRID_TAB, S_GRID_PART,
+  S_GRID_BOX, S_GRID_TAB, S_GRID_PART, S_PEAK,
   S_COUNT
 };
 
@@ -1010,15 +1010,15 @@ int shape_best_pose(shape_ctx* c, int32_t n_pairs, int32_t n_starts, const float
   return SHAPE_OK;
 }
 
-int shape_group_max(shape_ctx* c, const float* T, const int32_t* group_offset, int32_t n_groups,
-                    void* stream, float* best_T, int32_t* best_idx) {
+int shape_group_max(shape_ctx* c, const float* T, int64_t n_T, const int32_t* group_offset,
+                    int32_t n_groups, void* stream, float* best_T, int32_t* best_idx) {
   if (!c) return SHAPE_E_INVAL;
-  if (n_groups < 0) return fail(c, SHAPE_E_RANGE, "n_groups < 0");
+  if (n_groups < 0 || n_T < 0) return fail(c, SHAPE_E_RANGE, "n_groups < 0 or n_T < 0");
   if (n_groups == 0) return SHAPE_OK;
-  if (!T || !group_offset || !best_T) return fail(c, SHAPE_E_INVAL, "NULL array");
+  if (!group_offset || !best_T || (n_T > 0 && !T)) return fail(c, SHAPE_E_INVAL, "NULL array");
   int rc = set_device(c);
   if (rc) return rc;
-  HIP_TRY(c, shape::launch_group_max(T, group_offset, n_groups, best_T, best_idx,
+  HIP_TRY(c, shape::launch_group_max(T, n_T, group_offset, n_groups, best_T, best_idx, c->flag,
                                      (hipStream_t)stream),
           "group max kernel");
   return SHAPE_OK;
@@ -1394,6 +1394,50 @@ int shape_topk(shape_ctx* c, const float* score, int32_t n, int32_t k, void* str
           "top-k kernels");
   timer.stop();
   return SHAPE_OK;
+}
+
+int shape_peak_rates(shape_ctx* c, void* stream, double* rates) {
+  if (!c) return SHAPE_E_INVAL;
+  if (c->capturing) return refuse_in_capture(c, "shape_peak_rates");
+  if (!rates) return fail(c, SHAPE_E_INVAL, "rates is NULL");
+  try {
+    int rc;
+    if ((rc = set_device(c))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const int lanes = shape::peak_blocks(c->n_cu) * 256;
+    void* out;
+    if ((rc = ensure(c, S_PEAK, (size_t)lanes * sizeof(float), &out))) return rc;
+    hipEvent_t e0, e1;
+    HIP_TRY(c, hipEventCreate(&e0), "hipEventCreate");
+    hipError_t e = hipEventCreate(&e1);
+    if (e != hipSuccess) {
+      (void)hipEventDestroy(e0);
+      return hip_fail(c, e, "hipEventCreate");
+    }
+    // loop counts that keep each kernel busy for about a millisecond or more
+    const int iters[5] = {16384, 4096, 8192, 2048, 8192};
+    for (int w = 0; w < 5 && e == hipSuccess; ++w) {
+      float best = 3.0e38f;
+      e = shape::launch_peak(w, c->n_cu, 64, (float*)out, st);  // warm-up
+      for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
+        float ms = 0.0f;
+        e = hipEventRecord(e0, st);
+        if (e == hipSuccess) e = shape::launch_peak(w, c->n_cu, iters[w], (float*)out, st);
+        if (e == hipSuccess) e = hipEventRecord(e1, st);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e == hipSuccess && ms < best) best = ms;
+      }
+      if (e == hipSuccess)
+        rates[w] = (double)lanes * iters[w] * shape::peak_work_per_iter(w) / (best * 1e-3);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return hip_fail(c, e, "peak kernels");
+    return SHAPE_OK;
+  } catch (...) {
+    return fail(c, SHAPE_E_HIP, "internal error");
+  }
 }
 
 int shape_timing_enable(shape_ctx* c, int enable) {

@@ -672,13 +672,22 @@ __global__ void k_best_pose(const float* __restrict__ T, const float* __restrict
 // Conformer ensembles: the largest T of each group of consecutive entries
 // (max over conformers); lowest index on ties, NaN never wins (a group of
 // NaN gives NaN and index -1).
-__global__ void k_group_max(const float* __restrict__ T, const int* __restrict__ goff,
-                            int n_groups, float* __restrict__ best_T, int* __restrict__ best_idx) {
+__global__ void k_group_max(const float* __restrict__ T, int64_t n_T, const int* __restrict__ goff,
+                            int n_groups, float* __restrict__ best_T, int* __restrict__ best_idx,
+                            int* __restrict__ flag) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= n_groups) return;
   int b = -1;
   float bv = -INFINITY;
-  for (int e = goff[g]; e < goff[g + 1]; ++e) {
+  const int e0 = goff[g], e1 = goff[g + 1];
+  if (e0 < 0 || e1 > n_T || e1 < e0) {
+    // a group outside T (or reversed) reads nothing: NaN, -1, data error
+    best_T[g] = __builtin_nanf("");
+    if (best_idx) best_idx[g] = -1;
+    atomicOr(flag, 1);
+    return;
+  }
+  for (int e = e0; e < e1; ++e) {
     const float t = T[e];
     if (t > bv || (b < 0 && t == bv)) {
       bv = t;
@@ -778,10 +787,10 @@ hipError_t launch_best_pose(const float* T, const float* pose, int n_pairs, int 
   return hipGetLastError();
 }
 
-hipError_t launch_group_max(const float* T, const int* goff, int n_groups, float* best_T,
-                            int* best_idx, hipStream_t st) {
-  hipLaunchKernelGGL(k_group_max, dim3((n_groups + 255) / 256), dim3(256), 0, st, T, goff,
-                     n_groups, best_T, best_idx);
+hipError_t launch_group_max(const float* T, int64_t n_T, const int* goff, int n_groups,
+                            float* best_T, int* best_idx, int* flag, hipStream_t st) {
+  hipLaunchKernelGGL(k_group_max, dim3((n_groups + 255) / 256), dim3(256), 0, st, T, n_T, goff,
+                     n_groups, best_T, best_idx, flag);
   return hipGetLastError();
 }
 

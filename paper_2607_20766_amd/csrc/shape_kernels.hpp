@@ -149,8 +149,8 @@ hipError_t launch_fo_align(const MolsDev& A, const MolsDev& B, const int* badA, 
 hipError_t launch_best_pose(const float* T, const float* pose, int n_pairs, int n_starts,
                             float* best_pose, float* best_T, hipStream_t st);
 hipError_t launch_apply_pose(const MolsDev& M, const float* pose, float* out, hipStream_t st);
-hipError_t launch_group_max(const float* T, const int* goff, int n_groups, float* best_T,
-                            int* best_idx, hipStream_t st);
+hipError_t launch_group_max(const float* T, int64_t n_T, const int* goff, int n_groups,
+                            float* best_T, int* best_idx, int* flag, hipStream_t st);
 hipError_t launch_seed_budget(const float* raw, int64_t ld, const int* idx, int k, double y_mean,
                               double y_std, double tau, int round, int cap, int* n_start,
                               hipStream_t st);
@@ -205,5 +205,13 @@ size_t screen_lds_bytes(int max_q, int max_b);
 constexpr int kScreenVariants = 8;
 extern const int kScreenVariantShape[kScreenVariants][2];  // {kSA, kSB}
 hipError_t launch_screen(const ScreenArgs& a, int variant, hipStream_t st);
+
+// issue-rate microbenchmarks (measurement support): which = 0 FP32 FMA,
+// 1 v_exp_f32, 2 v_mad_u64_u32, 3 LDS 16-byte reads, 4 FP32 FMA with SGPR
+// operands; out holds one float per
+// lane of the grid (peak_blocks(n_cu) x 256)
+int peak_blocks(int n_cu);
+hipError_t launch_peak(int which, int n_cu, int iters, float* out, hipStream_t st);
+double peak_work_per_iter(int which);
 
 }  // namespace shape

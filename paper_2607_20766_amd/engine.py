@@ -139,7 +139,7 @@ def load_library():
                                      i32, vp, i32, ctypes.c_float, vp, vp, vp]
         L.shape_best_pose.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp]
         L.shape_apply_pose.argtypes = [vp, ctypes.POINTER(ShapeMols), vp, vp, vp]
-        L.shape_group_max.argtypes = [vp, vp, vp, i32, vp, vp, vp]
+        L.shape_group_max.argtypes = [vp, vp, i64, vp, i32, vp, vp, vp]
         L.shape_features.argtypes = [vp, ctypes.POINTER(ShapeMols), vp, vp]
         L.shape_pair_features.argtypes = [vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp]
         L.shape_mlp_infer.argtypes = [vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp]
@@ -157,6 +157,7 @@ def load_library():
                                  ctypes.c_float, ctypes.c_float, vp]
         L.shape_topk.argtypes = [vp, vp, i32, i32, vp, vp]
         L.shape_seed_budget.argtypes = [vp, vp, i64, vp, i32, d, d, d, i32, i32, vp, vp]
+        L.shape_peak_rates.argtypes = [vp, vp, ctypes.POINTER(d)]
         L.shape_timing_enable.argtypes = [vp, ctypes.c_int]
         L.shape_timing_read.argtypes = [vp, ctypes.POINTER(d), ctypes.POINTER(i64), ctypes.c_int]
         _lib = L
@@ -617,23 +618,22 @@ class Engine:
     def shape_group_max(self, T: torch.Tensor, group_offset: torch.Tensor, best_T=None,
                         best_idx=None, stream=None):
         """Max over each group of consecutive entries (conformer ensembles):
-        (best T [groups], its entry [groups]).  The last offset must not
-        exceed T's length (checked on the host: one small device read)."""
+        (best T [groups], its entry [groups]); a group reaching outside T
+        gives NaN and -1 (bounded in the kernel, reported by
+        shape_check_data)."""
         arg = _Args(self, stream)
         group_offset = arg(group_offset, "group_offset", torch.int32, shape=(None,))
         T = arg(T, "T", torch.float32)
         g = group_offset.numel() - 1
-        if g > 0 and int(group_offset[-1].item()) > T.numel():
-            raise ValueError("group_offset runs past the end of T")
         if best_T is None:
             best_T = torch.empty(g, dtype=torch.float32, device=self.torch_device)
         if best_idx is None:
             best_idx = torch.empty(g, dtype=torch.int32, device=self.torch_device)
         arg.out(best_T, "best_T", torch.float32, (g,))
         arg.out(best_idx, "best_idx", torch.int32, (g,))
-        self._check(load_library().shape_group_max(self._ctx, _ptr(T), _ptr(group_offset), g,
-                                                   _stream(stream), _ptr(best_T),
-                                                   _ptr(best_idx)))
+        self._check(load_library().shape_group_max(self._ctx, _ptr(T), T.numel(),
+                                                   _ptr(group_offset), g, _stream(stream),
+                                                   _ptr(best_T), _ptr(best_idx)))
         return best_T, best_idx
 
     def shape_apply_pose(self, M: Molecules, pose: torch.Tensor, out=None,
@@ -881,6 +881,16 @@ class Engine:
             float(y_std), float(tau), int(round_per_pair), int(cap_per_pair), _stream(stream),
             _ptr(out)))
         return out
+
+    def peak_rates(self, stream=None) -> dict:
+        """Measured issue rates: FP32 FMA (VGPR operands), v_exp_f32 and
+        v_mad_u64_u32 lane operations per second, LDS bytes read per second,
+        FP32 FMA lane operations per second with SGPR operands."""
+        out = (ctypes.c_double * 5)()
+        self._check(load_library().shape_peak_rates(self._ctx, _stream(stream), out))
+        return {"fma_lane_ops_per_s": out[0], "exp_lane_ops_per_s": out[1],
+                "mad_u64_u32_lane_ops_per_s": out[2], "lds_read_bytes_per_s": out[3],
+                "fma_sgpr_operand_lane_ops_per_s": out[4]}
 
     def shape_timing_enable(self, enable: bool = True):
         self._check(load_library().shape_timing_enable(self._ctx, int(enable)))

@@ -255,6 +255,7 @@ def test_group_max(eng):
     off = np.array([0, 3, 6, 6, 10, 15, 40], np.int32)   # group 2 empty
     bT, bi = eng.shape_group_max(torch.from_numpy(T).cuda(), torch.from_numpy(off).cuda())
     bT, bi = bT.cpu().numpy(), bi.cpu().numpy()
+    eng.shape_check_data()   # every group inside T: no data error
     for gi in range(off.size - 1):
         seg = T[off[gi]:off[gi + 1]]
         key = np.where(np.isnan(seg), -np.inf, seg)
@@ -263,6 +264,21 @@ def test_group_max(eng):
         else:
             j = int(np.argmax(key))
             assert bi[gi] == off[gi] + j and bT[gi] == seg[j]
+
+
+def test_group_max_bounds_its_reads(eng):
+    """Offsets outside T (or reversed) read nothing: NaN and -1, reported as
+    a data error; the other groups are unaffected."""
+    T = torch.arange(10, dtype=torch.float32, device="cuda")
+    off = torch.tensor([0, 4, 12, 8, 10], dtype=torch.int32, device="cuda")
+    bT, bi = eng.shape_group_max(T, off)
+    bT, bi = bT.cpu().numpy(), bi.cpu().numpy()
+    assert bT[0] == 3.0 and bi[0] == 3
+    assert np.isnan(bT[1]) and bi[1] == -1      # runs past the end of T
+    assert np.isnan(bT[2]) and bi[2] == -1      # reversed
+    assert bT[3] == 9.0 and bi[3] == 9
+    with pytest.raises(ShapeError):
+        eng.shape_check_data()
 
 
 @pytest.mark.parametrize("aligned", [False, True])
