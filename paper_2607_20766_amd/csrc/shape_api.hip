@@ -1148,8 +1148,8 @@ int shape_fo_overlap(shape_ctx* c, const shape_mols* query, const shape_mols* li
     if (!out) return fail(c, SHAPE_E_INVAL, "out is NULL");
     if ((rc = set_device(c))) return rc;
     hipStream_t st = (hipStream_t)stream;
-    HIP_TRY(c, shape::launch_fo_cross(mols_dev(query), mols_dev(lib), pairs, n_pairs, c->flag,
-                                      out, st),
+    HIP_TRY(c, shape::launch_fo_cross(mols_dev(query), mols_dev(lib), pairs, n_pairs, c->n_cu,
+                                      c->flag, out, st),
             "first-order overlap kernel");
     return SHAPE_OK;
   } catch (...) {

@@ -116,7 +116,7 @@ hipError_t launch_pair_features(const float* fq, const float* flib, const int* q
                                 const int* idx, int n, const float* fo_cross, const float* mean,
                                 const float* inv_std, float* out, hipStream_t st);
 hipError_t launch_fo_cross(const MolsDev& Q, const MolsDev& L, const int* pairs, int n_pairs,
-                           int* flag, float* out, hipStream_t st);
+                           int n_cu, int* flag, float* out, hipStream_t st);
 hipError_t launch_gemm(const GemmArgs& g, hipStream_t st);
 // several BF16 products with 64 x 64 tiles in one launch (plus one split-K
 // reduction launch); part holds the sum of gemm_set_part_elems of the set

@@ -202,10 +202,18 @@ __global__ void k_features_eigen(int n_mols, const float* __restrict__ mom,
 
 // First-order cross-overlap of (query, library molecule) pairs at their
 // current poses, Eq. fo: sum_ij (pi/(a_i+a_j))^(3/2)
-// exp(-a_i a_j/(a_i+a_j) |c_i - c_j|^2); one wave per pair (four per
-// workgroup, sharing the query's atoms in LDS), the N_q N_b atom
-// pairs spread over all 64 lanes (row i = p / N_b stepped incrementally),
-// FP32 sums, DPP wave sum.
+// exp(-a_i a_j/(a_i+a_j) |c_i - c_j|^2).  Four waves per workgroup share the
+// query's atoms in LDS; each wave walks a contiguous run of pairs, one pair
+// at a time with all 64 lanes.  The query is the same for every pair, so the
+// lanes are laid out as NI query slots x 64/NI phases: lane l holds QT query
+// atoms i = ib + l % NI + t NI (t < QT) in registers and walks the library
+// molecule's atoms j = l / NI, l / NI + 64/NI, ... as LDS broadcasts; one
+// read of atom j feeds QT independent terms.  Slots past the query's last
+// atom hold a phantom atom 10^18 A away whose terms are exactly zero.  A
+// pair is only ~15 terms per lane, so the wave hides the memory latency
+// itself: the headers (molecule index, atom range) of 64 pairs are read at
+// once, one per lane, and the next pair's atoms are loaded while the current
+// pair's terms are summed.  FP32 sums, DPP wave sum.
 constexpr int kFoWaves = 4;
 
 __device__ __forceinline__ bool atom_ok(float al, float x, float y, float z) {
@@ -216,14 +224,34 @@ __device__ __forceinline__ bool atom_ok(float al, float x, float y, float z) {
 // with invalid data (offsets out of range, alpha <= 0, non-finite values)
 // gives NaN and raises the data-error flag; a pair index outside the
 // library gives NaN.
+constexpr int kFoChunks = SHAPE_MAX_ATOMS / kWave;  // library atoms per lane, at most
+
+// Phantom atoms 10^18 A from every real atom, the query's at +10^18 and the
+// library's at -10^18 on each axis (so two phantoms are 2 10^18 apart too):
+// every term with a phantom is exactly zero (exp2 of minus a huge number),
+// so padded slots need no branch.
+__device__ __forceinline__ float4 fo_phantom(float at) { return make_float4(at, at, at, 1.0f); }
+
+// NI query slots x 64/NI phases; CH chunks of 64 library atoms per lane at
+// most (1 when no library molecule passes 64 atoms).
+template <int NI, int CH>
 __global__ __launch_bounds__(kWave * kFoWaves) void k_fo_cross(
-    MolsDev Q, MolsDev L, const int* __restrict__ pairs, int n_pairs, int* __restrict__ flag,
-    float* __restrict__ out) {
-  // the query's atoms once per workgroup, each wave's library molecule apart
-  __shared__ float4 sA[SHAPE_MAX_ATOMS];
-  __shared__ float4 sBall[kFoWaves][SHAPE_MAX_ATOMS];
+    MolsDev Q, MolsDev L, const int* __restrict__ pairs, int n_pairs, int per_wave,
+    int* __restrict__ flag, float* __restrict__ out) {
+  constexpr int kPhases = kWave / NI;
+  constexpr int kUnroll = 2;
+  constexpr int kPad = kPhases * kUnroll;  // library atoms padded to a multiple of this
+  // query atoms [max_q], then each wave's library molecule [max_b padded]:
+  // (x, y, z, a' = log2(e) alpha)
+  extern __shared__ float4 fo_lds[];
+  float4* sA = fo_lds;
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-  const int p = xcd_chunk(blockIdx.x, gridDim.x) * kFoWaves + w;
+  const int max_b_pad = (L.max_atoms + kPad - 1) / kPad * kPad;
+  float4* sB = fo_lds + Q.max_atoms + w * max_b_pad;
+  // this wave's pairs [p_begin, p_end)
+  const int64_t g = (int64_t)blockIdx.x * kFoWaves + w;
+  const int p_begin = (int)min((int64_t)n_pairs, g * per_wave);
+  const int p_end = (int)min((int64_t)n_pairs, (int64_t)p_begin + per_wave);
   const int q0 = Q.off[0], q1 = Q.off[1], nq = q1 - q0;
   const bool q_range = q0 >= 0 && (int64_t)q1 <= Q.n_atoms && nq >= 1 && nq <= Q.max_atoms;
   int q_bad = q_range ? 0 : 1;
@@ -238,68 +266,99 @@ __global__ __launch_bounds__(kWave * kFoWaves) void k_fo_cross(
   }
   // reached by every wave (no return before it); the outcome is grid-uniform
   if (__syncthreads_or(q_bad)) {
-    if (p < n_pairs && lane == 0) out[p] = __builtin_nanf("");
+    for (int p = p_begin + lane; p < p_end; p += kWave) out[p] = __builtin_nanf("");
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(flag, 1);
     return;
   }
-  if (p >= n_pairs) return;
-  const int m = pairs ? pairs[p] : p;
-  bool m_bad = !(m >= 0 && m < L.n_mols);
-  int b0 = 0, nb = 0;
-  if (!m_bad) {
-    b0 = L.off[m];
-    const int b1 = L.off[m + 1];
-    nb = b1 - b0;
-    m_bad = !(b0 >= 0 && (int64_t)b1 <= L.n_atoms && nb >= 1 && nb <= L.max_atoms);
-  }
-  float4* sB = sBall[w];
-  bool a_bad = false;
-  if (!m_bad) {
-    for (int j = lane; j < nb; j += kWave) {
-      const float al = L.alpha[b0 + j];
-      const float x = L.xyz[3 * (b0 + j)], y = L.xyz[3 * (b0 + j) + 1],
-                  z = L.xyz[3 * (b0 + j) + 2];
-      if (!atom_ok(al, x, y, z)) a_bad = true;
-      sB[j] = make_float4(x, y, z, 1.44269504088896f * al);
+  const int li = lane % NI, ph = lane / NI;
+  for (int sub = p_begin; sub < p_end; sub += kWave) {
+    const int cnt = min(kWave, p_end - sub);
+    // headers of up to 64 pairs, one per lane: bit 0 the atom range is
+    // valid, bit 1 the molecule index lies in the library
+    int hb0 = 0, hnb = 0, hfl = 0;
+    if (lane < cnt) {
+      const int m = pairs ? pairs[sub + lane] : sub + lane;
+      if (m >= 0 && m < L.n_mols) {
+        hb0 = L.off[m];
+        const int b1 = L.off[m + 1];
+        hnb = b1 - hb0;
+        hfl = 2 | ((hb0 >= 0 && (int64_t)b1 <= L.n_atoms && hnb >= 1 && hnb <= L.max_atoms)
+                       ? 1 : 0);
+      }
+    }
+    // atoms (x, y, z, alpha) of one pair into registers, lane j owns atoms
+    // j, j + 64, ...; the loads stay in flight until the values are used
+    float4 nxt[CH];
+    auto load = [&](int k) {
+      const int b0 = __builtin_amdgcn_readlane(hb0, k), nb = __builtin_amdgcn_readlane(hnb, k);
+      const bool ok = __builtin_amdgcn_readlane(hfl, k) & 1;
+#pragma unroll
+      for (int c = 0; c < CH; ++c) {
+        const int j = c * kWave + lane;
+        if (ok && j < nb) {
+          const size_t a = (size_t)b0 + j;
+          nxt[c] = make_float4(L.xyz[3 * a], L.xyz[3 * a + 1], L.xyz[3 * a + 2], L.alpha[a]);
+        }
+      }
+    };
+    load(0);
+    for (int k = 0; k < cnt; ++k) {
+      const int p = sub + k;
+      const int nb = __builtin_amdgcn_readlane(hnb, k), fl = __builtin_amdgcn_readlane(hfl, k);
+      const int nb_pad = (nb + kPad - 1) / kPad * kPad;
+      bool a_bad = false;
+      if (fl & 1) {
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+          const int j = c * kWave + lane;
+          if (j < nb) {
+            const float4 a = nxt[c];
+            if (!atom_ok(a.w, a.x, a.y, a.z)) a_bad = true;
+            sB[j] = make_float4(a.x, a.y, a.z, 1.44269504088896f * a.w);
+          } else if (j < nb_pad) {
+            sB[j] = fo_phantom(-1e18f);
+          }
+        }
+      }
+      const bool data_bad = __ballot(a_bad) != 0;
+      if (k + 1 < cnt) load(k + 1);  // the next pair's atoms arrive during this pair's terms
+      if (!(fl & 1) || data_bad) {
+        if (lane == 0) {
+          out[p] = __builtin_nanf("");
+          // invalid data is flagged; an index outside the library only gives NaN
+          if (data_bad || (fl & 2)) atomicOr(flag, 1);
+        }
+        continue;
+      }
+      wave_lds_sync();
+      // With widths a' = log2(e) a and s = a'_i + a'_j: a'_i a'_j / s =
+      // log2(e) a_i a_j / (a_i + a_j), the exp2 exponent per unit d2, and
+      // s^(-3/2) = log2(e)^(-3/2) (a_i + a_j)^(-3/2); the constant
+      // (pi log2(e))^(3/2) is applied to the wave sum.  Per term: 12 VALU,
+      // one rsq, one exp2.
+      float acc = 0.0f;
+      for (int ib = 0; ib < nq; ib += NI) {  // one block unless the query passes NI atoms
+        const int i = ib + li;
+        const float4 ci = i < nq ? sA[i] : fo_phantom(1e18f);
+        const int n_iter = nb_pad / kPad;  // wave-uniform trip count
+        for (int t = 0; t < n_iter; ++t) {
+          const int j = ph + t * kPad;
+#pragma unroll
+          for (int u = 0; u < kUnroll; ++u) {
+            const float4 cj = sB[j + u * kPhases];
+            const float dx = ci.x - cj.x, dy = ci.y - cj.y, dz = ci.z - cj.z;
+            const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+            const float rs = __builtin_amdgcn_rsqf(ci.w + cj.w);
+            const float ir = rs * rs;
+            acc = fmaf(ir * rs, __builtin_amdgcn_exp2f(-(ci.w * cj.w * ir * d2)), acc);
+          }
+        }
+      }
+      const float sum = 9.64909578231936f * wave_sum_dpp(acc);  // (pi log2(e))^(3/2)
+      if (lane == 0) out[p] = sum;
+      wave_lds_sync();  // every read of this pair's atoms before the next pair's writes
     }
   }
-  const bool data_bad = __ballot(a_bad) != 0;
-  if (m_bad || data_bad) {
-    if (lane == 0) {
-      out[p] = __builtin_nanf("");
-      // invalid data is flagged; an index outside the library only gives NaN
-      if (data_bad || (m >= 0 && m < L.n_mols)) atomicOr(flag, 1);
-    }
-    return;
-  }
-  wave_lds_sync();
-  // x / nb for x <= 64 and nb <= 256 from the hardware reciprocal: x * (1/nb)
-  // is within 2^-15 of the quotient, which is an integer or at least 2^-8
-  // below the next one, so adding 2^-12 and truncating is exact
-  const float inv_nb = __builtin_amdgcn_rcpf((float)nb);
-  const int di = (int)fmaf((float)kWave, inv_nb, 0x1p-12f), dj = kWave - di * nb;
-  int i = (int)fmaf((float)lane, inv_nb, 0x1p-12f), j = lane - i * nb;
-  // With widths a' = log2(e) a in LDS, s = a'_i + a'_j = log2(e) (a_i + a_j):
-  // a'_i a'_j / s = log2(e) a_i a_j / (a_i + a_j), the exp2 exponent per unit
-  // d2, and s^(-3/2) = log2(e)^(-3/2) (a_i + a_j)^(-3/2); the constant
-  // (pi log2(e))^(3/2) is applied to the wave sum.
-  float acc = 0.0f;
-  for (; i < nq;) {
-    const float4 ci = sA[i], cj = sB[j];
-    const float dx = ci.x - cj.x, dy = ci.y - cj.y, dz = ci.z - cj.z;
-    const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-    const float rs = __builtin_amdgcn_rsqf(ci.w + cj.w);
-    const float ir = rs * rs;
-    acc = fmaf(ir * rs, __builtin_amdgcn_exp2f(-(ci.w * cj.w * ir * d2)), acc);
-    i += di;
-    j += dj;
-    if (j >= nb) {
-      j -= nb;
-      ++i;
-    }
-  }
-  const float s = 9.64909578231936f * wave_sum_dpp(acc);  // (pi log2(e))^(3/2)
-  if (lane == 0) out[p] = s;
 }
 
 __device__ __forceinline__ float pair_feature(const float* __restrict__ fq,
@@ -1165,11 +1224,38 @@ hipError_t launch_pair_features(const float* fq, const float* flib, const int* q
   return hipGetLastError();
 }
 
-hipError_t launch_fo_cross(const MolsDev& Q, const MolsDev& L, const int* pairs, int n_pairs,
-                           int* flag, float* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_fo_cross, dim3((unsigned)((n_pairs + kFoWaves - 1) / kFoWaves)),
-                     dim3(kWave * kFoWaves), 0, st, Q, L, pairs, n_pairs, flag, out);
+template <int NI, int CH>
+static hipError_t launch_fo_cross_t(const MolsDev& Q, const MolsDev& L, const int* pairs,
+                                    int n_pairs, int n_cu, int* flag, float* out,
+                                    hipStream_t st) {
+  constexpr int kPad = (kWave / NI) * 2;
+  const int max_b_pad = (L.max_atoms + kPad - 1) / kPad * kPad;
+  const dim3 block(kWave * kFoWaves);
+  const size_t lds = (size_t)(Q.max_atoms + kFoWaves * max_b_pad) * sizeof(float4);
+  // eight waves per SIMD over the chip, each with a contiguous run of pairs
+  const int64_t waves_wanted = (int64_t)(n_cu > 0 ? n_cu : 256) * 32;
+  const int per_wave = (int)((n_pairs + waves_wanted - 1) / waves_wanted);
+  const int64_t waves = (n_pairs + per_wave - 1) / per_wave;
+  const dim3 grid((unsigned)((waves + kFoWaves - 1) / kFoWaves));
+  hipLaunchKernelGGL((k_fo_cross<NI, CH>), grid, block, lds, st, Q, L, pairs, n_pairs, per_wave,
+                     flag, out);
   return hipGetLastError();
+}
+
+hipError_t launch_fo_cross(const MolsDev& Q, const MolsDev& L, const int* pairs, int n_pairs,
+                           int n_cu, int* flag, float* out, hipStream_t st) {
+  if (n_pairs <= 0) return hipSuccess;
+  // query slots: 16 (4 phases) up to 16 query atoms, 32 (2 phases) up to 32,
+  // 64 beyond (blocks of 64); one chunk of library atoms per lane up to 64
+  const bool one = L.max_atoms <= kWave;
+  if (Q.max_atoms <= 16)
+    return one ? launch_fo_cross_t<16, 1>(Q, L, pairs, n_pairs, n_cu, flag, out, st)
+               : launch_fo_cross_t<16, kFoChunks>(Q, L, pairs, n_pairs, n_cu, flag, out, st);
+  if (Q.max_atoms <= 32)
+    return one ? launch_fo_cross_t<32, 1>(Q, L, pairs, n_pairs, n_cu, flag, out, st)
+               : launch_fo_cross_t<32, kFoChunks>(Q, L, pairs, n_pairs, n_cu, flag, out, st);
+  return one ? launch_fo_cross_t<64, 1>(Q, L, pairs, n_pairs, n_cu, flag, out, st)
+             : launch_fo_cross_t<64, kFoChunks>(Q, L, pairs, n_pairs, n_cu, flag, out, st);
 }
 
 // Workgroup tile of launch_gemm: BF16 products use the LDS-tiled kernel,

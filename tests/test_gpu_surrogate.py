@@ -157,6 +157,31 @@ def test_fo_overlap_matches_oracle(eng):
     assert np.allclose(g, ref, rtol=1e-5)
 
 
+@pytest.mark.parametrize("q_atoms", [1, 16, 17, 32, 33, 64, 65, 256])
+def test_fo_overlap_every_lane_layout(eng, q_atoms):
+    """The cross-overlap kernel's lane layouts: query atoms per lane group
+    16 (4 phases over the library atoms), 32 (2 phases), 64 (1 phase), and
+    blocks of 64 beyond 64 atoms; library molecules of 1 to 256 atoms, a
+    ragged pair count and a pairs list with repeats, against the oracle's
+    closed form (Eq. fo) at 1e-5."""
+    q = molgen.molecule(80, q_atoms, q_atoms)
+    L = molgen.MolSet.concat([molgen.molecule(81, i, n) for i, n in
+                              enumerate((1, 2, 15, 16, 17, 31, 33, 50, 63, 64, 65, 128, 256))])
+    Q = eng.molecules(q)
+    lib = eng.molecules(L)
+    pairs = torch.tensor([12, 0, 5, 5, 11, 3, 7], dtype=torch.int32, device="cuda")
+    print(f"case: first-order cross overlap, query {q_atoms} atoms", flush=True)
+    g_all = eng.shape_fo_overlap(Q, lib).cpu().numpy()
+    g_sub = eng.shape_fo_overlap(Q, lib, pairs=pairs).cpu().numpy()
+    qa = (q.xyz, O.alpha_from_radius(q.radius, LAMBDA_P27))
+    la = O.alpha_from_radius(L.radius, LAMBDA_P27)
+    ref = np.array([O.fo_overlap(qa, (L.xyz[L.offsets[m]:L.offsets[m + 1]],
+                                      la[L.offsets[m]:L.offsets[m + 1]]))
+                    for m in range(L.n_mols)])
+    assert np.all(np.abs(g_all - ref) <= 1e-5 * ref), np.max(np.abs(g_all - ref) / ref)
+    assert np.array_equal(g_sub, g_all[pairs.cpu().numpy()])
+
+
 def test_triage_gain(eng):
     """Surrogate-seeded screening spends far fewer IS samples than plain
     confidence-bounded IS over the whole library, keeps the top 1 %, and
