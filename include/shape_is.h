@@ -571,6 +571,81 @@ typedef struct shape_gemm_desc {
  * shape_gemm; SHAPE_E_RANGE for n outside 1..8. */
 int shape_gemm_set(shape_ctx* ctx, int32_t n, const shape_gemm_desc* d, void* stream);
 
+/* The surrogate's weights (96-256-256-256-2 network, params packed as for
+ * shape_mlp_infer) in the two bfloat16 layouts the fused training step reads:
+ * matrix-core fragments of W_l for the forward and of W_l^T (l = 1..3) for
+ * the input-gradient chain.  packed: device buffer of SHAPE_MLP_PACK_BYTES,
+ * 16-byte aligned, caller-owned.  Asynchronous.  Errors: SHAPE_E_INVAL,
+ * SHAPE_E_HIP. */
+#define SHAPE_MLP_PACK_BYTES 598016
+int shape_mlp_pack(shape_ctx* ctx, const float* params, void* stream, void* packed);
+
+/* Optimiser state of shape_mlp_train_step (all device memory). */
+typedef struct shape_mlp_adam {
+  float* params;    /* [n_params] network parameters, updated in place      */
+  float* m;         /* [n_params] Adam first moments, updated               */
+  float* v;         /* [n_params] Adam second moments, updated              */
+  int32_t* step;    /* [1] steps taken so far, incremented                  */
+  void* packed;     /* SHAPE_MLP_PACK_BYTES: shape_mlp_pack(params) on entry,
+                       rewritten from the updated params                    */
+  float lr, beta1, beta2, eps;
+} shape_mlp_adam;
+
+#define SHAPE_MLP_STEP_MAX_ROWS 65536
+
+/* One training step of the learned-triage surrogate (96-256-256-256-2, BF16
+ * operands, FP32 accumulation) on a minibatch of n pairs: the forward of
+ * shape_mlp_forward (pair features as there: f_q, f_lib, qidx, idx,
+ * fo_cross, mean, inv_std), the weighted MSE of shape_mse against target
+ * (device float [n][2]) with weights loss_w (device float [2]), the backward
+ * of shape_mlp_backward (BF16) and the Adam update of shape_adam, with the
+ * same arithmetic, so the same bits in params, m, v, step, grad and loss as
+ * that sequence of calls.  Two kernel launches: the forward and the
+ * row-local part of the backward (ReLU-gated input gradients, 32-row chunk
+ * sums of the bias gradients, the loss terms) for 64 rows per workgroup;
+ * then the weight gradients in shape_gemm_set's split-K chunks, the bias
+ * sums, the loss, Adam and the packing of the new weights.
+ *   n      rows, a multiple of 64 in [64, SHAPE_MLP_STEP_MAX_ROWS]
+ *   opt    optimiser state; opt->packed must hold shape_mlp_pack(opt->params)
+ *          (a previous step leaves it so)
+ *   grad   device float [n_params] dloss/dparams of this step, or NULL
+ *   loss   device float [1]: the minibatch loss
+ * Uses context scratch (about 3.4 KB per row).  Asynchronous.  Errors:
+ * SHAPE_E_INVAL (NULL or misaligned array), SHAPE_E_RANGE (n, Adam
+ * hyper-parameters), SHAPE_E_NOMEM, SHAPE_E_HIP. */
+int shape_mlp_train_step(shape_ctx* ctx, const float* f_q, const float* f_lib,
+                         const int32_t* qidx, const int32_t* idx, int32_t n,
+                         const float* fo_cross, const float* mean, const float* inv_std,
+                         const float* target, const float* loss_w, const shape_mlp_adam* opt,
+                         void* stream, float* grad, float* loss);
+
+/* Backward pass of a dense ReLU network (the surrogate of learned triage:
+ * 96-256-256-256-2) for one minibatch: the gradient of a loss with respect to
+ * every parameter, given the forward's inputs and activations and the
+ * gradient with respect to the output.
+ *   n_layers   number of layers L, 1..8
+ *   width      HOST int32 [L + 1]: width[0] inputs, width[L] outputs
+ *   batch      rows of the minibatch, >= 1
+ *   params     device float, packed W_0, b_0, W_1, b_1, ... (W_l row-major
+ *              [width[l]][width[l+1]]), as for shape_mlp_infer
+ *   act        HOST array of L device pointers: act[0] the inputs [batch]
+ *              [width[0]], act[l] (l >= 1) the outputs of hidden layer l after
+ *              ReLU [batch][width[l]] (shape_mlp_forward's x, h1, h2, h3)
+ *   dout       device float [batch][width[L]]: dloss/doutput
+ *   flags      SHAPE_GEMM_BF16 (operands rounded to bfloat16, FP32
+ *              accumulation) or 0 (FP32 operands)
+ *   grad       device float, same layout as params: dloss/dparams
+ * dloss/dW_l = act[l]^T g_l and dloss/db_l = column sums of g_l, with g_{L-1}
+ * = dout and g_{l-1} = (g_l W_l^T) zeroed where act[l] <= 0.  The arithmetic
+ * of shape_gemm (the input gradients, with the ReLU gate), shape_gemm_set
+ * (all weight gradients) and shape_colsum_set (all bias gradients), so the
+ * same bits as those calls.  Uses context scratch for the hidden-layer
+ * gradients.  Asynchronous.  Errors: SHAPE_E_INVAL, SHAPE_E_RANGE,
+ * SHAPE_E_NOMEM, SHAPE_E_HIP. */
+int shape_mlp_backward(shape_ctx* ctx, int32_t n_layers, const int32_t* width, int32_t batch,
+                       const float* params, const float* const* act, const float* dout,
+                       uint32_t flags, void* stream, float* grad);
+
 /* Column sums out[n] = sum_m A[m*lda + n] (device float).  Asynchronous. */
 int shape_colsum(shape_ctx* ctx, int32_t M, int32_t N, const float* A, int64_t lda,
                  float* out, void* stream);

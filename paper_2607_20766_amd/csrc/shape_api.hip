@@ -31,7 +31,7 @@ enum Slot {
   S_PARTIALS, S_RESULT, S_QS, S_QF2,
   S_SELF_A, S_SELF_B,
   S_MSE, S_TOPK_SEL, S_TOPK_HIST, S_TOPK_GT, S_TOPK_EQ, S_COLSUM, S_TUNE, S_MLP_PACK, S_FEAT_MOM, S_GEMM_PART,
-  S_GRID_BOX, S_GRID_TAB, S_GRID_PART, S_PEAK,
+  S_GRID_BOX, S_GRID_TAB, S_GRID_PART, S_PEAK, S_MLP_D, S_MLP_STEP,
   S_COUNT
 };
 
@@ -1304,6 +1304,149 @@ int shape_gemm_set(shape_ctx* c, int32_t n, const shape_gemm_desc* d, void* stre
     HIP_TRY(c, shape::launch_gemm_set(n_set, set, (float*)part, (hipStream_t)stream),
             "gemm set kernels");
     return SHAPE_OK;
+  } catch (...) {
+    return fail(c, SHAPE_E_HIP, "internal error");
+  }
+}
+
+int shape_mlp_pack(shape_ctx* c, const float* params, void* stream, void* packed) {
+  if (!c) return SHAPE_E_INVAL;
+  if (!params || !packed) return fail(c, SHAPE_E_INVAL, "NULL array");
+  if ((uintptr_t)packed & 15u) return fail(c, SHAPE_E_INVAL, "packed must be 16-byte aligned");
+  int rc = set_device(c);
+  if (rc) return rc;
+  HIP_TRY(c, shape::launch_mlp_pack_all(params, packed, (hipStream_t)stream), "packing kernels");
+  return SHAPE_OK;
+}
+
+int shape_mlp_train_step(shape_ctx* c, const float* f_q, const float* f_lib, const int32_t* qidx,
+                         const int32_t* idx, int32_t n, const float* fo_cross, const float* mean,
+                         const float* inv_std, const float* target, const float* loss_w,
+                         const shape_mlp_adam* opt, void* stream, float* grad, float* loss) {
+  if (!c) return SHAPE_E_INVAL;
+  try {
+    const int rows = shape::mlp_step_rows();
+    if (n < rows || n > SHAPE_MLP_STEP_MAX_ROWS || n % rows)
+      return fail(c, SHAPE_E_RANGE, "n = %d: the fused step takes a multiple of %d rows in "
+                  "[%d, %d]", n, rows, rows, SHAPE_MLP_STEP_MAX_ROWS);
+    if (!f_q || !f_lib || !mean || !inv_std || !target || !loss_w || !opt || !loss)
+      return fail(c, SHAPE_E_INVAL, "NULL array");
+    if (!opt->params || !opt->m || !opt->v || !opt->step || !opt->packed)
+      return fail(c, SHAPE_E_INVAL, "NULL optimiser array");
+    if ((uintptr_t)opt->packed & 15u)
+      return fail(c, SHAPE_E_INVAL, "packed must be 16-byte aligned");
+    if (!(opt->lr > 0.f) || !(opt->beta1 >= 0.f && opt->beta1 < 1.f) ||
+        !(opt->beta2 >= 0.f && opt->beta2 < 1.f) || !(opt->eps > 0.f))
+      return fail(c, SHAPE_E_RANGE, "Adam hyper-parameters out of range");
+    int rc = set_device(c);
+    if (rc) return rc;
+    void* scratch;
+    if ((rc = ensure(c, S_MLP_STEP, shape::mlp_step_scratch_bytes(n), &scratch))) return rc;
+    shape::MlpStep s{};
+    s.fq = f_q;
+    s.flib = f_lib;
+    s.qidx = qidx;
+    s.idx = idx;
+    s.n = n;
+    s.fo_cross = fo_cross;
+    s.mean = mean;
+    s.inv_std = inv_std;
+    s.target = target;
+    s.lw = loss_w;
+    s.params = opt->params;
+    s.m = opt->m;
+    s.v = opt->v;
+    s.step = opt->step;
+    s.packed = opt->packed;
+    s.lr = opt->lr;
+    s.b1 = opt->beta1;
+    s.b2 = opt->beta2;
+    s.eps = opt->eps;
+    s.grad = grad;
+    s.loss = loss;
+    KernelTimer timer(c, (hipStream_t)stream);
+    HIP_TRY(c, shape::launch_mlp_step(s, scratch, (hipStream_t)stream), "training step kernels");
+    timer.stop();
+    return SHAPE_OK;
+  } catch (...) {
+    return fail(c, SHAPE_E_HIP, "internal error");
+  }
+}
+
+int shape_mlp_backward(shape_ctx* c, int32_t n_layers, const int32_t* width, int32_t batch,
+                       const float* params, const float* const* act, const float* dout,
+                       uint32_t flags, void* stream, float* grad) {
+  if (!c) return SHAPE_E_INVAL;
+  try {
+    if (n_layers < 1 || n_layers > shape::kGemmSetMax)
+      return fail(c, SHAPE_E_RANGE, "n_layers must be in 1..%d", shape::kGemmSetMax);
+    if (batch < 1) return fail(c, SHAPE_E_RANGE, "batch < 1");
+    if (!width || !params || !act || !dout || !grad) return fail(c, SHAPE_E_INVAL, "NULL array");
+    if (flags & ~SHAPE_GEMM_BF16) return fail(c, SHAPE_E_INVAL, "bad flags");
+    int64_t d_elems = 0;
+    for (int l = 0; l <= n_layers; ++l) {
+      if (width[l] < 1 || width[l] > 65536)
+        return fail(c, SHAPE_E_RANGE, "width[%d] = %d outside [1, 65536]", l, width[l]);
+      if (l < n_layers && !act[l]) return fail(c, SHAPE_E_INVAL, "act[%d] is NULL", l);
+      if (l >= 1 && l < n_layers) d_elems += (int64_t)batch * width[l];
+    }
+    int rc = set_device(c);
+    if (rc) return rc;
+    // gradients w.r.t. the hidden layers' outputs, through their ReLUs: kept
+    // until the weight-gradient products below have read them
+    void* dbuf = nullptr;
+    if (d_elems > 0 &&
+        (rc = ensure(c, S_MLP_D, (size_t)d_elems * sizeof(float), &dbuf)))
+      return rc;
+    int64_t off[shape::kGemmSetMax + 1];
+    off[0] = 0;
+    for (int l = 0; l < n_layers; ++l)
+      off[l + 1] = off[l] + (int64_t)width[l] * width[l + 1] + width[l + 1];
+    int64_t d_off[shape::kGemmSetMax];
+    for (int l = 1, o = 0; l < n_layers; ++l) {
+      d_off[l] = o;
+      o += (int)((int64_t)batch * width[l]);
+    }
+    shape_gemm_desc wg[shape::kGemmSetMax];
+    int32_t cM[shape::kColSetMax], cN[shape::kColSetMax];
+    const float* cA[shape::kColSetMax];
+    int64_t cld[shape::kColSetMax];
+    float* cout_[shape::kColSetMax];
+    const float* dz = dout;
+    int n = 0;
+    for (int l = n_layers - 1; l >= 0; --l, ++n) {
+      const int n_in = width[l], n_out = width[l + 1];
+      // dW[i][o] = sum_b act[l][b][i] dz[b][o]; db[o] = sum_b dz[b][o]
+      shape_gemm_desc& d = wg[n];
+      d = shape_gemm_desc{};
+      d.A = act[l];
+      d.sam = 1;
+      d.sak = n_in;
+      d.B = dz;
+      d.sbk = n_out;
+      d.sbn = 1;
+      d.C = grad + off[l];
+      d.scm = n_out;
+      d.M = n_in;
+      d.N = n_out;
+      d.K = batch;
+      d.flags = flags;
+      cM[n] = batch;
+      cN[n] = n_out;
+      cA[n] = dz;
+      cld[n] = n_out;
+      cout_[n] = grad + off[l] + (int64_t)n_in * n_out;
+      if (l > 0) {
+        // dh[b][i] = sum_o dz[b][o] W[i][o], zero where the ReLU was off
+        float* dn = (float*)dbuf + d_off[l];
+        if ((rc = shape_gemm(c, batch, n_in, n_out, dz, n_out, 1, params + off[l], 1, n_out, dn,
+                             n_in, nullptr, act[l], n_in, flags, stream)))
+          return rc;
+        dz = dn;
+      }
+    }
+    if ((rc = shape_gemm_set(c, n, wg, stream))) return rc;
+    return shape_colsum_set(c, n, cM, cN, cA, cld, cout_, stream);
   } catch (...) {
     return fail(c, SHAPE_E_HIP, "internal error");
   }

@@ -126,6 +126,25 @@ size_t gemm_set_part_elems(const GemmArgs& g);
 int64_t gemm_set_blocks(const GemmArgs& g);
 hipError_t launch_gemm_set(int n, const GemmArgs* gs, float* part, hipStream_t st);
 size_t mlp_pack_bytes();
+// fused training step of the surrogate (forward, MSE, backward, Adam)
+struct MlpStep {
+  const float *fq, *flib;
+  const int *qidx, *idx;
+  int n;
+  const float* fo_cross;
+  const float *mean, *inv_std, *target, *lw;
+  float *params, *m, *v;
+  int* step;
+  void* packed;
+  float lr, b1, b2, eps;
+  float* grad;
+  float* loss;
+};
+size_t mlp_pack_all_bytes();
+hipError_t launch_mlp_pack_all(const float* params, void* packed, hipStream_t st);
+int mlp_step_rows();
+size_t mlp_step_scratch_bytes(int n);
+hipError_t launch_mlp_step(const MlpStep& s, void* scratch, hipStream_t st);
 // dense-grid quadrature
 struct GridDims {
   double lo[3];

@@ -728,83 +728,154 @@ struct MlpArgs {
   float* h_out[3];     // and the hidden activations [n][256] (FP32, after ReLU)
 };
 
+// Staging of the fused network kernels: the standardised pair features of
+// rows [row0, row0 + ROWS) rounded to bf16 into H (rows beyond n zero);
+// kAct also writes them to a.x_out (FP32), kF into the FP32 staging F (row
+// stride kTrLdf).  Thread (part h, row r) writes feature blocks h BPT .. h
+// BPT + BPT - 1 of row r — the blocks are f_q, f_m, |f_q - f_m|, f_q * f_m,
+// 24 values each; h is uniform per wave, so the statistics are scalar loads.
+// Same expressions as pair_feature.
+constexpr int kTrLdf = kMlpHid + 4;   // FP32 staging row stride (floats)
+
+template <int ROWS, bool kAct, bool kF>
+__device__ __forceinline__ void mlp_stage_features(const MlpArgs& a, int row0, short* H,
+                                                   float* F) {
+  constexpr int NH = 256 / ROWS;   // threads per row in the feature staging
+  constexpr int BPT = 4 / NH;      // feature blocks of 24 per thread
+  constexpr int FPT = 24 * BPT;    // features per thread
+  const int tid = threadIdx.x;
+  const int r = tid & (ROWS - 1);
+  const int h = __builtin_amdgcn_readfirstlane(tid / ROWS);
+  const int p = row0 + r;
+  float raw[FPT];
+  if (p < a.n) {
+    const int m = a.idx ? a.idx[p] : p;
+    const int q = a.qidx ? a.qidx[p] : 0;
+    const float* fa = a.fq + (size_t)q * 24;
+    const float* fb = a.flib + (size_t)m * 24;
+    float va[24], vb[24];
+#pragma unroll
+    for (int k = 0; k < 24; ++k) {
+      va[k] = fa[k];
+      vb[k] = fb[k];
+    }
+#pragma unroll
+    for (int bb = 0; bb < BPT; ++bb) {
+      const int b = h * BPT + bb;  // uniform
+      float* out = raw + 24 * bb;
+      if (b == 0) {
+#pragma unroll
+        for (int k = 0; k < 24; ++k) out[k] = va[k];
+      } else if (b == 1) {
+#pragma unroll
+        for (int k = 0; k < 24; ++k) out[k] = vb[k];
+      } else if (b == 2) {
+#pragma unroll
+        for (int k = 0; k < 24; ++k) out[k] = fabsf(va[k] - vb[k]);
+      } else {
+#pragma unroll
+        for (int k = 0; k < 24; ++k) out[k] = va[k] * vb[k];
+      }
+      if (a.fo_cross && b >= 2) {
+        const float o = a.fo_cross[p];
+        out[23] = b == 2 ? o / (va[23] + vb[23] - o) : o;
+      }
+    }
+    const float* mu = a.mean + FPT * h;
+    const float* is = a.inv_std + FPT * h;
+#pragma unroll
+    for (int t = 0; t < FPT; ++t) raw[t] = (raw[t] - mu[t]) * is[t];
+    if (kAct) {
+      float4* xo = reinterpret_cast<float4*>(a.x_out + (size_t)p * kMlpIn + FPT * h);
+#pragma unroll
+      for (int c = 0; c < FPT / 4; ++c)
+        xo[c] = make_float4(raw[4 * c], raw[4 * c + 1], raw[4 * c + 2], raw[4 * c + 3]);
+    }
+  } else {
+#pragma unroll
+    for (int t = 0; t < FPT; ++t) raw[t] = 0.0f;
+  }
+  if (kF) {
+    float4* fo = reinterpret_cast<float4*>(F + r * kTrLdf + FPT * h);
+#pragma unroll
+    for (int c = 0; c < FPT / 4; ++c)
+      fo[c] = make_float4(raw[4 * c], raw[4 * c + 1], raw[4 * c + 2], raw[4 * c + 3]);
+  }
+  uint2* dst = reinterpret_cast<uint2*>(&H[r * kMlpLd + FPT * h]);
+#pragma unroll
+  for (int c = 0; c < FPT / 4; ++c)
+    dst[c] = make_uint2(to_bf16x2(raw[4 * c], raw[4 * c + 1]),
+                        to_bf16x2(raw[4 * c + 2], raw[4 * c + 3]));
+}
+
+// One layer of the fused network kernels as the transposed product: wave w
+// computes outputs [64 w, 64 w + 64) (weights as the A operand, fragments
+// packed as by k_mlp_pack) for all RB x 16 rows of H (activations, k along
+// the row, as the B operand), kbs k-blocks of 32 in increasing order.  Lane
+// (li, lk) ends with row 16 i + li, outputs 64 w + 16 j + 4 lk .. + 3 in
+// acc[i][j].
+template <int RB>
+__device__ __forceinline__ void mlp_layer_mfma(const v8s* __restrict__ W, const short* H, int kbs,
+                                               int wave, int lane, v4f (&acc)[RB][4]) {
+  const int li = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int i = 0; i < RB; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+  // weight fragments one k-block ahead of the products
+  v8s bn[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) bn[j] = W[(wave * 4 + j) * kWave + lane];
+  for (int kb = 0; kb < kbs; ++kb) {
+    v8s b[4], x[RB];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) b[j] = bn[j];
+    if (kb + 1 < kbs) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bn[j] = W[((kb + 1) * 16 + wave * 4 + j) * kWave + lane];
+    }
+#pragma unroll
+    for (int i = 0; i < RB; ++i)
+      x[i] = *reinterpret_cast<const v8s*>(&H[(16 * i + li) * kMlpLd + kb * 32 + 8 * lk]);
+#pragma unroll
+    for (int i = 0; i < RB; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = mfma_bf16_k32(b[j], x[i], acc[i][j]);
+  }
+}
+
+// Output layer (2 columns, padded to 16) of the fused network kernels: rows
+// [rbase, rbase + 16 OB) of H against the packed W_3; lane (li, lk) ends with
+// column li, rows rbase + 16 i + 4 lk .. + 3 in acc[i].
+template <int OB>
+__device__ __forceinline__ void mlp_out_mfma(const v8s* __restrict__ W, const short* H, int rbase,
+                                             int lane, v4f (&acc)[OB]) {
+  const int li = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int i = 0; i < OB; ++i) acc[i] = v4f{0.f, 0.f, 0.f, 0.f};
+  for (int kb = 0; kb < kMlpHid / 32; ++kb) {
+    const v8s b = W[kb * kWave + lane];
+#pragma unroll
+    for (int i = 0; i < OB; ++i) {
+      const v8s x = *reinterpret_cast<const v8s*>(
+          &H[(rbase + 16 * i + li) * kMlpLd + kb * 32 + 8 * lk]);
+      acc[i] = mfma_bf16_k32(x, b, acc[i]);
+    }
+  }
+}
+
 // kAct (training forward): the FP32 standardised features and hidden
 // activations are also written out (the backward's inputs), the same values
 // that shape_pair_features and the per-layer products would have written.
 // ROWS pairs per workgroup (128, or 64 for more workgroups and residency).
 template <int ROWS, bool kAct>
 __global__ __launch_bounds__(256, ROWS == 64 ? 4 : 2) void k_mlp_infer(MlpArgs a) {
-  constexpr int NH = 256 / ROWS;   // threads per row in the feature staging
-  constexpr int BPT = 4 / NH;      // feature blocks of 24 per thread
-  constexpr int FPT = 24 * BPT;    // features per thread
   constexpr int RB = ROWS / 16;    // row blocks of 16 per wave in the hidden layers
   __shared__ __align__(16) short H[ROWS * kMlpLd];
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
   const int li = lane & 15, lk = lane >> 4;
   const int row0 = blockIdx.x * ROWS;
-  // standardised pair features, rounded to bf16 (rows beyond n are zero):
-  // thread (part h, row r) writes feature blocks h BPT .. h BPT + BPT - 1 of
-  // row r — the blocks are f_q, f_m, |f_q - f_m|, f_q * f_m, 24 values each;
-  // h is uniform per wave, so the statistics are scalar loads.  Same
-  // expressions as pair_feature.
-  {
-    const int r = tid & (ROWS - 1);
-    const int h = __builtin_amdgcn_readfirstlane(tid / ROWS);
-    const int p = row0 + r;
-    float raw[FPT];
-    if (p < a.n) {
-      const int m = a.idx ? a.idx[p] : p;
-      const int q = a.qidx ? a.qidx[p] : 0;
-      const float* fa = a.fq + (size_t)q * 24;
-      const float* fb = a.flib + (size_t)m * 24;
-      float va[24], vb[24];
-#pragma unroll
-      for (int k = 0; k < 24; ++k) {
-        va[k] = fa[k];
-        vb[k] = fb[k];
-      }
-#pragma unroll
-      for (int bb = 0; bb < BPT; ++bb) {
-        const int b = h * BPT + bb;  // uniform
-        float* out = raw + 24 * bb;
-        if (b == 0) {
-#pragma unroll
-          for (int k = 0; k < 24; ++k) out[k] = va[k];
-        } else if (b == 1) {
-#pragma unroll
-          for (int k = 0; k < 24; ++k) out[k] = vb[k];
-        } else if (b == 2) {
-#pragma unroll
-          for (int k = 0; k < 24; ++k) out[k] = fabsf(va[k] - vb[k]);
-        } else {
-#pragma unroll
-          for (int k = 0; k < 24; ++k) out[k] = va[k] * vb[k];
-        }
-        if (a.fo_cross && b >= 2) {
-          const float o = a.fo_cross[p];
-          out[23] = b == 2 ? o / (va[23] + vb[23] - o) : o;
-        }
-      }
-      const float* mu = a.mean + FPT * h;
-      const float* is = a.inv_std + FPT * h;
-#pragma unroll
-      for (int t = 0; t < FPT; ++t) raw[t] = (raw[t] - mu[t]) * is[t];
-      if (kAct) {
-        float4* xo = reinterpret_cast<float4*>(a.x_out + (size_t)p * kMlpIn + FPT * h);
-#pragma unroll
-        for (int c = 0; c < FPT / 4; ++c)
-          xo[c] = make_float4(raw[4 * c], raw[4 * c + 1], raw[4 * c + 2], raw[4 * c + 3]);
-      }
-    } else {
-#pragma unroll
-      for (int t = 0; t < FPT; ++t) raw[t] = 0.0f;
-    }
-    uint2* dst = reinterpret_cast<uint2*>(&H[r * kMlpLd + FPT * h]);
-#pragma unroll
-    for (int c = 0; c < FPT / 4; ++c)
-      dst[c] = make_uint2(to_bf16x2(raw[4 * c], raw[4 * c + 1]),
-                          to_bf16x2(raw[4 * c + 2], raw[4 * c + 3]));
-  }
+  mlp_stage_features<ROWS, kAct, false>(a, row0, H, nullptr);
   __syncthreads();
   // three hidden layers: wave w computes all ROWS rows x columns [64 w, 64 w + 64)
   // as the transposed product (weights as the A operand, activations as B),
@@ -813,32 +884,8 @@ __global__ __launch_bounds__(256, ROWS == 64 ? 4 : 2) void k_mlp_infer(MlpArgs a
 #pragma unroll 1
   for (int l = 0; l < 3; ++l) {
     const int kbs = (l == 0 ? kMlpIn : kMlpHid) / 32;
-    const v8s* W = a.W + mlp_pack_offset(l) / 8;
     v4f acc[RB][4];
-#pragma unroll
-    for (int i = 0; i < RB; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
-    // weight fragments one k-block ahead of the products
-    v8s bn[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) bn[j] = W[(wave * 4 + j) * kWave + lane];
-    for (int kb = 0; kb < kbs; ++kb) {
-      v8s b[4], x[RB];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = bn[j];
-      if (kb + 1 < kbs) {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) bn[j] = W[((kb + 1) * 16 + wave * 4 + j) * kWave + lane];
-      }
-#pragma unroll
-      for (int i = 0; i < RB; ++i)
-        x[i] = *reinterpret_cast<const v8s*>(&H[(16 * i + li) * kMlpLd + kb * 32 + 8 * lk]);
-#pragma unroll
-      for (int i = 0; i < RB; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = mfma_bf16_k32(b[j], x[i], acc[i][j]);
-    }
+    mlp_layer_mfma<RB>(a.W + mlp_pack_offset(l) / 8, H, kbs, wave, lane, acc);
     __syncthreads();  // every wave has read this layer's input
     const float* bias = a.b[l];
 #pragma unroll
@@ -863,23 +910,11 @@ __global__ __launch_bounds__(256, ROWS == 64 ? 4 : 2) void k_mlp_infer(MlpArgs a
     }
     __syncthreads();
   }
-  // output layer (2 columns, padded to 16): wave w computes rows
-  // [RPW w, RPW w + RPW), RPW = ROWS / 4
+  // output layer: wave w computes rows [RPW w, RPW w + RPW), RPW = ROWS / 4
   {
     constexpr int RPW = ROWS / 4, OB = RPW / 16;
-    const v8s* W = a.W + mlp_pack_offset(3) / 8;
     v4f acc[OB];
-#pragma unroll
-    for (int i = 0; i < OB; ++i) acc[i] = v4f{0.f, 0.f, 0.f, 0.f};
-    for (int kb = 0; kb < kMlpHid / 32; ++kb) {
-      const v8s b = W[kb * kWave + lane];
-#pragma unroll
-      for (int i = 0; i < OB; ++i) {
-        const v8s x = *reinterpret_cast<const v8s*>(
-            &H[(RPW * wave + 16 * i + li) * kMlpLd + kb * 32 + 8 * lk]);
-        acc[i] = mfma_bf16_k32(x, b, acc[i]);
-      }
-    }
+    mlp_out_mfma<OB>(a.W + mlp_pack_offset(3) / 8, H, RPW * wave, lane, acc);
     if (li < kMlpOut) {
       const float bc = a.b[3][li];
 #pragma unroll
@@ -999,7 +1034,13 @@ __global__ __launch_bounds__(1024) void k_colsum_set(ColsumSet s) {
 
 // Weighted mean squared error over a batch: loss = sum_j w_j mean_b (y - t)^2,
 // grad = 2 w_j (y - t) / B.  Loss partials per block, then one block sums them
-// in order.
+// in order.  The two terms of one element, shared with the fused training
+// step: e = y - t.
+__device__ __forceinline__ float mse_grad(float w, float e, int B) { return 2.f * w * e / (float)B; }
+__device__ __forceinline__ double mse_loss(float w, float e, int B) {
+  return (double)w * (double)e * (double)e / (double)B;
+}
+
 __global__ __launch_bounds__(256) void k_mse(const float* __restrict__ y,
                                              const float* __restrict__ t,
                                              const float* __restrict__ w, int B, int N,
@@ -1011,8 +1052,8 @@ __global__ __launch_bounds__(256) void k_mse(const float* __restrict__ y,
   if (i < (int64_t)B * N) {
     const int j = (int)(i % N);
     const float e = y[i] - t[i];
-    grad[i] = 2.f * w[j] * e / (float)B;
-    l = (double)w[j] * (double)e * (double)e / (double)B;
+    grad[i] = mse_grad(w[j], e, B);
+    l = mse_loss(w[j], e, B);
   }
   l = wave_sum(l);
   if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = l;
@@ -1027,6 +1068,19 @@ __global__ void k_sum_partials(const double* __restrict__ partial, int n, float*
   *out = (float)s;
 }
 
+// One Adam update at step t (bias-corrected moments); returns the new
+// parameter and updates the moments.  Shared by k_adam and the fused
+// training step.
+__device__ __forceinline__ float adam_apply(float p, float g, float& m, float& v, int t, float lr,
+                                            float b1, float b2, float eps) {
+  const float c1 = 1.f - powf(b1, (float)t), c2 = 1.f - powf(b2, (float)t);
+  const float mi = fmaf(b1, m, (1.f - b1) * g);
+  const float vi = fmaf(b2, v, (1.f - b2) * g * g);
+  m = mi;
+  v = vi;
+  return p - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
 // Adam on a flat FP32 vector; the step counter is read from device memory
 // and advanced by k_step_bump after the update.
 __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
@@ -1035,17 +1089,404 @@ __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int t = *step + 1;
-  const float c1 = 1.f - powf(b1, (float)t), c2 = 1.f - powf(b2, (float)t);
-  const float gi = g[i];
-  const float mi = fmaf(b1, m[i], (1.f - b1) * gi);
-  const float vi = fmaf(b2, v[i], (1.f - b2) * gi * gi);
+  float mi = m[i], vi = v[i];
+  p[i] = adam_apply(p[i], g[i], mi, vi, t, lr, b1, b2, eps);
   m[i] = mi;
   v[i] = vi;
-  p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
 __global__ void k_step_bump(int* step) {
   if (blockIdx.x == 0 && threadIdx.x == 0) *step += 1;
+}
+
+// ---------------------------------------------------------------------------
+// Fused training step of the 96-256-256-256-2 BF16 network: one minibatch's
+// forward, weighted MSE, backward and Adam update in two launches, with the
+// arithmetic of shape_mlp_forward, shape_mse, shape_mlp_backward (BF16) and
+// shape_adam, so the same bits:
+//
+//   k_mlp_train, one workgroup per 64 rows: the forward of k_mlp_infer; the
+//   MSE gradient and k_mse's per-wave loss sums; the input-gradient chain
+//   g_2 = (g_3 W_3^T) . [h3 > 0], g_1, g_0 as transposed products on the
+//   matrix cores (weights as the A operand, the previous gradient in LDS as
+//   B, the ReLU gates kept as bits from the forward); the FP32 sums of every
+//   gradient column over 32-row chunks (the first stage of the bias
+//   gradients); and every layer's input and gradient as bf16 columns
+//   (actT[l][feature][row], gT[l][unit][row]), the operands of the weight
+//   gradients.
+//
+//   k_mlp_update, one workgroup per 32 x 32 tile of a weight matrix: the
+//   weight gradient in shape_gemm_set's split-K chunks (each chunk one MFMA
+//   accumulation over its k-blocks of 32 rows, the eight waves taking eight
+//   chunks at a time), the chunks added in order in FP32; bias gradients as
+//   the FP64 sums of the chunk sums in order; the loss; Adam; and the
+//   updated weights packed to bf16 for the next step's forward and chain.
+//
+// Chain-packed weights: W_l (l = 1, 2, 3) as the A operand of the transposed
+// product dz W_l^T: block (kb, mb) of 32 outputs x 16 inputs holds 64 lanes x
+// 8 values, lane = 16 (o%32 / 8) + i%16, value o%8; W_3's two outputs are
+// padded to 32 with zeros.  Stored after the forward packing.
+// ---------------------------------------------------------------------------
+constexpr int kTrRows = 64;   // minibatch rows per workgroup of k_mlp_train
+
+__host__ __device__ constexpr int mlp_packT_offset(int layer) {
+  // blocks of 32 x 16 per layer: W_3 1 x 16, W_2 8 x 16, W_1 8 x 16
+  return kMlpPackElems + (layer == 3 ? 0 : layer == 2 ? 16 * 512 : (16 + 8 * 16) * 512);
+}
+constexpr int kMlpPackAllElems = kMlpPackElems + (16 + 2 * 8 * 16) * 512;
+static_assert(kMlpPackAllElems * 2 == SHAPE_MLP_PACK_BYTES, "packed size");
+
+__host__ __device__ constexpr int mlp_param_offset(int layer) {
+  return layer == 0 ? 0
+       : layer == 1 ? kMlpIn * kMlpHid + kMlpHid
+       : layer == 2 ? kMlpIn * kMlpHid + kMlpHid + kMlpHid * kMlpHid + kMlpHid
+                    : kMlpIn * kMlpHid + kMlpHid + 2 * (kMlpHid * kMlpHid + kMlpHid);
+}
+
+// Position of W_l[i][o] in the forward packing and in the chain packing.
+__device__ __forceinline__ int mlp_pack_index(int l, int i, int o) {
+  const int nbs = l == 3 ? 1 : kMlpHid / 16;
+  return mlp_pack_offset(l) + ((i >> 5) * nbs + (o >> 4)) * 512 +
+         (16 * ((i & 31) >> 3) + (o & 15)) * 8 + (i & 7);
+}
+__device__ __forceinline__ int mlp_packT_index(int l, int i, int o) {
+  return mlp_packT_offset(l) + ((o >> 5) * 16 + (i >> 4)) * 512 +
+         (16 * ((o & 31) >> 3) + (i & 15)) * 8 + (o & 7);
+}
+
+__global__ void k_mlp_pack_chain(const float* __restrict__ params, short* __restrict__ packed) {
+  const int t = kMlpPackElems + blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= kMlpPackAllElems) return;
+  const int layer = t < mlp_packT_offset(2) ? 3 : t < mlp_packT_offset(1) ? 2 : 1;
+  const int local = t - mlp_packT_offset(layer);
+  const int n_out = layer == 3 ? kMlpOut : kMlpHid;
+  const int blk = local / 512, within = local % 512;
+  const int kb = blk / 16, mb = blk % 16;
+  const int lane = within / 8, e = within % 8;
+  const int o = kb * 32 + 8 * (lane >> 4) + e;
+  const int i = mb * 16 + (lane & 15);
+  const float v = o < n_out ? params[mlp_param_offset(layer) + i * n_out + o] : 0.0f;
+  packed[t] = to_bf16(v);
+}
+
+struct MlpTrainArgs {
+  MlpArgs f;             // features, packed weights (both packings), biases, n = batch rows
+  const float* target;   // [n][2]
+  const float* lw;       // [2] loss weights
+  int* step;
+  short* actT[4];        // [width_l][n]: x, h1, h2, h3 by column (bf16)
+  short* gT[4];          // [width_{l+1}][n]: g_0 .. g_3 by column (bf16)
+  float* bsum[4];        // [n / 32][width_{l+1}]: FP32 sums of g_l over 32-row chunks
+  double* loss_part;     // [n / 32]: loss sums of k_mse's waves
+};
+
+__device__ __forceinline__ uint32_t bf16_pair(float lo, float hi) {
+  return (uint32_t)(uint16_t)to_bf16(lo) | ((uint32_t)(uint16_t)to_bf16(hi) << 16);
+}
+
+// Column t of the FP32 staging (kTrRows rows) to bf16 at dst (column-major,
+// rows contiguous, 16-byte stores) and, if bs, its FP32 sums over chunks of
+// kColRows rows in row order into bs[chunk * ld_bs] (k_colsum_set's first
+// stage).
+__device__ __forceinline__ void mlp_column_out(const float* F, int t, short* dst, float* bs,
+                                               int ld_bs) {
+  float s = 0.f;
+#pragma unroll
+  for (int q = 0; q < kTrRows / 8; ++q) {
+    float v[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = F[(8 * q + e) * kTrLdf + t];
+    if (bs) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) s += v[e];
+      if ((8 * q + 8) % kColRows == 0) {
+        bs[(8 * q / kColRows) * ld_bs] = s;
+        s = 0.f;
+      }
+    }
+    *reinterpret_cast<uint4*>(dst + 8 * q) = make_uint4(
+        bf16_pair(v[0], v[1]), bf16_pair(v[2], v[3]), bf16_pair(v[4], v[5]), bf16_pair(v[6], v[7]));
+  }
+}
+
+__global__ __launch_bounds__(256, 1) void k_mlp_train(MlpTrainArgs a) {
+  constexpr int RB = kTrRows / 16;
+  __shared__ __align__(16) short H[kTrRows * kMlpLd];
+  __shared__ __align__(16) float F[kTrRows * kTrLdf];
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+  const int li = lane & 15, lk = lane >> 4;
+  const int row0 = blockIdx.x * kTrRows;
+  const int n = a.f.n;
+  // the step number the update kernel's Adam uses (nothing else reads it here)
+  if (blockIdx.x == 0 && tid == 0) *a.step += 1;
+  mlp_stage_features<kTrRows, false, true>(a.f, row0, H, F);
+  __syncthreads();
+  if (tid < kMlpIn) mlp_column_out(F, tid, a.actT[0] + (size_t)tid * n + row0, nullptr, 0);
+  // forward: hidden layers as in k_mlp_infer; the ReLU gates as bits
+  // (16 j + 4 i + r) of gate[l], the activations by column for the update
+  uint64_t gate[3];
+#pragma unroll 1
+  for (int l = 0; l < 3; ++l) {
+    const int kbs = (l == 0 ? kMlpIn : kMlpHid) / 32;
+    v4f acc[RB][4];
+    mlp_layer_mfma<RB>(a.f.W + mlp_pack_offset(l) / 8, H, kbs, wave, lane, acc);
+    __syncthreads();  // H read by every wave, F by every column pass
+    const float* bias = a.f.b[l];
+    uint64_t gb = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int col0 = wave * 64 + 16 * j + 4 * lk;
+      const float4 bc = make_float4(bias[col0], bias[col0 + 1], bias[col0 + 2], bias[col0 + 3]);
+#pragma unroll
+      for (int i = 0; i < RB; ++i) {
+        float v0 = acc[i][j][0] + bc.x, v1 = acc[i][j][1] + bc.y;
+        float v2 = acc[i][j][2] + bc.z, v3 = acc[i][j][3] + bc.w;
+        const int bit = 16 * j + 4 * i;
+        gb |= (uint64_t)(v0 > 0.f) << bit | (uint64_t)(v1 > 0.f) << (bit + 1) |
+              (uint64_t)(v2 > 0.f) << (bit + 2) | (uint64_t)(v3 > 0.f) << (bit + 3);
+        v0 = v0 > 0.f ? v0 : 0.f;
+        v1 = v1 > 0.f ? v1 : 0.f;
+        v2 = v2 > 0.f ? v2 : 0.f;
+        v3 = v3 > 0.f ? v3 : 0.f;
+        *reinterpret_cast<uint2*>(&H[(16 * i + li) * kMlpLd + col0]) =
+            make_uint2(to_bf16x2(v0, v1), to_bf16x2(v2, v3));
+        *reinterpret_cast<float4*>(&F[(16 * i + li) * kTrLdf + col0]) =
+            make_float4(v0, v1, v2, v3);
+      }
+    }
+    gate[l] = gb;
+    __syncthreads();
+    mlp_column_out(F, tid, a.actT[l + 1] + (size_t)tid * n + row0, nullptr, 0);
+  }
+  // output layer, then dloss/dy = g_3 and the loss terms (e = y - t)
+  {
+    v4f acc[1];
+    mlp_out_mfma<1>(a.f.W + mlp_pack_offset(3) / 8, H, 16 * wave, lane, acc);
+    __syncthreads();  // H and F free
+    if (li < kMlpOut) {
+      const float bc = a.f.b[3][li];
+      const float w = a.lw[li];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * wave + 4 * lk + r;
+        const float e = (acc[0][r] + bc) - a.target[(size_t)(row0 + row) * kMlpOut + li];
+        F[row * kTrLdf + li] = mse_grad(w, e, n);
+        F[row * kTrLdf + kMlpOut + li] = e;
+      }
+    }
+    __syncthreads();
+    {  // g_3 as the chain's B operand: one k-block, zero past the 2 outputs
+      const int row = tid >> 2, q = tid & 3;
+      uint4 v = make_uint4(0u, 0u, 0u, 0u);
+      if (q == 0) v.x = bf16_pair(F[row * kTrLdf], F[row * kTrLdf + 1]);
+      *reinterpret_cast<uint4*>(&H[row * kMlpLd + 8 * q]) = v;
+    }
+    if (tid < 2 * kWave) {
+      // k_mse's loss sums: its wave covers 32 rows, lane 2 (row % 32) + j
+      const int row = tid >> 1, j = tid & 1;
+      double l = mse_loss(a.lw[j], F[row * kTrLdf + kMlpOut + j], n);
+      l = wave_sum(l);
+      if (lane == 0) a.loss_part[row0 / kColRows + wave] = l;
+    } else if (tid < 2 * kWave + 4) {
+      const int j = tid & 1, c = (tid - 2 * kWave) >> 1;
+      float s = 0.f;
+      for (int r = 0; r < kColRows; ++r) s += F[(kColRows * c + r) * kTrLdf + j];
+      a.bsum[3][(row0 / kColRows + c) * kMlpOut + j] = s;
+    } else if (tid < 2 * kWave + 4 + 16) {
+      const int j = (tid - 2 * kWave - 4) >> 3, q = (tid - 2 * kWave - 4) & 7;
+      const float* c = F + 8 * q * kTrLdf + j;
+      *reinterpret_cast<uint4*>(a.gT[3] + (size_t)j * n + row0 + 8 * q) = make_uint4(
+          bf16_pair(c[0], c[kTrLdf]), bf16_pair(c[2 * kTrLdf], c[3 * kTrLdf]),
+          bf16_pair(c[4 * kTrLdf], c[5 * kTrLdf]), bf16_pair(c[6 * kTrLdf], c[7 * kTrLdf]));
+    }
+    __syncthreads();
+  }
+  // chain: g_{l-1} = (g_l W_l^T) zeroed where h_l <= 0, l = 3, 2, 1
+#pragma unroll 1
+  for (int l = 3; l >= 1; --l) {
+    const int kbs = l == 3 ? 1 : kMlpHid / 32;
+    v4f acc[RB][4];
+    mlp_layer_mfma<RB>(a.f.W + mlp_packT_offset(l) / 8, H, kbs, wave, lane, acc);
+    __syncthreads();
+    const uint64_t gb = gate[l - 1];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int col0 = wave * 64 + 16 * j + 4 * lk;
+#pragma unroll
+      for (int i = 0; i < RB; ++i) {
+        const int bit = 16 * j + 4 * i;
+        const float v0 = (gb >> bit) & 1 ? acc[i][j][0] : 0.f;
+        const float v1 = (gb >> (bit + 1)) & 1 ? acc[i][j][1] : 0.f;
+        const float v2 = (gb >> (bit + 2)) & 1 ? acc[i][j][2] : 0.f;
+        const float v3 = (gb >> (bit + 3)) & 1 ? acc[i][j][3] : 0.f;
+        if (l > 1)
+          *reinterpret_cast<uint2*>(&H[(16 * i + li) * kMlpLd + col0]) =
+              make_uint2(bf16_pair(v0, v1), bf16_pair(v2, v3));
+        *reinterpret_cast<float4*>(&F[(16 * i + li) * kTrLdf + col0]) =
+            make_float4(v0, v1, v2, v3);
+      }
+    }
+    __syncthreads();
+    mlp_column_out(F, tid, a.gT[l - 1] + (size_t)tid * n + row0,
+                   a.bsum[l - 1] + (size_t)(row0 / kColRows) * kMlpHid + tid, kMlpHid);
+  }
+}
+
+constexpr int kUpdTile = 32, kUpdWaves = 8, kUpdLd = kUpdTile + 1;
+constexpr int kUpdChunks = 128;   // bias chunk sums staged per pass
+
+struct MlpUpdateArgs {
+  const short* actT[4];
+  const short* gT[4];
+  const float* bsum[4];
+  const double* loss_part;
+  int n;                  // batch rows
+  int kc[4], splits[4];   // weight gradients: rows per split-K chunk, chunks
+  int blk0[5];            // first workgroup of each layer's weight tiles
+  float* params;
+  float* m;
+  float* v;
+  const int* step;
+  float lr, b1, b2, eps;
+  float* grad;            // or NULL
+  short* packed;          // forward and chain packings, rewritten
+  float* loss;
+};
+
+__global__ __launch_bounds__(512) void k_mlp_update(MlpUpdateArgs a) {
+  __shared__ float P[kUpdWaves][kUpdTile * kUpdLd];
+  __shared__ float BS[kUpdChunks][kUpdTile];
+  __shared__ double LP[kUpdChunks * 4];
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+  const int li = lane & 15, lk = lane >> 4;
+  int l = 0;
+  while (l < 3 && (int)blockIdx.x >= a.blk0[l + 1]) ++l;  // uniform
+  const int n_in = l == 0 ? kMlpIn : kMlpHid, n_out = l == 3 ? kMlpOut : kMlpHid;
+  const int o_tiles = (n_out + kUpdTile - 1) / kUpdTile;
+  const int local = (int)blockIdx.x - a.blk0[l];
+  const int o0 = (local % o_tiles) * kUpdTile, i0 = (local / o_tiles) * kUpdTile;
+  const int n = a.n;
+  const short* __restrict__ gT = a.gT[l];
+  const short* __restrict__ aT = a.actT[l];
+  const int kc = a.kc[l], splits = a.splits[l];
+  // weight gradient of the tile: A = g^T (m = output o), B = act^T (n = input
+  // i), each chunk from zero over its k-blocks in order, the chunks then
+  // added in order from 0.f (one chunk: the accumulation itself)
+  float g[2] = {0.f, 0.f};
+  for (int z0 = 0; z0 < splits; z0 += kUpdWaves) {
+    const int z = z0 + wave;
+    if (z < splits) {
+      v4f acc[2][2];
+#pragma unroll
+      for (int ob = 0; ob < 2; ++ob)
+#pragma unroll
+        for (int ib = 0; ib < 2; ++ib) acc[ob][ib] = v4f{0.f, 0.f, 0.f, 0.f};
+      const int k1 = min(n, (z + 1) * kc);
+      for (int k = z * kc; k < k1; k += 32) {
+        v8s fa[2], fb[2];
+#pragma unroll
+        for (int ob = 0; ob < 2; ++ob) {
+          const int o = o0 + 16 * ob + li;
+          fa[ob] = o < n_out ? *reinterpret_cast<const v8s*>(gT + (size_t)o * n + k + 8 * lk)
+                             : v8s{0, 0, 0, 0, 0, 0, 0, 0};
+        }
+#pragma unroll
+        for (int ib = 0; ib < 2; ++ib) {
+          const int i = i0 + 16 * ib + li;
+          fb[ib] = i < n_in ? *reinterpret_cast<const v8s*>(aT + (size_t)i * n + k + 8 * lk)
+                            : v8s{0, 0, 0, 0, 0, 0, 0, 0};
+        }
+#pragma unroll
+        for (int ob = 0; ob < 2; ++ob)
+#pragma unroll
+          for (int ib = 0; ib < 2; ++ib) acc[ob][ib] = mfma_bf16_k32(fa[ob], fb[ib], acc[ob][ib]);
+      }
+      // lane (li, lk): o = 16 ob + 4 lk + r, i = 16 ib + li of the tile
+#pragma unroll
+      for (int ob = 0; ob < 2; ++ob)
+#pragma unroll
+        for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            P[wave][(16 * ib + li) * kUpdLd + 16 * ob + 4 * lk + r] = acc[ob][ib][r];
+    }
+    __syncthreads();
+    const int nz = min(kUpdWaves, splits - z0);
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int el = tid + 512 * e, pi = (el / kUpdTile) * kUpdLd + el % kUpdTile;
+      if (splits == 1) {
+        g[e] = P[0][pi];
+      } else {
+        for (int q = 0; q < nz; ++q) g[e] += P[q][pi];
+      }
+    }
+    __syncthreads();
+  }
+  const int t = *a.step;
+  const int base = mlp_param_offset(l);
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    const int el = tid + 512 * e;
+    const int i = i0 + el / kUpdTile, o = o0 + el % kUpdTile;
+    if (i < n_in && o < n_out) {
+      const int pi = base + i * n_out + o;
+      if (a.grad) a.grad[pi] = g[e];
+      float m = a.m[pi], v = a.v[pi];
+      const float p = adam_apply(a.params[pi], g[e], m, v, t, a.lr, a.b1, a.b2, a.eps);
+      a.params[pi] = p;
+      a.m[pi] = m;
+      a.v[pi] = v;
+      const short pb = to_bf16(p);
+      a.packed[mlp_pack_index(l, i, o)] = pb;
+      if (l > 0) a.packed[mlp_packT_index(l, i, o)] = pb;
+    }
+  }
+  // bias gradients (the workgroups of the first column of tiles): FP64 sums
+  // of the chunk sums in chunk order, as k_colsum_set
+  if (i0 == 0) {
+    const int chunks = n / kColRows;
+    double S = 0.0;
+    for (int c0 = 0; c0 < chunks; c0 += kUpdChunks) {
+      const int nc = min(kUpdChunks, chunks - c0);
+      for (int x = tid; x < nc * kUpdTile; x += blockDim.x) {
+        const int c = x / kUpdTile, o = o0 + x % kUpdTile;
+        BS[c][x % kUpdTile] = o < n_out ? a.bsum[l][(size_t)(c0 + c) * n_out + o] : 0.f;
+      }
+      __syncthreads();
+      if (tid < kUpdTile)
+        for (int c = 0; c < nc; ++c) S += BS[c][tid];
+      __syncthreads();
+    }
+    const int o = o0 + tid;
+    if (tid < kUpdTile && o < n_out) {
+      const int pi = base + n_in * n_out + o;
+      const float gb = (float)S;
+      if (a.grad) a.grad[pi] = gb;
+      float m = a.m[pi], v = a.v[pi];
+      a.params[pi] = adam_apply(a.params[pi], gb, m, v, t, a.lr, a.b1, a.b2, a.eps);
+      a.m[pi] = m;
+      a.v[pi] = v;
+    }
+  }
+  // loss: k_mse's block sums (four waves of 32 rows, missing waves 0) in
+  // block order, as k_sum_partials
+  if (blockIdx.x == 0) {
+    const int waves = n / kColRows, blocks = (waves + 3) / 4;
+    double s = 0.0;
+    for (int b0 = 0; b0 < blocks; b0 += kUpdChunks) {
+      const int nb = min(kUpdChunks, blocks - b0);
+      for (int x = tid; x < nb * 4; x += blockDim.x) {
+        const int w = 4 * b0 + x;
+        LP[x] = w < waves ? a.loss_part[w] : 0.0;
+      }
+      __syncthreads();
+      if (tid == 0)
+        for (int b = 0; b < nb; ++b) s += LP[4 * b] + LP[4 * b + 1] + LP[4 * b + 2] + LP[4 * b + 3];
+      __syncthreads();
+    }
+    if (tid == 0) *a.loss = (float)s;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1414,6 +1855,118 @@ hipError_t launch_mlp_infer(const float* fq, const float* flib, const int* qidx,
     hipLaunchKernelGGL((k_mlp_infer<64, false>), grid, dim3(256), 0, st, a);
   else
     hipLaunchKernelGGL((k_mlp_infer<128, false>), grid, dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+size_t mlp_pack_all_bytes() { return (size_t)kMlpPackAllElems * sizeof(short); }
+
+hipError_t launch_mlp_pack_all(const float* params, void* packed, hipStream_t st) {
+  hipLaunchKernelGGL(k_mlp_pack, dim3((kMlpPackElems + 255) / 256), dim3(256), 0, st, params,
+                     (short*)packed);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_mlp_pack_chain, dim3((kMlpPackAllElems - kMlpPackElems + 255) / 256),
+                     dim3(256), 0, st, params, (short*)packed);
+  return hipGetLastError();
+}
+
+int mlp_step_rows() { return kTrRows; }
+
+// Scratch of one training step of n rows: the bf16 columns of every layer's
+// input and gradient, the FP32 chunk sums of the gradients and the per-wave
+// loss sums, each 256-byte aligned.
+namespace {
+struct MlpStepLayout {
+  size_t actT[4], gT[4], bsum[4], loss, total;
+};
+MlpStepLayout mlp_step_layout(int n) {
+  MlpStepLayout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off += (bytes + 255) / 256 * 256;
+    return at;
+  };
+  for (int l = 0; l < 4; ++l) {
+    const int n_in = l == 0 ? kMlpIn : kMlpHid, n_out = l == 3 ? kMlpOut : kMlpHid;
+    L.actT[l] = take((size_t)n_in * n * sizeof(short));
+    L.gT[l] = take((size_t)n_out * n * sizeof(short));
+    L.bsum[l] = take((size_t)(n / kColRows) * n_out * sizeof(float));
+  }
+  L.loss = take((size_t)(n / kColRows) * sizeof(double));
+  L.total = off;
+  return L;
+}
+}  // namespace
+
+size_t mlp_step_scratch_bytes(int n) { return mlp_step_layout(n).total; }
+
+hipError_t launch_mlp_step(const MlpStep& s, void* scratch, hipStream_t st) {
+  const int n = s.n;
+  const MlpStepLayout L = mlp_step_layout(n);
+  char* base = (char*)scratch;
+  MlpTrainArgs ta{};
+  ta.f.fq = s.fq;
+  ta.f.flib = s.flib;
+  ta.f.qidx = s.qidx;
+  ta.f.idx = s.idx;
+  ta.f.n = n;
+  ta.f.fo_cross = s.fo_cross;
+  ta.f.mean = s.mean;
+  ta.f.inv_std = s.inv_std;
+  ta.f.W = (const v8s*)s.packed;
+  ta.target = s.target;
+  ta.lw = s.lw;
+  ta.step = s.step;
+  MlpUpdateArgs ua{};
+  int blocks = 0;
+  for (int l = 0; l < 4; ++l) {
+    const int n_in = l == 0 ? kMlpIn : kMlpHid, n_out = l == 3 ? kMlpOut : kMlpHid;
+    ta.f.b[l] = s.params + mlp_param_offset(l) + n_in * n_out;
+    ta.actT[l] = (short*)(base + L.actT[l]);
+    ta.gT[l] = (short*)(base + L.gT[l]);
+    ta.bsum[l] = (float*)(base + L.bsum[l]);
+    ua.actT[l] = ta.actT[l];
+    ua.gT[l] = ta.gT[l];
+    ua.bsum[l] = ta.bsum[l];
+    // the weight gradient's split-K chunks, as shape_gemm_set chooses them
+    GemmArgs g{};
+    g.M = n_in;
+    g.N = n_out;
+    g.K = n;
+    g.flags = SHAPE_GEMM_BF16;
+    int splits = gemm_splits(g);
+    int kc = n;
+    if (splits > 1) {
+      kc = ((n + splits - 1) / splits + kTK - 1) / kTK * kTK;
+      splits = (n + kc - 1) / kc;
+    } else {
+      splits = 1;
+    }
+    ua.kc[l] = kc;
+    ua.splits[l] = splits;
+    ua.blk0[l] = blocks;
+    blocks += ((n_out + kUpdTile - 1) / kUpdTile) * ((n_in + kUpdTile - 1) / kUpdTile);
+  }
+  ua.blk0[4] = blocks;
+  ta.loss_part = (double*)(base + L.loss);
+  ua.loss_part = ta.loss_part;
+  ua.n = n;
+  ua.params = s.params;
+  ua.m = s.m;
+  ua.v = s.v;
+  ua.step = s.step;
+  ua.lr = s.lr;
+  ua.b1 = s.b1;
+  ua.b2 = s.b2;
+  ua.eps = s.eps;
+  ua.grad = s.grad;
+  ua.packed = (short*)s.packed;
+  ua.loss = s.loss;
+  hipLaunchKernelGGL(k_mlp_train, dim3((unsigned)(n / kTrRows)), dim3(256), 0, st, ta);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_mlp_update, dim3((unsigned)blocks), dim3(512), 0, st, ua);
   return hipGetLastError();
 }
 

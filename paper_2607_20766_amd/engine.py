@@ -150,6 +150,10 @@ def load_library():
         L.shape_gemm.argtypes = [vp, i32, i32, i32, vp, i64, i64, vp, i64, i64, vp, i64, vp, vp,
                                  i64, ctypes.c_uint32, vp]
         L.shape_colsum.argtypes = [vp, i32, i32, vp, i64, vp, vp]
+        L.shape_mlp_backward.argtypes = [vp, i32, vp, i32, vp, vp, vp, ctypes.c_uint32, vp, vp]
+        L.shape_mlp_pack.argtypes = [vp, vp, vp, vp]
+        L.shape_mlp_train_step.argtypes = [vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp,
+                                           ctypes.POINTER(ShapeMlpAdam), vp, vp, vp]
         L.shape_colsum_set.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
         L.shape_gemm_set.argtypes = [vp, i32, ctypes.POINTER(ShapeGemmDesc), vp]
         L.shape_mse.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp, vp]
@@ -172,6 +176,18 @@ class ShapeGemmDesc(ctypes.Structure):
                 ("sbn", ctypes.c_int64), ("scm", ctypes.c_int64), ("sgm", ctypes.c_int64),
                 ("M", ctypes.c_int32), ("N", ctypes.c_int32), ("K", ctypes.c_int32),
                 ("flags", ctypes.c_uint32)]
+
+
+class ShapeMlpAdam(ctypes.Structure):
+    """shape_mlp_adam: optimiser state of the fused training step."""
+    _fields_ = [("params", ctypes.c_void_p), ("m", ctypes.c_void_p), ("v", ctypes.c_void_p),
+                ("step", ctypes.c_void_p), ("packed", ctypes.c_void_p),
+                ("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
+                ("eps", ctypes.c_float)]
+
+
+SHAPE_MLP_PACK_BYTES = 598016
+SHAPE_MLP_STEP_MAX_ROWS = 65536
 
 
 def _ptr(t):
@@ -741,6 +757,52 @@ class Engine:
             _ptr(h[1]), _ptr(h[2]), _ptr(out)))
         return out
 
+    def shape_mlp_pack(self, params, packed=None, stream=None):
+        """The network's weights in the two bf16 layouts of the fused
+        training step (shape_mlp_pack); returns packed (int16 tensor of
+        SHAPE_MLP_PACK_BYTES)."""
+        from .surrogate import n_params
+        arg = _Args(self, stream)
+        params = arg(params, "params", torch.float32, numel=n_params())
+        if packed is None:
+            packed = torch.empty(SHAPE_MLP_PACK_BYTES // 2, dtype=torch.int16,
+                                 device=self.torch_device)
+        arg.out(packed, "packed", torch.int16, (SHAPE_MLP_PACK_BYTES // 2,))
+        self._check(load_library().shape_mlp_pack(self._ctx, _ptr(params), _stream(stream),
+                                                  _ptr(packed)))
+        return packed
+
+    def shape_mlp_train_step(self, f_q, f_lib, mean, inv_std, target, loss_w, params, m, v,
+                             step, packed, lr, beta1=0.9, beta2=0.999, eps=1e-8, idx=None,
+                             qidx=None, n=None, fo_cross=None, grad=None, loss=None,
+                             stream=None):
+        """One fused training step of the surrogate (shape_mlp_train_step):
+        params, m, v, step and packed are updated in place; returns the loss
+        tensor [1] (loss if given).  grad (optional) receives dloss/dparams."""
+        from .surrogate import n_params
+        arg = _Args(self, stream)
+        f_q, f_lib, mean, inv_std, idx, qidx, n, fo_cross, _ = self._pair_args(
+            arg, f_q, f_lib, mean, inv_std, idx, qidx, n, fo_cross)
+        target = arg(target, "target", torch.float32, shape=(n, 2))
+        loss_w = arg(loss_w, "loss_w", torch.float32, numel=2)
+        npar = n_params()
+        for t, name in ((params, "params"), (m, "m"), (v, "v")):
+            arg.out(t, name, torch.float32, (npar,))
+        arg.out(step, "step", torch.int32, (1,))
+        arg.out(packed, "packed", torch.int16, (SHAPE_MLP_PACK_BYTES // 2,))
+        if grad is not None:
+            arg.out(grad, "grad", torch.float32, (npar,))
+        if loss is None:
+            loss = torch.empty(1, dtype=torch.float32, device=self.torch_device)
+        arg.out(loss, "loss", torch.float32, (1,))
+        opt = ShapeMlpAdam(params.data_ptr(), m.data_ptr(), v.data_ptr(), step.data_ptr(),
+                           packed.data_ptr(), float(lr), float(beta1), float(beta2), float(eps))
+        self._check(load_library().shape_mlp_train_step(
+            self._ctx, _ptr(f_q), _ptr(f_lib), _ptr(qidx), _ptr(idx), n, _ptr(fo_cross),
+            _ptr(mean), _ptr(inv_std), _ptr(target), _ptr(loss_w), ctypes.byref(opt),
+            _stream(stream), _ptr(grad), _ptr(loss)))
+        return loss
+
     def _strided(self, t, name, rows, cols, s_row, s_col, optional=False):
         """An operand addressed by the caller's own strides from its first
         element: float32 on the engine's device, used as it is (no copy,
@@ -801,6 +863,32 @@ class Engine:
             d.M, d.N, d.K = int(p["M"]), int(p["N"]), int(p["K"])
             d.flags = (1 if p.get("bf16", True) else 0) | (2 if p.get("relu", False) else 0)
         self._check(load_library().shape_gemm_set(self._ctx, n, arr, _stream(stream)))
+
+    def shape_mlp_backward(self, width, params, acts, dout, grad, bf16=True, stream=None):
+        """dloss/dparams of a dense ReLU network (shape_mlp_backward): acts
+        = [inputs, hidden outputs after ReLU ...] ([batch, width[l]] each),
+        dout = dloss/doutput [batch, width[-1]]; grad in params' layout."""
+        arg = _Args(self, stream)
+        width = [int(w) for w in width]
+        L = len(width) - 1
+        if len(acts) != L:
+            raise ValueError(f"acts holds {len(acts)} arrays, expected {L}")
+        batch = int(dout.shape[0])
+        from .surrogate import n_params
+        npar = n_params(width)
+        params = arg(params, "params", torch.float32, numel=npar)
+        arg.out(grad, "grad", torch.float32, tuple(grad.shape))
+        if grad.numel() != npar:
+            raise ValueError(f"grad has {grad.numel()} elements, expected {npar}")
+        dout = arg(dout, "dout", torch.float32, shape=(batch, width[-1]))
+        acts = [arg(a, f"acts[{l}]", torch.float32, shape=(batch, width[l]))
+                for l, a in enumerate(acts)]
+        w_arr = (ctypes.c_int32 * (L + 1))(*width)
+        a_arr = (ctypes.c_void_p * L)(*[a.data_ptr() for a in acts])
+        v = lambda a: ctypes.cast(a, ctypes.c_void_p)
+        self._check(load_library().shape_mlp_backward(
+            self._ctx, L, v(w_arr), batch, _ptr(params), v(a_arr), _ptr(dout),
+            1 if bf16 else 0, _stream(stream), _ptr(grad)))
 
     def shape_colsum(self, A, M, N, lda, out, stream=None):
         arg = _Args(self, stream)

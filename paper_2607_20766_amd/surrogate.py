@@ -21,7 +21,7 @@ import math
 import numpy as np
 import torch
 
-from .engine import SHAPE_SCREEN_ADAPTIVE, Engine, Molecules
+from .engine import SHAPE_MLP_STEP_MAX_ROWS, SHAPE_SCREEN_ADAPTIVE, Engine, Molecules
 
 WIDTH = (96, 256, 256, 256, 2)
 
@@ -57,6 +57,7 @@ class MLP:
         self.m = torch.zeros_like(self.params)
         self.v = torch.zeros_like(self.params)
         self.step = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.packed = None   # bf16 packings of the weights for the fused training step
         self._acts = {}
 
     def _views(self, flat):
@@ -75,7 +76,7 @@ class MLP:
             dev = self.eng.torch_device
             self._acts[B] = {
                 "h": [torch.empty(B, w, dtype=torch.float32, device=dev) for w in self.width[1:]],
-                "d": [torch.empty(B, w, dtype=torch.float32, device=dev) for w in self.width[1:]],
+                "dout": torch.empty(B, self.width[-1], dtype=torch.float32, device=dev),
                 "loss": torch.empty(1, dtype=torch.float32, device=dev),
             }
         return self._acts[B]
@@ -96,35 +97,12 @@ class MLP:
 
     def backward(self, x: torch.Tensor, dout: torch.Tensor):
         """Gradient of the loss w.r.t. the parameters into self.grad, given
-        d loss / d output (the activations of the last forward are reused)."""
-        B = x.shape[0]
-        buf = self._buffers(B)
-        L = len(self.width) - 1
-        Ws = self._views(self.params)
-        Gs = self._views(self.grad)
-        dz = dout
-        bias_grads, weight_grads = [], []
-        for l in range(L - 1, -1, -1):
-            n_in, n_out = self.width[l], self.width[l + 1]
-            h_in = x if l == 0 else buf["h"][l - 1]
-            gW, gb = Gs[l]
-            # dW[i][o] = sum_b h_in[b][i] dz[b][o]: all layers in one launch below
-            weight_grads.append(dict(M=n_in, N=n_out, K=B, A=h_in, sam=1, sak=n_in, B=dz,
-                                     sbk=n_out, sbn=1, C=gW, scm=n_out, bf16=self.bf16))
-            bias_grads.append((dz, B, n_out, n_out, gb))
-            if l > 0:
-                # dh[b][i] = sum_o dz[b][o] W[i][o], through the ReLU of layer l-1
-                W, _ = Ws[l]
-                dnext = buf["d"][l - 1]
-                self.eng.shape_gemm(B, n_in, n_out, dz, n_out, 1, W, 1, n_out, dnext, n_in,
-                                    gate=buf["h"][l - 1], sgm=n_in, bf16=self.bf16)
-                dz = dnext
-        # dW and db of every layer (8 per launch): the products of the weight
-        # gradients, then the column sums of each layer's dz
-        for i in range(0, len(weight_grads), 8):
-            self.eng.shape_gemm_set(weight_grads[i:i + 8])
-        for i in range(0, len(bias_grads), 8):
-            self.eng.shape_colsum_set(bias_grads[i:i + 8])
+        d loss / d output (the activations of the last forward are reused):
+        one shape_mlp_backward call."""
+        buf = self._buffers(x.shape[0])
+        acts = [x] + buf["h"][:-1]
+        self.eng.shape_mlp_backward(self.width, self.params, acts, dout, self.grad,
+                                    bf16=self.bf16)
 
     def loss_grad(self, x, target, loss_weights, loss_out=None):
         """Forward, weighted MSE and backward; returns the loss tensor [1]
@@ -138,11 +116,31 @@ class MLP:
         shape_mlp_forward); returns the loss tensor [1] (loss_out if given:
         the loss is written there directly)."""
         buf = self._buffers(x.shape[0])
-        dout = buf["d"][-1]
+        dout = buf["dout"]
         loss = buf["loss"] if loss_out is None else loss_out
         self.eng.shape_mse(buf["h"][-1], target, loss_weights, dout, loss)
         self.backward(x, dout)
         return loss
+
+    def fused_step_ok(self, batch: int) -> bool:
+        """Whether shape_mlp_train_step takes this network and batch."""
+        return (self.bf16 and self.width == WIDTH and batch % 64 == 0
+                and 64 <= batch <= SHAPE_MLP_STEP_MAX_ROWS)
+
+    def pack(self):
+        """Pack the current parameters for train_step (after any change to
+        self.params made outside train_step)."""
+        self.packed = self.eng.shape_mlp_pack(self.params, self.packed)
+
+    def train_step(self, f_q, f_lib, mean, inv_std, target, loss_weights, lr, idx=None,
+                   qidx=None, fo_cross=None, loss_out=None, beta1=0.9, beta2=0.999, eps=1e-8):
+        """Features, forward, loss, backward and Adam of one minibatch in two
+        launches (shape_mlp_train_step; self.packed must be current: pack());
+        the bits of forward + loss_grad_after_forward + adam_step."""
+        return self.eng.shape_mlp_train_step(
+            f_q, f_lib, mean, inv_std, target, loss_weights, self.params, self.m, self.v,
+            self.step, self.packed, lr, beta1, beta2, eps, idx=idx, qidx=qidx,
+            fo_cross=fo_cross, grad=self.grad, loss=loss_out)
 
     def adam_step(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):
         self.eng.shape_adam(self.params, self.grad, self.m, self.v, self.step, lr, beta1, beta2,
@@ -274,16 +272,17 @@ class Triage:
     def train(self, f_q, f_lib, qidx: np.ndarray, midx: np.ndarray, Y: np.ndarray,
               fo: np.ndarray | None = None, epochs: int = 8, batch: int = 4096,
               lr: float = 1e-3, seed: int = 0, log=None, graph: bool = True,
-              fused_forward: bool = True):
+              fused_forward: bool = True, fused_step: bool = True):
         """Minibatch Adam on the weighted MSE of standardised labels Y [n, 2].
 
         Each epoch's shuffled rows are copied into fixed device buffers, so
         after the first (eager) epoch the whole epoch of steps is captured
         once as a HIP graph and replayed (graph=True): identical kernels and
-        results, without a host round trip per launch.  fused_forward: each
-        minibatch's features and forward in one kernel (shape_mlp_forward,
-        BF16 network of the default widths), the same bits as the pair
-        features and one product per layer."""
+        results, without a host round trip per launch.  fused_step: each
+        minibatch in the two launches of shape_mlp_train_step (BF16 network
+        of the default widths, batch a multiple of 64); else fused_forward:
+        its features and forward in one kernel (shape_mlp_forward), then the
+        loss, backward and Adam calls.  All three give the same bits."""
         dev = self.eng.torch_device
         self.y_mean = Y.mean(0)
         self.y_std = Y.std(0)
@@ -301,11 +300,19 @@ class Triage:
         fo_ep = torch.empty(rows, dtype=torch.float32, device=dev) if self.use_fo else None
 
         fused = fused_forward and self.mlp.bf16 and self.mlp.width == WIDTH
+        one_call = fused_step and self.mlp.fused_step_ok(batch)
+        if one_call:
+            self.mlp.pack()
 
         def epoch_steps():
             for b in range(nb):
                 s, e = b * batch, (b + 1) * batch
                 fo_b = None if fo_ep is None else fo_ep[s:e]
+                if one_call:
+                    self.mlp.train_step(f_q, f_lib, self.mean, self.inv_std, y_ep[s:e], lw, lr,
+                                        idx=m_ep[s:e], qidx=q_ep[s:e], fo_cross=fo_b,
+                                        loss_out=losses[b:b + 1])
+                    continue
                 if fused:
                     acts = self.mlp._buffers(batch)["h"]
                     self.eng.shape_mlp_forward(f_q, f_lib, self.mean, self.inv_std,

@@ -137,3 +137,36 @@ def test_triage_arguments(eng):
                       torch.zeros(1))
     with pytest.raises(ValueError, match="out has shape"):
         eng.shape_topk(torch.zeros(20), 5, out=torch.zeros(4, dtype=torch.int32))
+
+
+def test_training_step_arrays(eng):
+    """The fused training step's in-place state must be the library's own
+    layout (no converted copy could carry the update back)."""
+    from paper_2607_20766_amd.engine import SHAPE_MLP_PACK_BYTES
+    from paper_2607_20766_amd.surrogate import n_params
+    npar = n_params()
+    f_q, f_lib = torch.zeros(1, 24), torch.zeros(128, 24)
+    mean, inv_std = torch.zeros(96), torch.ones(96)
+    target, lw = torch.zeros(128, 2), torch.ones(2)
+    p, m, v = torch.zeros(npar), torch.zeros(npar), torch.zeros(npar)
+    step = torch.zeros(1, dtype=torch.int32)
+    packed = torch.zeros(SHAPE_MLP_PACK_BYTES // 2, dtype=torch.int16)
+    args = [f_q, f_lib, mean, inv_std, target, lw, p, m, v, step, packed, 1e-3]
+    bad = list(args)
+    bad[6] = p.double()
+    with pytest.raises(ValueError, match="params has dtype"):
+        eng.shape_mlp_train_step(*bad)
+    bad = list(args)
+    bad[9] = step.long()
+    with pytest.raises(ValueError, match="step has dtype"):
+        eng.shape_mlp_train_step(*bad)
+    bad = list(args)
+    bad[10] = packed[:-8]
+    with pytest.raises(ValueError, match="packed has shape"):
+        eng.shape_mlp_train_step(*bad)
+    bad = list(args)
+    bad[4] = torch.zeros(127, 2)
+    with pytest.raises(ValueError, match="target has shape"):
+        eng.shape_mlp_train_step(*bad)
+    with pytest.raises(ValueError, match="grad has shape"):
+        eng.shape_mlp_train_step(*args, grad=torch.zeros(npar - 1))

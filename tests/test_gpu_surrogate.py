@@ -9,7 +9,7 @@ import torch
 import oracle as O
 from paper_2607_20766_amd import molgen
 from paper_2607_20766_amd.engine import LAMBDA_P27, SHAPE_SCREEN_ADAPTIVE, Engine, ShapeError
-from paper_2607_20766_amd.surrogate import MLP, WIDTH, Triage, init_params
+from paper_2607_20766_amd.surrogate import MLP, WIDTH, Triage, init_params, n_params
 from tests.gpu_common import require_gpu
 
 pytestmark = pytest.mark.gpu
@@ -364,9 +364,10 @@ def test_colsum_set_equals_colsum(eng):
 
 
 def test_training_with_fused_forward_equals_layers(eng):
-    """Training whose minibatch forward is one shape_mlp_forward kernel
-    gives the loss history and parameters of the per-layer path, bit for
-    bit (the backward reads identical activations)."""
+    """Training whose minibatch forward is one shape_mlp_forward kernel, and
+    training whose whole minibatch step is one shape_mlp_train_step call,
+    give the loss history, parameters, Adam moments and step count of the
+    per-layer path, bit for bit."""
     rng = np.random.default_rng(23)
     n_q, n_l, n = 3, 700, 5000
     f_q = rng.normal(size=(n_q, 24)).astype(np.float32)
@@ -378,15 +379,18 @@ def test_training_with_fused_forward_equals_layers(eng):
     Y = rng.normal(size=(n, 2))
     FO = rng.uniform(1, 40, n)
     res = []
-    for fused in (False, True):
-        print(f"case: training, fused forward={fused}", flush=True)
+    for fused, one_call in ((False, False), (True, False), (True, True)):
+        print(f"case: training, fused forward={fused}, fused step={one_call}", flush=True)
         tr = Triage(eng, seed=4)
         tr.fit_standardisation(fq, fl, qi, mi, fo=FO)
         hist = tr.train(fq, fl, qi, mi, Y, fo=FO, epochs=2, batch=1024, lr=1e-3,
-                        fused_forward=fused)
-        res.append((hist, tr.mlp.params.cpu().numpy().copy()))
-    assert res[0][0] == res[1][0]
-    assert np.array_equal(res[0][1], res[1][1])
+                        fused_forward=fused, fused_step=one_call)
+        res.append((hist, tr.mlp.params.cpu().numpy().copy(), tr.mlp.m.cpu().numpy().copy(),
+                    tr.mlp.v.cpu().numpy().copy(), int(tr.mlp.step.item())))
+    for r in res[1:]:
+        assert r[0] == res[0][0]
+        for a, b in zip(r[1:], res[0][1:]):
+            assert np.array_equal(a, b)
 
 
 def test_graph_training_equals_eager(eng):
@@ -435,3 +439,114 @@ def test_seed_budget_matches_host_rule(eng):
                                  tr.cap_per_pair).cpu().numpy()
     assert full[17] == tr.cap_per_pair and full[18] == tr.cap_per_pair
     assert full[19] == tr.round_per_pair
+
+
+def _backward_by_layers(eng, width, params, acts, dout, grad, bf16):
+    """The backward pass composed from the single products: input gradients
+    with shape_gemm (ReLU gate), every weight gradient with shape_gemm_set,
+    every bias gradient with shape_colsum_set."""
+    B = dout.shape[0]
+    L = len(width) - 1
+    offs = [0]
+    for i, o in zip(width[:-1], width[1:]):
+        offs.append(offs[-1] + i * o + o)
+    dz, wg, bg = dout, [], []
+    for l in range(L - 1, -1, -1):
+        n_in, n_out = width[l], width[l + 1]
+        gW = grad[offs[l]:offs[l] + n_in * n_out]
+        gb = grad[offs[l] + n_in * n_out:offs[l + 1]]
+        wg.append(dict(M=n_in, N=n_out, K=B, A=acts[l], sam=1, sak=n_in, B=dz, sbk=n_out,
+                       sbn=1, C=gW, scm=n_out, bf16=bf16))
+        bg.append((dz, B, n_out, n_out, gb))
+        if l > 0:
+            dn = torch.empty(B, n_in, dtype=torch.float32, device="cuda")
+            eng.shape_gemm(B, n_in, n_out, dz, n_out, 1, params[offs[l]:offs[l] + n_in * n_out],
+                           1, n_out, dn, n_in, gate=acts[l], sgm=n_in, bf16=bf16)
+            dz = dn
+    eng.shape_gemm_set(wg)
+    eng.shape_colsum_set(bg)
+
+
+@pytest.mark.parametrize("width,B", [(WIDTH, 4096), (WIDTH, 300), ((5, 37, 3), 1),
+                                     ((7, 2), 1000), ((33, 65, 129, 17, 8, 4), 777)])
+@pytest.mark.parametrize("bf16", [True, False])
+def test_mlp_backward_equals_layer_calls(eng, width, B, bf16):
+    """shape_mlp_backward gives the bits of the per-layer calls it replaces,
+    for the network's own shape and ragged ones (widths off the tiles, a
+    single layer, a single row)."""
+    width = list(width)
+    rng = np.random.default_rng(41)
+    params = torch.from_numpy(init_params(9, width)).cuda()
+    acts = [torch.from_numpy(rng.normal(size=(B, width[0])).astype(np.float32)).cuda()]
+    for w in width[1:-1]:
+        h = rng.normal(size=(B, w)).astype(np.float32)
+        acts.append(torch.from_numpy(np.maximum(h, 0)).cuda())   # post-ReLU: zeros gate
+    dout = torch.from_numpy(rng.normal(size=(B, width[-1])).astype(np.float32)).cuda()
+    print(f"case: MLP backward {width} batch {B} bf16={bf16}", flush=True)
+    ref = torch.full((n_params(width),), np.nan, device="cuda")
+    _backward_by_layers(eng, width, params, acts, dout, ref, bf16)
+    got = torch.full_like(ref, np.nan)
+    eng.shape_mlp_backward(width, params, acts, dout, got, bf16=bf16)
+    torch.cuda.synchronize()
+    assert torch.equal(got, ref)
+    with pytest.raises(ValueError):
+        eng.shape_mlp_backward(width, params, acts[:-1], dout, got)
+
+
+@pytest.mark.parametrize("n", [64, 576, 1024, 4096, 8192])
+def test_train_step_equals_calls(eng, n):
+    """shape_mlp_train_step against shape_mlp_forward, shape_mse,
+    shape_mlp_backward and shape_adam over three consecutive steps: loss,
+    gradient, parameters, moments, step counter and the repacked weights bit
+    for bit.  Batches of one workgroup, of a half-filled last loss block
+    (576 rows, ragged split-K chunks), of single-chunk weight gradients (64),
+    of the training batch (4096) and beyond it (8192: split-K chunks that
+    differ between layers)."""
+    rng = np.random.default_rng(50 + n)
+    n_q, n_l = 3, 20000
+    f_q = rng.normal(size=(n_q, 24)).astype(np.float32)
+    f_l = rng.normal(size=(n_l, 24)).astype(np.float32)
+    f_q[:, 23] = rng.uniform(50, 100, n_q)
+    f_l[:, 23] = rng.uniform(50, 100, n_l)
+    fq, fl = torch.from_numpy(f_q).cuda(), torch.from_numpy(f_l).cuda()
+    mean = torch.from_numpy(rng.normal(size=96).astype(np.float32) * 0.3).cuda()
+    inv_std = torch.from_numpy(rng.uniform(0.5, 1.5, 96).astype(np.float32)).cuda()
+    lw = torch.tensor([1.0, 0.5], dtype=torch.float32, device="cuda")
+    params = init_params(7)
+    ref, fus = MLP(eng, params), MLP(eng, params)
+    fus.pack()
+    xb = torch.empty(n, 96, dtype=torch.float32, device="cuda")
+    for it in range(3):
+        qi = torch.from_numpy(rng.integers(0, n_q, n).astype(np.int32)).cuda()
+        mi = torch.from_numpy(rng.integers(0, n_l, n).astype(np.int32)).cuda()
+        fo = torch.from_numpy(rng.uniform(1, 40, n).astype(np.float32)).cuda()
+        y = torch.from_numpy(rng.normal(size=(n, 2)).astype(np.float32)).cuda()
+        print(f"case: fused training step, {n} rows, step {it}", flush=True)
+        acts = ref._buffers(n)["h"]
+        eng.shape_mlp_forward(fq, fl, mean, inv_std, ref.params, xb, acts[:3], acts[3], idx=mi,
+                              qidx=qi, fo_cross=fo)
+        l_ref = ref.loss_grad_after_forward(xb, y, lw).clone()
+        ref.adam_step(1e-3)
+        l_fus = fus.train_step(fq, fl, mean, inv_std, y, lw, 1e-3, idx=mi, qidx=qi, fo_cross=fo)
+        torch.cuda.synchronize()
+        assert torch.equal(l_fus, l_ref), (l_fus.item(), l_ref.item())
+        assert torch.equal(fus.grad, ref.grad)
+        assert torch.equal(fus.params, ref.params)
+        assert torch.equal(fus.m, ref.m) and torch.equal(fus.v, ref.v)
+        assert torch.equal(fus.step, ref.step)
+    assert torch.equal(fus.packed, eng.shape_mlp_pack(ref.params))
+
+
+def test_train_step_rejects_batches_off_its_grid(eng):
+    net = MLP(eng, init_params(1))
+    net.pack()
+    fq = torch.zeros(1, 24, device="cuda")
+    fl = torch.ones(100, 24, device="cuda")
+    mean, inv_std = torch.zeros(96, device="cuda"), torch.ones(96, device="cuda")
+    lw = torch.ones(2, device="cuda")
+    for n in (100, 32):
+        with pytest.raises(ShapeError) as e:
+            net.train_step(fq, fl, mean, inv_std, torch.zeros(n, 2, device="cuda"), lw, 1e-3,
+                           idx=torch.zeros(n, dtype=torch.int32, device="cuda"))
+        assert e.value.code == -2
+    assert int(net.step.item()) == 0
