@@ -1333,8 +1333,8 @@ int shape_mlp_train_step(shape_ctx* c, const float* f_q, const float* f_lib, con
       return fail(c, SHAPE_E_INVAL, "NULL array");
     if (!opt->params || !opt->m || !opt->v || !opt->step || !opt->packed)
       return fail(c, SHAPE_E_INVAL, "NULL optimiser array");
-    if ((uintptr_t)opt->packed & 15u)
-      return fail(c, SHAPE_E_INVAL, "packed must be 16-byte aligned");
+    if (((uintptr_t)opt->packed | (uintptr_t)opt->params) & 15u)
+      return fail(c, SHAPE_E_INVAL, "packed and params must be 16-byte aligned");
     if (!(opt->lr > 0.f) || !(opt->beta1 >= 0.f && opt->beta1 < 1.f) ||
         !(opt->beta2 >= 0.f && opt->beta2 < 1.f) || !(opt->eps > 0.f))
       return fail(c, SHAPE_E_RANGE, "Adam hyper-parameters out of range");

@@ -3,6 +3,9 @@
 // FP32 accumulation), its loss, Adam, and top-k selection.
 #include "shape_kernels.hpp"
 
+#include <algorithm>
+#include <vector>
+
 #include <math.h>
 
 namespace shape {
@@ -421,18 +424,16 @@ __device__ __forceinline__ v4f mfma_bf16_k32(v8s a, v8s b, v4f c) {
                                                  __builtin_bit_cast(v8bf, b), c, 0, 0, 0);
 }
 
-__device__ __forceinline__ short to_bf16(float x) {
-  uint32_t u = __float_as_uint(x);
-  if ((u & 0x7F800000u) == 0x7F800000u) return (short)(u >> 16);  // inf / nan
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (short)(u >> 16);
-}
-
-// Two floats to packed bf16 (x in the low half) by gfx950's
-// v_cvt_pk_bf16_f32: round to nearest even, as to_bf16 for finite values.
+// Float to bfloat16 by gfx950's v_cvt_pk_bf16_f32 (round to nearest even;
+// NaN stays NaN): the one conversion of every BF16 operand in the library,
+// so the staged products, the fused network kernels and the packed weights
+// round alike.  to_bf16x2 converts two values (x in the low half) in one
+// instruction.
 __device__ __forceinline__ uint32_t to_bf16x2(float x, float y) {
   return __builtin_bit_cast(uint32_t, __builtin_convertvector((v2f{x, y}), v2bf));
 }
+
+__device__ __forceinline__ short to_bf16(float x) { return (short)(to_bf16x2(x, 0.f) & 0xFFFFu); }
 
 // FP32 products (tight-parity mode): operands read straight from global
 // memory, one v_mfma_f32_16x16x4f32 step per 4 values of k.
@@ -844,6 +845,42 @@ __device__ __forceinline__ void mlp_layer_mfma(const v8s* __restrict__ W, const 
   }
 }
 
+// The training kernel's form of these products: eight waves, wave w
+// computing outputs [32 w, 32 w + 32) (two 16-column fragments), with every
+// weight fragment of the layer loaded up front (KBS k-blocks x 2 per lane),
+// so that a layer's loads are in flight together and during the previous
+// layer's epilogue.  Lane (li, lk) ends with row 16 i + li, outputs 32 w +
+// 16 j + 4 lk .. + 3 in acc[i][j].
+template <int KBS>
+__device__ __forceinline__ void mlp_frags_load(const v8s* __restrict__ W, int wave, int lane,
+                                               v8s (&w)[8][2]) {
+#pragma unroll
+  for (int kb = 0; kb < KBS; ++kb)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) w[kb][j] = W[(kb * 16 + wave * 2 + j) * kWave + lane];
+}
+
+template <int RB, int KBS>
+__device__ __forceinline__ void mlp_frags_mfma(const v8s (&w)[8][2], const short* H, int lane,
+                                               v4f (&acc)[RB][2]) {
+  const int li = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int i = 0; i < RB; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int kb = 0; kb < KBS; ++kb) {
+    v8s x[RB];
+#pragma unroll
+    for (int i = 0; i < RB; ++i)
+      x[i] = *reinterpret_cast<const v8s*>(&H[(16 * i + li) * kMlpLd + kb * 32 + 8 * lk]);
+#pragma unroll
+    for (int i = 0; i < RB; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[i][j] = mfma_bf16_k32(w[kb][j], x[i], acc[i][j]);
+  }
+}
+
 // Output layer (2 columns, padded to 16) of the fused network kernels: rows
 // [rbase, rbase + 16 OB) of H against the packed W_3; lane (li, lk) ends with
 // column li, rows rbase + 16 i + 4 lk .. + 3 in acc[i].
@@ -1129,6 +1166,14 @@ __global__ void k_step_bump(int* step) {
 // ---------------------------------------------------------------------------
 constexpr int kTrRows = 64;   // minibatch rows per workgroup of k_mlp_train
 
+// Layout of the bf16 columns of a layer's inputs or gradients (width w, n
+// rows): blocks of kColRows rows, each holding every feature's 32 rows
+// contiguously, so 16 features of one k-block of 32 rows are 1 KB of
+// consecutive bytes (one fragment load of the weight gradient).
+__host__ __device__ constexpr size_t mlp_blk_index(int w, int f, int r) {
+  return ((size_t)(r / kColRows) * w + f) * kColRows + r % kColRows;
+}
+
 __host__ __device__ constexpr int mlp_packT_offset(int layer) {
   // blocks of 32 x 16 per layer: W_3 1 x 16, W_2 8 x 16, W_1 8 x 16
   return kMlpPackElems + (layer == 3 ? 0 : layer == 2 ? 16 * 512 : (16 + 8 * 16) * 512);
@@ -1174,42 +1219,107 @@ struct MlpTrainArgs {
   const float* target;   // [n][2]
   const float* lw;       // [2] loss weights
   int* step;
-  short* actT[4];        // [width_l][n]: x, h1, h2, h3 by column (bf16)
-  short* gT[4];          // [width_{l+1}][n]: g_0 .. g_3 by column (bf16)
+  short* actT[4];        // x, h1, h2, h3 by column, blocked (mlp_blk_index), bf16
+  short* gT[4];          // g_0 .. g_3 by column, blocked, bf16
   float* bsum[4];        // [n / 32][width_{l+1}]: FP32 sums of g_l over 32-row chunks
   double* loss_part;     // [n / 32]: loss sums of k_mse's waves
 };
 
-__device__ __forceinline__ uint32_t bf16_pair(float lo, float hi) {
-  return (uint32_t)(uint16_t)to_bf16(lo) | ((uint32_t)(uint16_t)to_bf16(hi) << 16);
-}
+__device__ __forceinline__ uint32_t bf16_pair(float lo, float hi) { return to_bf16x2(lo, hi); }
 
-// Column t of the FP32 staging (kTrRows rows) to bf16 at dst (column-major,
-// rows contiguous, 16-byte stores) and, if bs, its FP32 sums over chunks of
-// kColRows rows in row order into bs[chunk * ld_bs] (k_colsum_set's first
-// stage).
-__device__ __forceinline__ void mlp_column_out(const float* F, int t, short* dst, float* bs,
-                                               int ld_bs) {
+// Column c, rows [32 h, 32 h + 32) (one chunk of kColRows rows) of the FP32
+// staging to bf16 at dst (column-major, rows contiguous, 16-byte stores) and,
+// if bs, the FP32 sum of the chunk in row order from 0.f (k_colsum_set's
+// first stage).
+__device__ __forceinline__ void mlp_column_out(const float* F, int c, int h, short* dst,
+                                               float* bs) {
+  const float* f = F + kColRows * h * kTrLdf + c;
   float s = 0.f;
 #pragma unroll
-  for (int q = 0; q < kTrRows / 8; ++q) {
+  for (int q = 0; q < kColRows / 8; ++q) {
     float v[8];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) v[e] = F[(8 * q + e) * kTrLdf + t];
+    for (int e = 0; e < 8; ++e) v[e] = f[(8 * q + e) * kTrLdf];
     if (bs) {
 #pragma unroll
       for (int e = 0; e < 8; ++e) s += v[e];
-      if ((8 * q + 8) % kColRows == 0) {
-        bs[(8 * q / kColRows) * ld_bs] = s;
-        s = 0.f;
-      }
     }
     *reinterpret_cast<uint4*>(dst + 8 * q) = make_uint4(
-        bf16_pair(v[0], v[1]), bf16_pair(v[2], v[3]), bf16_pair(v[4], v[5]), bf16_pair(v[6], v[7]));
+        to_bf16x2(v[0], v[1]), to_bf16x2(v[2], v[3]), to_bf16x2(v[4], v[5]), to_bf16x2(v[6], v[7]));
+  }
+  if (bs) *bs = s;
+}
+
+constexpr int kTrThreads = 512;   // eight waves: 32 output columns each
+
+// Hidden-layer epilogue of the training forward (k_mlp_infer's arithmetic):
+// bias (bc, per fragment), ReLU, bf16 into H for the next layer, FP32 into F
+// for the column pass; returns the ReLU gates as bits 16 j + 4 i + r.
+template <int RB>
+__device__ __forceinline__ uint32_t train_hidden_out(const v4f (&acc)[RB][2], const float4 (&bc)[2],
+                                                     short* H, float* F, int wave, int lane) {
+  const int li = lane & 15, lk = lane >> 4;
+  uint32_t gb = 0;
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int col0 = wave * 32 + 16 * j + 4 * lk;
+#pragma unroll
+    for (int i = 0; i < RB; ++i) {
+      float v0 = acc[i][j][0] + bc[j].x, v1 = acc[i][j][1] + bc[j].y;
+      float v2 = acc[i][j][2] + bc[j].z, v3 = acc[i][j][3] + bc[j].w;
+      const int bit = 16 * j + 4 * i;
+      gb |= (uint32_t)(v0 > 0.f) << bit | (uint32_t)(v1 > 0.f) << (bit + 1) |
+            (uint32_t)(v2 > 0.f) << (bit + 2) | (uint32_t)(v3 > 0.f) << (bit + 3);
+      v0 = v0 > 0.f ? v0 : 0.f;
+      v1 = v1 > 0.f ? v1 : 0.f;
+      v2 = v2 > 0.f ? v2 : 0.f;
+      v3 = v3 > 0.f ? v3 : 0.f;
+      *reinterpret_cast<uint2*>(&H[(16 * i + li) * kMlpLd + col0]) =
+          make_uint2(to_bf16x2(v0, v1), to_bf16x2(v2, v3));
+      *reinterpret_cast<float4*>(&F[(16 * i + li) * kTrLdf + col0]) = make_float4(v0, v1, v2, v3);
+    }
+  }
+  return gb;
+}
+
+// x where gate bit `bit` is set, else +0 (shape_gemm's gate): the bit as an
+// all-ones or all-zeros mask on the float's bits.
+__device__ __forceinline__ float gate_bit(float x, uint32_t gb, int bit) {
+  const uint32_t mk = (uint32_t)((int32_t)(gb << (31 - bit)) >> 31);
+  return __uint_as_float(__float_as_uint(x) & mk);
+}
+
+// Chain epilogue: the product zeroed where the gate is off, FP32 into F and,
+// when another product follows, bf16 into H.
+template <int RB>
+__device__ __forceinline__ void train_chain_out(const v4f (&acc)[RB][2], uint32_t gb, bool to_h,
+                                                short* H, float* F, int wave, int lane) {
+  const int li = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int col0 = wave * 32 + 16 * j + 4 * lk;
+#pragma unroll
+    for (int i = 0; i < RB; ++i) {
+      const int bit = 16 * j + 4 * i;
+      const float v0 = gate_bit(acc[i][j][0], gb, bit), v1 = gate_bit(acc[i][j][1], gb, bit + 1);
+      const float v2 = gate_bit(acc[i][j][2], gb, bit + 2), v3 = gate_bit(acc[i][j][3], gb, bit + 3);
+      if (to_h)
+        *reinterpret_cast<uint2*>(&H[(16 * i + li) * kMlpLd + col0]) =
+            make_uint2(to_bf16x2(v0, v1), to_bf16x2(v2, v3));
+      *reinterpret_cast<float4*>(&F[(16 * i + li) * kTrLdf + col0]) = make_float4(v0, v1, v2, v3);
+    }
   }
 }
 
-__global__ __launch_bounds__(256, 1) void k_mlp_train(MlpTrainArgs a) {
+__device__ __forceinline__ void load_bias(const float* __restrict__ b, int wave, int lane,
+                                          float4 (&bc)[2]) {
+  const int lk = lane >> 4;
+#pragma unroll
+  for (int j = 0; j < 2; ++j)
+    bc[j] = *reinterpret_cast<const float4*>(b + wave * 32 + 16 * j + 4 * lk);
+}
+
+__global__ __launch_bounds__(kTrThreads, 1) void k_mlp_train(MlpTrainArgs a) {
   constexpr int RB = kTrRows / 16;
   __shared__ __align__(16) short H[kTrRows * kMlpLd];
   __shared__ __align__(16) float F[kTrRows * kTrLdf];
@@ -1217,68 +1327,89 @@ __global__ __launch_bounds__(256, 1) void k_mlp_train(MlpTrainArgs a) {
   const int li = lane & 15, lk = lane >> 4;
   const int row0 = blockIdx.x * kTrRows;
   const int n = a.f.n;
+  const int col = tid & (kMlpHid - 1), half = tid / kMlpHid;  // column pass: column, chunk
+  const v8s* __restrict__ W = a.f.W;
   // the step number the update kernel's Adam uses (nothing else reads it here)
   if (blockIdx.x == 0 && tid == 0) *a.step += 1;
-  mlp_stage_features<kTrRows, false, true>(a.f, row0, H, F);
+  // each layer's weight fragments (and biases) are requested before the
+  // previous layer's epilogue, the first layer's before the feature gather
+  v8s w[8][2];
+  float4 bc[2];
+  mlp_frags_load<kMlpIn / 32>(W + mlp_pack_offset(0) / 8, wave, lane, w);
+  load_bias(a.f.b[0], wave, lane, bc);
+  if (tid < 256) mlp_stage_features<kTrRows, false, true>(a.f, row0, H, F);
   __syncthreads();
-  if (tid < kMlpIn) mlp_column_out(F, tid, a.actT[0] + (size_t)tid * n + row0, nullptr, 0);
-  // forward: hidden layers as in k_mlp_infer; the ReLU gates as bits
-  // (16 j + 4 i + r) of gate[l], the activations by column for the update
-  uint64_t gate[3];
-#pragma unroll 1
-  for (int l = 0; l < 3; ++l) {
-    const int kbs = (l == 0 ? kMlpIn : kMlpHid) / 32;
-    v4f acc[RB][4];
-    mlp_layer_mfma<RB>(a.f.W + mlp_pack_offset(l) / 8, H, kbs, wave, lane, acc);
-    __syncthreads();  // H read by every wave, F by every column pass
-    const float* bias = a.f.b[l];
-    uint64_t gb = 0;
+  if (col < kMlpIn)
+    mlp_column_out(F, col, half, a.actT[0] + mlp_blk_index(kMlpIn, col, row0 + kColRows * half),
+                   nullptr);
+  // forward: hidden layers as in k_mlp_infer; the ReLU gates as bits of
+  // gate[l], the activations by column for the update
+  uint32_t gate[3];
+  v4f acc[RB][2];
+  mlp_frags_mfma<RB, kMlpIn / 32>(w, H, lane, acc);
+  mlp_frags_load<8>(W + mlp_pack_offset(1) / 8, wave, lane, w);
+  __syncthreads();  // H read by every wave, F by every column pass
+  gate[0] = train_hidden_out<RB>(acc, bc, H, F, wave, lane);
+  load_bias(a.f.b[1], wave, lane, bc);
+  __syncthreads();
+  mlp_column_out(F, col, half, a.actT[1] + mlp_blk_index(kMlpHid, col, row0 + kColRows * half),
+                 nullptr);
+  mlp_frags_mfma<RB, 8>(w, H, lane, acc);
+  mlp_frags_load<8>(W + mlp_pack_offset(2) / 8, wave, lane, w);
+  __syncthreads();
+  gate[1] = train_hidden_out<RB>(acc, bc, H, F, wave, lane);
+  load_bias(a.f.b[2], wave, lane, bc);
+  __syncthreads();
+  mlp_column_out(F, col, half, a.actT[2] + mlp_blk_index(kMlpHid, col, row0 + kColRows * half),
+                 nullptr);
+  mlp_frags_mfma<RB, 8>(w, H, lane, acc);
+  // output layer fragments (waves 0-3: one block of 16 rows each)
+  v8s wo[8];
+  if (wave < 4) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int col0 = wave * 64 + 16 * j + 4 * lk;
-      const float4 bc = make_float4(bias[col0], bias[col0 + 1], bias[col0 + 2], bias[col0 + 3]);
+    for (int kb = 0; kb < 8; ++kb) wo[kb] = W[mlp_pack_offset(3) / 8 + kb * kWave + lane];
+  }
+  __syncthreads();
+  gate[2] = train_hidden_out<RB>(acc, bc, H, F, wave, lane);
+  __syncthreads();
+  mlp_column_out(F, col, half, a.actT[3] + mlp_blk_index(kMlpHid, col, row0 + kColRows * half),
+                 nullptr);
+  // output layer (mlp_out_mfma's products), then dloss/dy = g_3 and the loss
+  // terms (e = y - t)
+  {
+    v4f ao = v4f{0.f, 0.f, 0.f, 0.f};
+    float tg[4] = {0.f, 0.f, 0.f, 0.f};
+    if (wave < 4) {
+      if (li < kMlpOut) {
 #pragma unroll
-      for (int i = 0; i < RB; ++i) {
-        float v0 = acc[i][j][0] + bc.x, v1 = acc[i][j][1] + bc.y;
-        float v2 = acc[i][j][2] + bc.z, v3 = acc[i][j][3] + bc.w;
-        const int bit = 16 * j + 4 * i;
-        gb |= (uint64_t)(v0 > 0.f) << bit | (uint64_t)(v1 > 0.f) << (bit + 1) |
-              (uint64_t)(v2 > 0.f) << (bit + 2) | (uint64_t)(v3 > 0.f) << (bit + 3);
-        v0 = v0 > 0.f ? v0 : 0.f;
-        v1 = v1 > 0.f ? v1 : 0.f;
-        v2 = v2 > 0.f ? v2 : 0.f;
-        v3 = v3 > 0.f ? v3 : 0.f;
-        *reinterpret_cast<uint2*>(&H[(16 * i + li) * kMlpLd + col0]) =
-            make_uint2(to_bf16x2(v0, v1), to_bf16x2(v2, v3));
-        *reinterpret_cast<float4*>(&F[(16 * i + li) * kTrLdf + col0]) =
-            make_float4(v0, v1, v2, v3);
+        for (int r = 0; r < 4; ++r)
+          tg[r] = a.target[(size_t)(row0 + 16 * wave + 4 * lk + r) * kMlpOut + li];
+      }
+#pragma unroll
+      for (int kb = 0; kb < 8; ++kb) {
+        const v8s x = *reinterpret_cast<const v8s*>(
+            &H[(16 * wave + li) * kMlpLd + kb * 32 + 8 * lk]);
+        ao = mfma_bf16_k32(x, wo[kb], ao);
       }
     }
-    gate[l] = gb;
-    __syncthreads();
-    mlp_column_out(F, tid, a.actT[l + 1] + (size_t)tid * n + row0, nullptr, 0);
-  }
-  // output layer, then dloss/dy = g_3 and the loss terms (e = y - t)
-  {
-    v4f acc[1];
-    mlp_out_mfma<1>(a.f.W + mlp_pack_offset(3) / 8, H, 16 * wave, lane, acc);
+    mlp_frags_load<1>(W + mlp_packT_offset(3) / 8, wave, lane, w);
     __syncthreads();  // H and F free
-    if (li < kMlpOut) {
-      const float bc = a.f.b[3][li];
-      const float w = a.lw[li];
+    if (wave < 4 && li < kMlpOut) {
+      const float b3 = a.f.b[3][li];
+      const float wl = a.lw[li];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = 16 * wave + 4 * lk + r;
-        const float e = (acc[0][r] + bc) - a.target[(size_t)(row0 + row) * kMlpOut + li];
-        F[row * kTrLdf + li] = mse_grad(w, e, n);
+        const float e = (ao[r] + b3) - tg[r];
+        F[row * kTrLdf + li] = mse_grad(wl, e, n);
         F[row * kTrLdf + kMlpOut + li] = e;
       }
     }
     __syncthreads();
-    {  // g_3 as the chain's B operand: one k-block, zero past the 2 outputs
+    if (tid < 256) {  // g_3 as the chain's B operand: one k-block, zero past the 2 outputs
       const int row = tid >> 2, q = tid & 3;
       uint4 v = make_uint4(0u, 0u, 0u, 0u);
-      if (q == 0) v.x = bf16_pair(F[row * kTrLdf], F[row * kTrLdf + 1]);
+      if (q == 0) v.x = to_bf16x2(F[row * kTrLdf], F[row * kTrLdf + 1]);
       *reinterpret_cast<uint4*>(&H[row * kMlpLd + 8 * q]) = v;
     }
     if (tid < 2 * kWave) {
@@ -1287,53 +1418,46 @@ __global__ __launch_bounds__(256, 1) void k_mlp_train(MlpTrainArgs a) {
       double l = mse_loss(a.lw[j], F[row * kTrLdf + kMlpOut + j], n);
       l = wave_sum(l);
       if (lane == 0) a.loss_part[row0 / kColRows + wave] = l;
-    } else if (tid < 2 * kWave + 4) {
-      const int j = tid & 1, c = (tid - 2 * kWave) >> 1;
-      float s = 0.f;
-      for (int r = 0; r < kColRows; ++r) s += F[(kColRows * c + r) * kTrLdf + j];
-      a.bsum[3][(row0 / kColRows + c) * kMlpOut + j] = s;
-    } else if (tid < 2 * kWave + 4 + 16) {
-      const int j = (tid - 2 * kWave - 4) >> 3, q = (tid - 2 * kWave - 4) & 7;
-      const float* c = F + 8 * q * kTrLdf + j;
-      *reinterpret_cast<uint4*>(a.gT[3] + (size_t)j * n + row0 + 8 * q) = make_uint4(
-          bf16_pair(c[0], c[kTrLdf]), bf16_pair(c[2 * kTrLdf], c[3 * kTrLdf]),
-          bf16_pair(c[4 * kTrLdf], c[5 * kTrLdf]), bf16_pair(c[6 * kTrLdf], c[7 * kTrLdf]));
+    } else if (tid >= 256 && tid < 256 + 4) {
+      const int j = tid & 1, h = (tid - 256) >> 1;
+      mlp_column_out(F, j, h, a.gT[3] + mlp_blk_index(kMlpOut, j, row0 + kColRows * h),
+                     a.bsum[3] + (row0 / kColRows + h) * kMlpOut + j);
     }
     __syncthreads();
   }
   // chain: g_{l-1} = (g_l W_l^T) zeroed where h_l <= 0, l = 3, 2, 1
-#pragma unroll 1
-  for (int l = 3; l >= 1; --l) {
-    const int kbs = l == 3 ? 1 : kMlpHid / 32;
-    v4f acc[RB][4];
-    mlp_layer_mfma<RB>(a.f.W + mlp_packT_offset(l) / 8, H, kbs, wave, lane, acc);
-    __syncthreads();
-    const uint64_t gb = gate[l - 1];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int col0 = wave * 64 + 16 * j + 4 * lk;
-#pragma unroll
-      for (int i = 0; i < RB; ++i) {
-        const int bit = 16 * j + 4 * i;
-        const float v0 = (gb >> bit) & 1 ? acc[i][j][0] : 0.f;
-        const float v1 = (gb >> (bit + 1)) & 1 ? acc[i][j][1] : 0.f;
-        const float v2 = (gb >> (bit + 2)) & 1 ? acc[i][j][2] : 0.f;
-        const float v3 = (gb >> (bit + 3)) & 1 ? acc[i][j][3] : 0.f;
-        if (l > 1)
-          *reinterpret_cast<uint2*>(&H[(16 * i + li) * kMlpLd + col0]) =
-              make_uint2(bf16_pair(v0, v1), bf16_pair(v2, v3));
-        *reinterpret_cast<float4*>(&F[(16 * i + li) * kTrLdf + col0]) =
-            make_float4(v0, v1, v2, v3);
-      }
-    }
-    __syncthreads();
-    mlp_column_out(F, tid, a.gT[l - 1] + (size_t)tid * n + row0,
-                   a.bsum[l - 1] + (size_t)(row0 / kColRows) * kMlpHid + tid, kMlpHid);
-  }
+  mlp_frags_mfma<RB, 1>(w, H, lane, acc);
+  mlp_frags_load<8>(W + mlp_packT_offset(2) / 8, wave, lane, w);
+  __syncthreads();
+  train_chain_out<RB>(acc, gate[2], true, H, F, wave, lane);
+  __syncthreads();
+  mlp_column_out(F, col, half, a.gT[2] + mlp_blk_index(kMlpHid, col, row0 + kColRows * half),
+                 a.bsum[2] + (size_t)(row0 / kColRows + half) * kMlpHid + col);
+  mlp_frags_mfma<RB, 8>(w, H, lane, acc);
+  mlp_frags_load<8>(W + mlp_packT_offset(1) / 8, wave, lane, w);
+  __syncthreads();
+  train_chain_out<RB>(acc, gate[1], true, H, F, wave, lane);
+  __syncthreads();
+  mlp_column_out(F, col, half, a.gT[1] + mlp_blk_index(kMlpHid, col, row0 + kColRows * half),
+                 a.bsum[1] + (size_t)(row0 / kColRows + half) * kMlpHid + col);
+  mlp_frags_mfma<RB, 8>(w, H, lane, acc);
+  __syncthreads();
+  train_chain_out<RB>(acc, gate[0], false, H, F, wave, lane);
+  __syncthreads();
+  mlp_column_out(F, col, half, a.gT[0] + mlp_blk_index(kMlpHid, col, row0 + kColRows * half),
+                 a.bsum[0] + (size_t)(row0 / kColRows + half) * kMlpHid + col);
 }
 
-constexpr int kUpdTile = 32, kUpdWaves = 8, kUpdLd = kUpdTile + 1;
-constexpr int kUpdChunks = 128;   // bias chunk sums staged per pass
+constexpr int kUpdTile = 32, kUpdLd = kUpdTile + 1;
+constexpr int kUpdThreads = kUpdTile * kUpdTile;  // one output element per thread
+constexpr int kUpdWaves = kUpdThreads / kWave;    // 16
+constexpr int kUpdZ = 32;                          // chunk partials held in LDS at once
+constexpr int kUpdKb = 4;                          // k-blocks loaded together
+constexpr int kUpdChunks = 256;                    // bias chunk sums staged per pass
+constexpr int kUpdBlocks = 192;                    // workgroups of k_mlp_update
+// work codes of the workgroups: kind << 24 | layer << 16 | output tile << 8 |
+// input tile; kind 0 = weight tile, 1 = bias tile, 2 = loss, -1 = none
+constexpr int kUpdWeight = 0, kUpdBias = 1, kUpdLoss = 2;
 
 struct MlpUpdateArgs {
   const short* actT[4];
@@ -1342,7 +1466,7 @@ struct MlpUpdateArgs {
   const double* loss_part;
   int n;                  // batch rows
   int kc[4], splits[4];   // weight gradients: rows per split-K chunk, chunks
-  int blk0[5];            // first workgroup of each layer's weight tiles
+  int work[kUpdBlocks];   // work code of each workgroup
   float* params;
   float* m;
   float* v;
@@ -1353,53 +1477,73 @@ struct MlpUpdateArgs {
   float* loss;
 };
 
-__global__ __launch_bounds__(512) void k_mlp_update(MlpUpdateArgs a) {
-  __shared__ float P[kUpdWaves][kUpdTile * kUpdLd];
-  __shared__ float BS[kUpdChunks][kUpdTile];
-  __shared__ double LP[kUpdChunks * 4];
+// One 32 x 32 tile (outputs o0.., inputs i0..) of W_l: its gradient in
+// shape_gemm_set's split-K chunks (each chunk from zero over its k-blocks in
+// order, wave w taking chunks w, w + 16, ...; the partials of up to kUpdZ
+// chunks in LDS, then added in chunk order from 0.f by the thread that owns
+// the element; one chunk: the accumulation itself), then Adam and the two
+// bf16 packings of the new weight.
+__device__ __forceinline__ void upd_weights(const MlpUpdateArgs& a, int l, int o0, int i0,
+                                            float (*P)[kUpdTile * kUpdLd]) {
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
   const int li = lane & 15, lk = lane >> 4;
-  int l = 0;
-  while (l < 3 && (int)blockIdx.x >= a.blk0[l + 1]) ++l;  // uniform
   const int n_in = l == 0 ? kMlpIn : kMlpHid, n_out = l == 3 ? kMlpOut : kMlpHid;
-  const int o_tiles = (n_out + kUpdTile - 1) / kUpdTile;
-  const int local = (int)blockIdx.x - a.blk0[l];
-  const int o0 = (local % o_tiles) * kUpdTile, i0 = (local / o_tiles) * kUpdTile;
-  const int n = a.n;
-  const short* __restrict__ gT = a.gT[l];
-  const short* __restrict__ aT = a.actT[l];
-  const int kc = a.kc[l], splits = a.splits[l];
-  // weight gradient of the tile: A = g^T (m = output o), B = act^T (n = input
-  // i), each chunk from zero over its k-blocks in order, the chunks then
-  // added in order from 0.f (one chunk: the accumulation itself)
-  float g[2] = {0.f, 0.f};
-  for (int z0 = 0; z0 < splits; z0 += kUpdWaves) {
-    const int z = z0 + wave;
-    if (z < splits) {
+  const int n = a.n, kc = a.kc[l], splits = a.splits[l];
+  const int el_i = tid / kUpdTile, el_o = tid % kUpdTile;
+  // this thread's parameter and Adam moments, requested before the products
+  const bool own = i0 + el_i < n_in && o0 + el_o < n_out;
+  const int pw = mlp_param_offset(l) + (i0 + el_i) * n_out + o0 + el_o;
+  float p_w = 0.f, m_w = 0.f, v_w = 0.f;
+  if (own) {
+    p_w = a.params[pw];
+    m_w = a.m[pw];
+    v_w = a.v[pw];
+  }
+  // fragment rows of this lane: A = g^T (m = output o), B = act^T (n = input
+  // i); rows past the matrix read as zeros.  One k-block of every feature is
+  // one block of the blocked layout: the next k-block lies w * 32 further.
+  const short* ga[2];
+  const short* gb[2];
+  bool va[2], vb[2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const int o = o0 + 16 * t + li, i = i0 + 16 * t + li;
+    va[t] = o < n_out;
+    vb[t] = i < n_in;
+    ga[t] = a.gT[l] + mlp_blk_index(n_out, va[t] ? o : 0, 8 * lk);
+    gb[t] = a.actT[l] + mlp_blk_index(n_in, vb[t] ? i : 0, 8 * lk);
+  }
+  const size_t sa = (size_t)n_out * kColRows, sb = (size_t)n_in * kColRows;
+  const v8s zero = v8s{0, 0, 0, 0, 0, 0, 0, 0};
+  float g = 0.f;
+  for (int z0 = 0; z0 < splits; z0 += kUpdZ) {
+    for (int z = z0 + wave; z < min(splits, z0 + kUpdZ); z += kUpdWaves) {
       v4f acc[2][2];
 #pragma unroll
       for (int ob = 0; ob < 2; ++ob)
 #pragma unroll
         for (int ib = 0; ib < 2; ++ib) acc[ob][ib] = v4f{0.f, 0.f, 0.f, 0.f};
       const int k1 = min(n, (z + 1) * kc);
-      for (int k = z * kc; k < k1; k += 32) {
-        v8s fa[2], fb[2];
+      for (int k = z * kc; k < k1; k += 32 * kUpdKb) {
+        const int nkb = min(kUpdKb, (k1 - k) / 32);
+        v8s fa[kUpdKb][2], fb[kUpdKb][2];
 #pragma unroll
-        for (int ob = 0; ob < 2; ++ob) {
-          const int o = o0 + 16 * ob + li;
-          fa[ob] = o < n_out ? *reinterpret_cast<const v8s*>(gT + (size_t)o * n + k + 8 * lk)
-                             : v8s{0, 0, 0, 0, 0, 0, 0, 0};
-        }
+        for (int q = 0; q < kUpdKb; ++q)
 #pragma unroll
-        for (int ib = 0; ib < 2; ++ib) {
-          const int i = i0 + 16 * ib + li;
-          fb[ib] = i < n_in ? *reinterpret_cast<const v8s*>(aT + (size_t)i * n + k + 8 * lk)
-                            : v8s{0, 0, 0, 0, 0, 0, 0, 0};
-        }
+          for (int t = 0; t < 2; ++t) {
+            const bool in = q < nkb;
+            const size_t kb = (size_t)(k / kColRows + q);
+            fa[q][t] = va[t] && in ? *reinterpret_cast<const v8s*>(ga[t] + kb * sa) : zero;
+            fb[q][t] = vb[t] && in ? *reinterpret_cast<const v8s*>(gb[t] + kb * sb) : zero;
+          }
 #pragma unroll
-        for (int ob = 0; ob < 2; ++ob)
+        for (int q = 0; q < kUpdKb; ++q)
+          if (q < nkb)
 #pragma unroll
-          for (int ib = 0; ib < 2; ++ib) acc[ob][ib] = mfma_bf16_k32(fa[ob], fb[ib], acc[ob][ib]);
+            for (int ob = 0; ob < 2; ++ob)
+#pragma unroll
+              for (int ib = 0; ib < 2; ++ib)
+                acc[ob][ib] = mfma_bf16_k32(fa[q][ob], fb[q][ib], acc[ob][ib]);
       }
       // lane (li, lk): o = 16 ob + 4 lk + r, i = 16 ib + li of the tile
 #pragma unroll
@@ -1408,85 +1552,131 @@ __global__ __launch_bounds__(512) void k_mlp_update(MlpUpdateArgs a) {
         for (int ib = 0; ib < 2; ++ib)
 #pragma unroll
           for (int r = 0; r < 4; ++r)
-            P[wave][(16 * ib + li) * kUpdLd + 16 * ob + 4 * lk + r] = acc[ob][ib][r];
+            P[z - z0][(16 * ib + li) * kUpdLd + 16 * ob + 4 * lk + r] = acc[ob][ib][r];
     }
     __syncthreads();
-    const int nz = min(kUpdWaves, splits - z0);
+    const int nz = min(kUpdZ, splits - z0), pi = el_i * kUpdLd + el_o;
+    if (splits == 1) {
+      g = P[0][pi];
+    } else {
+      // in order; the reads of eight partials issued before their adds
+      int q0 = 0;
+      for (; q0 + 8 <= nz; q0 += 8) {
+        float v[8];
 #pragma unroll
-    for (int e = 0; e < 2; ++e) {
-      const int el = tid + 512 * e, pi = (el / kUpdTile) * kUpdLd + el % kUpdTile;
-      if (splits == 1) {
-        g[e] = P[0][pi];
-      } else {
-        for (int q = 0; q < nz; ++q) g[e] += P[q][pi];
+        for (int q = 0; q < 8; ++q) v[q] = P[q0 + q][pi];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) g += v[q];
       }
+      for (; q0 < nz; ++q0) g += P[q0][pi];
     }
     __syncthreads();
   }
-  const int t = *a.step;
-  const int base = mlp_param_offset(l);
+  if (own) {
+    if (a.grad) a.grad[pw] = g;
+    const float p = adam_apply(p_w, g, m_w, v_w, *a.step, a.lr, a.b1, a.b2, a.eps);
+    a.params[pw] = p;
+    a.m[pw] = m_w;
+    a.v[pw] = v_w;
+    const short pb = to_bf16(p);
+    const int i = i0 + el_i, o = o0 + el_o;
+    a.packed[mlp_pack_index(l, i, o)] = pb;
+    if (l > 0) a.packed[mlp_packT_index(l, i, o)] = pb;
+  }
+}
+
+// Bias gradients of outputs o0 .. o0 + 31 of layer l: the FP64 sums of the
+// 32-row chunk sums in chunk order (k_colsum_set's second stage), then Adam.
+// The chunk sums are staged in LDS by all threads; a wave of 32 lanes adds.
+__device__ __forceinline__ void upd_bias(const MlpUpdateArgs& a, int l, int o0, float* BS) {
+  const int tid = threadIdx.x;
+  const int n_in = l == 0 ? kMlpIn : kMlpHid, n_out = l == 3 ? kMlpOut : kMlpHid;
+  const int chunks = a.n / kColRows;
+  const int o = o0 + tid;
+  const bool own = tid < kUpdTile && o < n_out;
+  const int pb = mlp_param_offset(l) + n_in * n_out + o;
+  float p_b = 0.f, m_b = 0.f, v_b = 0.f;
+  if (own) {
+    p_b = a.params[pb];
+    m_b = a.m[pb];
+    v_b = a.v[pb];
+  }
+  double S = 0.0;
+  for (int c0 = 0; c0 < chunks; c0 += kUpdChunks) {
+    const int nc = min(kUpdChunks, chunks - c0);
+    for (int x = tid; x < nc * kUpdTile; x += kUpdThreads) {
+      const int c = x / kUpdTile, oc = o0 + x % kUpdTile;
+      BS[x] = oc < n_out ? a.bsum[l][(size_t)(c0 + c) * n_out + oc] : 0.f;
+    }
+    __syncthreads();
+    if (tid < kUpdTile) {
+      int c = 0;
+      for (; c + 8 <= nc; c += 8) {
+        float v[8];
 #pragma unroll
-  for (int e = 0; e < 2; ++e) {
-    const int el = tid + 512 * e;
-    const int i = i0 + el / kUpdTile, o = o0 + el % kUpdTile;
-    if (i < n_in && o < n_out) {
-      const int pi = base + i * n_out + o;
-      if (a.grad) a.grad[pi] = g[e];
-      float m = a.m[pi], v = a.v[pi];
-      const float p = adam_apply(a.params[pi], g[e], m, v, t, a.lr, a.b1, a.b2, a.eps);
-      a.params[pi] = p;
-      a.m[pi] = m;
-      a.v[pi] = v;
-      const short pb = to_bf16(p);
-      a.packed[mlp_pack_index(l, i, o)] = pb;
-      if (l > 0) a.packed[mlp_packT_index(l, i, o)] = pb;
-    }
-  }
-  // bias gradients (the workgroups of the first column of tiles): FP64 sums
-  // of the chunk sums in chunk order, as k_colsum_set
-  if (i0 == 0) {
-    const int chunks = n / kColRows;
-    double S = 0.0;
-    for (int c0 = 0; c0 < chunks; c0 += kUpdChunks) {
-      const int nc = min(kUpdChunks, chunks - c0);
-      for (int x = tid; x < nc * kUpdTile; x += blockDim.x) {
-        const int c = x / kUpdTile, o = o0 + x % kUpdTile;
-        BS[c][x % kUpdTile] = o < n_out ? a.bsum[l][(size_t)(c0 + c) * n_out + o] : 0.f;
+        for (int u = 0; u < 8; ++u) v[u] = BS[(c + u) * kUpdTile + tid];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) S += v[u];
       }
-      __syncthreads();
-      if (tid < kUpdTile)
-        for (int c = 0; c < nc; ++c) S += BS[c][tid];
-      __syncthreads();
+      for (; c < nc; ++c) S += BS[c * kUpdTile + tid];
     }
-    const int o = o0 + tid;
-    if (tid < kUpdTile && o < n_out) {
-      const int pi = base + n_in * n_out + o;
-      const float gb = (float)S;
-      if (a.grad) a.grad[pi] = gb;
-      float m = a.m[pi], v = a.v[pi];
-      a.params[pi] = adam_apply(a.params[pi], gb, m, v, t, a.lr, a.b1, a.b2, a.eps);
-      a.m[pi] = m;
-      a.v[pi] = v;
-    }
+    __syncthreads();
   }
-  // loss: k_mse's block sums (four waves of 32 rows, missing waves 0) in
-  // block order, as k_sum_partials
-  if (blockIdx.x == 0) {
-    const int waves = n / kColRows, blocks = (waves + 3) / 4;
-    double s = 0.0;
-    for (int b0 = 0; b0 < blocks; b0 += kUpdChunks) {
-      const int nb = min(kUpdChunks, blocks - b0);
-      for (int x = tid; x < nb * 4; x += blockDim.x) {
-        const int w = 4 * b0 + x;
-        LP[x] = w < waves ? a.loss_part[w] : 0.0;
+  if (own) {
+    const float gbias = (float)S;
+    if (a.grad) a.grad[pb] = gbias;
+    a.params[pb] = adam_apply(p_b, gbias, m_b, v_b, *a.step, a.lr, a.b1, a.b2, a.eps);
+    a.m[pb] = m_b;
+    a.v[pb] = v_b;
+  }
+}
+
+// The minibatch loss: k_mse's block sums (its four waves of 32 rows, a
+// missing wave 0) added in block order, as k_sum_partials.
+__device__ __forceinline__ void upd_loss(const MlpUpdateArgs& a, double* LP) {
+  const int tid = threadIdx.x;
+  const int waves = a.n / kColRows, blocks = (waves + 3) / 4;
+  double s = 0.0;
+  for (int b0 = 0; b0 < blocks; b0 += kUpdThreads) {
+    const int nb = min(kUpdThreads, blocks - b0);
+    if (tid < nb) {
+      double r[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int w = 4 * (b0 + tid) + q;
+        r[q] = w < waves ? a.loss_part[w] : 0.0;
       }
-      __syncthreads();
-      if (tid == 0)
-        for (int b = 0; b < nb; ++b) s += LP[4 * b] + LP[4 * b + 1] + LP[4 * b + 2] + LP[4 * b + 3];
-      __syncthreads();
+      LP[tid] = r[0] + r[1] + r[2] + r[3];
     }
-    if (tid == 0) *a.loss = (float)s;
+    __syncthreads();
+    if (tid == 0) {
+      int b = 0;
+      for (; b + 8 <= nb; b += 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = LP[b + u];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += v[u];
+      }
+      for (; b < nb; ++b) s += LP[b];
+    }
+    __syncthreads();
   }
+  if (tid == 0) *a.loss = (float)s;
+}
+
+__global__ __launch_bounds__(kUpdThreads) void k_mlp_update(MlpUpdateArgs a) {
+  __shared__ float P[kUpdZ][kUpdTile * kUpdLd];
+  const int code = a.work[blockIdx.x];
+  if (code < 0) return;
+  const int kind = code >> 24, l = (code >> 16) & 0xFF;
+  const int o0 = ((code >> 8) & 0xFF) * kUpdTile, i0 = (code & 0xFF) * kUpdTile;
+  if (kind == kUpdWeight)
+    upd_weights(a, l, o0, i0, P);
+  else if (kind == kUpdBias)
+    upd_bias(a, l, o0, &P[0][0]);
+  else
+    upd_loss(a, reinterpret_cast<double*>(&P[0][0]));
 }
 
 // ---------------------------------------------------------------------------
@@ -1919,7 +2109,6 @@ hipError_t launch_mlp_step(const MlpStep& s, void* scratch, hipStream_t st) {
   ta.lw = s.lw;
   ta.step = s.step;
   MlpUpdateArgs ua{};
-  int blocks = 0;
   for (int l = 0; l < 4; ++l) {
     const int n_in = l == 0 ? kMlpIn : kMlpHid, n_out = l == 3 ? kMlpOut : kMlpHid;
     ta.f.b[l] = s.params + mlp_param_offset(l) + n_in * n_out;
@@ -1945,10 +2134,38 @@ hipError_t launch_mlp_step(const MlpStep& s, void* scratch, hipStream_t st) {
     }
     ua.kc[l] = kc;
     ua.splits[l] = splits;
-    ua.blk0[l] = blocks;
-    blocks += ((n_out + kUpdTile - 1) / kUpdTile) * ((n_in + kUpdTile - 1) / kUpdTile);
   }
-  ua.blk0[4] = blocks;
+  // Work of each workgroup.  Workgroups are dealt to the eight XCDs in turn
+  // (workgroup b on XCD b % 8), each XCD with its own L2: an XCD gets a block
+  // of tiles sharing rows of the operands (W_1, W_2: 2 output x 4 input tiles;
+  // W_0: one output tile x all 3 input tiles; W_3: one input tile), then the
+  // bias tiles and the loss.
+  std::vector<int> per_xcd[8];
+  auto code = [](int kind, int l, int ot, int it) { return kind << 24 | l << 16 | ot << 8 | it; };
+  for (int x = 0; x < 8; ++x) {
+    for (int l = 1; l <= 2; ++l)
+      for (int ot = 2 * (x % 4); ot < 2 * (x % 4) + 2; ++ot)
+        for (int it = 4 * (x / 4); it < 4 * (x / 4) + 4; ++it)
+          per_xcd[x].push_back(code(kUpdWeight, l, ot, it));
+    for (int it = 0; it < kMlpIn / kUpdTile; ++it) per_xcd[x].push_back(code(kUpdWeight, 0, x, it));
+    per_xcd[x].push_back(code(kUpdWeight, 3, 0, x));
+  }
+  std::vector<int> extra;
+  for (int l = 0; l < 4; ++l) {
+    const int n_out = l == 3 ? kMlpOut : kMlpHid;
+    for (int ot = 0; ot < (n_out + kUpdTile - 1) / kUpdTile; ++ot)
+      extra.push_back(code(kUpdBias, l, ot, 0));
+  }
+  extra.push_back(code(kUpdLoss, 0, 0, 0));
+  for (size_t e = 0; e < extra.size(); ++e) per_xcd[e % 8].push_back(extra[e]);
+  size_t slots = 0;
+  for (int x = 0; x < 8; ++x) slots = std::max(slots, per_xcd[x].size());
+  const int blocks = (int)(8 * slots);
+  if (blocks > kUpdBlocks) return hipErrorInvalidValue;
+  for (int b = 0; b < blocks; ++b) {
+    const std::vector<int>& q = per_xcd[b % 8];
+    ua.work[b] = (size_t)(b / 8) < q.size() ? q[b / 8] : -1;
+  }
   ta.loss_part = (double*)(base + L.loss);
   ua.loss_part = ta.loss_part;
   ua.n = n;
@@ -1963,10 +2180,10 @@ hipError_t launch_mlp_step(const MlpStep& s, void* scratch, hipStream_t st) {
   ua.grad = s.grad;
   ua.packed = (short*)s.packed;
   ua.loss = s.loss;
-  hipLaunchKernelGGL(k_mlp_train, dim3((unsigned)(n / kTrRows)), dim3(256), 0, st, ta);
+  hipLaunchKernelGGL(k_mlp_train, dim3((unsigned)(n / kTrRows)), dim3(kTrThreads), 0, st, ta);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_mlp_update, dim3((unsigned)blocks), dim3(512), 0, st, ua);
+  hipLaunchKernelGGL(k_mlp_update, dim3((unsigned)blocks), dim3(kUpdThreads), 0, st, ua);
   return hipGetLastError();
 }
 

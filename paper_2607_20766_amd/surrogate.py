@@ -275,10 +275,11 @@ class Triage:
               fused_forward: bool = True, fused_step: bool = True):
         """Minibatch Adam on the weighted MSE of standardised labels Y [n, 2].
 
-        Each epoch's shuffled rows are copied into fixed device buffers, so
-        after the first (eager) epoch the whole epoch of steps is captured
-        once as a HIP graph and replayed (graph=True): identical kernels and
-        results, without a host round trip per launch.  fused_step: each
+        Each epoch's shuffled rows are gathered on the device into fixed
+        buffers, so after the first (eager) epoch the whole epoch of steps is
+        captured once as a HIP graph and replayed (graph=True): identical
+        kernels and results, without a host round trip per launch; the loss
+        history is read once at the end.  fused_step: each
         minibatch in the two launches of shape_mlp_train_step (BF16 network
         of the default widths, batch a multiple of 64); else fused_forward:
         its features and forward in one kernel (shape_mlp_forward), then the
@@ -326,28 +327,48 @@ class Triage:
                     self.mlp.loss_grad(xb, y_ep[s:e], lw, losses[b:b + 1])
                 self.mlp.adam_step(lr)
 
+        # the training rows stay on the device; an epoch uploads only its
+        # permutation (pinned, double-buffered, so the host shuffles the next
+        # epoch while the device trains on this one) and gathers its rows
+        q_all = torch.from_numpy(qidx.astype(np.int32)).to(dev)
+        m_all = torch.from_numpy(midx.astype(np.int32)).to(dev)
+        y_all = torch.from_numpy(np.ascontiguousarray(Ys)).to(dev)
+        fo_all = (torch.from_numpy(np.ascontiguousarray(fo, np.float32)).to(dev)
+                  if fo_ep is not None else None)
+        perm_host = [torch.empty(rows, dtype=torch.int64, pin_memory=True) for _ in range(2)]
+        perm_done = [None, None]
+        perm_dev = torch.empty(rows, dtype=torch.int64, device=dev)
+        loss_hist = torch.empty(epochs, max(nb, 1), dtype=torch.float32, device=dev)
         g = None
-        history = []
         try:
             for ep in range(epochs):
-                perm = rng.permutation(n)[:rows]
-                q_ep.copy_(torch.from_numpy(qidx[perm].astype(np.int32)))
-                m_ep.copy_(torch.from_numpy(midx[perm].astype(np.int32)))
-                y_ep.copy_(torch.from_numpy(np.ascontiguousarray(Ys[perm])))
+                buf = ep % 2
+                if perm_done[buf] is not None:
+                    perm_done[buf].synchronize()   # its previous copy has been read
+                perm_host[buf].numpy()[:] = rng.permutation(n)[:rows]
+                perm_dev.copy_(perm_host[buf], non_blocking=True)
+                perm_done[buf] = torch.cuda.Event()
+                perm_done[buf].record()
+                torch.index_select(q_all, 0, perm_dev, out=q_ep)
+                torch.index_select(m_all, 0, perm_dev, out=m_ep)
+                torch.index_select(y_all, 0, perm_dev, out=y_ep)
                 if fo_ep is not None:
-                    fo_ep.copy_(torch.from_numpy(np.ascontiguousarray(fo[perm], np.float32)))
+                    torch.index_select(fo_all, 0, perm_dev, out=fo_ep)
                 if graph and ep > 0 and nb > 0:
                     if g is None:
                         g = self.eng.capture(epoch_steps, warmup=False)
                     g.replay()
                 else:
                     epoch_steps()
-                history.append(float(losses.cpu().numpy().mean()))
+                loss_hist[ep].copy_(losses)
                 if log:
-                    log(f"epoch {ep}: loss {history[-1]:.4f}")
+                    log(f"epoch {ep}: loss {float(losses.cpu().numpy().mean()):.4f}")
+            hist = loss_hist.cpu().numpy()
         finally:
             if g is not None:
                 g.close()
+        return [float(h.mean()) for h in hist]
+
         return history
 
     def predict_raw(self, f_q, f_lib, fo=None, chunk: int = 65536, fused: bool = True,
