@@ -519,6 +519,8 @@ def main():
                     help="only copy 1 GiB device to device three times (a plain copy of known "
                          "size for scaling the FETCH_SIZE / WRITE_SIZE counters) and exit")
     ap.add_argument("--triage-library", type=int, default=1000000)
+    ap.add_argument("--tune-cache", default=None,
+                    help="text file that keeps the screening kernel's tuning choices across runs")
     ap.add_argument("--peaks", action="store_true",
                     help="only measure the instruction issue rates (FP32 FMA, v_exp_f32, "
                          "v_mad_u64_u32, LDS reads) and exit")
@@ -527,8 +529,9 @@ def main():
                          "section")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: the engine has no multi-GPU path in this "
-              "build (pairs shard trivially; see the design notes)", file=sys.stderr)
+        print("bench.py measures a single GPU (--gpus 1): screening pairs shard across "
+              "GPUs without communication, and the library has no multi-GPU path",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -544,7 +547,9 @@ def main():
 
     from paper_2607_20766_amd import molgen
     from paper_2607_20766_amd.engine import (SCREEN_VARIANT_SHAPES, SHAPE_SCREEN_ADAPTIVE,
-                                             SHAPE_SCREEN_FIXED, Engine)
+                                             SHAPE_SCREEN_FIXED, Engine, tune_cache_file)
+    if args.tune_cache:
+        tune_cache_file(args.tune_cache)
 
     if args.peaks:
         eng = Engine(0)

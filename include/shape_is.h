@@ -69,7 +69,8 @@ int shape_create(shape_ctx** out, int device);
 void shape_destroy(shape_ctx* ctx);
 
 /* Message of the last failed call on ctx (ctx NULL: last failed
- * shape_create).  Never NULL; valid until the next call on ctx. */
+ * shape_create or context-free call on this thread).  Never NULL; valid until
+ * the next call on ctx. */
 const char* shape_last_error(const shape_ctx* ctx);
 
 /* Library version string (host memory, static). */
@@ -290,7 +291,23 @@ int shape_prepare_cache(shape_ctx* ctx, int enable);
  * times to ms[SHAPE_SCREEN_VARIANTS] (host, may be NULL).  Synchronises
  * `stream`.  Errors: as shape_screen; SHAPE_E_UNSUPPORTED during capture.
  * shape_screen_set_variant selects a variant by index (-1 = default);
- * shape_screen_get_variant returns the current one (-1 if ctx is NULL). */
+ * shape_screen_get_variant returns the current one (-1 if ctx is NULL).
+ *
+ * Tuning cache: each choice is remembered process-wide under the kind of
+ * screen — the device's architecture name and compute-unit count, mode,
+ * sampling, the sample schedule (n_per_side, or round_per_pair and
+ * cap_per_pair), whether n_start seeds the budgets, and the power-of-two
+ * classes (floor log2) of the pair count, the query's atom count and the
+ * library's mean atom count.  A later shape_screen_tune of the same kind, on
+ * any context, selects the remembered variant without launching anything
+ * (ms receives -1 for every variant); results are the same bits either way.
+ * shape_tune_cache_file(path) backs the table with a text file: its entries
+ * are read now (lines that do not parse are skipped; a missing file is
+ * created) and each new choice is appended as one line; NULL detaches the
+ * file (SHAPE_E_INVAL if it cannot be opened; message via
+ * shape_last_error(NULL)).  shape_tune_cache_clear forgets every entry
+ * (the file is left as it is); shape_tune_cache_size counts them.  These
+ * three are thread-safe. */
 #define SHAPE_SCREEN_VARIANTS 8
 int shape_screen_tune(shape_ctx* ctx, const shape_mols* query, const shape_mols* lib,
                       const int32_t* pairs, int32_t n_pairs,
@@ -298,6 +315,9 @@ int shape_screen_tune(shape_ctx* ctx, const shape_mols* query, const shape_mols*
                       int32_t* best);
 int shape_screen_set_variant(shape_ctx* ctx, int32_t variant);
 int32_t shape_screen_get_variant(const shape_ctx* ctx);
+int shape_tune_cache_file(const char* path);
+int shape_tune_cache_clear(void);
+int32_t shape_tune_cache_size(void);
 
 /* HIP graphs of a sequence of asynchronous calls (launch overhead only;
  * results are those of the same calls made directly).

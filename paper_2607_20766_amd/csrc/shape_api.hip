@@ -7,6 +7,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <map>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -68,6 +69,7 @@ struct shape_ctx {
   int device = -1;
   std::shared_ptr<GraphLife> life;
   int n_cu = 0;
+  char arch[64] = {0};          // gcnArchName of the device
   size_t lds_per_block = 0;
   std::string err;
   Buffer buf[S_COUNT];
@@ -429,6 +431,7 @@ int shape_create(shape_ctx** out, int device) {
   c->life->device = device;
   c->device = device;
   c->n_cu = prop.multiProcessorCount;
+  snprintf(c->arch, sizeof c->arch, "%s", prop.gcnArchName);
   c->lds_per_block = prop.sharedMemPerBlock;
   e = hipSetDevice(device);
   if (e == hipSuccess) e = hipMalloc(&c->flag, 3 * sizeof(int));
@@ -671,6 +674,85 @@ int shape_screen(shape_ctx* c, const shape_mols* query, const shape_mols* lib,
   }
 }
 
+// Tuning cache: the variant shape_screen_tune chose for a kind of screen,
+// process-wide (a variant suits any context on the same kind of device), and
+// optionally appended to a text file from which a later process reads it.
+namespace {
+
+std::mutex g_tune_m;
+std::map<std::string, int> g_tune;
+std::string g_tune_file;
+constexpr const char* kTuneTag = "shape-tune-v1";
+
+int floor_log2(int64_t x) {
+  int b = -1;
+  while (x > 0) {
+    x >>= 1;
+    ++b;
+  }
+  return b;
+}
+
+// The screen's kind: device (architecture, compute units), mode and
+// sampling, the per-pair sample schedule, whether budgets are seeded, and the
+// power-of-two classes of the pair count, the query's atom count and the
+// library's mean atom count.
+std::string tune_key(const shape_ctx* c, const shape_mols* query, const shape_mols* lib,
+                     int32_t n_pairs, const shape_screen_params* prm) {
+  const bool fixed = prm->mode == SHAPE_SCREEN_FIXED;
+  char k[256];
+  snprintf(k, sizeof k, "%s %d %d %d %d %d %d %d %d %d %d", c->arch, c->n_cu, prm->mode,
+           c->sampling, fixed ? prm->n_per_side : 0, fixed ? 0 : prm->round_per_pair,
+           fixed ? 0 : prm->cap_per_pair, (!fixed && prm->n_start) ? 1 : 0, floor_log2(n_pairs),
+           floor_log2(query->max_atoms), floor_log2(lib->n_atoms / (lib->n_mols > 0 ? lib->n_mols : 1)));
+  return k;
+}
+
+}  // namespace
+
+int shape_tune_cache_file(const char* path) {
+  std::lock_guard<std::mutex> lock(g_tune_m);
+  if (!path) {
+    g_tune_file.clear();
+    return SHAPE_OK;
+  }
+  if (!*path) return fail(nullptr, SHAPE_E_INVAL, "empty tuning-cache path");
+  if (FILE* f = fopen(path, "r")) {
+    char line[512];
+    while (fgets(line, sizeof line, f)) {
+      // tag, eleven key fields, variant; anything else is skipped
+      char tag[32], arch[64];
+      int v[10], variant;
+      if (sscanf(line, "%31s %63s %d %d %d %d %d %d %d %d %d %d %d", tag, arch, &v[0], &v[1],
+                 &v[2], &v[3], &v[4], &v[5], &v[6], &v[7], &v[8], &v[9], &variant) != 13 ||
+          strcmp(tag, kTuneTag) != 0 || variant < 0 || variant >= shape::kScreenVariants)
+        continue;
+      char k[256];
+      snprintf(k, sizeof k, "%s %d %d %d %d %d %d %d %d %d %d", arch, v[0], v[1], v[2], v[3],
+               v[4], v[5], v[6], v[7], v[8], v[9]);
+      g_tune[k] = variant;
+    }
+    fclose(f);
+  } else if (FILE* w = fopen(path, "a")) {
+    fclose(w);  // a new file: its directory is writable
+  } else {
+    return fail(nullptr, SHAPE_E_INVAL, "cannot open tuning cache %s", path);
+  }
+  g_tune_file = path;
+  return SHAPE_OK;
+}
+
+int shape_tune_cache_clear(void) {
+  std::lock_guard<std::mutex> lock(g_tune_m);
+  g_tune.clear();
+  return SHAPE_OK;
+}
+
+int32_t shape_tune_cache_size(void) {
+  std::lock_guard<std::mutex> lock(g_tune_m);
+  return (int32_t)g_tune.size();
+}
+
 int shape_screen_tune(shape_ctx* c, const shape_mols* query, const shape_mols* lib,
                       const int32_t* pairs, int32_t n_pairs, const shape_screen_params* prm,
                       void* stream, float* ms, int32_t* best) {
@@ -691,6 +773,19 @@ int shape_screen_tune(shape_ctx* c, const shape_mols* query, const shape_mols* l
     if ((rc = screen_setup(c, query, lib, pairs, n_pairs, prm, st, &o, &a))) return rc;
     float t[shape::kScreenVariants];
     int pick = 0;
+    std::string key;
+    if (a.n_pairs > 0) {
+      key = tune_key(c, query, lib, n_pairs, prm);
+      std::lock_guard<std::mutex> lock(g_tune_m);
+      auto it = g_tune.find(key);
+      if (it != g_tune.end()) {  // chosen before: no timing
+        c->screen_variant = it->second;
+        if (ms)
+          for (int v = 0; v < shape::kScreenVariants; ++v) ms[v] = -1.0f;
+        if (best) *best = it->second;
+        return SHAPE_OK;
+      }
+    }
     if (a.n_pairs > 0) {
       hipEvent_t e0, e1;
       HIP_TRY(c, hipEventCreate(&e0), "hipEventCreate");
@@ -716,6 +811,14 @@ int shape_screen_tune(shape_ctx* c, const shape_mols* query, const shape_mols* l
       (void)hipEventDestroy(e0);
       (void)hipEventDestroy(e1);
       if (e != hipSuccess) return hip_fail(c, e, "screen tuning");
+      std::lock_guard<std::mutex> lock(g_tune_m);
+      g_tune[key] = pick;
+      if (!g_tune_file.empty()) {
+        if (FILE* f = fopen(g_tune_file.c_str(), "a")) {
+          fprintf(f, "%s %s %d\n", kTuneTag, key.c_str(), pick);
+          fclose(f);
+        }
+      }
     } else {
       for (int v = 0; v < shape::kScreenVariants; ++v) t[v] = 0.0f;
     }

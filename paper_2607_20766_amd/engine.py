@@ -34,6 +34,24 @@ ERRORS = {-1: "SHAPE_E_INVAL", -2: "SHAPE_E_RANGE", -3: "SHAPE_E_NOMEM",
           -4: "SHAPE_E_HIP", -5: "SHAPE_E_UNSUPPORTED", -6: "SHAPE_E_DATA"}
 
 
+def tune_cache_file(path: str | None):
+    """Back the process-wide tuning cache with a text file (read now, new
+    choices appended); None detaches it."""
+    L = load_library()
+    rc = L.shape_tune_cache_file(None if path is None else os.fsencode(path))
+    if rc != SHAPE_OK:
+        raise ShapeError(rc, L.shape_last_error(None).decode(errors="replace"))
+
+
+def tune_cache_clear():
+    """Forget every remembered tuning choice of this process."""
+    load_library().shape_tune_cache_clear()
+
+
+def tune_cache_size() -> int:
+    return int(load_library().shape_tune_cache_size())
+
+
 class ShapeError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"{ERRORS.get(code, code)}: {msg}")
@@ -106,6 +124,10 @@ def load_library():
                                    vp, i32, ctypes.POINTER(ShapeScreenParams), vp,
                                    ctypes.POINTER(ShapeScreenOut)]
         L.shape_check_data.argtypes = [vp, vp]
+        L.shape_tune_cache_file.argtypes = [ctypes.c_char_p]
+        L.shape_tune_cache_clear.argtypes = []
+        L.shape_tune_cache_size.argtypes = []
+        L.shape_tune_cache_size.restype = i32
         L.shape_screen_tune.argtypes = [vp, ctypes.POINTER(ShapeMols),
                                         ctypes.POINTER(ShapeMols), vp, i32,
                                         ctypes.POINTER(ShapeScreenParams), vp, vp, vp]
@@ -445,7 +467,9 @@ class Engine:
                           n_pairs: int | None = None, n_start: torch.Tensor | None = None,
                           stream=None):
         """Time every tile variant of the screening kernel on this workload,
-        keep the fastest for later screens; returns (best, [ms per variant])."""
+        keep the fastest for later screens; returns (best, [ms per variant]).
+        A workload of a kind tuned before in this process (or read from the
+        tuning-cache file) reuses that choice without timing: ms are -1."""
         pairs, n, n_start, q, l_ = self._screen_call(query, lib, pairs, n_pairs, n_start, stream)
         prm = ShapeScreenParams(mode, n_per_side, round_per_pair, cap_per_pair, tau, seed,
                                 None if n_start is None else n_start.data_ptr())

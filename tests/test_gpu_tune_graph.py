@@ -8,7 +8,8 @@ import torch
 from paper_2607_20766_amd import molgen
 from paper_2607_20766_amd.engine import (SHAPE_E_UNSUPPORTED, SHAPE_SCREEN_ADAPTIVE,
                                          SHAPE_SCREEN_FIXED, SHAPE_SCREEN_VARIANTS, Engine,
-                                         ShapeError)
+                                         ShapeError, tune_cache_clear, tune_cache_file,
+                                         tune_cache_size)
 from tests.gpu_common import require_gpu
 
 pytestmark = pytest.mark.gpu
@@ -69,6 +70,7 @@ def test_all_variants_bit_identical(eng, data, kw):
 
 def test_tuner_picks_a_variant(eng, data):
     Q, lib = data
+    tune_cache_clear()
     before = _np(eng.shape_screen(Q, lib, mode=SHAPE_SCREEN_ADAPTIVE, seed=5))
     best, ms = eng.shape_screen_tune(Q, lib, mode=SHAPE_SCREEN_ADAPTIVE, seed=5)
     assert 0 <= best < SHAPE_SCREEN_VARIANTS
@@ -344,3 +346,51 @@ def test_features_and_first_order_flag_invalid_data(eng):
     fo2 = eng.shape_fo_overlap(Q, lib, pairs=bad_idx).cpu().numpy()
     assert np.isfinite(fo2[0]) and np.isnan(fo2[1:]).all()
     eng.shape_check_data()
+
+
+def test_tuner_cache_second_context_reuses_choice(eng, data):
+    """A second context tuning the same kind of screen takes the first
+    context's choice without timing anything, and screens to the same bits;
+    another schedule is a different kind and is timed."""
+    Q, lib = data
+    kw = dict(mode=SHAPE_SCREEN_ADAPTIVE, round_per_pair=512, cap_per_pair=8192, seed=11)
+    tune_cache_clear()
+    best1, ms1 = eng.shape_screen_tune(Q, lib, **kw)
+    assert all(t > 0 for t in ms1) and tune_cache_size() == 1
+    out1 = _np(eng.shape_screen(Q, lib, **kw))
+    e2 = Engine(0)
+    print("case: tuning cache, second context", flush=True)
+    best2, ms2 = e2.shape_screen_tune(Q, lib, **kw)
+    assert best2 == best1 and e2.screen_variant() == best1
+    assert all(t == -1 for t in ms2)
+    _same(out1, _np(e2.shape_screen(Q, lib, **kw)))
+    _, ms3 = e2.shape_screen_tune(Q, lib, **dict(kw, cap_per_pair=16384))
+    assert all(t > 0 for t in ms3) and tune_cache_size() == 2
+    eng.screen_variant(-1)
+
+
+def test_tuner_cache_file_round_trip(eng, data, tmp_path):
+    """Choices appended to the cache file are read back after the process
+    table is cleared (as by a new process), and reused without timing."""
+    Q, lib = data
+    kw = dict(mode=SHAPE_SCREEN_FIXED, n_per_side=1024, seed=3)
+    path = str(tmp_path / "tune.txt")
+    tune_cache_clear()
+    tune_cache_file(path)
+    try:
+        best, ms = eng.shape_screen_tune(Q, lib, **kw)
+        assert all(t > 0 for t in ms)
+        lines = open(path).read().splitlines()
+        assert len(lines) == 1 and lines[0].startswith("shape-tune-v1 gfx950")
+        assert lines[0].split()[-1] == str(best)
+        tune_cache_clear()
+        assert tune_cache_size() == 0
+        tune_cache_file(path)
+        assert tune_cache_size() == 1
+        e2 = Engine(0)
+        print("case: tuning cache read from a file", flush=True)
+        best2, ms2 = e2.shape_screen_tune(Q, lib, **kw)
+        assert best2 == best and all(t == -1 for t in ms2)
+    finally:
+        tune_cache_file(None)
+        eng.screen_variant(-1)
