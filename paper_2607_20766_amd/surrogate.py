@@ -268,11 +268,52 @@ class Triage:
         self.mean.copy_(torch.from_numpy(mu.astype(np.float32)))
         self.inv_std.copy_(torch.from_numpy((1.0 / sd).astype(np.float32)))
 
+    # -- checkpoints ---------------------------------------------------------------
+    def state_dict(self) -> dict:
+        """Everything training and screening read: network parameters, Adam
+        moments and step counter, feature standardisation and label
+        statistics, as CPU tensors."""
+        m = self.mlp
+        return {
+            "params": m.params.detach().cpu().clone(), "adam_m": m.m.detach().cpu().clone(),
+            "adam_v": m.v.detach().cpu().clone(), "adam_step": m.step.detach().cpu().clone(),
+            "feat_mean": self.mean.detach().cpu().clone(),
+            "feat_inv_std": self.inv_std.detach().cpu().clone(),
+            "y_mean": torch.from_numpy(np.asarray(self.y_mean, np.float64)),
+            "y_std": torch.from_numpy(np.asarray(self.y_std, np.float64)),
+            "width": torch.tensor(self.mlp.width, dtype=torch.int64),
+        }
+
+    def load_state_dict(self, sd: dict):
+        m = self.mlp
+        if tuple(int(w) for w in sd["width"]) != m.width:
+            raise ValueError(f"checkpoint widths {tuple(sd['width'].tolist())} != {m.width}")
+        for dst, key in ((m.params, "params"), (m.m, "adam_m"), (m.v, "adam_v"),
+                         (m.step, "adam_step"), (self.mean, "feat_mean"),
+                         (self.inv_std, "feat_inv_std")):
+            src = sd[key]
+            if src.shape != dst.shape or src.dtype != dst.dtype:
+                raise ValueError(f"checkpoint {key}: {tuple(src.shape)} {src.dtype}, expected "
+                                 f"{tuple(dst.shape)} {dst.dtype}")
+            dst.copy_(src)
+        self.y_mean = sd["y_mean"].numpy().copy()
+        self.y_std = sd["y_std"].numpy().copy()
+        m.packed = None   # repacked by the next training run
+
+    def save(self, path: str):
+        """Checkpoint to a safetensors file (tensors only, nothing executable)."""
+        from safetensors.torch import save_file
+        save_file(self.state_dict(), path)
+
+    def load(self, path: str):
+        from safetensors.torch import load_file
+        self.load_state_dict(load_file(path))
+
     # -- training --------------------------------------------------------------------
     def train(self, f_q, f_lib, qidx: np.ndarray, midx: np.ndarray, Y: np.ndarray,
               fo: np.ndarray | None = None, epochs: int = 8, batch: int = 4096,
               lr: float = 1e-3, seed: int = 0, log=None, graph: bool = True,
-              fused_forward: bool = True, fused_step: bool = True):
+              fused_forward: bool = True, fused_step: bool = True, start_epoch: int = 0):
         """Minibatch Adam on the weighted MSE of standardised labels Y [n, 2].
 
         Each epoch's shuffled rows are gathered on the device into fixed
@@ -283,7 +324,13 @@ class Triage:
         minibatch in the two launches of shape_mlp_train_step (BF16 network
         of the default widths, batch a multiple of 64); else fused_forward:
         its features and forward in one kernel (shape_mlp_forward), then the
-        loss, backward and Adam calls.  All three give the same bits."""
+        loss, backward and Adam calls.  All three give the same bits.
+
+        start_epoch resumes a run (after load_state_dict of its checkpoint):
+        the shuffles of the epochs before it are drawn and skipped, so
+        train(epochs=a) + checkpoint + train(epochs=b, start_epoch=a) ends
+        with the bits of train(epochs=a + b) (the history returned covers
+        the resumed epochs)."""
         dev = self.eng.torch_device
         self.y_mean = Y.mean(0)
         self.y_std = Y.std(0)
@@ -292,6 +339,8 @@ class Triage:
         n = qidx.size
         nb = n // batch
         rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([int(seed), 0x7EA])))
+        for _ in range(int(start_epoch)):
+            rng.permutation(qidx.size)
         xb = torch.empty(batch, 96, dtype=torch.float32, device=dev)
         losses = torch.empty(max(nb, 1), dtype=torch.float32, device=dev)
         rows = nb * batch

@@ -550,3 +550,41 @@ def test_train_step_rejects_batches_off_its_grid(eng):
                            idx=torch.zeros(n, dtype=torch.int32, device="cuda"))
         assert e.value.code == -2
     assert int(net.step.item()) == 0
+
+
+def test_training_resumes_from_checkpoint(eng, tmp_path):
+    """Train a epochs, checkpoint to a file, load into a fresh triage object
+    (other initial weights) and train b more from start_epoch = a: the
+    parameters, Adam state and loss history equal those of a + b epochs in
+    one run, bit for bit."""
+    rng = np.random.default_rng(27)
+    n_q, n_l, n = 3, 700, 5000
+    f_q = rng.normal(size=(n_q, 24)).astype(np.float32)
+    f_l = rng.normal(size=(n_l, 24)).astype(np.float32)
+    f_q[:, 23] = rng.uniform(50, 100, n_q)
+    f_l[:, 23] = rng.uniform(50, 100, n_l)
+    fq, fl = torch.from_numpy(f_q).cuda(), torch.from_numpy(f_l).cuda()
+    qi, mi = rng.integers(0, n_q, n), rng.integers(0, n_l, n)
+    Y = rng.normal(size=(n, 2))
+    FO = rng.uniform(1, 40, n)
+    print("case: training, 3 epochs in one run", flush=True)
+    ref = Triage(eng, seed=6)
+    ref.fit_standardisation(fq, fl, qi, mi, fo=FO)
+    h_ref = ref.train(fq, fl, qi, mi, Y, fo=FO, epochs=3, batch=1024, lr=1e-3)
+    print("case: training, 2 epochs, checkpoint, 1 more", flush=True)
+    a = Triage(eng, seed=6)
+    a.fit_standardisation(fq, fl, qi, mi, fo=FO)
+    h_a = a.train(fq, fl, qi, mi, Y, fo=FO, epochs=2, batch=1024, lr=1e-3)
+    path = str(tmp_path / "triage.safetensors")
+    a.save(path)
+    b = Triage(eng, seed=7)
+    b.load(path)
+    h_b = b.train(fq, fl, qi, mi, Y, fo=FO, epochs=1, batch=1024, lr=1e-3, start_epoch=2)
+    assert h_a + h_b == h_ref
+    for x, y in ((b.mlp.params, ref.mlp.params), (b.mlp.m, ref.mlp.m), (b.mlp.v, ref.mlp.v),
+                 (b.mlp.step, ref.mlp.step), (b.mean, ref.mean), (b.inv_std, ref.inv_std)):
+        assert torch.equal(x, y)
+    bad = b.state_dict()
+    bad["params"] = bad["params"][:-1]
+    with pytest.raises(ValueError):
+        b.load_state_dict(bad)
