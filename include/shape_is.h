@@ -723,6 +723,15 @@ int shape_seed_budget(shape_ctx* ctx, const float* raw, int64_t ld, const int32_
  * SHAPE_E_HIP; SHAPE_E_UNSUPPORTED during graph capture. */
 int shape_peak_rates(shape_ctx* ctx, void* stream, double* rates);
 
+/* Named ranges for profiles (roctx): every entry point that launches work
+ * opens a range with its own name around its host work and launches; a
+ * caller can bracket stages of its own pipeline with shape_range_push(name)
+ * / shape_range_pop() (host strings, thread-local nesting).  Without an
+ * attached profiler these cost a few nanoseconds and record nothing.
+ * Errors: SHAPE_E_INVAL (NULL name). */
+int shape_range_push(const char* name);
+int shape_range_pop(void);
+
 /* Kernel timing (measurement support, not part of the method).  While
  * enabled, every call records a pair of HIP events on its stream around its
  * dominant kernel (the screening kernel of shape_screen, the sample kernel of

@@ -1,6 +1,7 @@
 // C-ABI layer of the IS shape-overlap engine: argument validation, context
 // scratch, launches.  No exception crosses the ABI.
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <math.h>
 #include <stdarg.h>
@@ -303,6 +304,15 @@ struct KernelTimer {
   }
 };
 
+// A named roctx range around one entry point's host work and launches (a
+// no-op unless a profiler listens), so traces attribute kernels to calls.
+struct ProfRange {
+  explicit ProfRange(const char* name) { roctxRangePushA(name); }
+  ~ProfRange() { roctxRangePop(); }
+  ProfRange(const ProfRange&) = delete;
+  ProfRange& operator=(const ProfRange&) = delete;
+};
+
 // Validation, molecule preparation and the query-side sample cache of a
 // screen; fills the kernel arguments (a->n_pairs = 0: nothing to launch).
 int screen_setup(shape_ctx* c, const shape_mols* query, const shape_mols* lib,
@@ -520,6 +530,7 @@ extern "C" {
 int shape_estimate(shape_ctx* c, const shape_mols* A, const shape_mols* B, int64_t n_a,
                    int64_t n_b, uint64_t seed, void* stream, shape_result* out) {
   if (!c) return SHAPE_E_INVAL;
+  ProfRange range_("shape_estimate");
   if (c->capturing) return refuse_in_capture(c, "shape_estimate");
   try {
     int rc;
@@ -565,6 +576,7 @@ int shape_estimate_noalloc(shape_ctx* c, const shape_mols* A, const shape_mols* 
                            int64_t n_a, int64_t n_b, uint64_t seed, void* stream,
                            shape_result* out) {
   if (!c) return SHAPE_E_INVAL;
+  ProfRange range_("shape_estimate_noalloc");
   if (c->capturing) return refuse_in_capture(c, "shape_estimate_noalloc");
   try {
     int rc;
@@ -626,6 +638,7 @@ int shape_sample_points(shape_ctx* c, const shape_mols* M, int32_t mol, int64_t 
                         uint64_t seed, void* stream, uint32_t* thr, uint32_t* words,
                         int32_t* comp, float* r) {
   if (!c) return SHAPE_E_INVAL;
+  ProfRange range_("shape_sample_points");
   if (c->capturing) return refuse_in_capture(c, "shape_sample_points");
   try {
     int rc;
@@ -660,6 +673,7 @@ int shape_screen(shape_ctx* c, const shape_mols* query, const shape_mols* lib,
                  const int32_t* pairs, int32_t n_pairs, const shape_screen_params* prm,
                  void* stream, const shape_screen_out* out) {
   if (!c) return SHAPE_E_INVAL;
+  ProfRange range_("shape_screen");
   try {
     hipStream_t st = (hipStream_t)stream;
     shape::ScreenArgs a;
@@ -757,6 +771,7 @@ int shape_screen_tune(shape_ctx* c, const shape_mols* query, const shape_mols* l
                       const int32_t* pairs, int32_t n_pairs, const shape_screen_params* prm,
                       void* stream, float* ms, int32_t* best) {
   if (!c) return SHAPE_E_INVAL;
+  ProfRange range_("shape_screen_tune");
   if (c->capturing) return refuse_in_capture(c, "shape_screen_tune");
   try {
     hipStream_t st = (hipStream_t)stream;
@@ -864,6 +879,7 @@ int32_t shape_screen_get_variant(const shape_ctx* c) { return c ? c->screen_vari
 int shape_self_overlap(shape_ctx* c, const shape_mols* M, int32_t n_samples, uint64_t seed,
                        void* stream, float* O_self) {
   if (!c) return SHAPE_E_INVAL;
+  ProfRange range_("shape_self_overlap");
   try {
     int rc;
     if ((rc = check_mols(c, M, "M", false))) return rc;
@@ -934,6 +950,7 @@ int shape_align_grad(shape_ctx* c, const shape_mols* A, const shape_mols* B, int
                      const float* pose, const float* O_aa, const float* O_bb, int32_t n_samples,
                      uint64_t seed, void* stream, float* T, float* dT_dpose) {
   if (!c) return SHAPE_E_INVAL;
+  ProfRange range_("shape_align_grad");
   try {
     int rc;
     if ((rc = align_check(c, A, B, n_starts, n_samples))) return rc;
@@ -975,6 +992,7 @@ int shape_align(shape_ctx* c, const shape_mols* A, const shape_mols* B, int32_t 
                 float* pose, int32_t n_samples, int32_t n_steps, float lr, uint64_t seed,
                 void* stream, float* T_final, int32_t* best) {
   if (!c) return SHAPE_E_INVAL;
+  ProfRange range_("shape_align");
   try {
     int rc;
     if ((rc = align_check(c, A, B, n_starts, n_samples))) return rc;
@@ -1049,6 +1067,7 @@ shape::MolsDev mols_dev(const shape_mols* m) {
 int shape_fo_starts(shape_ctx* c, const shape_mols* A, const shape_mols* B, int32_t n_random,
                     uint64_t seed, void* stream, float* pose) {
   if (!c) return SHAPE_E_INVAL;
+  ProfRange range_("shape_fo_starts");
   try {
     int rc;
     if ((rc = fo_pairs_check(c, A, B))) return rc;
@@ -1072,6 +1091,7 @@ int shape_fo_align(shape_ctx* c, const shape_mols* A, const shape_mols* B, int32
                    float* pose, int32_t n_steps, float lr, void* stream, float* T,
                    float* grad) {
   if (!c) return SHAPE_E_INVAL;
+  ProfRange range_("shape_fo_align");
   try {
     int rc;
     if ((rc = fo_pairs_check(c, A, B))) return rc;
@@ -1116,6 +1136,7 @@ int shape_best_pose(shape_ctx* c, int32_t n_pairs, int32_t n_starts, const float
 int shape_group_max(shape_ctx* c, const float* T, int64_t n_T, const int32_t* group_offset,
                     int32_t n_groups, void* stream, float* best_T, int32_t* best_idx) {
   if (!c) return SHAPE_E_INVAL;
+  ProfRange range_("shape_group_max");
   if (n_groups < 0 || n_T < 0) return fail(c, SHAPE_E_RANGE, "n_groups < 0 or n_T < 0");
   if (n_groups == 0) return SHAPE_OK;
   if (!group_offset || !best_T || (n_T > 0 && !T)) return fail(c, SHAPE_E_INVAL, "NULL array");
@@ -1142,6 +1163,7 @@ int shape_apply_pose(shape_ctx* c, const shape_mols* M, const float* pose, void*
 int shape_grid_integrals(shape_ctx* c, const shape_mols* A, const shape_mols* B, double h,
                          double pad, void* stream, double* out8) {
   if (!c) return SHAPE_E_INVAL;
+  ProfRange range_("shape_grid_integrals");
   if (c->capturing) return refuse_in_capture(c, "shape_grid_integrals");
   try {
     int rc;
@@ -1219,6 +1241,7 @@ int shape_grid_integrals(shape_ctx* c, const shape_mols* A, const shape_mols* B,
 
 int shape_features(shape_ctx* c, const shape_mols* M, void* stream, float* out) {
   if (!c) return SHAPE_E_INVAL;
+  ProfRange range_("shape_features");
   try {
     int rc;
     if ((rc = check_mols(c, M, "M", false))) return rc;
@@ -1240,6 +1263,7 @@ int shape_features(shape_ctx* c, const shape_mols* M, void* stream, float* out) 
 int shape_fo_overlap(shape_ctx* c, const shape_mols* query, const shape_mols* lib,
                      const int32_t* pairs, int32_t n_pairs, void* stream, float* out) {
   if (!c) return SHAPE_E_INVAL;
+  ProfRange range_("shape_fo_overlap");
   try {
     int rc;
     if ((rc = check_mols(c, query, "query", true))) return rc;
@@ -1264,6 +1288,7 @@ int shape_pair_features(shape_ctx* c, const float* f_q, const float* f_lib, cons
                         const int32_t* idx, int32_t n, const float* fo_cross, const float* mean,
                         const float* inv_std, void* stream, float* out) {
   if (!c) return SHAPE_E_INVAL;
+  ProfRange range_("shape_pair_features");
   if (n < 0) return fail(c, SHAPE_E_RANGE, "n < 0");
   if (n == 0) return SHAPE_OK;
   if (!f_q || !f_lib || !mean || !inv_std || !out) return fail(c, SHAPE_E_INVAL, "NULL array");
@@ -1279,6 +1304,7 @@ int shape_mlp_infer(shape_ctx* c, const float* f_q, const float* f_lib, const in
                     const int32_t* idx, int32_t n, const float* fo_cross, const float* mean,
                     const float* inv_std, const float* params, void* stream, float* out) {
   if (!c) return SHAPE_E_INVAL;
+  ProfRange range_("shape_mlp_infer");
   try {
     if (n < 0) return fail(c, SHAPE_E_RANGE, "n < 0");
     if (n == 0) return SHAPE_OK;
@@ -1304,6 +1330,7 @@ int shape_mlp_forward(shape_ctx* c, const float* f_q, const float* f_lib, const 
                       const float* inv_std, const float* params, void* stream, float* x,
                       float* h1, float* h2, float* h3, float* out) {
   if (!c) return SHAPE_E_INVAL;
+  ProfRange range_("shape_mlp_forward");
   try {
     if (n < 0) return fail(c, SHAPE_E_RANGE, "n < 0");
     if (n == 0) return SHAPE_OK;
@@ -1331,6 +1358,7 @@ int shape_seed_budget(shape_ctx* c, const float* raw, int64_t ld, const int32_t*
                       double y_mean, double y_std, double tau, int32_t round_per_pair,
                       int32_t cap_per_pair, void* stream, int32_t* n_start) {
   if (!c) return SHAPE_E_INVAL;
+  ProfRange range_("shape_seed_budget");
   if (k < 0) return fail(c, SHAPE_E_RANGE, "k < 0");
   if (k == 0) return SHAPE_OK;
   if (!raw || !n_start) return fail(c, SHAPE_E_INVAL, "NULL array");
@@ -1369,6 +1397,7 @@ int shape_gemm(shape_ctx* c, int32_t M, int32_t N, int32_t K, const float* A, in
 
 int shape_gemm_set(shape_ctx* c, int32_t n, const shape_gemm_desc* d, void* stream) {
   if (!c) return SHAPE_E_INVAL;
+  ProfRange range_("shape_gemm_set");
   if (n < 1 || n > shape::kGemmSetMax)
     return fail(c, SHAPE_E_RANGE, "n must be in 1..%d", shape::kGemmSetMax);
   if (!d) return fail(c, SHAPE_E_INVAL, "NULL descriptor array");
@@ -1414,6 +1443,7 @@ int shape_gemm_set(shape_ctx* c, int32_t n, const shape_gemm_desc* d, void* stre
 
 int shape_mlp_pack(shape_ctx* c, const float* params, void* stream, void* packed) {
   if (!c) return SHAPE_E_INVAL;
+  ProfRange range_("shape_mlp_pack");
   if (!params || !packed) return fail(c, SHAPE_E_INVAL, "NULL array");
   if ((uintptr_t)packed & 15u) return fail(c, SHAPE_E_INVAL, "packed must be 16-byte aligned");
   int rc = set_device(c);
@@ -1427,6 +1457,7 @@ int shape_mlp_train_step(shape_ctx* c, const float* f_q, const float* f_lib, con
                          const float* inv_std, const float* target, const float* loss_w,
                          const shape_mlp_adam* opt, void* stream, float* grad, float* loss) {
   if (!c) return SHAPE_E_INVAL;
+  ProfRange range_("shape_mlp_train_step");
   try {
     const int rows = shape::mlp_step_rows();
     if (n < rows || n > SHAPE_MLP_STEP_MAX_ROWS || n % rows)
@@ -1480,6 +1511,7 @@ int shape_mlp_backward(shape_ctx* c, int32_t n_layers, const int32_t* width, int
                        const float* params, const float* const* act, const float* dout,
                        uint32_t flags, void* stream, float* grad) {
   if (!c) return SHAPE_E_INVAL;
+  ProfRange range_("shape_mlp_backward");
   try {
     if (n_layers < 1 || n_layers > shape::kGemmSetMax)
       return fail(c, SHAPE_E_RANGE, "n_layers must be in 1..%d", shape::kGemmSetMax);
@@ -1574,6 +1606,7 @@ int shape_colsum_set(shape_ctx* c, int32_t n_mats, const int32_t* M, const int32
                      const float* const* A, const int64_t* lda, float* const* out,
                      void* stream) {
   if (!c) return SHAPE_E_INVAL;
+  ProfRange range_("shape_colsum_set");
   if (n_mats < 1 || n_mats > shape::kColSetMax)
     return fail(c, SHAPE_E_RANGE, "n_mats must be in 1..%d", shape::kColSetMax);
   if (!M || !N || !A || !lda || !out) return fail(c, SHAPE_E_INVAL, "NULL array");
@@ -1624,6 +1657,7 @@ int shape_adam(shape_ctx* c, float* p, const float* g, float* m, float* v, int64
 int shape_topk(shape_ctx* c, const float* score, int32_t n, int32_t k, void* stream,
                int32_t* idx) {
   if (!c) return SHAPE_E_INVAL;
+  ProfRange range_("shape_topk");
   if (n < 1 || k < 1 || k > n) return fail(c, SHAPE_E_RANGE, "need 1 <= k <= n");
   if (!score || !idx) return fail(c, SHAPE_E_INVAL, "NULL array");
   int rc = set_device(c);
@@ -1684,6 +1718,17 @@ int shape_peak_rates(shape_ctx* c, void* stream, double* rates) {
   } catch (...) {
     return fail(c, SHAPE_E_HIP, "internal error");
   }
+}
+
+int shape_range_push(const char* name) {
+  if (!name) return fail(nullptr, SHAPE_E_INVAL, "range name is NULL");
+  roctxRangePushA(name);
+  return SHAPE_OK;
+}
+
+int shape_range_pop(void) {
+  roctxRangePop();
+  return SHAPE_OK;
 }
 
 int shape_timing_enable(shape_ctx* c, int enable) {
@@ -1795,6 +1840,7 @@ int shape_graph_end(shape_ctx* c, void* stream, shape_graph** out) {
 
 int shape_graph_launch(shape_ctx* c, shape_graph* g, void* stream) {
   if (!c) return SHAPE_E_INVAL;
+  ProfRange range_("shape_graph_launch");
   if (!g || !g->exec) return fail(c, SHAPE_E_INVAL, "graph is NULL");
   if (g->life != c->life)
     return fail(c, SHAPE_E_INVAL, "the graph was captured on another context");

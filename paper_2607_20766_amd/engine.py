@@ -6,6 +6,7 @@ built (``python -m paper_2607_20766_amd.build``); there is no fallback.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
 import dataclasses
 import os
@@ -32,6 +33,19 @@ LAMBDA_P27 = 2.7 ** (-2.0 / 3.0)
 
 ERRORS = {-1: "SHAPE_E_INVAL", -2: "SHAPE_E_RANGE", -3: "SHAPE_E_NOMEM",
           -4: "SHAPE_E_HIP", -5: "SHAPE_E_UNSUPPORTED", -6: "SHAPE_E_DATA"}
+
+
+@contextlib.contextmanager
+def profile_range(name: str):
+    """A named roctx range (shape_range_push/pop) around a block of calls."""
+    L = load_library()
+    rc = L.shape_range_push(name.encode())
+    if rc != SHAPE_OK:
+        raise ShapeError(rc, L.shape_last_error(None).decode(errors="replace"))
+    try:
+        yield
+    finally:
+        L.shape_range_pop()
 
 
 def tune_cache_file(path: str | None):
@@ -124,6 +138,8 @@ def load_library():
                                    vp, i32, ctypes.POINTER(ShapeScreenParams), vp,
                                    ctypes.POINTER(ShapeScreenOut)]
         L.shape_check_data.argtypes = [vp, vp]
+        L.shape_range_push.argtypes = [ctypes.c_char_p]
+        L.shape_range_pop.argtypes = []
         L.shape_tune_cache_file.argtypes = [ctypes.c_char_p]
         L.shape_tune_cache_clear.argtypes = []
         L.shape_tune_cache_size.argtypes = []

@@ -21,7 +21,8 @@ import math
 import numpy as np
 import torch
 
-from .engine import SHAPE_MLP_STEP_MAX_ROWS, SHAPE_SCREEN_ADAPTIVE, Engine, Molecules
+from .engine import (SHAPE_MLP_STEP_MAX_ROWS, SHAPE_SCREEN_ADAPTIVE, Engine, Molecules,
+                     profile_range)
 
 WIDTH = (96, 256, 256, 256, 2)
 
@@ -316,8 +317,9 @@ class Triage:
               fused_forward: bool = True, fused_step: bool = True, start_epoch: int = 0):
         """Minibatch Adam on the weighted MSE of standardised labels Y [n, 2].
 
-        Each epoch's shuffled rows are gathered on the device into fixed
-        buffers, so after the first (eager) epoch the whole epoch of steps is
+        Each epoch's shuffle is drawn on the device (seeded generator) and
+        its rows gathered there into fixed buffers, so after the first
+        (eager) epoch the whole epoch of steps is
         captured once as a HIP graph and replayed (graph=True): identical
         kernels and results, without a host round trip per launch; the loss
         history is read once at the end.  fused_step: each
@@ -338,9 +340,11 @@ class Triage:
         lw = torch.ones(2, dtype=torch.float32, device=dev)
         n = qidx.size
         nb = n // batch
-        rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([int(seed), 0x7EA])))
+        # each epoch's shuffle is drawn on the device from a seeded generator
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(int(np.random.SeedSequence([int(seed), 0x7EA]).generate_state(1)[0]))
         for _ in range(int(start_epoch)):
-            rng.permutation(qidx.size)
+            torch.randperm(qidx.size, generator=gen, device=dev)
         xb = torch.empty(batch, 96, dtype=torch.float32, device=dev)
         losses = torch.empty(max(nb, 1), dtype=torch.float32, device=dev)
         rows = nb * batch
@@ -376,39 +380,30 @@ class Triage:
                     self.mlp.loss_grad(xb, y_ep[s:e], lw, losses[b:b + 1])
                 self.mlp.adam_step(lr)
 
-        # the training rows stay on the device; an epoch uploads only its
-        # permutation (pinned, double-buffered, so the host shuffles the next
-        # epoch while the device trains on this one) and gathers its rows
+        # the training rows stay on the device; an epoch draws its
+        # permutation there and gathers its rows
         q_all = torch.from_numpy(qidx.astype(np.int32)).to(dev)
         m_all = torch.from_numpy(midx.astype(np.int32)).to(dev)
         y_all = torch.from_numpy(np.ascontiguousarray(Ys)).to(dev)
         fo_all = (torch.from_numpy(np.ascontiguousarray(fo, np.float32)).to(dev)
                   if fo_ep is not None else None)
-        perm_host = [torch.empty(rows, dtype=torch.int64, pin_memory=True) for _ in range(2)]
-        perm_done = [None, None]
-        perm_dev = torch.empty(rows, dtype=torch.int64, device=dev)
         loss_hist = torch.empty(epochs, max(nb, 1), dtype=torch.float32, device=dev)
         g = None
         try:
             for ep in range(epochs):
-                buf = ep % 2
-                if perm_done[buf] is not None:
-                    perm_done[buf].synchronize()   # its previous copy has been read
-                perm_host[buf].numpy()[:] = rng.permutation(n)[:rows]
-                perm_dev.copy_(perm_host[buf], non_blocking=True)
-                perm_done[buf] = torch.cuda.Event()
-                perm_done[buf].record()
+                perm_dev = torch.randperm(n, generator=gen, device=dev)[:rows]
                 torch.index_select(q_all, 0, perm_dev, out=q_ep)
                 torch.index_select(m_all, 0, perm_dev, out=m_ep)
                 torch.index_select(y_all, 0, perm_dev, out=y_ep)
                 if fo_ep is not None:
                     torch.index_select(fo_all, 0, perm_dev, out=fo_ep)
-                if graph and ep > 0 and nb > 0:
-                    if g is None:
-                        g = self.eng.capture(epoch_steps, warmup=False)
-                    g.replay()
-                else:
-                    epoch_steps()
+                with profile_range(f"triage.epoch {start_epoch + ep}"):
+                    if graph and ep > 0 and nb > 0:
+                        if g is None:
+                            g = self.eng.capture(epoch_steps, warmup=False)
+                        g.replay()
+                    else:
+                        epoch_steps()
                 loss_hist[ep].copy_(losses)
                 if log:
                     log(f"epoch {ep}: loss {float(losses.cpu().numpy().mean()):.4f}")
@@ -481,15 +476,17 @@ class Triage:
             bufs = self.screen_buffers(n, frac)
         assert bufs["n"] == n
         k = bufs["k"]
-        fo = (self.eng.shape_fo_overlap(query, lib, out=bufs["fo"]) if self.use_fo else None)
-        raw = self.predict_raw(f_q, f_lib, fo, out=bufs["raw"])
-        bufs["score"].copy_(raw[:, 0])
-        top = self.eng.shape_topk(bufs["score"], k, out=bufs["top"])
-        budget = self.eng.shape_seed_budget(raw, self.y_mean[1], self.y_std[1], self.tau,
-                                            self.round_per_pair, self.cap_per_pair, idx=top,
-                                            out=bufs["budget"])
-        out = self.eng.shape_screen(query, lib, mode=SHAPE_SCREEN_ADAPTIVE, pairs=top,
-                                    round_per_pair=self.round_per_pair,
-                                    cap_per_pair=self.cap_per_pair, tau=self.tau, seed=seed,
-                                    n_start=budget, out=bufs["out"])
+        with profile_range("triage.screen"):
+            fo = (self.eng.shape_fo_overlap(query, lib, out=bufs["fo"]) if self.use_fo
+                  else None)
+            raw = self.predict_raw(f_q, f_lib, fo, out=bufs["raw"])
+            bufs["score"].copy_(raw[:, 0])
+            top = self.eng.shape_topk(bufs["score"], k, out=bufs["top"])
+            budget = self.eng.shape_seed_budget(raw, self.y_mean[1], self.y_std[1], self.tau,
+                                                self.round_per_pair, self.cap_per_pair,
+                                                idx=top, out=bufs["budget"])
+            out = self.eng.shape_screen(query, lib, mode=SHAPE_SCREEN_ADAPTIVE, pairs=top,
+                                        round_per_pair=self.round_per_pair,
+                                        cap_per_pair=self.cap_per_pair, tau=self.tau,
+                                        seed=seed, n_start=budget, out=bufs["out"])
         return top, out, raw

@@ -73,3 +73,14 @@ def test_create_without_device_reports_hip_error():
     assert rc == -4
     assert not ctx
     assert b"device" in lib.shape_last_error(None)
+
+
+def test_profile_ranges_without_a_profiler():
+    """The roctx ranges cost nothing and record nothing without a profiler;
+    a NULL name is refused."""
+    from paper_2607_20766_amd.engine import load_library, profile_range
+    lib = load_library()
+    with profile_range("outer"):
+        with profile_range("inner"):
+            pass
+    assert lib.shape_range_push(None) == -1
