@@ -622,10 +622,10 @@ typedef struct shape_mlp_adam {
  * same arithmetic, so the same bits in params, m, v, step, grad and loss as
  * that sequence of calls.  Two kernel launches: the forward and the
  * row-local part of the backward (ReLU-gated input gradients, 32-row chunk
- * sums of the bias gradients, the loss terms) for 64 rows per workgroup;
+ * sums of the bias gradients, the loss terms) for 32 rows per workgroup;
  * then the weight gradients in shape_gemm_set's split-K chunks, the bias
  * sums, the loss, Adam and the packing of the new weights.
- *   n      rows, a multiple of 64 in [64, SHAPE_MLP_STEP_MAX_ROWS]
+ *   n      rows, a multiple of 32 in [32, SHAPE_MLP_STEP_MAX_ROWS]
  *   opt    optimiser state; opt->packed must hold shape_mlp_pack(opt->params)
  *          (a previous step leaves it so)
  *   grad   device float [n_params] dloss/dparams of this step, or NULL

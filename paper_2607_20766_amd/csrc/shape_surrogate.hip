@@ -741,12 +741,14 @@ constexpr int kTrLdf = kMlpHid + 4;   // FP32 staging row stride (floats)
 template <int ROWS, bool kAct, bool kF>
 __device__ __forceinline__ void mlp_stage_features(const MlpArgs& a, int row0, short* H,
                                                    float* F) {
-  constexpr int NH = 256 / ROWS;   // threads per row in the feature staging
+  // threads per row (the first NH x ROWS threads of the workgroup take part)
+  constexpr int NH = ROWS >= 64 ? 256 / ROWS : 4;
   constexpr int BPT = 4 / NH;      // feature blocks of 24 per thread
   constexpr int FPT = 24 * BPT;    // features per thread
   const int tid = threadIdx.x;
   const int r = tid & (ROWS - 1);
-  const int h = __builtin_amdgcn_readfirstlane(tid / ROWS);
+  // the part is uniform per wave when ROWS >= 64 (then scalar statistics)
+  const int h = ROWS >= 64 ? __builtin_amdgcn_readfirstlane(tid / ROWS) : tid / ROWS;
   const int p = row0 + r;
   float raw[FPT];
   if (p < a.n) {
@@ -1142,7 +1144,7 @@ __global__ void k_step_bump(int* step) {
 // arithmetic of shape_mlp_forward, shape_mse, shape_mlp_backward (BF16) and
 // shape_adam, so the same bits:
 //
-//   k_mlp_train, one workgroup per 64 rows: the forward of k_mlp_infer; the
+//   k_mlp_train, one workgroup per 32 rows: the forward of k_mlp_infer; the
 //   MSE gradient and k_mse's per-wave loss sums; the input-gradient chain
 //   g_2 = (g_3 W_3^T) . [h3 > 0], g_1, g_0 as transposed products on the
 //   matrix cores (weights as the A operand, the previous gradient in LDS as
@@ -1164,7 +1166,7 @@ __global__ void k_step_bump(int* step) {
 // 8 values, lane = 16 (o%32 / 8) + i%16, value o%8; W_3's two outputs are
 // padded to 32 with zeros.  Stored after the forward packing.
 // ---------------------------------------------------------------------------
-constexpr int kTrRows = 64;   // minibatch rows per workgroup of k_mlp_train
+constexpr int kTrRows = 32;   // minibatch rows per workgroup of k_mlp_train (32 or 64)
 
 // Layout of the bf16 columns of a layer's inputs or gradients (width w, n
 // rows): blocks of kColRows rows, each holding every feature's 32 rows
@@ -1319,15 +1321,20 @@ __device__ __forceinline__ void load_bias(const float* __restrict__ b, int wave,
     bc[j] = *reinterpret_cast<const float4*>(b + wave * 32 + 16 * j + 4 * lk);
 }
 
+template <int ROWS>
 __global__ __launch_bounds__(kTrThreads, 1) void k_mlp_train(MlpTrainArgs a) {
-  constexpr int RB = kTrRows / 16;
-  __shared__ __align__(16) short H[kTrRows * kMlpLd];
-  __shared__ __align__(16) float F[kTrRows * kTrLdf];
+  constexpr int RB = ROWS / 16;                // row blocks of 16
+  constexpr int kHalves = ROWS / kColRows;     // 32-row chunks
+  constexpr int kStage = (ROWS >= 64 ? 256 / ROWS : 4) * ROWS;  // feature-staging threads
+  __shared__ __align__(16) short H[ROWS * kMlpLd];
+  __shared__ __align__(16) float F[ROWS * kTrLdf];
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
   const int li = lane & 15, lk = lane >> 4;
-  const int row0 = blockIdx.x * kTrRows;
+  const int row0 = blockIdx.x * ROWS;
   const int n = a.f.n;
-  const int col = tid & (kMlpHid - 1), half = tid / kMlpHid;  // column pass: column, chunk
+  // column pass: thread (col, half) takes rows [32 half, 32 half + 32) of one column
+  const int col = tid & (kMlpHid - 1), half = tid / kMlpHid;
+  const bool col_pass = half < kHalves;
   const v8s* __restrict__ W = a.f.W;
   // the step number the update kernel's Adam uses (nothing else reads it here)
   if (blockIdx.x == 0 && tid == 0) *a.step += 1;
@@ -1337,9 +1344,9 @@ __global__ __launch_bounds__(kTrThreads, 1) void k_mlp_train(MlpTrainArgs a) {
   float4 bc[2];
   mlp_frags_load<kMlpIn / 32>(W + mlp_pack_offset(0) / 8, wave, lane, w);
   load_bias(a.f.b[0], wave, lane, bc);
-  if (tid < 256) mlp_stage_features<kTrRows, false, true>(a.f, row0, H, F);
+  if (tid < kStage) mlp_stage_features<ROWS, false, true>(a.f, row0, H, F);
   __syncthreads();
-  if (col < kMlpIn)
+  if (col_pass && col < kMlpIn)
     mlp_column_out(F, col, half, a.actT[0] + mlp_blk_index(kMlpIn, col, row0 + kColRows * half),
                    nullptr);
   // forward: hidden layers as in k_mlp_infer; the ReLU gates as bits of
@@ -1352,7 +1359,8 @@ __global__ __launch_bounds__(kTrThreads, 1) void k_mlp_train(MlpTrainArgs a) {
   gate[0] = train_hidden_out<RB>(acc, bc, H, F, wave, lane);
   load_bias(a.f.b[1], wave, lane, bc);
   __syncthreads();
-  mlp_column_out(F, col, half, a.actT[1] + mlp_blk_index(kMlpHid, col, row0 + kColRows * half),
+  if (col_pass)
+    mlp_column_out(F, col, half, a.actT[1] + mlp_blk_index(kMlpHid, col, row0 + kColRows * half),
                  nullptr);
   mlp_frags_mfma<RB, 8>(w, H, lane, acc);
   mlp_frags_load<8>(W + mlp_pack_offset(2) / 8, wave, lane, w);
@@ -1360,26 +1368,28 @@ __global__ __launch_bounds__(kTrThreads, 1) void k_mlp_train(MlpTrainArgs a) {
   gate[1] = train_hidden_out<RB>(acc, bc, H, F, wave, lane);
   load_bias(a.f.b[2], wave, lane, bc);
   __syncthreads();
-  mlp_column_out(F, col, half, a.actT[2] + mlp_blk_index(kMlpHid, col, row0 + kColRows * half),
+  if (col_pass)
+    mlp_column_out(F, col, half, a.actT[2] + mlp_blk_index(kMlpHid, col, row0 + kColRows * half),
                  nullptr);
   mlp_frags_mfma<RB, 8>(w, H, lane, acc);
-  // output layer fragments (waves 0-3: one block of 16 rows each)
+  // output layer fragments (one wave per block of 16 rows)
   v8s wo[8];
-  if (wave < 4) {
+  if (wave < RB) {
 #pragma unroll
     for (int kb = 0; kb < 8; ++kb) wo[kb] = W[mlp_pack_offset(3) / 8 + kb * kWave + lane];
   }
   __syncthreads();
   gate[2] = train_hidden_out<RB>(acc, bc, H, F, wave, lane);
   __syncthreads();
-  mlp_column_out(F, col, half, a.actT[3] + mlp_blk_index(kMlpHid, col, row0 + kColRows * half),
+  if (col_pass)
+    mlp_column_out(F, col, half, a.actT[3] + mlp_blk_index(kMlpHid, col, row0 + kColRows * half),
                  nullptr);
   // output layer (mlp_out_mfma's products), then dloss/dy = g_3 and the loss
   // terms (e = y - t)
   {
     v4f ao = v4f{0.f, 0.f, 0.f, 0.f};
     float tg[4] = {0.f, 0.f, 0.f, 0.f};
-    if (wave < 4) {
+    if (wave < RB) {
       if (li < kMlpOut) {
 #pragma unroll
         for (int r = 0; r < 4; ++r)
@@ -1394,7 +1404,7 @@ __global__ __launch_bounds__(kTrThreads, 1) void k_mlp_train(MlpTrainArgs a) {
     }
     mlp_frags_load<1>(W + mlp_packT_offset(3) / 8, wave, lane, w);
     __syncthreads();  // H and F free
-    if (wave < 4 && li < kMlpOut) {
+    if (wave < RB && li < kMlpOut) {
       const float b3 = a.f.b[3][li];
       const float wl = a.lw[li];
 #pragma unroll
@@ -1406,19 +1416,19 @@ __global__ __launch_bounds__(kTrThreads, 1) void k_mlp_train(MlpTrainArgs a) {
       }
     }
     __syncthreads();
-    if (tid < 256) {  // g_3 as the chain's B operand: one k-block, zero past the 2 outputs
+    if (tid < 4 * ROWS) {  // g_3 as the chain's B operand: one k-block, zero past 2 outputs
       const int row = tid >> 2, q = tid & 3;
       uint4 v = make_uint4(0u, 0u, 0u, 0u);
       if (q == 0) v.x = to_bf16x2(F[row * kTrLdf], F[row * kTrLdf + 1]);
       *reinterpret_cast<uint4*>(&H[row * kMlpLd + 8 * q]) = v;
     }
-    if (tid < 2 * kWave) {
+    if (tid < 2 * ROWS) {
       // k_mse's loss sums: its wave covers 32 rows, lane 2 (row % 32) + j
       const int row = tid >> 1, j = tid & 1;
       double l = mse_loss(a.lw[j], F[row * kTrLdf + kMlpOut + j], n);
       l = wave_sum(l);
       if (lane == 0) a.loss_part[row0 / kColRows + wave] = l;
-    } else if (tid >= 256 && tid < 256 + 4) {
+    } else if (tid >= 256 && tid < 256 + 2 * kHalves) {
       const int j = tid & 1, h = (tid - 256) >> 1;
       mlp_column_out(F, j, h, a.gT[3] + mlp_blk_index(kMlpOut, j, row0 + kColRows * h),
                      a.bsum[3] + (row0 / kColRows + h) * kMlpOut + j);
@@ -1431,20 +1441,23 @@ __global__ __launch_bounds__(kTrThreads, 1) void k_mlp_train(MlpTrainArgs a) {
   __syncthreads();
   train_chain_out<RB>(acc, gate[2], true, H, F, wave, lane);
   __syncthreads();
-  mlp_column_out(F, col, half, a.gT[2] + mlp_blk_index(kMlpHid, col, row0 + kColRows * half),
+  if (col_pass)
+    mlp_column_out(F, col, half, a.gT[2] + mlp_blk_index(kMlpHid, col, row0 + kColRows * half),
                  a.bsum[2] + (size_t)(row0 / kColRows + half) * kMlpHid + col);
   mlp_frags_mfma<RB, 8>(w, H, lane, acc);
   mlp_frags_load<8>(W + mlp_packT_offset(1) / 8, wave, lane, w);
   __syncthreads();
   train_chain_out<RB>(acc, gate[1], true, H, F, wave, lane);
   __syncthreads();
-  mlp_column_out(F, col, half, a.gT[1] + mlp_blk_index(kMlpHid, col, row0 + kColRows * half),
+  if (col_pass)
+    mlp_column_out(F, col, half, a.gT[1] + mlp_blk_index(kMlpHid, col, row0 + kColRows * half),
                  a.bsum[1] + (size_t)(row0 / kColRows + half) * kMlpHid + col);
   mlp_frags_mfma<RB, 8>(w, H, lane, acc);
   __syncthreads();
   train_chain_out<RB>(acc, gate[0], false, H, F, wave, lane);
   __syncthreads();
-  mlp_column_out(F, col, half, a.gT[0] + mlp_blk_index(kMlpHid, col, row0 + kColRows * half),
+  if (col_pass)
+    mlp_column_out(F, col, half, a.gT[0] + mlp_blk_index(kMlpHid, col, row0 + kColRows * half),
                  a.bsum[0] + (size_t)(row0 / kColRows + half) * kMlpHid + col);
 }
 
@@ -2180,7 +2193,8 @@ hipError_t launch_mlp_step(const MlpStep& s, void* scratch, hipStream_t st) {
   ua.grad = s.grad;
   ua.packed = (short*)s.packed;
   ua.loss = s.loss;
-  hipLaunchKernelGGL(k_mlp_train, dim3((unsigned)(n / kTrRows)), dim3(kTrThreads), 0, st, ta);
+  hipLaunchKernelGGL(k_mlp_train<kTrRows>, dim3((unsigned)(n / kTrRows)), dim3(kTrThreads), 0, st,
+                     ta);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_mlp_update, dim3((unsigned)blocks), dim3(kUpdThreads), 0, st, ua);

@@ -125,8 +125,8 @@ class MLP:
 
     def fused_step_ok(self, batch: int) -> bool:
         """Whether shape_mlp_train_step takes this network and batch."""
-        return (self.bf16 and self.width == WIDTH and batch % 64 == 0
-                and 64 <= batch <= SHAPE_MLP_STEP_MAX_ROWS)
+        return (self.bf16 and self.width == WIDTH and batch % 32 == 0
+                and 32 <= batch <= SHAPE_MLP_STEP_MAX_ROWS)
 
     def pack(self):
         """Pack the current parameters for train_step (after any change to
@@ -324,7 +324,7 @@ class Triage:
         kernels and results, without a host round trip per launch; the loss
         history is read once at the end.  fused_step: each
         minibatch in the two launches of shape_mlp_train_step (BF16 network
-        of the default widths, batch a multiple of 64); else fused_forward:
+        of the default widths, batch a multiple of 32); else fused_forward:
         its features and forward in one kernel (shape_mlp_forward), then the
         loss, backward and Adam calls.  All three give the same bits.
 

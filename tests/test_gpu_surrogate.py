@@ -493,7 +493,7 @@ def test_mlp_backward_equals_layer_calls(eng, width, B, bf16):
         eng.shape_mlp_backward(width, params, acts[:-1], dout, got)
 
 
-@pytest.mark.parametrize("n", [64, 576, 1024, 4096, 8192])
+@pytest.mark.parametrize("n", [32, 64, 576, 1024, 4096, 8192])
 def test_train_step_equals_calls(eng, n):
     """shape_mlp_train_step against shape_mlp_forward, shape_mse,
     shape_mlp_backward and shape_adam over three consecutive steps: loss,
@@ -501,7 +501,7 @@ def test_train_step_equals_calls(eng, n):
     for bit.  Batches of one workgroup, of a half-filled last loss block
     (576 rows, ragged split-K chunks), of single-chunk weight gradients (64),
     of the training batch (4096) and beyond it (8192: split-K chunks that
-    differ between layers)."""
+    differ between layers), and a single 32-row workgroup."""
     rng = np.random.default_rng(50 + n)
     n_q, n_l = 3, 20000
     f_q = rng.normal(size=(n_q, 24)).astype(np.float32)
@@ -544,7 +544,7 @@ def test_train_step_rejects_batches_off_its_grid(eng):
     fl = torch.ones(100, 24, device="cuda")
     mean, inv_std = torch.zeros(96, device="cuda"), torch.ones(96, device="cuda")
     lw = torch.ones(2, device="cuda")
-    for n in (100, 32):
+    for n in (100, 16):
         with pytest.raises(ShapeError) as e:
             net.train_step(fq, fl, mean, inv_std, torch.zeros(n, 2, device="cuda"), lw, 1e-3,
                            idx=torch.zeros(n, dtype=torch.int32, device="cuda"))
