@@ -1538,9 +1538,10 @@ int shape_mlp_backward(shape_ctx* c, int32_t n_layers, const int32_t* width, int
     for (int l = 0; l < n_layers; ++l)
       off[l + 1] = off[l] + (int64_t)width[l] * width[l + 1] + width[l + 1];
     int64_t d_off[shape::kGemmSetMax];
-    for (int l = 1, o = 0; l < n_layers; ++l) {
+    int64_t o = 0;
+    for (int l = 1; l < n_layers; ++l) {
       d_off[l] = o;
-      o += (int)((int64_t)batch * width[l]);
+      o += (int64_t)batch * width[l];
     }
     shape_gemm_desc wg[shape::kGemmSetMax];
     int32_t cM[shape::kColSetMax], cN[shape::kColSetMax];
