@@ -493,7 +493,7 @@ def test_mlp_backward_equals_layer_calls(eng, width, B, bf16):
         eng.shape_mlp_backward(width, params, acts[:-1], dout, got)
 
 
-@pytest.mark.parametrize("n", [32, 64, 576, 1024, 4096, 8192])
+@pytest.mark.parametrize("n", [32, 64, 576, 1024, 4096, 4128, 8192, 65536])
 def test_train_step_equals_calls(eng, n):
     """shape_mlp_train_step against shape_mlp_forward, shape_mse,
     shape_mlp_backward and shape_adam over three consecutive steps: loss,
@@ -501,7 +501,10 @@ def test_train_step_equals_calls(eng, n):
     for bit.  Batches of one workgroup, of a half-filled last loss block
     (576 rows, ragged split-K chunks), of single-chunk weight gradients (64),
     of the training batch (4096) and beyond it (8192: split-K chunks that
-    differ between layers), and a single 32-row workgroup."""
+    differ between layers), a single 32-row workgroup, 4,128 rows (a
+    loss block of one 32-row wave; 26 split-K chunks of 160 rows, the last
+    one shorter) and the largest batch (up to 128 chunks per weight tile,
+    bias and loss sums over several staging passes)."""
     rng = np.random.default_rng(50 + n)
     n_q, n_l = 3, 20000
     f_q = rng.normal(size=(n_q, 24)).astype(np.float32)
