@@ -217,3 +217,25 @@ def test_adaptive_seeded_budgets(eng, small_lib):
                        seed=3, n_start=n_start)
     assert np.all(g["n_used"] >= np.minimum(n_start, 16384))
     compare_adaptive(g, r, q, L, 0.005, 16384, 3, QUERY_ID, min_same=0.95)
+
+
+def test_screen_resumes_from_checkpoint(eng, tmp_path):
+    """An adaptive screen run in chunks of pairs, interrupted after two
+    chunks and resumed from its state file, equals one whole-library screen
+    bit for bit; a state file of another screen is refused."""
+    from paper_2607_20766_amd.resume import screen_in_chunks
+    q = molgen.molecule(1, 0, 30)
+    L = molgen.library(23, 1000, 10, 50, workers=1)
+    Q = eng.molecules(q, mol_id=[QUERY_ID])
+    lib = eng.molecules(L)
+    kw = dict(mode=SHAPE_SCREEN_ADAPTIVE, round_per_pair=512, cap_per_pair=8192, tau=0.005,
+              seed=8)
+    full = _to_np(eng.shape_screen(Q, lib, **kw))
+    path = str(tmp_path / "screen.safetensors")
+    print("case: chunked screen, interrupted after two chunks", flush=True)
+    assert screen_in_chunks(eng, Q, lib, 300, path, stop_after=2, **kw) is None
+    out = screen_in_chunks(eng, Q, lib, 300, path, **kw)
+    for k in full:
+        assert np.array_equal(out[k], full[k]), k
+    with pytest.raises(ValueError):
+        screen_in_chunks(eng, Q, lib, 300, path, **dict(kw, seed=9))
