@@ -723,6 +723,12 @@ int shape_seed_budget(shape_ctx* ctx, const float* raw, int64_t ld, const int32_
  * SHAPE_E_HIP; SHAPE_E_UNSUPPORTED during graph capture. */
 int shape_peak_rates(shape_ctx* ctx, void* stream, double* rates);
 
+/* Failure injection for tests of error handling: the next n scratch
+ * allocations of ctx fail as if the device were out of memory (the call
+ * returns SHAPE_E_NOMEM; the context stays usable and its earlier scratch
+ * stays valid); n = 0 turns it off.  Errors: SHAPE_E_INVAL, SHAPE_E_RANGE. */
+int shape_fail_allocations(shape_ctx* ctx, int32_t n);
+
 /* Named ranges for profiles (roctx): every entry point that launches work
  * opens a range with its own name around its host work and launches; a
  * caller can bracket stages of its own pipeline with shape_range_push(name)

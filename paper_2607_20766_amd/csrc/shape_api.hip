@@ -71,6 +71,7 @@ struct shape_ctx {
   std::shared_ptr<GraphLife> life;
   int n_cu = 0;
   char arch[64] = {0};          // gcnArchName of the device
+  int fail_allocs = 0;          // scratch allocations still to refuse (failure injection)
   size_t lds_per_block = 0;
   std::string err;
   Buffer buf[S_COUNT];
@@ -174,6 +175,11 @@ int ensure(shape_ctx* c, Slot s, size_t bytes, void** out) {
       return fail(c, SHAPE_E_UNSUPPORTED,
                   "scratch would grow during graph capture: make the same calls once "
                   "before capturing");
+    if (c->fail_allocs > 0) {  // injected failure: the slot keeps its old buffer
+      --c->fail_allocs;
+      return fail(c, SHAPE_E_NOMEM, "scratch allocation of %zu bytes refused (injected)",
+                  bytes);
+    }
     if (b.ptr) {
       std::lock_guard<std::mutex> lk(c->life->m);
       if (c->life->live > 0) {
@@ -1719,6 +1725,13 @@ int shape_peak_rates(shape_ctx* c, void* stream, double* rates) {
   } catch (...) {
     return fail(c, SHAPE_E_HIP, "internal error");
   }
+}
+
+int shape_fail_allocations(shape_ctx* c, int32_t n) {
+  if (!c) return SHAPE_E_INVAL;
+  if (n < 0) return fail(c, SHAPE_E_RANGE, "n < 0");
+  c->fail_allocs = n;
+  return SHAPE_OK;
 }
 
 int shape_range_push(const char* name) {

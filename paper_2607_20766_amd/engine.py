@@ -138,6 +138,7 @@ def load_library():
                                    vp, i32, ctypes.POINTER(ShapeScreenParams), vp,
                                    ctypes.POINTER(ShapeScreenOut)]
         L.shape_check_data.argtypes = [vp, vp]
+        L.shape_fail_allocations.argtypes = [vp, i32]
         L.shape_range_push.argtypes = [ctypes.c_char_p]
         L.shape_range_pop.argtypes = []
         L.shape_tune_cache_file.argtypes = [ctypes.c_char_p]
@@ -508,6 +509,11 @@ class Engine:
         """Reuse the preparation of an unchanged molecule set across calls
         (see shape_prepare_cache); enabling also forgets earlier ones."""
         self._check(load_library().shape_prepare_cache(self._ctx, int(enable)))
+
+    def fail_allocations(self, n: int):
+        """Make the next n scratch allocations of this context fail as out of
+        memory (shape_fail_allocations; tests of error handling)."""
+        self._check(load_library().shape_fail_allocations(self._ctx, int(n)))
 
     def screen_variant(self, variant: int | None = None) -> int:
         """Select the screening tile variant (-1 = default) if given; return

@@ -239,3 +239,30 @@ def test_screen_resumes_from_checkpoint(eng, tmp_path):
         assert np.array_equal(out[k], full[k]), k
     with pytest.raises(ValueError):
         screen_in_chunks(eng, Q, lib, 300, path, **dict(kw, seed=9))
+
+
+def test_allocation_failure_is_reported_and_recovered(eng):
+    """An injected out-of-memory failure of a fresh context's scratch comes
+    back as SHAPE_E_NOMEM without a launch that could use the missing
+    buffer; the same context then screens normally, to the bits of another
+    context, and so does a failure in the middle of its preparations."""
+    from paper_2607_20766_amd.engine import ShapeError
+    q = molgen.molecule(1, 0, 30)
+    L = molgen.library(24, 300, 10, 50, workers=1)
+    Q = eng.molecules(q, mol_id=[QUERY_ID])
+    lib = eng.molecules(L)
+    kw = dict(mode=SHAPE_SCREEN_ADAPTIVE, round_per_pair=512, cap_per_pair=8192, seed=2)
+    want = _to_np(eng.shape_screen(Q, lib, **kw))
+    for n_fail in (1, 3):
+        e2 = Engine(0)
+        e2.fail_allocations(n_fail)
+        print(f"case: {n_fail} injected allocation failures", flush=True)
+        for _ in range(n_fail):
+            with pytest.raises(ShapeError) as err:
+                e2.shape_screen(Q, lib, **kw)
+            assert err.value.code == -3
+        got = _to_np(e2.shape_screen(Q, lib, **kw))
+        for k in want:
+            assert np.array_equal(got[k], want[k]), k
+    with pytest.raises(ShapeError):
+        eng.fail_allocations(-1)
