@@ -242,10 +242,10 @@ def test_screen_resumes_from_checkpoint(eng, tmp_path):
 
 
 def test_allocation_failure_is_reported_and_recovered(eng):
-    """An injected out-of-memory failure of a fresh context's scratch comes
-    back as SHAPE_E_NOMEM without a launch that could use the missing
-    buffer; the same context then screens normally, to the bits of another
-    context, and so does a failure in the middle of its preparations."""
+    """Injected out-of-memory failures of a fresh context's scratch (one,
+    then three calls in a row) come back as SHAPE_E_NOMEM without a launch
+    that could use the missing buffer; the same context then screens
+    normally, to the bits of another context."""
     from paper_2607_20766_amd.engine import ShapeError
     q = molgen.molecule(1, 0, 30)
     L = molgen.library(24, 300, 10, 50, workers=1)
