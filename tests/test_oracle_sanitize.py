@@ -1,4 +1,4 @@
-"""The FP64 oracle judges every parity claim, and it indexes and allocates by
+"""The FP64 oracle is the reference of every parity claim, and it indexes and allocates by
 hand: build it with AddressSanitizer and UndefinedBehaviorSanitizer (gcc,
 host code only) and run oracle/sanitize_driver.c, which calls every entry
 point that allocates or indexes on small molecules, including adaptive
