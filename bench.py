@@ -41,6 +41,7 @@ N_FIXED = 4096
 # and one exponential, which is not counted as a flop.  Peak: the published
 # FP32 vector rate of the MI355X, 157.3 TFLOP/s.
 FLOPS_PER_EVAL = 13
+PEAK_BF16_TFLOPS = 2500.0   # dense BF16 matrix-core peak of MI355X
 PEAK_FP32_TFLOPS = 157.3
 # Per launch of the adaptive screening kernel on this workload (deterministic
 # for a given kernel build), from the rocprofv3 summaries in profiles/:
@@ -338,6 +339,47 @@ def bench_ensemble(eng, Q, n_mols=5000, n_conf=10):
     return res
 
 
+def train_step_timing(eng, f_q, f_lib, tr, batch=4096, steps=64):
+    """Kernel time of one fused training step (its two launches, HIP events
+    around the call) on a scratch network with the trained statistics, and
+    its BF16 products against the dense MFMA peak."""
+    import torch
+
+    from paper_2607_20766_amd.surrogate import MLP, WIDTH, init_params
+    dev = eng.torch_device
+    net = MLP(eng, init_params(1))
+    net.pack()
+    g = torch.Generator(device=dev)
+    g.manual_seed(5)
+    qi = torch.randint(0, f_q.shape[0], (batch,), generator=g, device=dev, dtype=torch.int32)
+    mi = torch.randint(0, f_lib.shape[0], (batch,), generator=g, device=dev, dtype=torch.int32)
+    y = torch.randn(batch, 2, generator=g, device=dev)
+    fo = torch.rand(batch, generator=g, device=dev) * 40
+    lw = torch.ones(2, device=dev)
+    for _ in range(4):
+        net.train_step(f_q, f_lib, tr.mean, tr.inv_std, y, lw, 1e-3, idx=mi, qidx=qi, fo_cross=fo)
+    eng.shape_timing_enable(True)
+    eng.shape_timing_read(reset=True)
+    for _ in range(steps):
+        net.train_step(f_q, f_lib, tr.mean, tr.inv_std, y, lw, 1e-3, idx=mi, qidx=qi, fo_cross=fo)
+    torch.cuda.synchronize()
+    kern_ms, launches = eng.shape_timing_read(reset=True)
+    eng.shape_timing_enable(False)
+    step_us = kern_ms / max(launches, 1) * 1e3
+    # multiply-adds per row: forward, input gradients (layers 3..1), weight gradients
+    macs = sum(i * o for i, o in zip(WIDTH[:-1], WIDTH[1:]))
+    macs_in = sum(i * o for i, o in zip(WIDTH[1:-1], WIDTH[2:]))
+    flops = 2.0 * batch * (2 * macs + macs_in)
+    achieved = flops / (step_us * 1e-6) / 1e12
+    return {"batch": batch, "kernel_us_per_step": step_us, "launches_per_step": 2,
+            "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_TFLOPS,
+                         "unit": "TFLOP/s", "frac": achieved / PEAK_BF16_TFLOPS,
+                         "flops_per_step": flops,
+                         "note": "BF16 products of one step (forward, input gradients, weight "
+                                 "gradients) / kernel time of its two launches, against the "
+                                 "dense BF16 matrix-core peak"}}
+
+
 def bench_triage(eng, n_lib, n_queries=256, n_train_lib=3907, epochs=10):
     """Learned triage: a BF16 MLP trained on ~10^6 IS-labelled pairs (256
     queries x 3907 molecules) ranks an n_lib-molecule library against a
@@ -373,6 +415,7 @@ def bench_triage(eng, n_lib, n_queries=256, n_train_lib=3907, epochs=10):
     hist = tr.train(f_q, f_lib_t, qi, mi, Y, fo=FO, epochs=epochs, batch=4096, lr=1e-3)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
+    step = train_step_timing(eng, f_q, f_lib_t, tr)
 
     log(f"triage: {n_lib}-molecule library")
     qt = molgen.molecule(5, 0, 30)
@@ -491,6 +534,7 @@ def bench_triage(eng, n_lib, n_queries=256, n_train_lib=3907, epochs=10):
         "spearman_surrogate_vs_is": float(scipy.stats.spearmanr(T_hat, T_plain)[0]),
         "recall_top1pct_within_fo_tanimoto_top5pct": len(true_top & fo_top) / k1,
         "train_s": t_train,
+        "train_step": step,
         "label_s": t_labels,
         "final_train_loss": hist[-1],
     }
