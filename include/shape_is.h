@@ -230,8 +230,11 @@ typedef struct {
  * (then n_pairs <= lib->n_mols).  Outputs are indexed by pair; an index
  * outside [0, lib->n_mols) gives NaN outputs and n_used 0.
  * Asynchronous.  Invalid molecules produce NaN outputs and are reported by
- * shape_check_data.  Errors: SHAPE_E_INVAL, SHAPE_E_RANGE, SHAPE_E_NOMEM,
- * SHAPE_E_HIP. */
+ * shape_check_data.  A screen of at least 16 pairs per compute unit runs its
+ * pairs longest first (estimated from atom counts and n_start, computed on
+ * the device in the same call, with 4 (n_pairs + 32768) bytes of context
+ * scratch); every pair's outputs are the same in any order.  Errors:
+ * SHAPE_E_INVAL, SHAPE_E_RANGE, SHAPE_E_NOMEM, SHAPE_E_HIP. */
 int shape_screen(shape_ctx* ctx, const shape_mols* query, const shape_mols* lib,
                  const int32_t* pairs, int32_t n_pairs,
                  const shape_screen_params* params, void* stream,

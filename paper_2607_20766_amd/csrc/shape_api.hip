@@ -33,7 +33,7 @@ enum Slot {
   S_PARTIALS, S_RESULT, S_QS, S_QF2,
   S_SELF_A, S_SELF_B,
   S_MSE, S_TOPK_SEL, S_TOPK_HIST, S_TOPK_GT, S_TOPK_EQ, S_COLSUM, S_TUNE, S_MLP_PACK, S_FEAT_MOM, S_GEMM_PART,
-  S_GRID_BOX, S_GRID_TAB, S_GRID_PART, S_PEAK, S_MLP_D, S_MLP_STEP,
+  S_GRID_BOX, S_GRID_TAB, S_GRID_PART, S_PEAK, S_MLP_D, S_MLP_STEP, S_ORDER,
   S_COUNT
 };
 
@@ -319,6 +319,12 @@ struct ProfRange {
   ProfRange& operator=(const ProfRange&) = delete;
 };
 
+// Screens of at least this many pairs per compute unit are launched in the
+// order shape::launch_screen_order computes (a few microseconds of work);
+// smaller ones run at most a few pairs per workgroup slot, where the order
+// hardly changes when the last ones finish.
+constexpr int kOrderPairsPerCu = 16;
+
 // Validation, molecule preparation and the query-side sample cache of a
 // screen; fills the kernel arguments (a->n_pairs = 0: nothing to launch).
 int screen_setup(shape_ctx* c, const shape_mols* query, const shape_mols* lib,
@@ -377,6 +383,15 @@ int screen_setup(shape_ctx* c, const shape_mols* query, const shape_mols* lib,
   void *qs, *qf2;
   if ((rc = ensure(c, S_QS, (size_t)n_cache * sizeof(float4), &qs))) return rc;
   if ((rc = ensure(c, S_QF2, (size_t)n_cache * sizeof(float), &qf2))) return rc;
+  // a screen of many pairs runs them longest first (results do not depend on
+  // the order; the last workgroups then finish closer together)
+  int* order = nullptr;
+  if ((int64_t)n_pairs >= (int64_t)kOrderPairsPerCu * c->n_cu) {
+    void* ord;
+    const size_t ints = (size_t)n_pairs + (size_t)shape::screen_order_work_ints();
+    if ((rc = ensure(c, S_ORDER, ints * sizeof(int), &ord))) return rc;
+    order = (int*)ord;
+  }
   const uint2 key = key_of(prm->seed);
   HIP_TRY(c, shape::launch_query_cache(PQ, query->atom_offset, n_cache, key, anti ? 1 : 0,
                                        (float4*)qs,
@@ -407,6 +422,11 @@ int screen_setup(shape_ctx* c, const shape_mols* query, const shape_mols* lib,
   a->O_aa = out->O_aa;
   a->O_bb = out->O_bb;
   a->n_used = out->n_used;
+  a->order = nullptr;
+  if (order) {
+    HIP_TRY(c, shape::launch_screen_order(*a, order, order + n_pairs, st), "screen order kernels");
+    a->order = order;
+  }
   return SHAPE_OK;
 }
 

@@ -429,8 +429,9 @@ __global__ __launch_bounds__(64) void k_screen(ScreenArgs a) {
   float* aBA = aBB + a.max_b;
   float* aAB = aBA + a.max_b;
   const int lane = threadIdx.x;
-  const int p = xcd_chunk(blockIdx.x, gridDim.x);  // grid = n_pairs
-  if (p >= a.n_pairs) return;
+  // grid = n_pairs; a launch order, when given, is a permutation of the pairs
+  const int p = a.order ? a.order[blockIdx.x] : xcd_chunk(blockIdx.x, gridDim.x);
+  if (p < 0 || p >= a.n_pairs) return;
   const int m = a.pairs ? a.pairs[p] : p;
   const bool bad = a.Q.bad[0] != 0 || m < 0 || m >= a.n_lib || a.L.bad[m] != 0;
   if (bad) {
@@ -713,6 +714,116 @@ hipError_t launch_sample_points(const Prepared& P, const int* off, int mol, int 
   const int blocks = (threads + 255) / 256;
   hipLaunchKernelGGL(k_sample_points, dim3(blocks), dim3(256), 0, st, P, off, mol, k0, n, key,
                      anti, thr, words, comp, r);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Launch order of a large screen: longest pairs first.  A pair's result
+// depends on that pair alone, so the order in which workgroups take the pairs
+// changes no output; it changes how long the last workgroups run on after the
+// others have finished.  A pair's work is estimated from its atom counts, and
+// from its seeded budget when one is given: per pair of samples, N_B
+// evaluations at the query's sample, N_B + N_A at the library's, and the
+// sampling and weight steps (worth about 24 evaluations), times the rounds
+// the budget asks for.  Pairs are bucketed by the logarithm of that estimate,
+// 16 buckets per octave, and laid out from the largest bucket down by a
+// counting sort in three launches: kOrderBlocks blocks histogram their
+// contiguous share of the pairs in LDS; one block turns the histograms into
+// each block's first slot per bucket; the same blocks then place their pairs
+// with LDS atomics (the order inside a bucket is not fixed).  Every slot is
+// written on every call, so no memory needs clearing.
+// ---------------------------------------------------------------------------
+constexpr int kOrderBuckets = 512;
+constexpr int kOrderBlocks = 64;
+constexpr int kOrderThreads = 1024;
+
+__device__ __forceinline__ int screen_order_key(const ScreenArgs& a, int p) {
+  const int m = a.pairs ? a.pairs[p] : p;
+  if (m < 0 || m >= a.n_lib) return 0;  // an invalid pair only writes NaN
+  int nb = a.offL[m + 1] - a.offL[m];
+  nb = nb < 0 ? 0 : (nb > a.max_b ? a.max_b : nb);
+  uint32_t cost = (uint32_t)(2 * nb + a.max_q + 24);  // < 2^10
+  if (a.n_start) {
+    const int64_t rp = 2 * (int64_t)a.round_side;
+    const int64_t s = a.n_start[p];
+    const int64_t r = s <= rp ? 1 : (s >= a.cap_pair ? a.cap_pair / rp : (s + rp - 1) / rp);
+    cost *= (uint32_t)r;  // r <= 2^14: cost < 2^24
+  }
+  const int e = 31 - __clz(cost);  // cost >= 24: e >= 4
+  return 16 * e + (int)((cost >> (e - 4)) & 15u);  // < 16 * 24 <= kOrderBuckets
+}
+
+__device__ __forceinline__ void screen_order_share(int n, int& begin, int& end) {
+  const int per = (n + kOrderBlocks - 1) / kOrderBlocks;
+  begin = (int)min((int64_t)n, (int64_t)blockIdx.x * per);
+  end = (int)min((int64_t)n, (int64_t)begin + per);
+}
+
+// hist[b][k]: pairs of block b's share in bucket k
+__global__ __launch_bounds__(kOrderThreads) void k_order_hist(ScreenArgs a,
+                                                              int* __restrict__ hist) {
+  __shared__ int h[kOrderBuckets];
+  for (int k = threadIdx.x; k < kOrderBuckets; k += kOrderThreads) h[k] = 0;
+  __syncthreads();
+  int begin, end;
+  screen_order_share(a.n_pairs, begin, end);
+  for (int p = begin + (int)threadIdx.x; p < end; p += kOrderThreads)
+    atomicAdd(&h[screen_order_key(a, p)], 1);
+  __syncthreads();
+  for (int k = threadIdx.x; k < kOrderBuckets; k += kOrderThreads)
+    hist[blockIdx.x * kOrderBuckets + k] = h[k];
+}
+
+// One block, thread k = bucket k: replaces hist[b][k] by the first slot of
+// block b's pairs of bucket k (buckets from the largest down, blocks in order
+// within a bucket).
+__global__ __launch_bounds__(kOrderBuckets) void k_order_scan(int* __restrict__ hist) {
+  __shared__ int v[kOrderBuckets];
+  const int k = threadIdx.x;
+  int h[kOrderBlocks];
+  int tot = 0;
+#pragma unroll
+  for (int b = 0; b < kOrderBlocks; ++b) {
+    h[b] = hist[b * kOrderBuckets + k];
+    tot += h[b];
+  }
+  // suffix sums: v[k] = pairs in buckets k and above
+  v[k] = tot;
+  __syncthreads();
+  for (int d = 1; d < kOrderBuckets; d <<= 1) {
+    const int x = k + d < kOrderBuckets ? v[k + d] : 0;
+    __syncthreads();
+    v[k] += x;
+    __syncthreads();
+  }
+  int slot = v[k] - tot;
+#pragma unroll
+  for (int b = 0; b < kOrderBlocks; ++b) {
+    hist[b * kOrderBuckets + k] = slot;
+    slot += h[b];
+  }
+}
+
+__global__ __launch_bounds__(kOrderThreads) void k_order_place(ScreenArgs a,
+                                                               const int* __restrict__ first,
+                                                               int* __restrict__ order) {
+  __shared__ int cur[kOrderBuckets];
+  for (int k = threadIdx.x; k < kOrderBuckets; k += kOrderThreads)
+    cur[k] = first[blockIdx.x * kOrderBuckets + k];
+  __syncthreads();
+  int begin, end;
+  screen_order_share(a.n_pairs, begin, end);
+  for (int p = begin + (int)threadIdx.x; p < end; p += kOrderThreads)
+    order[atomicAdd(&cur[screen_order_key(a, p)], 1)] = p;
+}
+
+int screen_order_work_ints() { return kOrderBlocks * kOrderBuckets; }
+
+hipError_t launch_screen_order(const ScreenArgs& a, int* order, int* work, hipStream_t st) {
+  hipLaunchKernelGGL(k_order_hist, dim3(kOrderBlocks), dim3(kOrderThreads), 0, st, a, work);
+  hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(kOrderBuckets), 0, st, work);
+  hipLaunchKernelGGL(k_order_place, dim3(kOrderBlocks), dim3(kOrderThreads), 0, st, a,
+                     (const int*)work, order);
   return hipGetLastError();
 }
 

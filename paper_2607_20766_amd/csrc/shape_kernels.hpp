@@ -53,6 +53,7 @@ struct ScreenArgs {
   uint2 key;
   const int* n_start;  // optional per-pair budgets (adaptive)
   int anti;            // antithetic sampling: terms are pair means
+  const int* order;    // optional launch order: block b screens pair order[b]
   float* T;
   float* se_T;
   float* O_ab;
@@ -224,6 +225,10 @@ size_t screen_lds_bytes(int max_q, int max_b);
 constexpr int kScreenVariants = 8;
 extern const int kScreenVariantShape[kScreenVariants][2];  // {kSA, kSB}
 hipError_t launch_screen(const ScreenArgs& a, int variant, hipStream_t st);
+// Launch order of a screen, longest pairs first (a permutation of
+// [0, n_pairs) into order); work holds screen_order_work_ints() ints.
+int screen_order_work_ints();
+hipError_t launch_screen_order(const ScreenArgs& a, int* order, int* work, hipStream_t st);
 
 // issue-rate microbenchmarks (measurement support): which = 0 FP32 FMA,
 // 1 v_exp_f32, 2 v_mad_u64_u32, 3 LDS 16-byte reads, 4 FP32 FMA with SGPR

@@ -266,3 +266,51 @@ def test_allocation_failure_is_reported_and_recovered(eng):
             assert np.array_equal(got[k], want[k]), k
     with pytest.raises(ShapeError):
         eng.fail_allocations(-1)
+
+
+@pytest.mark.parametrize("case", ["fixed", "adaptive", "seeded", "antithetic"])
+def test_long_screen_in_launch_order_same_bits(case):
+    """A screen of at least 16 pairs per compute unit runs its pairs longest
+    first (the order comes from the atom counts and any seeded budgets);
+    every pair's outputs equal those of the same pair screened in calls of
+    1,000 pairs, which keep the plain order, bit for bit.  The pairs repeat
+    molecules, mix 1- to 96-atom molecules and include indices outside the
+    library (NaN, no samples)."""
+    require_gpu()
+    e = Engine(0)
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    n = 16 * n_cu + 123
+    q = molgen.molecule(1, 0, 30)
+    L = molgen.library(26, 2500, 1, 96, workers=4)
+    rng = np.random.default_rng(26)
+    pairs = rng.integers(0, L.n_mols, n).astype(np.int32)
+    pairs[rng.choice(n, 9, replace=False)] = [-1, -7, L.n_mols, L.n_mols + 3, -1, L.n_mols,
+                                              -2, L.n_mols + 1, -1]
+    kw = dict(mode=SHAPE_SCREEN_ADAPTIVE, round_per_pair=512, cap_per_pair=4096, tau=0.01,
+              seed=5)
+    if case == "fixed":
+        kw = dict(mode=SHAPE_SCREEN_FIXED, n_per_side=256, seed=5)
+    n_start = None
+    if case == "seeded":
+        n_start = (rng.integers(0, 9, n) * 512).astype(np.int32)
+    e.sampling(case == "antithetic")
+    Q = e.molecules(q, mol_id=[QUERY_ID])
+    lib = e.molecules(L)
+    dev = e.torch_device
+    print(f"case: {case}, {n} pairs", flush=True)
+    full = _to_np(e.shape_screen(
+        Q, lib, pairs=torch.from_numpy(pairs).to(dev),
+        n_start=None if n_start is None else torch.from_numpy(n_start).to(dev), **kw))
+    parts = []
+    for a in range(0, n, 1000):
+        sl = slice(a, min(n, a + 1000))
+        parts.append(_to_np(e.shape_screen(
+            Q, lib, pairs=torch.from_numpy(pairs[sl]).to(dev),
+            n_start=None if n_start is None else torch.from_numpy(n_start[sl]).to(dev), **kw)))
+    e.sampling(False)
+    bad = (pairs < 0) | (pairs >= L.n_mols)
+    for k in full:
+        got = np.concatenate([p[k] for p in parts])
+        assert np.array_equal(full[k], got, equal_nan=k != "n_used"), k
+    assert np.all(np.isnan(full["T"][bad])) and np.all(full["n_used"][bad] == 0)
+    assert np.all(np.isfinite(full["T"][~bad]))
