@@ -232,7 +232,7 @@ typedef struct {
  * Asynchronous.  Invalid molecules produce NaN outputs and are reported by
  * shape_check_data.  A screen of at least 16 pairs per compute unit runs its
  * pairs longest first (estimated from atom counts and n_start, computed on
- * the device in the same call, with 4 (n_pairs + 32768) bytes of context
+ * the device in the same call, with 4 (n_pairs + 131072) bytes of context
  * scratch); every pair's outputs are the same in any order.  Errors:
  * SHAPE_E_INVAL, SHAPE_E_RANGE, SHAPE_E_NOMEM, SHAPE_E_HIP. */
 int shape_screen(shape_ctx* ctx, const shape_mols* query, const shape_mols* lib,

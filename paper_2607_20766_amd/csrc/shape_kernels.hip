@@ -725,21 +725,35 @@ hipError_t launch_sample_points(const Prepared& P, const int* off, int mol, int 
 // from its seeded budget when one is given: per pair of samples, N_B
 // evaluations at the query's sample, N_B + N_A at the library's, and the
 // sampling and weight steps (worth about 24 evaluations), times the rounds
-// the budget asks for.  Pairs are bucketed by the logarithm of that estimate,
-// 16 buckets per octave, and laid out from the largest bucket down by a
-// counting sort in three launches: kOrderBlocks blocks histogram their
-// contiguous share of the pairs in LDS; one block turns the histograms into
-// each block's first slot per bucket; the same blocks then place their pairs
-// with LDS atomics (the order inside a bucket is not fixed).  Every slot is
-// written on every call, so no memory needs clearing.
+// the budget asks for; pairs are bucketed by the logarithm of that estimate,
+// 8 buckets per octave.  Each XCD keeps the pairs xcd_chunk gives it (so its
+// L2 still sees whole tiles of consecutive molecules and outputs) and takes
+// them from its largest bucket down: block b = 8 r + x, the r-th block the
+// round-robin dispatch sends to XCD x, screens the r-th pair of XCD x's
+// order.  A counting sort over (XCD, bucket) in three launches: kOrderBlocks
+// blocks histogram their contiguous share of the pairs in LDS; one block
+// turns the histograms into each block's first rank per bucket; the same
+// blocks then place their pairs with LDS atomics (the order inside a bucket
+// is not fixed).  Every slot is written on every call, so no memory needs
+// clearing.
 // ---------------------------------------------------------------------------
-constexpr int kOrderBuckets = 512;
+constexpr int kOrderKeys = 256;                    // work buckets per XCD
+constexpr int kOrderBuckets = kXcds * kOrderKeys;  // (XCD, bucket) pairs
 constexpr int kOrderBlocks = 64;
 constexpr int kOrderThreads = 1024;
 
+// XCD of the block that xcd_chunk maps to item p of a grid of G blocks:
+// below F = G - G mod (8 kXcdTile) tile p / kXcdTile sits on XCD tile mod 8;
+// blocks from F on keep their index, so block p runs on XCD p mod 8.
+__device__ __forceinline__ int xcd_of_item(int p, int G) {
+  const int F = G - G % (kXcds * kXcdTile);
+  return p >= F ? p % kXcds : (p / kXcdTile) % kXcds;
+}
+
 __device__ __forceinline__ int screen_order_key(const ScreenArgs& a, int p) {
+  const int x = xcd_of_item(p, a.n_pairs);
   const int m = a.pairs ? a.pairs[p] : p;
-  if (m < 0 || m >= a.n_lib) return 0;  // an invalid pair only writes NaN
+  if (m < 0 || m >= a.n_lib) return x * kOrderKeys;  // an invalid pair only writes NaN
   int nb = a.offL[m + 1] - a.offL[m];
   nb = nb < 0 ? 0 : (nb > a.max_b ? a.max_b : nb);
   uint32_t cost = (uint32_t)(2 * nb + a.max_q + 24);  // < 2^10
@@ -750,7 +764,7 @@ __device__ __forceinline__ int screen_order_key(const ScreenArgs& a, int p) {
     cost *= (uint32_t)r;  // r <= 2^14: cost < 2^24
   }
   const int e = 31 - __clz(cost);  // cost >= 24: e >= 4
-  return 16 * e + (int)((cost >> (e - 4)) & 15u);  // < 16 * 24 <= kOrderBuckets
+  return x * kOrderKeys + 8 * e + (int)((cost >> (e - 3)) & 7u);  // 8 e + 7 < kOrderKeys
 }
 
 __device__ __forceinline__ void screen_order_share(int n, int& begin, int& end) {
@@ -759,7 +773,7 @@ __device__ __forceinline__ void screen_order_share(int n, int& begin, int& end) 
   end = (int)min((int64_t)n, (int64_t)begin + per);
 }
 
-// hist[b][k]: pairs of block b's share in bucket k
+// hist[b][k]: pairs of block b's share with key k
 __global__ __launch_bounds__(kOrderThreads) void k_order_hist(ScreenArgs a,
                                                               int* __restrict__ hist) {
   __shared__ int h[kOrderBuckets];
@@ -774,33 +788,56 @@ __global__ __launch_bounds__(kOrderThreads) void k_order_hist(ScreenArgs a,
     hist[blockIdx.x * kOrderBuckets + k] = h[k];
 }
 
-// One block, thread k = bucket k: replaces hist[b][k] by the first slot of
-// block b's pairs of bucket k (buckets from the largest down, blocks in order
-// within a bucket).
-__global__ __launch_bounds__(kOrderBuckets) void k_order_scan(int* __restrict__ hist) {
+// One block: replaces hist[b][k] by the rank, within its XCD's order, of the
+// first of block b's pairs with key k (an XCD's buckets from the largest
+// down, blocks in order within a bucket).
+__global__ __launch_bounds__(kOrderThreads) void k_order_scan(int* __restrict__ hist) {
+  constexpr int kPer = kOrderBuckets / kOrderThreads;
+  constexpr int kBatch = 16;
   __shared__ int v[kOrderBuckets];
-  const int k = threadIdx.x;
-  int h[kOrderBlocks];
-  int tot = 0;
+  int tot[kPer];
 #pragma unroll
-  for (int b = 0; b < kOrderBlocks; ++b) {
-    h[b] = hist[b * kOrderBuckets + k];
-    tot += h[b];
+  for (int j = 0; j < kPer; ++j) {
+    const int k = threadIdx.x + j * kOrderThreads;
+    int t = 0;
+    for (int b0 = 0; b0 < kOrderBlocks; b0 += kBatch) {
+      int h[kBatch];
+#pragma unroll
+      for (int i = 0; i < kBatch; ++i) h[i] = hist[(b0 + i) * kOrderBuckets + k];
+#pragma unroll
+      for (int i = 0; i < kBatch; ++i) t += h[i];
+    }
+    tot[j] = t;
+    v[k] = t;
   }
-  // suffix sums: v[k] = pairs in buckets k and above
-  v[k] = tot;
   __syncthreads();
-  for (int d = 1; d < kOrderBuckets; d <<= 1) {
-    const int x = k + d < kOrderBuckets ? v[k + d] : 0;
+  // suffix sums within each XCD's segment: v[k] = its pairs with keys >= k
+  for (int d = 1; d < kOrderKeys; d <<= 1) {
+    int add[kPer];
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+      const int k = threadIdx.x + j * kOrderThreads;
+      add[j] = (k % kOrderKeys) + d < kOrderKeys ? v[k + d] : 0;
+    }
     __syncthreads();
-    v[k] += x;
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) v[threadIdx.x + j * kOrderThreads] += add[j];
     __syncthreads();
   }
-  int slot = v[k] - tot;
 #pragma unroll
-  for (int b = 0; b < kOrderBlocks; ++b) {
-    hist[b * kOrderBuckets + k] = slot;
-    slot += h[b];
+  for (int j = 0; j < kPer; ++j) {
+    const int k = threadIdx.x + j * kOrderThreads;
+    int rank = v[k] - tot[j];
+    for (int b0 = 0; b0 < kOrderBlocks; b0 += kBatch) {
+      int h[kBatch];
+#pragma unroll
+      for (int i = 0; i < kBatch; ++i) h[i] = hist[(b0 + i) * kOrderBuckets + k];
+#pragma unroll
+      for (int i = 0; i < kBatch; ++i) {
+        hist[(b0 + i) * kOrderBuckets + k] = rank;
+        rank += h[i];
+      }
+    }
   }
 }
 
@@ -813,15 +850,18 @@ __global__ __launch_bounds__(kOrderThreads) void k_order_place(ScreenArgs a,
   __syncthreads();
   int begin, end;
   screen_order_share(a.n_pairs, begin, end);
-  for (int p = begin + (int)threadIdx.x; p < end; p += kOrderThreads)
-    order[atomicAdd(&cur[screen_order_key(a, p)], 1)] = p;
+  for (int p = begin + (int)threadIdx.x; p < end; p += kOrderThreads) {
+    const int key = screen_order_key(a, p);
+    const int r = atomicAdd(&cur[key], 1);
+    order[kXcds * r + key / kOrderKeys] = p;
+  }
 }
 
 int screen_order_work_ints() { return kOrderBlocks * kOrderBuckets; }
 
 hipError_t launch_screen_order(const ScreenArgs& a, int* order, int* work, hipStream_t st) {
   hipLaunchKernelGGL(k_order_hist, dim3(kOrderBlocks), dim3(kOrderThreads), 0, st, a, work);
-  hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(kOrderBuckets), 0, st, work);
+  hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(kOrderThreads), 0, st, work);
   hipLaunchKernelGGL(k_order_place, dim3(kOrderBlocks), dim3(kOrderThreads), 0, st, a,
                      (const int*)work, order);
   return hipGetLastError();
