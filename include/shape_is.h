@@ -383,6 +383,9 @@ int shape_self_overlap(shape_ctx* ctx, const shape_mols* M, int32_t n_samples,
  * (from shape_self_overlap with the same n_samples and seed).  n_samples in
  * [64, 4096], n_starts >= 1.  T: device float [pairs][n_starts];
  * dT_dpose: device float [pairs][n_starts][7], or NULL for values only.
+ * At least 4 pairs per compute unit run largest pair first (the order
+ * computed on the device from the atom counts, 4 (pairs + 131072) bytes of
+ * context scratch); every pair's outputs are the same in any order.
  * Asynchronous.  Errors: SHAPE_E_INVAL, SHAPE_E_RANGE (including on-chip
  * staging larger than the device allows), SHAPE_E_NOMEM, SHAPE_E_HIP. */
 int shape_align_grad(shape_ctx* ctx, const shape_mols* A, const shape_mols* B,
@@ -408,7 +411,8 @@ int shape_adam_pose(shape_ctx* ctx, float* pose, const float* dT_dpose, float* m
  * two entry points in turn.
  * pose: device float [pairs][n_starts][7], updated in place.  T_final:
  * device float [pairs][n_starts].  best: device int32 [pairs] or NULL.
- * Adam uses beta1 = 0.9, beta2 = 0.999, eps = 1e-8.  Asynchronous. */
+ * Adam uses beta1 = 0.9, beta2 = 0.999, eps = 1e-8.  Pairs are launched in
+ * the order of shape_align_grad.  Asynchronous. */
 int shape_align(shape_ctx* ctx, const shape_mols* A, const shape_mols* B, int32_t n_starts,
                 float* pose, int32_t n_samples, int32_t n_steps, float lr, uint64_t seed,
                 void* stream, float* T_final, int32_t* best);
@@ -458,7 +462,11 @@ int shape_fo_starts(shape_ctx* ctx, const shape_mols* A, const shape_mols* B,
  * [n_pairs][n_starts], T_FO at the final poses; grad (device float
  * [n_pairs][n_starts][7] or NULL): dT_FO/dpose there.  n_steps = 0
  * evaluates T_FO and its gradient at the given poses.  FP32, one wave per
- * (pair, start), the whole optimisation in one launch.  Asynchronous.
+ * (pair, start), the whole optimisation in one launch; when A has at most
+ * 64 atoms, one workgroup per pair (a start per 16-lane row), and with at
+ * least 16 pairs per compute unit those run largest B first (order computed
+ * on the device, 4 (pairs + 131072) bytes of context scratch; outputs the
+ * same in any order).  Asynchronous.
  * Errors: SHAPE_E_INVAL, SHAPE_E_RANGE (also molecules too large for the
  * kernel's LDS), SHAPE_E_NOMEM, SHAPE_E_HIP. */
 int shape_fo_align(shape_ctx* ctx, const shape_mols* A, const shape_mols* B, int32_t n_starts,

@@ -96,7 +96,7 @@ __global__ __launch_bounds__(kAlignThreads) void k_align(AlignArgs a) {
   float* sAa = reinterpret_cast<float*>(sAS + a.max_a);                    // [max_a]
   float* sBa = sAa + a.max_a;                                              // [waves][max_b]
 
-  const int pair = blockIdx.x;
+  const int pair = a.order ? a.order[blockIdx.x] : blockIdx.x;
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = threadIdx.x / kWave;
   const bool bad = a.A.bad[pair] != 0 || a.B.bad[pair] != 0;

@@ -8,6 +8,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -319,11 +320,50 @@ struct ProfRange {
   ProfRange& operator=(const ProfRange&) = delete;
 };
 
-// Screens of at least this many pairs per compute unit are launched in the
-// order shape::launch_screen_order computes (a few microseconds of work);
-// smaller ones run at most a few pairs per workgroup slot, where the order
-// hardly changes when the last ones finish.
-constexpr int kOrderPairsPerCu = 16;
+// Grids of one workgroup per pair are launched in the order
+// shape::launch_work_order computes (largest estimated work first; a few
+// microseconds) when they hold at least this many pairs per compute unit:
+// fewer run in a few waves of workgroups, where the order hardly changes
+// when the last ones finish.  Screens run up to eight 64-lane workgroups per
+// SIMD, alignments four 256-lane workgroups per compute unit.
+constexpr int kOrderScreenPerCu = 16;
+constexpr int kOrderAlignPerCu = 4;
+constexpr int kOrderFoAlignPerCu = 16;
+
+// The context's launch-order buffer for n pairs, or nullptr when the grid is
+// too short for the order to matter.
+int work_order_slot(shape_ctx* c, int64_t n, int min_per_cu, int** order) {
+  *order = nullptr;
+  if (n < (int64_t)min_per_cu * c->n_cu) return SHAPE_OK;
+  void* ord;
+  const size_t ints = (size_t)n + (size_t)shape::work_order_ints();
+  const int rc = ensure(c, S_ORDER, ints * sizeof(int), &ord);
+  if (rc) return rc;
+  *order = (int*)ord;
+  return SHAPE_OK;
+}
+
+// Work of an alignment pair in atoms' worth, per CRN sample: A's atoms and
+// sampling once, then per start and step the forward and adjoint passes over
+// B's atoms (about two evaluations per atom) and the per-sample weight and
+// gradient steps.
+shape::OrderArgs align_order_args(const shape_mols* A, const shape_mols* B, int n_starts,
+                                  int n_steps) {
+  const uint32_t S = (uint32_t)std::min<int64_t>((int64_t)(n_steps + 1) * n_starts, 1 << 20);
+  shape::OrderArgs o{};
+  o.n = A->n_mols;
+  o.per_xcd = 0;
+  o.offA = A->atom_offset;
+  o.nA_mols = A->n_mols;
+  o.max_a = A->max_atoms;
+  o.offB = B->atom_offset;
+  o.nB_mols = B->n_mols;
+  o.max_b = B->max_atoms;
+  o.wA = 1;
+  o.wB = 2 * S;
+  o.w0 = 24 + 4 * S;
+  return o;
+}
 
 // Validation, molecule preparation and the query-side sample cache of a
 // screen; fills the kernel arguments (a->n_pairs = 0: nothing to launch).
@@ -385,13 +425,8 @@ int screen_setup(shape_ctx* c, const shape_mols* query, const shape_mols* lib,
   if ((rc = ensure(c, S_QF2, (size_t)n_cache * sizeof(float), &qf2))) return rc;
   // a screen of many pairs runs them longest first (results do not depend on
   // the order; the last workgroups then finish closer together)
-  int* order = nullptr;
-  if ((int64_t)n_pairs >= (int64_t)kOrderPairsPerCu * c->n_cu) {
-    void* ord;
-    const size_t ints = (size_t)n_pairs + (size_t)shape::screen_order_work_ints();
-    if ((rc = ensure(c, S_ORDER, ints * sizeof(int), &ord))) return rc;
-    order = (int*)ord;
-  }
+  int* order;
+  if ((rc = work_order_slot(c, n_pairs, kOrderScreenPerCu, &order))) return rc;
   const uint2 key = key_of(prm->seed);
   HIP_TRY(c, shape::launch_query_cache(PQ, query->atom_offset, n_cache, key, anti ? 1 : 0,
                                        (float4*)qs,
@@ -424,7 +459,27 @@ int screen_setup(shape_ctx* c, const shape_mols* query, const shape_mols* lib,
   a->n_used = out->n_used;
   a->order = nullptr;
   if (order) {
-    HIP_TRY(c, shape::launch_screen_order(*a, order, order + n_pairs, st), "screen order kernels");
+    // per pair of samples: N_B evaluations at the query's sample, N_B + N_A
+    // at the library's, and Philox, inverse normals, component choice and
+    // weights, worth about 24 evaluations; times the rounds of a seeded budget
+    shape::OrderArgs o{};
+    o.n = n_pairs;
+    o.per_xcd = 1;
+    o.pairs = pairs;
+    o.offA = query->atom_offset;
+    o.nA_mols = 1;
+    o.max_a = query->max_atoms;
+    o.a_single = 1;
+    o.offB = lib->atom_offset;
+    o.nB_mols = lib->n_mols;
+    o.max_b = lib->max_atoms;
+    o.wA = 1;
+    o.wB = 2;
+    o.w0 = 24;
+    o.n_start = a->n_start;
+    o.round_pair = 2 * (int64_t)round_side;
+    o.cap = cap;
+    HIP_TRY(c, shape::launch_work_order(o, order, order + n_pairs, st), "launch order kernels");
     a->order = order;
   }
   return SHAPE_OK;
@@ -947,7 +1002,11 @@ int align_check(shape_ctx* c, const shape_mols* A, const shape_mols* B, int32_t 
 int align_launch(shape_ctx* c, const shape_mols* A, const shape_mols* B,
                  const shape::Prepared& PA, const shape::Prepared& PB, int32_t n_starts,
                  const float* pose, const float* O_aa, const float* O_bb, int32_t n_samples,
-                 uint64_t seed, hipStream_t st, float* T, float* grad) {
+                 uint64_t seed, hipStream_t st, float* T, float* grad, int* order) {
+  if (order)
+    HIP_TRY(c, shape::launch_work_order(align_order_args(A, B, n_starts, 0), order,
+                                        order + A->n_mols, st),
+            "launch order kernels");
   shape::AlignArgs a;
   a.A = PA;
   a.offA = A->atom_offset;
@@ -966,6 +1025,7 @@ int align_launch(shape_ctx* c, const shape_mols* A, const shape_mols* B,
   a.n_steps = 0;
   a.lr = 0.f;
   a.pose_out = nullptr;
+  a.order = order;
   HIP_TRY(c, shape::launch_align(a, A->n_mols, st), "alignment kernel");
   return SHAPE_OK;
 }
@@ -983,12 +1043,14 @@ int shape_align_grad(shape_ctx* c, const shape_mols* A, const shape_mols* B, int
     if (!pose || !O_aa || !O_bb || !T) return fail(c, SHAPE_E_INVAL, "NULL array");
     if ((rc = set_device(c))) return rc;
     hipStream_t st = (hipStream_t)stream;
+    int* order;
+    if ((rc = work_order_slot(c, A->n_mols, kOrderAlignPerCu, &order))) return rc;
     shape::Prepared PA, PB;
     if ((rc = prepare(c, A, true, st, &PA))) return rc;
     if ((rc = prepare(c, B, false, st, &PB))) return rc;
     KernelTimer timer(c, st);
     rc = align_launch(c, A, B, PA, PB, n_starts, pose, O_aa, O_bb, n_samples, seed, st, T,
-                      dT_dpose);
+                      dT_dpose, order);
     timer.stop();
     return rc;
   } catch (...) {
@@ -1032,6 +1094,8 @@ int shape_align(shape_ctx* c, const shape_mols* A, const shape_mols* B, int32_t 
     void *saa, *sbb;
     if ((rc = ensure(c, S_SELF_A, (size_t)pairs * sizeof(float), &saa))) return rc;
     if ((rc = ensure(c, S_SELF_B, (size_t)pairs * sizeof(float), &sbb))) return rc;
+    int* order;
+    if ((rc = work_order_slot(c, pairs, kOrderAlignPerCu, &order))) return rc;
     // self-overlaps use the library slots; prepare both sets afterwards
     if ((rc = prepare(c, A, false, st, &PB))) return rc;
     HIP_TRY(c, shape::launch_self_overlap(PB, A->atom_offset, pairs, n_samples, key_of(seed),
@@ -1063,6 +1127,11 @@ int shape_align(shape_ctx* c, const shape_mols* A, const shape_mols* B, int32_t 
     a.n_steps = n_steps;
     a.lr = lr;
     a.pose_out = pose;
+    a.order = order;
+    if (order)
+      HIP_TRY(c, shape::launch_work_order(align_order_args(A, B, n_starts, n_steps), order,
+                                          order + pairs, st),
+              "launch order kernels");
     KernelTimer timer(c, st);
     HIP_TRY(c, shape::launch_align(a, pairs, st), "alignment kernel");
     timer.stop();
@@ -1131,12 +1200,30 @@ int shape_fo_align(shape_ctx* c, const shape_mols* A, const shape_mols* B, int32
       return fail(c, SHAPE_E_RANGE, "molecules too large for the alignment kernel's LDS");
     if ((rc = set_device(c))) return rc;
     hipStream_t st = (hipStream_t)stream;
+    int* order = nullptr;
+    if (shape::fo_align_pair_major(A->max_atoms, B->max_atoms, n_starts) &&
+        (rc = work_order_slot(c, B->n_mols, kOrderFoAlignPerCu, &order)))
+      return rc;
     shape::Prepared PA, PB;
     if ((rc = prepare(c, A, true, st, &PA))) return rc;
     if ((rc = prepare(c, B, false, st, &PB))) return rc;
+    if (order) {
+      // per step and start: one pass over B's atoms (A's atoms sit on the
+      // lanes) and the rotation, sums and Adam step, worth about 4 atoms
+      shape::OrderArgs o{};
+      o.n = B->n_mols;
+      o.per_xcd = 1;
+      o.offB = B->atom_offset;
+      o.nB_mols = B->n_mols;
+      o.max_b = B->max_atoms;
+      o.wB = 1;
+      o.w0 = 4;
+      HIP_TRY(c, shape::launch_work_order(o, order, order + B->n_mols, st),
+              "launch order kernels");
+    }
     KernelTimer timer(c, st);
     HIP_TRY(c, shape::launch_fo_align(mols_dev(A), mols_dev(B), PA.bad, PB.bad, n_starts,
-                                      n_steps, lr, pose, T, grad, st),
+                                      n_steps, lr, pose, T, grad, st, order),
             "first-order alignment kernel");
     timer.stop();
     return SHAPE_OK;

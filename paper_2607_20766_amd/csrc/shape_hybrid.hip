@@ -204,6 +204,7 @@ struct FoAlignArgs {
   float* pose;  // [pairs][starts][7], read and written
   float* T;     // [pairs][starts]
   float* grad;  // [pairs][starts][7] at the final pose, or nullptr
+  const int* order;  // optional launch order of the row layout: block x takes pair order[x]
 };
 
 // One pass over the N_A x N_B atom pairs spread over the lanes (the row of
@@ -476,7 +477,7 @@ __global__ __launch_bounds__(256) void k_fo_align_rows(FoAlignArgs a) {
   constexpr int RA16 = RA * 16;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
   const int l16 = lane & 15, row = lane >> 4;
-  const int pair = xcd_chunk(blockIdx.x, gridDim.x);
+  const int pair = a.order ? a.order[blockIdx.x] : xcd_chunk(blockIdx.x, gridDim.x);
   const int s_raw = blockIdx.y * kFoRowsStarts + wave * 4 + row;
   const bool live = s_raw < a.n_starts;
   const int s = live ? s_raw : a.n_starts - 1;  // spare rows repeat the last start
@@ -752,6 +753,10 @@ static size_t fo_rows_lds_bytes(int max_a, int max_b, int n_starts) {
   return bytes <= kFoRowsLdsMax ? bytes : 0;
 }
 
+bool fo_align_pair_major(int max_a, int max_b, int n_starts) {
+  return fo_rows_lds_bytes(max_a, max_b, n_starts) > 0;
+}
+
 template <int RA>
 static void launch_fo_rows_t(const FoAlignArgs& a, size_t lds, hipStream_t st) {
   const int rows = fo_rows_per_block(a.n_starts);
@@ -762,10 +767,11 @@ static void launch_fo_rows_t(const FoAlignArgs& a, size_t lds, hipStream_t st) {
 
 hipError_t launch_fo_align(const MolsDev& A, const MolsDev& B, const int* badA, const int* badB,
                            int n_starts, int n_steps, float lr, float* pose, float* T,
-                           float* grad, hipStream_t st) {
-  FoAlignArgs a{A, B, badA, badB, n_starts, n_steps, lr, pose, T, grad};
+                           float* grad, hipStream_t st, const int* order) {
+  FoAlignArgs a{A, B, badA, badB, n_starts, n_steps, lr, pose, T, grad, nullptr};
   const size_t lds = fo_rows_lds_bytes(A.max_atoms, B.max_atoms, n_starts);
   if (lds > 0) {
+    a.order = order;
     switch ((A.max_atoms + 15) / 16) {
       case 1: launch_fo_rows_t<1>(a, lds, st); break;
       case 2: launch_fo_rows_t<2>(a, lds, st); break;

@@ -718,27 +718,25 @@ hipError_t launch_sample_points(const Prepared& P, const int* off, int mol, int 
 }
 
 // ---------------------------------------------------------------------------
-// Launch order of a large screen: longest pairs first.  A pair's result
-// depends on that pair alone, so the order in which workgroups take the pairs
-// changes no output; it changes how long the last workgroups run on after the
-// others have finished.  A pair's work is estimated from its atom counts, and
-// from its seeded budget when one is given: per pair of samples, N_B
-// evaluations at the query's sample, N_B + N_A at the library's, and the
-// sampling and weight steps (worth about 24 evaluations), times the rounds
-// the budget asks for; pairs are bucketed by the logarithm of that estimate,
-// 8 buckets per octave.  Each XCD keeps the pairs xcd_chunk gives it (so its
-// L2 still sees whole tiles of consecutive molecules and outputs) and takes
-// them from its largest bucket down: block b = 8 r + x, the r-th block the
-// round-robin dispatch sends to XCD x, screens the r-th pair of XCD x's
-// order.  A counting sort over (XCD, bucket) in three launches: kOrderBlocks
-// blocks histogram their contiguous share of the pairs in LDS; one block
-// turns the histograms into each block's first rank per bucket; the same
-// blocks then place their pairs with LDS atomics (the order inside a bucket
-// is not fixed).  Every slot is written on every call, so no memory needs
-// clearing.
+// Launch order of a grid with one workgroup per pair: largest estimated work
+// first.  A pair's result depends on that pair alone, so the order in which
+// workgroups take the pairs changes no output; it changes how long the last
+// workgroups run on after the others have finished.  The caller states the
+// work of a pair in atoms' worth from its atom counts (and seeded budget);
+// pairs are bucketed by its logarithm, 8 buckets per octave.  With per_xcd,
+// each XCD keeps the pairs xcd_chunk deals it (so its L2 still sees whole
+// tiles of consecutive molecules and output lines) and takes them largest
+// first: block b = 8 r + x, the r-th block the round-robin dispatch sends to
+// XCD x, takes the r-th pair of XCD x's order; otherwise block b takes the
+// b-th largest.  A counting sort over (group, bucket) in three launches:
+// kOrderBlocks blocks histogram their contiguous share of the pairs in LDS;
+// one block turns the histograms into each block's first rank per bucket;
+// the same blocks then place their pairs with LDS atomics (the order inside a
+// bucket is not fixed).  Every slot is written on every call, so no memory
+// needs clearing.
 // ---------------------------------------------------------------------------
-constexpr int kOrderKeys = 256;                    // work buckets per XCD
-constexpr int kOrderBuckets = kXcds * kOrderKeys;  // (XCD, bucket) pairs
+constexpr int kOrderKeys = 256;                    // work buckets per group
+constexpr int kOrderBuckets = kXcds * kOrderKeys;  // (group, bucket) pairs
 constexpr int kOrderBlocks = 64;
 constexpr int kOrderThreads = 1024;
 
@@ -750,46 +748,56 @@ __device__ __forceinline__ int xcd_of_item(int p, int G) {
   return p >= F ? p % kXcds : (p / kXcdTile) % kXcds;
 }
 
-__device__ __forceinline__ int screen_order_key(const ScreenArgs& a, int p) {
-  const int x = xcd_of_item(p, a.n_pairs);
-  const int m = a.pairs ? a.pairs[p] : p;
-  if (m < 0 || m >= a.n_lib) return x * kOrderKeys;  // an invalid pair only writes NaN
-  int nb = a.offL[m + 1] - a.offL[m];
-  nb = nb < 0 ? 0 : (nb > a.max_b ? a.max_b : nb);
-  uint32_t cost = (uint32_t)(2 * nb + a.max_q + 24);  // < 2^10
-  if (a.n_start) {
-    const int64_t rp = 2 * (int64_t)a.round_side;
-    const int64_t s = a.n_start[p];
-    const int64_t r = s <= rp ? 1 : (s >= a.cap_pair ? a.cap_pair / rp : (s + rp - 1) / rp);
-    cost *= (uint32_t)r;  // r <= 2^14: cost < 2^24
-  }
-  const int e = 31 - __clz(cost);  // cost >= 24: e >= 4
-  return x * kOrderKeys + 8 * e + (int)((cost >> (e - 3)) & 7u);  // 8 e + 7 < kOrderKeys
+__device__ __forceinline__ int atoms_of(const int* off, int m, int max_atoms) {
+  const int n = off[m + 1] - off[m];
+  return n < 0 ? 0 : (n > max_atoms ? max_atoms : n);
 }
 
-__device__ __forceinline__ void screen_order_share(int n, int& begin, int& end) {
+__device__ __forceinline__ int order_key(const OrderArgs& o, int p) {
+  const int g = o.per_xcd ? xcd_of_item(p, o.n) : 0;
+  const int m = o.pairs ? o.pairs[p] : p;
+  if (m < 0 || m >= o.nB_mols) return g * kOrderKeys;  // an invalid pair only writes NaN
+  uint64_t cost = (uint64_t)o.wB * (uint64_t)atoms_of(o.offB, m, o.max_b) + o.w0;
+  if (o.offA) {
+    const int ma = o.a_single ? 0 : p;
+    if (ma < o.nA_mols) cost += (uint64_t)o.wA * (uint64_t)atoms_of(o.offA, ma, o.max_a);
+  }
+  if (o.n_start) {
+    const int64_t s = o.n_start[p];
+    const int64_t r = s <= o.round_pair ? 1
+                    : (s >= o.cap ? o.cap / o.round_pair
+                                  : (s + o.round_pair - 1) / o.round_pair);
+    cost *= (uint64_t)r;
+  }
+  const uint32_t c = cost == 0 ? 1u : (cost > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)cost);
+  const int e = 31 - __clz(c);
+  const uint32_t mant = e >= 3 ? (c >> (e - 3)) & 7u : (c << (3 - e)) & 7u;
+  return g * kOrderKeys + 8 * e + (int)mant;  // 8 e + 7 < kOrderKeys
+}
+
+__device__ __forceinline__ void order_share(int n, int& begin, int& end) {
   const int per = (n + kOrderBlocks - 1) / kOrderBlocks;
   begin = (int)min((int64_t)n, (int64_t)blockIdx.x * per);
   end = (int)min((int64_t)n, (int64_t)begin + per);
 }
 
 // hist[b][k]: pairs of block b's share with key k
-__global__ __launch_bounds__(kOrderThreads) void k_order_hist(ScreenArgs a,
+__global__ __launch_bounds__(kOrderThreads) void k_order_hist(OrderArgs o,
                                                               int* __restrict__ hist) {
   __shared__ int h[kOrderBuckets];
   for (int k = threadIdx.x; k < kOrderBuckets; k += kOrderThreads) h[k] = 0;
   __syncthreads();
   int begin, end;
-  screen_order_share(a.n_pairs, begin, end);
+  order_share(o.n, begin, end);
   for (int p = begin + (int)threadIdx.x; p < end; p += kOrderThreads)
-    atomicAdd(&h[screen_order_key(a, p)], 1);
+    atomicAdd(&h[order_key(o, p)], 1);
   __syncthreads();
   for (int k = threadIdx.x; k < kOrderBuckets; k += kOrderThreads)
     hist[blockIdx.x * kOrderBuckets + k] = h[k];
 }
 
-// One block: replaces hist[b][k] by the rank, within its XCD's order, of the
-// first of block b's pairs with key k (an XCD's buckets from the largest
+// One block: replaces hist[b][k] by the rank, within its group's order, of
+// the first of block b's pairs with key k (a group's buckets from the largest
 // down, blocks in order within a bucket).
 __global__ __launch_bounds__(kOrderThreads) void k_order_scan(int* __restrict__ hist) {
   constexpr int kPer = kOrderBuckets / kOrderThreads;
@@ -811,7 +819,7 @@ __global__ __launch_bounds__(kOrderThreads) void k_order_scan(int* __restrict__ 
     v[k] = t;
   }
   __syncthreads();
-  // suffix sums within each XCD's segment: v[k] = its pairs with keys >= k
+  // suffix sums within each group's segment: v[k] = its pairs with keys >= k
   for (int d = 1; d < kOrderKeys; d <<= 1) {
     int add[kPer];
 #pragma unroll
@@ -841,7 +849,7 @@ __global__ __launch_bounds__(kOrderThreads) void k_order_scan(int* __restrict__ 
   }
 }
 
-__global__ __launch_bounds__(kOrderThreads) void k_order_place(ScreenArgs a,
+__global__ __launch_bounds__(kOrderThreads) void k_order_place(OrderArgs o,
                                                                const int* __restrict__ first,
                                                                int* __restrict__ order) {
   __shared__ int cur[kOrderBuckets];
@@ -849,20 +857,21 @@ __global__ __launch_bounds__(kOrderThreads) void k_order_place(ScreenArgs a,
     cur[k] = first[blockIdx.x * kOrderBuckets + k];
   __syncthreads();
   int begin, end;
-  screen_order_share(a.n_pairs, begin, end);
+  order_share(o.n, begin, end);
+  const int groups = o.per_xcd ? kXcds : 1;
   for (int p = begin + (int)threadIdx.x; p < end; p += kOrderThreads) {
-    const int key = screen_order_key(a, p);
+    const int key = order_key(o, p);
     const int r = atomicAdd(&cur[key], 1);
-    order[kXcds * r + key / kOrderKeys] = p;
+    order[groups * r + key / kOrderKeys] = p;
   }
 }
 
-int screen_order_work_ints() { return kOrderBlocks * kOrderBuckets; }
+int work_order_ints() { return kOrderBlocks * kOrderBuckets; }
 
-hipError_t launch_screen_order(const ScreenArgs& a, int* order, int* work, hipStream_t st) {
-  hipLaunchKernelGGL(k_order_hist, dim3(kOrderBlocks), dim3(kOrderThreads), 0, st, a, work);
+hipError_t launch_work_order(const OrderArgs& o, int* order, int* work, hipStream_t st) {
+  hipLaunchKernelGGL(k_order_hist, dim3(kOrderBlocks), dim3(kOrderThreads), 0, st, o, work);
   hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(kOrderThreads), 0, st, work);
-  hipLaunchKernelGGL(k_order_place, dim3(kOrderBlocks), dim3(kOrderThreads), 0, st, a,
+  hipLaunchKernelGGL(k_order_place, dim3(kOrderBlocks), dim3(kOrderThreads), 0, st, o,
                      (const int*)work, order);
   return hipGetLastError();
 }

@@ -83,6 +83,7 @@ struct AlignArgs {
   int n_steps;
   float lr;
   float* pose_out;    // the pose array again (written when n_steps > 0)
+  const int* order;   // optional launch order: block b aligns pair order[b]
 };
 
 // Dense layer C = epilogue(A B) with strided operands (see shape_gemm).
@@ -165,7 +166,10 @@ hipError_t launch_fo_starts(const MolsDev& A, const MolsDev& B, const int* badA,
 size_t fo_align_lds_bytes(int max_a, int max_b);
 hipError_t launch_fo_align(const MolsDev& A, const MolsDev& B, const int* badA, const int* badB,
                            int n_starts, int n_steps, float lr, float* pose, float* T,
-                           float* grad, hipStream_t st);
+                           float* grad, hipStream_t st,
+                           const int* order = nullptr);
+// whether launch_fo_align runs one workgroup per pair (the row layout)
+bool fo_align_pair_major(int max_a, int max_b, int n_starts);
 hipError_t launch_best_pose(const float* T, const float* pose, int n_pairs, int n_starts,
                             float* best_pose, float* best_T, hipStream_t st);
 hipError_t launch_apply_pose(const MolsDev& M, const float* pose, float* out, hipStream_t st);
@@ -225,10 +229,26 @@ size_t screen_lds_bytes(int max_q, int max_b);
 constexpr int kScreenVariants = 8;
 extern const int kScreenVariantShape[kScreenVariants][2];  // {kSA, kSB}
 hipError_t launch_screen(const ScreenArgs& a, int variant, hipStream_t st);
-// Launch order of a screen, longest pairs first (a permutation of
-// [0, n_pairs) into order); work holds screen_order_work_ints() ints.
-int screen_order_work_ints();
-hipError_t launch_screen_order(const ScreenArgs& a, int* order, int* work, hipStream_t st);
+// Launch order of a grid with one workgroup per pair (blocks along x):
+// largest estimated work first.  The work of pair p is
+// wA N_A + wB N_B + w0 atoms' worth, times the rounds of its seeded budget
+// when n_start is given; with per_xcd each XCD keeps the pairs xcd_chunk
+// deals it and takes them largest first, else one order over all blocks.
+struct OrderArgs {
+  int n;                // pairs
+  int per_xcd;
+  const int* pairs;     // optional: pair -> molecule of set B (else p)
+  const int* offA;      // optional set A: molecule p, or molecule 0 if a_single
+  int nA_mols, max_a, a_single;
+  const int* offB;
+  int nB_mols, max_b;
+  uint32_t wA, wB, w0;
+  const int* n_start;   // optional per-pair sample budgets
+  int64_t round_pair, cap;
+};
+// order: int [n] (a permutation of [0, n)); work: work_order_ints() ints
+int work_order_ints();
+hipError_t launch_work_order(const OrderArgs& o, int* order, int* work, hipStream_t st);
 
 // issue-rate microbenchmarks (measurement support): which = 0 FP32 FMA,
 // 1 v_exp_f32, 2 v_mad_u64_u32, 3 LDS 16-byte reads, 4 FP32 FMA with SGPR

@@ -159,3 +159,38 @@ def test_displaced_copy_recovered(eng):
     T, best = eng.shape_align(gA, gB, pose, n_samples=NS, n_steps=60, lr=0.05)
     assert float(T.max()) > 0.97
     assert float(T.max()) > float(T0.max()) + 0.1
+
+
+def test_long_alignments_in_launch_order_same_bits(eng):
+    """At least 4 pairs per compute unit are aligned largest pair first (the
+    order comes from the atom counts); T, gradients, final poses and best
+    starts equal those of the same pairs aligned in calls of 500, which keep
+    the plain order, bit for bit (shape_align_grad and shape_align)."""
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    n = 4 * n_cu + 37
+    A = molgen.library(32, n, 5, 60, workers=4)
+    B = molgen.library(33, n, 1, 70, workers=4)
+    ida = np.arange(n, dtype=np.uint32) * 2
+    gA, gB = eng.molecules(A, mol_id=ida), eng.molecules(B, mol_id=ida + 1)
+    dev = eng.torch_device
+    poses = torch.from_numpy(molgen.random_poses(5, n, 3)).to(dev)
+    saa, sbb = eng.shape_self_overlap(gA, 256), eng.shape_self_overlap(gB, 256)
+    print(f"case: {n} pairs", flush=True)
+    T, g = eng.shape_align_grad(gA, gB, poses, saa, sbb, 256)
+    pose_f = poses.clone()
+    Tf, best = eng.shape_align(gA, gB, pose_f, n_samples=256, n_steps=3, lr=0.05)
+    parts = []
+    for a in range(0, n, 500):
+        idx = np.arange(a, min(n, a + 500))
+        cA = eng.molecules(A.subset(idx), mol_id=ida[idx])
+        cB = eng.molecules(B.subset(idx), mol_id=ida[idx] + 1)
+        sl = slice(a, a + len(idx))
+        Tc, gc = eng.shape_align_grad(cA, cB, poses[sl].contiguous(), saa[sl].contiguous(),
+                                      sbb[sl].contiguous(), 256)
+        pc = poses[sl].clone()
+        Tfc, bc = eng.shape_align(cA, cB, pc, n_samples=256, n_steps=3, lr=0.05)
+        parts.append([x.cpu().numpy() for x in (Tc, gc, pc, Tfc, bc)])
+    for k, full in enumerate((T, g, pose_f, Tf, best)):
+        got = np.concatenate([p[k] for p in parts])
+        assert np.array_equal(full.cpu().numpy(), got), k
+    assert np.all(np.isfinite(T.cpu().numpy()))

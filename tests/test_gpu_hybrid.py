@@ -349,3 +349,32 @@ def test_every_launch_shape_matches_oracle(eng, a_atoms, b_atoms, n_starts):
         pr, Tr5 = O.fo_align_adam(oa, ob, poses[p].astype(np.float64), n_steps=5, lr=0.05)
         assert np.abs(p5[p] - pr).max() <= 1e-3, (p, p5[p], pr)
         assert np.abs(T5[p] - Tr5).max() <= 1e-4, (p, T5[p], Tr5)
+
+
+def test_long_first_order_alignment_in_launch_order_same_bits(eng):
+    """At least 16 library molecules per compute unit are aligned on the
+    query largest first (row layout); T, gradients and final poses equal
+    those of the same molecules aligned in calls of 1,000, which keep the
+    plain numbering, bit for bit."""
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    n = 16 * n_cu + 37
+    q = molgen.molecule(1, 0, 30)
+    L = molgen.library(34, n, 1, 90, workers=4)
+    Q = eng.molecules(q, mol_id=[QUERY_ID])
+    lib = eng.molecules(L)
+    dev = eng.torch_device
+    p0 = torch.from_numpy(_poses(n, 8, seed=6)).to(dev)
+    print(f"case: {n} molecules", flush=True)
+    pose = p0.clone()
+    T, g = eng.shape_fo_align(Q, lib, pose, 5, 0.05, need_grad=True)
+    parts = []
+    for a in range(0, n, 1000):
+        idx = np.arange(a, min(n, a + 1000))
+        sub = eng.molecules(L.subset(idx))
+        pc = p0[a:a + len(idx)].clone()
+        Tc, gc = eng.shape_fo_align(Q, sub, pc, 5, 0.05, need_grad=True)
+        parts.append([x.cpu().numpy() for x in (Tc, gc, pc)])
+    for k, full in enumerate((T, g, pose)):
+        got = np.concatenate([p[k] for p in parts])
+        assert np.array_equal(full.cpu().numpy(), got), k
+    assert np.all(np.isfinite(T.cpu().numpy()))
