@@ -232,7 +232,7 @@ typedef struct {
  * Asynchronous.  Invalid molecules produce NaN outputs and are reported by
  * shape_check_data.  A screen of at least 16 pairs per compute unit runs its
  * pairs longest first (estimated from atom counts and n_start, computed on
- * the device in the same call, with 4 (n_pairs + 131072) bytes of context
+ * the device in the same call, with 4 (n_pairs + 133120) bytes of context
  * scratch); every pair's outputs are the same in any order.  Errors:
  * SHAPE_E_INVAL, SHAPE_E_RANGE, SHAPE_E_NOMEM, SHAPE_E_HIP. */
 int shape_screen(shape_ctx* ctx, const shape_mols* query, const shape_mols* lib,
@@ -384,7 +384,7 @@ int shape_self_overlap(shape_ctx* ctx, const shape_mols* M, int32_t n_samples,
  * [64, 4096], n_starts >= 1.  T: device float [pairs][n_starts];
  * dT_dpose: device float [pairs][n_starts][7], or NULL for values only.
  * At least 4 pairs per compute unit run largest pair first (the order
- * computed on the device from the atom counts, 4 (pairs + 131072) bytes of
+ * computed on the device from the atom counts, 4 (pairs + 133120) bytes of
  * context scratch); every pair's outputs are the same in any order.
  * Asynchronous.  Errors: SHAPE_E_INVAL, SHAPE_E_RANGE (including on-chip
  * staging larger than the device allows), SHAPE_E_NOMEM, SHAPE_E_HIP. */
@@ -465,7 +465,7 @@ int shape_fo_starts(shape_ctx* ctx, const shape_mols* A, const shape_mols* B,
  * (pair, start), the whole optimisation in one launch; when A has at most
  * 64 atoms, one workgroup per pair (a start per 16-lane row), and with at
  * least 16 pairs per compute unit those run largest B first (order computed
- * on the device, 4 (pairs + 131072) bytes of context scratch; outputs the
+ * on the device, 4 (pairs + 133120) bytes of context scratch; outputs the
  * same in any order).  Asynchronous.
  * Errors: SHAPE_E_INVAL, SHAPE_E_RANGE (also molecules too large for the
  * kernel's LDS), SHAPE_E_NOMEM, SHAPE_E_HIP. */

@@ -330,16 +330,21 @@ constexpr int kOrderScreenPerCu = 16;
 constexpr int kOrderAlignPerCu = 4;
 constexpr int kOrderFoAlignPerCu = 16;
 
-// The context's launch-order buffer for n pairs, or nullptr when the grid is
-// too short for the order to matter.
-int work_order_slot(shape_ctx* c, int64_t n, int min_per_cu, int** order) {
-  *order = nullptr;
+// The context's launch-order buffers for n pairs (the sort's work area, then
+// the order), or nullptr when the grid is too short for the order to matter.
+struct WorkOrder {
+  int* work = nullptr;
+  int* order = nullptr;
+};
+int work_order_slot(shape_ctx* c, int64_t n, int min_per_cu, WorkOrder* w) {
+  *w = WorkOrder{};
   if (n < (int64_t)min_per_cu * c->n_cu) return SHAPE_OK;
-  void* ord;
-  const size_t ints = (size_t)n + (size_t)shape::work_order_ints();
-  const int rc = ensure(c, S_ORDER, ints * sizeof(int), &ord);
+  void* buf;
+  const size_t ints = (size_t)shape::work_order_ints() + (size_t)n;
+  const int rc = ensure(c, S_ORDER, ints * sizeof(int), &buf);  // hipMalloc: aligned
   if (rc) return rc;
-  *order = (int*)ord;
+  w->work = (int*)buf;
+  w->order = w->work + shape::work_order_ints();
   return SHAPE_OK;
 }
 
@@ -425,8 +430,8 @@ int screen_setup(shape_ctx* c, const shape_mols* query, const shape_mols* lib,
   if ((rc = ensure(c, S_QF2, (size_t)n_cache * sizeof(float), &qf2))) return rc;
   // a screen of many pairs runs them longest first (results do not depend on
   // the order; the last workgroups then finish closer together)
-  int* order;
-  if ((rc = work_order_slot(c, n_pairs, kOrderScreenPerCu, &order))) return rc;
+  WorkOrder wo;
+  if ((rc = work_order_slot(c, n_pairs, kOrderScreenPerCu, &wo))) return rc;
   const uint2 key = key_of(prm->seed);
   HIP_TRY(c, shape::launch_query_cache(PQ, query->atom_offset, n_cache, key, anti ? 1 : 0,
                                        (float4*)qs,
@@ -458,7 +463,7 @@ int screen_setup(shape_ctx* c, const shape_mols* query, const shape_mols* lib,
   a->O_bb = out->O_bb;
   a->n_used = out->n_used;
   a->order = nullptr;
-  if (order) {
+  if (wo.order) {
     // per pair of samples: N_B evaluations at the query's sample, N_B + N_A
     // at the library's, and Philox, inverse normals, component choice and
     // weights, worth about 24 evaluations; times the rounds of a seeded budget
@@ -479,8 +484,8 @@ int screen_setup(shape_ctx* c, const shape_mols* query, const shape_mols* lib,
     o.n_start = a->n_start;
     o.round_pair = 2 * (int64_t)round_side;
     o.cap = cap;
-    HIP_TRY(c, shape::launch_work_order(o, order, order + n_pairs, st), "launch order kernels");
-    a->order = order;
+    HIP_TRY(c, shape::launch_work_order(o, wo.order, wo.work, st), "launch order kernels");
+    a->order = wo.order;
   }
   return SHAPE_OK;
 }
@@ -1002,10 +1007,11 @@ int align_check(shape_ctx* c, const shape_mols* A, const shape_mols* B, int32_t 
 int align_launch(shape_ctx* c, const shape_mols* A, const shape_mols* B,
                  const shape::Prepared& PA, const shape::Prepared& PB, int32_t n_starts,
                  const float* pose, const float* O_aa, const float* O_bb, int32_t n_samples,
-                 uint64_t seed, hipStream_t st, float* T, float* grad, int* order) {
-  if (order)
-    HIP_TRY(c, shape::launch_work_order(align_order_args(A, B, n_starts, 0), order,
-                                        order + A->n_mols, st),
+                 uint64_t seed, hipStream_t st, float* T, float* grad,
+                 const WorkOrder& wo) {
+  if (wo.order)
+    HIP_TRY(c, shape::launch_work_order(align_order_args(A, B, n_starts, 0), wo.order, wo.work,
+                                        st),
             "launch order kernels");
   shape::AlignArgs a;
   a.A = PA;
@@ -1025,7 +1031,7 @@ int align_launch(shape_ctx* c, const shape_mols* A, const shape_mols* B,
   a.n_steps = 0;
   a.lr = 0.f;
   a.pose_out = nullptr;
-  a.order = order;
+  a.order = wo.order;
   HIP_TRY(c, shape::launch_align(a, A->n_mols, st), "alignment kernel");
   return SHAPE_OK;
 }
@@ -1043,14 +1049,14 @@ int shape_align_grad(shape_ctx* c, const shape_mols* A, const shape_mols* B, int
     if (!pose || !O_aa || !O_bb || !T) return fail(c, SHAPE_E_INVAL, "NULL array");
     if ((rc = set_device(c))) return rc;
     hipStream_t st = (hipStream_t)stream;
-    int* order;
-    if ((rc = work_order_slot(c, A->n_mols, kOrderAlignPerCu, &order))) return rc;
+    WorkOrder wo;
+    if ((rc = work_order_slot(c, A->n_mols, kOrderAlignPerCu, &wo))) return rc;
     shape::Prepared PA, PB;
     if ((rc = prepare(c, A, true, st, &PA))) return rc;
     if ((rc = prepare(c, B, false, st, &PB))) return rc;
     KernelTimer timer(c, st);
     rc = align_launch(c, A, B, PA, PB, n_starts, pose, O_aa, O_bb, n_samples, seed, st, T,
-                      dT_dpose, order);
+                      dT_dpose, wo);
     timer.stop();
     return rc;
   } catch (...) {
@@ -1094,8 +1100,8 @@ int shape_align(shape_ctx* c, const shape_mols* A, const shape_mols* B, int32_t 
     void *saa, *sbb;
     if ((rc = ensure(c, S_SELF_A, (size_t)pairs * sizeof(float), &saa))) return rc;
     if ((rc = ensure(c, S_SELF_B, (size_t)pairs * sizeof(float), &sbb))) return rc;
-    int* order;
-    if ((rc = work_order_slot(c, pairs, kOrderAlignPerCu, &order))) return rc;
+    WorkOrder wo;
+    if ((rc = work_order_slot(c, pairs, kOrderAlignPerCu, &wo))) return rc;
     // self-overlaps use the library slots; prepare both sets afterwards
     if ((rc = prepare(c, A, false, st, &PB))) return rc;
     HIP_TRY(c, shape::launch_self_overlap(PB, A->atom_offset, pairs, n_samples, key_of(seed),
@@ -1127,10 +1133,10 @@ int shape_align(shape_ctx* c, const shape_mols* A, const shape_mols* B, int32_t 
     a.n_steps = n_steps;
     a.lr = lr;
     a.pose_out = pose;
-    a.order = order;
-    if (order)
-      HIP_TRY(c, shape::launch_work_order(align_order_args(A, B, n_starts, n_steps), order,
-                                          order + pairs, st),
+    a.order = wo.order;
+    if (wo.order)
+      HIP_TRY(c, shape::launch_work_order(align_order_args(A, B, n_starts, n_steps), wo.order,
+                                          wo.work, st),
               "launch order kernels");
     KernelTimer timer(c, st);
     HIP_TRY(c, shape::launch_align(a, pairs, st), "alignment kernel");
@@ -1200,14 +1206,14 @@ int shape_fo_align(shape_ctx* c, const shape_mols* A, const shape_mols* B, int32
       return fail(c, SHAPE_E_RANGE, "molecules too large for the alignment kernel's LDS");
     if ((rc = set_device(c))) return rc;
     hipStream_t st = (hipStream_t)stream;
-    int* order = nullptr;
+    WorkOrder wo;
     if (shape::fo_align_pair_major(A->max_atoms, B->max_atoms, n_starts) &&
-        (rc = work_order_slot(c, B->n_mols, kOrderFoAlignPerCu, &order)))
+        (rc = work_order_slot(c, B->n_mols, kOrderFoAlignPerCu, &wo)))
       return rc;
     shape::Prepared PA, PB;
     if ((rc = prepare(c, A, true, st, &PA))) return rc;
     if ((rc = prepare(c, B, false, st, &PB))) return rc;
-    if (order) {
+    if (wo.order) {
       // per step and start: one pass over B's atoms (A's atoms sit on the
       // lanes) and the rotation, sums and Adam step, worth about 4 atoms
       shape::OrderArgs o{};
@@ -1218,12 +1224,11 @@ int shape_fo_align(shape_ctx* c, const shape_mols* A, const shape_mols* B, int32
       o.max_b = B->max_atoms;
       o.wB = 1;
       o.w0 = 4;
-      HIP_TRY(c, shape::launch_work_order(o, order, order + B->n_mols, st),
-              "launch order kernels");
+      HIP_TRY(c, shape::launch_work_order(o, wo.order, wo.work, st), "launch order kernels");
     }
     KernelTimer timer(c, st);
     HIP_TRY(c, shape::launch_fo_align(mols_dev(A), mols_dev(B), PA.bad, PB.bad, n_starts,
-                                      n_steps, lr, pose, T, grad, st, order),
+                                      n_steps, lr, pose, T, grad, st, wo.order),
             "first-order alignment kernel");
     timer.stop();
     return SHAPE_OK;

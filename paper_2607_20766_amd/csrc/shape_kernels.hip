@@ -730,10 +730,10 @@ hipError_t launch_sample_points(const Prepared& P, const int* off, int mol, int 
 // XCD x, takes the r-th pair of XCD x's order; otherwise block b takes the
 // b-th largest.  A counting sort over (group, bucket) in three launches:
 // kOrderBlocks blocks histogram their contiguous share of the pairs in LDS;
-// one block turns the histograms into each block's first rank per bucket;
-// the same blocks then place their pairs with LDS atomics (the order inside a
-// bucket is not fixed).  Every slot is written on every call, so no memory
-// needs clearing.
+// one thread per bucket sums its counts over the blocks (prefix and total);
+// the same blocks again, each after an LDS scan of the totals, place their
+// pairs with LDS atomics (the order inside a bucket is not fixed).  Every
+// slot is written on every call, so no memory needs clearing.
 // ---------------------------------------------------------------------------
 constexpr int kOrderKeys = 256;                    // work buckets per group
 constexpr int kOrderBuckets = kXcds * kOrderKeys;  // (group, bucket) pairs
@@ -781,7 +781,8 @@ __device__ __forceinline__ void order_share(int n, int& begin, int& end) {
   end = (int)min((int64_t)n, (int64_t)begin + per);
 }
 
-// hist[b][k]: pairs of block b's share with key k
+// hist[k][b]: pairs of block b's share with key k (bucket-major, so that
+// the scan reads each bucket's counts as 16 consecutive 16-byte words)
 __global__ __launch_bounds__(kOrderThreads) void k_order_hist(OrderArgs o,
                                                               int* __restrict__ hist) {
   __shared__ int h[kOrderBuckets];
@@ -793,68 +794,69 @@ __global__ __launch_bounds__(kOrderThreads) void k_order_hist(OrderArgs o,
     atomicAdd(&h[order_key(o, p)], 1);
   __syncthreads();
   for (int k = threadIdx.x; k < kOrderBuckets; k += kOrderThreads)
-    hist[blockIdx.x * kOrderBuckets + k] = h[k];
+    hist[k * kOrderBlocks + blockIdx.x] = h[k];
 }
 
-// One block: replaces hist[b][k] by the rank, within its group's order, of
-// the first of block b's pairs with key k (a group's buckets from the largest
-// down, blocks in order within a bucket).
-__global__ __launch_bounds__(kOrderThreads) void k_order_scan(int* __restrict__ hist) {
+// One thread per key k: replaces hist[k][b] by the number of pairs with key k
+// in blocks before b, and writes the key's total to tot[k].  hist is 16-byte
+// aligned.
+constexpr int kOrderScanThreads = 64;
+__global__ __launch_bounds__(kOrderScanThreads) void k_order_scan(int* __restrict__ hist,
+                                                                 int* __restrict__ tot) {
+  constexpr int kVec = kOrderBlocks / 4;
+  const int k = blockIdx.x * kOrderScanThreads + threadIdx.x;
+  int4* row = reinterpret_cast<int4*>(hist + k * kOrderBlocks);
+  int4 h[kVec];
+#pragma unroll
+  for (int i = 0; i < kVec; ++i) h[i] = row[i];
+  int rank = 0;
+#pragma unroll
+  for (int i = 0; i < kVec; ++i) {
+    int4 r;
+    r.x = rank; rank += h[i].x;
+    r.y = rank; rank += h[i].y;
+    r.z = rank; rank += h[i].z;
+    r.w = rank; rank += h[i].w;
+    row[i] = r;
+  }
+  tot[k] = rank;
+}
+
+// Block b places its share: pair p with key k goes to rank
+// (pairs of its group with larger keys) + (key-k pairs of earlier blocks) +
+// (its arrival among block b's key-k pairs) of its group's order.
+__global__ __launch_bounds__(kOrderThreads) void k_order_place(OrderArgs o,
+                                                               const int* __restrict__ before,
+                                                               const int* __restrict__ tot,
+                                                               int* __restrict__ order) {
   constexpr int kPer = kOrderBuckets / kOrderThreads;
-  constexpr int kBatch = 16;
-  __shared__ int v[kOrderBuckets];
-  int tot[kPer];
+  __shared__ int cur[kOrderBuckets];
+  int t[kPer];
 #pragma unroll
   for (int j = 0; j < kPer; ++j) {
     const int k = threadIdx.x + j * kOrderThreads;
-    int t = 0;
-    for (int b0 = 0; b0 < kOrderBlocks; b0 += kBatch) {
-      int h[kBatch];
-#pragma unroll
-      for (int i = 0; i < kBatch; ++i) h[i] = hist[(b0 + i) * kOrderBuckets + k];
-#pragma unroll
-      for (int i = 0; i < kBatch; ++i) t += h[i];
-    }
-    tot[j] = t;
-    v[k] = t;
+    t[j] = tot[k];
+    cur[k] = t[j];
   }
   __syncthreads();
-  // suffix sums within each group's segment: v[k] = its pairs with keys >= k
+  // suffix sums within each group's segment: cur[k] = its pairs with keys >= k
   for (int d = 1; d < kOrderKeys; d <<= 1) {
     int add[kPer];
 #pragma unroll
     for (int j = 0; j < kPer; ++j) {
       const int k = threadIdx.x + j * kOrderThreads;
-      add[j] = (k % kOrderKeys) + d < kOrderKeys ? v[k + d] : 0;
+      add[j] = (k % kOrderKeys) + d < kOrderKeys ? cur[k + d] : 0;
     }
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < kPer; ++j) v[threadIdx.x + j * kOrderThreads] += add[j];
+    for (int j = 0; j < kPer; ++j) cur[threadIdx.x + j * kOrderThreads] += add[j];
     __syncthreads();
   }
 #pragma unroll
   for (int j = 0; j < kPer; ++j) {
     const int k = threadIdx.x + j * kOrderThreads;
-    int rank = v[k] - tot[j];
-    for (int b0 = 0; b0 < kOrderBlocks; b0 += kBatch) {
-      int h[kBatch];
-#pragma unroll
-      for (int i = 0; i < kBatch; ++i) h[i] = hist[(b0 + i) * kOrderBuckets + k];
-#pragma unroll
-      for (int i = 0; i < kBatch; ++i) {
-        hist[(b0 + i) * kOrderBuckets + k] = rank;
-        rank += h[i];
-      }
-    }
+    cur[k] += before[k * kOrderBlocks + blockIdx.x] - t[j];
   }
-}
-
-__global__ __launch_bounds__(kOrderThreads) void k_order_place(OrderArgs o,
-                                                               const int* __restrict__ first,
-                                                               int* __restrict__ order) {
-  __shared__ int cur[kOrderBuckets];
-  for (int k = threadIdx.x; k < kOrderBuckets; k += kOrderThreads)
-    cur[k] = first[blockIdx.x * kOrderBuckets + k];
   __syncthreads();
   int begin, end;
   order_share(o.n, begin, end);
@@ -866,13 +868,15 @@ __global__ __launch_bounds__(kOrderThreads) void k_order_place(OrderArgs o,
   }
 }
 
-int work_order_ints() { return kOrderBlocks * kOrderBuckets; }
+int work_order_ints() { return kOrderBlocks * kOrderBuckets + kOrderBuckets; }
 
 hipError_t launch_work_order(const OrderArgs& o, int* order, int* work, hipStream_t st) {
+  int* tot = work + kOrderBlocks * kOrderBuckets;
   hipLaunchKernelGGL(k_order_hist, dim3(kOrderBlocks), dim3(kOrderThreads), 0, st, o, work);
-  hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(kOrderThreads), 0, st, work);
+  hipLaunchKernelGGL(k_order_scan, dim3(kOrderBuckets / kOrderScanThreads),
+                     dim3(kOrderScanThreads), 0, st, work, tot);
   hipLaunchKernelGGL(k_order_place, dim3(kOrderBlocks), dim3(kOrderThreads), 0, st, o,
-                     (const int*)work, order);
+                     (const int*)work, (const int*)tot, order);
   return hipGetLastError();
 }
 

@@ -246,7 +246,8 @@ struct OrderArgs {
   const int* n_start;   // optional per-pair sample budgets
   int64_t round_pair, cap;
 };
-// order: int [n] (a permutation of [0, n)); work: work_order_ints() ints
+// order: int [n] (a permutation of [0, n)); work: work_order_ints() ints,
+// 16-byte aligned
 int work_order_ints();
 hipError_t launch_work_order(const OrderArgs& o, int* order, int* work, hipStream_t st);
 
