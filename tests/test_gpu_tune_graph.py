@@ -394,3 +394,47 @@ def test_tuner_cache_file_round_trip(eng, data, tmp_path):
     finally:
         tune_cache_file(None)
         eng.screen_variant(-1)
+
+
+def test_graph_of_long_screen_recomputes_its_order(eng):
+    """A captured screen long enough to be launched in work order (seeded
+    budgets) recomputes the order on every replay: replays equal direct calls,
+    also after the budgets change in place and after eager long screens that
+    reuse the context's order buffer for other pairs."""
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    n = 16 * n_cu + 77
+    q = molgen.molecule(1, 0, 30)
+    L = molgen.library(27, 3000, 1, 80, workers=4)
+    Q, lib = eng.molecules(q, mol_id=[QUERY_ID]), eng.molecules(L)
+    dev = eng.torch_device
+    rng = np.random.default_rng(27)
+    pairs = torch.from_numpy(rng.integers(0, L.n_mols, n).astype(np.int32)).to(dev)
+    n_start = torch.from_numpy((rng.integers(0, 6, n) * 512).astype(np.int32)).to(dev)
+    other_pairs = torch.flip(pairs, [0]).contiguous()
+    kw = dict(mode=SHAPE_SCREEN_ADAPTIVE, round_per_pair=512, cap_per_pair=4096, tau=0.01,
+              seed=4)
+    out = _alloc(n, dev)
+    scratch = _alloc(n, dev)
+
+    def step():
+        eng.shape_screen(Q, lib, pairs=pairs, n_start=n_start, out=out, **kw)
+
+    step()
+    torch.cuda.synchronize()
+    g = eng.capture(step)
+    try:
+        for rep in range(4):
+            if rep == 2:   # new budgets, written in place
+                n_start.copy_(torch.flip(n_start, [0]))
+            print(f"case: long-screen graph replay {rep}", flush=True)
+            direct = _np(eng.shape_screen(Q, lib, pairs=pairs, n_start=n_start, **kw))
+            for v in out.values():
+                v.fill_(-1)
+            g.replay()
+            torch.cuda.synchronize()
+            _same(direct, _np(out))
+            # eager long screen of other pairs between replays
+            eng.shape_screen(Q, lib, pairs=other_pairs, out=scratch, **kw)
+            torch.cuda.synchronize()
+    finally:
+        g.close()
