@@ -776,7 +776,7 @@ __device__ __forceinline__ int order_key(const OrderArgs& o, int p) {
 }
 
 __device__ __forceinline__ void order_share(int n, int& begin, int& end) {
-  const int per = (n + kOrderBlocks - 1) / kOrderBlocks;
+  const int64_t per = ((int64_t)n + kOrderBlocks - 1) / kOrderBlocks;
   begin = (int)min((int64_t)n, (int64_t)blockIdx.x * per);
   end = (int)min((int64_t)n, (int64_t)begin + per);
 }
@@ -790,8 +790,8 @@ __global__ __launch_bounds__(kOrderThreads) void k_order_hist(OrderArgs o,
   __syncthreads();
   int begin, end;
   order_share(o.n, begin, end);
-  for (int p = begin + (int)threadIdx.x; p < end; p += kOrderThreads)
-    atomicAdd(&h[order_key(o, p)], 1);
+  for (int64_t p = begin + (int64_t)threadIdx.x; p < end; p += kOrderThreads)
+    atomicAdd(&h[order_key(o, (int)p)], 1);
   __syncthreads();
   for (int k = threadIdx.x; k < kOrderBuckets; k += kOrderThreads)
     hist[k * kOrderBlocks + blockIdx.x] = h[k];
@@ -861,10 +861,10 @@ __global__ __launch_bounds__(kOrderThreads) void k_order_place(OrderArgs o,
   int begin, end;
   order_share(o.n, begin, end);
   const int groups = o.per_xcd ? kXcds : 1;
-  for (int p = begin + (int)threadIdx.x; p < end; p += kOrderThreads) {
-    const int key = order_key(o, p);
+  for (int64_t p = begin + (int64_t)threadIdx.x; p < end; p += kOrderThreads) {
+    const int key = order_key(o, (int)p);
     const int r = atomicAdd(&cur[key], 1);
-    order[groups * r + key / kOrderKeys] = p;
+    order[(int64_t)groups * r + key / kOrderKeys] = (int)p;
   }
 }
 
