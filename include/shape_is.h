@@ -35,6 +35,9 @@
  *    in which case they synchronise the stream before returning.
  *  - The context owns only internal scratch (grown on demand with hipMalloc,
  *    which happens at most on the first calls with a given problem size).
+ *    Calls of one context share that scratch: calls queued on different
+ *    streams of one context must not run at the same time (order them with
+ *    events, or give each stream its own context).
  *  - Return value: SHAPE_OK or a negative SHAPE_E_* code; a message is kept
  *    in the context (shape_last_error).  No exception or abort crosses the
  *    ABI.  A context is not thread-safe: one host thread per context.
