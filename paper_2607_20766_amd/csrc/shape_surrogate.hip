@@ -208,15 +208,27 @@ __global__ void k_features_eigen(int n_mols, const float* __restrict__ mom,
 // exp(-a_i a_j/(a_i+a_j) |c_i - c_j|^2).  Four waves per workgroup share the
 // query's atoms in LDS; each wave walks a contiguous run of pairs, one pair
 // at a time with all 64 lanes.  The query is the same for every pair, so the
-// lanes are laid out as NI query slots x 64/NI phases: lane l holds QT query
-// atoms i = ib + l % NI + t NI (t < QT) in registers and walks the library
-// molecule's atoms j = l / NI, l / NI + 64/NI, ... as LDS broadcasts; one
-// read of atom j feeds QT independent terms.  Slots past the query's last
-// atom hold a phantom atom 10^18 A away whose terms are exactly zero.  A
-// pair is only ~15 terms per lane, so the wave hides the memory latency
+// lanes are laid out as NI query slots x 64/NI phases: lane l holds query
+// atom i = ib + l % NI in registers and walks the library molecule's atoms
+// j = l / NI, l / NI + 64/NI, ... as LDS broadcasts.  Slots past the query's
+// last atom hold a phantom atom 10^18 A away whose terms are exactly zero.
+// A pair is only ~15 terms per lane, so the wave hides the memory latency
 // itself: the headers (molecule index, atom range) of 64 pairs are read at
 // once, one per lane, and the next pair's atoms are loaded while the current
 // pair's terms are summed.  FP32 sums, DPP wave sum.
+//
+// Per term the widths enter as b = 1/a' (a' = log2(e) a): with
+// k = 1/(b_i + b_j) = a'_i a'_j/(a'_i + a'_j), the term is
+// (pi log2(e))^(3/2) (b_i b_j)^(3/2) k^(3/2) exp2(-k d^2), and
+// b_j^(3/2) exp2(-k d^2) = exp2(-k d^2 + 1.5 log2 b_j), so a term is one
+// rsq (k^(1/2)), one exp2 and five VALU; b_i^(3/2) scales the lane's sum
+// once.  The squared distance is the expanded form
+// |c_i|^2 + |c_j|^2 - 2 c_i . c_j (four VALU) in a frame centred on the
+// query's centroid, where the atoms that overlap have small coordinates: an
+// FP32 emulation over molecules of 1-256 atoms (with correctly rounded rsq,
+// exp2 and log2; the hardware's are within a few ulp) stays within 7e-7 of
+// the FP64 closed form.  Library widths use the hardware reciprocal and
+// log2 (once per atom and pair).
 constexpr int kFoWaves = 4;
 
 __device__ __forceinline__ bool atom_ok(float al, float x, float y, float z) {
@@ -230,10 +242,16 @@ __device__ __forceinline__ bool atom_ok(float al, float x, float y, float z) {
 constexpr int kFoChunks = SHAPE_MAX_ATOMS / kWave;  // library atoms per lane, at most
 
 // Phantom atoms 10^18 A from every real atom, the query's at +10^18 and the
-// library's at -10^18 on each axis (so two phantoms are 2 10^18 apart too):
-// every term with a phantom is exactly zero (exp2 of minus a huge number),
-// so padded slots need no branch.
-__device__ __forceinline__ float4 fo_phantom(float at) { return make_float4(at, at, at, 1.0f); }
+// library's at -10^18 on each axis (so two phantoms are 2 10^18 apart too),
+// both with b = 1: every term with a phantom is exactly zero (exp2 of minus
+// a huge number), so padded slots need no branch.  Query records hold
+// (-2 c, |c|^2), library records (c, |c|^2).
+__device__ __forceinline__ float4 fo_phantom_query() {
+  return make_float4(-2e18f, -2e18f, -2e18f, 3e36f);
+}
+__device__ __forceinline__ float4 fo_phantom_lib() {
+  return make_float4(-1e18f, -1e18f, -1e18f, 3e36f);
+}
 
 // NI query slots x 64/NI phases; CH chunks of 64 library atoms per lane at
 // most (1 when no library molecule passes 64 atoms).
@@ -244,19 +262,39 @@ __global__ __launch_bounds__(kWave * kFoWaves) void k_fo_cross(
   constexpr int kPhases = kWave / NI;
   constexpr int kUnroll = 2;
   constexpr int kPad = kPhases * kUnroll;  // library atoms padded to a multiple of this
-  // query atoms [max_q], then each wave's library molecule [max_b padded]:
-  // (x, y, z, a' = log2(e) alpha)
+  // query records [max_q]; each wave's library atoms [max_b padded], two
+  // 16-byte words per atom (c, |c|^2) and (b, 1.5 log2 b, -, -) read from one
+  // address; the query's widths (b, b^1.5) [max_q]
   extern __shared__ float4 fo_lds[];
-  float4* sA = fo_lds;
+  __shared__ float4 s_cen;  // the query's centroid
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
   const int max_b_pad = (L.max_atoms + kPad - 1) / kPad * kPad;
-  float4* sB = fo_lds + Q.max_atoms + w * max_b_pad;
+  float4* sA = fo_lds;
+  float4* sB = fo_lds + Q.max_atoms + 2 * w * max_b_pad;
+  float2* sAw = reinterpret_cast<float2*>(fo_lds + Q.max_atoms + 2 * kFoWaves * max_b_pad);
   // this wave's pairs [p_begin, p_end)
   const int64_t g = (int64_t)blockIdx.x * kFoWaves + w;
   const int p_begin = (int)min((int64_t)n_pairs, g * per_wave);
   const int p_end = (int)min((int64_t)n_pairs, (int64_t)p_begin + per_wave);
   const int q0 = Q.off[0], q1 = Q.off[1], nq = q1 - q0;
   const bool q_range = q0 >= 0 && (int64_t)q1 <= Q.n_atoms && nq >= 1 && nq <= Q.max_atoms;
+  if (w == 0) {  // centroid: lane-strided sums in atom order, one DPP wave sum
+    float sx = 0.0f, sy = 0.0f, sz = 0.0f;
+    if (q_range) {
+      for (int i = lane; i < nq; i += kWave) {
+        sx += Q.xyz[3 * (q0 + i)];
+        sy += Q.xyz[3 * (q0 + i) + 1];
+        sz += Q.xyz[3 * (q0 + i) + 2];
+      }
+    }
+    sx = wave_sum_dpp(sx);
+    sy = wave_sum_dpp(sy);
+    sz = wave_sum_dpp(sz);
+    const float inv = 1.0f / (float)(q_range ? nq : 1);
+    if (lane == 0) s_cen = make_float4(sx * inv, sy * inv, sz * inv, 0.0f);
+  }
+  __syncthreads();
+  const float4 cen = s_cen;
   int q_bad = q_range ? 0 : 1;
   if (q_range) {
     for (int i = threadIdx.x; i < nq; i += kWave * kFoWaves) {
@@ -264,7 +302,10 @@ __global__ __launch_bounds__(kWave * kFoWaves) void k_fo_cross(
       const float x = Q.xyz[3 * (q0 + i)], y = Q.xyz[3 * (q0 + i) + 1],
                   z = Q.xyz[3 * (q0 + i) + 2];
       if (!atom_ok(al, x, y, z)) q_bad = 1;
-      sA[i] = make_float4(x, y, z, 1.44269504088896f * al);
+      const float dx = x - cen.x, dy = y - cen.y, dz = z - cen.z;
+      const float b = 1.0f / (1.44269504088896f * al);
+      sA[i] = make_float4(-2.0f * dx, -2.0f * dy, -2.0f * dz, fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
+      sAw[i] = make_float2(b, b * sqrtf(b));
     }
   }
   // reached by every wave (no return before it); the outcome is grid-uniform
@@ -317,9 +358,13 @@ __global__ __launch_bounds__(kWave * kFoWaves) void k_fo_cross(
           if (j < nb) {
             const float4 a = nxt[c];
             if (!atom_ok(a.w, a.x, a.y, a.z)) a_bad = true;
-            sB[j] = make_float4(a.x, a.y, a.z, 1.44269504088896f * a.w);
+            const float dx = a.x - cen.x, dy = a.y - cen.y, dz = a.z - cen.z;
+            const float b = __builtin_amdgcn_rcpf(1.44269504088896f * a.w);
+            sB[2 * j] = make_float4(dx, dy, dz, fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
+            sB[2 * j + 1] = make_float4(b, 1.5f * __builtin_amdgcn_logf(b), 0.0f, 0.0f);
           } else if (j < nb_pad) {
-            sB[j] = fo_phantom(-1e18f);
+            sB[2 * j] = fo_phantom_lib();
+            sB[2 * j + 1] = make_float4(1.0f, 0.0f, 0.0f, 0.0f);
           }
         }
       }
@@ -334,28 +379,27 @@ __global__ __launch_bounds__(kWave * kFoWaves) void k_fo_cross(
         continue;
       }
       wave_lds_sync();
-      // With widths a' = log2(e) a and s = a'_i + a'_j: a'_i a'_j / s =
-      // log2(e) a_i a_j / (a_i + a_j), the exp2 exponent per unit d2, and
-      // s^(-3/2) = log2(e)^(-3/2) (a_i + a_j)^(-3/2); the constant
-      // (pi log2(e))^(3/2) is applied to the wave sum.  Per term: 12 VALU,
-      // one rsq, one exp2.
       float acc = 0.0f;
       for (int ib = 0; ib < nq; ib += NI) {  // one block unless the query passes NI atoms
         const int i = ib + li;
-        const float4 ci = i < nq ? sA[i] : fo_phantom(1e18f);
+        const bool real = i < nq;
+        const float4 ci = real ? sA[i] : fo_phantom_query();
+        const float2 wi = real ? sAw[i] : make_float2(1.0f, 1.0f);
         const int n_iter = nb_pad / kPad;  // wave-uniform trip count
+        float accb = 0.0f;
         for (int t = 0; t < n_iter; ++t) {
           const int j = ph + t * kPad;
 #pragma unroll
           for (int u = 0; u < kUnroll; ++u) {
-            const float4 cj = sB[j + u * kPhases];
-            const float dx = ci.x - cj.x, dy = ci.y - cj.y, dz = ci.z - cj.z;
-            const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-            const float rs = __builtin_amdgcn_rsqf(ci.w + cj.w);
-            const float ir = rs * rs;
-            acc = fmaf(ir * rs, __builtin_amdgcn_exp2f(-(ci.w * cj.w * ir * d2)), acc);
+            const float4 cj = sB[2 * (j + u * kPhases)];
+            const float4 wj = sB[2 * (j + u * kPhases) + 1];
+            const float d2 = fmaf(ci.x, cj.x, fmaf(ci.y, cj.y, fmaf(ci.z, cj.z, ci.w + cj.w)));
+            const float r = __builtin_amdgcn_rsqf(wi.x + wj.x);  // k^(1/2)
+            const float kk = r * r;
+            accb = fmaf(kk * r, __builtin_amdgcn_exp2f(fmaf(-kk, d2, wj.y)), accb);
           }
         }
+        acc = fmaf(accb, wi.y, acc);
       }
       const float sum = 9.64909578231936f * wave_sum_dpp(acc);  // (pi log2(e))^(3/2)
       if (lane == 0) out[p] = sum;
@@ -1875,7 +1919,8 @@ static hipError_t launch_fo_cross_t(const MolsDev& Q, const MolsDev& L, const in
   constexpr int kPad = (kWave / NI) * 2;
   const int max_b_pad = (L.max_atoms + kPad - 1) / kPad * kPad;
   const dim3 block(kWave * kFoWaves);
-  const size_t lds = (size_t)(Q.max_atoms + kFoWaves * max_b_pad) * sizeof(float4);
+  const size_t lds = (size_t)Q.max_atoms * (sizeof(float4) + sizeof(float2)) +
+                     (size_t)kFoWaves * max_b_pad * 2 * sizeof(float4);
   // eight waves per SIMD over the chip, each with a contiguous run of pairs
   const int64_t waves_wanted = (int64_t)(n_cu > 0 ? n_cu : 256) * 32;
   const int per_wave = (int)((n_pairs + waves_wanted - 1) / waves_wanted);

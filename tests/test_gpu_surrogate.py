@@ -144,9 +144,16 @@ def test_topk_exact(eng):
         assert np.array_equal(got, want), (n, k)
 
 
-def test_fo_overlap_matches_oracle(eng):
+@pytest.mark.parametrize("shift", [(0.0, 0.0, 0.0), (120.0, -75.0, 40.0)])
+def test_fo_overlap_matches_oracle(eng, shift):
+    """First-order cross overlaps (Eq. fo) against the oracle's closed form
+    at 1e-5, also with query and library moved together far from the origin
+    (the kernel's expanded distances are taken about the query's centroid)."""
     q = molgen.molecule(1, 0, 30)
     L = molgen.library(11, 50, 10, 50, workers=1)
+    d = np.asarray(shift, np.float32)
+    q.xyz = (q.xyz + d).astype(np.float32)
+    L.xyz = (L.xyz + d).astype(np.float32)
     Q = eng.molecules(q)
     lib = eng.molecules(L)
     g = eng.shape_fo_overlap(Q, lib).cpu().numpy()
