@@ -94,14 +94,52 @@ __device__ __forceinline__ int select_component(const AtomSampling* samp, int n,
   return j;
 }
 
+// Guide table of a molecule's component choice, built once per molecule in
+// LDS: guide[g] = #{i < n-1 : thr_i <= g 2^24} for the top eight bits g of
+// a word.  Every threshold counted there lies at or below any word whose top
+// bits are g, so that word's count starts at guide[g] and steps only over
+// the thresholds inside its 2^24-wide bucket (on average (n-1)/256 of them):
+// the same count as select_component's, from one table read and a short
+// scan instead of ceil(log2(n)) dependent reads.
+constexpr int kGuideBits = 8;
+constexpr int kGuideSize = 1 << kGuideBits;
+
+__device__ __forceinline__ void build_guide(const AtomSampling* samp, int n, int* guide,
+                                            int tid, int nthreads) {
+  const int last = n - 1;
+  for (int g = tid; g < kGuideSize; g += nthreads) {
+    const uint32_t x = (uint32_t)g << (32 - kGuideBits);
+    int c = 0;  // largest c <= last with thr_{c-1} <= x (thresholds non-decreasing)
+    if (last > 0) {
+      for (int step = 1 << (31 - __builtin_clz((unsigned)last)); step > 0; step >>= 1) {
+        const int t = c + step;
+        if (t <= last && samp[t - 1].thr <= x) c = t;
+      }
+    }
+    guide[g] = c;
+  }
+}
+
+__device__ __forceinline__ int select_component_guided(const AtomSampling* samp,
+                                                       const int* guide, int n,
+                                                       uint32_t word) {
+  const int last = n - 1;
+  int j = guide[word >> (32 - kGuideBits)];
+  while (j < last && word >= samp[j].thr) ++j;
+  return j;
+}
+
 // Sample point k of a molecule (exact draw from its normalised mixture):
 // component by integer thresholds, then r = c_j + z * sd_j per axis.
-// atoms/samp point at the molecule's own records (LDS or global).
+// atoms/samp point at the molecule's own records (LDS or global); guide, if
+// given, is the molecule's guide table (the component is the same).
 __device__ __forceinline__ void sample_point(const Atom* atoms, const AtomSampling* samp,
                                              int n, uint32_t mol_id, uint64_t k, uint2 key,
-                                             float& rx, float& ry, float& rz) {
+                                             float& rx, float& ry, float& rz,
+                                             const int* guide = nullptr) {
   const uint4 x = philox4x32_10(make_uint4((uint32_t)k, (uint32_t)(k >> 32), mol_id, 0u), key);
-  const int j = select_component(samp, n, x.x);
+  const int j = guide ? select_component_guided(samp, guide, n, x.x)
+                      : select_component(samp, n, x.x);
   const Atom c = atoms[j];
   const float sd = samp[j].sd;
   rx = fmaf(normal_from_bits(x.y), sd, c.x);
@@ -114,11 +152,13 @@ __device__ __forceinline__ void sample_point(const Atom* atoms, const AtomSampli
 // takes the normals with the opposite sign.
 __device__ __forceinline__ void sample_point_anti(const Atom* atoms, const AtomSampling* samp,
                                                   int n, uint32_t mol_id, uint64_t k, uint2 key,
-                                                  float& rx, float& ry, float& rz) {
+                                                  float& rx, float& ry, float& rz,
+                                                  const int* guide = nullptr) {
   const uint64_t p = k >> 1;
   const float sg = (k & 1) ? -1.0f : 1.0f;
   const uint4 x = philox4x32_10(make_uint4((uint32_t)p, (uint32_t)(p >> 32), mol_id, 0u), key);
-  const int j = select_component(samp, n, x.x);
+  const int j = guide ? select_component_guided(samp, guide, n, x.x)
+                      : select_component(samp, n, x.x);
   const Atom c = atoms[j];
   const float sd = samp[j].sd;
   rx = fmaf(sg * normal_from_bits(x.y), sd, c.x);
@@ -130,9 +170,10 @@ __device__ __forceinline__ void sample_point_anti(const Atom* atoms, const AtomS
 __device__ __forceinline__ void sample_pair(const Atom* atoms, const AtomSampling* samp, int n,
                                             uint32_t mol_id, uint64_t p, uint2 key, float& ax,
                                             float& ay, float& az, float& bx, float& by,
-                                            float& bz) {
+                                            float& bz, const int* guide = nullptr) {
   const uint4 x = philox4x32_10(make_uint4((uint32_t)p, (uint32_t)(p >> 32), mol_id, 0u), key);
-  const int j = select_component(samp, n, x.x);
+  const int j = guide ? select_component_guided(samp, guide, n, x.x)
+                      : select_component(samp, n, x.x);
   const Atom c = atoms[j];
   const float sd = samp[j].sd;
   const float zx = normal_from_bits(x.y), zy = normal_from_bits(x.z), zz = normal_from_bits(x.w);

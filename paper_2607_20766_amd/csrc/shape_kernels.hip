@@ -417,6 +417,7 @@ __global__ __launch_bounds__(64) void k_screen(ScreenArgs a) {
   //   sBB   [max_b] AtomRec + a2  library atoms, library frame (own density)
   //   sBA   [max_b] AtomRec + a2  library atoms, query frame (side A partner)
   //   sAB   [max_q] AtomRec + a2  query atoms, library frame (side B partner)
+  //   guide [kGuideSize] int      the library molecule's component guide
   // 16-byte records first, then the 8-byte, then the 4-byte arrays, so every
   // array is aligned to its element size whatever the atom counts.
   extern __shared__ __align__(16) unsigned char smem[];
@@ -428,6 +429,7 @@ __global__ __launch_bounds__(64) void k_screen(ScreenArgs a) {
   float* aBB = reinterpret_cast<float*>(sBS + a.max_b);
   float* aBA = aBB + a.max_b;
   float* aAB = aBA + a.max_b;
+  int* guide = reinterpret_cast<int*>(aAB + a.max_q);  // [kGuideSize] of the library molecule
   const int lane = threadIdx.x;
   // grid = n_pairs; a launch order, when given, is a permutation of the pairs
   const int p = a.order ? a.order[blockIdx.x] : xcd_chunk(blockIdx.x, gridDim.x);
@@ -462,6 +464,8 @@ __global__ __launch_bounds__(64) void k_screen(ScreenArgs a) {
     make_rec(at, cB.x, cB.y, cB.z, sBB[i], aBB[i]);
     make_rec(at, cA.x, cA.y, cA.z, sBA[i], aBA[i]);
   }
+  __syncthreads();
+  build_guide(sBS, nb, guide, lane, kWave);
   __syncthreads();
   const double Za = a.Q.Z[0];
   const uint32_t idb = a.L.id[m];
@@ -527,18 +531,18 @@ __global__ __launch_bounds__(64) void k_screen(ScreenArgs a) {
         const int i = ok ? t + s : t;
         if (!anti) {
           const int64_t k = n_side + (int64_t)lane + (int64_t)kWave * i;
-          sample_point(sBF, sBS, nb, idb, (uint64_t)k, a.key, rx[s], ry[s], rz[s]);
+          sample_point(sBF, sBS, nb, idb, (uint64_t)k, a.key, rx[s], ry[s], rz[s], guide);
         } else if (kSB % 2 == 0) {
           // both members of the pair from one Philox block (t and s even)
           if ((s & 1) == 0) {
             const int64_t pr = n_side / 2 + (int64_t)lane + (int64_t)kWave * (i >> 1);
             sample_pair(sBF, sBS, nb, idb, (uint64_t)pr, a.key, rx[s], ry[s], rz[s],
                         rx[s + 1 < kSB ? s + 1 : s], ry[s + 1 < kSB ? s + 1 : s],
-                        rz[s + 1 < kSB ? s + 1 : s]);
+                        rz[s + 1 < kSB ? s + 1 : s], guide);
           }
         } else {
           const int64_t k = n_side + 2 * (int64_t)lane + 2 * (int64_t)kWave * (i >> 1) + (i & 1);
-          sample_point_anti(sBF, sBS, nb, idb, (uint64_t)k, a.key, rx[s], ry[s], rz[s]);
+          sample_point_anti(sBF, sBS, nb, idb, (uint64_t)k, a.key, rx[s], ry[s], rz[s], guide);
         }
         valid[s] = ok ? 1.0f : 0.0f;
       }
@@ -883,7 +887,7 @@ hipError_t launch_work_order(const OrderArgs& o, int* order, int* work, hipStrea
 size_t screen_lds_bytes(int max_q, int max_b) {
   return (size_t)max_b * (sizeof(Atom) + 2 * (sizeof(AtomRec) + sizeof(float)) +
                           sizeof(AtomSampling)) +
-         (size_t)max_q * (sizeof(AtomRec) + sizeof(float));
+         (size_t)max_q * (sizeof(AtomRec) + sizeof(float)) + kGuideSize * sizeof(int);
 }
 
 template <int A, int B>
