@@ -48,8 +48,8 @@ PEAK_FP32_TFLOPS = 157.3
 # HBM bytes (FETCH_SIZE x2.0 + WRITE_SIZE x1.0, scaled by a 1 GiB copy of
 # known size) and executed wave instructions (SQ_INSTS_VALU,
 # SQ_INSTS_VALU_TRANS_F32).  None until taken on the current kernel.
-TRAFFIC_BYTES = 49011.1 * 1024 * 2.0 + 8340.4 * 1024 * 1.0
-VALU_INSTS = 6603888384
+TRAFFIC_BYTES = 48951.3 * 1024 * 2.0 + 7670.2 * 1024 * 1.0
+VALU_INSTS = 6483674909
 TRANS_INSTS = 744223320
 COUNTER_SOURCE = "profiles/k_screen_100k_library_counters.md"
 
