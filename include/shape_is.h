@@ -524,7 +524,8 @@ int shape_features(shape_ctx* ctx, const shape_mols* M, void* stream, float* out
  * m = p).  O(N_q N_m) per pair.  out: device float [n_pairs].  Asynchronous.
  * Reads the caller's arrays directly; an invalid molecule gives NaN and
  * raises the flag that shape_check_data reports; a pairs entry outside the
- * library gives NaN. */
+ * library gives NaN.  FP32 with the widths entering as 1/(log2(e) alpha):
+ * alpha from 1e-6 to 1e6 A^-2 (atomic widths are 0.1-10). */
 int shape_fo_overlap(shape_ctx* ctx, const shape_mols* query, const shape_mols* lib,
                      const int32_t* pairs, int32_t n_pairs, void* stream, float* out);
 
