@@ -174,8 +174,10 @@ int shape_estimate_noalloc(shape_ctx* ctx, const shape_mols* A, const shape_mols
  *   words  uint32 [n][4]: the Philox block of each sample (antithetic
  *          sampling: block k/2)
  *   comp   int32 [n]: the selected component #{i < N-1 : words[k][0] >= thr_i}
- *   r      float32 [n][3]: the sample point c_j + z sd_j (coordinates of M)
- * The same device functions as every sampling kernel compute these.
+ *          (by binary lifting over the thresholds)
+ *   r      float32 [n][3]: the sample point c_j + z sd_j (coordinates of M),
+ *          its component taken through the screening kernel's guide table
+ * The same device functions as the sampling kernels compute these.
  * Synchronises `stream` once (validity of the molecule) and then queues the
  * export asynchronously.  Errors: SHAPE_E_INVAL, SHAPE_E_RANGE, SHAPE_E_DATA
  * (invalid molecule), SHAPE_E_NOMEM, SHAPE_E_HIP; SHAPE_E_UNSUPPORTED during

@@ -621,9 +621,11 @@ __global__ __launch_bounds__(64) void k_screen(ScreenArgs a) {
 // Export of the sampling steps of one prepared molecule (section
 // "Importance-sampling estimator": exact draws from the normalised mixture),
 // for exact comparison of the integer steps: the molecule's thresholds, and
-// for samples k0 .. k0+n-1 the Philox block, the selected component and the
-// point, computed by the same device functions as every sampling kernel.
-// One thread per sample (and per atom for the thresholds); records from HBM.
+// for samples k0 .. k0+n-1 the Philox block, the selected component (binary
+// lifting, as in the single-pair, query-cache and alignment kernels) and the
+// point (through the guide table, as in the screening kernel), computed by
+// the same device functions as those kernels.  One thread per sample (and
+// per atom for the thresholds); records from HBM.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_sample_points(Prepared P, const int* __restrict__ off,
                                                        int mol, int64_t k0, int n, uint2 key,
@@ -631,11 +633,14 @@ __global__ __launch_bounds__(256) void k_sample_points(Prepared P, const int* __
                                                        uint32_t* __restrict__ words,
                                                        int* __restrict__ comp,
                                                        float* __restrict__ r) {
+  __shared__ int guide[kGuideSize];  // the screening kernel's table, one entry per thread
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int a0 = off[mol], na = off[mol + 1] - a0;
   const Atom* atoms = P.atom + a0;
   const AtomSampling* samp = P.samp + a0;
   if (thr && i < na) thr[i] = samp[i].thr;
+  build_guide(samp, na, guide, threadIdx.x, blockDim.x);
+  __syncthreads();
   if (i >= n) return;
   const uint64_t k = (uint64_t)(k0 + i);
   const uint64_t blk = anti ? k >> 1 : k;
@@ -644,11 +649,13 @@ __global__ __launch_bounds__(256) void k_sample_points(Prepared P, const int* __
   if (words) reinterpret_cast<uint4*>(words)[i] = x;
   if (comp) comp[i] = select_component(samp, na, x.x);
   if (r) {
+    // the point through the guide table: a component other than comp's
+    // would move it far outside the bound of its floating-point steps
     float rx, ry, rz;
     if (anti)
-      sample_point_anti(atoms, samp, na, P.id[mol], k, key, rx, ry, rz);
+      sample_point_anti(atoms, samp, na, P.id[mol], k, key, rx, ry, rz, guide);
     else
-      sample_point(atoms, samp, na, P.id[mol], k, key, rx, ry, rz);
+      sample_point(atoms, samp, na, P.id[mol], k, key, rx, ry, rz, guide);
     r[3 * (size_t)i] = rx;
     r[3 * (size_t)i + 1] = ry;
     r[3 * (size_t)i + 2] = rz;

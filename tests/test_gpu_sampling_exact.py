@@ -2,8 +2,10 @@
 "Importance-sampling estimator": exact draws from the normalised mixture q =
 m/Z) between the HIP path and the FP64 oracle, through shape_sample_points:
 the uint32 thresholds, the Philox blocks and the selected component indices
-are compared exactly; the points within the bound their floating-point steps
-allow.  Molecules of 1, 2, 63, 64, 65 and 256 atoms (a single component, one
+(binary lifting) are compared exactly; the points, whose component is taken
+through the screening kernel's guide table, within the bound their
+floating-point steps allow (another component would put a point an atom's
+distance away).  Molecules of 1, 2, 63, 64, 65 and 256 atoms (a single component, one
 threshold, sizes about the 64-lane width, SHAPE_MAX_ATOMS), counters on both
 sides of 2^32, a molecule that is not the first of its set, and antithetic
 sampling."""
