@@ -468,8 +468,10 @@ __global__ __launch_bounds__(64) void k_fo_align(FoAlignArgs a) {
 // c''_j x (s d) = c_i x (s d), so the torque about B's origin is
 // sum_i c_i x F_i less t x sum F, formed once per lane instead of per term;
 // dO/dc''_j = 2 k K d = -2 ln(2) kk K d scales F once at the end.
-// Every lane of a row holds the same pose, moments and gradient (row sums
-// leave identical bits in all 16 lanes), so Adam runs redundantly per lane.
+// Every lane of a row holds the same pose and gradient (row sums leave
+// identical bits in all 16 lanes); Adam's seven components are updated one
+// per lane (lanes 0-6 of the row, with their moments) and read back by the
+// whole row, instead of all seven in every lane.
 // ---------------------------------------------------------------------------
 template <int RA>
 __global__ __launch_bounds__(256) void k_fo_align_rows(FoAlignArgs a) {
@@ -526,14 +528,14 @@ __global__ __launch_bounds__(256) void k_fo_align_rows(FoAlignArgs a) {
   }
   float4* mine = sM + (size_t)(wave * 4 + row) * stride;
   const float2* trow = tab + l16;
-  float x[7], m[7], v[7];
+  // the pose in every lane of the row; Adam's moments of component
+  // cA = min(l16, 6) in lane l16 (lanes past 6 repeat component 6)
+  float x[7];
   float* ps = a.pose + item * 7;
 #pragma unroll
-  for (int c = 0; c < 7; ++c) {
-    x[c] = ps[c];
-    m[c] = 0.f;
-    v[c] = 0.f;
-  }
+  for (int c = 0; c < 7; ++c) x[c] = ps[c];
+  const int cA = l16 < 7 ? l16 : 6;
+  float mA = 0.f, vA = 0.f;
   const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
   float b1t = 1.f, b2t = 1.f;
   float T = 0.f, g[7];
@@ -606,7 +608,6 @@ __global__ __launch_bounds__(256) void k_fo_align_rows(FoAlignArgs a) {
     r7[5] = sc * row_sum16(ty) - (x[6] * r7[1] - x[4] * r7[3]);
     r7[6] = sc * row_sum16(tz) - (x[4] * r7[2] - x[5] * r7[1]);
     const float D = S - r7[0];
-    T = r7[0] / D;
     const float iD = __builtin_amdgcn_rcpf(D);
     const float dTdO = S * iD * iD;
     const float gth[3] = {dTdO * r7[4], dTdO * r7[5], dTdO * r7[6]};
@@ -618,21 +619,34 @@ __global__ __launch_bounds__(256) void k_fo_align_rows(FoAlignArgs a) {
     g[4] = dTdO * r7[1];
     g[5] = dTdO * r7[2];
     g[6] = dTdO * r7[3];
-    if (it == a.n_steps) break;
-    // Adam on -T, as in the one-start-per-wave kernel, every component in
-    // every lane of the row
+    if (it == a.n_steps) {
+      T = r7[0] / D;  // only the final pose's T is returned
+      break;
+    }
+    // Adam on -T, the one-start-per-wave kernel's arithmetic: lane l16 < 7
+    // of the row updates component l16, then the row reads the seven new
+    // components back from those lanes
     b1t *= b1;
     b2t *= b2;
     const float ic1 = __builtin_amdgcn_rcpf(1.f - b1t), ic2 = __builtin_amdgcn_rcpf(1.f - b2t);
+    float gA = g[0], xA = x[0];
+#pragma unroll
+    for (int c = 1; c < 7; ++c) {
+      if (cA == c) {
+        gA = g[c];
+        xA = x[c];
+      }
+    }
+    {
+      const float gc = -gA;
+      mA = fmaf(b1, mA, (1.f - b1) * gc);
+      vA = fmaf(b2, vA, (1.f - b2) * gc * gc);
+      const float den = __builtin_amdgcn_sqrtf(vA * ic2) + eps;
+      xA = xA - a.lr * (mA * ic1) * __builtin_amdgcn_rcpf(den);
+    }
     float xn[7];
 #pragma unroll
-    for (int c = 0; c < 7; ++c) {
-      const float gc = -g[c];
-      m[c] = fmaf(b1, m[c], (1.f - b1) * gc);
-      v[c] = fmaf(b2, v[c], (1.f - b2) * gc * gc);
-      const float den = __builtin_amdgcn_sqrtf(v[c] * ic2) + eps;
-      xn[c] = x[c] - a.lr * (m[c] * ic1) * __builtin_amdgcn_rcpf(den);
-    }
+    for (int c = 0; c < 7; ++c) xn[c] = __shfl(xA, (lane & ~15) + c, kWave);
     const float inv = rsqrtf(xn[0] * xn[0] + xn[1] * xn[1] + xn[2] * xn[2] + xn[3] * xn[3]);
 #pragma unroll
     for (int c = 0; c < 4; ++c) x[c] = xn[c] * inv;
