@@ -93,8 +93,8 @@ int main(void) {
   expect("screen cap not whole rounds", or_screen(NQ, xq, aq, 1, NL, off, lx, la, ids, NULL,
                                                   NL, 1, 0, 512, 1000, 0.01, 3, 1, NULL, 0,
                                                   out6), -2);
-  expect("screen round 1", or_screen(NQ, xq, aq, 1, NL, off, lx, la, ids, NULL, NL, 1, 0, 1, 4,
-                                     0.01, 3, 1, NULL, 0, out6), -2);
+  expect("screen odd round size", or_screen(NQ, xq, aq, 1, NL, off, lx, la, ids, NULL, NL, 1, 0,
+                                            1, 4, 0.01, 3, 1, NULL, 0, out6), -2);
 
   double s = or_incexc(5, lx + 3 * off[4], la + off[4], 3, lx, la);
   printf("%-34s %.6f\n", "incexc", s);
