@@ -314,3 +314,40 @@ def test_long_screen_in_launch_order_same_bits(case):
         assert np.array_equal(full[k], got, equal_nan=k != "n_used"), k
     assert np.all(np.isnan(full["T"][bad])) and np.all(full["n_used"][bad] == 0)
     assert np.all(np.isfinite(full["T"][~bad]))
+
+
+def test_long_screen_order_edge_cases():
+    """The launch order at its threshold (exactly 16 pairs per compute unit)
+    with budgets below zero, zero and far above the cap, against calls too
+    small to be reordered, bit for bit; and a long screen whose pairs all lie
+    outside the library (every output NaN, no samples)."""
+    require_gpu()
+    e = Engine(0)
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    n = 16 * n_cu
+    q = molgen.molecule(1, 0, 30)
+    L = molgen.library(28, 1500, 5, 60, workers=4)
+    Q, lib = e.molecules(q, mol_id=[QUERY_ID]), e.molecules(L)
+    dev = e.torch_device
+    rng = np.random.default_rng(28)
+    pairs = rng.integers(0, L.n_mols, n).astype(np.int32)
+    n_start = rng.choice(np.array([-5, 0, 512, 3000, 10**9], np.int32), n)
+    kw = dict(mode=SHAPE_SCREEN_ADAPTIVE, round_per_pair=512, cap_per_pair=4096, tau=0.01,
+              seed=8)
+    print(f"case: {n} pairs at the threshold, extreme budgets", flush=True)
+    full = _to_np(e.shape_screen(Q, lib, pairs=torch.from_numpy(pairs).to(dev),
+                                 n_start=torch.from_numpy(n_start).to(dev), **kw))
+    parts = []
+    for a in range(0, n, 777):
+        sl = slice(a, min(n, a + 777))
+        parts.append(_to_np(e.shape_screen(Q, lib, pairs=torch.from_numpy(pairs[sl]).to(dev),
+                                           n_start=torch.from_numpy(n_start[sl]).to(dev),
+                                           **kw)))
+    for k in full:
+        assert np.array_equal(full[k], np.concatenate([p[k] for p in parts])), k
+    assert np.all(full["n_used"][n_start >= 4096] == 4096)
+    print("case: a long screen of pairs outside the library", flush=True)
+    bad = torch.full((n + 5,), -1, dtype=torch.int32, device=dev)
+    bad[::2] = L.n_mols
+    out = _to_np(e.shape_screen(Q, lib, pairs=bad, **kw))
+    assert np.all(np.isnan(out["T"])) and np.all(out["n_used"] == 0)
