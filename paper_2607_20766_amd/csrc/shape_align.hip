@@ -21,7 +21,7 @@ namespace shape {
 
 constexpr int kAlignThreads = 256;
 constexpr int kAlignWaves = kAlignThreads / kWave;
-constexpr int kAS = 2;  // points per lane evaluated together
+constexpr int kAS = 4;  // points per lane evaluated together
 
 __device__ __forceinline__ void quat_rotation(float qw, float qx, float qy, float qz,
                                               float (&R)[9], float& inv_norm) {
