@@ -517,8 +517,13 @@ int shape_apply_pose(shape_ctx* ctx, const shape_mols* M, const float* pose, voi
  * - mu mu^T; [19..22] atoms per width class (alpha < 0.767, < 0.893, < 0.995,
  * otherwise); [23] the first-order self-overlap (Eq. fo with B = A).
  * Reads the caller's arrays directly; invalid molecules (as in shape_screen)
- * give NaN rows and raise the flag that shape_check_data reports.
- * Asynchronous. */
+ * give NaN rows and raise the flag that shape_check_data reports.  From 512
+ * molecules per compute unit on, the molecules are taken in descending
+ * order of their squared atom count (computed on the device in the same
+ * call, 4 (n_mols + 133120) bytes of context scratch) so that each wave's
+ * four molecules are of about one size; every row is the same in any order.
+ * Asynchronous.  Errors: SHAPE_E_INVAL, SHAPE_E_RANGE, SHAPE_E_NOMEM,
+ * SHAPE_E_HIP. */
 int shape_features(shape_ctx* ctx, const shape_mols* M, void* stream, float* out);
 
 /* First-order cross-overlap (Eq. fo) of the query with library molecules at

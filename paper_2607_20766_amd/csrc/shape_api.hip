@@ -329,6 +329,9 @@ struct ProfRange {
 constexpr int kOrderScreenPerCu = 16;
 constexpr int kOrderAlignPerCu = 4;
 constexpr int kOrderFoAlignPerCu = 16;
+// Features: the order groups molecules of one size into a wave (it matters
+// at any size, but its three launches cost a few microseconds).
+constexpr int kOrderFeaturesPerCu = 512;
 
 // The context's launch-order buffers for n pairs (the sort's work area, then
 // the order), or nullptr when the grid is too short for the order to matter.
@@ -1368,8 +1371,22 @@ int shape_features(shape_ctx* c, const shape_mols* M, void* stream, float* out) 
     hipStream_t st = (hipStream_t)stream;
     void* mom;
     if ((rc = ensure(c, S_FEAT_MOM, (size_t)M->n_mols * 6 * sizeof(float), &mom))) return rc;
+    WorkOrder wo;
+    if ((rc = work_order_slot(c, M->n_mols, kOrderFeaturesPerCu, &wo))) return rc;
     KernelTimer timer(c, st);
-    HIP_TRY(c, shape::launch_features(mols_dev(M), c->flag, out, (float*)mom, st),
+    if (wo.order) {
+      // molecules by descending squared atom count (the overlap triangle)
+      shape::OrderArgs o{};
+      o.n = M->n_mols;
+      o.offB = M->atom_offset;
+      o.nB_mols = M->n_mols;
+      o.max_b = M->max_atoms;
+      o.quad_b = 1;
+      o.wB = 1;
+      o.w0 = 64;
+      HIP_TRY(c, shape::launch_work_order(o, wo.order, wo.work, st), "features launch order");
+    }
+    HIP_TRY(c, shape::launch_features(mols_dev(M), c->flag, out, (float*)mom, st, wo.order),
             "features kernel");
     timer.stop();
     return SHAPE_OK;

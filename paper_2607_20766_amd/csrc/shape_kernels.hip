@@ -733,7 +733,8 @@ hipError_t launch_sample_points(const Prepared& P, const int* off, int mol, int 
 // first.  A pair's result depends on that pair alone, so the order in which
 // workgroups take the pairs changes no output; it changes how long the last
 // workgroups run on after the others have finished.  The caller states the
-// work of a pair in atoms' worth from its atom counts (and seeded budget);
+// work of a pair in atoms' worth from its atom counts (B's, or their square,
+// in a quadratic pass) and seeded budget;
 // pairs are bucketed by its logarithm, 8 buckets per octave.  With per_xcd,
 // each XCD keeps the pairs xcd_chunk deals it (so its L2 still sees whole
 // tiles of consecutive molecules and output lines) and takes them largest
@@ -768,7 +769,8 @@ __device__ __forceinline__ int order_key(const OrderArgs& o, int p) {
   const int g = o.per_xcd ? xcd_of_item(p, o.n) : 0;
   const int m = o.pairs ? o.pairs[p] : p;
   if (m < 0 || m >= o.nB_mols) return g * kOrderKeys;  // an invalid pair only writes NaN
-  uint64_t cost = (uint64_t)o.wB * (uint64_t)atoms_of(o.offB, m, o.max_b) + o.w0;
+  const uint64_t nb = (uint64_t)atoms_of(o.offB, m, o.max_b);
+  uint64_t cost = (uint64_t)o.wB * (o.quad_b ? nb * nb : nb) + o.w0;
   if (o.offA) {
     const int ma = o.a_single ? 0 : p;
     if (ma < o.nA_mols) cost += (uint64_t)o.wA * (uint64_t)atoms_of(o.offA, ma, o.max_a);

@@ -111,9 +111,10 @@ struct GemmArgs {
 int gemm_splits(const GemmArgs& g);
 
 // Features and first-order cross-overlaps read the caller's arrays directly;
-// invalid molecules give NaN and raise *flag.
+// invalid molecules give NaN and raise *flag.  order (optional): a
+// permutation of the molecules, taken four to a wave in its order.
 hipError_t launch_features(const MolsDev& M, int* flag, float* out, float* mom,
-                           hipStream_t st);
+                           hipStream_t st, const int* order = nullptr);
 hipError_t launch_pair_features(const float* fq, const float* flib, const int* qidx,
                                 const int* idx, int n, const float* fo_cross, const float* mean,
                                 const float* inv_std, float* out, hipStream_t st);
@@ -242,6 +243,7 @@ struct OrderArgs {
   int nA_mols, max_a, a_single;
   const int* offB;
   int nB_mols, max_b;
+  int quad_b;           // B's term is wB n_B^2 (else wB n_B)
   uint32_t wA, wB, w0;
   const int* n_start;   // optional per-pair sample budgets
   int64_t round_pair, cap;

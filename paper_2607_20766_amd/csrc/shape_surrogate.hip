@@ -4,6 +4,7 @@
 #include "shape_kernels.hpp"
 
 #include <algorithm>
+#include <utility>
 #include <vector>
 
 #include <math.h>
@@ -55,9 +56,60 @@ __device__ void sym3_eigen_desc(double a00, double a11, double a22, double a01, 
       }
 }
 
-// First-order Gaussian pair terms (pi/(a+b))^(3/2) exp(-a b/(a+b) d2) below:
-// rs = 1/sqrt(a+b) from one hardware rsqrt gives (a+b)^(-3/2) = rs^3 and
-// 1/(a+b) = rs^2; exp by exp2 (features, not estimates: ~1e-6 relative).
+// First-order Gaussian pair terms (pi/(a+b))^(3/2) exp(-a b/(a+b) d2) below,
+// from hardware rsqrt, reciprocal and exp2 (features, not estimates: ~1e-6
+// relative): a diagonal term (2a)^(-3/2) is rs^3 with rs = 1/sqrt(2a).
+
+// Pair terms of the self-overlap triangle in the width form of the
+// cross-overlaps: with b = 1/(log2(e) a) and B = b^(3/2) per atom and
+// k = 1/(b_i + b_j), the term (a_i + a_j)^(-3/2) exp(-a_i a_j/(a_i+a_j) d2)
+// is log2(e)^(3/2) B_i B_j k^(3/2) exp2(-k d2).  Padding atoms have B = 0
+// and b = 1 (finite, no contribution).  FP32 for widths from 1e-6 to 1e6.
+struct TriAtom {
+  float x, y, z, b, B;
+};
+
+__device__ __forceinline__ TriAtom tri_atom(const float4* sC, int i, int n) {
+  TriAtom t{0.f, 0.f, 0.f, 1.f, 0.f};
+  if (i < n) {
+    const float4 c = sC[i];
+    t.x = c.x; t.y = c.y; t.z = c.z;
+    t.b = __builtin_amdgcn_rcpf(1.44269504088896f * c.w);
+    t.B = t.b * __builtin_amdgcn_sqrtf(t.b);
+  }
+  return t;
+}
+
+// v from the lane C places before this one in its row of 16 (row rotation)
+template <int C>
+__device__ __forceinline__ float row_ror(float v) {
+  if constexpr (C == 0) {
+    return v;
+  } else {
+    return __builtin_bit_cast(
+        float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x120 + C, 0xf, 0xf, true));
+  }
+}
+
+// acc + B_p k^(3/2) exp2(-k d2) for this lane's atom s and the atom p of the
+// lane C places back in the row
+template <int C>
+__device__ __forceinline__ float tri_term(const TriAtom& s, const TriAtom& p, float acc) {
+  const float dx = row_ror<C>(p.x) - s.x, dy = row_ror<C>(p.y) - s.y,
+              dz = row_ror<C>(p.z) - s.z;
+  const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+  const float r = __builtin_amdgcn_rsqf(row_ror<C>(p.b) + s.b);
+  const float kk = r * r;
+  const float e = __builtin_amdgcn_exp2f(-kk * d2);
+  return fmaf(row_ror<C>(p.B) * (kk * r), e, acc);
+}
+
+template <int... C>
+__device__ __forceinline__ float tri_terms(const TriAtom& s, const TriAtom& p, float acc,
+                                           std::integer_sequence<int, C...>) {
+  ((acc = tri_term<C>(s, p, acc)), ...);
+  return acc;
+}
 
 // The caller's arrays are read directly (no preparation pass): validity as
 // in the preparation (offsets in range, 1..max_atoms atoms, alpha > 0, all
@@ -68,16 +120,27 @@ __device__ void sym3_eigen_desc(double a00, double a11, double a22, double a01, 
 // its row's lanes, and each sum is a 16-lane row sum (row_sum16, the same
 // bits in every lane of the row).  Histogram and width-class counts are
 // integer LDS atomics (exact, independent of their order).  The overlap
-// triangle i < j is flattened over the row's 16 lanes.
+// triangle i < j runs over 16-atom blocks, so a wave runs as long as its
+// largest molecule's triangle: given a launch order (molecules
+// by descending size, order[slot] = molecule), the wave's four rows take
+// slots 4 b .. 4 b + 3 and hold molecules of about one size.  A molecule's
+// features depend on it alone, so the order changes no output.
 constexpr int kFeatRows = 4;
 
-__global__ __launch_bounds__(64) void k_features(MolsDev in, int* __restrict__ flag,
+__global__ __launch_bounds__(64) void k_features(MolsDev in, const int* __restrict__ order,
+                                                 int* __restrict__ flag,
                                                  float* __restrict__ out,
                                                  float* __restrict__ mom) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int sCount[kFeatRows][20];  // 16 radial bins, 4 width classes
   const int lane = threadIdx.x, l16 = lane & 15, row = lane >> 4;
-  const int mol = xcd_chunk(blockIdx.x, gridDim.x) * kFeatRows + row;
+  int mol;
+  if (order) {
+    const int slot = blockIdx.x * kFeatRows + row;
+    mol = slot < in.n_mols ? order[slot] : in.n_mols;
+  } else {
+    mol = xcd_chunk(blockIdx.x, gridDim.x) * kFeatRows + row;
+  }
   float4* sC = reinterpret_cast<float4*>(smem) + (size_t)row * in.max_atoms;  // x, y, z, alpha
   const bool live = mol < in.n_mols;
   int a0 = 0, n = 0;
@@ -90,17 +153,31 @@ __global__ __launch_bounds__(64) void k_features(MolsDev in, int* __restrict__ f
     if (bad) n = 0;
   }
   for (int k = l16; k < 20; k += 16) sCount[row][k] = 0;
+  // staging: the row's first 64 atoms (four per lane) are requested before
+  // any is used, so that their loads overlap; larger molecules go on in a
+  // loop
   float zl = 0.f;
-  for (int i = l16; i < n; i += 16) {
-    const float al = in.alpha[a0 + i];
-    const float x = in.xyz[3 * (a0 + i)], y = in.xyz[3 * (a0 + i) + 1],
-                z = in.xyz[3 * (a0 + i) + 2];
-    if (!(al > 0.0f) || !isfinite(al) || !isfinite(x) || !isfinite(y) || !isfinite(z))
+  const auto stage = [&](float4 c, int i) {
+    if (!(c.w > 0.0f) || !isfinite(c.w) || !isfinite(c.x) || !isfinite(c.y) || !isfinite(c.z))
       bad = true;
-    sC[i] = make_float4(x, y, z, al);
-    const float t = 3.14159265358979f * __builtin_amdgcn_rcpf(al);
+    sC[i] = c;
+    const float t = 3.14159265358979f * __builtin_amdgcn_rcpf(c.w);
     zl += t * __builtin_amdgcn_sqrtf(t);
+  };
+  const auto fetch = [&](int i) {
+    const float* p = in.xyz + 3 * (int64_t)(a0 + i);
+    return make_float4(p[0], p[1], p[2], in.alpha[a0 + i]);
+  };
+  {
+    float4 st[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (l16 + 16 * k < n) st[k] = fetch(l16 + 16 * k);
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (l16 + 16 * k < n) stage(st[k], l16 + 16 * k);
   }
+  for (int i = l16 + 64; i < n; i += 16) stage(fetch(i), i);
   // a row is bad if any of its lanes saw bad data: OR over the row's bits
   const uint64_t bb = __ballot(bad);
   bad = ((bb >> (16 * row)) & 0xFFFFull) != 0;
@@ -137,37 +214,34 @@ __global__ __launch_bounds__(64) void k_features(MolsDev in, int* __restrict__ f
   }
   sxx = row_sum16(sxx); syy = row_sum16(syy); szz = row_sum16(szz);
   sxy = row_sum16(sxy); sxz = row_sum16(sxz); syz = row_sum16(syz);
-  // first-order self-overlap: diagonal + 2 x the i < j triangle, flattened.
-  // Terms are summed as (a+b)^(-3/2) exp(-ab/(a+b) d2); pi^(3/2) and the
-  // triangle's factor 2 are applied to the row sums.
+  // first-order self-overlap: diagonal + 2 x the i < j triangle.  Diagonal
+  // terms are summed as (2a)^(-3/2); pi^(3/2) and the triangle's factor 2
+  // are applied to the row sums.
   float fo = 0.f, tri = 0.f;
   for (int i = l16; i < n; i += 16) {
     const float a = sC[i].w, rs = __builtin_amdgcn_rsqf(a + a);
     fo = fmaf(rs * rs, rs, fo);
   }
-  // strict upper triangle i < j in row-major order, flat index p = l16 +
-  // 16 t: the first position from the row lengths, then stepped by 16
-  // (row i holds j = i+1 .. n-1)
-  int i = 0, j = 1 + l16;
-  while (i < n - 1 && j >= n) {
-    j -= n - i - 2;  // j - n + (i + 2): onto the next row
-    ++i;
-  }
-  while (i < n - 1) {
-    const float4 ci = sC[i], cj = sC[j];
-    const float dx = ci.x - cj.x, dy = ci.y - cj.y, dz = ci.z - cj.z;
-    const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-    const float rs = __builtin_amdgcn_rsqf(ci.w + cj.w);
-    const float ir = rs * rs;
-    const float e = __builtin_amdgcn_exp2f((-1.44269504088896f * ci.w) * cj.w * ir * d2);
-    tri = fmaf(ir * rs, e, tri);
-    j += 16;
-    while (i < n - 1 && j >= n) {
-      j -= n - i - 2;
-      ++i;
+  // The triangle by 16-atom blocks a <= b of the row's atoms (padded with
+  // atoms of weight 0): each lane holds one atom of block a and one of block
+  // b, and row rotations bring it every atom of block b in turn (tri_terms),
+  // so the terms read no LDS.
+  const int nb = (n + 15) >> 4;
+  for (int ba = 0; ba < nb; ++ba) {
+    const TriAtom own = tri_atom(sC, 16 * ba + l16, n);
+    // the diagonal block: rotations 1..7, and 8 on half of the lanes (the
+    // pairs at rotation 8 are met twice in the row)
+    float acc = tri_terms(own, own, 0.f, std::integer_sequence<int, 1, 2, 3, 4, 5, 6, 7>{});
+    const float a8 = tri_term<8>(own, own, 0.f);
+    acc += l16 < 8 ? a8 : 0.f;
+    for (int bb = ba + 1; bb < nb; ++bb) {
+      const TriAtom other = tri_atom(sC, 16 * bb + l16, n);
+      acc = tri_terms(own, other, acc, std::make_integer_sequence<int, 16>{});
     }
+    tri = fmaf(own.B, acc, tri);
   }
-  const float fo_sum = 5.56832799683170785f * (row_sum16(fo) + 2.0f * row_sum16(tri));
+  const float fo_sum =
+      5.56832799683170785f * (row_sum16(fo) + 2.0f * 1.73285334265681730f * row_sum16(tri));
   wave_lds_sync();  // the counts are complete
   if (!live) return;
   float* f = out + (size_t)mol * 24;
@@ -1891,11 +1965,11 @@ __global__ __launch_bounds__(256) void k_select_write(const float* __restrict__ 
 // Launchers.
 // ---------------------------------------------------------------------------
 hipError_t launch_features(const MolsDev& M, int* flag, float* out, float* mom,
-                           hipStream_t st) {
+                           hipStream_t st, const int* order) {
   if (M.n_mols <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_features, dim3((unsigned)((M.n_mols + kFeatRows - 1) / kFeatRows)),
-                     dim3(kWave), (size_t)kFeatRows * M.max_atoms * sizeof(float4), st, M, flag,
-                     out, mom);
+                     dim3(kWave), (size_t)kFeatRows * M.max_atoms * sizeof(float4), st, M,
+                     order, flag, out, mom);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_features_eigen, dim3((unsigned)((M.n_mols + 255) / 256)), dim3(256), 0,

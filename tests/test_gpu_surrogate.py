@@ -8,7 +8,8 @@ import torch
 
 import oracle as O
 from paper_2607_20766_amd import molgen
-from paper_2607_20766_amd.engine import LAMBDA_P27, SHAPE_SCREEN_ADAPTIVE, Engine, ShapeError
+from paper_2607_20766_amd.engine import (LAMBDA_P27, SHAPE_SCREEN_ADAPTIVE, Engine, Molecules,
+                                         ShapeError)
 from paper_2607_20766_amd.surrogate import MLP, WIDTH, Triage, init_params, n_params
 from tests.gpu_common import require_gpu
 
@@ -41,6 +42,42 @@ def test_features_match_oracle(eng):
     assert np.all(diff.sum(1) == 0) and np.abs(diff).sum() <= 2
     assert np.allclose(g[:, 16:19], r[:, 16:19], rtol=1e-5, atol=1e-6)
     assert np.allclose(g[:, 23], r[:, 23], rtol=1e-5)
+
+
+def test_large_library_features_in_launch_order_same_bits(eng):
+    """From 512 molecules per compute unit on, the features kernel takes the
+    molecules in descending order of their squared atom count (four to a
+    wave); every row equals the row of the same molecule in a call of 5,000
+    molecules, which keeps the plain order, bit for bit.  1- to 96-atom
+    molecules drawn with repeats from 3,000; two invalid ones give NaN rows
+    and the data-error flag."""
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    n = 512 * n_cu + 77
+    L0 = molgen.library(27, 3000, 1, 96, workers=4)
+    L = L0.subset(np.random.default_rng(27).integers(0, L0.n_mols, n))
+    L.xyz[L.offsets[17] + 2, 1] = np.nan
+    lib = eng.molecules(L)
+    lib.alpha[int(L.offsets[n - 5])] = -1.0
+    print(f"features of {n} molecules", flush=True)
+    full = eng.shape_features(lib).cpu().numpy()
+    with pytest.raises(ShapeError):
+        eng.shape_check_data()
+    eng.shape_check_data()
+    bad = [17, n - 5]
+    assert np.isnan(full[bad]).all()
+    assert np.isfinite(np.delete(full, bad, 0)).all()
+    parts = []
+    for a in range(0, n, 5000):
+        b = min(n, a + 5000)
+        o0, o1 = int(L.offsets[a]), int(L.offsets[b])
+        part = Molecules((lib.offsets[a:b + 1] - o0).contiguous(), lib.xyz[o0:o1],
+                         lib.alpha[o0:o1], None, lib.max_atoms)
+        parts.append(eng.shape_features(part).cpu().numpy())
+    with pytest.raises(ShapeError):
+        eng.shape_check_data()
+    eng.shape_check_data()
+    plain = np.concatenate(parts)
+    assert np.array_equal(full, plain, equal_nan=True)
 
 
 @pytest.mark.parametrize("bf16", [False, True])
