@@ -455,14 +455,15 @@ __global__ __launch_bounds__(64) void k_fo_align(FoAlignArgs a) {
 // i = l + 16 r (r < RA; rows past N_A are padding whose terms add exactly
 // 0) and walks all of B's moved atoms, read as LDS
 // broadcasts.  The pose-independent constants of every atom pair,
-// kk = -log2(e) k_ij and lp = log2((pi/(a_i+a_j))^(3/2)), sit in an LDS table
-// filled once per workgroup (padding rows: kk = 0, lp = -inf, so K = 0).
-// Per term, with d = c_i - c''_j:
-//   |d|^2 = (|c_i|^2 + |c''_j|^2) + (-2 c_i) . c''_j   (|c''_j|^2 stored with
-//           the moved atom)
-//   K = exp2(kk |d|^2 + lp)
-// (FP32 emulation on drug-sized molecules against FP64: relative error of O
-// at most 4.7e-7, of its gradient 8.2e-6; 11 VALU + exp per term.)
+// kk = -log2(e) k_ij and lq = log2((pi/(a_i+a_j))^(3/2)) + kk |c_i|^2 (A's
+// atoms do not move), sit in an LDS table filled once per workgroup (padding
+// rows: kk = 0, lq = -inf, so K = 0).  Per term, with d = c_i - c''_j and
+// |d|^2 = |c_i|^2 + |c''_j|^2 + (-2 c_i) . c''_j:
+//   K = exp2(kk (|c''_j|^2 + (-2 c_i) . c''_j) + lq)   (|c''_j|^2 stored
+//       with the moved atom)
+// (FP32 emulation on drug-sized molecules at random poses against FP64:
+// relative error of O at most 7.7e-7, of its gradient 2.2e-6 (1.0e-6 and
+// 3.3e-6 with |c_i|^2 added per term); 10 VALU + exp per term.)
 // and the lane keeps O_i = sum_j K, W_i = sum_j kk K, P_i = sum_j kk K c''_j,
 // so that F_i = sum_j kk K d = c_i W_i - P_i.  Since dO/dc''_j is parallel to d,
 // c''_j x (s d) = c_i x (s d), so the torque about B's origin is
@@ -510,13 +511,17 @@ __global__ __launch_bounds__(256) void k_fo_align_rows(FoAlignArgs a) {
   __syncthreads();
   for (int e = tid; e < nb * RA16; e += blockDim.x) {
     const int j = e / RA16, i = e % RA16;
-    float kk = 0.f, pre = 0.f, f2;
-    if (i < na) fo_consts(sA[i].w, sB[j].w, kk, pre, f2);
-    tab[e] = make_float2(kk, i < na ? log2f(pre) : -INFINITY);
+    float kk = 0.f, pre = 0.f, f2, lq = -INFINITY;
+    if (i < na) {
+      const float4 c = sA[i];
+      fo_consts(c.w, sB[j].w, kk, pre, f2);
+      lq = fmaf(kk, norm2(c.x, c.y, c.z), log2f(pre));
+    }
+    tab[e] = make_float2(kk, lq);
   }
   __syncthreads();
   const float S = fo_self(sA, na) + fo_self(sB, nb);  // O_AA + O_BB
-  float cx[RA], cy[RA], cz[RA], ci2[RA];
+  float cx[RA], cy[RA], cz[RA];
 #pragma unroll
   for (int r = 0; r < RA; ++r) {
     const int i = l16 + 16 * r;
@@ -524,7 +529,6 @@ __global__ __launch_bounds__(256) void k_fo_align_rows(FoAlignArgs a) {
     cx[r] = c.x;
     cy[r] = c.y;
     cz[r] = c.z;
-    ci2[r] = norm2(c.x, c.y, c.z);
   }
   float4* mine = sM + (size_t)(wave * 4 + row) * stride;
   const float2* trow = tab + l16;
@@ -565,9 +569,9 @@ __global__ __launch_bounds__(256) void k_fo_align_rows(FoAlignArgs a) {
 #pragma unroll
       for (int r = 0; r < RA; ++r) {
         const float2 kp = trow[j * RA16 + 16 * r];
-        const float d2 = fmaf(-2.f * cx[r], cj.x,
-                              fmaf(-2.f * cy[r], cj.y, fmaf(-2.f * cz[r], cj.z, ci2[r] + cj.w)));
-        const float K = __builtin_amdgcn_exp2f(fmaf(kp.x, d2, kp.y));
+        const float e = fmaf(-2.f * cx[r], cj.x,
+                             fmaf(-2.f * cy[r], cj.y, fmaf(-2.f * cz[r], cj.z, cj.w)));
+        const float K = __builtin_amdgcn_exp2f(fmaf(kp.x, e, kp.y));
         O[r] += K;
         const float fs = kp.x * K;
         W[r] += fs;
