@@ -215,8 +215,8 @@ __global__ __launch_bounds__(64) void k_features(MolsDev in, const int* __restri
   sxx = row_sum16(sxx); syy = row_sum16(syy); szz = row_sum16(szz);
   sxy = row_sum16(sxy); sxz = row_sum16(sxz); syz = row_sum16(syz);
   // first-order self-overlap: diagonal + 2 x the i < j triangle.  Diagonal
-  // terms are summed as (2a)^(-3/2); pi^(3/2) and the triangle's factor 2
-  // are applied to the row sums.
+  // terms are summed as (2a)^(-3/2); pi^(3/2), the triangle's factor 2 and
+  // the width form's log2(e)^(3/2) are applied to the row sums.
   float fo = 0.f, tri = 0.f;
   for (int i = l16; i < n; i += 16) {
     const float a = sC[i].w, rs = __builtin_amdgcn_rsqf(a + a);
