@@ -181,6 +181,22 @@ def test_topk_exact(eng):
         assert np.array_equal(got, want), (n, k)
 
 
+def test_topk_degenerate_scores(eng):
+    """Top-k when every radix digit is shared: all scores equal, all NaN
+    (NaN ranks lowest), k = n, and one score above a sea of equal ones; ties
+    go to the lower index."""
+    cases = [(np.full(5000, 0.25, np.float32), 123), (np.full(777, np.nan, np.float32), 7),
+             (np.full(300, -1.0, np.float32), 300)]
+    one = np.full(100000, 3.0, np.float32)
+    one[54321] = 3.0000002
+    cases.append((one, 10))
+    for s, k in cases:
+        got = eng.shape_topk(torch.from_numpy(s).cuda(), k).cpu().numpy()
+        key = np.where(np.isnan(s), -np.inf, s)
+        want = np.sort(np.lexsort((np.arange(s.size), -key))[:k])
+        assert np.array_equal(got, want), (s.size, k)
+
+
 @pytest.mark.parametrize("shift", [(0.0, 0.0, 0.0), (120.0, -75.0, 40.0)])
 def test_fo_overlap_matches_oracle(eng, shift):
     """First-order cross overlaps (Eq. fo) against the oracle's closed form
