@@ -780,6 +780,8 @@ int shape_screen(shape_ctx* c, const shape_mols* query, const shape_mols* lib,
 // Tuning cache: the variant shape_screen_tune chose for a kind of screen,
 // process-wide (a variant suits any context on the same kind of device), and
 // optionally appended to a text file from which a later process reads it.
+}  // extern "C"
+
 namespace {
 
 std::mutex g_tune_m;
@@ -812,6 +814,8 @@ std::string tune_key(const shape_ctx* c, const shape_mols* query, const shape_mo
 }
 
 }  // namespace
+
+extern "C" {
 
 int shape_tune_cache_file(const char* path) {
   std::lock_guard<std::mutex> lock(g_tune_m);
@@ -988,6 +992,8 @@ int shape_self_overlap(shape_ctx* c, const shape_mols* M, int32_t n_samples, uin
   }
 }
 
+}  // extern "C"
+
 namespace {
 
 int align_check(shape_ctx* c, const shape_mols* A, const shape_mols* B, int32_t n_starts,
@@ -1040,6 +1046,8 @@ int align_launch(shape_ctx* c, const shape_mols* A, const shape_mols* B,
 }
 
 }  // namespace
+
+extern "C" {
 
 int shape_align_grad(shape_ctx* c, const shape_mols* A, const shape_mols* B, int32_t n_starts,
                      const float* pose, const float* O_aa, const float* O_bb, int32_t n_samples,
